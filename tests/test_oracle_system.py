@@ -1,0 +1,225 @@
+"""Pins of the oracle's saddle-point system (Sec. 4, eq. (matrix)), its block
+preconditioners (Sec. 5), GMRES (Sec. 6 stopping rule) and the time step.
+
+CPU only.  The checks: a manufactured Stokes solution converging at the Taylor-Hood rates;
+the discrete energy identity of a step (which fixes the signs of the coupling blocks);
+the rows of the solid equations; the sparse direct solve against GMRES and against an
+independent route (condensing the solid unknowns, Schur complement); the finite-step
+convergence that the rank of the preconditioned operator implies; and the closed-form
+inverse of the solid block.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import fluid, gmres, quadrature, system
+from oracle import step as ostep
+from paper_2301_10041_amd import inputs
+
+
+@pytest.fixture(scope="module")
+def sys32():
+    wl = inputs.WORKLOADS["disk32"]
+    S = system.FSISystem.from_workload(wl)
+    S.set_position(S.xy_ref)
+    return S, wl
+
+
+def test_sizes_config_small(sys32):
+    S, _ = sys32
+    assert (S.lay.N2, S.lay.Np, S.lay.Ns, S.lay.N) == (4225, 1089, 127, 10047)
+    assert S.tri.shape[0] == 216
+
+
+def test_direct_solve_equals_gmres_both_preconditioners(sys32):
+    S, wl = sys32
+    b = S.random_rhs(wl.seed)
+    A = S.matrix()
+    xs = S.solve_direct(b)
+    assert np.linalg.norm(A @ xs - b) <= 1e-10 * np.linalg.norm(b)
+    for pc in ("diag", "tri"):
+        x, info = gmres.gmres(lambda v: A @ v, b, precond=lambda r: S.apply_precond(r, pc), restart=30, rtol=1e-12)
+        assert info["converged"]
+        assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_condensed_schur_route():
+    """Eliminate (X, lam) with A22^{-1}; solve the fluid Schur system densely;
+    back-substitute.  A second way to x*, sharing only the blocks."""
+    wl = inputs.small_workload(16, 4, (0.48, 0.53), 0.2)
+    S = system.FSISystem.from_workload(wl)
+    S.set_position(inputs.rotation(S.xy_ref, (0.48, 0.53), 0.2))
+    b = S.random_rhs(7)
+    xs = S.solve_direct(b)
+    nf = S.lay.nf
+    A11, A22, A21 = S.A11(), S.A22(), S.A21()
+    A12 = S.matrix()[:nf, nf:]
+    A22d = A22.toarray()
+    Sc = A11.toarray() - A12.toarray() @ np.linalg.solve(A22d, A21.toarray())
+    r1 = b[:nf] - A12.toarray() @ np.linalg.solve(A22d, b[nf:])
+    x1 = np.linalg.solve(Sc, r1)
+    x2 = np.linalg.solve(A22d, b[nf:] - A21 @ x1)
+    x = np.concatenate([x1, x2])
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_a22_closed_form_inverse(sys32):
+    """z_X = -dt C_s^{-1} r_lam, z_lam = C_s^{-1} (A_s z_X - r_X) inverts A22."""
+    S, _ = sys32
+    ns = S.lay.Ns
+    rng = np.random.default_rng(5)
+    r = rng.uniform(-1, 1, 4 * ns)
+    z = S.apply_A22_inv(r)
+    Ms, As, dt = S.S["Ms"].tocsc(), S.S["As"], S.dt
+    lu = spla.splu(Ms)
+    for c in range(2):
+        rX = r[c * ns:(c + 1) * ns]
+        rl = r[2 * ns + c * ns:2 * ns + (c + 1) * ns]
+        zX = -dt * lu.solve(rl)
+        zl = lu.solve(As @ zX - rX)
+        assert np.allclose(z[c * ns:(c + 1) * ns], zX, rtol=1e-11, atol=1e-13)
+        assert np.allclose(z[2 * ns + c * ns:2 * ns + (c + 1) * ns], zl, rtol=1e-11, atol=1e-13)
+    assert np.allclose(S.A22() @ z, r, atol=1e-10)
+
+
+@pytest.mark.parametrize("pc,factor", [("tri", 2), ("diag", 4)])
+def test_rank_bound_on_tiny_solid(pc, factor):
+    """With exact blocks, P^{-1}-preconditioned A is I plus a matrix of rank <= 2 Ns
+    (triangular) or 4 Ns (diagonal): GMRES converges in at most that many steps + 1."""
+    n = 8
+    xy = np.array([[0.41, 0.43], [0.58, 0.46], [0.47, 0.6]])
+    tri = np.array([[0, 1, 2]], dtype=np.int32)
+    S = system.FSISystem(n, xy, tri, dt=0.01)
+    S.set_position(xy)
+    A = S.matrix()
+    b = S.random_rhs(3)
+    x, info = gmres.gmres(lambda v: A @ v, b, precond=lambda r: S.apply_precond(r, pc), restart=200, rtol=1e-11)
+    assert info["converged"] and info["its"] <= factor * 3 + 1
+    # and the identity preconditioner would need many more steps
+    _, info0 = gmres.gmres(lambda v: A @ v, b, restart=200, rtol=1e-11, maxit=60)
+    assert info0["its"] > factor * 3 + 1
+
+
+def test_step_energy_identity_and_solid_rows():
+    """For the exact step solution: (rho/dt) u.M(u - u^n) + u.K u + (1/dt)(X - X^n).A_s X = 0
+    (the coupling terms cancel), lam = C_s^{-1} A_s X and X = X^n + dt C_s^{-1} C_f u."""
+    wl = inputs.small_workload(16, 3, (0.5, 0.5), 0.2, dt=0.01)
+    S = system.FSISystem.from_workload(wl)
+    lay = S.lay
+    rng = np.random.default_rng(9)
+    u_n = rng.uniform(-1, 1, 2 * lay.N2)
+    bnd2 = np.concatenate([S.F["bnd"], S.F["bnd"]])
+    u_n[bnd2] = 0.0
+    Xn = inputs.rotation(S.xy_ref, (0.5, 0.5), 0.05)
+    x, _ = ostep.step(S, u_n, Xn, solver="direct")
+    sl = lay.slices()
+    u = x[:2 * lay.N2]
+    X = np.stack([x[sl["Xx"]], x[sl["Xy"]]], axis=1)
+    lam = np.stack([x[sl["lx"]], x[sl["ly"]]], axis=1)
+    Mf, K = S.F["Mf"], S.F["K"]
+    N2 = lay.N2
+    du = u - u_n
+    kin = (S.rho / S.dt) * (u[:N2] @ (Mf @ du[:N2]) + u[N2:] @ (Mf @ du[N2:]))
+    visc = (u[:N2] @ (K[(0, 0)] @ u[:N2] + K[(0, 1)] @ u[N2:]) + u[N2:] @ (K[(1, 0)] @ u[:N2] + K[(1, 1)] @ u[N2:]))
+    As = S.S["As"]
+    el = sum((X[:, c] - Xn[:, c]) @ (As @ X[:, c]) for c in range(2)) / S.dt
+    scale = abs(kin) + abs(visc) + abs(el)
+    assert abs(kin + visc + el) <= 1e-9 * scale
+    Ms = S.S["Ms"].tocsc()
+    for c in range(2):
+        assert np.allclose(lam[:, c], spla.spsolve(Ms, As @ X[:, c]), rtol=1e-9, atol=1e-9)
+        Cu = S.Cf @ u[c * N2:(c + 1) * N2]
+        assert np.allclose(X[:, c], Xn[:, c] + S.dt * spla.spsolve(Ms, Cu), rtol=1e-10, atol=1e-12)
+
+
+def _stokes_errors(n, rho=1.0, nu=1.0, dt=0.01):
+    """Solve the fluid block A11 [u; p] = [F; 0] for the manufactured solution
+    u = curl(sin^2(pi x) sin^2(pi y)), p = cos(pi x) cos(pi y), with forcing
+    f = (rho/dt) u - (nu/2) Lap u + grad p (a = nu (eps, eps)); return L2 errors of u and
+    of the mean-free pressure."""
+    pi = np.pi
+    s, c = np.sin, np.cos
+
+    def u_ex(x, y):
+        return (2 * pi * s(pi * x) ** 2 * s(pi * y) * c(pi * y), -2 * pi * s(pi * y) ** 2 * s(pi * x) * c(pi * x))
+
+    def lap_u(x, y):
+        # Laplacians of the two components, by hand
+        ux = 2 * pi * (2 * pi ** 2 * c(2 * pi * x) * s(pi * y) * c(pi * y)
+                       + s(pi * x) ** 2 * (-4 * pi ** 2) * s(pi * y) * c(pi * y))
+        uy = -2 * pi * (2 * pi ** 2 * c(2 * pi * y) * s(pi * x) * c(pi * x)
+                        + s(pi * y) ** 2 * (-4 * pi ** 2) * s(pi * x) * c(pi * x))
+        return ux, uy
+
+    def p_ex(x, y):
+        return c(pi * x) * c(pi * y)
+
+    def grad_p(x, y):
+        return -pi * s(pi * x) * c(pi * y), -pi * c(pi * x) * s(pi * y)
+
+    F = fluid.assemble(n, nu=nu, rho=rho, dt=dt)
+    p2, p1, vx = fluid.triangle_nodes(n)
+    N2, Np = F["N2"], F["Np"]
+    from oracle import poly
+    phi = poly.p2_basis()
+    pts, wts = quadrature.conical_rule(6)
+    rhs = np.zeros(2 * N2 + Np)
+    for T in range(p2.shape[0]):
+        V = vx[T]
+        area = 0.5 * abs((V[1, 0] - V[0, 0]) * (V[2, 1] - V[0, 1]) - (V[2, 0] - V[0, 0]) * (V[1, 1] - V[0, 1]))
+        for (l0, l1, l2), w in zip(pts, wts):
+            x, y = l0 * V[0] + l1 * V[1] + l2 * V[2]
+            ue = u_ex(x, y)
+            lu = lap_u(x, y)
+            gp = grad_p(x, y)
+            f = [(rho / dt) * ue[k] - 0.5 * nu * lu[k] + gp[k] for k in range(2)]
+            for jj in range(6):
+                v = poly.evaluate(phi[jj], l0, l1, l2) * w * area
+                rhs[p2[T, jj]] += f[0] * v
+                rhs[N2 + p2[T, jj]] += f[1] * v
+    bnd = F["bnd"]
+    rhs[:N2][bnd] = 0.0
+    rhs[N2:2 * N2][bnd] = 0.0
+    pin = sp.csr_matrix(([1.0], ([0], [0])), shape=(Np, Np))
+    A11 = sp.bmat([[F["Af"], -F["Bbc"].T], [-F["Bbc"], pin]], format="csc")
+    sol = spla.spsolve(A11, rhs)
+    u, p = sol[:2 * N2], sol[2 * N2:]
+    p = p - (F["Mp"] @ p).sum()                      # mean-free (|Omega| = 1)
+    eu = ep = 0.0
+    for T in range(p2.shape[0]):
+        V = vx[T]
+        area = 0.5 * abs((V[1, 0] - V[0, 0]) * (V[2, 1] - V[0, 1]) - (V[2, 0] - V[0, 0]) * (V[1, 1] - V[0, 1]))
+        for (l0, l1, l2), w in zip(pts, wts):
+            x, y = l0 * V[0] + l1 * V[1] + l2 * V[2]
+            ph = [poly.evaluate(f, l0, l1, l2) for f in phi]
+            uh = (sum(ph[k] * u[p2[T, k]] for k in range(6)), sum(ph[k] * u[N2 + p2[T, k]] for k in range(6)))
+            phh = l0 * p[p1[T, 0]] + l1 * p[p1[T, 1]] + l2 * p[p1[T, 2]]
+            ue = u_ex(x, y)
+            eu += w * area * ((uh[0] - ue[0]) ** 2 + (uh[1] - ue[1]) ** 2)
+            ep += w * area * (phh - p_ex(x, y)) ** 2
+    return np.sqrt(eu), np.sqrt(ep)
+
+
+@pytest.mark.slow
+def test_manufactured_stokes_rates():
+    e = [_stokes_errors(n) for n in (4, 8, 16)]
+    ru = [np.log2(e[k][0] / e[k + 1][0]) for k in range(2)]
+    rp = [np.log2(e[k][1] / e[k + 1][1]) for k in range(2)]
+    assert ru[-1] > 2.7, (e, ru)          # O(h^3) velocity in L2
+    assert rp[-1] > 1.7, (e, rp)          # O(h^2) pressure in L2
+
+
+def test_gmres_on_known_small_system():
+    """The oracle's GMRES solves a dense nonsymmetric system to the requested relative
+    residual and reports the number of Arnoldi steps; with m = N it terminates in <= N."""
+    rng = np.random.default_rng(0)
+    A = rng.normal(size=(12, 12)) + 6 * np.eye(12)
+    b = rng.normal(size=12)
+    x, info = gmres.gmres(lambda v: A @ v, b, restart=12, rtol=1e-12)
+    assert info["converged"] and info["its"] <= 12
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-10)
+    # restarted with a short cycle still converges, taking more steps
+    x2, info2 = gmres.gmres(lambda v: A @ v, b, restart=3, rtol=1e-10)
+    assert info2["converged"] and info2["restarts"] > 1
+    assert np.linalg.norm(A @ x2 - b) <= 1e-10 * np.linalg.norm(b) * 1.0000001
