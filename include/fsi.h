@@ -1,0 +1,207 @@
+/*
+ * libfsi: one time step of the distributed-Lagrange-multiplier fictitious-domain FSI
+ * method (Boffi, Credali, Gastaldi, Scacchi, "A parallel solver for FSI problems with
+ * fictitious domain approach"), on one AMD Instinct MI355X (gfx950).
+ *
+ * The library solves, at each step, the saddle-point system of Sec. 4, eq. (matrix):
+ *
+ *   [ A_f   -B^T    0            C_f^T ] [u]     [g1]
+ *   [ -B     pin    0            0     ] [p]  =  [0 ]
+ *   [ 0      0      A_s         -C_s   ] [X]     [0 ]
+ *   [ C_f    0     -(1/dt) C_s   0     ] [lam]   [g2]
+ *
+ * with A_f = (rho/dt) M_f + K_f, K_f the form nu (eps(u), eps(v)), B the divergence,
+ * A_s = kappa (grad, grad)_B, C_s the solid mass, C_f(X^n) the coupling (chi_l, phi_j(X^n))_B,
+ * g1 = (rho/dt) M_f u^n, g2 = -(1/dt) C_s X^n.  GMRES is right-preconditioned by the
+ * block-diagonal or block-triangular preconditioner of Sec. 5.
+ *
+ * Discretisation (readings where the paper leaves a choice):
+ *  - fluid: [0,1]^2, n x n squares split along (i,j)->(i+1,j+1); P2 velocity, continuous
+ *    P1 pressure; P2 node (I,J), 0<=I,J<=2n, has index J(2n+1)+I; P1 node (i,j) has
+ *    index j(n+1)+i; homogeneous Dirichlet velocity on the whole boundary, imposed by
+ *    value (rows/columns zeroed, 1 on the A_f diagonal); pressure pinned at P1 node 0
+ *    ("pin" is 1 at (p0,p0), row 0 of B is zero);
+ *  - solid: P1 triangles (CCW), X and lam both P1 on the solid mesh; A_s, C_s, C_f act on
+ *    the two components separately.
+ *
+ * Unknown vector (FP64, N entries, structure of arrays):
+ *   x = [u_x (N2) | u_y (N2) | p (Np) | X_x (Ns) | X_y (Ns) | lam_x (Ns) | lam_y (Ns)]
+ * with N2 = (2n+1)^2, Np = (n+1)^2, Ns = number of solid nodes.
+ *
+ * Conventions of every call:
+ *  - the return value is an fsi_status (0 = FSI_OK, negative = error); no C++ exception
+ *    crosses this interface; fsi_last_error(ctx) gives a message for the last error;
+ *  - host arrays given to fsi_create are copied and stay owned by the caller;
+ *  - vector arguments are DEVICE pointers (FP64), owned by the caller, which keeps them
+ *    valid until the work enqueued on the context's stream completes;
+ *  - work is enqueued on the context's HIP stream (fsi_set_stream); calls that return
+ *    statistics or counts synchronise that stream;
+ *  - a context serves one host thread and one stream at a time;
+ *  - on error outputs are unspecified, except FSI_E_NOCONV (x holds the last iterate and
+ *    the statistics are filled in);
+ *  - 32-bit indices: every matrix of a context must have fewer than 2^31 entries
+ *    (n <= 4096 for the fluid blocks).
+ */
+#ifndef FSI_H
+#define FSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fsi_ctx fsi_ctx;
+
+enum fsi_status {
+  FSI_OK = 0,
+  FSI_E_ARG = -1,        /* null pointer, size mismatch, unsupported value */
+  FSI_E_MESH = -2,       /* degenerate/clockwise reference triangle, X^n(E) inverted or outside [0,1]^2 */
+  FSI_E_NOMEM = -3,      /* device memory (or the given budget) exhausted */
+  FSI_E_NOCONV = -4,     /* Krylov solve reached maxit */
+  FSI_E_NONFINITE = -5,  /* NaN/Inf met in a residual */
+  FSI_E_HIP = -6,        /* HIP runtime error */
+  FSI_E_CAPACITY = -7,   /* a fixed per-row limit of the coupling assembly was exceeded */
+  FSI_E_STATE = -8       /* call order: e.g. operator apply before fsi_assemble_coupling */
+};
+
+enum fsi_prec { FSI_FP64 = 0, FSI_FP32 = 1 };  /* arithmetic of SpMV and inner solves */
+enum fsi_pc { FSI_PC_DIAG = 0, FSI_PC_TRI = 1 };/* Sec. 5: block-diagonal / block-triangular */
+
+/* Fluid: n x n grid on [0,1]^2 (n >= 2), viscosity nu, density rho (= solid density,
+ * Sec. 3, Problem 2), time step dt. */
+typedef struct {
+  int32_t n;
+  double nu, rho, dt;
+} fsi_fluid_desc;
+
+/* Solid reference mesh (host arrays, copied): xy = [x (n_nodes) | y (n_nodes)],
+ * tri = 3 node ids per triangle, counter-clockwise; kappa of the law P(F) = kappa F. */
+typedef struct {
+  int32_t n_nodes, n_tris;
+  const double *xy;
+  const int32_t *tri;
+  double kappa;
+} fsi_solid_desc;
+
+typedef struct {
+  int64_t N2, Np, Ns, Nt, N;
+  int64_t off_ux, off_uy, off_p, off_Xx, off_Xy, off_lx, off_ly;
+  int64_t nnz_Af;   /* P2-P2 pattern entries (each carries xx, xy, yx, yy) */
+  int64_t nnz_B;    /* P1-P2 pattern entries of B (each carries B_x, B_y) */
+  int64_t nnz_s;    /* solid P1 pattern entries (A_s and C_s share it) */
+  int64_t nnz_Cf;   /* C_f entries after the last fsi_assemble_coupling (0 before) */
+  int64_t n_pairs;  /* intersection pieces after the last fsi_assemble_coupling */
+  int64_t device_bytes;
+  int32_t mg_levels_u, mg_levels_p;
+} fsi_sizes_t;
+
+typedef struct {
+  int64_t n_pairs;  /* kept (solid triangle, fluid triangle) intersection pieces */
+  int64_t nnz;      /* entries of the scalar C_f pattern */
+} fsi_coupling_info;
+
+typedef struct {
+  int32_t restart;      /* outer FGMRES restart length m (default 30) */
+  int32_t maxit;        /* outer Arnoldi steps over all restarts (default 10000) */
+  double rtol;          /* ||b - A x||_2 <= rtol ||b||_2 (default 1e-8, Sec. 6) */
+  int32_t pc;           /* fsi_pc */
+  int32_t prec;         /* fsi_prec: FP32 = SpMV and inner solves in FP32 (refinement in FP64) */
+  double inner_rtol;    /* relative tolerance of the inner A11 solve (default 1e-10 / 1e-6) */
+  int32_t inner_maxit;  /* inner MINRES steps per A11 solve (default 1000) */
+} fsi_solve_opts;
+
+typedef struct {
+  int32_t its;          /* outer Arnoldi steps, summed over restarts (and refinement cycles) */
+  int32_t restarts;     /* outer cycles */
+  int64_t inner_its;    /* inner MINRES steps, summed */
+  int32_t converged;
+  int32_t refinements;  /* FP64 true-residual cycles (mixed precision) */
+  double relres_true;   /* ||b - A x|| / ||b|| recomputed in FP64 */
+  double relres_est;
+  double t_coup, t_rhs, t_solve;  /* seconds (stream-synchronised wall time) */
+} fsi_solve_stats;
+
+/* Blocks exported by fsi_export_csr (host copies, for tests). */
+enum fsi_block {
+  FSI_BLK_AF = 0,   /* A_f, BC applied: width 4 (xx, xy, yx, yy) on the P2-P2 pattern */
+  FSI_BLK_MF = 1,   /* M_f, no BC: width 1, same pattern */
+  FSI_BLK_B = 2,    /* B, BC + pin applied: width 2 (B_x, B_y), rows P1, columns P2 */
+  FSI_BLK_BT = 3,   /* B^T stored explicitly: width 2, rows P2, columns P1 */
+  FSI_BLK_AS = 4,   /* A_s = kappa K_s: width 1, solid pattern */
+  FSI_BLK_CS = 5,   /* C_s: width 1, solid pattern */
+  FSI_BLK_CF = 6,   /* C_f(X^n): width 1, rows solid nodes, columns P2 nodes */
+  FSI_BLK_CFT = 7,  /* C_f^T: width 1, rows P2 nodes, columns solid nodes */
+  FSI_BLK_MP = 8    /* pressure mass (used by the preconditioner): width 1, P1-P1 */
+};
+
+/* Build the time-independent blocks (Sec. 4: A_f, B, A_s, C_s), the multigrid
+ * hierarchies of the preconditioner and all work space on the current HIP device.
+ * hip_stream: a hipStream_t (NULL = default stream).  hbm_budget: maximum device
+ * bytes the context may hold (0 = no limit); FSI_E_NOMEM if the footprint exceeds it.
+ * Errors: FSI_E_ARG, FSI_E_MESH (a reference triangle with area <= 0), FSI_E_NOMEM,
+ * FSI_E_HIP. */
+int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *hip_stream,
+               size_t hbm_budget, fsi_ctx **out);
+void fsi_destroy(fsi_ctx *ctx);
+int fsi_set_stream(fsi_ctx *ctx, void *hip_stream);
+int fsi_sizes(const fsi_ctx *ctx, fsi_sizes_t *out);
+
+/* C_f(X^n) and its transpose (Sec. 4, the coupling assembly): the mapped solid triangles
+ * X^n(E) are clipped (Sutherland-Hodgman) with the fluid triangles of the cells in their
+ * bounding box; each kept piece is integrated exactly (the integrand is cubic).
+ * Xn: device, 2 Ns doubles [x | y].  info may be NULL (then no synchronisation).
+ * Errors: FSI_E_MESH if some X^n(E) has area <= 0 or leaves [0,1]^2 (detected on the
+ * device, reported at the next synchronising call or here when info != NULL),
+ * FSI_E_CAPACITY if the pieces around one solid node span more than 5,400 P2 nodes. */
+int fsi_assemble_coupling(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *info);
+
+/* (g1, 0, 0, g2) of eq. (matrix): g1 = (rho/dt) M_f u^n with boundary rows zero (u^n is
+ * taken as zero on the boundary), g2 = -(1/dt) C_s X^n.  u_n: device 2 N2, X_n: device
+ * 2 Ns, b: device N. */
+int fsi_build_rhs(fsi_ctx *ctx, const double *u_n, const double *X_n, double *b);
+
+/* y = A x with the full operator of eq. (matrix) (needs fsi_assemble_coupling).
+ * prec = FSI_FP32 rounds x and the matrix values to FP32, accumulates in FP32 and
+ * writes FP64.  x, y: device N (no aliasing). */
+int fsi_apply_operator(fsi_ctx *ctx, int prec, const double *x, double *y);
+
+/* z = P^{-1} r, P = diag(A11, A22) or [[A11, 0], [A21, A22]] (Sec. 5).  A22^{-1} in
+ * closed form (two solid mass solves and one A_s product); A11^{-1} by an inner MINRES
+ * solve to the context's inner tolerance (fsi_set_inner), preconditioned by a P2
+ * geometric multigrid V-cycle on A_f and a Cahouet-Chabard pressure approximation.
+ * r, z: device N (no aliasing). */
+int fsi_apply_precond(fsi_ctx *ctx, int pc, int prec, const double *r, double *z);
+int fsi_set_inner(fsi_ctx *ctx, double inner_rtol, int32_t inner_maxit);
+
+/* Right-preconditioned flexible GMRES(m) on eq. (matrix) from the initial guess in x,
+ * stopping when ||b - A x||_2 <= rtol ||b||_2 (Sec. 6, recomputed in FP64).  With
+ * prec = FSI_FP32 the solve is an iterative refinement: FP64 residual, FGMRES correction
+ * with FP32 operator and preconditioner, FP64 update.  b, x: device N.  stats may be NULL.
+ * Errors: FSI_E_NOCONV, FSI_E_NONFINITE, FSI_E_STATE. */
+int fsi_gmres_solve(fsi_ctx *ctx, const fsi_solve_opts *opts, const double *b, double *x,
+                    fsi_solve_stats *stats);
+
+/* One semi-implicit step (Sec. 4, Problem 3): fsi_assemble_coupling(X_n), fsi_build_rhs,
+ * then fsi_gmres_solve from x = 0.  u_n: device 2 N2, X_n: device 2 Ns, state: device N
+ * (u, p, X, lam at n+1). */
+int fsi_step(fsi_ctx *ctx, const fsi_solve_opts *opts, const double *u_n, const double *X_n,
+             double *state, fsi_solve_stats *stats);
+
+/* Test exports (host copies; synchronising).  fsi_export_pairs writes up to cap pieces
+ * (solid triangle E, fluid triangle T) in the canonical order (by E, then cell j-major,
+ * then T) and stores the total in *count.  fsi_export_csr: call with NULL arrays to get
+ * nrows, nnz and width (values per entry); then rowptr (nrows+1), col (nnz) and
+ * val (nnz*width) are filled. */
+int fsi_export_pairs(fsi_ctx *ctx, int32_t *E, int32_t *T, int64_t cap, int64_t *count);
+int fsi_export_csr(fsi_ctx *ctx, int block, int64_t *nrows, int64_t *nnz, int32_t *width,
+                   int32_t *rowptr, int32_t *col, double *val);
+
+const char *fsi_strerror(int status);
+const char *fsi_last_error(const fsi_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,330 @@
+// extern "C" entry points of libfsi (declared in include/fsi.h).  Every call catches
+// the library's exceptions and returns an fsi_status; the message is kept in the context.
+#include <chrono>
+#include <cstring>
+
+#include "ctx.h"
+#include "kernels.h"
+
+struct fsi_ctx {
+  fsi::Ctx c;
+};
+
+namespace fsi {
+
+Ctx::~Ctx() {
+  if (hpin) hipHostFree(hpin);
+}
+
+size_t Ctx::device_bytes() const {
+  size_t b = Af.bytes() + Mf.bytes() + B.bytes() + BT.bytes() + Mp.bytes() + Mp_dinv.bytes() +
+             Mp_dinv32.bytes() + bnd.bytes();
+  b += tri.bytes() + ref_xy.bytes() + ref_area.bytes() + n2e_ptr.bytes() + n2e.bytes() + S.bytes() +
+       Cs.bytes() + Cs32.bytes() + Cs_dinv.bytes() + Cs_dinv32.bytes();
+  b += Cf.bytes() + CfT.bytes() + cand_off.bytes() + piece_cnt.bytes() + pair_E.bytes() +
+       pair_T.bytes() + piece_L.bytes() + e_piece.bytes() + cft_fill.bytes() + dflag.bytes();
+  b += mgu.bytes() + mgp.bytes();
+  for (int i = 0; i < 9; ++i) b += inner.v64[i].bytes() + inner.v32[i].bytes();
+  b += outer.V.bytes() + outer.Z.bytes() + outer.w.bytes() + outer.r.bytes() + outer.x32.bytes() +
+       outer.y32.bytes();
+  b += red.bytes() + dscal.bytes() + tmpN.bytes() + tmpS.bytes();
+  return b;
+}
+
+// Footprint estimate made before any allocation (FP64 + FP32 shadows, MG, Krylov with
+// m = 30 and both precisions' inner vectors).
+static size_t estimate_bytes(int64_t n, int64_t ns, int64_t nt) {
+  double n2 = (double)n * n;
+  double zaf = 46 * n2, zb = 19 * n2, N2 = 4 * n2, Np = n2, N = 2 * N2 + Np + 4 * ns;
+  double fluid = zaf * (32 + 4 + 8 + 16) + 2 * zb * (16 + 4 + 8) + 9 * Np * 12 + 4 * (N2 + Np);
+  double mg = fluid * 0.45 + 10 * N2 * 12 / 3;
+  double krylov = 61 * N * 8 + 9 * (2 * N2 + Np) * 12 + 4 * N * 8;
+  double solid = ns * (7 * 12 * 2 + 200) + nt * 60 + 60 * ns * 12;
+  double cf = nt * 12 * (18 * 8 + 16) + 2 * 60 * ns * 12 + N2 * 8;
+  return (size_t)(fluid + mg + krylov + solid + cf);
+}
+
+}  // namespace fsi
+
+using fsi::Ctx;
+using fsi::Error;
+
+static thread_local std::string g_create_error;
+
+template <typename F>
+static int guarded(fsi_ctx *h, F &&f) {
+  try {
+    f();
+    return FSI_OK;
+  } catch (const Error &e) {
+    if (h) h->c.last_error = e.what();
+    else g_create_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    if (h) h->c.last_error = "host allocation failed";
+    return FSI_E_NOMEM;
+  } catch (const std::exception &e) {
+    if (h) h->c.last_error = e.what();
+    return FSI_E_HIP;
+  }
+}
+
+extern "C" {
+
+int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *hip_stream,
+               size_t hbm_budget, fsi_ctx **out) {
+  if (!out) return FSI_E_ARG;
+  *out = nullptr;
+  fsi_ctx *h = nullptr;
+  int rc = guarded(nullptr, [&] {
+    FSI_REQUIRE(fluid && solid, FSI_E_ARG, "null descriptor");
+    FSI_REQUIRE(fluid->n >= 2 && fluid->n <= 4096, FSI_E_ARG, "fluid n must be in [2, 4096]");
+    FSI_REQUIRE(fluid->nu > 0 && fluid->rho > 0 && fluid->dt > 0, FSI_E_ARG, "nu, rho, dt must be > 0");
+    FSI_REQUIRE(solid->n_nodes >= 3 && solid->n_tris >= 1 && solid->xy && solid->tri, FSI_E_ARG,
+                "solid mesh needs >= 3 nodes, >= 1 triangle and non-null arrays");
+    FSI_REQUIRE(solid->kappa >= 0, FSI_E_ARG, "kappa must be >= 0");
+    const int64_t n = fluid->n, ns = solid->n_nodes, nt = solid->n_tris;
+    if (hbm_budget) {
+      size_t est = fsi::estimate_bytes(n, ns, nt);
+      FSI_REQUIRE(est <= hbm_budget, FSI_E_NOMEM,
+                  "estimated footprint " + std::to_string(est) + " B exceeds the budget");
+    }
+    h = new fsi_ctx();
+    Ctx &c = h->c;
+    c.n = fluid->n;
+    c.nu = fluid->nu;
+    c.rho = fluid->rho;
+    c.dt = fluid->dt;
+    c.kappa = solid->kappa;
+    c.N2 = (2 * n + 1) * (2 * n + 1);
+    c.Np = (n + 1) * (n + 1);
+    c.Ns = ns;
+    c.Nt = nt;
+    c.N = 2 * c.N2 + c.Np + 4 * ns;
+    c.stream = (hipStream_t)hip_stream;
+    c.budget = hbm_budget;
+    c.h_tri.assign(solid->tri, solid->tri + 3 * nt);
+    c.h_xy.assign(solid->xy, solid->xy + 2 * ns);
+    FSI_HIP(hipHostMalloc((void **)&c.hpin, 4096 * sizeof(double), hipHostMallocDefault));
+    fsi::build_solid(c);
+    fsi::build_fluid(c);
+    fsi::build_multigrid(c);
+    fsi::make_shadow(c.Af, c.stream);
+    fsi::make_shadow(c.B, c.stream);
+    fsi::make_shadow(c.BT, c.stream);
+    fsi::make_shadow(c.S, c.stream);
+    c.tmpN.alloc(c.N);
+    c.tmpS.alloc(12 * ns);
+    c.dscal.alloc(512);
+    FSI_HIP(hipStreamSynchronize(c.stream));
+    if (hbm_budget)
+      FSI_REQUIRE(c.device_bytes() <= hbm_budget, FSI_E_NOMEM, "device footprint exceeds the budget");
+  });
+  if (rc != FSI_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return FSI_OK;
+}
+
+void fsi_destroy(fsi_ctx *ctx) {
+  if (!ctx) return;
+  hipStreamSynchronize(ctx->c.stream);
+  delete ctx;
+}
+
+int fsi_set_stream(fsi_ctx *ctx, void *hip_stream) {
+  if (!ctx) return FSI_E_ARG;
+  ctx->c.stream = (hipStream_t)hip_stream;
+  return FSI_OK;
+}
+
+int fsi_sizes(const fsi_ctx *ctx, fsi_sizes_t *o) {
+  if (!ctx || !o) return FSI_E_ARG;
+  const Ctx &c = ctx->c;
+  std::memset(o, 0, sizeof(*o));
+  o->N2 = c.N2; o->Np = c.Np; o->Ns = c.Ns; o->Nt = c.Nt; o->N = c.N;
+  o->off_ux = 0; o->off_uy = c.N2; o->off_p = 2 * c.N2; o->off_Xx = 2 * c.N2 + c.Np;
+  o->off_Xy = o->off_Xx + c.Ns; o->off_lx = o->off_Xy + c.Ns; o->off_ly = o->off_lx + c.Ns;
+  o->nnz_Af = c.Af.nnz; o->nnz_B = c.B.nnz; o->nnz_s = c.S.nnz;
+  o->nnz_Cf = c.have_cf ? c.Cf.nnz : 0;
+  o->n_pairs = c.have_cf ? c.n_pairs : 0;
+  o->device_bytes = (int64_t)c.device_bytes();
+  o->mg_levels_u = (int32_t)c.mgu.lv.size();
+  o->mg_levels_p = (int32_t)c.mgp.lv.size();
+  return FSI_OK;
+}
+
+int fsi_assemble_coupling(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *info) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    FSI_REQUIRE(Xn, FSI_E_ARG, "null X^n");
+    fsi::assemble_coupling(ctx->c, Xn, info != nullptr);
+    if (info) {
+      FSI_HIP(hipStreamSynchronize(ctx->c.stream));
+      info->n_pairs = ctx->c.n_pairs;
+      info->nnz = ctx->c.Cf.nnz;
+    }
+  });
+}
+
+int fsi_build_rhs(fsi_ctx *ctx, const double *u_n, const double *X_n, double *b) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    FSI_REQUIRE(u_n && X_n && b, FSI_E_ARG, "null vector");
+    fsi::build_rhs(ctx->c, u_n, X_n, b);
+  });
+}
+
+int fsi_apply_operator(fsi_ctx *ctx, int prec, const double *x, double *y) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    FSI_REQUIRE(x && y && x != y, FSI_E_ARG, "null or aliased vectors");
+    FSI_REQUIRE(ctx->c.have_cf, FSI_E_STATE, "call fsi_assemble_coupling first");
+    if (prec == FSI_FP64) fsi::apply_operator<double, double>(ctx->c, x, y, false);
+    else if (prec == FSI_FP32) fsi::apply_operator<float, double>(ctx->c, x, y, false);
+    else throw Error(FSI_E_ARG, "unknown precision");
+  });
+}
+
+int fsi_apply_precond(fsi_ctx *ctx, int pc, int prec, const double *r, double *z) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    FSI_REQUIRE(r && z && r != z, FSI_E_ARG, "null or aliased vectors");
+    ctx->c.dscal.reserve(512);
+    fsi::apply_precond(ctx->c, pc, prec, r, z);
+  });
+}
+
+int fsi_set_inner(fsi_ctx *ctx, double inner_rtol, int32_t inner_maxit) {
+  if (!ctx) return FSI_E_ARG;
+  if (inner_maxit < 0) return FSI_E_ARG;
+  ctx->c.inner_rtol = inner_rtol;
+  if (inner_maxit > 0) ctx->c.inner_maxit = inner_maxit;
+  return FSI_OK;
+}
+
+int fsi_gmres_solve(fsi_ctx *ctx, const fsi_solve_opts *opts, const double *b, double *x,
+                    fsi_solve_stats *stats) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    FSI_REQUIRE(opts && b && x && b != x, FSI_E_ARG, "null options or vectors");
+    auto t0 = std::chrono::steady_clock::now();
+    fsi_solve_stats st{};
+    int rc = FSI_OK;
+    try {
+      fsi::gmres_solve(ctx->c, *opts, b, x, &st);
+    } catch (const Error &e) {
+      if (e.code != FSI_E_NOCONV) throw;
+      rc = e.code;
+      ctx->c.last_error = e.what();
+    }
+    FSI_HIP(hipStreamSynchronize(ctx->c.stream));
+    st.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    if (rc != FSI_OK) throw Error(rc, ctx->c.last_error);
+  });
+}
+
+int fsi_step(fsi_ctx *ctx, const fsi_solve_opts *opts, const double *u_n, const double *X_n,
+             double *state, fsi_solve_stats *stats) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    FSI_REQUIRE(opts && u_n && X_n && state, FSI_E_ARG, "null options or vectors");
+    Ctx &c = ctx->c;
+    using clk = std::chrono::steady_clock;
+    auto t0 = clk::now();
+    fsi::assemble_coupling(c, X_n, true);
+    FSI_HIP(hipStreamSynchronize(c.stream));
+    auto t1 = clk::now();
+    double *b = c.tmpN.p;
+    fsi::build_rhs(c, u_n, X_n, b);
+    fsi::fill(state, c.N, 0.0, c.stream);
+    FSI_HIP(hipStreamSynchronize(c.stream));
+    auto t2 = clk::now();
+    fsi_solve_stats st{};
+    int rc = FSI_OK;
+    try {
+      fsi::gmres_solve(c, *opts, b, state, &st);
+    } catch (const Error &e) {
+      if (e.code != FSI_E_NOCONV) throw;
+      rc = e.code;
+      c.last_error = e.what();
+    }
+    FSI_HIP(hipStreamSynchronize(c.stream));
+    auto t3 = clk::now();
+    st.t_coup = std::chrono::duration<double>(t1 - t0).count();
+    st.t_rhs = std::chrono::duration<double>(t2 - t1).count();
+    st.t_solve = std::chrono::duration<double>(t3 - t2).count();
+    if (stats) *stats = st;
+    if (rc != FSI_OK) throw Error(rc, c.last_error);
+  });
+}
+
+int fsi_export_pairs(fsi_ctx *ctx, int32_t *E, int32_t *T, int64_t cap, int64_t *count) {
+  if (!ctx || !count) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    Ctx &c = ctx->c;
+    FSI_REQUIRE(c.have_cf, FSI_E_STATE, "call fsi_assemble_coupling first");
+    *count = c.n_pairs;
+    int64_t m = std::min<int64_t>(cap, c.n_pairs);
+    if (m > 0 && E) FSI_HIP(hipMemcpyAsync(E, c.pair_E.p, m * 4, hipMemcpyDeviceToHost, c.stream));
+    if (m > 0 && T) FSI_HIP(hipMemcpyAsync(T, c.pair_T.p, m * 4, hipMemcpyDeviceToHost, c.stream));
+    FSI_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+int fsi_export_csr(fsi_ctx *ctx, int block, int64_t *nrows, int64_t *nnz, int32_t *width,
+                   int32_t *rowptr, int32_t *col, double *val) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    Ctx &c = ctx->c;
+    const fsi::Csr *A = nullptr;
+    const double *v = nullptr;
+    int w = 1;
+    switch (block) {
+      case FSI_BLK_AF: A = &c.Af; v = c.Af.val.p; w = 4; break;
+      case FSI_BLK_MF: A = &c.Af; v = c.Mf.p; w = 1; break;
+      case FSI_BLK_B: A = &c.B; v = c.B.val.p; w = 2; break;
+      case FSI_BLK_BT: A = &c.BT; v = c.BT.val.p; w = 2; break;
+      case FSI_BLK_AS: A = &c.S; v = c.S.val.p; w = 1; break;
+      case FSI_BLK_CS: A = &c.S; v = c.Cs.p; w = 1; break;
+      case FSI_BLK_CF: A = &c.Cf; v = c.Cf.val.p; w = 1; break;
+      case FSI_BLK_CFT: A = &c.CfT; v = c.CfT.val.p; w = 1; break;
+      case FSI_BLK_MP: A = &c.Mp; v = c.Mp.val.p; w = 1; break;
+      default: throw Error(FSI_E_ARG, "unknown block id");
+    }
+    if (block == FSI_BLK_CF || block == FSI_BLK_CFT)
+      FSI_REQUIRE(c.have_cf, FSI_E_STATE, "call fsi_assemble_coupling first");
+    if (nrows) *nrows = A->nrows;
+    if (nnz) *nnz = A->nnz;
+    if (width) *width = w;
+    if (rowptr) FSI_HIP(hipMemcpyAsync(rowptr, A->rowptr.p, (A->nrows + 1) * 4, hipMemcpyDeviceToHost, c.stream));
+    if (col && A->nnz) FSI_HIP(hipMemcpyAsync(col, A->col.p, A->nnz * 4, hipMemcpyDeviceToHost, c.stream));
+    if (val && A->nnz) FSI_HIP(hipMemcpyAsync(val, v, A->nnz * w * 8, hipMemcpyDeviceToHost, c.stream));
+    FSI_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+const char *fsi_strerror(int status) {
+  switch (status) {
+    case FSI_OK: return "ok";
+    case FSI_E_ARG: return "invalid argument";
+    case FSI_E_MESH: return "invalid mesh or solid position";
+    case FSI_E_NOMEM: return "out of device memory or budget";
+    case FSI_E_NOCONV: return "Krylov solve did not converge";
+    case FSI_E_NONFINITE: return "non-finite value";
+    case FSI_E_HIP: return "HIP runtime error";
+    case FSI_E_CAPACITY: return "fixed capacity exceeded";
+    case FSI_E_STATE: return "call order";
+    default: return "unknown status";
+  }
+}
+
+const char *fsi_last_error(const fsi_ctx *ctx) {
+  if (!ctx) return g_create_error.c_str();
+  return ctx->c.last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,828 @@
+// Assembly of the time-independent blocks of eq. (matrix) (Sec. 4) on the device:
+//   A_f = (rho/dt) M_f + K_f (2x2 blocks, K_f from nu (eps(u), eps(v))), M_f, B (div),
+//   B^T, the pressure mass M_p and the P1 pressure Laplacian L_p (preconditioner);
+//   A_s = kappa K_s and C_s = M_s on the solid mesh;
+// and the geometric multigrid hierarchies (P2 velocity, P1 pressure) with nested
+// prolongations.  Every matrix row is gathered by one thread from the triangles around
+// its node, so there are no atomics and the result is deterministic.  Columns of a row
+// are visited in a fixed window order that coincides with ascending node index.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "ctx.h"
+#include "kernels.h"
+
+namespace fsi {
+
+// ---------------------------------------------------------------- element matrices
+// Degree-4 six-point rule on a triangle (Dunavant, 1985): positive weights, exact for
+// polynomials of degree <= 4, which covers every integrand below (P2 x P2 mass).
+static const double kDunA[2] = {0.445948490915965, 0.091576213509771};
+static const double kDunW[2] = {0.223381589678011, 0.109951743655322};
+
+// Layout of one element type in the device table.
+constexpr int EM_M = 0, EM_K = 36, EM_B = 180, EM_MP = 216, EM_LP = 225, EM_SIZE = 234;
+
+// Lattice offsets of the six P2 nodes (a, b, c, ab, bc, ca) of the two triangles of a
+// cell, in units of h/2 from the cell's lower-left node (2i, 2j).
+__constant__ int kOff[2][6][2] = {{{0, 0}, {2, 0}, {2, 2}, {1, 0}, {2, 1}, {1, 1}},
+                                  {{0, 0}, {2, 2}, {0, 2}, {1, 1}, {1, 2}, {0, 1}}};
+
+// Element matrices of T0 = (v00, v10, v11) and T1 = (v00, v11, v01) of a cell of side h.
+static void element_tables(int n, double nu, std::vector<double> &out) {
+  const double h = 1.0 / n;
+  const double area = 0.5 * h * h;
+  out.assign(2 * EM_SIZE, 0.0);
+  for (int t = 0; t < 2; ++t) {
+    // barycentric gradients (constant on the triangle)
+    double g[3][2];
+    if (t == 0) {   // l0 = 1 - xi, l1 = xi - eta, l2 = eta
+      g[0][0] = -1 / h; g[0][1] = 0;
+      g[1][0] = 1 / h;  g[1][1] = -1 / h;
+      g[2][0] = 0;      g[2][1] = 1 / h;
+    } else {        // l0 = 1 - eta, l1 = xi, l2 = eta - xi
+      g[0][0] = 0;      g[0][1] = -1 / h;
+      g[1][0] = 1 / h;  g[1][1] = 0;
+      g[2][0] = -1 / h; g[2][1] = 1 / h;
+    }
+    double *E = out.data() + t * EM_SIZE;
+    for (int q = 0; q < 6; ++q) {
+      int grp = q / 3, rot = q % 3;
+      double a = kDunA[grp], b = 1.0 - 2.0 * a;
+      double l[3];
+      l[rot] = b; l[(rot + 1) % 3] = a; l[(rot + 2) % 3] = a;
+      double w = kDunW[grp] * area;
+      static const int ea[3] = {0, 1, 2}, eb[3] = {1, 2, 0};
+      double phi[6], dphi[6][2];
+      for (int k = 0; k < 3; ++k) {
+        phi[k] = l[k] * (2 * l[k] - 1);
+        for (int c = 0; c < 2; ++c) dphi[k][c] = (4 * l[k] - 1) * g[k][c];
+      }
+      for (int k = 0; k < 3; ++k) {
+        int p = ea[k], r = eb[k];
+        phi[3 + k] = 4 * l[p] * l[r];
+        for (int c = 0; c < 2; ++c) dphi[3 + k][c] = 4 * (l[r] * g[p][c] + l[p] * g[r][c]);
+      }
+      for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+          E[EM_M + i * 6 + j] += w * phi[i] * phi[j];
+          double gg = dphi[i][0] * dphi[j][0] + dphi[i][1] * dphi[j][1];
+          // eps(phi_j e_beta) : eps(phi_i e_alpha) = (delta_ab grad phi_i . grad phi_j
+          //                                           + d_beta phi_i d_alpha phi_j) / 2
+          for (int al = 0; al < 2; ++al)
+            for (int be = 0; be < 2; ++be)
+              E[EM_K + ((al * 2 + be) * 6 + i) * 6 + j] +=
+                  w * nu * 0.5 * ((al == be ? gg : 0.0) + dphi[i][be] * dphi[j][al]);
+        }
+      for (int al = 0; al < 2; ++al)
+        for (int k = 0; k < 3; ++k)
+          for (int i = 0; i < 6; ++i) E[EM_B + (al * 3 + k) * 6 + i] += w * dphi[i][al] * l[k];
+      for (int k = 0; k < 3; ++k)
+        for (int m = 0; m < 3; ++m) {
+          E[EM_MP + k * 3 + m] += w * l[k] * l[m];
+          E[EM_LP + k * 3 + m] += w * (g[k][0] * g[m][0] + g[k][1] * g[m][1]);
+        }
+    }
+  }
+}
+
+__global__ void k_diag_inv(int64_t nrows, const int *rowptr, const int *col, const double *v,
+                           double *dinv);
+
+// ---------------------------------------------------------------- structured adjacency
+struct Adj {
+  int ci, cj, t, a;
+};
+
+// Triangles containing P2 lattice node (I, J) (0 <= I, J <= 2n), with the node's local
+// index a in each.  At most 6 (out must hold 8).
+__device__ __forceinline__ int adjacent_tris(int I, int J, int n, Adj *out) {
+  int ilo = (I - 1) >> 1, ihi = I >> 1, jlo = (J - 1) >> 1, jhi = J >> 1;
+  if (ilo < 0) ilo = 0;
+  if (jlo < 0) jlo = 0;
+  if (ihi > n - 1) ihi = n - 1;
+  if (jhi > n - 1) jhi = n - 1;
+  int cnt = 0;
+  for (int cj = jlo; cj <= jhi; ++cj)
+    for (int ci = ilo; ci <= ihi; ++ci)
+      for (int t = 0; t < 2; ++t)
+        for (int a = 0; a < 6; ++a)
+          if (2 * ci + kOff[t][a][0] == I && 2 * cj + kOff[t][a][1] == J) {
+            out[cnt++] = Adj{ci, cj, t, a};
+            break;
+          }
+  return cnt;
+}
+
+__device__ __forceinline__ int local_of(const Adj &t, int I, int J) {
+  for (int b = 0; b < 6; ++b)
+    if (2 * t.ci + kOff[t.t][b][0] == I && 2 * t.cj + kOff[t.t][b][1] == J) return b;
+  return -1;
+}
+
+__device__ __forceinline__ bool p2_boundary(int I, int J, int n) {
+  return I == 0 || J == 0 || I == 2 * n || J == 2 * n;
+}
+
+// P2 x P2 rows: A_f (width 4, BC by value) and optionally M_f (width 1, no BC).
+// pass 0: cnt[row] = number of columns; pass 1: fill.
+__global__ void k_asm_p2p2(int n, int pass, const double *__restrict__ E, double rdt,
+                           int *cnt, const int *rowptr, int *col, double *A, double *M) {
+  int64_t L = 2 * n + 1;
+  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= L * L) return;
+  int I = (int)(row % L), J = (int)(row / L);
+  Adj adj[8];
+  int na = adjacent_tris(I, J, n, adj);
+  bool rb = p2_boundary(I, J, n);
+  int k = pass ? rowptr[row] : 0;
+  int c = 0;
+  for (int dJ = -2; dJ <= 2; ++dJ)
+    for (int dI = -2; dI <= 2; ++dI) {
+      int I2 = I + dI, J2 = J + dJ;
+      if (I2 < 0 || J2 < 0 || I2 > 2 * n || J2 > 2 * n) continue;
+      bool touched = false;
+      double m = 0, kxx = 0, kxy = 0, kyx = 0, kyy = 0;
+      for (int q = 0; q < na; ++q) {
+        int b = local_of(adj[q], I2, J2);
+        if (b < 0) continue;
+        touched = true;
+        const double *e = E + adj[q].t * EM_SIZE;
+        int a = adj[q].a;
+        m += e[EM_M + a * 6 + b];
+        kxx += e[EM_K + ((0 * 2 + 0) * 6 + a) * 6 + b];
+        kxy += e[EM_K + ((0 * 2 + 1) * 6 + a) * 6 + b];
+        kyx += e[EM_K + ((1 * 2 + 0) * 6 + a) * 6 + b];
+        kyy += e[EM_K + ((1 * 2 + 1) * 6 + a) * 6 + b];
+      }
+      if (!touched) continue;
+      if (pass) {
+        int64_t cidx = (int64_t)J2 * L + I2;
+        col[k] = (int)cidx;
+        double *v = A + 4 * (int64_t)k;
+        if (rb || p2_boundary(I2, J2, n)) {
+          double dg = (cidx == row) ? 1.0 : 0.0;
+          v[0] = dg; v[1] = 0.0; v[2] = 0.0; v[3] = dg;
+        } else {
+          v[0] = rdt * m + kxx; v[1] = kxy; v[2] = kyx; v[3] = rdt * m + kyy;
+        }
+        if (M) M[k] = m;
+        ++k;
+      }
+      ++c;
+    }
+  if (!pass) cnt[row] = c;
+}
+
+// Rows of B (P1 node (i, j)), columns P2 nodes; width 2; row 0 and boundary columns zero.
+__global__ void k_asm_b(int n, int pass, const double *__restrict__ E, int *cnt,
+                        const int *rowptr, int *col, double *V) {
+  int64_t L1 = n + 1, L = 2 * n + 1;
+  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= L1 * L1) return;
+  int I = 2 * (int)(row % L1), J = 2 * (int)(row / L1);
+  Adj adj[8];
+  int na = adjacent_tris(I, J, n, adj);
+  int k = pass ? rowptr[row] : 0, c = 0;
+  for (int dJ = -2; dJ <= 2; ++dJ)
+    for (int dI = -2; dI <= 2; ++dI) {
+      int I2 = I + dI, J2 = J + dJ;
+      if (I2 < 0 || J2 < 0 || I2 > 2 * n || J2 > 2 * n) continue;
+      bool touched = false;
+      double bx = 0, by = 0;
+      for (int q = 0; q < na; ++q) {
+        int b = local_of(adj[q], I2, J2);
+        if (b < 0) continue;
+        touched = true;
+        const double *e = E + adj[q].t * EM_SIZE;
+        int a = adj[q].a;   // vertex: P1 local index = P2 local index
+        bx += e[EM_B + (0 * 3 + a) * 6 + b];
+        by += e[EM_B + (1 * 3 + a) * 6 + b];
+      }
+      if (!touched) continue;
+      if (pass) {
+        col[k] = (int)((int64_t)J2 * L + I2);
+        bool z = (row == 0) || p2_boundary(I2, J2, n);
+        V[2 * (int64_t)k] = z ? 0.0 : bx;
+        V[2 * (int64_t)k + 1] = z ? 0.0 : by;
+        ++k;
+      }
+      ++c;
+    }
+  if (!pass) cnt[row] = c;
+}
+
+// Rows of B^T (P2 node (I, J)), columns P1 nodes; width 2; boundary rows and column 0 zero.
+__global__ void k_asm_bt(int n, int pass, const double *__restrict__ E, int *cnt,
+                         const int *rowptr, int *col, double *V) {
+  int64_t L = 2 * n + 1, L1 = n + 1;
+  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= L * L) return;
+  int I = (int)(row % L), J = (int)(row / L);
+  Adj adj[8];
+  int na = adjacent_tris(I, J, n, adj);
+  bool rb = p2_boundary(I, J, n);
+  int ilo = (I - 1) >> 1, ihi = (I + 2) >> 1, jlo = (J - 1) >> 1, jhi = (J + 2) >> 1;
+  if (ilo < 0) ilo = 0;
+  if (jlo < 0) jlo = 0;
+  if (ihi > n) ihi = n;
+  if (jhi > n) jhi = n;
+  int k = pass ? rowptr[row] : 0, c = 0;
+  for (int j2 = jlo; j2 <= jhi; ++j2)
+    for (int i2 = ilo; i2 <= ihi; ++i2) {
+      bool touched = false;
+      double bx = 0, by = 0;
+      for (int q = 0; q < na; ++q) {
+        int b = local_of(adj[q], 2 * i2, 2 * j2);
+        if (b < 0) continue;      // b in {0, 1, 2}: a vertex of the triangle
+        touched = true;
+        const double *e = E + adj[q].t * EM_SIZE;
+        int a = adj[q].a;
+        bx += e[EM_B + (0 * 3 + b) * 6 + a];
+        by += e[EM_B + (1 * 3 + b) * 6 + a];
+      }
+      if (!touched) continue;
+      if (pass) {
+        int64_t cidx = (int64_t)j2 * L1 + i2;
+        col[k] = (int)cidx;
+        bool z = rb || cidx == 0;
+        V[2 * (int64_t)k] = z ? 0.0 : bx;
+        V[2 * (int64_t)k + 1] = z ? 0.0 : by;
+        ++k;
+      }
+      ++c;
+    }
+  if (!pass) cnt[row] = c;
+}
+
+// P1 x P1 rows (P1 node (i, j)) of the table entry `which` (EM_MP or EM_LP); with `pin`
+// row and column 0 are zeroed and (0, 0) = 1.
+__global__ void k_asm_p1p1(int n, int pass, const double *__restrict__ E, int which, int pin,
+                           int *cnt, const int *rowptr, int *col, double *V) {
+  int64_t L1 = n + 1;
+  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= L1 * L1) return;
+  int i = (int)(row % L1), j = (int)(row / L1);
+  Adj adj[8];
+  int na = adjacent_tris(2 * i, 2 * j, n, adj);
+  int k = pass ? rowptr[row] : 0, c = 0;
+  for (int dj = -1; dj <= 1; ++dj)
+    for (int di = -1; di <= 1; ++di) {
+      int i2 = i + di, j2 = j + dj;
+      if (i2 < 0 || j2 < 0 || i2 > n || j2 > n) continue;
+      bool touched = false;
+      double v = 0;
+      for (int q = 0; q < na; ++q) {
+        int b = local_of(adj[q], 2 * i2, 2 * j2);
+        if (b < 0) continue;
+        touched = true;
+        v += E[adj[q].t * EM_SIZE + which + adj[q].a * 3 + b];
+      }
+      if (!touched) continue;
+      if (pass) {
+        int64_t cidx = (int64_t)j2 * L1 + i2;
+        col[k] = (int)cidx;
+        if (pin && (row == 0 || cidx == 0)) v = (row == cidx) ? 1.0 : 0.0;
+        V[k] = v;
+        ++k;
+      }
+      ++c;
+    }
+  if (!pass) cnt[row] = c;
+}
+
+__global__ void k_p2_boundary_flags(int n, unsigned char *bnd) {
+  int64_t L = 2 * n + 1;
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= L * L) return;
+  bnd[r] = p2_boundary((int)(r % L), (int)(r / L), n) ? 1 : 0;
+}
+
+// Two-pass row builder shared by every structured block.
+template <typename Launch>
+static void build_rows(Csr &A, int64_t nrows, int64_t ncols, int width, hipStream_t s,
+                       DevBuf<int> &tmp, Launch launch, bool with_m = false,
+                       DevBuf<double> *M = nullptr) {
+  A.nrows = nrows;
+  A.ncols = ncols;
+  A.width = width;
+  A.rowptr.alloc(nrows + 1);
+  launch(0, A.rowptr.p, nullptr, nullptr, nullptr, nullptr);
+  scan_excl(A.rowptr.p, A.rowptr.p, nrows, tmp, s);
+  int nnz = 0;
+  FSI_HIP(hipMemcpyAsync(&nnz, A.rowptr.p + nrows, sizeof(int), hipMemcpyDeviceToHost, s));
+  FSI_HIP(hipStreamSynchronize(s));
+  A.nnz = nnz;
+  A.col.alloc(nnz);
+  A.val.alloc((size_t)nnz * width);
+  if (with_m) M->alloc(nnz);
+  launch(1, nullptr, A.rowptr.p, A.col.p, A.val.p, with_m ? M->p : nullptr);
+  FSI_CHECK_LAUNCH();
+}
+
+static void assemble_p2p2(Csr &A, DevBuf<double> *M, int n, const double *dE, double rdt,
+                          DevBuf<int> &tmp, hipStream_t s) {
+  int64_t rows = (int64_t)(2 * n + 1) * (2 * n + 1);
+  unsigned g = grid_for(rows, 256);
+  build_rows(A, rows, rows, 4, s, tmp,
+             [&](int pass, int *cnt, const int *rp, int *col, double *v, double *m) {
+               hipLaunchKernelGGL(k_asm_p2p2, dim3(g), dim3(256), 0, s, n, pass, dE, rdt, cnt,
+                                  rp, col, v, m);
+             },
+             M != nullptr, M);
+}
+
+static void assemble_p1p1(Csr &A, int n, const double *dE, int which, int pin, DevBuf<int> &tmp,
+                          hipStream_t s) {
+  int64_t rows = (int64_t)(n + 1) * (n + 1);
+  unsigned g = grid_for(rows, 256);
+  build_rows(A, rows, rows, 1, s, tmp,
+             [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+               hipLaunchKernelGGL(k_asm_p1p1, dim3(g), dim3(256), 0, s, n, pass, dE, which, pin,
+                                  cnt, rp, col, v);
+             });
+}
+
+void build_fluid(Ctx &c) {
+  hipStream_t s = c.stream;
+  std::vector<double> hE;
+  element_tables(c.n, c.nu, hE);
+  DevBuf<double> dE(hE.size());
+  FSI_HIP(hipMemcpyAsync(dE.p, hE.data(), hE.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  DevBuf<int> tmp;
+  const int n = c.n;
+  assemble_p2p2(c.Af, &c.Mf, n, dE.p, c.rho / c.dt, tmp, s);
+  int64_t np = (int64_t)(n + 1) * (n + 1), n2 = (int64_t)(2 * n + 1) * (2 * n + 1);
+  unsigned gp = grid_for(np, 256), g2 = grid_for(n2, 256);
+  build_rows(c.B, np, n2, 2, s, tmp,
+             [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+               hipLaunchKernelGGL(k_asm_b, dim3(gp), dim3(256), 0, s, n, pass, dE.p, cnt, rp, col, v);
+             });
+  build_rows(c.BT, n2, np, 2, s, tmp,
+             [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+               hipLaunchKernelGGL(k_asm_bt, dim3(g2), dim3(256), 0, s, n, pass, dE.p, cnt, rp, col, v);
+             });
+  assemble_p1p1(c.Mp, n, dE.p, EM_MP, 0, tmp, s);
+  c.Mp_dinv.alloc(np);
+  hipLaunchKernelGGL(k_diag_inv, dim3(gp), dim3(256), 0, s, np, c.Mp.rowptr.p, c.Mp.col.p, c.Mp.val.p,
+                     c.Mp_dinv.p);
+  c.bnd.alloc(n2);
+  hipLaunchKernelGGL(k_p2_boundary_flags, dim3(g2), dim3(256), 0, s, n, c.bnd.p);
+  FSI_CHECK_LAUNCH();
+  FSI_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------- solid blocks
+// Row l gathers, over the triangles around node l (sorted by element id), the P1
+// stiffness kappa |E| grad l_a . grad l_b and mass |E| (1 + delta_ab) / 12.
+__global__ void k_asm_solid(int64_t ns, const int *__restrict__ n2e_ptr, const int *__restrict__ n2e,
+                            const int *__restrict__ tri, const double *__restrict__ xy,
+                            const int *__restrict__ rowptr, const int *__restrict__ col,
+                            double kappa, double *As, double *Cs) {
+  int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= ns) return;
+  int r0 = rowptr[l], r1 = rowptr[l + 1];
+  for (int k = r0; k < r1; ++k) { As[k] = 0.0; Cs[k] = 0.0; }
+  for (int q = n2e_ptr[l]; q < n2e_ptr[l + 1]; ++q) {
+    int e = n2e[q] >> 2, a = n2e[q] & 3;
+    int v[3] = {tri[3 * e], tri[3 * e + 1], tri[3 * e + 2]};
+    double x[3], y[3];
+    for (int m = 0; m < 3; ++m) { x[m] = xy[v[m]]; y[m] = xy[ns + v[m]]; }
+    double d = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]);
+    double area = 0.5 * d;
+    double gx[3] = {(y[1] - y[2]) / d, (y[2] - y[0]) / d, (y[0] - y[1]) / d};
+    double gy[3] = {(x[2] - x[1]) / d, (x[0] - x[2]) / d, (x[1] - x[0]) / d};
+    for (int b = 0; b < 3; ++b) {
+      int cb = v[b];
+      int pos = r0;
+      while (pos < r1 && col[pos] != cb) ++pos;
+      As[pos] += kappa * area * (gx[a] * gx[b] + gy[a] * gy[b]);
+      Cs[pos] += area * (a == b ? 2.0 : 1.0) / 12.0;
+    }
+  }
+}
+
+__global__ void k_diag_inv(int64_t nrows, const int *rowptr, const int *col, const double *v,
+                           double *dinv) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  double d = 0.0;
+  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
+    if (col[k] == r) d = v[k];
+  dinv[r] = 1.0 / d;
+}
+
+void build_solid(Ctx &c) {
+  hipStream_t s = c.stream;
+  const int64_t ns = c.Ns, nt = c.Nt;
+  // reference areas (validated on the host: counter-clockwise, non-degenerate)
+  std::vector<double> area(nt);
+  for (int64_t e = 0; e < nt; ++e) {
+    const int *t = &c.h_tri[3 * e];
+    for (int m = 0; m < 3; ++m)
+      FSI_REQUIRE(t[m] >= 0 && t[m] < ns, FSI_E_ARG, "solid triangle refers to a missing node");
+    double x0 = c.h_xy[t[0]], y0 = c.h_xy[ns + t[0]];
+    double x1 = c.h_xy[t[1]], y1 = c.h_xy[ns + t[1]];
+    double x2 = c.h_xy[t[2]], y2 = c.h_xy[ns + t[2]];
+    area[e] = 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
+    FSI_REQUIRE(area[e] > 0.0, FSI_E_MESH, "solid reference triangle " + std::to_string(e) +
+                                               " is degenerate or clockwise");
+  }
+  // node -> (element, local vertex), sorted by element
+  std::vector<int> cnt(ns + 1, 0);
+  for (int64_t e = 0; e < nt; ++e)
+    for (int m = 0; m < 3; ++m) cnt[c.h_tri[3 * e + m] + 1]++;
+  for (int64_t l = 0; l < ns; ++l) cnt[l + 1] += cnt[l];
+  std::vector<int> adj(cnt[ns]);
+  std::vector<int> fillp(cnt.begin(), cnt.end() - 1);
+  c.max_adj = 0;
+  for (int64_t e = 0; e < nt; ++e)
+    for (int m = 0; m < 3; ++m) adj[fillp[c.h_tri[3 * e + m]]++] = (int)(4 * e + m);
+  for (int64_t l = 0; l < ns; ++l) {
+    c.max_adj = std::max(c.max_adj, cnt[l + 1] - cnt[l]);
+    FSI_REQUIRE(cnt[l + 1] > cnt[l], FSI_E_MESH, "solid node " + std::to_string(l) + " is in no triangle");
+  }
+  FSI_REQUIRE(4 * nt < (int64_t)INT32_MAX, FSI_E_ARG, "too many solid triangles");
+  // pattern: sorted unique neighbours
+  std::vector<int> rp(ns + 1, 0), cols;
+  cols.reserve(7 * ns);
+  std::vector<int> tmpn;
+  for (int64_t l = 0; l < ns; ++l) {
+    tmpn.clear();
+    for (int q = cnt[l]; q < cnt[l + 1]; ++q) {
+      int e = adj[q] >> 2;
+      for (int m = 0; m < 3; ++m) tmpn.push_back(c.h_tri[3 * e + m]);
+    }
+    std::sort(tmpn.begin(), tmpn.end());
+    tmpn.erase(std::unique(tmpn.begin(), tmpn.end()), tmpn.end());
+    cols.insert(cols.end(), tmpn.begin(), tmpn.end());
+    rp[l + 1] = (int)cols.size();
+  }
+  auto up = [&](auto &buf, const auto &vec) {
+    using T = typename std::decay_t<decltype(vec)>::value_type;
+    buf.alloc(vec.size());
+    FSI_HIP(hipMemcpyAsync(buf.p, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  };
+  up(c.tri, c.h_tri);
+  up(c.ref_xy, c.h_xy);
+  up(c.ref_area, area);
+  up(c.n2e_ptr, cnt);
+  up(c.n2e, adj);
+  c.S.nrows = ns; c.S.ncols = ns; c.S.width = 1; c.S.nnz = (int64_t)cols.size();
+  up(c.S.rowptr, rp);
+  up(c.S.col, cols);
+  c.S.val.alloc(cols.size());
+  c.Cs.alloc(cols.size());
+  hipLaunchKernelGGL(k_asm_solid, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, c.n2e_ptr.p,
+                     c.n2e.p, c.tri.p, c.ref_xy.p, c.S.rowptr.p, c.S.col.p, c.kappa, c.S.val.p,
+                     c.Cs.p);
+  c.Cs_dinv.alloc(ns);
+  hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, c.S.rowptr.p,
+                     c.S.col.p, c.Cs.p, c.Cs_dinv.p);
+  FSI_CHECK_LAUNCH();
+  c.Cs32.alloc(cols.size());
+  convert(c.Cs32.p, c.Cs.p, (int64_t)cols.size(), s);
+  c.Cs_dinv32.alloc(ns);
+  convert(c.Cs_dinv32.p, c.Cs_dinv.p, ns, s);
+  FSI_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------- multigrid transfers
+// Coarse P2 weights at fine P2 lattice node (I, J) of an nf grid (coarse grid nf / 2):
+// the fine node lies in a coarse triangle where the coarse quadratic basis is evaluated
+// exactly (barycentric coordinates are multiples of 1/4).  Returns the entries with
+// non-zero weight at interior coarse nodes, sorted by coarse index.
+__device__ int p2_prolong_row(int I, int J, int nf, int *cidx, double *w) {
+  int nc = nf / 2;
+  int64_t Lc = 2 * nc + 1;
+  int ci = I / 4, cj = J / 4;
+  if (ci > nc - 1) ci = nc - 1;
+  if (cj > nc - 1) cj = nc - 1;
+  double xi = (I - 4 * ci) * 0.25, eta = (J - 4 * cj) * 0.25;
+  int t;
+  double l[3];
+  if (xi >= eta) { t = 0; l[0] = 1.0 - xi; l[1] = xi - eta; l[2] = eta; }
+  else { t = 1; l[0] = 1.0 - eta; l[1] = xi; l[2] = eta - xi; }
+  double phi[6] = {l[0] * (2 * l[0] - 1), l[1] * (2 * l[1] - 1), l[2] * (2 * l[2] - 1),
+                   4 * l[0] * l[1], 4 * l[1] * l[2], 4 * l[2] * l[0]};
+  int cnt = 0;
+  for (int b = 0; b < 6; ++b) {
+    if (phi[b] == 0.0) continue;
+    int Ic = 2 * ci + kOff[t][b][0], Jc = 2 * cj + kOff[t][b][1];
+    if (Ic == 0 || Jc == 0 || Ic == 2 * nc || Jc == 2 * nc) continue;
+    int idx = (int)(Jc * Lc + Ic);
+    int p = cnt++;
+    while (p > 0 && cidx[p - 1] > idx) { cidx[p] = cidx[p - 1]; w[p] = w[p - 1]; --p; }
+    cidx[p] = idx;
+    w[p] = phi[b];
+  }
+  return cnt;
+}
+
+__global__ void k_p2_prolong(int nf, int pass, int *cnt, const int *rowptr, int *col, double *V) {
+  int64_t L = 2 * nf + 1;
+  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= L * L) return;
+  int I = (int)(row % L), J = (int)(row / L);
+  int ci[6];
+  double w[6];
+  int m = p2_boundary(I, J, nf) ? 0 : p2_prolong_row(I, J, nf, ci, w);
+  if (!pass) { cnt[row] = m; return; }
+  int k = rowptr[row];
+  for (int q = 0; q < m; ++q) { col[k + q] = ci[q]; V[k + q] = w[q]; }
+}
+
+__global__ void k_p2_restrict(int nf, int pass, int *cnt, const int *rowptr, int *col, double *V) {
+  int nc = nf / 2;
+  int64_t Lc = 2 * nc + 1, L = 2 * nf + 1;
+  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= Lc * Lc) return;
+  int Ic = (int)(row % Lc), Jc = (int)(row / Lc);
+  int k = pass ? rowptr[row] : 0, c = 0;
+  if (!p2_boundary(Ic, Jc, nc)) {
+    for (int J = 2 * Jc - 4; J <= 2 * Jc + 4; ++J)
+      for (int I = 2 * Ic - 4; I <= 2 * Ic + 4; ++I) {
+        if (I < 0 || J < 0 || I > 2 * nf || J > 2 * nf || p2_boundary(I, J, nf)) continue;
+        int ci[6];
+        double w[6];
+        int m = p2_prolong_row(I, J, nf, ci, w);
+        for (int q = 0; q < m; ++q)
+          if (ci[q] == row) {
+            if (pass) { col[k] = (int)((int64_t)J * L + I); V[k] = w[q]; ++k; }
+            ++c;
+          }
+      }
+  }
+  if (!pass) cnt[row] = c;
+}
+
+// P1 (pressure) prolongation: linear interpolation on the nested triangulation; fine
+// node 0 and coarse node 0 (the pinned pressure node) are excluded.
+__device__ int p1_prolong_row(int i, int j, int nf, int *cidx, double *w) {
+  int nc = nf / 2;
+  int64_t Lc = nc + 1;
+  int ci = i >> 1, cj = j >> 1;
+  int pts[2][2];
+  int m;
+  if (!(i & 1) && !(j & 1)) { pts[0][0] = ci; pts[0][1] = cj; m = 1; }
+  else if ((i & 1) && !(j & 1)) { pts[0][0] = ci; pts[0][1] = cj; pts[1][0] = ci + 1; pts[1][1] = cj; m = 2; }
+  else if (!(i & 1) && (j & 1)) { pts[0][0] = ci; pts[0][1] = cj; pts[1][0] = ci; pts[1][1] = cj + 1; m = 2; }
+  else { pts[0][0] = ci; pts[0][1] = cj; pts[1][0] = ci + 1; pts[1][1] = cj + 1; m = 2; }
+  int cnt = 0;
+  for (int q = 0; q < m; ++q) {
+    int idx = (int)(pts[q][1] * Lc + pts[q][0]);
+    if (idx == 0) continue;
+    cidx[cnt] = idx;
+    w[cnt] = (m == 1) ? 1.0 : 0.5;
+    ++cnt;
+  }
+  return cnt;
+}
+
+__global__ void k_p1_prolong(int nf, int pass, int *cnt, const int *rowptr, int *col, double *V) {
+  int64_t L = nf + 1;
+  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= L * L) return;
+  int ci[2];
+  double w[2];
+  int m = row == 0 ? 0 : p1_prolong_row((int)(row % L), (int)(row / L), nf, ci, w);
+  if (!pass) { cnt[row] = m; return; }
+  int k = rowptr[row];
+  for (int q = 0; q < m; ++q) { col[k + q] = ci[q]; V[k + q] = w[q]; }
+}
+
+__global__ void k_p1_restrict(int nf, int pass, int *cnt, const int *rowptr, int *col, double *V) {
+  int nc = nf / 2;
+  int64_t Lc = nc + 1, L = nf + 1;
+  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= Lc * Lc) return;
+  int ic = (int)(row % Lc), jc = (int)(row / Lc);
+  int k = pass ? rowptr[row] : 0, c = 0;
+  if (row != 0) {
+    for (int j = 2 * jc - 1; j <= 2 * jc + 1; ++j)
+      for (int i = 2 * ic - 1; i <= 2 * ic + 1; ++i) {
+        if (i < 0 || j < 0 || i > nf || j > nf) continue;
+        int64_t f = (int64_t)j * L + i;
+        if (f == 0) continue;
+        int cidx[2];
+        double w[2];
+        int m = p1_prolong_row(i, j, nf, cidx, w);
+        for (int q = 0; q < m; ++q)
+          if (cidx[q] == row) {
+            if (pass) { col[k] = (int)f; V[k] = w[q]; ++k; }
+            ++c;
+          }
+      }
+  }
+  if (!pass) cnt[row] = c;
+}
+
+// Inverse of the 2x2 diagonal blocks (width 4) or of the scalar diagonal (width 1).
+__global__ void k_block_diag_inv(int64_t nrows, int width, const int *rowptr, const int *col,
+                                 const double *v, double *dinv) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+    if (col[k] != r) continue;
+    if (width == 4) {
+      double a = v[4 * (int64_t)k], b = v[4 * (int64_t)k + 1], c = v[4 * (int64_t)k + 2],
+             d = v[4 * (int64_t)k + 3];
+      double det = a * d - b * c;
+      dinv[4 * r] = d / det;
+      dinv[4 * r + 1] = -b / det;
+      dinv[4 * r + 2] = -c / det;
+      dinv[4 * r + 3] = a / det;
+    } else {
+      dinv[r] = 1.0 / v[k];
+    }
+  }
+}
+
+// z = Dinv y (2x2 blocks: NC = 2, stride nodes; scalar: NC = 1)
+__global__ void k_apply_dinv(int64_t nodes, int width, const double *dinv, const double *y,
+                             double *z) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nodes) return;
+  if (width == 4) {
+    double a = y[r], b = y[nodes + r];
+    z[r] = dinv[4 * r] * a + dinv[4 * r + 1] * b;
+    z[nodes + r] = dinv[4 * r + 2] * a + dinv[4 * r + 3] * b;
+  } else {
+    z[r] = dinv[r] * y[r];
+  }
+}
+
+static double dev_norm(const double *d, int64_t n, DevBuf<double> &part, DevBuf<double> &out,
+                       hipStream_t s) {
+  multidot(d, 0, 1, d, n, out.p, part, s);
+  double h = 0.0;
+  FSI_HIP(hipMemcpyAsync(&h, out.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  FSI_HIP(hipStreamSynchronize(s));
+  return std::sqrt(h);
+}
+
+// lambda_max(D^{-1} A) by power iteration from a fixed pseudo-random start.
+static double power_lmax(MgLevel &L, int comps, hipStream_t s) {
+  int64_t m = comps * L.nodes;
+  std::vector<double> h(m);
+  uint64_t st = 0x9E3779B97F4A7C15ull;
+  for (int64_t i = 0; i < m; ++i) {
+    st ^= st << 13; st ^= st >> 7; st ^= st << 17;
+    h[i] = (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  }
+  DevBuf<double> x(m), y(m), part, out(1);
+  FSI_HIP(hipMemcpyAsync(x.p, h.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
+  double lam = 0.0, nx = dev_norm(x.p, m, part, out, s);
+  for (int it = 0; it < 30; ++it) {
+    if (L.A.width == 4)
+      spmv<double, 4, 2, SP_APPLY>(L.A.nrows, L.A.rowptr.p, L.A.col.p, L.A.val.p, x.p, L.nodes,
+                                   y.p, L.nodes, s);
+    else
+      spmv<double, 1, 1, SP_APPLY>(L.A.nrows, L.A.rowptr.p, L.A.col.p, L.A.val.p, x.p, L.nodes,
+                                   y.p, L.nodes, s);
+    hipLaunchKernelGGL(k_apply_dinv, dim3(grid_for(L.nodes, 256)), dim3(256), 0, s, L.nodes,
+                       L.A.width, L.dinv.p, y.p, x.p);
+    FSI_CHECK_LAUNCH();
+    double nz = dev_norm(x.p, m, part, out, s);
+    lam = nz / nx;
+    axpby(x.p, x.p, 1.0 / nz, 0.0, m, s);
+    nx = 1.0;
+  }
+  return lam;
+}
+
+// Dense inverse of the coarsest operator by Gauss-Jordan elimination with partial
+// pivoting (host, FP64).  Unknown order: component-major ([x | y] for velocity).
+static void coarse_inverse(Mg &mg, hipStream_t s) {
+  MgLevel &L = mg.lv.back();
+  const int64_t nodes = L.nodes, m = mg.comps * nodes;
+  FSI_REQUIRE(m <= 6000, FSI_E_ARG, "coarsest multigrid level too large: n must be 2^k * m with m <= 6");
+  std::vector<int> rp(L.A.nrows + 1), cl(L.A.nnz);
+  std::vector<double> v(L.A.nnz * L.A.width);
+  FSI_HIP(hipMemcpyAsync(rp.data(), L.A.rowptr.p, rp.size() * 4, hipMemcpyDeviceToHost, s));
+  FSI_HIP(hipMemcpyAsync(cl.data(), L.A.col.p, cl.size() * 4, hipMemcpyDeviceToHost, s));
+  FSI_HIP(hipMemcpyAsync(v.data(), L.A.val.p, v.size() * 8, hipMemcpyDeviceToHost, s));
+  FSI_HIP(hipStreamSynchronize(s));
+  std::vector<double> A(m * m, 0.0), X(m * m, 0.0);
+  for (int64_t r = 0; r < nodes; ++r)
+    for (int k = rp[r]; k < rp[r + 1]; ++k) {
+      int64_t cc = cl[k];
+      if (mg.comps == 2) {
+        A[r * m + cc] = v[4 * k];
+        A[r * m + nodes + cc] = v[4 * k + 1];
+        A[(nodes + r) * m + cc] = v[4 * k + 2];
+        A[(nodes + r) * m + nodes + cc] = v[4 * k + 3];
+      } else {
+        A[r * m + cc] = v[k];
+      }
+    }
+  for (int64_t i = 0; i < m; ++i) X[i * m + i] = 1.0;
+  for (int64_t col = 0; col < m; ++col) {
+    int64_t piv = col;
+    for (int64_t r = col + 1; r < m; ++r)
+      if (std::fabs(A[r * m + col]) > std::fabs(A[piv * m + col])) piv = r;
+    FSI_REQUIRE(A[piv * m + col] != 0.0, FSI_E_ARG, "singular coarse operator");
+    if (piv != col)
+      for (int64_t k = 0; k < m; ++k) {
+        std::swap(A[piv * m + k], A[col * m + k]);
+        std::swap(X[piv * m + k], X[col * m + k]);
+      }
+    double inv = 1.0 / A[col * m + col];
+    for (int64_t k = 0; k < m; ++k) { A[col * m + k] *= inv; X[col * m + k] *= inv; }
+    for (int64_t r = 0; r < m; ++r) {
+      if (r == col) continue;
+      double f = A[r * m + col];
+      if (f == 0.0) continue;
+      for (int64_t k = 0; k < m; ++k) {
+        A[r * m + k] -= f * A[col * m + k];
+        X[r * m + k] -= f * X[col * m + k];
+      }
+    }
+  }
+  mg.ncoarse = m;
+  mg.cinv.alloc(m * m);
+  FSI_HIP(hipMemcpyAsync(mg.cinv.p, X.data(), m * m * 8, hipMemcpyHostToDevice, s));
+  mg.cinv32.alloc(m * m);
+  convert(mg.cinv32.p, mg.cinv.p, m * m, s);
+  FSI_HIP(hipStreamSynchronize(s));
+}
+
+size_t Mg::bytes() const {
+  size_t b = cinv.bytes() + cinv32.bytes();
+  for (auto &L : lv) {
+    b += L.A.bytes() + L.P.bytes() + L.R.bytes() + L.dinv.bytes() + L.dinv32.bytes();
+    for (int i = 0; i < 5; ++i) b += L.w64[i].bytes() + L.w32[i].bytes();
+  }
+  return b;
+}
+
+void build_multigrid(Ctx &c) {
+  hipStream_t s = c.stream;
+  DevBuf<int> tmp;
+  std::vector<int> ns;
+  for (int m = c.n;; m /= 2) {
+    ns.push_back(m);
+    if (m <= 4 || (m & 1)) break;
+  }
+  // velocity: A_f per level (re-discretised = Galerkin for nested P2 spaces)
+  c.mgu.comps = 2;
+  c.mgp.comps = 1;
+  c.mgu.lv.resize(ns.size());
+  c.mgp.lv.resize(ns.size());
+  for (size_t l = 0; l < ns.size(); ++l) {
+    int m = ns[l];
+    std::vector<double> hE;
+    element_tables(m, c.nu, hE);
+    DevBuf<double> dE(hE.size());
+    FSI_HIP(hipMemcpyAsync(dE.p, hE.data(), hE.size() * 8, hipMemcpyHostToDevice, s));
+    MgLevel &U = c.mgu.lv[l];
+    MgLevel &P = c.mgp.lv[l];
+    U.n = P.n = m;
+    U.nodes = (int64_t)(2 * m + 1) * (2 * m + 1);
+    P.nodes = (int64_t)(m + 1) * (m + 1);
+    assemble_p2p2(U.A, nullptr, m, dE.p, c.rho / c.dt, tmp, s);
+    assemble_p1p1(P.A, m, dE.p, EM_LP, 1, tmp, s);
+    FSI_HIP(hipStreamSynchronize(s));
+    U.dinv.alloc(4 * U.nodes);
+    P.dinv.alloc(P.nodes);
+    hipLaunchKernelGGL(k_block_diag_inv, dim3(grid_for(U.nodes, 256)), dim3(256), 0, s, U.nodes, 4,
+                       U.A.rowptr.p, U.A.col.p, U.A.val.p, U.dinv.p);
+    hipLaunchKernelGGL(k_block_diag_inv, dim3(grid_for(P.nodes, 256)), dim3(256), 0, s, P.nodes, 1,
+                       P.A.rowptr.p, P.A.col.p, P.A.val.p, P.dinv.p);
+    FSI_CHECK_LAUNCH();
+    U.lmax = 1.1 * power_lmax(U, 2, s);
+    P.lmax = 1.1 * power_lmax(P, 1, s);
+    if (l + 1 < ns.size()) {
+      int64_t nc2 = (int64_t)(m + 1) * (m + 1);          // coarse P2 nodes = (2 (m/2) + 1)^2
+      int64_t nc1 = (int64_t)(m / 2 + 1) * (m / 2 + 1);
+      unsigned gf2 = grid_for(U.nodes, 256), gc2 = grid_for(nc2, 256);
+      build_rows(U.P, U.nodes, nc2, 1, s, tmp,
+                 [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+                   hipLaunchKernelGGL(k_p2_prolong, dim3(gf2), dim3(256), 0, s, m, pass, cnt, rp, col, v);
+                 });
+      build_rows(U.R, nc2, U.nodes, 1, s, tmp,
+                 [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+                   hipLaunchKernelGGL(k_p2_restrict, dim3(gc2), dim3(256), 0, s, m, pass, cnt, rp, col, v);
+                 });
+      unsigned gf1 = grid_for(P.nodes, 256), gc1 = grid_for(nc1, 256);
+      build_rows(P.P, P.nodes, nc1, 1, s, tmp,
+                 [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+                   hipLaunchKernelGGL(k_p1_prolong, dim3(gf1), dim3(256), 0, s, m, pass, cnt, rp, col, v);
+                 });
+      build_rows(P.R, nc1, P.nodes, 1, s, tmp,
+                 [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+                   hipLaunchKernelGGL(k_p1_restrict, dim3(gc1), dim3(256), 0, s, m, pass, cnt, rp, col, v);
+                 });
+    }
+    for (int i = 0; i < 5; ++i) {
+      U.w64[i].alloc(2 * U.nodes);
+      P.w64[i].alloc(P.nodes);
+    }
+  }
+  coarse_inverse(c.mgu, s);
+  coarse_inverse(c.mgp, s);
+  FSI_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace fsi

@@ -1,0 +1,511 @@
+// C_f(X^n) on the device (Sec. 4, the coupling assembly after eq. (matrix)):
+//   (C_f)_lj = sum_E (|E| / |X^n(E)|) int_{X^n(E)} lam_l(x) phi_j(x) dx,
+// where X^n is affine on each solid triangle E, lam_l are the barycentric coordinates of
+// the mapped triangle and phi_j the P2 fluid basis.  The paper finds the fluid elements
+// met by X^n(E) through its bounding box on the Cartesian grid and clips with the
+// Sutherland-Hodgman algorithm; each piece is integrated exactly.
+//
+// Pipeline (all on the stream, no floating-point atomics):
+//   1. per solid triangle: validity (area > 0, inside [0,1]^2) and candidate cell count
+//   2. scan -> candidate offsets
+//   3. per candidate cell: clip, count kept pieces (fluid triangles T0/T1 of the cell)
+//   4. scan -> piece offsets
+//   5. per candidate cell: clip again, write (E, T) and the 3x6 local matrix of each piece
+//   6. per solid node (one wavefront): rows of C_f with a window bitmap in LDS (columns in
+//      ascending order), values summed in a fixed order
+//   7. C_f^T: counting transpose with a per-row sort (deterministic)
+//
+// Clipping arithmetic (must be reproduced bit for bit wherever the intersection list is
+// compared): clip against x >= x_i, x <= x_{i+1}, y >= y_j, y <= y_{j+1}, then against
+// (x - x_i) - (y - y_j) >= 0 (T0) or (y - y_j) - (x - x_i) >= 0 (T1); keep a vertex if its
+// value is >= 0, emit a crossing a + t (b - a), t = f_a / (f_a - f_b), only for strictly
+// opposite signs, with the axis coordinate set to the line value; keep a piece iff its fan
+// area from vertex 0 exceeds 5e-11 h^2.  This file is compiled with -ffp-contract=off so
+// that no product is fused into an addition.
+#include <cmath>
+
+#include "ctx.h"
+#include "kernels.h"
+
+namespace fsi {
+
+constexpr int kMaxPoly = 12;       // a triangle clipped by 5 half-planes has <= 8 vertices
+constexpr int kWinCap = 4096;      // LDS window of P2 nodes per C_f row (64 x 64)
+
+enum { DF_MESH = 1, DF_CAP = 2 };
+
+struct Pt {
+  double x, y;
+};
+
+__device__ __forceinline__ void load_tri(const double *X, int64_t ns, const int *tri, int e, Pt *P) {
+  for (int m = 0; m < 3; ++m) {
+    int v = tri[3 * e + m];
+    P[m].x = X[v];
+    P[m].y = X[ns + v];
+  }
+}
+
+__device__ __forceinline__ double tri_area(const Pt *P) {
+  return 0.5 * ((P[1].x - P[0].x) * (P[2].y - P[0].y) - (P[2].x - P[0].x) * (P[1].y - P[0].y));
+}
+
+__device__ __forceinline__ void cell_range(const Pt *P, int n, int &i0, int &i1, int &j0, int &j1) {
+  double xmin = fmin(fmin(P[0].x, P[1].x), P[2].x), xmax = fmax(fmax(P[0].x, P[1].x), P[2].x);
+  double ymin = fmin(fmin(P[0].y, P[1].y), P[2].y), ymax = fmax(fmax(P[0].y, P[1].y), P[2].y);
+  double dn = (double)n;
+  i0 = (int)floor(xmin * dn);
+  i1 = (int)floor(xmax * dn);
+  j0 = (int)floor(ymin * dn);
+  j1 = (int)floor(ymax * dn);
+  i0 = min(max(i0, 0), n - 1);
+  i1 = min(max(i1, 0), n - 1);
+  j0 = min(max(j0, 0), n - 1);
+  j1 = min(max(j1, 0), n - 1);
+}
+
+// keep coord(axis) >= c (ge) or <= c
+__device__ __forceinline__ int clip_axis(const Pt *in, int m, Pt *out, int axis, double c, bool ge) {
+  int k = 0;
+  for (int q = 0; q < m; ++q) {
+    Pt a = in[q], b = in[(q + 1) % m];
+    double av = axis ? a.y : a.x, bv = axis ? b.y : b.x;
+    double fa = ge ? (av - c) : (c - av);
+    double fb = ge ? (bv - c) : (c - bv);
+    if (fa >= 0.0) out[k++] = a;
+    if ((fa > 0.0 && fb < 0.0) || (fa < 0.0 && fb > 0.0)) {
+      double t = fa / (fa - fb);
+      if (axis == 0) out[k++] = Pt{c, a.y + t * (b.y - a.y)};
+      else out[k++] = Pt{a.x + t * (b.x - a.x), c};
+    }
+  }
+  return k;
+}
+
+__device__ __forceinline__ int clip_diag(const Pt *in, int m, Pt *out, double xi, double yj, bool upper) {
+  int k = 0;
+  for (int q = 0; q < m; ++q) {
+    Pt a = in[q], b = in[(q + 1) % m];
+    double fa, fb;
+    if (upper) {
+      fa = (a.y - yj) - (a.x - xi);
+      fb = (b.y - yj) - (b.x - xi);
+    } else {
+      fa = (a.x - xi) - (a.y - yj);
+      fb = (b.x - xi) - (b.y - yj);
+    }
+    if (fa >= 0.0) out[k++] = a;
+    if ((fa > 0.0 && fb < 0.0) || (fa < 0.0 && fb > 0.0)) {
+      double t = fa / (fa - fb);
+      out[k++] = Pt{a.x + t * (b.x - a.x), a.y + t * (b.y - a.y)};
+    }
+  }
+  return k;
+}
+
+__device__ __forceinline__ double fan_area(const Pt *p, int m) {
+  if (m < 3) return 0.0;
+  double s = 0.0;
+  for (int k = 1; k < m - 1; ++k)
+    s += (p[k].x - p[0].x) * (p[k + 1].y - p[0].y) - (p[k + 1].x - p[0].x) * (p[k].y - p[0].y);
+  return 0.5 * s;
+}
+
+// Square clip of the mapped triangle with cell (i, j); returns the vertex count in sq.
+__device__ __forceinline__ int clip_cell(const Pt *P, int n, int i, int j, Pt *sq) {
+  Pt a[kMaxPoly], b[kMaxPoly];
+  double dn = (double)n;
+  double xi = (double)i / dn, xi1 = (double)(i + 1) / dn;
+  double yj = (double)j / dn, yj1 = (double)(j + 1) / dn;
+  int m = clip_axis(P, 3, a, 0, xi, true);
+  m = clip_axis(a, m, b, 0, xi1, false);
+  m = clip_axis(b, m, a, 1, yj, true);
+  m = clip_axis(a, m, sq, 1, yj1, false);
+  return m;
+}
+
+// bit t set iff the piece with fluid triangle t of cell (i, j) is kept; the pieces are
+// returned in q[t] / mq[t].
+__device__ __forceinline__ int clip_pieces(const Pt *P, int n, int i, int j, Pt q[2][kMaxPoly], int mq[2]) {
+  Pt sq[kMaxPoly];
+  int m = clip_cell(P, n, i, j, sq);
+  int mask = 0;
+  mq[0] = mq[1] = 0;
+  if (m < 3) return 0;
+  double dn = (double)n;
+  double xi = (double)i / dn, yj = (double)j / dn;
+  double h = 1.0 / dn;
+  double tau = 5e-11 * h * h;
+  for (int t = 0; t < 2; ++t) {
+    int k = clip_diag(sq, m, q[t], xi, yj, t == 1);
+    if (k >= 3 && fan_area(q[t], k) > tau) {
+      mask |= 1 << t;
+      mq[t] = k;
+    }
+  }
+  return mask;
+}
+
+__global__ void k_cand_count(int64_t nt, int64_t ns, int n, const double *__restrict__ X,
+                             const int *__restrict__ tri, int *cnt, int *flag) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nt) return;
+  Pt P[3];
+  load_tri(X, ns, tri, (int)e, P);
+  bool ok = tri_area(P) > 0.0;
+  for (int m = 0; m < 3; ++m)
+    ok = ok && P[m].x >= 0.0 && P[m].x <= 1.0 && P[m].y >= 0.0 && P[m].y <= 1.0;
+  if (!ok) {
+    atomicOr(flag, DF_MESH);
+    cnt[e] = 0;
+    return;
+  }
+  int i0, i1, j0, j1;
+  cell_range(P, n, i0, i1, j0, j1);
+  cnt[e] = (i1 - i0 + 1) * (j1 - j0 + 1);
+}
+
+__device__ __forceinline__ int find_owner(const int *off, int64_t nt, int64_t c) {
+  // largest e with off[e] <= c  (off is non-decreasing, off[0] = 0)
+  int64_t lo = 0, hi = nt;   // answer in [0, nt)
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  return (int)lo;
+}
+
+__device__ __forceinline__ void cand_cell(const Pt *P, int n, int q, int &i, int &j) {
+  int i0, i1, j0, j1;
+  cell_range(P, n, i0, i1, j0, j1);
+  int w = i1 - i0 + 1;
+  i = i0 + q % w;
+  j = j0 + q / w;
+}
+
+__global__ void k_clip_count(int64_t ncand, int64_t nt, int64_t ns, int n, const double *__restrict__ X,
+                             const int *__restrict__ tri, const int *__restrict__ cand_off,
+                             int *piece_cnt) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncand) return;
+  int e = find_owner(cand_off, nt, c);
+  Pt P[3];
+  load_tri(X, ns, tri, e, P);
+  int i, j;
+  cand_cell(P, n, (int)(c - cand_off[e]), i, j);
+  Pt q[2][kMaxPoly];
+  int mq[2];
+  int mask = clip_pieces(P, n, i, j, q, mq);
+  piece_cnt[c] = (mask & 1) + ((mask >> 1) & 1);
+}
+
+// Degree-4 six-point rule (Dunavant) on each fan triangle: exact for the cubic
+// integrand lam_l * phi_j.
+__constant__ double kQa[2] = {0.445948490915965, 0.091576213509771};
+__constant__ double kQw[2] = {0.223381589678011, 0.109951743655322};
+
+__device__ void piece_matrix(const Pt *P, const Pt *q, int m, int i, int j, int t, int n,
+                             double ratio, double *L) {
+  double acc[18];
+  for (int k = 0; k < 18; ++k) acc[k] = 0.0;
+  double D = (P[1].x - P[0].x) * (P[2].y - P[0].y) - (P[2].x - P[0].x) * (P[1].y - P[0].y);
+  double dn = (double)n;
+  double xi0 = (double)i / dn, yj0 = (double)j / dn;
+  for (int k = 1; k < m - 1; ++k) {
+    Pt A = q[0], B = q[k], C = q[k + 1];
+    double a2 = 0.5 * ((B.x - A.x) * (C.y - A.y) - (C.x - A.x) * (B.y - A.y));
+    for (int g = 0; g < 6; ++g) {
+      int grp = g / 3, rot = g % 3;
+      double la = kQa[grp], lb = 1.0 - 2.0 * la;
+      double l[3];
+      l[rot] = lb; l[(rot + 1) % 3] = la; l[(rot + 2) % 3] = la;
+      double w = kQw[grp] * a2;
+      double x = l[0] * A.x + l[1] * B.x + l[2] * C.x;
+      double y = l[0] * A.y + l[1] * B.y + l[2] * C.y;
+      // barycentric coordinates in the mapped solid triangle
+      double lam[3];
+      lam[0] = ((P[1].x - x) * (P[2].y - y) - (P[2].x - x) * (P[1].y - y)) / D;
+      lam[1] = ((P[2].x - x) * (P[0].y - y) - (P[0].x - x) * (P[2].y - y)) / D;
+      lam[2] = 1.0 - lam[0] - lam[1];
+      // P2 basis on the fluid triangle (local coordinates of the cell)
+      double xs = (x - xi0) * dn, ys = (y - yj0) * dn;
+      double mu[3];
+      if (t == 0) { mu[0] = 1.0 - xs; mu[1] = xs - ys; mu[2] = ys; }
+      else { mu[0] = 1.0 - ys; mu[1] = xs; mu[2] = ys - xs; }
+      double phi[6] = {mu[0] * (2 * mu[0] - 1), mu[1] * (2 * mu[1] - 1), mu[2] * (2 * mu[2] - 1),
+                       4 * mu[0] * mu[1], 4 * mu[1] * mu[2], 4 * mu[2] * mu[0]};
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 6; ++b) acc[a * 6 + b] += w * lam[a] * phi[b];
+    }
+  }
+  for (int k = 0; k < 18; ++k) L[k] = ratio * acc[k];
+}
+
+__global__ void k_clip_emit(int64_t ncand, int64_t nt, int64_t ns, int n, const double *__restrict__ X,
+                            const int *__restrict__ tri, const double *__restrict__ ref_area,
+                            const int *__restrict__ cand_off, const int *__restrict__ piece_off,
+                            int *pair_E, int *pair_T, double *piece_L) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncand) return;
+  int e = find_owner(cand_off, nt, c);
+  Pt P[3];
+  load_tri(X, ns, tri, e, P);
+  int i, j;
+  cand_cell(P, n, (int)(c - cand_off[e]), i, j);
+  Pt q[2][kMaxPoly];
+  int mq[2];
+  int mask = clip_pieces(P, n, i, j, q, mq);
+  int p = piece_off[c];
+  double ratio = ref_area[e] / tri_area(P);
+  for (int t = 0; t < 2; ++t) {
+    if (!(mask & (1 << t))) continue;
+    pair_E[p] = e;
+    pair_T[p] = 2 * (j * n + i) + t;
+    piece_matrix(P, q[t], mq[t], i, j, t, n, ratio, piece_L + 18 * (int64_t)p);
+    ++p;
+  }
+}
+
+__global__ void k_elem_piece_off(int64_t nt, const int *cand_off, const int *piece_off, int *e_piece) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > nt) return;
+  e_piece[e] = piece_off[cand_off[e]];
+}
+
+// ---- rows of C_f: one wavefront per solid node
+__constant__ int kOffC[2][6][2] = {{{0, 0}, {2, 0}, {2, 2}, {1, 0}, {2, 1}, {1, 1}},
+                                   {{0, 0}, {2, 2}, {0, 2}, {1, 1}, {1, 2}, {0, 1}}};
+
+__global__ void __launch_bounds__(kWave) k_cf_rows(int pass, int64_t ns, int n,
+                                                   const int *__restrict__ n2e_ptr,
+                                                   const int *__restrict__ n2e,
+                                                   const int *__restrict__ e_piece,
+                                                   const int *__restrict__ pair_T,
+                                                   const double *__restrict__ piece_L,
+                                                   int *cnt, const int *rowptr, int *col,
+                                                   double *val, int *flag) {
+  __shared__ int wflag[kWinCap];
+  __shared__ double wval[kWinCap];
+  int64_t l = blockIdx.x;
+  if (l >= ns) return;
+  int lane = threadIdx.x;
+  const int L = 2 * n + 1;
+  // window of lattice nodes covered by the pieces around node l
+  int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
+  int q0 = n2e_ptr[l], q1 = n2e_ptr[l + 1];
+  for (int q = q0; q < q1; ++q) {
+    int e = n2e[q] >> 2;
+    for (int p = e_piece[e] + lane; p < e_piece[e + 1]; p += kWave) {
+      int T = pair_T[p];
+      int cell = T >> 1;
+      int ci = cell % n, cj = cell / n;
+      imin = min(imin, 2 * ci); imax = max(imax, 2 * ci + 2);
+      jmin = min(jmin, 2 * cj); jmax = max(jmax, 2 * cj + 2);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    imin = min(imin, __shfl_xor(imin, off, kWave));
+    imax = max(imax, __shfl_xor(imax, off, kWave));
+    jmin = min(jmin, __shfl_xor(jmin, off, kWave));
+    jmax = max(jmax, __shfl_xor(jmax, off, kWave));
+  }
+  if (imax < 0) {              // no pieces (cannot happen for a valid map)
+    if (!pass && lane == 0) cnt[l] = 0;
+    return;
+  }
+  int wI = imax - imin + 1, wJ = jmax - jmin + 1;
+  int W = wI * wJ;
+  if (W > kWinCap) {
+    if (lane == 0) {
+      atomicOr(flag, DF_CAP);
+      if (!pass) cnt[l] = 0;
+    }
+    return;
+  }
+  for (int p = lane; p < W; p += kWave) { wflag[p] = 0; wval[p] = 0.0; }
+  __syncthreads();
+  // mark the columns
+  for (int q = q0; q < q1; ++q) {
+    int e = n2e[q] >> 2;
+    for (int p = e_piece[e] + lane; p < e_piece[e + 1]; p += kWave) {
+      int T = pair_T[p], t = T & 1, cell = T >> 1;
+      int ci = cell % n, cj = cell / n;
+      for (int b = 0; b < 6; ++b) {
+        int I = 2 * ci + kOffC[t][b][0] - imin, J = 2 * cj + kOffC[t][b][1] - jmin;
+        wflag[J * wI + I] = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (!pass) {
+    int c = 0;
+    for (int p = lane; p < W; p += kWave) c += wflag[p];
+    c = wave_sum(c);
+    if (lane == 0) cnt[l] = c;
+    return;
+  }
+  // values: item order is fixed (adjacency, piece, local node); window position p is
+  // summed by lane p % 64 only, so the order of every sum is fixed.
+  for (int q = q0; q < q1; ++q) {
+    int e = n2e[q] >> 2, a = n2e[q] & 3;
+    for (int p = e_piece[e]; p < e_piece[e + 1]; ++p) {
+      int T = pair_T[p], t = T & 1, cell = T >> 1;
+      int ci = cell % n, cj = cell / n;
+      for (int b = 0; b < 6; ++b) {
+        int I = 2 * ci + kOffC[t][b][0] - imin, J = 2 * cj + kOffC[t][b][1] - jmin;
+        int pos = J * wI + I;
+        if ((pos & (kWave - 1)) == lane) wval[pos] += piece_L[18 * (int64_t)p + a * 6 + b];
+      }
+    }
+  }
+  __syncthreads();
+  // compact in window order (= ascending column index)
+  int base = rowptr[l];
+  for (int p0 = 0; p0 < W; p0 += kWave) {
+    int p = p0 + lane;
+    int f = (p < W) ? wflag[p] : 0;
+    int incl = f;
+    for (int off = 1; off < kWave; off <<= 1) {
+      int t = __shfl_up(incl, off, kWave);
+      if (lane >= off) incl += t;
+    }
+    if (f) {
+      int I = imin + p % wI, J = jmin + p / wI;
+      bool bndc = I == 0 || J == 0 || I == 2 * n || J == 2 * n;
+      col[base + incl - 1] = J * L + I;
+      val[base + incl - 1] = bndc ? 0.0 : wval[p];
+    }
+    base += __shfl(incl, kWave - 1, kWave);
+  }
+}
+
+// ---- transpose
+__global__ void k_count_cols(int64_t nnz, const int *col, int *cnt) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) atomicAdd(&cnt[col[k]], 1);
+}
+
+__global__ void k_scatter_t(int64_t nrows, const int *rowptr, const int *col, const double *val,
+                            const int *tptr, int *fill, int *tcol, double *tval) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+    int c = col[k];
+    int pos = tptr[c] + atomicAdd(&fill[c], 1);
+    tcol[pos] = (int)r;
+    tval[pos] = val[k];
+  }
+}
+
+__global__ void k_sort_rows(int64_t nrows, const int *rowptr, int *col, double *val) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int k0 = rowptr[r], k1 = rowptr[r + 1];
+  for (int k = k0 + 1; k < k1; ++k) {
+    int c = col[k];
+    double v = val[k];
+    int p = k;
+    while (p > k0 && col[p - 1] > c) { col[p] = col[p - 1]; val[p] = val[p - 1]; --p; }
+    col[p] = c;
+    val[p] = v;
+  }
+}
+
+static int read_int(const int *d, hipStream_t s) {
+  int h = 0;
+  FSI_HIP(hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, s));
+  FSI_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+static void check_flags(Ctx &c) {
+  int f = read_int(c.dflag.p, c.stream);
+  if (f) fill(c.dflag.p, 1, 0, c.stream);
+  FSI_REQUIRE(!(f & DF_MESH), FSI_E_MESH, "X^n maps a solid triangle to a degenerate/inverted triangle or outside [0,1]^2");
+  FSI_REQUIRE(!(f & DF_CAP), FSI_E_CAPACITY, "coupling pieces around one solid node span more than 4096 P2 nodes");
+}
+
+void assemble_coupling(Ctx &c, const double *Xn, bool) {
+  hipStream_t s = c.stream;
+  const int64_t nt = c.Nt, ns = c.Ns;
+  const int n = c.n;
+  DevBuf<int> tmp;
+  if (!c.dflag.p) {
+    c.dflag.alloc(4);
+    fill(c.dflag.p, 4, 0, s);
+  }
+  c.have_cf = false;
+  c.cand_off.reserve(nt + 1);
+  hipLaunchKernelGGL(k_cand_count, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, ns, n, Xn, c.tri.p,
+                     c.cand_off.p, c.dflag.p);
+  FSI_CHECK_LAUNCH();
+  scan_excl(c.cand_off.p, c.cand_off.p, nt, tmp, s);
+  check_flags(c);
+  int ncand = read_int(c.cand_off.p + nt, s);
+  c.n_cand = ncand;
+  c.piece_cnt.reserve(ncand + 1);
+  hipLaunchKernelGGL(k_clip_count, dim3(grid_for(ncand, 128)), dim3(128), 0, s, (int64_t)ncand, nt,
+                     ns, n, Xn, c.tri.p, c.cand_off.p, c.piece_cnt.p);
+  FSI_CHECK_LAUNCH();
+  scan_excl(c.piece_cnt.p, c.piece_cnt.p, ncand, tmp, s);
+  int npieces = read_int(c.piece_cnt.p + ncand, s);
+  c.n_pairs = npieces;
+  c.pair_E.reserve(npieces);
+  c.pair_T.reserve(npieces);
+  c.piece_L.reserve(18 * (size_t)npieces);
+  hipLaunchKernelGGL(k_clip_emit, dim3(grid_for(ncand, 128)), dim3(128), 0, s, (int64_t)ncand, nt,
+                     ns, n, Xn, c.tri.p, c.ref_area.p, c.cand_off.p, c.piece_cnt.p, c.pair_E.p,
+                     c.pair_T.p, c.piece_L.p);
+  c.e_piece.reserve(nt + 1);
+  hipLaunchKernelGGL(k_elem_piece_off, dim3(grid_for(nt + 1, 256)), dim3(256), 0, s, nt,
+                     c.cand_off.p, c.piece_cnt.p, c.e_piece.p);
+  FSI_CHECK_LAUNCH();
+  // rows of C_f
+  Csr &Cf = c.Cf;
+  Cf.nrows = ns;
+  Cf.ncols = c.N2;
+  Cf.width = 1;
+  Cf.rowptr.reserve(ns + 1);
+  hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 0, ns, n, c.n2e_ptr.p, c.n2e.p,
+                     c.e_piece.p, c.pair_T.p, c.piece_L.p, Cf.rowptr.p, nullptr, nullptr, nullptr,
+                     c.dflag.p);
+  FSI_CHECK_LAUNCH();
+  scan_excl(Cf.rowptr.p, Cf.rowptr.p, ns, tmp, s);
+  check_flags(c);
+  int nnz = read_int(Cf.rowptr.p + ns, s);
+  Cf.nnz = nnz;
+  Cf.col.reserve(nnz);
+  Cf.val.reserve(nnz);
+  hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 1, ns, n, c.n2e_ptr.p, c.n2e.p,
+                     c.e_piece.p, c.pair_T.p, c.piece_L.p, nullptr, Cf.rowptr.p, Cf.col.p, Cf.val.p,
+                     c.dflag.p);
+  FSI_CHECK_LAUNCH();
+  // C_f^T
+  Csr &Ct = c.CfT;
+  Ct.nrows = c.N2;
+  Ct.ncols = ns;
+  Ct.width = 1;
+  Ct.nnz = nnz;
+  Ct.rowptr.reserve(c.N2 + 1);
+  c.cft_fill.reserve(c.N2);
+  fill(Ct.rowptr.p, c.N2 + 1, 0, s);
+  fill(c.cft_fill.p, c.N2, 0, s);
+  hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256)), dim3(256), 0, s, (int64_t)nnz, Cf.col.p,
+                     Ct.rowptr.p);
+  scan_excl(Ct.rowptr.p, Ct.rowptr.p, c.N2, tmp, s);
+  Ct.col.reserve(nnz);
+  Ct.val.reserve(nnz);
+  hipLaunchKernelGGL(k_scatter_t, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, Cf.rowptr.p, Cf.col.p,
+                     Cf.val.p, Ct.rowptr.p, c.cft_fill.p, Ct.col.p, Ct.val.p);
+  hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(c.N2, 256)), dim3(256), 0, s, c.N2, Ct.rowptr.p,
+                     Ct.col.p, Ct.val.p);
+  FSI_CHECK_LAUNCH();
+  Cf.val32.reserve(nnz);
+  Ct.val32.reserve(nnz);
+  convert(Cf.val32.p, Cf.val.p, nnz, s);
+  convert(Ct.val32.p, Ct.val.p, nnz, s);
+  c.have_cf = true;
+}
+
+}  // namespace fsi

@@ -1,0 +1,134 @@
+// Internal state of a libfsi context and the host-side entry points of each module.
+#pragma once
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace fsi {
+
+// CSR matrix with `width` values per entry (1: scalar, 2: (x, y) pair, 4: 2x2 block
+// stored xx, xy, yx, yy).  FP64 master values and an FP32 shadow made on demand.
+struct Csr {
+  int64_t nrows = 0, ncols = 0, nnz = 0;
+  int width = 1;
+  DevBuf<int> rowptr, col;
+  DevBuf<double> val;
+  DevBuf<float> val32;
+  size_t bytes() const { return rowptr.bytes() + col.bytes() + val.bytes() + val32.bytes(); }
+};
+
+// One level of a geometric multigrid hierarchy on the structured grid.
+struct MgLevel {
+  int n = 0;               // cells per side at this level
+  int64_t nodes = 0;       // P2 nodes (velocity) or P1 nodes (pressure)
+  Csr A;                   // operator (width 4 for velocity, 1 for pressure)
+  DevBuf<double> dinv;     // inverse diagonal: 4 per node (2x2 blocks) or 1 per node
+  DevBuf<float> dinv32;
+  double lmax = 0.0;       // upper bound of the spectrum of D^{-1} A (power iteration x 1.1)
+  Csr P, R;                // prolongation from the next coarser level into this one; R = P^T
+  DevBuf<double> w64[5];   // x, b, r, d, x2 work vectors
+  DevBuf<float> w32[5];
+};
+
+struct Mg {
+  int comps = 1;           // unknowns per node: 2 (velocity, 2x2 blocks) or 1 (pressure)
+  int degree = 3;          // Chebyshev smoothing steps before and after the coarse correction
+  std::vector<MgLevel> lv; // lv[0] finest
+  int64_t ncoarse = 0;     // unknowns of the coarsest level
+  DevBuf<double> cinv;     // dense inverse of the coarsest operator (row major)
+  DevBuf<float> cinv32;
+  size_t bytes() const;
+};
+
+struct Ctx {
+  // problem
+  int n = 0;
+  double nu = 1, rho = 1, dt = 0.01, kappa = 10;
+  int64_t N2 = 0, Np = 0, Ns = 0, Nt = 0, N = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  std::string last_error;
+
+  // fluid blocks on the finest grid
+  Csr Af;                  // A_f with Dirichlet rows/columns, width 4
+  DevBuf<double> Mf;       // M_f (no BC) on the A_f pattern, width 1
+  Csr B;                   // B with BC and pin, width 2, rows P1
+  Csr BT;                  // B^T, width 2, rows P2
+  Csr Mp;                  // pressure mass, width 1
+  DevBuf<double> Mp_dinv;  // 1 / diag(M_p)
+  DevBuf<float> Mp_dinv32;
+  DevBuf<unsigned char> bnd;  // 1 on boundary P2 nodes
+
+  // solid blocks
+  std::vector<int> h_tri;  // host copy of the connectivity
+  std::vector<double> h_xy;
+  DevBuf<int> tri;         // 3 per triangle
+  DevBuf<double> ref_xy;   // [x | y]
+  DevBuf<double> ref_area; // |E|
+  DevBuf<int> n2e_ptr, n2e;// node -> 4*element + local vertex (sorted by element)
+  int max_adj = 0;
+  Csr S;                   // solid P1 pattern; val = A_s
+  DevBuf<double> Cs;       // C_s on the same pattern
+  DevBuf<float> Cs32;
+  DevBuf<double> Cs_dinv;  // 1 / diag(C_s)
+  DevBuf<float> Cs_dinv32;
+
+  // coupling (rebuilt by every fsi_assemble_coupling)
+  bool have_cf = false;
+  Csr Cf, CfT;
+  int64_t n_pairs = 0, n_cand = 0;
+  DevBuf<int> cand_off;    // Nt + 1
+  DevBuf<int> piece_cnt;   // per candidate cell (then scanned in place, + 1)
+  DevBuf<int> pair_E, pair_T;
+  DevBuf<double> piece_L;  // 18 per piece: (|E|/|X(E)|) int lam_l phi_j
+  DevBuf<int> e_piece;     // Nt + 1: first piece of each element
+  DevBuf<int> cf_cnt, cft_cnt, cft_fill;
+  DevBuf<int> dflag;       // device error flags (mesh / capacity)
+
+  // multigrid hierarchies of the preconditioner
+  Mg mgu, mgp;
+
+  // Krylov work space (allocated on first use)
+  struct Inner {
+    DevBuf<double> v64[9];
+    DevBuf<float> v32[9];
+  } inner;
+  struct Outer {
+    int m = 0;
+    DevBuf<double> V, Z, w, r, t, t2;
+    DevBuf<float> x32, y32;
+  } outer;
+  DevBuf<double> red;      // reduction partials
+  DevBuf<double> dscal;    // device scalars
+  double *hpin = nullptr;  // pinned host staging (hipHostMalloc)
+  DevBuf<double> tmpN;     // N (operator/residual scratch)
+  DevBuf<double> tmpS;     // 12 Ns (solid block scratch)
+
+  double inner_rtol = -1.0;   // < 0: default per precision
+  int inner_maxit = 1000;
+  int64_t inner_its_total = 0;
+
+  ~Ctx();
+  size_t device_bytes() const;
+};
+
+// ---- module entry points (host side) ----
+// assemble.hip
+void build_fluid(Ctx &c);
+void build_solid(Ctx &c);
+void build_multigrid(Ctx &c);
+// coupling.hip
+void assemble_coupling(Ctx &c, const double *Xn, bool sync_check);
+// ops.hip (operator of eq. (matrix) and its pieces)
+template <typename T, typename Tx>
+void apply_operator(Ctx &c, const Tx *x, double *y, bool fluid_only);
+void build_rhs(Ctx &c, const double *u_n, const double *X_n, double *b);
+void make_shadow(Csr &A, hipStream_t s);
+// solve.hip
+void apply_precond(Ctx &c, int pc, int prec, const double *r, double *z);
+void gmres_solve(Ctx &c, const fsi_solve_opts &o, const double *b, double *x, fsi_solve_stats *st);
+
+}  // namespace fsi

@@ -1,0 +1,517 @@
+// Block preconditioners (Sec. 5) and the outer Krylov solve (Sec. 6).
+//
+// P = diag(A11, A22) or [[A11, 0], [A21, A22]], applied exactly up to the inner tolerance:
+//  * A22^{-1} in closed form: A22 = [[A_s, -C_s], [-(1/dt) C_s, 0]] gives
+//      z_X = -dt C_s^{-1} r_lam,   z_lam = C_s^{-1} (A_s z_X - r_X),
+//    with C_s^{-1} by Chebyshev iteration on D^{-1} C_s, whose spectrum lies in [1/2, 2] for
+//    P1 triangles (Wathen's bound), run to the rounding level; always FP64 (the block is
+//    small and its exactness matters);
+//  * A11^{-1} by preconditioned MINRES on [[A_f, -B^T], [-B, pin]] to a relative tolerance,
+//    with the SPD block preconditioner diag(V, S^{-1}):
+//      V      one V-cycle of geometric multigrid for A_f on the nested P2 grids
+//             (Chebyshev smoothing with 2x2 point-block Jacobi, exact coarse solve);
+//      S^{-1} the Cahouet-Chabard approximation nu M_p^{-1} + (rho/dt) L_p^{-1} of the
+//             pressure Schur complement, with M_p^{-1} by Chebyshev-Jacobi and L_p^{-1} by
+//             one P1 multigrid V-cycle; the pinned node is the identity.
+// The outer solve is right-preconditioned flexible GMRES(m) with classical Gram-Schmidt
+// applied twice, FP64 Arnoldi vectors and the Givens reduction on the host; with FP32
+// arithmetic it is wrapped in iterative refinement on the FP64 residual.
+#include <chrono>
+#include <cmath>
+
+#include "ctx.h"
+#include "kernels.h"
+
+namespace fsi {
+
+template <typename T>
+void apply_a11(Ctx &c, const T *x, T *y);
+
+// ---------------------------------------------------------------- small kernels
+// First Chebyshev step from x = 0: d = x = scale * Dinv b (NC components of `nodes`).
+template <typename T, int W, int NC>
+__global__ void k_dinv_first(int64_t nodes, const T *dinv, const T *b, T scale, T *d, T *x) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nodes) return;
+  if constexpr (W == 4) {
+    T b0 = b[r], b1 = b[nodes + r];
+    T z0 = scale * (dinv[4 * r] * b0 + dinv[4 * r + 1] * b1);
+    T z1 = scale * (dinv[4 * r + 2] * b0 + dinv[4 * r + 3] * b1);
+    d[r] = z0; x[r] = z0;
+    d[nodes + r] = z1; x[nodes + r] = z1;
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T z = scale * dinv[r] * b[c * nodes + r];
+      d[c * nodes + r] = z;
+      x[c * nodes + r] = z;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_dense_mv(int m, const T *A, const T *x, T *y) {
+  int r = blockIdx.x;
+  if (r >= m) return;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < m; k += kWave) s += (double)A[(int64_t)r * m + k] * (double)x[k];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) y[r] = (T)s;
+}
+
+// y = a x + b y + c z
+template <typename T>
+__global__ void k_axpbypcz(T *y, const T *x, const T *z, T a, T b, T c, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i] + c * z[i];
+}
+
+// y -= (alpha[0] * s) r   (alpha on the device)
+template <typename T>
+__global__ void k_sub_dev(T *y, const T *r, const double *alpha, double s, int64_t n) {
+  T c = (T)(alpha[0] * s);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] -= c * r[i];
+}
+
+// MINRES direction and iterate: wn = (v - e w1 - d w2) / g;  x += phi wn
+template <typename T>
+__global__ void k_minres_update(T *wn, const T *v, const T *w1, const T *w2, T *x, T e, T d, T ginv,
+                                T phi, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    T w = (v[i] - e * w1[i] - d * w2[i]) * ginv;
+    wn[i] = w;
+    x[i] += phi * w;
+  }
+}
+
+template <typename T>
+__global__ void k_set_pinned(T *z, const T *r) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) z[0] = r[0];
+}
+
+template <typename T>
+__global__ void k_negate(T *y, const T *x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = -x[i];
+}
+
+// ---------------------------------------------------------------- precision helpers
+template <typename T> struct Pr;
+template <> struct Pr<double> {
+  static const double *val(const Csr &A) { return A.val.p; }
+  static double *w(MgLevel &L, int i) { return L.w64[i].p; }
+  static DevBuf<double> &wb(MgLevel &L, int i) { return L.w64[i]; }
+  static const double *dinv(const MgLevel &L) { return L.dinv.p; }
+  static const double *cinv(const Mg &m) { return m.cinv.p; }
+  static DevBuf<double> &inner(Ctx &c, int i) { return c.inner.v64[i]; }
+};
+template <> struct Pr<float> {
+  static const float *val(const Csr &A) { return A.val32.p; }
+  static float *w(MgLevel &L, int i) { return L.w32[i].p; }
+  static DevBuf<float> &wb(MgLevel &L, int i) { return L.w32[i]; }
+  static const float *dinv(const MgLevel &L) { return L.dinv32.p; }
+  static const float *cinv(const Mg &m) { return m.cinv32.p; }
+  static DevBuf<float> &inner(Ctx &c, int i) { return c.inner.v32[i]; }
+};
+
+static void ensure_fp32_mg(Ctx &c) {
+  for (Mg *mg : {&c.mgu, &c.mgp})
+    for (auto &L : mg->lv) {
+      if (!L.A.val32.p) make_shadow(L.A, c.stream);
+      if (L.P.nnz && !L.P.val32.p) make_shadow(L.P, c.stream);
+      if (L.R.nnz && !L.R.val32.p) make_shadow(L.R, c.stream);
+      if (!L.dinv32.p) {
+        L.dinv32.alloc(L.dinv.n);
+        convert(L.dinv32.p, L.dinv.p, (int64_t)L.dinv.n, c.stream);
+      }
+      for (int i = 0; i < 5; ++i)
+        if (!L.w32[i].p) L.w32[i].alloc(L.w64[i].n);
+    }
+  if (!c.Mp.val32.p) make_shadow(c.Mp, c.stream);
+}
+
+// ---------------------------------------------------------------- Chebyshev smoothing
+// `steps` Chebyshev iterations for A x = b preconditioned by D^{-1}, on the spectral
+// interval [lmin, lmax] of D^{-1} A.  zero_init: start from x = 0.  x and x2 are
+// ping-pong buffers; returns the buffer holding the result.  W = 4: 2x2 blocks (NC = 2).
+template <typename T, int W, int NC>
+static T *chebyshev(int64_t nrows, const int *rp, const int *col, const T *val, const T *dinv,
+                    double lmin, double lmax, int steps, const T *b, T *x, T *x2, T *d,
+                    bool zero_init, hipStream_t s) {
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  int k;
+  if (zero_init) {
+    hipLaunchKernelGGL((k_dinv_first<T, W, NC>), dim3(grid_for(nrows, 256)), dim3(256), 0, s, nrows,
+                       dinv, b, (T)(1.0 / theta), d, x);
+    FSI_CHECK_LAUNCH();
+  } else {
+    spmv<T, W, NC, SP_CHEB>(nrows, rp, col, val, x, nrows, x2, nrows, s, b, d, dinv, (T)0,
+                            (T)(1.0 / theta));
+    std::swap(x, x2);
+  }
+  for (k = 1; k < steps; ++k) {
+    double rho1 = 1.0 / (2.0 * sigma - rho);
+    spmv<T, W, NC, SP_CHEB>(nrows, rp, col, val, x, nrows, x2, nrows, s, b, d, dinv,
+                            (T)(rho1 * rho), (T)(2.0 * rho1 / delta));
+    std::swap(x, x2);
+    rho = rho1;
+  }
+  return x;
+}
+
+// ---------------------------------------------------------------- V-cycle
+// One V-cycle at level l for right-hand side b (comps * nodes entries, component-major).
+// Returns the level work vector that holds the result.
+template <typename T, int W, int NC>
+static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s) {
+  MgLevel &L = mg.lv[l];
+  T *x = Pr<T>::w(L, 0), *x2 = Pr<T>::w(L, 4), *r = Pr<T>::w(L, 2), *d = Pr<T>::w(L, 3);
+  if (l + 1 == (int)mg.lv.size()) {
+    hipLaunchKernelGGL(k_dense_mv<T>, dim3((unsigned)mg.ncoarse), dim3(kWave), 0, s,
+                       (int)mg.ncoarse, Pr<T>::cinv(mg), b, x);
+    FSI_CHECK_LAUNCH();
+    return x;
+  }
+  const double lmax = L.lmax, lmin = L.lmax / 30.0;
+  const T *dinv = Pr<T>::dinv(L);
+  const T *val = Pr<T>::val(L.A);
+  T *xs = chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, mg.degree,
+                              b, x, x2, d, true, s);
+  T *xo = (xs == x) ? x2 : x;
+  spmv<T, W, NC, SP_RESID>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, xs, L.nodes, r, L.nodes, s, b);
+  MgLevel &C = mg.lv[l + 1];
+  T *bc = Pr<T>::w(C, 1);
+  spmv<T, 1, NC, SP_APPLY>(L.R.nrows, L.R.rowptr.p, L.R.col.p, Pr<T>::val(L.R), r, L.nodes, bc,
+                           C.nodes, s);
+  T *xc = vcycle<T, W, NC>(mg, l + 1, bc, s);
+  spmv<T, 1, NC, SP_ADD>(L.P.nrows, L.P.rowptr.p, L.P.col.p, Pr<T>::val(L.P), xc, C.nodes, xs,
+                         L.nodes, s);
+  return chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, mg.degree, b,
+                             xs, xo, d, false, s);
+}
+
+// ---------------------------------------------------------------- A11 preconditioner
+template <typename T> static const T *mp_dinv(Ctx &c);
+template <> const double *mp_dinv<double>(Ctx &c) { return c.Mp_dinv.p; }
+template <> const float *mp_dinv<float>(Ctx &c) { return c.Mp_dinv32.p; }
+
+constexpr int kMpSteps = 8;   // Chebyshev-Jacobi steps of the pressure mass inverse
+
+// z = diag(V, S^{-1}) r on [u | p]
+template <typename T>
+static void a11_precond(Ctx &c, const T *r, T *z) {
+  hipStream_t s = c.stream;
+  const int64_t N2 = c.N2, Np = c.Np;
+  T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s);
+  FSI_HIP(hipMemcpyAsync(z, xu, 2 * N2 * sizeof(T), hipMemcpyDeviceToDevice, s));
+  // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
+  T *rp = Pr<T>::inner(c, 8).p;
+  FSI_HIP(hipMemcpyAsync(rp, r + 2 * N2, Np * sizeof(T), hipMemcpyDeviceToDevice, s));
+  fill(rp, 1, (T)0, s);
+  T *xp = vcycle<T, 1, 1>(c.mgp, 0, rp, s);
+  T *mx = Pr<T>::inner(c, 7).p, *mx2 = mx + Np, *md = mx + 2 * Np;
+  T *mres = chebyshev<T, 1, 1>(Np, c.Mp.rowptr.p, c.Mp.col.p, Pr<T>::val(c.Mp), mp_dinv<T>(c), 0.5,
+                               2.0, kMpSteps, rp, mx, mx2, md, true, s);
+  lincomb(z + 2 * N2, mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, s);
+  hipLaunchKernelGGL(k_set_pinned<T>, dim3(1), dim3(1), 0, s, z + 2 * N2, r + 2 * N2);
+  FSI_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------- inner MINRES
+// Preconditioned MINRES (Paige-Saunders recurrences) for A11 x = b from x = 0; stops when
+// the preconditioned residual estimate falls below tol times its initial value.
+template <typename T>
+static int minres_a11(Ctx &c, const T *b, T *x, double tol, int maxit) {
+  hipStream_t s = c.stream;
+  const int64_t nf = 2 * c.N2 + c.Np;
+  T *v = Pr<T>::inner(c, 0).p, *y = Pr<T>::inner(c, 1).p, *r1 = Pr<T>::inner(c, 2).p,
+    *r2 = Pr<T>::inner(c, 3).p, *w = Pr<T>::inner(c, 4).p, *w1 = Pr<T>::inner(c, 5).p,
+    *w2 = Pr<T>::inner(c, 6).p;
+  double *dv = c.dscal.p;   // [0] alfa, [1] beta^2
+  fill(x, nf, (T)0, s);
+  fill(w, nf, (T)0, s);
+  fill(w2, nf, (T)0, s);
+  FSI_HIP(hipMemcpyAsync(r1, b, nf * sizeof(T), hipMemcpyDeviceToDevice, s));
+  a11_precond<T>(c, r1, y);
+  multidot(r1, 0, 1, y, nf, dv + 1, c.red, s);
+  FSI_HIP(hipMemcpyAsync(c.hpin, dv, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  FSI_HIP(hipStreamSynchronize(s));
+  double b2 = c.hpin[1];
+  FSI_REQUIRE(std::isfinite(b2), FSI_E_NONFINITE, "non-finite residual in the inner A11 solve");
+  if (b2 <= 0.0) return 0;
+  FSI_HIP(hipMemcpyAsync(r2, r1, nf * sizeof(T), hipMemcpyDeviceToDevice, s));
+  double beta1 = std::sqrt(b2), beta = beta1, oldb = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta1;
+  double cs = -1.0, sn = 0.0;
+  int it;
+  for (it = 1; it <= maxit; ++it) {
+    lincomb(v, y, y, (T)(1.0 / beta), (T)0, nf, s);
+    apply_a11<T>(c, v, y);
+    if (it >= 2) axpby(y, r1, (T)(-beta / oldb), (T)1, nf, s);
+    multidot(v, 0, 1, y, nf, dv, c.red, s);
+    hipLaunchKernelGGL(k_sub_dev<T>, dim3(vgrid(nf)), dim3(256), 0, s, y, r2, dv, 1.0 / beta, nf);
+    FSI_CHECK_LAUNCH();
+    std::swap(r1, r2);   // r1 <- previous r2
+    std::swap(r2, y);    // r2 <- new Lanczos vector
+    a11_precond<T>(c, r2, y);
+    multidot(r2, 0, 1, y, nf, dv + 1, c.red, s);
+    FSI_HIP(hipMemcpyAsync(c.hpin, dv, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    double alfa = c.hpin[0], nb2 = c.hpin[1];
+    FSI_REQUIRE(std::isfinite(alfa) && std::isfinite(nb2), FSI_E_NONFINITE,
+                "non-finite value in the inner A11 solve");
+    oldb = beta;
+    beta = std::sqrt(nb2 > 0.0 ? nb2 : 0.0);
+    double oldeps = epsln;
+    double delta = cs * dbar + sn * alfa;
+    double gbar = sn * dbar - cs * alfa;
+    epsln = sn * beta;
+    dbar = -cs * beta;
+    double gamma = std::sqrt(gbar * gbar + beta * beta);
+    if (gamma < 1e-300) gamma = 1e-300;
+    cs = gbar / gamma;
+    sn = beta / gamma;
+    double phi = cs * phibar;
+    phibar = sn * phibar;
+    // new direction from the previous two (w2 and w); w1's buffer is free
+    T *wn = w1;
+    hipLaunchKernelGGL(k_minres_update<T>, dim3(vgrid(nf)), dim3(256), 0, s, wn, v, w2, w, x,
+                       (T)oldeps, (T)delta, (T)(1.0 / gamma), (T)phi, nf);
+    FSI_CHECK_LAUNCH();
+    w1 = w2;
+    w2 = w;
+    w = wn;
+    if (phibar <= tol * beta1 || beta == 0.0) break;
+  }
+  return it > maxit ? maxit : it;
+}
+
+// ---------------------------------------------------------------- A22 closed form (FP64)
+constexpr int kCsSteps = 36;   // (1/3)^36 < 1e-17: C_s^{-1} to the rounding level
+
+static const double *cs_solve(Ctx &c, const double *b, double *scratch) {
+  const int64_t ns = c.Ns;
+  double *t = scratch, *t2 = t + 2 * ns, *d = t + 4 * ns;
+  return chebyshev<double, 1, 2>(ns, c.S.rowptr.p, c.S.col.p, c.Cs.p, c.Cs_dinv.p, 0.5, 2.0,
+                                 kCsSteps, b, t, t2, d, true, c.stream);
+}
+
+// z2 = A22^{-1} r2 on [X | lam] (4 Ns entries)
+static void a22_solve(Ctx &c, const double *rX, const double *rl, double *zX, double *zl) {
+  hipStream_t s = c.stream;
+  const int64_t ns = c.Ns;
+  double *scr = c.tmpS.p, *u = c.tmpS.p + 6 * ns;
+  const double *t = cs_solve(c, rl, scr);
+  lincomb(zX, t, t, -c.dt, 0.0, 2 * ns, s);
+  // u = r_X - A_s z_X;  z_lam = C_s^{-1} (A_s z_X - r_X) = -C_s^{-1} u
+  spmv<double, 1, 2, SP_RESID>(ns, c.S.rowptr.p, c.S.col.p, c.S.val.p, zX, ns, u, ns, s, rX);
+  const double *t2 = cs_solve(c, u, scr);
+  hipLaunchKernelGGL(k_negate<double>, dim3(vgrid(2 * ns)), dim3(256), 0, s, zl, t2, 2 * ns);
+  FSI_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------- block preconditioner
+static void ensure_inner(Ctx &c, int prec) {
+  const int64_t nf = 2 * c.N2 + c.Np;
+  if (prec == FSI_FP64) {
+    for (int i = 0; i < 9; ++i)
+      if (!c.inner.v64[i].p) c.inner.v64[i].alloc(nf);
+  } else {
+    ensure_fp32_mg(c);
+    for (int i = 0; i < 9; ++i)
+      if (!c.inner.v32[i].p) c.inner.v32[i].alloc(nf);
+    if (!c.outer.x32.p) { c.outer.x32.alloc(nf); c.outer.y32.alloc(nf); }
+    if (!c.Mp_dinv32.p) {
+      c.Mp_dinv32.alloc(c.Np);
+      convert(c.Mp_dinv32.p, c.Mp_dinv.p, c.Np, c.stream);
+    }
+  }
+}
+
+double inner_tol(const Ctx &c, int prec) {
+  if (c.inner_rtol > 0) return c.inner_rtol;
+  return prec == FSI_FP64 ? 1e-10 : 1e-6;
+}
+
+void apply_precond(Ctx &c, int pc, int prec, const double *r, double *z) {
+  hipStream_t s = c.stream;
+  FSI_REQUIRE(pc == FSI_PC_DIAG || pc == FSI_PC_TRI, FSI_E_ARG, "unknown preconditioner");
+  FSI_REQUIRE(prec == FSI_FP64 || prec == FSI_FP32, FSI_E_ARG, "unknown precision");
+  FSI_REQUIRE(c.have_cf || pc == FSI_PC_DIAG, FSI_E_STATE, "block-triangular needs C_f: call fsi_assemble_coupling");
+  ensure_inner(c, prec);
+  const int64_t nf = 2 * c.N2 + c.Np, ns = c.Ns;
+  const double tol = inner_tol(c, prec);
+  int its;
+  if (prec == FSI_FP64) {
+    its = minres_a11<double>(c, r, z, tol, c.inner_maxit);
+  } else {
+    convert(c.outer.x32.p, r, nf, s);
+    its = minres_a11<float>(c, c.outer.x32.p, c.outer.y32.p, tol, c.inner_maxit);
+    convert(z, c.outer.y32.p, nf, s);
+  }
+  c.inner_its_total += its;
+  const double *rX = r + nf, *rl = r + nf + 2 * ns;
+  double *zX = z + nf, *zl = z + nf + 2 * ns;
+  if (pc == FSI_PC_TRI) {
+    // r_lam - C_f z_u  (A21 z1 = [0; C_f z_u])
+    double *t = c.tmpS.p + 8 * ns;
+    spmv<double, 1, 2, SP_RESID>(ns, c.Cf.rowptr.p, c.Cf.col.p, c.Cf.val.p, z, c.N2, t, ns, s, rl);
+    rl = t;
+  }
+  a22_solve(c, rX, rl, zX, zl);
+}
+
+// ---------------------------------------------------------------- outer FGMRES
+template <typename T>
+static double dev_dot(Ctx &c, const double *x, const double *y, int64_t n) {
+  multidot(x, 0, 1, y, n, c.dscal.p, c.red, c.stream);
+  FSI_HIP(hipMemcpyAsync(c.hpin, c.dscal.p, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  FSI_HIP(hipStreamSynchronize(c.stream));
+  return c.hpin[0];
+}
+
+static void op_apply(Ctx &c, int prec, const double *x, double *y) {
+  if (prec == FSI_FP64) apply_operator<double, double>(c, x, y, false);
+  else apply_operator<float, double>(c, x, y, false);
+}
+
+// r = b - A x (FP64)
+static void residual64(Ctx &c, const double *b, const double *x, double *r) {
+  apply_operator<double, double>(c, x, r, false);
+  axpby(r, b, 1.0, -1.0, c.N, c.stream);
+}
+
+struct CycleOut {
+  int steps;
+  double est;
+};
+
+// One FGMRES cycle of at most `maxsteps` Arnoldi steps on A d = r0 (beta = ||r0||) with
+// operator and preconditioner in precision `prec`; adds the correction to x.
+static CycleOut fgmres_cycle(Ctx &c, int pc, int prec, const double *r0, double beta, double target,
+                             int maxsteps, double *x) {
+  hipStream_t s = c.stream;
+  const int m = c.outer.m;
+  const int64_t N = c.N;
+  double *V = c.outer.V.p, *Z = c.outer.Z.p, *w = c.outer.w.p;
+  lincomb(V, r0, r0, 1.0 / beta, 0.0, N, s);
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
+  g[0] = beta;
+  int k = 0;
+  double est = beta;
+  double *dh = c.dscal.p + 8;   // h1 (m+1), h2 (m+1), hn2
+  for (int j = 0; j < maxsteps && j < m; ++j) {
+    double *Vj = V + (int64_t)j * N, *Zj = Z + (int64_t)j * N;
+    apply_precond(c, pc, prec, Vj, Zj);
+    op_apply(c, prec, Zj, w);
+    multidot(V, N, j + 1, w, N, dh, c.red, s);
+    hipLaunchKernelGGL(k_multiaxpy_sub, dim3(vgrid(N)), dim3(256), 0, s, w, V, N, j + 1, dh, N);
+    multidot(V, N, j + 1, w, N, dh + (m + 1), c.red, s);
+    hipLaunchKernelGGL(k_multiaxpy_sub, dim3(vgrid(N)), dim3(256), 0, s, w, V, N, j + 1, dh + (m + 1), N);
+    multidot(w, 0, 1, w, N, dh + 2 * (m + 1), c.red, s);
+    FSI_CHECK_LAUNCH();
+    FSI_HIP(hipMemcpyAsync(c.hpin, dh, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    double *hcol = &H[(size_t)j * (m + 1)];   // column j, rows 0..j+1
+    for (int i = 0; i <= j; ++i) hcol[i] = c.hpin[i] + c.hpin[(m + 1) + i];
+    double hn = std::sqrt(c.hpin[2 * (m + 1)] > 0 ? c.hpin[2 * (m + 1)] : 0.0);
+    FSI_REQUIRE(std::isfinite(hn), FSI_E_NONFINITE, "non-finite Arnoldi vector");
+    hcol[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
+      hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
+      hcol[i] = t;
+    }
+    double den = std::hypot(hcol[j], hcol[j + 1]);
+    cs[j] = hcol[j] / den;
+    sn[j] = hcol[j + 1] / den;
+    hcol[j] = den;
+    hcol[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    k = j + 1;
+    est = std::fabs(g[j + 1]);
+    if (est <= target || hn == 0.0) break;
+    lincomb(V + (int64_t)(j + 1) * N, w, w, 1.0 / hn, 0.0, N, s);
+  }
+  // back substitution H y = g
+  std::vector<double> y(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    double t = g[i];
+    for (int q = i + 1; q < k; ++q) t -= H[(size_t)q * (m + 1) + i] * y[q];
+    y[i] = t / H[(size_t)i * (m + 1) + i];
+  }
+  if (k > 0) {
+    for (int i = 0; i < k; ++i) c.hpin[i] = y[i];
+    FSI_HIP(hipMemcpyAsync(dh, c.hpin, k * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_multiaxpy_add, dim3(vgrid(N)), dim3(256), 0, s, x, Z, N, k, dh, N);
+    FSI_CHECK_LAUNCH();
+    FSI_HIP(hipStreamSynchronize(s));   // hpin is reused by the next call
+  }
+  return {k, est};
+}
+
+void gmres_solve(Ctx &c, const fsi_solve_opts &o, const double *b, double *x, fsi_solve_stats *st) {
+  hipStream_t s = c.stream;
+  FSI_REQUIRE(c.have_cf, FSI_E_STATE, "the solve needs C_f: call fsi_assemble_coupling first");
+  const int m = o.restart > 0 ? o.restart : 30;
+  FSI_REQUIRE(m <= 200, FSI_E_ARG, "restart length above 200");
+  const int maxit = o.maxit > 0 ? o.maxit : 10000;
+  const double rtol = o.rtol > 0 ? o.rtol : 1e-8;
+  const int prec = o.prec;
+  FSI_REQUIRE(prec == FSI_FP64 || prec == FSI_FP32, FSI_E_ARG, "unknown precision");
+  if (o.inner_rtol > 0) c.inner_rtol = o.inner_rtol;
+  if (o.inner_maxit > 0) c.inner_maxit = o.inner_maxit;
+  const int64_t N = c.N;
+  if (c.outer.m < m) {
+    c.outer.V.alloc((size_t)(m + 1) * N);
+    c.outer.Z.alloc((size_t)m * N);
+    c.outer.m = m;
+  }
+  c.outer.m = m;
+  c.outer.w.reserve(N);
+  c.outer.r.reserve(N);
+  c.dscal.reserve(8 + 2 * (m + 1) + 1 + 64);
+  c.inner_its_total = 0;
+  fsi_solve_stats S{};
+  double bnorm = std::sqrt(dev_dot<double>(c, b, b, N));
+  FSI_REQUIRE(std::isfinite(bnorm), FSI_E_NONFINITE, "non-finite right-hand side");
+  if (bnorm == 0.0) {
+    fill(x, N, 0.0, s);
+    S.converged = 1;
+    if (st) *st = S;
+    return;
+  }
+  const double target = rtol * bnorm;
+  double *r = c.outer.r.p;
+  bool conv = false;
+  double rn = 0.0;
+  while (true) {
+    residual64(c, b, x, r);
+    rn = std::sqrt(dev_dot<double>(c, r, r, N));
+    FSI_REQUIRE(std::isfinite(rn), FSI_E_NONFINITE, "non-finite residual");
+    if (rn <= target) { conv = true; break; }
+    if (S.its >= maxit) break;
+    // FP64: restart cycles toward the final target; FP32: refinement cycles that each
+    // reduce the FP64 residual by about 1e-5 (the FP32 operator's accuracy)
+    double cyc_target = prec == FSI_FP64 ? target : std::max(target, 1e-5 * rn);
+    CycleOut co = fgmres_cycle(c, o.pc, prec, r, rn, cyc_target, maxit - S.its, x);
+    S.its += co.steps;
+    S.restarts += 1;
+    if (prec == FSI_FP32) S.refinements += 1;
+    S.relres_est = co.est / bnorm;
+  }
+  S.converged = conv ? 1 : 0;
+  S.relres_true = rn / bnorm;
+  S.inner_its = c.inner_its_total;
+  if (st) *st = S;
+  FSI_REQUIRE(conv, FSI_E_NOCONV, "GMRES reached maxit");
+}
+
+}  // namespace fsi

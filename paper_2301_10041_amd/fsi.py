@@ -1,0 +1,248 @@
+"""ctypes binding of libfsi (include/fsi.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts torch tensors to device
+pointers, host arrays to C arrays, and status codes to exceptions.  It raises
+``FsiLibraryMissing`` when libfsi.so has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfsi.so")
+
+FSI_OK, FSI_E_ARG, FSI_E_MESH, FSI_E_NOMEM, FSI_E_NOCONV, FSI_E_NONFINITE, FSI_E_HIP, \
+    FSI_E_CAPACITY, FSI_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+FP64, FP32 = 0, 1
+PC_DIAG, PC_TRI = 0, 1
+BLOCKS = dict(AF=0, MF=1, B=2, BT=3, AS=4, CS=5, CF=6, CFT=7, MP=8)
+
+
+class FsiLibraryMissing(RuntimeError):
+    pass
+
+
+class FsiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libfsi error {code}: {msg}")
+        self.code = code
+
+
+class FluidDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nu", C.c_double), ("rho", C.c_double), ("dt", C.c_double)]
+
+
+class SolidDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_tris", C.c_int32), ("xy", C.POINTER(C.c_double)),
+                ("tri", C.POINTER(C.c_int32)), ("kappa", C.c_double)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("N2", "Np", "Ns", "Nt", "N", "off_ux", "off_uy", "off_p",
+                                          "off_Xx", "off_Xy", "off_lx", "off_ly", "nnz_Af", "nnz_B",
+                                          "nnz_s", "nnz_Cf", "n_pairs", "device_bytes")] + \
+              [("mg_levels_u", C.c_int32), ("mg_levels_p", C.c_int32)]
+
+
+class CouplingInfo(C.Structure):
+    _fields_ = [("n_pairs", C.c_int64), ("nnz", C.c_int64)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double), ("pc", C.c_int32),
+                ("prec", C.c_int32), ("inner_rtol", C.c_double), ("inner_maxit", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("its", C.c_int32), ("restarts", C.c_int32), ("inner_its", C.c_int64),
+                ("converged", C.c_int32), ("refinements", C.c_int32), ("relres_true", C.c_double),
+                ("relres_est", C.c_double), ("t_coup", C.c_double), ("t_rhs", C.c_double),
+                ("t_solve", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+_SIGS = {
+    "fsi_create": (C.c_int, [C.POINTER(FluidDesc), C.POINTER(SolidDesc), C.c_void_p, C.c_size_t,
+                             C.POINTER(C.c_void_p)]),
+    "fsi_destroy": (None, [C.c_void_p]),
+    "fsi_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fsi_sizes": (C.c_int, [C.c_void_p, C.POINTER(Sizes)]),
+    "fsi_assemble_coupling": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(CouplingInfo)]),
+    "fsi_build_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsi_apply_operator": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "fsi_apply_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
+    "fsi_set_inner": (C.c_int, [C.c_void_p, C.c_double, C.c_int32]),
+    "fsi_gmres_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
+                                  C.POINTER(SolveStats)]),
+    "fsi_step": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.POINTER(SolveStats)]),
+    "fsi_export_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                   C.POINTER(C.c_int64)]),
+    "fsi_export_csr": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsi_strerror": (C.c_char_p, [C.c_int]),
+    "fsi_last_error": (C.c_char_p, [C.c_void_p]),
+}
+
+
+def lib():
+    """Load libfsi.so (once).  Raises FsiLibraryMissing if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FsiLibraryMissing(f"{LIB_PATH} not built: run python -m paper_2301_10041_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(t, dtype_name="float64"):
+    """Device pointer of a contiguous CUDA tensor of the given dtype."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor on the GPU")
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != f"torch.{dtype_name}":
+        raise ValueError(f"expected a contiguous {dtype_name} CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class Opts:
+    restart: int = 30
+    maxit: int = 10000
+    rtol: float = 1e-8
+    pc: int = PC_TRI
+    prec: int = FP64
+    inner_rtol: float = 0.0
+    inner_maxit: int = 0
+
+    def c(self):
+        return SolveOpts(self.restart, self.maxit, self.rtol, self.pc, self.prec, self.inner_rtol,
+                         self.inner_maxit)
+
+
+class Context:
+    """One fluid grid, one solid mesh and all device state of libfsi."""
+
+    def __init__(self, n, xy, tri, nu=1.0, rho=1.0, dt=0.01, kappa=10.0, stream=None, budget=0):
+        L = lib()
+        xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64))
+        if xy.ndim != 2 or xy.shape[1] != 2:
+            raise ValueError("xy must be [Ns, 2]")
+        self._xy_soa = np.ascontiguousarray(np.concatenate([xy[:, 0], xy[:, 1]]))
+        self._tri = np.ascontiguousarray(np.asarray(tri, dtype=np.int32).reshape(-1))
+        fd = FluidDesc(int(n), float(nu), float(rho), float(dt))
+        sd = SolidDesc(xy.shape[0], self._tri.size // 3,
+                       self._xy_soa.ctypes.data_as(C.POINTER(C.c_double)),
+                       self._tri.ctypes.data_as(C.POINTER(C.c_int32)), float(kappa))
+        h = C.c_void_p()
+        rc = L.fsi_create(C.byref(fd), C.byref(sd), _stream_handle(stream), int(budget), C.byref(h))
+        if rc != FSI_OK:
+            raise FsiError(rc, L.fsi_last_error(None).decode())
+        self._h = h
+        self.n, self.nu, self.rho, self.dt, self.kappa = int(n), nu, rho, dt, kappa
+        self.sizes = self._sizes()
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        xy, tri = wl.solid_mesh()
+        return cls(wl.n, xy, tri, nu=wl.nu, rho=wl.rho, dt=wl.dt, kappa=wl.kappa, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fsi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != FSI_OK:
+            raise FsiError(rc, lib().fsi_last_error(self._h).decode())
+
+    def _sizes(self):
+        s = Sizes()
+        self._check(lib().fsi_sizes(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in Sizes._fields_}
+
+    def refresh_sizes(self):
+        self.sizes = self._sizes()
+        return self.sizes
+
+    def set_stream(self, stream=None):
+        self._check(lib().fsi_set_stream(self._h, _stream_handle(stream)))
+
+    def assemble_coupling(self, Xn, sync=True):
+        info = CouplingInfo()
+        self._check(lib().fsi_assemble_coupling(self._h, _ptr(Xn), C.byref(info) if sync else None))
+        return dict(n_pairs=info.n_pairs, nnz=info.nnz)
+
+    def build_rhs(self, u_n, X_n, b):
+        self._check(lib().fsi_build_rhs(self._h, _ptr(u_n), _ptr(X_n), _ptr(b)))
+
+    def apply_operator(self, x, y, prec=FP64):
+        self._check(lib().fsi_apply_operator(self._h, int(prec), _ptr(x), _ptr(y)))
+
+    def apply_precond(self, r, z, pc=PC_TRI, prec=FP64):
+        self._check(lib().fsi_apply_precond(self._h, int(pc), int(prec), _ptr(r), _ptr(z)))
+
+    def set_inner(self, rtol, maxit=0):
+        self._check(lib().fsi_set_inner(self._h, float(rtol), int(maxit)))
+
+    def gmres_solve(self, b, x, opts: Opts | None = None, raise_noconv=True):
+        st = SolveStats()
+        o = (opts or Opts()).c()
+        rc = lib().fsi_gmres_solve(self._h, C.byref(o), _ptr(b), _ptr(x), C.byref(st))
+        if rc != FSI_OK and (raise_noconv or rc != FSI_E_NOCONV):
+            self._check(rc)
+        return st.as_dict()
+
+    def step(self, u_n, X_n, state, opts: Opts | None = None):
+        st = SolveStats()
+        o = (opts or Opts()).c()
+        self._check(lib().fsi_step(self._h, C.byref(o), _ptr(u_n), _ptr(X_n), _ptr(state), C.byref(st)))
+        return st.as_dict()
+
+    def export_pairs(self):
+        cnt = C.c_int64()
+        self._check(lib().fsi_export_pairs(self._h, None, None, 0, C.byref(cnt)))
+        E = np.zeros(cnt.value, dtype=np.int32)
+        T = np.zeros(cnt.value, dtype=np.int32)
+        self._check(lib().fsi_export_pairs(self._h, E.ctypes.data_as(C.c_void_p),
+                                           T.ctypes.data_as(C.c_void_p), cnt.value, C.byref(cnt)))
+        return E, T
+
+    def export_csr(self, block):
+        """(rowptr, col, val[nnz, width]) host copies of one block."""
+        bid = BLOCKS[block] if isinstance(block, str) else int(block)
+        nr, nz, w = C.c_int64(), C.c_int64(), C.c_int32()
+        self._check(lib().fsi_export_csr(self._h, bid, C.byref(nr), C.byref(nz), C.byref(w), None, None, None))
+        rp = np.zeros(nr.value + 1, dtype=np.int32)
+        col = np.zeros(max(nz.value, 1), dtype=np.int32)
+        val = np.zeros(max(nz.value, 1) * w.value, dtype=np.float64)
+        self._check(lib().fsi_export_csr(self._h, bid, C.byref(nr), C.byref(nz), C.byref(w),
+                                         rp.ctypes.data_as(C.c_void_p), col.ctypes.data_as(C.c_void_p),
+                                         val.ctypes.data_as(C.c_void_p)))
+        return rp, col[:nz.value], val[:nz.value * w.value].reshape(nz.value, w.value)

@@ -1,0 +1,303 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Bit-exact: sparsity patterns of every block, the intersection list (E, T) and the C_f
+pattern.  FP64 values: relative differences at the rounding level of the assembly
+(1e-12).  Solutions: relative error 1e-8 against the oracle's direct solve, with GMRES
+iteration counts within the oracle's exact-block counts plus max(2, 10%).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fluid, gmres, system
+from paper_2301_10041_amd import fsi, inputs
+
+from gpu_helpers import csr_from_export, make_pair, rel, small_workloads, soa, to_dev, to_host, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch_dev()
+    fsi.lib()
+
+
+def _same_pattern(rp, col, A):
+    A = A.tocsr()
+    assert np.array_equal(rp, A.indptr.astype(np.int32))
+    assert np.array_equal(col, A.indices.astype(np.int32))
+
+
+@pytest.mark.parametrize("n", [2, 5, 8, 32])
+def test_fluid_blocks(n):
+    print(f"[fluid blocks n={n}]", flush=True)
+    wl = inputs.small_workload(n, 1, (0.5, 0.5), 0.2)
+    xy, tri = wl.solid_mesh()
+    ctx = fsi.Context(n, xy, tri, nu=1.3, rho=0.9, dt=0.02)
+    F = fluid.assemble(n, nu=1.3, rho=0.9, dt=0.02)
+    rp, col, val = ctx.export_csr("AF")
+    blk = F["Af_blocks"]
+    _same_pattern(rp, col, blk[(0, 0)])
+    scale = max(abs(blk[(0, 0)].data).max(), 1.0)
+    for k, key in enumerate([(0, 0), (0, 1), (1, 0), (1, 1)]):
+        B = blk[key].tocsr()
+        _same_pattern(rp, col, B)
+        assert np.abs(val[:, k] - B.data).max() <= 1e-12 * scale
+    rp, col, val = ctx.export_csr("MF")
+    _same_pattern(rp, col, F["Mf"])
+    assert np.abs(val[:, 0] - F["Mf"].data).max() <= 1e-14 * abs(F["Mf"].data).max()
+    rp, col, val = ctx.export_csr("B")
+    for k, B in enumerate([F["Bx_bc"], F["By_bc"]]):
+        _same_pattern(rp, col, B)
+        assert np.abs(val[:, k] - B.tocsr().data).max() <= 1e-13 * abs(B.data).max()
+    rp, col, val = ctx.export_csr("BT")
+    for k, B in enumerate([F["Bx_bc"], F["By_bc"]]):
+        Bt = B.T.tocsr()
+        Bt.sort_indices()
+        _same_pattern(rp, col, Bt)
+        assert np.abs(val[:, k] - Bt.data).max() <= 1e-13 * abs(B.data).max()
+    rp, col, val = ctx.export_csr("MP")
+    _same_pattern(rp, col, F["Mp"])
+    assert np.abs(val[:, 0] - F["Mp"].data).max() <= 1e-14 * abs(F["Mp"].data).max()
+    ctx.close()
+
+
+def test_solid_blocks():
+    print("[solid blocks]", flush=True)
+    wl = inputs.small_workload(16, 7, (0.45, 0.55), semi_axes=(0.25, 0.15), kappa=3.5)
+    S = system.FSISystem.from_workload(wl)
+    ctx = fsi.Context.from_workload(wl)
+    for name, A in (("AS", S.S["As"]), ("CS", S.S["Ms"])):
+        rp, col, val = ctx.export_csr(name)
+        _same_pattern(rp, col, A)
+        assert np.abs(val[:, 0] - A.data).max() <= 1e-13 * abs(A.data).max()
+    ctx.close()
+
+
+def _positions(name, S, angle):
+    X = S.xy_ref
+    if angle is None:
+        return X
+    Xr = inputs.rotation(X, (0.5, 0.5), angle)
+    Xr[:, 0] = 0.5 + 1.05 * (Xr[:, 0] - 0.5)
+    return Xr
+
+
+@pytest.mark.parametrize("name", list(small_workloads()))
+def test_coupling_bitexact(name):
+    print(f"[coupling {name}]", flush=True)
+    wl, angle = small_workloads()[name]
+    S = system.FSISystem.from_workload(wl)
+    X = _positions(name, S, angle)
+    S.set_position(X)
+    ctx = fsi.Context.from_workload(wl)
+    info = ctx.assemble_coupling(to_dev(soa(X)))
+    E, T = ctx.export_pairs()
+    ref = np.array(S.pieces, dtype=np.int64).reshape(-1, 2)
+    assert info["n_pairs"] == ref.shape[0]
+    assert np.array_equal(E, ref[:, 0]) and np.array_equal(T, ref[:, 1])
+    rp, col, val = ctx.export_csr("CF")
+    _same_pattern(rp, col, S.Cf)
+    assert np.abs(val[:, 0] - S.Cf.data).max() <= 1e-12 * abs(S.Cf.data).max()
+    rp, col, val = ctx.export_csr("CFT")
+    Ct = S.Cf.T.tocsr()
+    Ct.sort_indices()
+    _same_pattern(rp, col, Ct)
+    assert np.abs(val[:, 0] - Ct.data).max() <= 1e-12 * abs(S.Cf.data).max()
+    ctx.close()
+
+
+def test_coupling_matching_mesh_degenerate_contacts():
+    """Solid triangles equal to fluid triangles (every edge on a grid line)."""
+    print("[coupling matching mesh]", flush=True)
+    n = 8
+    p2, p1, _ = fluid.triangle_nodes(n)
+    Ts = [2 * (j * n + i) + t for j in (2, 3, 4) for i in (3, 4) for t in (0, 1)]
+    verts = sorted(set(int(v) for T in Ts for v in p1[T]))
+    ren = {v: k for k, v in enumerate(verts)}
+    xy = fluid.p1_coords(n)[verts]
+    tri = np.array([[ren[int(v)] for v in p1[T]] for T in Ts], dtype=np.int32)
+    S = system.FSISystem(n, xy, tri)
+    S.set_position(xy)
+    ctx = fsi.Context(n, xy, tri)
+    ctx.assemble_coupling(to_dev(soa(xy)))
+    E, T = ctx.export_pairs()
+    assert list(zip(E.tolist(), T.tolist())) == [(e, t) for e, t in S.pieces]
+    assert [t for _, t in S.pieces] == Ts
+    rp, col, val = ctx.export_csr("CF")
+    _same_pattern(rp, col, S.Cf)
+    assert np.abs(val[:, 0] - S.Cf.data).max() <= 1e-12 * abs(S.Cf.data).max()
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def pair32():
+    wl = inputs.WORKLOADS["disk32"]
+    S, ctx, X = make_pair(wl)
+    yield S, ctx, wl
+    ctx.close()
+
+
+def test_operator_fp64_fp32(pair32):
+    print("[operator]", flush=True)
+    S, ctx, wl = pair32
+    A = S.matrix()
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-1, 1, S.lay.N)
+    y_ref = A @ x
+    torch = torch_dev()
+    xd = to_dev(x)
+    yd = torch.zeros_like(xd)
+    ctx.apply_operator(xd, yd, fsi.FP64)
+    y = to_host(yd)
+    assert rel(y, y_ref) <= 1e-13
+    assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
+    ctx.apply_operator(xd, yd, fsi.FP32)
+    assert rel(to_host(yd), y_ref) <= 2e-6
+
+
+def test_rhs(pair32):
+    print("[rhs]", flush=True)
+    S, ctx, wl = pair32
+    lay = S.lay
+    rng = np.random.default_rng(12)
+    u = rng.uniform(-1, 1, 2 * lay.N2)
+    X = inputs.rotation(S.xy_ref, (0.5, 0.5), 0.1)
+    b_ref = S.rhs(u, X)
+    torch = torch_dev()
+    b = torch.zeros(lay.N, dtype=torch.float64, device="cuda")
+    ctx.build_rhs(to_dev(u), to_dev(soa(X)), b)
+    assert rel(to_host(b), b_ref) <= 1e-13
+
+
+def test_precond_blocks(pair32):
+    print("[precond]", flush=True)
+    S, ctx, wl = pair32
+    lay = S.lay
+    nf = lay.nf
+    rng = np.random.default_rng(13)
+    r = S.random_rhs(0, rng.uniform(-1, 1, lay.N))
+    torch = torch_dev()
+    rd = to_dev(r)
+    zd = torch.zeros_like(rd)
+    ctx.set_inner(1e-13, 2000)
+    ctx.apply_precond(rd, zd, fsi.PC_DIAG, fsi.FP64)
+    z = to_host(zd)
+    z22 = S.apply_A22_inv(r[nf:])
+    assert rel(z[nf:], z22) <= 1e-12
+    z11 = S.apply_A11_inv(r[:nf])
+    assert rel(z[:nf], z11) <= 1e-9
+    ctx.apply_precond(rd, zd, fsi.PC_TRI, fsi.FP64)
+    zt = to_host(zd)
+    zref = S.apply_precond(r, "tri")
+    assert rel(zt, zref) <= 1e-9
+    ctx.set_inner(-1.0, 1000)
+
+
+def _its_bound(its_oracle):
+    return its_oracle + max(2, math.ceil(0.1 * its_oracle))
+
+
+@pytest.mark.parametrize("pc", ["diag", "tri"])
+def test_gmres_small_case(pair32, pc):
+    print(f"[gmres {pc}]", flush=True)
+    S, ctx, wl = pair32
+    b = S.random_rhs(wl.seed)
+    A = S.matrix()
+    xs = S.solve_direct(b)
+    _, info = gmres.gmres(lambda v: A @ v, b, precond=lambda r: S.apply_precond(r, pc), restart=30, rtol=1e-8)
+    torch = torch_dev()
+    bd = to_dev(b)
+    xd = torch.zeros_like(bd)
+    st = ctx.gmres_solve(bd, xd, fsi.Opts(pc=fsi.PC_TRI if pc == "tri" else fsi.PC_DIAG))
+    x = to_host(xd)
+    print(f"  gpu its {st['its']} oracle its {info['its']} relres {st['relres_true']:.2e}", flush=True)
+    assert st["converged"] and st["relres_true"] <= 1e-8
+    assert rel(A @ x, b) <= 1e-8 * 1.0001
+    assert rel(x, xs) <= 1e-7
+    assert st["its"] <= _its_bound(info["its"])
+
+
+def test_gmres_mixed_precision(pair32):
+    print("[gmres mixed]", flush=True)
+    S, ctx, wl = pair32
+    b = S.random_rhs(wl.seed)
+    A = S.matrix()
+    xs = S.solve_direct(b)
+    torch = torch_dev()
+    bd = to_dev(b)
+    xd = torch.zeros_like(bd)
+    st = ctx.gmres_solve(bd, xd, fsi.Opts(pc=fsi.PC_TRI, prec=fsi.FP32))
+    x = to_host(xd)
+    print(f"  mixed its {st['its']} refinements {st['refinements']} relres {st['relres_true']:.2e}", flush=True)
+    assert st["converged"] and rel(A @ x, b) <= 1e-8 * 1.0001
+    assert rel(x, xs) <= 1e-7
+
+
+def test_step_against_oracle():
+    print("[step]", flush=True)
+    wl = inputs.small_workload(16, 4, (0.5, 0.5), 0.2, dt=0.01)
+    S = system.FSISystem.from_workload(wl)
+    lay = S.lay
+    rng = np.random.default_rng(21)
+    u = rng.uniform(-1, 1, 2 * lay.N2)
+    bnd2 = np.concatenate([S.F["bnd"], S.F["bnd"]])
+    u[bnd2] = 0.0
+    X = inputs.rotation(S.xy_ref, (0.5, 0.5), 0.2)
+    from oracle import step as ostep
+    x_ref, _ = ostep.step(S, u, X, solver="direct")
+    ctx = fsi.Context.from_workload(wl)
+    torch = torch_dev()
+    out = torch.zeros(lay.N, dtype=torch.float64, device="cuda")
+    st = ctx.step(to_dev(u), to_dev(soa(X)), out, fsi.Opts(pc=fsi.PC_TRI, rtol=1e-10))
+    assert st["converged"]
+    assert rel(to_host(out), x_ref) <= 1e-8
+    ctx.close()
+
+
+def test_error_paths():
+    print("[errors]", flush=True)
+    wl = inputs.small_workload(8, 2, (0.5, 0.5), 0.2)
+    xy, tri = wl.solid_mesh()
+    ctx = fsi.Context.from_workload(wl)
+    torch = torch_dev()
+    N = ctx.sizes["N"]
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(x)
+    with pytest.raises(fsi.FsiError) as e:
+        ctx.apply_operator(x, y)
+    assert e.value.code == fsi.FSI_E_STATE
+    bad = xy.copy()
+    bad[:, 0] = 1.0 - bad[:, 0]
+    with pytest.raises(fsi.FsiError) as e:
+        ctx.assemble_coupling(to_dev(soa(bad)))
+    assert e.value.code == fsi.FSI_E_MESH
+    out = xy.copy()
+    out[:, 0] += 0.45
+    with pytest.raises(fsi.FsiError) as e:
+        ctx.assemble_coupling(to_dev(soa(out)))
+    assert e.value.code == fsi.FSI_E_MESH
+    # a valid position afterwards still works
+    ctx.assemble_coupling(to_dev(soa(xy)))
+    ctx.apply_operator(x, y)
+    with pytest.raises(fsi.FsiError) as e:
+        fsi.Context(8, xy, tri[:, ::-1])
+    assert e.value.code == fsi.FSI_E_MESH
+    ctx.close()
+
+
+def test_repeatable_bitwise(pair32):
+    print("[determinism]", flush=True)
+    S, ctx, wl = pair32
+    b = S.random_rhs(wl.seed)
+    torch = torch_dev()
+    bd = to_dev(b)
+    outs = []
+    for _ in range(2):
+        ctx.assemble_coupling(to_dev(soa(S.xy_ref)))
+        xd = torch.zeros_like(bd)
+        ctx.gmres_solve(bd, xd, fsi.Opts(pc=fsi.PC_TRI))
+        outs.append(to_host(xd))
+    assert np.array_equal(outs[0], outs[1])
