@@ -16,6 +16,38 @@ Ctx::~Ctx() {
   if (hpin) hipHostFree(hpin);
 }
 
+void Prof::begin(hipStream_t s) {
+  if (used + 2 > ev.size()) {
+    for (int k = 0; k < 256; ++k) {
+      hipEvent_t e;
+      FSI_HIP(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+  }
+  FSI_HIP(hipEventRecord(ev[used], s));
+}
+
+void Prof::end(hipStream_t s) {
+  FSI_HIP(hipEventRecord(ev[used + 1], s));
+  used += 2;
+}
+
+double Prof::total_ms(int64_t &launches) {
+  double t = 0.0;
+  for (size_t k = 0; k + 1 < used; k += 2) {
+    float ms = 0.f;
+    FSI_HIP(hipEventSynchronize(ev[k + 1]));
+    FSI_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+    t += ms;
+  }
+  launches = (int64_t)(used / 2);
+  return t;
+}
+
+Prof::~Prof() {
+  for (auto e : ev) hipEventDestroy(e);
+}
+
 size_t Ctx::device_bytes() const {
   size_t b = Af.bytes() + Mf.bytes() + B.bytes() + BT.bytes() + Mp.bytes() + Mp_dinv.bytes() +
              Mp_dinv32.bytes() + bnd.bytes();
@@ -304,6 +336,34 @@ int fsi_export_csr(fsi_ctx *ctx, int block, int64_t *nrows, int64_t *nnz, int32_
     if (col && A->nnz) FSI_HIP(hipMemcpyAsync(col, A->col.p, A->nnz * 4, hipMemcpyDeviceToHost, c.stream));
     if (val && A->nnz) FSI_HIP(hipMemcpyAsync(val, v, A->nnz * w * 8, hipMemcpyDeviceToHost, c.stream));
     FSI_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+int fsi_profile(fsi_ctx *ctx, int enable) {
+  if (!ctx) return FSI_E_ARG;
+  Ctx &c = ctx->c;
+  c.prof64.on = c.prof32.on = enable != 0;
+  c.prof64.reset();
+  c.prof32.reset();
+  return FSI_OK;
+}
+
+int fsi_profile_read(fsi_ctx *ctx, int prec, int64_t *launches, double *total_ms,
+                     double *bytes_per_launch) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    Ctx &c = ctx->c;
+    FSI_REQUIRE(prec == FSI_FP64 || prec == FSI_FP32, FSI_E_ARG, "unknown precision");
+    FSI_HIP(hipStreamSynchronize(c.stream));
+    fsi::Prof &p = prec == FSI_FP64 ? c.prof64 : c.prof32;
+    int64_t cnt = 0;
+    double t = p.total_ms(cnt);
+    const double w = prec == FSI_FP64 ? 8.0 : 4.0;
+    const fsi::MgLevel &L = c.mgu.lv[0];
+    if (launches) *launches = cnt;
+    if (total_ms) *total_ms = t;
+    if (bytes_per_launch)
+      *bytes_per_launch = (double)L.A.nnz * (4 * w + 4) + (double)L.nodes * (4 + 14 * w) + 4.0;
   });
 }
 

@@ -43,6 +43,18 @@ struct Mg {
   size_t bytes() const;
 };
 
+// Event timing of one kernel class (pairs of events on the launching stream).
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  void begin(hipStream_t s);
+  void end(hipStream_t s);
+  double total_ms(int64_t &launches);
+  void reset() { used = 0; }
+  ~Prof();
+};
+
 struct Ctx {
   // problem
   int n = 0;
@@ -106,6 +118,8 @@ struct Ctx {
   double *hpin = nullptr;  // pinned host staging (hipHostMalloc)
   DevBuf<double> tmpN;     // N (operator/residual scratch)
   DevBuf<double> tmpS;     // 12 Ns (solid block scratch)
+
+  Prof prof64, prof32;        // finest-level Chebyshev product on A_f
 
   double inner_rtol = -1.0;   // < 0: default per precision
   int inner_maxit = 1000;

@@ -142,7 +142,7 @@ static void ensure_fp32_mg(Ctx &c) {
 template <typename T, int W, int NC>
 static T *chebyshev(int64_t nrows, const int *rp, const int *col, const T *val, const T *dinv,
                     double lmin, double lmax, int steps, const T *b, T *x, T *x2, T *d,
-                    bool zero_init, hipStream_t s) {
+                    bool zero_init, hipStream_t s, Prof *prof = nullptr) {
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
@@ -152,14 +152,18 @@ static T *chebyshev(int64_t nrows, const int *rp, const int *col, const T *val, 
                        dinv, b, (T)(1.0 / theta), d, x);
     FSI_CHECK_LAUNCH();
   } else {
+    if (prof) prof->begin(s);
     spmv<T, W, NC, SP_CHEB>(nrows, rp, col, val, x, nrows, x2, nrows, s, b, d, dinv, (T)0,
                             (T)(1.0 / theta));
+    if (prof) prof->end(s);
     std::swap(x, x2);
   }
   for (k = 1; k < steps; ++k) {
     double rho1 = 1.0 / (2.0 * sigma - rho);
+    if (prof) prof->begin(s);
     spmv<T, W, NC, SP_CHEB>(nrows, rp, col, val, x, nrows, x2, nrows, s, b, d, dinv,
                             (T)(rho1 * rho), (T)(2.0 * rho1 / delta));
+    if (prof) prof->end(s);
     std::swap(x, x2);
     rho = rho1;
   }
@@ -170,7 +174,7 @@ static T *chebyshev(int64_t nrows, const int *rp, const int *col, const T *val, 
 // One V-cycle at level l for right-hand side b (comps * nodes entries, component-major).
 // Returns the level work vector that holds the result.
 template <typename T, int W, int NC>
-static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s) {
+static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr) {
   MgLevel &L = mg.lv[l];
   T *x = Pr<T>::w(L, 0), *x2 = Pr<T>::w(L, 4), *r = Pr<T>::w(L, 2), *d = Pr<T>::w(L, 3);
   if (l + 1 == (int)mg.lv.size()) {
@@ -182,8 +186,9 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s) {
   const double lmax = L.lmax, lmin = L.lmax / 30.0;
   const T *dinv = Pr<T>::dinv(L);
   const T *val = Pr<T>::val(L.A);
+  Prof *pl = (l == 0) ? prof : nullptr;
   T *xs = chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, mg.degree,
-                              b, x, x2, d, true, s);
+                              b, x, x2, d, true, s, pl);
   T *xo = (xs == x) ? x2 : x;
   spmv<T, W, NC, SP_RESID>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, xs, L.nodes, r, L.nodes, s, b);
   MgLevel &C = mg.lv[l + 1];
@@ -194,7 +199,7 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s) {
   spmv<T, 1, NC, SP_ADD>(L.P.nrows, L.P.rowptr.p, L.P.col.p, Pr<T>::val(L.P), xc, C.nodes, xs,
                          L.nodes, s);
   return chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, mg.degree, b,
-                             xs, xo, d, false, s);
+                             xs, xo, d, false, s, pl);
 }
 
 // ---------------------------------------------------------------- A11 preconditioner
@@ -209,7 +214,8 @@ template <typename T>
 static void a11_precond(Ctx &c, const T *r, T *z) {
   hipStream_t s = c.stream;
   const int64_t N2 = c.N2, Np = c.Np;
-  T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s);
+  Prof *pf = std::is_same<T, double>::value ? &c.prof64 : &c.prof32;
+  T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr);
   FSI_HIP(hipMemcpyAsync(z, xu, 2 * N2 * sizeof(T), hipMemcpyDeviceToDevice, s));
   // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
   T *rp = Pr<T>::inner(c, 8).p;

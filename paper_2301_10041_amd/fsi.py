@@ -88,6 +88,9 @@ _SIGS = {
                                    C.POINTER(C.c_int64)]),
     "fsi_export_csr": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsi_profile": (C.c_int, [C.c_void_p, C.c_int]),
+    "fsi_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)]),
     "fsi_strerror": (C.c_char_p, [C.c_int]),
     "fsi_last_error": (C.c_char_p, [C.c_void_p]),
 }
@@ -224,6 +227,15 @@ class Context:
         o = (opts or Opts()).c()
         self._check(lib().fsi_step(self._h, C.byref(o), _ptr(u_n), _ptr(X_n), _ptr(state), C.byref(st)))
         return st.as_dict()
+
+    def profile(self, enable=True):
+        self._check(lib().fsi_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self, prec=FP64):
+        """(launches, total_ms, algorithmic bytes per launch) of the dominant kernel."""
+        n, t, b = C.c_int64(), C.c_double(), C.c_double()
+        self._check(lib().fsi_profile_read(self._h, int(prec), C.byref(n), C.byref(t), C.byref(b)))
+        return n.value, t.value, b.value
 
     def export_pairs(self):
         cnt = C.c_int64()
