@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--pc", choices=["tri", "diag"], default="tri")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-only", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run 3 plain device copies of 2 GiB (counter calibration)")
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
@@ -100,6 +102,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = inputs.WORKLOADS[args.workload]
     xy, tri = wl.solid_mesh()
     t0 = time.perf_counter()

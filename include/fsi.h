@@ -108,8 +108,11 @@ typedef struct {
   double rtol;          /* ||b - A x||_2 <= rtol ||b||_2 (default 1e-8, Sec. 6) */
   int32_t pc;           /* fsi_pc */
   int32_t prec;         /* fsi_prec: FP32 = SpMV and inner solves in FP32 (refinement in FP64) */
-  double inner_rtol;    /* relative tolerance of the inner A11 solve (default 1e-10 / 1e-6) */
-  int32_t inner_maxit;  /* inner MINRES steps per A11 solve (default 1000) */
+  double inner_rtol;    /* relative tolerance of the inner A11 solve (0: default, 1e-4 in FP64,
+                           1e-3 in FP32) */
+  int32_t inner_maxit;  /* inner MINRES steps per A11 solve (default 1000; 300 in FP32) */
+  double cycle_rtol;    /* FP32 refinement: residual reduction asked of each FGMRES cycle
+                           (default 1e-5); ignored in FP64 */
 } fsi_solve_opts;
 
 typedef struct {

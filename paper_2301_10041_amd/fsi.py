@@ -54,7 +54,8 @@ class CouplingInfo(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double), ("pc", C.c_int32),
-                ("prec", C.c_int32), ("inner_rtol", C.c_double), ("inner_maxit", C.c_int32)]
+                ("prec", C.c_int32), ("inner_rtol", C.c_double), ("inner_maxit", C.c_int32),
+                ("cycle_rtol", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -137,10 +138,11 @@ class Opts:
     prec: int = FP64
     inner_rtol: float = 0.0
     inner_maxit: int = 0
+    cycle_rtol: float = 0.0
 
     def c(self):
         return SolveOpts(self.restart, self.maxit, self.rtol, self.pc, self.prec, self.inner_rtol,
-                         self.inner_maxit)
+                         self.inner_maxit, self.cycle_rtol)
 
 
 class Context:
