@@ -64,6 +64,22 @@ def cpu_baseline_leg(workload: str) -> dict:
             "sample_s_per_step": t}
 
 
+def recorded_traffic(workload: str, kernel_key: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    record (profiles/traffic.json), or None when the record is for another workload or
+    the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))[f"{kernel_key}@{workload}"]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+            return None
+        return rec["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_cpu_baseline(workload: str):
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--workload", workload]
@@ -163,7 +179,9 @@ def main():
     m = res[main_tag]
     k = m["kernel"]
     roofline = {"bound": "hbm", "achieved": round(k["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(k["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(k["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                "traffic": recorded_traffic(args.workload, "k_spmv<double,4,2,4,SP_CHEB>")
+                if main_tag == "fp64" else None,
                 "kernel": "k_spmv<double,4,2,4,SP_CHEB> (finest-level Chebyshev product on A_f)"
                 if main_tag == "fp64" else "k_spmv<float,4,2,4,SP_CHEB>",
                 "bytes_per_launch": k["bytes_per_launch"], "avg_us": round(k["avg_us"], 2),
