@@ -301,3 +301,28 @@ def test_repeatable_bitwise(pair32):
         ctx.gmres_solve(bd, xd, fsi.Opts(pc=fsi.PC_TRI))
         outs.append(to_host(xd))
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_time_loop_against_oracle():
+    """Row a9: prescribed rotation (0.1 rad/s about the centre), u^{n+1} feeds the next
+    step, C_f re-clipped every step; every state within 1e-8 of the oracle's."""
+    print("[time loop]", flush=True)
+    wl = inputs.small_workload(16, 4, (0.5, 0.5), 0.2, dt=0.05)
+    S = system.FSISystem.from_workload(wl)
+    lay = S.lay
+    from oracle import step as ostep
+    Xk = lambda k: inputs.rotation(S.xy_ref, (0.5, 0.5), 0.1 * k * wl.dt * 20)
+    rng = np.random.default_rng(5)
+    u0 = rng.uniform(-1, 1, 2 * lay.N2)
+    steps = 4
+    ref = ostep.time_loop(S, Xk, steps, u0=u0, solver="direct")
+    ctx = fsi.Context.from_workload(wl)
+    torch = torch_dev()
+    u = to_dev(u0)
+    out = torch.zeros(lay.N, dtype=torch.float64, device="cuda")
+    for k in range(steps):
+        st = ctx.step(u, to_dev(soa(Xk(k))), out, fsi.Opts(pc=fsi.PC_TRI, rtol=1e-10))
+        assert st["converged"]
+        assert rel(to_host(out), ref[k]) <= 1e-8, k
+        u = out[:2 * lay.N2].clone()
+    ctx.close()
