@@ -90,6 +90,32 @@ def run_cpu_baseline(workload: str):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def run_serving(count: int, slots: int) -> dict:
+    """Request loop: `count` independent mixed-precision steps arriving by a Poisson
+    process at 200 req/s (grid 32..256, disk or ellipse, 216 to 12,150 triangles; request
+    i draws u^n from seed 1000 + i); HBM budget = free memory - 8 GB."""
+    from paper_2301_10041_amd import fsi, inputs, serve
+
+    trace = inputs.request_trace(count, 200.0, seed=4)
+    reqs = serve.requests_from_trace(trace)
+    srv = serve.Server(max_slots=slots, prec=fsi.FP32, pc=fsi.PC_TRI, rtol=1e-8)
+    # resident slots sized for the largest solid of the trace, two per grid size
+    warm = [inputs.Workload(f"warm{n}", n, [inputs.Solid(45, (0.5, 0.5), 0.2)], dt=0.01)
+            for n in (32, 64, 128, 256) for _ in range(2)]
+    srv.prewarm(warm)
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    summ = serve.summarize(res)
+    out = {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in summ.items()}
+    out.update(slots=slots, max_inflight=srv.max_inflight, evictions=srv.evictions,
+               budget_gb=round(srv.budget / 2**30, 1), wall_s=round(wall, 3),
+               steps_per_s=float(f"{len(res) / wall:.6g}"), dtype="f32+f64",
+               trace="512 requests, Poisson 200 req/s, n in {32,64,128,256}, m in 6..45")
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +126,9 @@ def main():
     ap.add_argument("--pc", choices=["tri", "diag"], default="tri")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-only", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run 3 plain device copies of 2 GiB (counter calibration)")
     args = ap.parse_args()
@@ -209,9 +238,13 @@ def main():
         out[tag] = {kk: (float(f"{v:.6g}") if isinstance(v, float) else v) for kk, v in r.items()}
     if "fp64" in res and "mixed" in res:
         out["mixed_speedup"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
+    ctx.close()
+    del state, Xs, u0
+    torch.cuda.empty_cache()
+    if not args.no_serve:
+        out["serving"] = run_serving(args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(args.workload)
-    ctx.close()
     print(json.dumps(out))
     return 0
 

@@ -148,7 +148,17 @@ enum fsi_block {
 int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *hip_stream,
                size_t hbm_budget, fsi_ctx **out);
 void fsi_destroy(fsi_ctx *ctx);
+
+/* Replace the solid mesh of an existing context (fluid blocks and multigrid are kept).
+ * Device buffers only grow, so re-meshing with a solid no larger than any earlier one
+ * allocates nothing: this lets a request loop keep one context per slot resident.  The
+ * coupling must be assembled again afterwards.  Errors: FSI_E_ARG, FSI_E_MESH, FSI_E_NOMEM. */
+int fsi_set_solid(fsi_ctx *ctx, const fsi_solid_desc *solid);
 int fsi_set_stream(fsi_ctx *ctx, void *hip_stream);
+
+/* Device bytes a context for this fluid grid and a solid of n_nodes / n_tris would hold
+ * (the estimate fsi_create checks against its budget); for admission control. */
+int fsi_footprint(const fsi_fluid_desc *fluid, int64_t n_nodes, int64_t n_tris, size_t *bytes);
 int fsi_sizes(const fsi_ctx *ctx, fsi_sizes_t *out);
 
 /* C_f(X^n) and its transpose (Sec. 4, the coupling assembly): the mapped solid triangles

@@ -73,7 +73,9 @@ static size_t estimate_bytes(int64_t n, int64_t ns, int64_t nt) {
   double krylov = 61 * N * 8 + 9 * (2 * N2 + Np) * 12 + 4 * N * 8;
   double solid = ns * (7 * 12 * 2 + 200) + nt * 60 + 60 * ns * 12;
   double cf = nt * 12 * (18 * 8 + 16) + 2 * 60 * ns * 12 + N2 * 8;
-  return (size_t)(fluid + mg + krylov + solid + cf);
+  // fixed work space (reduction partials, device scalars, pinned staging, small
+  // buffers) and a 10% margin so that the estimate bounds the measured footprint
+  return (size_t)(1.1 * (fluid + mg + krylov + solid + cf) + (4 << 20));
 }
 
 }  // namespace fsi
@@ -145,8 +147,8 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     fsi::make_shadow(c.B, c.stream);
     fsi::make_shadow(c.BT, c.stream);
     fsi::make_shadow(c.S, c.stream);
-    c.tmpN.alloc(c.N);
-    c.tmpS.alloc(12 * ns);
+    c.tmpN.reserve(c.N);
+    c.tmpS.reserve(12 * ns);
     c.dscal.alloc(512);
     FSI_HIP(hipStreamSynchronize(c.stream));
     if (hbm_budget)
@@ -164,6 +166,36 @@ void fsi_destroy(fsi_ctx *ctx) {
   if (!ctx) return;
   hipStreamSynchronize(ctx->c.stream);
   delete ctx;
+}
+
+int fsi_set_solid(fsi_ctx *ctx, const fsi_solid_desc *solid) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    FSI_REQUIRE(solid && solid->n_nodes >= 3 && solid->n_tris >= 1 && solid->xy && solid->tri,
+                FSI_E_ARG, "solid mesh needs >= 3 nodes, >= 1 triangle and non-null arrays");
+    FSI_REQUIRE(solid->kappa >= 0, FSI_E_ARG, "kappa must be >= 0");
+    Ctx &c = ctx->c;
+    FSI_HIP(hipStreamSynchronize(c.stream));
+    const int64_t ns = solid->n_nodes, nt = solid->n_tris;
+    c.have_cf = false;
+    c.kappa = solid->kappa;
+    c.Ns = ns;
+    c.Nt = nt;
+    c.N = 2 * c.N2 + c.Np + 4 * ns;
+    c.h_tri.assign(solid->tri, solid->tri + 3 * nt);
+    c.h_xy.assign(solid->xy, solid->xy + 2 * ns);
+    fsi::build_solid(c);
+    fsi::make_shadow(c.S, c.stream);
+    c.tmpN.reserve(c.N);
+    c.tmpS.reserve(12 * ns);
+    FSI_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+int fsi_footprint(const fsi_fluid_desc *fluid, int64_t n_nodes, int64_t n_tris, size_t *bytes) {
+  if (!fluid || !bytes || fluid->n < 2 || n_nodes < 3 || n_tris < 1) return FSI_E_ARG;
+  *bytes = fsi::estimate_bytes(fluid->n, n_nodes, n_tris);
+  return FSI_OK;
 }
 
 int fsi_set_stream(fsi_ctx *ctx, void *hip_stream) {

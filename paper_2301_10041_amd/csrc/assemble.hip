@@ -459,9 +459,11 @@ void build_solid(Ctx &c) {
     cols.insert(cols.end(), tmpn.begin(), tmpn.end());
     rp[l + 1] = (int)cols.size();
   }
+  // grow-only buffers: a context re-meshed with a solid of equal or smaller size
+  // (fsi_set_solid) allocates nothing
   auto up = [&](auto &buf, const auto &vec) {
     using T = typename std::decay_t<decltype(vec)>::value_type;
-    buf.alloc(vec.size());
+    buf.reserve(vec.size());
     FSI_HIP(hipMemcpyAsync(buf.p, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, s));
   };
   up(c.tri, c.h_tri);
@@ -472,18 +474,18 @@ void build_solid(Ctx &c) {
   c.S.nrows = ns; c.S.ncols = ns; c.S.width = 1; c.S.nnz = (int64_t)cols.size();
   up(c.S.rowptr, rp);
   up(c.S.col, cols);
-  c.S.val.alloc(cols.size());
-  c.Cs.alloc(cols.size());
+  c.S.val.reserve(cols.size());
+  c.Cs.reserve(cols.size());
   hipLaunchKernelGGL(k_asm_solid, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, c.n2e_ptr.p,
                      c.n2e.p, c.tri.p, c.ref_xy.p, c.S.rowptr.p, c.S.col.p, c.kappa, c.S.val.p,
                      c.Cs.p);
-  c.Cs_dinv.alloc(ns);
+  c.Cs_dinv.reserve(ns);
   hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, c.S.rowptr.p,
                      c.S.col.p, c.Cs.p, c.Cs_dinv.p);
   FSI_CHECK_LAUNCH();
-  c.Cs32.alloc(cols.size());
+  c.Cs32.reserve(cols.size());
   convert(c.Cs32.p, c.Cs.p, (int64_t)cols.size(), s);
-  c.Cs_dinv32.alloc(ns);
+  c.Cs_dinv32.reserve(ns);
   convert(c.Cs_dinv32.p, c.Cs_dinv.p, ns, s);
   FSI_HIP(hipStreamSynchronize(s));
 }

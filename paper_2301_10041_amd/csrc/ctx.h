@@ -110,6 +110,7 @@ struct Ctx {
   } inner;
   struct Outer {
     int m = 0;
+    int64_t ncap = 0;      // N the basis was allocated for
     DevBuf<double> V, Z, w, r, t, t2;
     DevBuf<float> x32, y32;
   } outer;

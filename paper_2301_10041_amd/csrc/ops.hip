@@ -130,7 +130,7 @@ const float *vals<float>(const Csr &A) { return A.val32.p; }
 
 void make_shadow(Csr &A, hipStream_t s) {
   size_t m = (size_t)A.nnz * A.width;
-  if (A.val32.n < m || !A.val32.p) A.val32.alloc(m);
+  A.val32.reserve(m);
   convert(A.val32.p, A.val.p, (int64_t)m, s);
 }
 

@@ -403,10 +403,9 @@ struct CycleOut {
 
 // One FGMRES cycle of at most `maxsteps` Arnoldi steps on A d = r0 (beta = ||r0||) with
 // operator and preconditioner in precision `prec`; adds the correction to x.
-static CycleOut fgmres_cycle(Ctx &c, int pc, int prec, const double *r0, double beta, double target,
-                             int maxsteps, double *x) {
+static CycleOut fgmres_cycle(Ctx &c, int m, int pc, int prec, const double *r0, double beta,
+                             double target, int maxsteps, double *x) {
   hipStream_t s = c.stream;
-  const int m = c.outer.m;
   const int64_t N = c.N;
   double *V = c.outer.V.p, *Z = c.outer.Z.p, *w = c.outer.w.p;
   lincomb(V, r0, r0, 1.0 / beta, 0.0, N, s);
@@ -486,12 +485,14 @@ void gmres_solve(Ctx &c, const fsi_solve_opts &o, const double *b, double *x, fs
   if (o.inner_maxit > 0) c.inner_maxit = o.inner_maxit;
   else if (prec == FSI_FP32) c.inner_maxit = std::min(c.inner_maxit, 300);
   const int64_t N = c.N;
-  if (c.outer.m < m) {
-    c.outer.V.alloc((size_t)(m + 1) * N);
-    c.outer.Z.alloc((size_t)m * N);
-    c.outer.m = m;
+  if (c.outer.m < m || c.outer.ncap < N) {
+    const int mm = std::max(m, c.outer.m);
+    const int64_t nn = std::max(N, c.outer.ncap);
+    c.outer.V.alloc((size_t)(mm + 1) * nn);
+    c.outer.Z.alloc((size_t)mm * nn);
+    c.outer.m = mm;
+    c.outer.ncap = nn;
   }
-  c.outer.m = m;
   c.outer.w.reserve(N);
   c.outer.r.reserve(N);
   c.dscal.reserve(8 + 2 * (m + 1) + 1 + 64);
@@ -519,7 +520,7 @@ void gmres_solve(Ctx &c, const fsi_solve_opts &o, const double *b, double *x, fs
     // reduce the FP64 residual by about 1e-5 (the FP32 operator's accuracy)
     const double cyc = o.cycle_rtol > 0 ? o.cycle_rtol : 1e-5;
     double cyc_target = prec == FSI_FP64 ? target : std::max(target, cyc * rn);
-    CycleOut co = fgmres_cycle(c, o.pc, prec, r, rn, cyc_target, maxit - S.its, x);
+    CycleOut co = fgmres_cycle(c, m, o.pc, prec, r, rn, cyc_target, maxit - S.its, x);
     S.its += co.steps;
     S.restarts += 1;
     if (prec == FSI_FP32) S.refinements += 1;

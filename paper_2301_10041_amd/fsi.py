@@ -75,6 +75,8 @@ _SIGS = {
                              C.POINTER(C.c_void_p)]),
     "fsi_destroy": (None, [C.c_void_p]),
     "fsi_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fsi_set_solid": (C.c_int, [C.c_void_p, C.POINTER(SolidDesc)]),
+    "fsi_footprint": (C.c_int, [C.POINTER(FluidDesc), C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "fsi_sizes": (C.c_int, [C.c_void_p, C.POINTER(Sizes)]),
     "fsi_assemble_coupling": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(CouplingInfo)]),
     "fsi_build_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -127,6 +129,15 @@ def _stream_handle(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return C.c_void_p(stream.cuda_stream)
+
+
+def footprint(n, n_nodes, n_tris, nu=1.0, rho=1.0, dt=0.01):
+    """Device bytes a context of this size would hold (admission estimate)."""
+    b = C.c_size_t()
+    rc = lib().fsi_footprint(C.byref(FluidDesc(int(n), nu, rho, dt)), int(n_nodes), int(n_tris), C.byref(b))
+    if rc != FSI_OK:
+        raise FsiError(rc, "fsi_footprint")
+    return b.value
 
 
 @dataclass
@@ -195,6 +206,19 @@ class Context:
     def refresh_sizes(self):
         self.sizes = self._sizes()
         return self.sizes
+
+    def set_solid(self, xy, tri, kappa=None):
+        """Replace the solid mesh (keeps fluid blocks; buffers only grow)."""
+        xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64))
+        self._xy_soa = np.ascontiguousarray(np.concatenate([xy[:, 0], xy[:, 1]]))
+        self._tri = np.ascontiguousarray(np.asarray(tri, dtype=np.int32).reshape(-1))
+        k = self.kappa if kappa is None else float(kappa)
+        sd = SolidDesc(xy.shape[0], self._tri.size // 3,
+                       self._xy_soa.ctypes.data_as(C.POINTER(C.c_double)),
+                       self._tri.ctypes.data_as(C.POINTER(C.c_int32)), k)
+        self._check(lib().fsi_set_solid(self._h, C.byref(sd)))
+        self.kappa = k
+        self.sizes = self._sizes()
 
     def set_stream(self, stream=None):
         self._check(lib().fsi_set_stream(self._h, _stream_handle(stream)))
