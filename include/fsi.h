@@ -66,7 +66,15 @@ enum fsi_status {
   FSI_E_STATE = -8       /* call order: e.g. operator apply before fsi_assemble_coupling */
 };
 
-enum fsi_prec { FSI_FP64 = 0, FSI_FP32 = 1 };  /* arithmetic of SpMV and inner solves */
+/* Arithmetic of a solve.  FSI_FP64: everything FP64.  FSI_FP32 (mixed): the inner block
+ * solves' multigrid V-cycles, Chebyshev mass solves and Schur approximation in FP32 with
+ * FP32 accumulation (the bulk of the bytes); Arnoldi, the operator, the A11 product of
+ * the inner Krylov recurrence, A22, residuals and clipping in FP64.  FSI_FP32_IR: as
+ * FSI_FP32 and the operator of the Arnoldi process in FP32 too, with iterative refinement
+ * on the FP64 residual (an FP32 product loses about kappa * 6e-8 to cancellation on smooth
+ * vectors, so each cycle gains only a few digits on fine grids).  fsi_apply_operator
+ * takes FSI_FP64 or FSI_FP32 (operator in FP32 arithmetic). */
+enum fsi_prec { FSI_FP64 = 0, FSI_FP32 = 1, FSI_FP32_IR = 2 };
 enum fsi_pc { FSI_PC_DIAG = 0, FSI_PC_TRI = 1 };/* Sec. 5: block-diagonal / block-triangular */
 
 /* Fluid: n x n grid on [0,1]^2 (n >= 2), viscosity nu, density rho (= solid density,
@@ -107,12 +115,12 @@ typedef struct {
   int32_t maxit;        /* outer Arnoldi steps over all restarts (default 10000) */
   double rtol;          /* ||b - A x||_2 <= rtol ||b||_2 (default 1e-8, Sec. 6) */
   int32_t pc;           /* fsi_pc */
-  int32_t prec;         /* fsi_prec: FP32 = SpMV and inner solves in FP32 (refinement in FP64) */
+  int32_t prec;         /* fsi_prec */
   double inner_rtol;    /* relative tolerance of the inner A11 solve (0: default, 1e-4 in FP64,
                            1e-3 in FP32) */
   int32_t inner_maxit;  /* inner MINRES steps per A11 solve (default 1000; 300 in FP32) */
-  double cycle_rtol;    /* FP32 refinement: residual reduction asked of each FGMRES cycle
-                           (default 1e-5); ignored in FP64 */
+  double cycle_rtol;    /* FSI_FP32_IR: residual reduction asked of each FGMRES cycle
+                           (default 1e-5); ignored otherwise */
 } fsi_solve_opts;
 
 typedef struct {
@@ -189,9 +197,8 @@ int fsi_apply_precond(fsi_ctx *ctx, int pc, int prec, const double *r, double *z
 int fsi_set_inner(fsi_ctx *ctx, double inner_rtol, int32_t inner_maxit);
 
 /* Right-preconditioned flexible GMRES(m) on eq. (matrix) from the initial guess in x,
- * stopping when ||b - A x||_2 <= rtol ||b||_2 (Sec. 6, recomputed in FP64).  With
- * prec = FSI_FP32 the solve is an iterative refinement: FP64 residual, FGMRES correction
- * with FP32 operator and preconditioner, FP64 update.  b, x: device N.  stats may be NULL.
+ * stopping when ||b - A x||_2 <= rtol ||b||_2 (Sec. 6, recomputed in FP64); precision
+ * forms as in fsi_prec.  b, x: device N.  stats may be NULL.
  * Errors: FSI_E_NOCONV, FSI_E_NONFINITE, FSI_E_STATE. */
 int fsi_gmres_solve(fsi_ctx *ctx, const fsi_solve_opts *opts, const double *b, double *x,
                     fsi_solve_stats *stats);

@@ -173,6 +173,14 @@ void apply_a11(Ctx &c, const T *x, T *y) {
 template void apply_a11<double>(Ctx &, const double *, double *);
 template void apply_a11<float>(Ctx &, const float *, float *);
 
+// A11 on FP64 vectors, arithmetic and matrix values in TA (FP32: values from the shadows)
+template <typename TA>
+void apply_a11_on64(Ctx &c, const double *x, double *y) {
+  launch_operator<TA, double, double>(c, x, y, true);
+}
+template void apply_a11_on64<double>(Ctx &, const double *, double *);
+template void apply_a11_on64<float>(Ctx &, const double *, double *);
+
 // ---- right-hand side of eq. (matrix)
 __global__ void k_rhs_u(int64_t N2, const int *rp, const int *col, const double *M,
                         const unsigned char *bnd, const double *u, double rdt, double *b) {

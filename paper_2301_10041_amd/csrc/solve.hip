@@ -14,18 +14,35 @@
 //             pressure Schur complement, with M_p^{-1} by Chebyshev-Jacobi and L_p^{-1} by
 //             one P1 multigrid V-cycle; the pinned node is the identity.
 // The outer solve is right-preconditioned flexible GMRES(m) with classical Gram-Schmidt
-// applied twice, FP64 Arnoldi vectors and the Givens reduction on the host; with FP32
-// arithmetic it is wrapped in iterative refinement on the FP64 residual.
+// applied twice, FP64 Arnoldi vectors and the Givens reduction on the host.  Mixed
+// precision (FP32) runs the preconditioner's multigrid and Schur parts in FP32; the
+// FP32_IR variant also applies the operator in FP32 inside the Arnoldi process and wraps
+// the cycles in iterative refinement on the FP64 residual.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "ctx.h"
 #include "kernels.h"
 
 namespace fsi {
 
+// FSI_TRACE=1 in the environment prints one line per inner solve and per outer cycle.
+static bool trace_on() {
+  static int on = -1;
+  if (on < 0) {
+    const char *e = std::getenv("FSI_TRACE");
+    on = (e && e[0] == '1') ? 1 : 0;
+  }
+  return on == 1;
+}
+
 template <typename T>
 void apply_a11(Ctx &c, const T *x, T *y);
+// A11 on FP64 vectors with arithmetic (and matrix values) in TA
+template <typename TA>
+void apply_a11_on64(Ctx &c, const double *x, double *y);
 
 // ---------------------------------------------------------------- small kernels
 // First Chebyshev step from x = 0: d = x = scale * Dinv b (NC components of `nodes`).
@@ -231,41 +248,59 @@ static void a11_precond(Ctx &c, const T *r, T *z) {
 }
 
 // ---------------------------------------------------------------- inner MINRES
+// The A11 preconditioner on FP64 vectors with arithmetic TA: FP32 runs on converted copies.
+template <typename TA>
+static void a11_precond_on64(Ctx &c, const double *r, double *z) {
+  if constexpr (std::is_same<TA, double>::value) {
+    a11_precond<double>(c, r, z);
+  } else {
+    const int64_t nf = 2 * c.N2 + c.Np;
+    convert(c.outer.x32.p, r, nf, c.stream);
+    a11_precond<float>(c, c.outer.x32.p, c.outer.y32.p);
+    convert(z, c.outer.y32.p, nf, c.stream);
+  }
+}
+
 // Preconditioned MINRES (Paige-Saunders recurrences) for A11 x = b from x = 0; stops when
-// the preconditioned residual estimate falls below tol times its initial value.
-template <typename T>
-static int minres_a11(Ctx &c, const T *b, T *x, double tol, int maxit) {
+// the preconditioned residual estimate falls below tol times its initial value.  The
+// Lanczos vectors, dot products, updates and the A11 product are FP64 in every mode; TA is
+// the arithmetic of the preconditioner (V-cycle, Chebyshev mass solve, pressure V-cycle).
+// An FP32 product of A_f on a smooth vector loses about kappa * eps_32 (0.06 at 1024^2
+// cells) to cancellation, which stalls the recurrence; inside the V-cycle the residuals
+// are not smooth-dominated and FP32 arithmetic costs the preconditioner nothing.
+template <typename TA>
+static int minres_a11(Ctx &c, const double *b, double *x, double tol, int maxit) {
   hipStream_t s = c.stream;
   const int64_t nf = 2 * c.N2 + c.Np;
-  T *v = Pr<T>::inner(c, 0).p, *y = Pr<T>::inner(c, 1).p, *r1 = Pr<T>::inner(c, 2).p,
-    *r2 = Pr<T>::inner(c, 3).p, *w = Pr<T>::inner(c, 4).p, *w1 = Pr<T>::inner(c, 5).p,
-    *w2 = Pr<T>::inner(c, 6).p;
+  double *v = c.inner.v64[0].p, *y = c.inner.v64[1].p, *r1 = c.inner.v64[2].p,
+         *r2 = c.inner.v64[3].p, *w = c.inner.v64[4].p, *w1 = c.inner.v64[5].p,
+         *w2 = c.inner.v64[6].p;
   double *dv = c.dscal.p;   // [0] alfa, [1] beta^2
-  fill(x, nf, (T)0, s);
-  fill(w, nf, (T)0, s);
-  fill(w2, nf, (T)0, s);
-  FSI_HIP(hipMemcpyAsync(r1, b, nf * sizeof(T), hipMemcpyDeviceToDevice, s));
-  a11_precond<T>(c, r1, y);
+  fill(x, nf, 0.0, s);
+  fill(w, nf, 0.0, s);
+  fill(w2, nf, 0.0, s);
+  FSI_HIP(hipMemcpyAsync(r1, b, nf * sizeof(double), hipMemcpyDeviceToDevice, s));
+  a11_precond_on64<TA>(c, r1, y);
   multidot(r1, 0, 1, y, nf, dv + 1, c.red, s);
   FSI_HIP(hipMemcpyAsync(c.hpin, dv, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   FSI_HIP(hipStreamSynchronize(s));
   double b2 = c.hpin[1];
   FSI_REQUIRE(std::isfinite(b2), FSI_E_NONFINITE, "non-finite residual in the inner A11 solve");
   if (b2 <= 0.0) return 0;
-  FSI_HIP(hipMemcpyAsync(r2, r1, nf * sizeof(T), hipMemcpyDeviceToDevice, s));
+  FSI_HIP(hipMemcpyAsync(r2, r1, nf * sizeof(double), hipMemcpyDeviceToDevice, s));
   double beta1 = std::sqrt(b2), beta = beta1, oldb = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta1;
   double cs = -1.0, sn = 0.0;
   int it;
   for (it = 1; it <= maxit; ++it) {
-    lincomb(v, y, y, (T)(1.0 / beta), (T)0, nf, s);
-    apply_a11<T>(c, v, y);
-    if (it >= 2) axpby(y, r1, (T)(-beta / oldb), (T)1, nf, s);
+    lincomb(v, y, y, 1.0 / beta, 0.0, nf, s);
+    apply_a11_on64<double>(c, v, y);
+    if (it >= 2) axpby(y, r1, -beta / oldb, 1.0, nf, s);
     multidot(v, 0, 1, y, nf, dv, c.red, s);
-    hipLaunchKernelGGL(k_sub_dev<T>, dim3(vgrid(nf)), dim3(256), 0, s, y, r2, dv, 1.0 / beta, nf);
+    hipLaunchKernelGGL(k_sub_dev<double>, dim3(vgrid(nf)), dim3(256), 0, s, y, r2, dv, 1.0 / beta, nf);
     FSI_CHECK_LAUNCH();
     std::swap(r1, r2);   // r1 <- previous r2
     std::swap(r2, y);    // r2 <- new Lanczos vector
-    a11_precond<T>(c, r2, y);
+    a11_precond_on64<TA>(c, r2, y);
     multidot(r2, 0, 1, y, nf, dv + 1, c.red, s);
     FSI_HIP(hipMemcpyAsync(c.hpin, dv, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     FSI_HIP(hipStreamSynchronize(s));
@@ -286,15 +321,19 @@ static int minres_a11(Ctx &c, const T *b, T *x, double tol, int maxit) {
     double phi = cs * phibar;
     phibar = sn * phibar;
     // new direction from the previous two (w2 and w); w1's buffer is free
-    T *wn = w1;
-    hipLaunchKernelGGL(k_minres_update<T>, dim3(vgrid(nf)), dim3(256), 0, s, wn, v, w2, w, x,
-                       (T)oldeps, (T)delta, (T)(1.0 / gamma), (T)phi, nf);
+    double *wn = w1;
+    hipLaunchKernelGGL(k_minres_update<double>, dim3(vgrid(nf)), dim3(256), 0, s, wn, v, w2, w, x,
+                       oldeps, delta, 1.0 / gamma, phi, nf);
     FSI_CHECK_LAUNCH();
     w1 = w2;
     w2 = w;
     w = wn;
     if (phibar <= tol * beta1 || beta == 0.0) break;
   }
+  if (trace_on())
+    std::fprintf(stderr, "[fsi] minres<%s> its=%d relres_est=%.3e beta=%.3e\n",
+                 std::is_same<TA, double>::value ? "f64" : "f32", it > maxit ? maxit : it,
+                 phibar / beta1, beta);
   return it > maxit ? maxit : it;
 }
 
@@ -325,12 +364,11 @@ static void a22_solve(Ctx &c, const double *rX, const double *rl, double *zX, do
 // ---------------------------------------------------------------- block preconditioner
 static void ensure_inner(Ctx &c, int prec) {
   const int64_t nf = 2 * c.N2 + c.Np;
-  if (prec == FSI_FP64) {
-    for (int i = 0; i < 9; ++i)
-      if (!c.inner.v64[i].p) c.inner.v64[i].alloc(nf);
-  } else {
+  for (int i = 0; i < 9; ++i)
+    if (!c.inner.v64[i].p) c.inner.v64[i].alloc(nf);
+  if (prec == FSI_FP32) {
     ensure_fp32_mg(c);
-    for (int i = 0; i < 9; ++i)
+    for (int i = 7; i < 9; ++i)       // pressure scratch of the FP32 preconditioner
       if (!c.inner.v32[i].p) c.inner.v32[i].alloc(nf);
     if (!c.outer.x32.p) { c.outer.x32.alloc(nf); c.outer.y32.alloc(nf); }
     if (!c.Mp_dinv32.p) {
@@ -351,19 +389,15 @@ double inner_tol(const Ctx &c, int prec) {
 void apply_precond(Ctx &c, int pc, int prec, const double *r, double *z) {
   hipStream_t s = c.stream;
   FSI_REQUIRE(pc == FSI_PC_DIAG || pc == FSI_PC_TRI, FSI_E_ARG, "unknown preconditioner");
-  FSI_REQUIRE(prec == FSI_FP64 || prec == FSI_FP32, FSI_E_ARG, "unknown precision");
+  FSI_REQUIRE(prec == FSI_FP64 || prec == FSI_FP32 || prec == FSI_FP32_IR, FSI_E_ARG,
+              "unknown precision");
+  if (prec == FSI_FP32_IR) prec = FSI_FP32;
   FSI_REQUIRE(c.have_cf || pc == FSI_PC_DIAG, FSI_E_STATE, "block-triangular needs C_f: call fsi_assemble_coupling");
   ensure_inner(c, prec);
   const int64_t nf = 2 * c.N2 + c.Np, ns = c.Ns;
   const double tol = inner_tol(c, prec);
-  int its;
-  if (prec == FSI_FP64) {
-    its = minres_a11<double>(c, r, z, tol, c.inner_maxit);
-  } else {
-    convert(c.outer.x32.p, r, nf, s);
-    its = minres_a11<float>(c, c.outer.x32.p, c.outer.y32.p, tol, c.inner_maxit);
-    convert(z, c.outer.y32.p, nf, s);
-  }
+  int its = prec == FSI_FP64 ? minres_a11<double>(c, r, z, tol, c.inner_maxit)
+                             : minres_a11<float>(c, r, z, tol, c.inner_maxit);
   c.inner_its_total += its;
   const double *rX = r + nf, *rl = r + nf + 2 * ns;
   double *zX = z + nf, *zl = z + nf + 2 * ns;
@@ -403,8 +437,8 @@ struct CycleOut {
 
 // One FGMRES cycle of at most `maxsteps` Arnoldi steps on A d = r0 (beta = ||r0||) with
 // operator and preconditioner in precision `prec`; adds the correction to x.
-static CycleOut fgmres_cycle(Ctx &c, int m, int pc, int prec, const double *r0, double beta,
-                             double target, int maxsteps, double *x) {
+static CycleOut fgmres_cycle(Ctx &c, int m, int pc, int op_prec, int pc_prec, const double *r0,
+                             double beta, double target, int maxsteps, double *x) {
   hipStream_t s = c.stream;
   const int64_t N = c.N;
   double *V = c.outer.V.p, *Z = c.outer.Z.p, *w = c.outer.w.p;
@@ -416,8 +450,8 @@ static CycleOut fgmres_cycle(Ctx &c, int m, int pc, int prec, const double *r0, 
   double *dh = c.dscal.p + 8;   // h1 (m+1), h2 (m+1), hn2
   for (int j = 0; j < maxsteps && j < m; ++j) {
     double *Vj = V + (int64_t)j * N, *Zj = Z + (int64_t)j * N;
-    apply_precond(c, pc, prec, Vj, Zj);
-    op_apply(c, prec, Zj, w);
+    apply_precond(c, pc, pc_prec, Vj, Zj);
+    op_apply(c, op_prec, Zj, w);
     multidot(V, N, j + 1, w, N, dh, c.red, s);
     hipLaunchKernelGGL(k_multiaxpy_sub, dim3(vgrid(N)), dim3(256), 0, s, w, V, N, j + 1, dh, N);
     multidot(V, N, j + 1, w, N, dh + (m + 1), c.red, s);
@@ -473,7 +507,12 @@ void gmres_solve(Ctx &c, const fsi_solve_opts &o, const double *b, double *x, fs
   const int maxit = o.maxit > 0 ? o.maxit : 10000;
   const double rtol = o.rtol > 0 ? o.rtol : 1e-8;
   const int prec = o.prec;
-  FSI_REQUIRE(prec == FSI_FP64 || prec == FSI_FP32, FSI_E_ARG, "unknown precision");
+  FSI_REQUIRE(prec == FSI_FP64 || prec == FSI_FP32 || prec == FSI_FP32_IR, FSI_E_ARG,
+              "unknown precision");
+  // operator of the Arnoldi process and arithmetic of the preconditioner
+  const int op_prec = prec == FSI_FP32_IR ? FSI_FP32 : FSI_FP64;
+  const int pc_prec = prec == FSI_FP64 ? FSI_FP64 : FSI_FP32;
+  const bool refine = prec == FSI_FP32_IR;
   // per-solve inner settings; the context's own (fsi_set_inner) come back afterwards
   struct Restore {
     Ctx &c;
@@ -516,14 +555,17 @@ void gmres_solve(Ctx &c, const fsi_solve_opts &o, const double *b, double *x, fs
     FSI_REQUIRE(std::isfinite(rn), FSI_E_NONFINITE, "non-finite residual");
     if (rn <= target) { conv = true; break; }
     if (S.its >= maxit) break;
-    // FP64: restart cycles toward the final target; FP32: refinement cycles that each
-    // reduce the FP64 residual by about 1e-5 (the FP32 operator's accuracy)
+    // restart cycles toward the final target; with FP32_IR, refinement cycles that each
+    // ask the FP32 operator for a cycle_rtol reduction of the FP64 residual
     const double cyc = o.cycle_rtol > 0 ? o.cycle_rtol : 1e-5;
-    double cyc_target = prec == FSI_FP64 ? target : std::max(target, cyc * rn);
-    CycleOut co = fgmres_cycle(c, m, o.pc, prec, r, rn, cyc_target, maxit - S.its, x);
+    double cyc_target = refine ? std::max(target, cyc * rn) : target;
+    CycleOut co = fgmres_cycle(c, m, o.pc, op_prec, pc_prec, r, rn, cyc_target, maxit - S.its, x);
+    if (trace_on())
+      std::fprintf(stderr, "[fsi] cycle prec=%d steps=%d rn/bn=%.3e est/bn=%.3e\n", prec, co.steps,
+                   rn / bnorm, co.est / bnorm);
     S.its += co.steps;
     S.restarts += 1;
-    if (prec == FSI_FP32) S.refinements += 1;
+    if (refine) S.refinements += 1;
     S.relres_est = co.est / bnorm;
   }
   S.converged = conv ? 1 : 0;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfsi.so")
 
 FSI_OK, FSI_E_ARG, FSI_E_MESH, FSI_E_NOMEM, FSI_E_NOCONV, FSI_E_NONFINITE, FSI_E_HIP, \
     FSI_E_CAPACITY, FSI_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
-FP64, FP32 = 0, 1
+FP64, FP32, FP32_IR = 0, 1, 2
 PC_DIAG, PC_TRI = 0, 1
 BLOCKS = dict(AF=0, MF=1, B=2, BT=3, AS=4, CS=5, CF=6, CFT=7, MP=8)
 

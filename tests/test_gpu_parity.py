@@ -231,9 +231,11 @@ def test_gmres_mixed_precision(pair32):
     xd = torch.zeros_like(bd)
     st = ctx.gmres_solve(bd, xd, fsi.Opts(pc=fsi.PC_TRI, prec=fsi.FP32))
     x = to_host(xd)
-    print(f"  mixed its {st['its']} refinements {st['refinements']} relres {st['relres_true']:.2e}", flush=True)
+    _, info = gmres.gmres(lambda v: A @ v, b, precond=lambda r: S.apply_precond(r, "tri"), restart=30, rtol=1e-8)
+    print(f"  mixed its {st['its']} (oracle {info['its']}) relres {st['relres_true']:.2e}", flush=True)
     assert st["converged"] and rel(A @ x, b) <= 1e-8 * 1.0001
     assert rel(x, xs) <= 1e-7
+    assert st["its"] <= _its_bound(info["its"])
 
 
 def test_step_against_oracle():
@@ -326,3 +328,20 @@ def test_time_loop_against_oracle():
         assert rel(to_host(out), ref[k]) <= 1e-8, k
         u = out[:2 * lay.N2].clone()
     ctx.close()
+
+
+def test_gmres_fp32_ir(pair32):
+    """The refinement form: FP32 operator inside the Arnoldi process, FP64 residuals."""
+    print("[gmres fp32-ir]", flush=True)
+    S, ctx, wl = pair32
+    b = S.random_rhs(wl.seed)
+    A = S.matrix()
+    xs = S.solve_direct(b)
+    torch = torch_dev()
+    bd = to_dev(b)
+    xd = torch.zeros_like(bd)
+    st = ctx.gmres_solve(bd, xd, fsi.Opts(pc=fsi.PC_TRI, prec=fsi.FP32_IR))
+    x = to_host(xd)
+    print(f"  fp32-ir its {st['its']} refinements {st['refinements']} relres {st['relres_true']:.2e}", flush=True)
+    assert st["converged"] and st["refinements"] >= 1 and rel(A @ x, b) <= 1e-8 * 1.0001
+    assert rel(x, xs) <= 1e-7
