@@ -214,10 +214,10 @@ def main():
     k = m["kernel"]
     roofline = {"bound": "hbm", "achieved": round(k["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(k["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                "traffic": recorded_traffic(args.workload, "k_spmv<double,4,2,4,SP_CHEB>")
+                "traffic": recorded_traffic(args.workload, "k_stencil<double,SP_CHEB>")
                 if main_tag == "fp64" else None,
-                "kernel": "k_spmv<double,4,2,4,SP_CHEB> (finest-level Chebyshev product on A_f)"
-                if main_tag == "fp64" else "k_spmv<float,4,2,4,SP_CHEB>",
+                "kernel": ("k_stencil<%s,SP_CHEB> (finest-level matrix-free Chebyshev step on A_f)"
+                           % ("double" if main_tag == "fp64" else "float")),
                 "bytes_per_launch": k["bytes_per_launch"], "avg_us": round(k["avg_us"], 2),
                 "launches": k["launches"]}
     out = {

@@ -218,15 +218,24 @@ int fsi_export_pairs(fsi_ctx *ctx, int32_t *E, int32_t *T, int64_t cap, int64_t 
 int fsi_export_csr(fsi_ctx *ctx, int block, int64_t *nrows, int64_t *nnz, int32_t *width,
                    int32_t *rowptr, int32_t *col, double *val);
 
+/* Products with A_f inside the multigrid V-cycle: FSI_SMOOTH_STENCIL (default) applies
+ * A_f matrix-free from four translation-invariant 2x2-block stencils of the structured
+ * grid (same element matrices as the assembled A_f; boundary rows identity, boundary
+ * columns zero); FSI_SMOOTH_CSR reads the assembled blocks.  Both give the same V-cycle up
+ * to the order of the sums. */
+enum fsi_smoother { FSI_SMOOTH_CSR = 0, FSI_SMOOTH_STENCIL = 1 };
+int fsi_set_smoother(fsi_ctx *ctx, int kind);
+
 /* Measurement of the dominant kernel: the finest-level Chebyshev smoothing product on A_f
  * (2x2 blocks; d = c1 d + c2 D^{-1}(b - A_f x), y = x + d), which carries most of the
  * bytes of a step.  fsi_profile(ctx, 1) starts (and resets) timing every such launch with
  * a pair of HIP events on the context's stream; fsi_profile(ctx, 0) stops.
  * fsi_profile_read synchronises and returns, for precision prec, the number of timed
  * launches, their summed duration in milliseconds and the algorithmic bytes one launch
- * must move: nnz (4 w + 4) + N2 (4 + 14 w) + 4 with w = 8 (FP64) or 4 (FP32) bytes
- * (values and column indices once; per node the row pointer, x, b, d read and written,
- * the inverse 2x2 diagonal block and y). */
+ * must move, with w = 8 (FP64) or 4 (FP32) bytes: stencil form 10 w N2 (x, b, d read, d
+ * and y written, two components each); CSR form nnz (4 w + 4) + N2 (4 + 14 w) + 4 (values
+ * and column indices once; per node the row pointer, x, b, d read and written, the
+ * inverse 2x2 diagonal block and y). */
 int fsi_profile(fsi_ctx *ctx, int enable);
 int fsi_profile_read(fsi_ctx *ctx, int prec, int64_t *launches, double *total_ms,
                      double *bytes_per_launch);

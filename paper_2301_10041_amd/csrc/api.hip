@@ -143,6 +143,7 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     fsi::build_solid(c);
     fsi::build_fluid(c);
     fsi::build_multigrid(c);
+    c.mgu.stencil = true;
     fsi::make_shadow(c.Af, c.stream);
     fsi::make_shadow(c.B, c.stream);
     fsi::make_shadow(c.BT, c.stream);
@@ -190,6 +191,13 @@ int fsi_set_solid(fsi_ctx *ctx, const fsi_solid_desc *solid) {
     c.tmpS.reserve(12 * ns);
     FSI_HIP(hipStreamSynchronize(c.stream));
   });
+}
+
+int fsi_set_smoother(fsi_ctx *ctx, int kind) {
+  if (!ctx) return FSI_E_ARG;
+  if (kind != FSI_SMOOTH_CSR && kind != FSI_SMOOTH_STENCIL) return FSI_E_ARG;
+  ctx->c.mgu.stencil = kind == FSI_SMOOTH_STENCIL;
+  return FSI_OK;
 }
 
 int fsi_footprint(const fsi_fluid_desc *fluid, int64_t n_nodes, int64_t n_tris, size_t *bytes) {
@@ -395,7 +403,9 @@ int fsi_profile_read(fsi_ctx *ctx, int prec, int64_t *launches, double *total_ms
     if (launches) *launches = cnt;
     if (total_ms) *total_ms = t;
     if (bytes_per_launch)
-      *bytes_per_launch = (double)L.A.nnz * (4 * w + 4) + (double)L.nodes * (4 + 14 * w) + 4.0;
+      *bytes_per_launch = c.mgu.stencil
+                              ? (double)L.nodes * 10 * w
+                              : (double)L.A.nnz * (4 * w + 4) + (double)L.nodes * (4 + 14 * w) + 4.0;
   });
 }
 

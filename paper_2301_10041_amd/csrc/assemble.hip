@@ -8,10 +8,12 @@
 // are visited in a fixed window order that coincides with ascending node index.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 
 #include "ctx.h"
 #include "kernels.h"
+#include "stencil.h"
 
 namespace fsi {
 
@@ -27,6 +29,8 @@ constexpr int EM_M = 0, EM_K = 36, EM_B = 180, EM_MP = 216, EM_LP = 225, EM_SIZE
 // Lattice offsets of the six P2 nodes (a, b, c, ab, bc, ca) of the two triangles of a
 // cell, in units of h/2 from the cell's lower-left node (2i, 2j).
 __constant__ int kOff[2][6][2] = {{{0, 0}, {2, 0}, {2, 2}, {1, 0}, {2, 1}, {1, 1}},
+                                  {{0, 0}, {2, 2}, {0, 2}, {1, 1}, {1, 2}, {0, 1}}};
+static const int hOff[2][6][2] = {{{0, 0}, {2, 0}, {2, 2}, {1, 0}, {2, 1}, {1, 1}},
                                   {{0, 0}, {2, 2}, {0, 2}, {1, 1}, {1, 2}, {0, 1}}};
 
 // Element matrices of T0 = (v00, v10, v11) and T1 = (v00, v11, v01) of a cell of side h.
@@ -89,6 +93,71 @@ static void element_tables(int n, double nu, std::vector<double> &out) {
 
 __global__ void k_diag_inv(int64_t nrows, const int *rowptr, const int *col, const double *v,
                            double *dinv);
+
+// Host: rows of A_f at one interior node of each class, gathered like k_asm_p2p2 (the same
+// window order and the same order of triangles), with offsets relative to the node.
+void stencil_tables(int n, double nu, double rdt, StencilTable<double> &t64, StencilTable<float> &t32) {
+  FSI_REQUIRE(n >= 2, FSI_E_ARG, "stencil tables need n >= 2");
+  std::vector<double> E;
+  element_tables(n, nu, E);
+  std::memset(&t64, 0, sizeof(t64));
+  std::memset(&t32, 0, sizeof(t32));
+  for (int cls = 0; cls < 4; ++cls) {
+    const int I = 2 + (cls & 1), J = 2 + ((cls >> 1) & 1);   // interior for n >= 2
+    struct A { int ci, cj, t, a; } adj[8];
+    int na = 0;
+    for (int cj = std::max(0, (J - 1) >> 1); cj <= std::min(n - 1, J >> 1); ++cj)
+      for (int ci = std::max(0, (I - 1) >> 1); ci <= std::min(n - 1, I >> 1); ++ci)
+        for (int t = 0; t < 2; ++t)
+          for (int a = 0; a < 6; ++a)
+            if (2 * ci + hOff[t][a][0] == I && 2 * cj + hOff[t][a][1] == J) {
+              adj[na++] = A{ci, cj, t, a};
+              break;
+            }
+    int cnt = 0;
+    for (int dJ = -2; dJ <= 2; ++dJ)
+      for (int dI = -2; dI <= 2; ++dI) {
+        bool touched = false;
+        double m = 0, kxx = 0, kxy = 0, kyx = 0, kyy = 0;
+        for (int q = 0; q < na; ++q) {
+          int b = -1;
+          for (int bb = 0; bb < 6; ++bb)
+            if (2 * adj[q].ci + hOff[adj[q].t][bb][0] == I + dI && 2 * adj[q].cj + hOff[adj[q].t][bb][1] == J + dJ) b = bb;
+          if (b < 0) continue;
+          touched = true;
+          const double *e = E.data() + adj[q].t * EM_SIZE;
+          const int a = adj[q].a;
+          m += e[EM_M + a * 6 + b];
+          kxx += e[EM_K + ((0 * 2 + 0) * 6 + a) * 6 + b];
+          kxy += e[EM_K + ((0 * 2 + 1) * 6 + a) * 6 + b];
+          kyx += e[EM_K + ((1 * 2 + 0) * 6 + a) * 6 + b];
+          kyy += e[EM_K + ((1 * 2 + 1) * 6 + a) * 6 + b];
+        }
+        if (!touched) continue;
+        FSI_REQUIRE(cnt < kStencilMax, FSI_E_ARG, "stencil too wide");
+        double v[4] = {rdt * m + kxx, kxy, kyx, rdt * m + kyy};
+        t64.off[cls][cnt][0] = t32.off[cls][cnt][0] = dI;
+        t64.off[cls][cnt][1] = t32.off[cls][cnt][1] = dJ;
+        t64.lin[cls][cnt] = t32.lin[cls][cnt] = dJ * (2 * n + 1) + dI;
+        t64.lds[cls][cnt] = t32.lds[cls][cnt] = dJ * (kTileC + 4) + dI;
+        for (int q = 0; q < 4; ++q) {
+          t64.coef[cls][cnt][q] = v[q];
+          t32.coef[cls][cnt][q] = (float)v[q];
+        }
+        if (dI == 0 && dJ == 0) {
+          double det = v[0] * v[3] - v[1] * v[2];
+          double di[4] = {v[3] / det, -v[1] / det, -v[2] / det, v[0] / det};
+          for (int q = 0; q < 4; ++q) {
+            t64.dinv[cls][q] = di[q];
+            t32.dinv[cls][q] = (float)di[q];
+          }
+        }
+        ++cnt;
+      }
+    t64.count[cls] = t32.count[cls] = cnt;
+    FSI_REQUIRE(cnt == kStencilCount[cls], FSI_E_ARG, "unexpected stencil width");
+  }
+}
 
 // ---------------------------------------------------------------- structured adjacency
 struct Adj {
@@ -794,6 +863,16 @@ void build_multigrid(Ctx &c) {
                        P.A.rowptr.p, P.A.col.p, P.A.val.p, P.dinv.p);
     FSI_CHECK_LAUNCH();
     U.lmax = 1.1 * power_lmax(U, 2, s);
+    {
+      StencilTable<double> t64;
+      StencilTable<float> t32;
+      stencil_tables(m, c.nu, c.rho / c.dt, t64, t32);
+      U.stab64.alloc(sizeof(t64));
+      U.stab32.alloc(sizeof(t32));
+      FSI_HIP(hipMemcpyAsync(U.stab64.p, &t64, sizeof(t64), hipMemcpyHostToDevice, s));
+      FSI_HIP(hipMemcpyAsync(U.stab32.p, &t32, sizeof(t32), hipMemcpyHostToDevice, s));
+      FSI_HIP(hipStreamSynchronize(s));
+    }
     P.lmax = 1.1 * power_lmax(P, 1, s);
     if (l + 1 < ns.size()) {
       int64_t nc2 = (int64_t)(m + 1) * (m + 1);          // coarse P2 nodes = (2 (m/2) + 1)^2

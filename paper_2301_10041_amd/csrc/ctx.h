@@ -31,10 +31,12 @@ struct MgLevel {
   Csr P, R;                // prolongation from the next coarser level into this one; R = P^T
   DevBuf<double> w64[5];   // x, b, r, d, x2 work vectors
   DevBuf<float> w32[5];
+  DevBuf<unsigned char> stab64, stab32;   // StencilTable<double/float> (velocity levels)
 };
 
 struct Mg {
   int comps = 1;           // unknowns per node: 2 (velocity, 2x2 blocks) or 1 (pressure)
+  bool stencil = false;    // velocity smoothing and residuals matrix-free (structured grid)
   int degree = 3;          // Chebyshev smoothing steps before and after the coarse correction
   std::vector<MgLevel> lv; // lv[0] finest
   int64_t ncoarse = 0;     // unknowns of the coarsest level

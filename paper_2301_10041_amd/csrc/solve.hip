@@ -25,6 +25,7 @@
 
 #include "ctx.h"
 #include "kernels.h"
+#include "stencil.h"
 
 namespace fsi {
 
@@ -187,6 +188,43 @@ static T *chebyshev(int64_t nrows, const int *rp, const int *col, const T *val, 
   return x;
 }
 
+// The same Chebyshev iteration with the matrix-free A_f product on an n x n grid.
+template <typename T>
+static T *chebyshev_stencil(int n, const StencilTable<T> *tab, int64_t nodes, const T *dinv,
+                            double lmin, double lmax, int steps, const T *b, T *x, T *x2, T *d,
+                            bool zero_init, hipStream_t s, Prof *prof) {
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (zero_init) {
+    hipLaunchKernelGGL((k_dinv_first<T, 4, 2>), dim3(grid_for(nodes, 256)), dim3(256), 0, s, nodes,
+                       dinv, b, (T)(1.0 / theta), d, x);
+    FSI_CHECK_LAUNCH();
+  } else {
+    if (prof) prof->begin(s);
+    stencil_launch<T, SP_CHEB>(n, tab, x, b, d, x2, (T)0, (T)(1.0 / theta), s);
+    if (prof) prof->end(s);
+    std::swap(x, x2);
+  }
+  for (int k = 1; k < steps; ++k) {
+    double rho1 = 1.0 / (2.0 * sigma - rho);
+    if (prof) prof->begin(s);
+    stencil_launch<T, SP_CHEB>(n, tab, x, b, d, x2, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), s);
+    if (prof) prof->end(s);
+    std::swap(x, x2);
+    rho = rho1;
+  }
+  return x;
+}
+
+template <typename T> static const StencilTable<T> *stab(const MgLevel &L);
+template <> const StencilTable<double> *stab<double>(const MgLevel &L) {
+  return (const StencilTable<double> *)L.stab64.p;
+}
+template <> const StencilTable<float> *stab<float>(const MgLevel &L) {
+  return (const StencilTable<float> *)L.stab32.p;
+}
+
 // ---------------------------------------------------------------- V-cycle
 // One V-cycle at level l for right-hand side b (comps * nodes entries, component-major).
 // Returns the level work vector that holds the result.
@@ -204,10 +242,16 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr)
   const T *dinv = Pr<T>::dinv(L);
   const T *val = Pr<T>::val(L.A);
   Prof *pl = (l == 0) ? prof : nullptr;
-  T *xs = chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, mg.degree,
-                              b, x, x2, d, true, s, pl);
+  const bool mf = (W == 4) && mg.stencil;   // matrix-free A_f products
+  T *xs = mf ? chebyshev_stencil<T>(L.n, stab<T>(L), L.nodes, dinv, lmin, lmax, mg.degree, b, x, x2, d,
+                                    true, s, pl)
+             : chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax,
+                                   mg.degree, b, x, x2, d, true, s, pl);
   T *xo = (xs == x) ? x2 : x;
-  spmv<T, W, NC, SP_RESID>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, xs, L.nodes, r, L.nodes, s, b);
+  if (mf)
+    stencil_launch<T, SP_RESID>(L.n, stab<T>(L), xs, b, nullptr, r, (T)0, (T)0, s);
+  else
+    spmv<T, W, NC, SP_RESID>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, xs, L.nodes, r, L.nodes, s, b);
   MgLevel &C = mg.lv[l + 1];
   T *bc = Pr<T>::w(C, 1);
   spmv<T, 1, NC, SP_APPLY>(L.R.nrows, L.R.rowptr.p, L.R.col.p, Pr<T>::val(L.R), r, L.nodes, bc,
@@ -215,6 +259,9 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr)
   T *xc = vcycle<T, W, NC>(mg, l + 1, bc, s);
   spmv<T, 1, NC, SP_ADD>(L.P.nrows, L.P.rowptr.p, L.P.col.p, Pr<T>::val(L.P), xc, C.nodes, xs,
                          L.nodes, s);
+  if (mf)
+    return chebyshev_stencil<T>(L.n, stab<T>(L), L.nodes, dinv, lmin, lmax, mg.degree, b, xs, xo, d,
+                                false, s, pl);
   return chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, mg.degree, b,
                              xs, xo, d, false, s, pl);
 }

@@ -19,6 +19,7 @@ FSI_OK, FSI_E_ARG, FSI_E_MESH, FSI_E_NOMEM, FSI_E_NOCONV, FSI_E_NONFINITE, FSI_E
     FSI_E_CAPACITY, FSI_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FP64, FP32, FP32_IR = 0, 1, 2
 PC_DIAG, PC_TRI = 0, 1
+SMOOTH_CSR, SMOOTH_STENCIL = 0, 1
 BLOCKS = dict(AF=0, MF=1, B=2, BT=3, AS=4, CS=5, CF=6, CFT=7, MP=8)
 
 
@@ -76,6 +77,7 @@ _SIGS = {
     "fsi_destroy": (None, [C.c_void_p]),
     "fsi_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fsi_set_solid": (C.c_int, [C.c_void_p, C.POINTER(SolidDesc)]),
+    "fsi_set_smoother": (C.c_int, [C.c_void_p, C.c_int]),
     "fsi_footprint": (C.c_int, [C.POINTER(FluidDesc), C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "fsi_sizes": (C.c_int, [C.c_void_p, C.POINTER(Sizes)]),
     "fsi_assemble_coupling": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(CouplingInfo)]),
@@ -236,6 +238,9 @@ class Context:
 
     def apply_precond(self, r, z, pc=PC_TRI, prec=FP64):
         self._check(lib().fsi_apply_precond(self._h, int(pc), int(prec), _ptr(r), _ptr(z)))
+
+    def set_smoother(self, kind):
+        self._check(lib().fsi_set_smoother(self._h, int(kind)))
 
     def set_inner(self, rtol, maxit=0):
         self._check(lib().fsi_set_inner(self._h, float(rtol), int(maxit)))

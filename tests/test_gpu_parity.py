@@ -345,3 +345,32 @@ def test_gmres_fp32_ir(pair32):
     print(f"  fp32-ir its {st['its']} refinements {st['refinements']} relres {st['relres_true']:.2e}", flush=True)
     assert st["converged"] and st["refinements"] >= 1 and rel(A @ x, b) <= 1e-8 * 1.0001
     assert rel(x, xs) <= 1e-7
+
+
+@pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
+def test_stencil_smoother_equals_csr(pair32, prec):
+    """The matrix-free A_f products of the V-cycle give the same preconditioner as the
+    assembled blocks: after one or two inner steps (isolating the V-cycle) and converged."""
+    print(f"[stencil vs csr prec={prec}]", flush=True)
+    S, ctx, wl = pair32
+    lay = S.lay
+    rng = np.random.default_rng(31)
+    r = S.random_rhs(0, rng.uniform(-1, 1, lay.N))
+    torch = torch_dev()
+    rd = to_dev(r)
+    out = {}
+    for maxit, tol in ((1, 1e-30), (2, 1e-30), (2000, 1e-12)):
+        for kind in (fsi.SMOOTH_CSR, fsi.SMOOTH_STENCIL):
+            ctx.set_smoother(kind)
+            ctx.set_inner(tol, maxit)
+            zd = torch.zeros_like(rd)
+            ctx.apply_precond(rd, zd, fsi.PC_TRI, prec)
+            out[(maxit, kind)] = to_host(zd)
+        d = rel(out[(maxit, fsi.SMOOTH_STENCIL)], out[(maxit, fsi.SMOOTH_CSR)])
+        print(f"  maxit {maxit}: rel diff {d:.2e}", flush=True)
+        assert d <= (1e-12 if prec == fsi.FP64 else 1e-5)
+    ctx.set_smoother(fsi.SMOOTH_STENCIL)
+    ctx.set_inner(-1.0, 1000)
+    if prec == fsi.FP64:
+        zref = S.apply_precond(r, "tri")
+        assert rel(out[(2000, fsi.SMOOTH_STENCIL)], zref) <= 1e-9
