@@ -26,6 +26,8 @@ Test infrastructure (FP64 oracle); see ``oracle/__init__.py``.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 import scipy.sparse as sp
 
@@ -44,8 +46,9 @@ def p1_index(n, i, j):
     return j * (n + 1) + i
 
 
+@functools.lru_cache(maxsize=2)
 def triangle_nodes(n):
-    """Local-to-global maps.
+    """Local-to-global maps (cached; callers must not modify the arrays).
 
     Returns ``(p2, p1, verts)``: int arrays [2 n^2, 6] (P2 nodes), [2 n^2, 3] (P1 nodes)
     and float [2 n^2, 3, 2] (vertex coordinates), in global triangle order.
@@ -233,3 +236,105 @@ def zero_row(A, r):
     A = A.tocsr().copy()
     A.data[A.indptr[r]:A.indptr[r + 1]] = 0.0
     return A
+
+
+def _adjacent(n, I, J):
+    """Triangles (global id, local P2 index of node (I, J)) containing P2 node (I, J)."""
+    out = []
+    for cj in range(max(0, (J - 1) // 2), min(n - 1, J // 2) + 1):
+        for ci in range(max(0, (I - 1) // 2), min(n - 1, I // 2) + 1):
+            for t in (0, 1):
+                V = [(ci, cj), (ci + 1, cj), (ci + 1, cj + 1)] if t == 0 else \
+                    [(ci, cj), (ci + 1, cj + 1), (ci, cj + 1)]
+                P = [(2 * a, 2 * b) for (a, b) in V]
+                M = [((P[0][0] + P[1][0]) // 2, (P[0][1] + P[1][1]) // 2),
+                     ((P[1][0] + P[2][0]) // 2, (P[1][1] + P[2][1]) // 2),
+                     ((P[2][0] + P[0][0]) // 2, (P[2][1] + P[0][1]) // 2)]
+                nodes = P + M
+                if (I, J) in nodes:
+                    out.append((2 * (cj * n + ci) + t, nodes.index((I, J)), nodes, V))
+    return out
+
+
+def rows_Af(n, nodes, nu=1.0, rho=1.0, dt=0.01):
+    """Rows of A_f (with the boundary condition) at the given P2 nodes, by summing the
+    element matrices of the triangles around each node: {node: {col: (xx, xy, yx, yy)}}.
+    Also the rows of M_f (no boundary condition): {node: {col: m}}.  For spot checks of
+    grids too large to assemble whole."""
+    h = 1.0 / n
+    el = [element_matrices(np.array([(0, 0), (h, 0), (h, h)]), nu),
+          element_matrices(np.array([(0, 0), (h, h), (0, h)]), nu)]
+    L = 2 * n + 1
+    bnd = lambda I, J: I == 0 or J == 0 or I == 2 * n or J == 2 * n
+    A, Mrows = {}, {}
+    for r in nodes:
+        I, J = r % L, r // L
+        row, mrow = {}, {}
+        for (T, a, P2, _) in _adjacent(n, I, J):
+            e = el[T & 1]
+            for b, (I2, J2) in enumerate(P2):
+                c = J2 * L + I2
+                v = row.setdefault(c, [0.0, 0.0, 0.0, 0.0])
+                v[0] += e["K"][0, 0][a, b]
+                v[1] += e["K"][0, 1][a, b]
+                v[2] += e["K"][1, 0][a, b]
+                v[3] += e["K"][1, 1][a, b]
+                mrow[c] = mrow.get(c, 0.0) + e["M"][a, b]
+        for c in row:
+            if bnd(I, J) or bnd(c % L, c // L):
+                row[c] = (1.0, 0.0, 0.0, 1.0) if c == r else (0.0, 0.0, 0.0, 0.0)
+            else:
+                v = row[c]
+                row[c] = (v[0] + (rho / dt) * mrow[c], v[1], v[2], v[3] + (rho / dt) * mrow[c])
+        A[r] = dict(sorted(row.items()))
+        Mrows[r] = dict(sorted(mrow.items()))
+    return A, Mrows
+
+
+def rows_B(n, p1nodes):
+    """Rows of B (boundary columns and row 0 zeroed) at P1 nodes: {k: {col: (bx, by)}}."""
+    h = 1.0 / n
+    el = [element_matrices(np.array([(0, 0), (h, 0), (h, h)]), 1.0),
+          element_matrices(np.array([(0, 0), (h, h), (0, h)]), 1.0)]
+    L, L1 = 2 * n + 1, n + 1
+    out = {}
+    for k in p1nodes:
+        i, j = k % L1, k // L1
+        row = {}
+        for (T, a, P2, _) in _adjacent(n, 2 * i, 2 * j):
+            e = el[T & 1]
+            for b, (I2, J2) in enumerate(P2):
+                c = J2 * L + I2
+                v = row.setdefault(c, [0.0, 0.0])
+                v[0] += e["B"][0, a, b]
+                v[1] += e["B"][1, a, b]
+        for c in row:
+            I2, J2 = c % L, c // L
+            if k == 0 or I2 == 0 or J2 == 0 or I2 == 2 * n or J2 == 2 * n:
+                row[c] = (0.0, 0.0)
+            else:
+                row[c] = tuple(row[c])
+        out[k] = dict(sorted(row.items()))
+    return out
+
+
+def rows_BT(n, p2nodes):
+    """Rows of B^T (boundary rows and column 0 zeroed) at P2 nodes: {r: {p1 col: (bx, by)}}."""
+    h = 1.0 / n
+    el = [element_matrices(np.array([(0, 0), (h, 0), (h, h)]), 1.0),
+          element_matrices(np.array([(0, 0), (h, h), (0, h)]), 1.0)]
+    L, L1 = 2 * n + 1, n + 1
+    out = {}
+    for r in p2nodes:
+        I, J = r % L, r // L
+        row = {}
+        for (T, a, P2, V) in _adjacent(n, I, J):
+            e = el[T & 1]
+            for kk, (vi, vj) in enumerate(V):
+                c = vj * L1 + vi
+                v = row.setdefault(c, [0.0, 0.0])
+                v[0] += e["B"][0, kk, a]
+                v[1] += e["B"][1, kk, a]
+        rb = I == 0 or J == 0 or I == 2 * n or J == 2 * n
+        out[r] = {c: ((0.0, 0.0) if (rb or c == 0) else tuple(v)) for c, v in sorted(row.items())}
+    return out

@@ -99,7 +99,7 @@ inline void scan_excl(const int *in, int *out, int64_t n, DevBuf<int> &tmp, hipS
 }
 
 // ------------------------------------------------------------------ sparse products
-enum SpmvMode { SP_APPLY = 0, SP_RESID = 1, SP_ADD = 2, SP_CHEB = 3 };
+enum SpmvMode { SP_APPLY = 0, SP_RESID = 1, SP_ADD = 2, SP_CHEB = 3, SP_A11 = 4 };
 
 // G lanes per row.  W = 4: 2x2 blocks on NC = 2 components; W = 1: the scalar matrix
 // is applied to each of NC components.  Component c of a vector lives at v + c * stride.

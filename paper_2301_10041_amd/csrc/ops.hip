@@ -12,6 +12,7 @@
 // A11 on [u | p] (the C_f^T term and the solid rows are skipped).
 #include "ctx.h"
 #include "kernels.h"
+#include "stencil.h"
 
 namespace fsi {
 
@@ -135,7 +136,7 @@ void make_shadow(Csr &A, hipStream_t s) {
 }
 
 template <typename T, typename Tx, typename Ty>
-static void launch_operator(Ctx &c, const Tx *x, Ty *y, bool fluid_only) {
+static void launch_operator(Ctx &c, const Tx *x, Ty *y, bool fluid_only, bool pressure_only = false) {
   OpArgs<T, Tx, Ty> a{};
   a.N2 = c.N2; a.Np = c.Np; a.Ns = fluid_only ? 0 : c.Ns;
   a.inv_dt = (T)(1.0 / c.dt);
@@ -151,7 +152,7 @@ static void launch_operator(Ctx &c, const Tx *x, Ty *y, bool fluid_only) {
   a.x = x;
   a.y = y;
   a.fluid_only = fluid_only ? 1 : 0;
-  a.gU = (unsigned)((c.N2 + kRowsPerBlock - 1) / kRowsPerBlock);
+  a.gU = pressure_only ? 0u : (unsigned)((c.N2 + kRowsPerBlock - 1) / kRowsPerBlock);
   a.gP = (unsigned)((c.Np + kRowsPerBlock - 1) / kRowsPerBlock);
   unsigned gS = fluid_only ? 0u : (unsigned)((c.Ns + kRowsPerBlock - 1) / kRowsPerBlock);
   hipLaunchKernelGGL((k_operator<T, Tx, Ty>), dim3(a.gU + a.gP + gS), dim3(kOpBlock), 0, c.stream, a);
@@ -173,9 +174,20 @@ void apply_a11(Ctx &c, const T *x, T *y) {
 template void apply_a11<double>(Ctx &, const double *, double *);
 template void apply_a11<float>(Ctx &, const float *, float *);
 
-// A11 on FP64 vectors, arithmetic and matrix values in TA (FP32: values from the shadows)
+// A11 on FP64 vectors, arithmetic and matrix values in TA (FP32: values from the shadows).
+// With the structured-grid smoother enabled, the A_f part is the matrix-free stencil
+// (velocity rows: A_f x_u - B^T x_p in one tiled launch) and the pressure rows are the
+// CSR product -B x_u (+ the pin); otherwise everything reads the assembled blocks.
 template <typename TA>
 void apply_a11_on64(Ctx &c, const double *x, double *y) {
+  if constexpr (std::is_same<TA, double>::value) {
+    if (c.mgu.stencil) {
+      stencil_a11_velocity<double>(c.n, (const StencilTable<double> *)c.mgu.lv[0].stab64.p,
+                                   c.BT.rowptr.p, c.BT.col.p, c.BT.val.p, x, y, c.stream);
+      launch_operator<double, double, double>(c, x, y, true, true);
+      return;
+    }
+  }
   launch_operator<TA, double, double>(c, x, y, true);
 }
 template void apply_a11_on64<double>(Ctx &, const double *, double *);

@@ -30,6 +30,10 @@ template <typename T, int MODE>
 void stencil_launch(int n, const StencilTable<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2,
                     hipStream_t s);
 
+template <typename T>
+void stencil_a11_velocity(int n, const StencilTable<T> *tab, const int *bt_rp, const int *bt_col,
+                          const T *bt_val, const T *x, T *y, hipStream_t s);
+
 // Host: the tables of A_f on an n x n grid from the element matrices (assemble.hip).
 void stencil_tables(int n, double nu, double rdt, StencilTable<double> &t64, StencilTable<float> &t32);
 

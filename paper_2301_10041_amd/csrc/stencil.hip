@@ -22,6 +22,9 @@ struct StencilArgs {
   T *d, *y;
   int L2;                      // nodes per component (2n+1)^2
   T c1, c2;
+  // SP_A11 only: y_u = A_f x_u - B^T x_p with B^T as CSR (2 values per entry)
+  const int *bt_rp, *bt_col;
+  const T *bt_val, *xp;
 };
 
 // Tiled kernel.  A block owns kTileR lattice rows x kTileC nodes.  Phase 1 stages x with a
@@ -108,6 +111,15 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a) {
     if constexpr (MODE == SP_APPLY) {
       a.y[r] = s0;
       a.y[a.L2 + r] = s1;
+    } else if constexpr (MODE == SP_A11) {
+      T t0 = s0, t1 = s1;
+      for (int k = a.bt_rp[r]; k < a.bt_rp[r + 1]; ++k) {
+        const T pj = a.xp[a.bt_col[k]];
+        t0 -= a.bt_val[2 * k] * pj;
+        t1 -= a.bt_val[2 * k + 1] * pj;
+      }
+      a.y[r] = t0;
+      a.y[a.L2 + r] = t1;
     } else if constexpr (MODE == SP_RESID) {
       a.y[r] = a.b[r] - s0;
       a.y[a.L2 + r] = a.b[a.L2 + r] - s1;
@@ -133,12 +145,28 @@ void stencil_launch(int n, const StencilTable<T> *tab, const T *x, const T *b, T
                     hipStream_t s) {
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
   static_assert(kTileR * kWave == 256 && 2 * kWave == kTileC, "one tile row per wave, two nodes per lane");
-  StencilArgs<T> a{n, tab, x, b, d, y, (2 * n + 1) * (2 * n + 1), c1, c2};
+  StencilArgs<T> a{n, tab, x, b, d, y, (2 * n + 1) * (2 * n + 1), c1, c2, nullptr, nullptr, nullptr,
+                   nullptr};
   const int L = 2 * n + 1;
   dim3 grid((unsigned)((L + kTileC - 1) / kTileC), (unsigned)((L + kTileR - 1) / kTileR));
   hipLaunchKernelGGL((k_stencil<T, MODE>), grid, dim3(256), 0, s, a);
   FSI_CHECK_LAUNCH();
 }
+
+// y_u = A_f x_u - B^T x_p on the fluid vector [u_x | u_y | p] (velocity rows of A11)
+template <typename T>
+void stencil_a11_velocity(int n, const StencilTable<T> *tab, const int *bt_rp, const int *bt_col,
+                          const T *bt_val, const T *x, T *y, hipStream_t s) {
+  const int L = 2 * n + 1, L2 = L * L;
+  StencilArgs<T> a{n, tab, x, nullptr, nullptr, y, L2, T(0), T(0), bt_rp, bt_col, bt_val, x + 2 * (int64_t)L2};
+  dim3 grid((unsigned)((L + kTileC - 1) / kTileC), (unsigned)((L + kTileR - 1) / kTileR));
+  hipLaunchKernelGGL((k_stencil<T, SP_A11>), grid, dim3(256), 0, s, a);
+  FSI_CHECK_LAUNCH();
+}
+template void stencil_a11_velocity<double>(int, const StencilTable<double> *, const int *, const int *,
+                                           const double *, const double *, double *, hipStream_t);
+template void stencil_a11_velocity<float>(int, const StencilTable<float> *, const int *, const int *,
+                                          const float *, const float *, float *, hipStream_t);
 
 template void stencil_launch<double, SP_APPLY>(int, const StencilTable<double> *, const double *, const double *,
                                                double *, double *, double, double, hipStream_t);

@@ -231,3 +231,31 @@ def test_ring_mesh_counts_and_orientation():
         assert (d > 0).all()
         # the triangles tile the inscribed polygon: total area = sum over rings
         assert np.unique(np.sort(tri, axis=1), axis=0).shape[0] == tri.shape[0]
+
+
+@pytest.mark.parametrize("n", [3, 8])
+def test_row_assembly_equals_full_assembly(n):
+    """The oracle's row-by-row assembly (used for spot checks of grids too large to
+    assemble whole) reproduces the full assembly: same columns, same values."""
+    F = fluid.assemble(n, nu=0.7, rho=1.3, dt=0.05)
+    N2, Np = F["N2"], F["Np"]
+    A, M = fluid.rows_Af(n, range(N2), 0.7, 1.3, 0.05)
+    for k, key in enumerate([(0, 0), (0, 1), (1, 0), (1, 1)]):
+        B = F["Af_blocks"][key].tocsr()
+        for r in range(N2):
+            cols = B.indices[B.indptr[r]:B.indptr[r + 1]]
+            assert list(cols) == list(A[r])
+            assert np.allclose(B.data[B.indptr[r]:B.indptr[r + 1]], [A[r][c][k] for c in cols], rtol=0, atol=1e-13)
+    Mf = F["Mf"].tocsr()
+    for r in range(N2):
+        cols = Mf.indices[Mf.indptr[r]:Mf.indptr[r + 1]]
+        assert np.allclose(Mf.data[Mf.indptr[r]:Mf.indptr[r + 1]], [M[r][c] for c in cols], rtol=0, atol=1e-16)
+    Bx, By = F["Bx_bc"].tocsr(), F["By_bc"].tocsr()
+    for k, row in fluid.rows_B(n, range(Np)).items():
+        assert list(Bx.indices[Bx.indptr[k]:Bx.indptr[k + 1]]) == list(row)
+        for c, v in row.items():
+            assert abs(Bx[k, c] - v[0]) < 1e-15 and abs(By[k, c] - v[1]) < 1e-15
+    BxT = Bx.T.tocsr()
+    BxT.sort_indices()
+    for r, row in fluid.rows_BT(n, range(N2)).items():
+        assert list(BxT.indices[BxT.indptr[r]:BxT.indptr[r + 1]]) == list(row)
