@@ -51,12 +51,19 @@ __device__ __forceinline__ void tile_row_products(const StencilTable<T> &tb, con
   }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b to XCD b % 8); each XCD
+// gets a contiguous band of tiles in row-major order, so the halo rows a tile shares with
+// the tile below are still in that XCD's L2.
+constexpr int kXcd = 8;
+
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a) {
+__global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, int tiles, int band) {
   __shared__ T X[2][kTH * kTW];
   __shared__ T S[2][kTileR * kTileC];
+  const int t = (blockIdx.x % kXcd) * band + blockIdx.x / kXcd;
+  if (t >= tiles) return;
   const int n2 = 2 * a.n, L = n2 + 1;
-  const int I0 = blockIdx.x * kTileC, J0 = blockIdx.y * kTileR;
+  const int I0 = (t % tiles_x) * kTileC, J0 = (t / tiles_x) * kTileR;
   const int tid = threadIdx.x;
   const StencilTable<T> &tb = *a.tab;
   // phase 1: x tile with halo
@@ -141,16 +148,22 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a) {
 }
 
 template <typename T, int MODE>
+static void launch_tiles(int n, const StencilArgs<T> &a, hipStream_t s) {
+  const int L = 2 * n + 1;
+  const int tx = (L + kTileC - 1) / kTileC, ty = (L + kTileR - 1) / kTileR;
+  const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
+  hipLaunchKernelGGL((k_stencil<T, MODE>), dim3((unsigned)(band * kXcd)), dim3(256), 0, s, a, tx, tiles, band);
+  FSI_CHECK_LAUNCH();
+}
+
+template <typename T, int MODE>
 void stencil_launch(int n, const StencilTable<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2,
                     hipStream_t s) {
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
   static_assert(kTileR * kWave == 256 && 2 * kWave == kTileC, "one tile row per wave, two nodes per lane");
   StencilArgs<T> a{n, tab, x, b, d, y, (2 * n + 1) * (2 * n + 1), c1, c2, nullptr, nullptr, nullptr,
                    nullptr};
-  const int L = 2 * n + 1;
-  dim3 grid((unsigned)((L + kTileC - 1) / kTileC), (unsigned)((L + kTileR - 1) / kTileR));
-  hipLaunchKernelGGL((k_stencil<T, MODE>), grid, dim3(256), 0, s, a);
-  FSI_CHECK_LAUNCH();
+  launch_tiles<T, MODE>(n, a, s);
 }
 
 // y_u = A_f x_u - B^T x_p on the fluid vector [u_x | u_y | p] (velocity rows of A11)
@@ -159,9 +172,7 @@ void stencil_a11_velocity(int n, const StencilTable<T> *tab, const int *bt_rp, c
                           const T *bt_val, const T *x, T *y, hipStream_t s) {
   const int L = 2 * n + 1, L2 = L * L;
   StencilArgs<T> a{n, tab, x, nullptr, nullptr, y, L2, T(0), T(0), bt_rp, bt_col, bt_val, x + 2 * (int64_t)L2};
-  dim3 grid((unsigned)((L + kTileC - 1) / kTileC), (unsigned)((L + kTileR - 1) / kTileR));
-  hipLaunchKernelGGL((k_stencil<T, SP_A11>), grid, dim3(256), 0, s, a);
-  FSI_CHECK_LAUNCH();
+  launch_tiles<T, SP_A11>(n, a, s);
 }
 template void stencil_a11_velocity<double>(int, const StencilTable<double> *, const int *, const int *,
                                            const double *, const double *, double *, hipStream_t);
