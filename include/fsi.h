@@ -226,6 +226,12 @@ int fsi_export_csr(fsi_ctx *ctx, int block, int64_t *nrows, int64_t *nnz, int32_
 enum fsi_smoother { FSI_SMOOTH_CSR = 0, FSI_SMOOTH_STENCIL = 1 };
 int fsi_set_smoother(fsi_ctx *ctx, int kind);
 
+/* Replay the A11 preconditioner (V-cycles, Chebyshev mass solve, pressure V-cycle: about
+ * 60 launches) as one captured HIP graph per precision.  Default: on for n <= 256, where
+ * a step is bound by launch latency.  The graph holds kernel nodes only; results are the
+ * same as without it. */
+int fsi_set_graphs(fsi_ctx *ctx, int enable);
+
 /* Measurement of the dominant kernel: the finest-level Chebyshev smoothing product on A_f
  * (2x2 blocks; d = c1 d + c2 D^{-1}(b - A_f x), y = x + d), which carries most of the
  * bytes of a step.  fsi_profile(ctx, 1) starts (and resets) timing every such launch with

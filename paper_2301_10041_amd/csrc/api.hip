@@ -13,6 +13,8 @@ struct fsi_ctx {
 namespace fsi {
 
 Ctx::~Ctx() {
+  drop_graphs();
+  if (cap_stream) hipStreamDestroy(cap_stream);
   if (hpin) hipHostFree(hpin);
 }
 
@@ -144,6 +146,7 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     fsi::build_fluid(c);
     fsi::build_multigrid(c);
     c.mgu.stencil = true;
+    c.use_graphs = c.n <= 256;   // launch-bound sizes
     fsi::make_shadow(c.Af, c.stream);
     fsi::make_shadow(c.B, c.stream);
     fsi::make_shadow(c.BT, c.stream);
@@ -196,7 +199,17 @@ int fsi_set_solid(fsi_ctx *ctx, const fsi_solid_desc *solid) {
 int fsi_set_smoother(fsi_ctx *ctx, int kind) {
   if (!ctx) return FSI_E_ARG;
   if (kind != FSI_SMOOTH_CSR && kind != FSI_SMOOTH_STENCIL) return FSI_E_ARG;
+  hipStreamSynchronize(ctx->c.stream);
+  ctx->c.drop_graphs();
   ctx->c.mgu.stencil = kind == FSI_SMOOTH_STENCIL;
+  return FSI_OK;
+}
+
+int fsi_set_graphs(fsi_ctx *ctx, int enable) {
+  if (!ctx) return FSI_E_ARG;
+  hipStreamSynchronize(ctx->c.stream);
+  ctx->c.drop_graphs();
+  ctx->c.use_graphs = enable != 0;
   return FSI_OK;
 }
 

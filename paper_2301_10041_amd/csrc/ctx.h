@@ -124,6 +124,14 @@ struct Ctx {
 
   Prof prof64, prof32;        // finest-level Chebyshev product on A_f
 
+  // HIP graphs of the A11 preconditioner (one per precision), replayed on fixed staging
+  // buffers; captured on first use, dropped when the smoother changes
+  bool use_graphs = false;
+  hipGraphExec_t pc_graph[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;   // capture only (default priority)
+  DevBuf<double> pc_in, pc_out;
+  void drop_graphs();
+
   double inner_rtol = -1.0;   // < 0: default per precision
   int inner_maxit = 1000;
   int64_t inner_its_total = 0;

@@ -282,10 +282,10 @@ static void a11_precond(Ctx &c, const T *r, T *z) {
   const int64_t N2 = c.N2, Np = c.Np;
   Prof *pf = std::is_same<T, double>::value ? &c.prof64 : &c.prof32;
   T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr);
-  FSI_HIP(hipMemcpyAsync(z, xu, 2 * N2 * sizeof(T), hipMemcpyDeviceToDevice, s));
+  convert(z, xu, 2 * N2, s);
   // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
   T *rp = Pr<T>::inner(c, 8).p;
-  FSI_HIP(hipMemcpyAsync(rp, r + 2 * N2, Np * sizeof(T), hipMemcpyDeviceToDevice, s));
+  convert(rp, r + 2 * N2, Np, s);
   fill(rp, 1, (T)0, s);
   T *xp = vcycle<T, 1, 1>(c.mgp, 0, rp, s);
   T *mx = Pr<T>::inner(c, 7).p, *mx2 = mx + Np, *md = mx + 2 * Np;
@@ -310,6 +310,59 @@ static void a11_precond_on64(Ctx &c, const double *r, double *z) {
   }
 }
 
+// The preconditioner through a HIP graph: captured once per precision on the staging
+// buffers (a fixed sequence of kernels with fixed arguments), then replayed.  Only kernel
+// nodes are captured (copies are kernels too).
+template <typename TA>
+static void a11_precond_graph(Ctx &c, const double *r, double *z) {
+  hipStream_t s = c.stream;
+  const int64_t nf = 2 * c.N2 + c.Np;
+  const int k = std::is_same<TA, double>::value ? 0 : 1;
+  if (!c.pc_in.p) {
+    c.pc_in.alloc(nf);
+    c.pc_out.alloc(nf);
+  }
+  convert(c.pc_in.p, r, nf, s);
+  if (!c.pc_graph[k]) {
+    // capture on the context's own stream (the NULL stream cannot be captured); the
+    // capture only records, the replay below runs on the caller's stream
+    if (!c.cap_stream) FSI_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    FSI_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
+    c.stream = c.cap_stream;
+    try {
+      a11_precond_on64<TA>(c, c.pc_in.p, c.pc_out.p);
+    } catch (...) {
+      c.stream = s;
+      hipStreamEndCapture(c.cap_stream, &g);
+      if (g) hipGraphDestroy(g);
+      throw;
+    }
+    c.stream = s;
+    FSI_HIP(hipStreamEndCapture(c.cap_stream, &g));
+    hipError_t e = hipGraphInstantiate(&c.pc_graph[k], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    FSI_HIP(e);
+  }
+  FSI_HIP(hipGraphLaunch(c.pc_graph[k], s));
+  convert(z, c.pc_out.p, nf, s);
+}
+
+template <typename TA>
+static void a11_precond_any(Ctx &c, const double *r, double *z) {
+  const bool profiling = c.prof64.on || c.prof32.on;
+  if (c.use_graphs && !profiling) a11_precond_graph<TA>(c, r, z);
+  else a11_precond_on64<TA>(c, r, z);
+}
+
+void Ctx::drop_graphs() {
+  for (auto &g : pc_graph)
+    if (g) {
+      hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
 // Preconditioned MINRES (Paige-Saunders recurrences) for A11 x = b from x = 0; stops when
 // the preconditioned residual estimate falls below tol times its initial value.  The
 // Lanczos vectors, dot products, updates and the A11 product are FP64 in every mode; TA is
@@ -329,7 +382,7 @@ static int minres_a11(Ctx &c, const double *b, double *x, double tol, int maxit)
   fill(w, nf, 0.0, s);
   fill(w2, nf, 0.0, s);
   FSI_HIP(hipMemcpyAsync(r1, b, nf * sizeof(double), hipMemcpyDeviceToDevice, s));
-  a11_precond_on64<TA>(c, r1, y);
+  a11_precond_any<TA>(c, r1, y);
   multidot(r1, 0, 1, y, nf, dv + 1, c.red, s);
   FSI_HIP(hipMemcpyAsync(c.hpin, dv, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   FSI_HIP(hipStreamSynchronize(s));
@@ -349,7 +402,7 @@ static int minres_a11(Ctx &c, const double *b, double *x, double tol, int maxit)
     FSI_CHECK_LAUNCH();
     std::swap(r1, r2);   // r1 <- previous r2
     std::swap(r2, y);    // r2 <- new Lanczos vector
-    a11_precond_on64<TA>(c, r2, y);
+    a11_precond_any<TA>(c, r2, y);
     multidot(r2, 0, 1, y, nf, dv + 1, c.red, s);
     FSI_HIP(hipMemcpyAsync(c.hpin, dv, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     FSI_HIP(hipStreamSynchronize(s));

@@ -78,6 +78,7 @@ _SIGS = {
     "fsi_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fsi_set_solid": (C.c_int, [C.c_void_p, C.POINTER(SolidDesc)]),
     "fsi_set_smoother": (C.c_int, [C.c_void_p, C.c_int]),
+    "fsi_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "fsi_footprint": (C.c_int, [C.POINTER(FluidDesc), C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "fsi_sizes": (C.c_int, [C.c_void_p, C.POINTER(Sizes)]),
     "fsi_assemble_coupling": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(CouplingInfo)]),
@@ -241,6 +242,9 @@ class Context:
 
     def set_smoother(self, kind):
         self._check(lib().fsi_set_smoother(self._h, int(kind)))
+
+    def set_graphs(self, enable=True):
+        self._check(lib().fsi_set_graphs(self._h, 1 if enable else 0))
 
     def set_inner(self, rtol, maxit=0):
         self._check(lib().fsi_set_inner(self._h, float(rtol), int(maxit)))

@@ -266,8 +266,12 @@ def summarize(results, wall=None):
     first = min(r.arrival for r in results)
     last = max(r.done for r in results)
     span = last - first if wall is None else wall
+    by_n = {}
+    for n in sorted({r.n for r in results}):
+        svc = [r.done - r.start for r in results if r.n == n]
+        by_n[n] = dict(count=len(svc), service_ms=float(np.mean(svc) * 1e3))
     return dict(requests=len(results), p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
                 throughput_req_s=len(results) / span, span_s=span,
                 its_mean=float(np.mean([r.stats.get("its", 0) for r in results])),
-                converged=int(sum(1 for r in results if r.stats.get("converged"))))
+                converged=int(sum(1 for r in results if r.stats.get("converged"))), by_n=by_n)

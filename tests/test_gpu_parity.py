@@ -374,3 +374,39 @@ def test_stencil_smoother_equals_csr(pair32, prec):
     if prec == fsi.FP64:
         zref = S.apply_precond(r, "tri")
         assert rel(out[(2000, fsi.SMOOTH_STENCIL)], zref) <= 1e-9
+
+
+@pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
+def test_graph_replays_equal_eager(pair32, prec):
+    """The captured preconditioner graph, replayed many times with different inputs and
+    with eager work and synchronisations in between, gives the eager result bitwise."""
+    print(f"[graph replays prec={prec}]", flush=True)
+    S, ctx, wl = pair32
+    lay = S.lay
+    torch = torch_dev()
+    rng = np.random.default_rng(41)
+    rs = [to_dev(S.random_rhs(0, rng.uniform(-1, 1, lay.N))) for _ in range(3)]
+    eager = []
+    ctx.set_graphs(False)
+    for rd in rs:
+        zd = torch.zeros_like(rd)
+        ctx.apply_precond(rd, zd, fsi.PC_TRI, prec)
+        eager.append(to_host(zd))
+    ctx.set_graphs(True)
+    for rep in range(3):
+        for k, rd in enumerate(rs):
+            zd = torch.zeros_like(rd)
+            ctx.apply_precond(rd, zd, fsi.PC_TRI, prec)
+            torch.cuda.synchronize()
+            assert np.array_equal(to_host(zd), eager[k]), (rep, k)
+            # eager work on the same stream between replays
+            y = torch.zeros_like(rd)
+            ctx.apply_operator(rd, y)
+    b = to_dev(S.random_rhs(wl.seed))
+    x1 = torch.zeros_like(b)
+    ctx.gmres_solve(b, x1, fsi.Opts(pc=fsi.PC_TRI, prec=prec))
+    ctx.set_graphs(False)
+    x0 = torch.zeros_like(b)
+    ctx.gmres_solve(b, x0, fsi.Opts(pc=fsi.PC_TRI, prec=prec))
+    assert np.array_equal(to_host(x0), to_host(x1))
+    ctx.set_graphs(True)
