@@ -129,6 +129,10 @@ struct Ctx {
   bool use_graphs = false;
   hipGraphExec_t pc_graph[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;   // capture only (default priority)
+  // inner MINRES: device-side scalar state, its own reduction buffer and solution vector
+  // (allocated once: captured graphs hold these pointers), graphs per precision and phase
+  DevBuf<double> ms_state, ms_red, ms_x;
+  hipGraphExec_t ms_graph[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   DevBuf<double> pc_in, pc_out;
   void drop_graphs();
 

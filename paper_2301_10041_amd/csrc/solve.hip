@@ -361,6 +361,12 @@ void Ctx::drop_graphs() {
       hipGraphExecDestroy(g);
       g = nullptr;
     }
+  for (auto &row : ms_graph)
+    for (auto &g : row)
+      if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
+      }
 }
 
 // Preconditioned MINRES (Paige-Saunders recurrences) for A11 x = b from x = 0; stops when
@@ -370,73 +376,210 @@ void Ctx::drop_graphs() {
 // An FP32 product of A_f on a smooth vector loses about kappa * eps_32 (0.06 at 1024^2
 // cells) to cancellation, which stalls the recurrence; inside the V-cycle the residuals
 // are not smooth-dominated and FP32 arithmetic costs the preconditioner nothing.
+//
+// The scalar recurrence runs on the device (one thread), so an iteration is a fixed
+// sequence of kernels: on small grids it is replayed as a captured graph (three graphs,
+// one per rotation of the Lanczos and direction buffers) and the host looks at the
+// convergence flag every few iterations.  Once converged, a flag freezes x, so the result
+// does not depend on how often the host checks.
+struct MinresState {
+  double alfa, beta2;                         // dot products of the iteration
+  double beta, oldb, dbar, epsln, phibar, cs, sn, beta1, tol;
+  double s, c_r1;                             // 1 / beta, -beta / oldb
+  double e, d, ginv, phi;                     // direction update
+  double it, done, apply;                     // iterations; converged; update valid
+};
+constexpr int kMsDoubles = sizeof(MinresState) / sizeof(double);
+
+__global__ void k_ms_init(MinresState *st, double tol) {
+  if (threadIdx.x || blockIdx.x) return;
+  double b2 = st->beta2;
+  double b = (b2 > 0.0 && b2 == b2) ? sqrt(b2) : 0.0;
+  st->beta = st->beta1 = st->phibar = b;
+  st->oldb = st->dbar = st->epsln = st->sn = 0.0;
+  st->cs = -1.0;
+  st->tol = tol;
+  st->s = b > 0.0 ? 1.0 / b : 0.0;
+  st->c_r1 = 0.0;
+  st->it = 0.0;
+  st->done = b > 0.0 ? 0.0 : 1.0;
+  st->apply = 0.0;
+}
+
+// After the two dot products of an iteration: Givens rotation and the next coefficients.
+__global__ void k_ms_step(MinresState *st) {
+  if (threadIdx.x || blockIdx.x) return;
+  if (st->done != 0.0) {
+    st->apply = 0.0;
+    return;
+  }
+  const double alfa = st->alfa, nb2 = st->beta2;
+  const double oldb = st->beta;
+  const double beta = sqrt(nb2 > 0.0 ? nb2 : 0.0);
+  const double oldeps = st->epsln;
+  const double delta = st->cs * st->dbar + st->sn * alfa;
+  const double gbar = st->sn * st->dbar - st->cs * alfa;
+  st->epsln = st->sn * beta;
+  st->dbar = -st->cs * beta;
+  double gamma = sqrt(gbar * gbar + beta * beta);
+  if (gamma < 1e-300) gamma = 1e-300;
+  st->cs = gbar / gamma;
+  st->sn = beta / gamma;
+  st->phi = st->cs * st->phibar;
+  st->phibar = st->sn * st->phibar;
+  st->e = oldeps;
+  st->d = delta;
+  st->ginv = 1.0 / gamma;
+  st->apply = 1.0;
+  st->it += 1.0;
+  st->oldb = oldb;
+  st->beta = beta;
+  st->s = beta > 0.0 ? 1.0 / beta : 0.0;
+  st->c_r1 = beta > 0.0 ? -beta / oldb : 0.0;
+  if (!(st->phibar > st->tol * st->beta1) || beta == 0.0 || !(alfa == alfa)) st->done = 1.0;
+}
+
+// v = s y
+__global__ void k_ms_scale(double *v, const double *y, const MinresState *st, int64_t n) {
+  const double a = st->s;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = a * y[i];
+}
+
+// y += c_r1 r1 - (alfa s) r2   (the second term after alfa is known: two launches)
+__global__ void k_ms_axpy(double *y, const double *r, const MinresState *st, int which, int64_t n) {
+  const double a = which == 0 ? st->c_r1 : -st->alfa * st->s;
+  if (a == 0.0) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * r[i];
+}
+
+// wn = (v - e w1 - d w2) ginv;  x += phi wn   (skipped once converged)
+__global__ void k_ms_update(double *wn, const double *v, const double *w1, const double *w2, double *x,
+                            const MinresState *st, int64_t n) {
+  if (st->apply == 0.0) return;
+  const double e = st->e, d = st->d, g = st->ginv, phi = st->phi;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double w = (v[i] - e * w1[i] - d * w2[i]) * g;
+    wn[i] = w;
+    x[i] += phi * w;
+  }
+}
+
+// Buffers of one rotation phase (0, 1, 2).  Lanczos: r1 (old), r2 (current), y (new);
+// directions: w1 (two back, overwritten by the new one), w2, w.
+struct MsBufs {
+  double *v, *r1, *r2, *y, *w1, *w2, *w, *x;
+};
+
+static MsBufs ms_bufs(Ctx &c, double *x, int phase) {
+  double *B[3] = {c.inner.v64[2].p, c.inner.v64[3].p, c.inner.v64[1].p};   // r1, r2, y at phase 0
+  double *W[3] = {c.inner.v64[5].p, c.inner.v64[6].p, c.inner.v64[4].p};   // w1, w2, w at phase 0
+  MsBufs b;
+  b.v = c.inner.v64[0].p;
+  b.r1 = B[phase % 3];
+  b.r2 = B[(phase + 1) % 3];
+  b.y = B[(phase + 2) % 3];
+  b.w1 = W[phase % 3];
+  b.w2 = W[(phase + 1) % 3];
+  b.w = W[(phase + 2) % 3];
+  b.x = x;
+  return b;
+}
+
 template <typename TA>
-static int minres_a11(Ctx &c, const double *b, double *x, double tol, int maxit) {
+static void ms_iteration(Ctx &c, const MsBufs &b, MinresState *st) {
   hipStream_t s = c.stream;
   const int64_t nf = 2 * c.N2 + c.Np;
-  double *v = c.inner.v64[0].p, *y = c.inner.v64[1].p, *r1 = c.inner.v64[2].p,
-         *r2 = c.inner.v64[3].p, *w = c.inner.v64[4].p, *w1 = c.inner.v64[5].p,
-         *w2 = c.inner.v64[6].p;
-  double *dv = c.dscal.p;   // [0] alfa, [1] beta^2
+  const unsigned g = vgrid(nf);
+  double *dv = (double *)st;   // alfa at 0, beta2 at 1
+  hipLaunchKernelGGL(k_ms_scale, dim3(g), dim3(256), 0, s, b.v, b.y, st, nf);
+  apply_a11_on64<double>(c, b.v, b.y);
+  hipLaunchKernelGGL(k_ms_axpy, dim3(g), dim3(256), 0, s, b.y, b.r1, st, 0, nf);
+  multidot(b.v, 0, 1, b.y, nf, dv, c.ms_red, s);
+  hipLaunchKernelGGL(k_ms_axpy, dim3(g), dim3(256), 0, s, b.y, b.r2, st, 1, nf);
+  // new Lanczos vector is b.y: precondition it into the buffer of r1 (no longer needed)
+  a11_precond_on64<TA>(c, b.y, b.r1);
+  multidot(b.y, 0, 1, b.r1, nf, dv + 1, c.ms_red, s);
+  hipLaunchKernelGGL(k_ms_step, dim3(1), dim3(1), 0, s, st);
+  hipLaunchKernelGGL(k_ms_update, dim3(g), dim3(256), 0, s, b.w1, b.v, b.w2, b.w, b.x, st, nf);
+  FSI_CHECK_LAUNCH();
+}
+
+template <typename TA>
+static int minres_a11(Ctx &c, const double *b, double *xout, double tol, int maxit) {
+  hipStream_t s = c.stream;
+  const int64_t nf = 2 * c.N2 + c.Np;
+  MinresState *st = (MinresState *)c.ms_state.p;
+  double *dv = (double *)st;
+  double *x = c.ms_x.p;
+  MsBufs b0 = ms_bufs(c, x, 0);
   fill(x, nf, 0.0, s);
-  fill(w, nf, 0.0, s);
-  fill(w2, nf, 0.0, s);
-  FSI_HIP(hipMemcpyAsync(r1, b, nf * sizeof(double), hipMemcpyDeviceToDevice, s));
-  a11_precond_any<TA>(c, r1, y);
-  multidot(r1, 0, 1, y, nf, dv + 1, c.red, s);
-  FSI_HIP(hipMemcpyAsync(c.hpin, dv, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  FSI_HIP(hipStreamSynchronize(s));
-  double b2 = c.hpin[1];
-  FSI_REQUIRE(std::isfinite(b2), FSI_E_NONFINITE, "non-finite residual in the inner A11 solve");
-  if (b2 <= 0.0) return 0;
-  FSI_HIP(hipMemcpyAsync(r2, r1, nf * sizeof(double), hipMemcpyDeviceToDevice, s));
-  double beta1 = std::sqrt(b2), beta = beta1, oldb = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta1;
-  double cs = -1.0, sn = 0.0;
-  int it;
-  for (it = 1; it <= maxit; ++it) {
-    lincomb(v, y, y, 1.0 / beta, 0.0, nf, s);
-    apply_a11_on64<double>(c, v, y);
-    if (it >= 2) axpby(y, r1, -beta / oldb, 1.0, nf, s);
-    multidot(v, 0, 1, y, nf, dv, c.red, s);
-    hipLaunchKernelGGL(k_sub_dev<double>, dim3(vgrid(nf)), dim3(256), 0, s, y, r2, dv, 1.0 / beta, nf);
-    FSI_CHECK_LAUNCH();
-    std::swap(r1, r2);   // r1 <- previous r2
-    std::swap(r2, y);    // r2 <- new Lanczos vector
-    a11_precond_any<TA>(c, r2, y);
-    multidot(r2, 0, 1, y, nf, dv + 1, c.red, s);
-    FSI_HIP(hipMemcpyAsync(c.hpin, dv, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    FSI_HIP(hipStreamSynchronize(s));
-    double alfa = c.hpin[0], nb2 = c.hpin[1];
-    FSI_REQUIRE(std::isfinite(alfa) && std::isfinite(nb2), FSI_E_NONFINITE,
-                "non-finite value in the inner A11 solve");
-    oldb = beta;
-    beta = std::sqrt(nb2 > 0.0 ? nb2 : 0.0);
-    double oldeps = epsln;
-    double delta = cs * dbar + sn * alfa;
-    double gbar = sn * dbar - cs * alfa;
-    epsln = sn * beta;
-    dbar = -cs * beta;
-    double gamma = std::sqrt(gbar * gbar + beta * beta);
-    if (gamma < 1e-300) gamma = 1e-300;
-    cs = gbar / gamma;
-    sn = beta / gamma;
-    double phi = cs * phibar;
-    phibar = sn * phibar;
-    // new direction from the previous two (w2 and w); w1's buffer is free
-    double *wn = w1;
-    hipLaunchKernelGGL(k_minres_update<double>, dim3(vgrid(nf)), dim3(256), 0, s, wn, v, w2, w, x,
-                       oldeps, delta, 1.0 / gamma, phi, nf);
-    FSI_CHECK_LAUNCH();
-    w1 = w2;
-    w2 = w;
-    w = wn;
-    if (phibar <= tol * beta1 || beta == 0.0) break;
+  fill(b0.w, nf, 0.0, s);
+  fill(b0.w2, nf, 0.0, s);
+  // phase 0 expects: r2 = current Lanczos vector, y = M r2
+  convert(b0.r2, b, nf, s);
+  a11_precond_any<TA>(c, b0.r2, b0.y);
+  multidot(b0.r2, 0, 1, b0.y, nf, dv + 1, c.ms_red, s);
+  hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(1), 0, s, st, tol);
+  FSI_CHECK_LAUNCH();
+  const bool graphs = c.use_graphs && !(c.prof64.on || c.prof32.on);
+  const int check_every = graphs ? 8 : 1;
+  const int k = std::is_same<TA, double>::value ? 0 : 1;
+  int it = 0;
+  double *h = c.hpin;
+  while (it < maxit) {
+    const int phase = it % 3;
+    // the rotation: in phase p the roles are shifted by p (r2 of phase p is y of p-1, ...)
+    const MsBufs bq = ms_bufs(c, x, phase);
+    if (graphs) {
+      hipGraphExec_t &ge = c.ms_graph[k][phase];
+      if (!ge) {
+        if (!c.cap_stream) FSI_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        FSI_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
+        c.stream = c.cap_stream;
+        try {
+          ms_iteration<TA>(c, bq, st);
+        } catch (...) {
+          c.stream = s;
+          hipStreamEndCapture(c.cap_stream, &g);
+          if (g) hipGraphDestroy(g);
+          throw;
+        }
+        c.stream = s;
+        FSI_HIP(hipStreamEndCapture(c.cap_stream, &g));
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        FSI_HIP(e);
+      }
+      FSI_HIP(hipGraphLaunch(ge, s));
+    } else {
+      ms_iteration<TA>(c, bq, st);
+    }
+    ++it;
+    if (it % check_every == 0 || it == maxit) {
+      FSI_HIP(hipMemcpyAsync(h, st, kMsDoubles * sizeof(double), hipMemcpyDeviceToHost, s));
+      FSI_HIP(hipStreamSynchronize(s));
+      const MinresState *hs = (const MinresState *)h;
+      FSI_REQUIRE(hs->phibar == hs->phibar && hs->beta == hs->beta, FSI_E_NONFINITE,
+                  "non-finite value in the inner A11 solve");
+      if (hs->done != 0.0) break;
+    }
   }
+  FSI_HIP(hipMemcpyAsync(h, st, kMsDoubles * sizeof(double), hipMemcpyDeviceToHost, s));
+  FSI_HIP(hipStreamSynchronize(s));
+  const MinresState *hs = (const MinresState *)h;
+  const int its = (int)hs->it;
+  convert(xout, x, nf, s);
   if (trace_on())
-    std::fprintf(stderr, "[fsi] minres<%s> its=%d relres_est=%.3e beta=%.3e\n",
-                 std::is_same<TA, double>::value ? "f64" : "f32", it > maxit ? maxit : it,
-                 phibar / beta1, beta);
-  return it > maxit ? maxit : it;
+    std::fprintf(stderr, "[fsi] minres<%s> its=%d relres_est=%.3e beta=%.3e graphs=%d\n",
+                 std::is_same<TA, double>::value ? "f64" : "f32", its,
+                 hs->beta1 > 0 ? hs->phibar / hs->beta1 : 0.0, hs->beta, graphs ? 1 : 0);
+  return its;
 }
 
 // ---------------------------------------------------------------- A22 closed form (FP64)
@@ -468,6 +611,11 @@ static void ensure_inner(Ctx &c, int prec) {
   const int64_t nf = 2 * c.N2 + c.Np;
   for (int i = 0; i < 9; ++i)
     if (!c.inner.v64[i].p) c.inner.v64[i].alloc(nf);
+  if (!c.ms_x.p) {
+    c.ms_x.alloc(nf);
+    c.ms_state.alloc(kMsDoubles);
+    c.ms_red.alloc(red_blocks(nf));   // multidot with k = 1: never regrown
+  }
   if (prec == FSI_FP32) {
     ensure_fp32_mg(c);
     for (int i = 7; i < 9; ++i)       // pressure scratch of the FP32 preconditioner
