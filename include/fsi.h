@@ -218,11 +218,14 @@ int fsi_export_pairs(fsi_ctx *ctx, int32_t *E, int32_t *T, int64_t cap, int64_t 
 int fsi_export_csr(fsi_ctx *ctx, int block, int64_t *nrows, int64_t *nnz, int32_t *width,
                    int32_t *rowptr, int32_t *col, double *val);
 
-/* Products with A_f inside the multigrid V-cycle: FSI_SMOOTH_STENCIL (default) applies
- * A_f matrix-free from four translation-invariant 2x2-block stencils of the structured
- * grid (same element matrices as the assembled A_f; boundary rows identity, boundary
- * columns zero); FSI_SMOOTH_CSR reads the assembled blocks.  Both give the same V-cycle up
- * to the order of the sums. */
+/* Products inside the A11 preconditioner (both multigrid hierarchies and the pressure
+ * mass solve): FSI_SMOOTH_STENCIL (default) applies them matrix-free on the structured
+ * grid: A_f from four translation-invariant 2x2-block stencils (boundary rows identity,
+ * boundary columns zero), L_p and M_p from 7-point stencils in nine position classes
+ * (L_p: pinned node identity row, zero column), and the P2 / P1 prolongations and
+ * restrictions from the nested refinement, all with the same element matrices and
+ * interpolation weights as the assembled operators.  FSI_SMOOTH_CSR reads the assembled
+ * matrices.  Both give the same preconditioner up to the order of the sums. */
 enum fsi_smoother { FSI_SMOOTH_CSR = 0, FSI_SMOOTH_STENCIL = 1 };
 int fsi_set_smoother(fsi_ctx *ctx, int kind);
 

@@ -145,7 +145,7 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     fsi::build_solid(c);
     fsi::build_fluid(c);
     fsi::build_multigrid(c);
-    c.mgu.stencil = true;
+    c.mgu.stencil = c.mgp.stencil = true;
     c.use_graphs = c.n <= 256;   // launch-bound sizes
     fsi::make_shadow(c.Af, c.stream);
     fsi::make_shadow(c.B, c.stream);
@@ -201,7 +201,7 @@ int fsi_set_smoother(fsi_ctx *ctx, int kind) {
   if (kind != FSI_SMOOTH_CSR && kind != FSI_SMOOTH_STENCIL) return FSI_E_ARG;
   hipStreamSynchronize(ctx->c.stream);
   ctx->c.drop_graphs();
-  ctx->c.mgu.stencil = kind == FSI_SMOOTH_STENCIL;
+  ctx->c.mgu.stencil = ctx->c.mgp.stencil = kind == FSI_SMOOTH_STENCIL;
   return FSI_OK;
 }
 

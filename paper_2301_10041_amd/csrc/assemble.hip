@@ -13,9 +13,17 @@
 
 #include "ctx.h"
 #include "kernels.h"
+#include "lattice.h"
 #include "stencil.h"
 
 namespace fsi {
+
+// Copy of a host table into a device buffer (synchronous: the host object is a local).
+static void upload_bytes(DevBuf<unsigned char> &dst, const void *src, size_t bytes, hipStream_t s) {
+  dst.alloc(bytes);
+  FSI_HIP(hipMemcpyAsync(dst.p, src, bytes, hipMemcpyHostToDevice, s));
+  FSI_HIP(hipStreamSynchronize(s));
+}
 
 // ---------------------------------------------------------------- element matrices
 // Degree-4 six-point rule on a triangle (Dunavant, 1985): positive weights, exact for
@@ -157,6 +165,42 @@ void stencil_tables(int n, double nu, double rdt, StencilTable<double> &t64, Ste
     t64.count[cls] = t32.count[cls] = cnt;
     FSI_REQUIRE(cnt == kStencilCount[cls], FSI_E_ARG, "unexpected stencil width");
   }
+}
+
+// Host: rows of a P1 x P1 matrix (EM_MP: mass, EM_LP: Laplacian) at one node of each of
+// the nine position classes of an n x n grid, summed over the triangles around the node.
+void p1_tables(int n, int which, int pin, P1Table<double> &t64, P1Table<float> &t32) {
+  FSI_REQUIRE(n >= 2, FSI_E_ARG, "P1 tables need n >= 2");
+  std::vector<double> E;
+  element_tables(n, 1.0, E);
+  std::memset(&t64, 0, sizeof(t64));
+  std::memset(&t32, 0, sizeof(t32));
+  static const int nb[kP1Nbr][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {1, 1}};
+  const int rep[3] = {0, 1, n};
+  for (int cls = 0; cls < 9; ++cls) {
+    const int i = rep[cls % 3], j = rep[cls / 3];
+    for (int k = 0; k < kP1Nbr; ++k) {
+      const int i2 = i + nb[k][0], j2 = j + nb[k][1];
+      double v = 0.0;
+      for (int cj = std::max(0, j - 1); cj <= std::min(n - 1, j); ++cj)
+        for (int ci = std::max(0, i - 1); ci <= std::min(n - 1, i); ++ci)
+          for (int t = 0; t < 2; ++t) {
+            int a = -1, b = -1;
+            for (int q = 0; q < 3; ++q) {
+              if (2 * ci + hOff[t][q][0] == 2 * i && 2 * cj + hOff[t][q][1] == 2 * j) a = q;
+              if (2 * ci + hOff[t][q][0] == 2 * i2 && 2 * cj + hOff[t][q][1] == 2 * j2) b = q;
+            }
+            if (a >= 0 && b >= 0) v += E[t * EM_SIZE + which + a * 3 + b];
+          }
+      if (pin && cls == 0) v = (k == 0) ? 1.0 : 0.0;   // identity row of the pinned node 0
+      t64.coef[cls][k] = v;
+      t32.coef[cls][k] = (float)v;
+    }
+    FSI_REQUIRE(t64.coef[cls][0] > 0.0, FSI_E_ARG, "P1 table: non-positive diagonal");
+    t64.dinv[cls] = 1.0 / t64.coef[cls][0];
+    t32.dinv[cls] = (float)t64.dinv[cls];
+  }
+  t64.pin = t32.pin = pin;
 }
 
 // ---------------------------------------------------------------- structured adjacency
@@ -436,6 +480,13 @@ void build_fluid(Ctx &c) {
   c.Mp_dinv.alloc(np);
   hipLaunchKernelGGL(k_diag_inv, dim3(gp), dim3(256), 0, s, np, c.Mp.rowptr.p, c.Mp.col.p, c.Mp.val.p,
                      c.Mp_dinv.p);
+  {
+    P1Table<double> t64;
+    P1Table<float> t32;
+    p1_tables(n, EM_MP, 0, t64, t32);
+    upload_bytes(c.mptab64, &t64, sizeof(t64), s);
+    upload_bytes(c.mptab32, &t32, sizeof(t32), s);
+  }
   c.bnd.alloc(n2);
   hipLaunchKernelGGL(k_p2_boundary_flags, dim3(g2), dim3(256), 0, s, n, c.bnd.p);
   FSI_CHECK_LAUNCH();
@@ -820,9 +871,10 @@ static void coarse_inverse(Mg &mg, hipStream_t s) {
 }
 
 size_t Mg::bytes() const {
-  size_t b = cinv.bytes() + cinv32.bytes();
+  size_t b = cinv.bytes() + cinv32.bytes() + rtab64.bytes() + rtab32.bytes();
   for (auto &L : lv) {
-    b += L.A.bytes() + L.P.bytes() + L.R.bytes() + L.dinv.bytes() + L.dinv32.bytes();
+    b += L.A.bytes() + L.P.bytes() + L.R.bytes() + L.dinv.bytes() + L.dinv32.bytes() + L.stab64.bytes() +
+         L.stab32.bytes() + L.p1tab64.bytes() + L.p1tab32.bytes();
     for (int i = 0; i < 5; ++i) b += L.w64[i].bytes() + L.w32[i].bytes();
   }
   return b;
@@ -873,6 +925,13 @@ void build_multigrid(Ctx &c) {
       FSI_HIP(hipMemcpyAsync(U.stab32.p, &t32, sizeof(t32), hipMemcpyHostToDevice, s));
       FSI_HIP(hipStreamSynchronize(s));
     }
+    if (m >= 2) {
+      P1Table<double> t64;
+      P1Table<float> t32;
+      p1_tables(m, EM_LP, 1, t64, t32);
+      upload_bytes(P.p1tab64, &t64, sizeof(t64), s);
+      upload_bytes(P.p1tab32, &t32, sizeof(t32), s);
+    }
     P.lmax = 1.1 * power_lmax(P, 1, s);
     if (l + 1 < ns.size()) {
       int64_t nc2 = (int64_t)(m + 1) * (m + 1);          // coarse P2 nodes = (2 (m/2) + 1)^2
@@ -900,6 +959,13 @@ void build_multigrid(Ctx &c) {
       U.w64[i].alloc(2 * U.nodes);
       P.w64[i].alloc(P.nodes);
     }
+  }
+  {
+    P2RestrTable<double> t64;
+    P2RestrTable<float> t32;
+    p2_restrict_tables(t64, t32);
+    upload_bytes(c.mgu.rtab64, &t64, sizeof(t64), s);
+    upload_bytes(c.mgu.rtab32, &t32, sizeof(t32), s);
   }
   coarse_inverse(c.mgu, s);
   coarse_inverse(c.mgp, s);

@@ -32,16 +32,18 @@ struct MgLevel {
   DevBuf<double> w64[5];   // x, b, r, d, x2 work vectors
   DevBuf<float> w32[5];
   DevBuf<unsigned char> stab64, stab32;   // StencilTable<double/float> (velocity levels)
+  DevBuf<unsigned char> p1tab64, p1tab32; // P1Table<double/float> of L_p (pressure levels)
 };
 
 struct Mg {
   int comps = 1;           // unknowns per node: 2 (velocity, 2x2 blocks) or 1 (pressure)
-  bool stencil = false;    // velocity smoothing and residuals matrix-free (structured grid)
+  bool stencil = false;    // smoothing, residuals and transfers matrix-free (structured grid)
   int degree = 3;          // Chebyshev smoothing steps before and after the coarse correction
   std::vector<MgLevel> lv; // lv[0] finest
   int64_t ncoarse = 0;     // unknowns of the coarsest level
   DevBuf<double> cinv;     // dense inverse of the coarsest operator (row major)
   DevBuf<float> cinv32;
+  DevBuf<unsigned char> rtab64, rtab32;   // P2RestrTable<double/float> (velocity)
   size_t bytes() const;
 };
 
@@ -74,6 +76,7 @@ struct Ctx {
   Csr Mp;                  // pressure mass, width 1
   DevBuf<double> Mp_dinv;  // 1 / diag(M_p)
   DevBuf<float> Mp_dinv32;
+  DevBuf<unsigned char> mptab64, mptab32;  // P1Table<double/float> of M_p
   DevBuf<unsigned char> bnd;  // 1 on boundary P2 nodes
 
   // solid blocks

@@ -1,0 +1,111 @@
+// Matrix-free pieces of the two multigrid hierarchies on the structured grid (see
+// lattice.hip): P1 pressure operators (L_p with the pinned node, M_p), the first Chebyshev
+// step with class-wise diagonal inverses, and the P2 / P1 grid transfers.
+#pragma once
+
+#include "common.h"
+#include "stencil.h"
+
+namespace fsi {
+
+// P1 lattice (n + 1)^2 with the diagonal of each cell from (i, j) to (i + 1, j + 1): a node
+// couples with itself and the six nodes at these offsets.
+constexpr int kP1Nbr = 7;
+// offsets: self, (-1,0), (+1,0), (0,-1), (0,+1), (-1,-1), (+1,+1)
+
+// Node classes by position: ci = 0 (i = 0), 1 (interior), 2 (i = n); the same for j;
+// class = 3 cj + ci.  coef[c][k] couples a node of class c with the node at offset k
+// (zero where that node is outside the lattice).  pin = 1: the row of node 0 is the
+// identity and its column is zero (the pressure level is fixed at node 0).
+template <typename T>
+struct P1Table {
+  T coef[9][kP1Nbr];
+  T dinv[9];
+  int pin;
+};
+
+// P2 restriction R = P^T: for each class of coarse node (bit 0 = Ic odd, bit 1 = Jc odd),
+// the fine nodes (offsets from the fine node 2 Ic, 2 Jc) whose interpolated value uses the
+// coarse node, with the coarse basis function's value there as weight.
+constexpr int kRestrMax = 81;
+template <typename T>
+struct P2RestrTable {
+  int count[4];
+  int off[4][kRestrMax][2];
+  T w[4][kRestrMax];
+};
+
+// Lattice offsets (units h/2 from the cell's lower-left node) of the six P2 nodes of
+// triangle t of a cell: T0 = (v00, v10, v11), T1 = (v00, v11, v01); vertices a, b, c
+// then edge midpoints ab, bc, ca.
+__host__ __device__ inline void p2_node_offset(int t, int b, int &dI, int &dJ) {
+  const int vx[2][3] = {{0, 2, 2}, {0, 2, 0}};
+  const int vy[2][3] = {{0, 0, 2}, {0, 2, 2}};
+  if (b < 3) {
+    dI = vx[t][b];
+    dJ = vy[t][b];
+  } else {
+    const int p = b - 3, q = (p + 1) % 3;
+    dI = (vx[t][p] + vx[t][q]) / 2;
+    dJ = (vy[t][p] + vy[t][q]) / 2;
+  }
+}
+
+// Coarse P2 interpolation at fine lattice node (I, J) of an nf grid (coarse grid nf / 2,
+// nested): the coarse triangle holding the node, its barycentric coordinates (multiples of
+// 1/4) and the non-zero values of the six coarse basis functions there.  Writes the coarse
+// lattice coordinates and weights of up to 6 nodes; boundary nodes are not excluded.
+__host__ __device__ inline int p2_prolong_weights(int I, int J, int nf, int *Ic, int *Jc, double *w) {
+  const int nc = nf / 2;
+  int ci = I / 4, cj = J / 4;
+  if (ci > nc - 1) ci = nc - 1;
+  if (cj > nc - 1) cj = nc - 1;
+  const double xi = (I - 4 * ci) * 0.25, eta = (J - 4 * cj) * 0.25;
+  int t;
+  double l0, l1, l2;
+  if (xi >= eta) {
+    t = 0; l0 = 1.0 - xi; l1 = xi - eta; l2 = eta;
+  } else {
+    t = 1; l0 = 1.0 - eta; l1 = xi; l2 = eta - xi;
+  }
+  const double phi[6] = {l0 * (2 * l0 - 1), l1 * (2 * l1 - 1), l2 * (2 * l2 - 1),
+                         4 * l0 * l1,       4 * l1 * l2,       4 * l2 * l0};
+  int cnt = 0;
+  for (int b = 0; b < 6; ++b) {
+    if (phi[b] == 0.0) continue;
+    int dI, dJ;
+    p2_node_offset(t, b, dI, dJ);
+    Ic[cnt] = 2 * ci + dI;
+    Jc[cnt] = 2 * cj + dJ;
+    w[cnt] = phi[b];
+    ++cnt;
+  }
+  return cnt;
+}
+
+// Host table builders
+void p1_tables(int n, int which, int pin, P1Table<double> &t64, P1Table<float> &t32);   // assemble.hip
+void p2_restrict_tables(P2RestrTable<double> &t64, P2RestrTable<float> &t32);          // lattice.hip
+
+// Launchers (stream-ordered, no synchronisation).  Vectors are component-major with the
+// level's node count as stride.
+template <typename T, int MODE>   // SP_APPLY, SP_RESID or SP_CHEB as for the A_f stencil
+void p1_launch(int n, const P1Table<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2,
+               hipStream_t s);
+// d = x = scale D^{-1} b (first Chebyshev step from zero), class-wise diagonal
+template <typename T>
+void p1_first(int n, const P1Table<T> *tab, const T *b, T scale, T *d, T *x, hipStream_t s);
+template <typename T>
+void p2_first(int n, const StencilTable<T> *tab, const T *b, T scale, T *d, T *x, hipStream_t s);
+// y += P xc (fine grid nf; coarse vector on the nf / 2 grid); P2 has two components
+template <typename T>
+void p2_prolong_add(int nf, const T *xc, T *y, hipStream_t s);
+template <typename T>
+void p1_prolong_add(int nf, const T *xc, T *y, hipStream_t s);
+// bc = R r
+template <typename T>
+void p2_restrict(int nf, const P2RestrTable<T> *tab, const T *r, T *bc, hipStream_t s);
+template <typename T>
+void p1_restrict(int nf, const T *r, T *bc, hipStream_t s);
+
+}  // namespace fsi

@@ -1,0 +1,290 @@
+// Matrix-free multigrid pieces on the structured grid: P1 pressure operators, the first
+// Chebyshev step with class-wise diagonal inverses, and P2 / P1 grid transfers.  Each
+// equals the corresponding assembled (CSR) product up to the order of the sums; the CSR
+// path stays available and serves as the reference in the tests.
+//
+// Bytes per node (scalar values of width w per component):
+//   P1 Chebyshev step   x, b, d read; d, y written           5 w
+//   first step          b read; d, x written                 3 w per component
+//   P2 prolongation-add fine y read and written, coarse x    (2 + 1/4) w per component
+//   P2 restriction      fine r read, coarse b written        (1 + 1/4) w per component
+#include <cstring>
+
+#include "kernels.h"
+#include "lattice.h"
+
+namespace fsi {
+
+// ---------------------------------------------------------------- P1 operators
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_p1(int n, const P1Table<T> *__restrict__ tabp, const T *__restrict__ x,
+                                            const T *__restrict__ b, T *d, T *y, T c1, T c2) {
+  const int L = n + 1;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (int64_t)L * L) return;
+  const int i = (int)(r % L), j = (int)(r / L);
+  const P1Table<T> &tb = *tabp;
+  const int ci = i == 0 ? 0 : (i == n ? 2 : 1), cj = j == 0 ? 0 : (j == n ? 2 : 1);
+  const int cls = 3 * cj + ci;
+  const bool pin = tb.pin != 0;
+  const T xc = x[r];
+  T s;
+  if (pin && r == 0) {
+    s = xc;                                    // identity row of the pinned node
+  } else {
+    const T *c = tb.coef[cls];
+    // column 0 is zero when pinned: its value is read as 0
+    auto ld = [&](int64_t q) -> T { return (pin && q == 0) ? T(0) : x[q]; };
+    s = c[0] * xc;
+    if (i > 0) s += c[1] * ld(r - 1);
+    if (i < n) s += c[2] * x[r + 1];
+    if (j > 0) s += c[3] * ld(r - L);
+    if (j < n) s += c[4] * x[r + L];
+    if (i > 0 && j > 0) s += c[5] * ld(r - L - 1);
+    if (i < n && j < n) s += c[6] * x[r + L + 1];
+  }
+  if constexpr (MODE == SP_APPLY) {
+    y[r] = s;
+  } else if constexpr (MODE == SP_RESID) {
+    y[r] = b[r] - s;
+  } else {
+    const T z = tb.dinv[cls] * (b[r] - s);
+    const T dn = c1 * d[r] + c2 * z;
+    d[r] = dn;
+    y[r] = xc + dn;
+  }
+}
+
+template <typename T, int MODE>
+void p1_launch(int n, const P1Table<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2, hipStream_t s) {
+  const int64_t nodes = (int64_t)(n + 1) * (n + 1);
+  hipLaunchKernelGGL((k_p1<T, MODE>), dim3(grid_for(nodes, 256)), dim3(256), 0, s, n, tab, x, b, d, y, c1, c2);
+  FSI_CHECK_LAUNCH();
+}
+
+template <typename T>
+__global__ void k_p1_first(int n, const P1Table<T> *__restrict__ tabp, const T *__restrict__ b, T scale, T *d,
+                           T *x) {
+  const int L = n + 1;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (int64_t)L * L) return;
+  const int i = (int)(r % L), j = (int)(r / L);
+  const int ci = i == 0 ? 0 : (i == n ? 2 : 1), cj = j == 0 ? 0 : (j == n ? 2 : 1);
+  const T z = scale * (tabp->dinv[3 * cj + ci] * b[r]);
+  d[r] = z;
+  x[r] = z;
+}
+
+template <typename T>
+void p1_first(int n, const P1Table<T> *tab, const T *b, T scale, T *d, T *x, hipStream_t s) {
+  const int64_t nodes = (int64_t)(n + 1) * (n + 1);
+  hipLaunchKernelGGL(k_p1_first<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, n, tab, b, scale, d, x);
+  FSI_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------- P2 first Chebyshev step
+template <typename T>
+__global__ void k_p2_first(int n, const StencilTable<T> *__restrict__ tabp, const T *__restrict__ b, T scale,
+                           T *d, T *x) {
+  const int L = 2 * n + 1;
+  const int64_t N = (int64_t)L * L;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const int I = (int)(r % L), J = (int)(r / L);
+  const T b0 = b[r], b1 = b[N + r];
+  T z0, z1;
+  if (I == 0 || J == 0 || I == 2 * n || J == 2 * n) {
+    z0 = scale * b0;                           // identity rows (Dirichlet nodes)
+    z1 = scale * b1;
+  } else {
+    const T *di = tabp->dinv[(I & 1) | ((J & 1) << 1)];
+    z0 = scale * (di[0] * b0 + di[1] * b1);
+    z1 = scale * (di[2] * b0 + di[3] * b1);
+  }
+  d[r] = z0;
+  x[r] = z0;
+  d[N + r] = z1;
+  x[N + r] = z1;
+}
+
+template <typename T>
+void p2_first(int n, const StencilTable<T> *tab, const T *b, T scale, T *d, T *x, hipStream_t s) {
+  const int64_t nodes = (int64_t)(2 * n + 1) * (2 * n + 1);
+  hipLaunchKernelGGL(k_p2_first<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, n, tab, b, scale, d, x);
+  FSI_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------- P2 transfers
+__device__ __forceinline__ bool on_p2_boundary(int I, int J, int n) {
+  return I == 0 || J == 0 || I == 2 * n || J == 2 * n;
+}
+
+// y += P xc: coarse quadratic evaluated at the fine node; Dirichlet nodes (fine rows and
+// coarse columns) take no part.
+template <typename T>
+__global__ void __launch_bounds__(256) k_p2_prolong_add(int nf, const T *__restrict__ xc, T *y) {
+  const int L = 2 * nf + 1, nc = nf / 2, Lc = 2 * nc + 1;
+  const int64_t Nf = (int64_t)L * L, Nc = (int64_t)Lc * Lc;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= Nf) return;
+  const int I = (int)(r % L), J = (int)(r / L);
+  if (on_p2_boundary(I, J, nf)) return;
+  int Ic[6], Jc[6];
+  double w[6];
+  const int m = p2_prolong_weights(I, J, nf, Ic, Jc, w);
+  T s0 = 0, s1 = 0;
+  for (int q = 0; q < m; ++q) {
+    if (on_p2_boundary(Ic[q], Jc[q], nc)) continue;
+    const int64_t k = (int64_t)Jc[q] * Lc + Ic[q];
+    s0 += (T)w[q] * xc[k];
+    s1 += (T)w[q] * xc[Nc + k];
+  }
+  y[r] += s0;
+  y[Nf + r] += s1;
+}
+
+template <typename T>
+void p2_prolong_add(int nf, const T *xc, T *y, hipStream_t s) {
+  const int64_t nodes = (int64_t)(2 * nf + 1) * (2 * nf + 1);
+  hipLaunchKernelGGL(k_p2_prolong_add<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, nf, xc, y);
+  FSI_CHECK_LAUNCH();
+}
+
+// bc = R r = P^T r over the interior fine nodes; Dirichlet coarse rows are zero.
+template <typename T>
+__global__ void __launch_bounds__(256) k_p2_restrict(int nf, const P2RestrTable<T> *__restrict__ tabp,
+                                                     const T *__restrict__ r, T *bc) {
+  const int L = 2 * nf + 1, nc = nf / 2, Lc = 2 * nc + 1;
+  const int64_t Nf = (int64_t)L * L, Nc = (int64_t)Lc * Lc;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Nc) return;
+  const int Ic = (int)(q % Lc), Jc = (int)(q / Lc);
+  T s0 = 0, s1 = 0;
+  if (!on_p2_boundary(Ic, Jc, nc)) {
+    const int cls = (Ic & 1) | ((Jc & 1) << 1);
+    const P2RestrTable<T> &tb = *tabp;
+    const int cnt = tb.count[cls];
+    for (int k = 0; k < cnt; ++k) {
+      const int I = 2 * Ic + tb.off[cls][k][0], J = 2 * Jc + tb.off[cls][k][1];
+      if (I <= 0 || J <= 0 || I >= 2 * nf || J >= 2 * nf) continue;
+      const int64_t f = (int64_t)J * L + I;
+      s0 += tb.w[cls][k] * r[f];
+      s1 += tb.w[cls][k] * r[Nf + f];
+    }
+  }
+  bc[q] = s0;
+  bc[Nc + q] = s1;
+}
+
+template <typename T>
+void p2_restrict(int nf, const P2RestrTable<T> *tab, const T *r, T *bc, hipStream_t s) {
+  const int nc = nf / 2;
+  const int64_t nodes = (int64_t)(2 * nc + 1) * (2 * nc + 1);
+  hipLaunchKernelGGL(k_p2_restrict<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, nf, tab, r, bc);
+  FSI_CHECK_LAUNCH();
+}
+
+// Host: the restriction weights do not depend on the level (nested uniform refinement),
+// so they are read off at interior coarse nodes of a 16 x 16 fine grid.
+void p2_restrict_tables(P2RestrTable<double> &t64, P2RestrTable<float> &t32) {
+  std::memset(&t64, 0, sizeof(t64));
+  std::memset(&t32, 0, sizeof(t32));
+  const int nf = 16;
+  for (int cls = 0; cls < 4; ++cls) {
+    const int Ic = 4 + (cls & 1), Jc = 4 + (cls >> 1);
+    int cnt = 0;
+    for (int dJ = -4; dJ <= 4; ++dJ)
+      for (int dI = -4; dI <= 4; ++dI) {
+        int ic[6], jc[6];
+        double w[6];
+        const int m = p2_prolong_weights(2 * Ic + dI, 2 * Jc + dJ, nf, ic, jc, w);
+        for (int q = 0; q < m; ++q)
+          if (ic[q] == Ic && jc[q] == Jc) {
+            FSI_REQUIRE(cnt < kRestrMax, FSI_E_ARG, "restriction table overflow");
+            t64.off[cls][cnt][0] = t32.off[cls][cnt][0] = dI;
+            t64.off[cls][cnt][1] = t32.off[cls][cnt][1] = dJ;
+            t64.w[cls][cnt] = w[q];
+            t32.w[cls][cnt] = (float)w[q];
+            ++cnt;
+          }
+      }
+    t64.count[cls] = t32.count[cls] = cnt;
+  }
+}
+
+// ---------------------------------------------------------------- P1 transfers
+// Linear interpolation on the nested triangulation; the pinned node 0 is excluded on both
+// grids (fine row 0 and coarse column 0 are empty).
+template <typename T>
+__global__ void __launch_bounds__(256) k_p1_prolong_add(int nf, const T *__restrict__ xc, T *y) {
+  const int L = nf + 1, Lc = nf / 2 + 1;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0 || r >= (int64_t)L * L) return;
+  const int i = (int)(r % L), j = (int)(r / L), ci = i >> 1, cj = j >> 1;
+  auto cv = [&](int a, int bb) -> T {
+    const int64_t k = (int64_t)bb * Lc + a;
+    return k == 0 ? T(0) : xc[k];
+  };
+  T s;
+  if (!(i & 1) && !(j & 1)) s = cv(ci, cj);
+  else if (!(j & 1)) s = T(0.5) * cv(ci, cj) + T(0.5) * cv(ci + 1, cj);
+  else if (!(i & 1)) s = T(0.5) * cv(ci, cj) + T(0.5) * cv(ci, cj + 1);
+  else s = T(0.5) * cv(ci, cj) + T(0.5) * cv(ci + 1, cj + 1);
+  y[r] += s;
+}
+
+template <typename T>
+void p1_prolong_add(int nf, const T *xc, T *y, hipStream_t s) {
+  const int64_t nodes = (int64_t)(nf + 1) * (nf + 1);
+  hipLaunchKernelGGL(k_p1_prolong_add<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, nf, xc, y);
+  FSI_CHECK_LAUNCH();
+}
+
+// Coarse node (ic, jc) collects the fine node on it (weight 1) and the six fine edge
+// midpoints around it (weight 1/2): horizontal, vertical and the two along the cell
+// diagonals through it.
+template <typename T>
+__global__ void __launch_bounds__(256) k_p1_restrict(int nf, const T *__restrict__ r, T *bc) {
+  const int L = nf + 1, Lc = nf / 2 + 1;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)Lc * Lc) return;
+  if (q == 0) {
+    bc[0] = T(0);
+    return;
+  }
+  const int fi = 2 * (int)(q % Lc), fj = 2 * (int)(q / Lc);
+  auto fv = [&](int a, int bb) -> T {
+    if (a < 0 || bb < 0 || a > nf || bb > nf) return T(0);
+    const int64_t f = (int64_t)bb * L + a;
+    return f == 0 ? T(0) : r[f];
+  };
+  const T edges = fv(fi - 1, fj) + fv(fi + 1, fj) + fv(fi, fj - 1) + fv(fi, fj + 1) + fv(fi + 1, fj + 1) +
+                  fv(fi - 1, fj - 1);
+  bc[q] = fv(fi, fj) + T(0.5) * edges;
+}
+
+template <typename T>
+void p1_restrict(int nf, const T *r, T *bc, hipStream_t s) {
+  const int64_t nodes = (int64_t)(nf / 2 + 1) * (nf / 2 + 1);
+  hipLaunchKernelGGL(k_p1_restrict<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, nf, r, bc);
+  FSI_CHECK_LAUNCH();
+}
+
+#define FSI_LATTICE_INST(T)                                                                                 \
+  template void p1_launch<T, SP_APPLY>(int, const P1Table<T> *, const T *, const T *, T *, T *, T, T,       \
+                                       hipStream_t);                                                        \
+  template void p1_launch<T, SP_RESID>(int, const P1Table<T> *, const T *, const T *, T *, T *, T, T,       \
+                                       hipStream_t);                                                        \
+  template void p1_launch<T, SP_CHEB>(int, const P1Table<T> *, const T *, const T *, T *, T *, T, T,        \
+                                      hipStream_t);                                                         \
+  template void p1_first<T>(int, const P1Table<T> *, const T *, T, T *, T *, hipStream_t);                 \
+  template void p2_first<T>(int, const StencilTable<T> *, const T *, T, T *, T *, hipStream_t);            \
+  template void p2_prolong_add<T>(int, const T *, T *, hipStream_t);                                        \
+  template void p1_prolong_add<T>(int, const T *, T *, hipStream_t);                                        \
+  template void p2_restrict<T>(int, const P2RestrTable<T> *, const T *, T *, hipStream_t);                 \
+  template void p1_restrict<T>(int, const T *, T *, hipStream_t);
+
+FSI_LATTICE_INST(double)
+FSI_LATTICE_INST(float)
+
+}  // namespace fsi

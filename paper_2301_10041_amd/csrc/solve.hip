@@ -25,6 +25,7 @@
 
 #include "ctx.h"
 #include "kernels.h"
+#include "lattice.h"
 #include "stencil.h"
 
 namespace fsi {
@@ -188,33 +189,53 @@ static T *chebyshev(int64_t nrows, const int *rp, const int *col, const T *val, 
   return x;
 }
 
-// The same Chebyshev iteration with the matrix-free A_f product on an n x n grid.
-template <typename T>
-static T *chebyshev_stencil(int n, const StencilTable<T> *tab, int64_t nodes, const T *dinv,
-                            double lmin, double lmax, int steps, const T *b, T *x, T *x2, T *d,
-                            bool zero_init, hipStream_t s, Prof *prof) {
+// The same Chebyshev iteration with matrix-free products: first(scale, d, x) does the
+// step from zero (d = x = scale D^{-1} b), step(x, x2, c1, c2) one step from x into x2.
+template <typename T, typename First, typename Step>
+static T *chebyshev_mf(First first, Step step, double lmin, double lmax, int steps, T *x, T *x2,
+                       bool zero_init, hipStream_t s, Prof *prof) {
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
   if (zero_init) {
-    hipLaunchKernelGGL((k_dinv_first<T, 4, 2>), dim3(grid_for(nodes, 256)), dim3(256), 0, s, nodes,
-                       dinv, b, (T)(1.0 / theta), d, x);
-    FSI_CHECK_LAUNCH();
+    first((T)(1.0 / theta), x);
   } else {
     if (prof) prof->begin(s);
-    stencil_launch<T, SP_CHEB>(n, tab, x, b, d, x2, (T)0, (T)(1.0 / theta), s);
+    step(x, x2, (T)0, (T)(1.0 / theta));
     if (prof) prof->end(s);
     std::swap(x, x2);
   }
   for (int k = 1; k < steps; ++k) {
     double rho1 = 1.0 / (2.0 * sigma - rho);
     if (prof) prof->begin(s);
-    stencil_launch<T, SP_CHEB>(n, tab, x, b, d, x2, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), s);
+    step(x, x2, (T)(rho1 * rho), (T)(2.0 * rho1 / delta));
     if (prof) prof->end(s);
     std::swap(x, x2);
     rho = rho1;
   }
   return x;
+}
+
+// Chebyshev on A_f (stencil) and on a P1 table (L_p level or M_p) with right-hand side b
+// and direction buffer d.
+template <typename T>
+static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, double lmax, int steps,
+                            const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s, Prof *prof) {
+  return chebyshev_mf<T>([&](T sc, T *xo) { p2_first<T>(n, tab, b, sc, d, xo, s); },
+                         [&](const T *xi, T *xo, T c1, T c2) {
+                           stencil_launch<T, SP_CHEB>(n, tab, xi, b, d, xo, c1, c2, s);
+                         },
+                         lmin, lmax, steps, x, x2, zero_init, s, prof);
+}
+
+template <typename T>
+static T *chebyshev_p1(int n, const P1Table<T> *tab, double lmin, double lmax, int steps, const T *b,
+                       T *x, T *x2, T *d, bool zero_init, hipStream_t s) {
+  return chebyshev_mf<T>([&](T sc, T *xo) { p1_first<T>(n, tab, b, sc, d, xo, s); },
+                         [&](const T *xi, T *xo, T c1, T c2) {
+                           p1_launch<T, SP_CHEB>(n, tab, xi, b, d, xo, c1, c2, s);
+                         },
+                         lmin, lmax, steps, x, x2, zero_init, s, nullptr);
 }
 
 template <typename T> static const StencilTable<T> *stab(const MgLevel &L);
@@ -223,6 +244,12 @@ template <> const StencilTable<double> *stab<double>(const MgLevel &L) {
 }
 template <> const StencilTable<float> *stab<float>(const MgLevel &L) {
   return (const StencilTable<float> *)L.stab32.p;
+}
+template <typename T> static const P1Table<T> *p1tab(const MgLevel &L) {
+  return (const P1Table<T> *)(std::is_same<T, double>::value ? L.p1tab64.p : L.p1tab32.p);
+}
+template <typename T> static const P2RestrTable<T> *rtab(const Mg &mg) {
+  return (const P2RestrTable<T> *)(std::is_same<T, double>::value ? mg.rtab64.p : mg.rtab32.p);
 }
 
 // ---------------------------------------------------------------- V-cycle
@@ -242,26 +269,40 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr)
   const T *dinv = Pr<T>::dinv(L);
   const T *val = Pr<T>::val(L.A);
   Prof *pl = (l == 0) ? prof : nullptr;
-  const bool mf = (W == 4) && mg.stencil;   // matrix-free A_f products
-  T *xs = mf ? chebyshev_stencil<T>(L.n, stab<T>(L), L.nodes, dinv, lmin, lmax, mg.degree, b, x, x2, d,
-                                    true, s, pl)
-             : chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax,
-                                   mg.degree, b, x, x2, d, true, s, pl);
-  T *xo = (xs == x) ? x2 : x;
-  if (mf)
-    stencil_launch<T, SP_RESID>(L.n, stab<T>(L), xs, b, nullptr, r, (T)0, (T)0, s);
-  else
-    spmv<T, W, NC, SP_RESID>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, xs, L.nodes, r, L.nodes, s, b);
   MgLevel &C = mg.lv[l + 1];
   T *bc = Pr<T>::w(C, 1);
+  if (mg.stencil) {   // matrix-free smoothing, residual and transfers
+    auto smooth = [&](T *x0, T *x1, bool zero) -> T * {
+      if constexpr (W == 4)
+        return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, mg.degree, b, x0, x1, d, zero, s, pl);
+      else
+        return chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, mg.degree, b, x0, x1, d, zero, s);
+    };
+    T *xs = smooth(x, x2, true);
+    T *xo = (xs == x) ? x2 : x;
+    if constexpr (W == 4) {
+      stencil_launch<T, SP_RESID>(L.n, stab<T>(L), xs, b, nullptr, r, (T)0, (T)0, s);
+      p2_restrict<T>(L.n, rtab<T>(mg), r, bc, s);
+    } else {
+      p1_launch<T, SP_RESID>(L.n, p1tab<T>(L), xs, b, nullptr, r, (T)0, (T)0, s);
+      p1_restrict<T>(L.n, r, bc, s);
+    }
+    T *xc = vcycle<T, W, NC>(mg, l + 1, bc, s);
+    if constexpr (W == 4)
+      p2_prolong_add<T>(L.n, xc, xs, s);
+    else
+      p1_prolong_add<T>(L.n, xc, xs, s);
+    return smooth(xs, xo, false);
+  }
+  T *xs = chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, mg.degree, b, x,
+                              x2, d, true, s, pl);
+  T *xo = (xs == x) ? x2 : x;
+  spmv<T, W, NC, SP_RESID>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, xs, L.nodes, r, L.nodes, s, b);
   spmv<T, 1, NC, SP_APPLY>(L.R.nrows, L.R.rowptr.p, L.R.col.p, Pr<T>::val(L.R), r, L.nodes, bc,
                            C.nodes, s);
   T *xc = vcycle<T, W, NC>(mg, l + 1, bc, s);
   spmv<T, 1, NC, SP_ADD>(L.P.nrows, L.P.rowptr.p, L.P.col.p, Pr<T>::val(L.P), xc, C.nodes, xs,
                          L.nodes, s);
-  if (mf)
-    return chebyshev_stencil<T>(L.n, stab<T>(L), L.nodes, dinv, lmin, lmax, mg.degree, b, xs, xo, d,
-                                false, s, pl);
   return chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, mg.degree, b,
                              xs, xo, d, false, s, pl);
 }
@@ -289,8 +330,12 @@ static void a11_precond(Ctx &c, const T *r, T *z) {
   fill(rp, 1, (T)0, s);
   T *xp = vcycle<T, 1, 1>(c.mgp, 0, rp, s);
   T *mx = Pr<T>::inner(c, 7).p, *mx2 = mx + Np, *md = mx + 2 * Np;
-  T *mres = chebyshev<T, 1, 1>(Np, c.Mp.rowptr.p, c.Mp.col.p, Pr<T>::val(c.Mp), mp_dinv<T>(c), 0.5,
-                               2.0, kMpSteps, rp, mx, mx2, md, true, s);
+  T *mres = c.mgp.stencil
+                ? chebyshev_p1<T>(c.n, (const P1Table<T> *)(std::is_same<T, double>::value ? c.mptab64.p
+                                                                                          : c.mptab32.p),
+                                  0.5, 2.0, kMpSteps, rp, mx, mx2, md, true, s)
+                : chebyshev<T, 1, 1>(Np, c.Mp.rowptr.p, c.Mp.col.p, Pr<T>::val(c.Mp), mp_dinv<T>(c), 0.5,
+                                     2.0, kMpSteps, rp, mx, mx2, md, true, s);
   lincomb(z + 2 * N2, mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, s);
   hipLaunchKernelGGL(k_set_pinned<T>, dim3(1), dim3(1), 0, s, z + 2 * N2, r + 2 * N2);
   FSI_CHECK_LAUNCH();
