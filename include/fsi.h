@@ -185,7 +185,9 @@ int fsi_build_rhs(fsi_ctx *ctx, const double *u_n, const double *X_n, double *b)
 
 /* y = A x with the full operator of eq. (matrix) (needs fsi_assemble_coupling).
  * prec = FSI_FP32 rounds x and the matrix values to FP32, accumulates in FP32 and
- * writes FP64.  x, y: device N (no aliasing). */
+ * writes FP64.  FSI_FP64 with the structured-grid products on (fsi_set_smoother,
+ * default) computes the fluid rows matrix-free (A_f, B, B^T from the element matrices;
+ * C_f^T from its CSR).  x, y: device N (no aliasing). */
 int fsi_apply_operator(fsi_ctx *ctx, int prec, const double *x, double *y);
 
 /* z = P^{-1} r, P = diag(A11, A22) or [[A11, 0], [A21, A22]] (Sec. 5).  A22^{-1} in
@@ -225,7 +227,9 @@ int fsi_export_csr(fsi_ctx *ctx, int block, int64_t *nrows, int64_t *nnz, int32_
  * (L_p: pinned node identity row, zero column), and the P2 / P1 prolongations and
  * restrictions from the nested refinement, all with the same element matrices and
  * interpolation weights as the assembled operators.  FSI_SMOOTH_CSR reads the assembled
- * matrices.  Both give the same preconditioner up to the order of the sums. */
+ * matrices.  The same switch selects the matrix-free fluid rows of the FP64 operator
+ * (A11 in the inner solves and fsi_apply_operator).  Both settings give the same results
+ * up to the order of the sums. */
 enum fsi_smoother { FSI_SMOOTH_CSR = 0, FSI_SMOOTH_STENCIL = 1 };
 int fsi_set_smoother(fsi_ctx *ctx, int kind);
 

@@ -167,6 +167,79 @@ void stencil_tables(int n, double nu, double rdt, StencilTable<double> &t64, Ste
   }
 }
 
+// Host: B^T rows of the four interior P2 node classes and the B row of an interior P1
+// node, summed over the triangles around the node from the element blocks
+// B_alpha(k, i) = int d_alpha phi_i lam_k.
+void div_tables(int n, DivTable<double> &t64, DivTable<float> &t32) {
+  FSI_REQUIRE(n >= 2, FSI_E_ARG, "divergence tables need n >= 2");
+  std::vector<double> E;
+  element_tables(n, 1.0, E);
+  std::memset(&t64, 0, sizeof(t64));
+  std::memset(&t32, 0, sizeof(t32));
+  struct A { int ci, cj, t, a; };
+  auto around = [&](int I, int J, A *adj) {
+    int na = 0;
+    for (int cj = std::max(0, (J - 1) >> 1); cj <= std::min(n - 1, J >> 1); ++cj)
+      for (int ci = std::max(0, (I - 1) >> 1); ci <= std::min(n - 1, I >> 1); ++ci)
+        for (int t = 0; t < 2; ++t)
+          for (int a = 0; a < 6; ++a)
+            if (2 * ci + hOff[t][a][0] == I && 2 * cj + hOff[t][a][1] == J) {
+              adj[na++] = A{ci, cj, t, a};
+              break;
+            }
+    return na;
+  };
+  A adj[8];
+  for (int cls = 0; cls < 4; ++cls) {
+    const int I = 2 + (cls & 1), J = 2 + (cls >> 1);
+    const int na = around(I, J, adj);
+    int cnt = 0;
+    for (int q = 0; q < na; ++q)
+      for (int v = 0; v < 3; ++v) {   // P1 vertex v of the triangle
+        const int di = (2 * adj[q].ci + hOff[adj[q].t][v][0]) / 2 - (I >> 1);
+        const int dj = (2 * adj[q].cj + hOff[adj[q].t][v][1]) / 2 - (J >> 1);
+        int k = 0;
+        while (k < cnt && !(t64.bt_off[cls][k][0] == di && t64.bt_off[cls][k][1] == dj)) ++k;
+        if (k == cnt) {
+          FSI_REQUIRE(cnt < kBtMax, FSI_E_ARG, "B^T stencil too wide");
+          t64.bt_off[cls][k][0] = t32.bt_off[cls][k][0] = di;
+          t64.bt_off[cls][k][1] = t32.bt_off[cls][k][1] = dj;
+          ++cnt;
+        }
+        const double *e = E.data() + adj[q].t * EM_SIZE + EM_B;
+        for (int al = 0; al < 2; ++al) t64.bt_coef[cls][k][al] += e[(al * 3 + v) * 6 + adj[q].a];
+      }
+    t64.bt_count[cls] = t32.bt_count[cls] = cnt;
+  }
+  {
+    const int na = around(2, 2, adj);   // P1 node (1, 1)
+    int cnt = 0;
+    for (int q = 0; q < na; ++q) {
+      FSI_REQUIRE(adj[q].a < 3, FSI_E_ARG, "P1 node is not a vertex");
+      for (int b = 0; b < 6; ++b) {
+        const int dI = 2 * adj[q].ci + hOff[adj[q].t][b][0] - 2, dJ = 2 * adj[q].cj + hOff[adj[q].t][b][1] - 2;
+        int k = 0;
+        while (k < cnt && !(t64.b_off[k][0] == dI && t64.b_off[k][1] == dJ)) ++k;
+        if (k == cnt) {
+          FSI_REQUIRE(cnt < kBMax, FSI_E_ARG, "B stencil too wide");
+          t64.b_off[k][0] = t32.b_off[k][0] = dI;
+          t64.b_off[k][1] = t32.b_off[k][1] = dJ;
+          t64.b_lds[k] = t32.b_lds[k] = dJ * (kTileC + 4) + dI;
+          ++cnt;
+        }
+        const double *e = E.data() + adj[q].t * EM_SIZE + EM_B;
+        for (int al = 0; al < 2; ++al) t64.b_coef[k][al] += e[(al * 3 + adj[q].a) * 6 + b];
+      }
+    }
+    t64.b_count = t32.b_count = cnt;
+  }
+  for (int c = 0; c < 4; ++c)
+    for (int k = 0; k < kBtMax; ++k)
+      for (int al = 0; al < 2; ++al) t32.bt_coef[c][k][al] = (float)t64.bt_coef[c][k][al];
+  for (int k = 0; k < kBMax; ++k)
+    for (int al = 0; al < 2; ++al) t32.b_coef[k][al] = (float)t64.b_coef[k][al];
+}
+
 // Host: rows of a P1 x P1 matrix (EM_MP: mass, EM_LP: Laplacian) at one node of each of
 // the nine position classes of an n x n grid, summed over the triangles around the node.
 void p1_tables(int n, int which, int pin, P1Table<double> &t64, P1Table<float> &t32) {
@@ -480,6 +553,13 @@ void build_fluid(Ctx &c) {
   c.Mp_dinv.alloc(np);
   hipLaunchKernelGGL(k_diag_inv, dim3(gp), dim3(256), 0, s, np, c.Mp.rowptr.p, c.Mp.col.p, c.Mp.val.p,
                      c.Mp_dinv.p);
+  {
+    DivTable<double> t64;
+    DivTable<float> t32;
+    div_tables(n, t64, t32);
+    upload_bytes(c.divtab64, &t64, sizeof(t64), s);
+    upload_bytes(c.divtab32, &t32, sizeof(t32), s);
+  }
   {
     P1Table<double> t64;
     P1Table<float> t32;

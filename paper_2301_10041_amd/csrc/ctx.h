@@ -77,6 +77,7 @@ struct Ctx {
   DevBuf<double> Mp_dinv;  // 1 / diag(M_p)
   DevBuf<float> Mp_dinv32;
   DevBuf<unsigned char> mptab64, mptab32;  // P1Table<double/float> of M_p
+  DevBuf<unsigned char> divtab64, divtab32;  // DivTable<double/float> (B and B^T)
   DevBuf<unsigned char> bnd;  // 1 on boundary P2 nodes
 
   // solid blocks

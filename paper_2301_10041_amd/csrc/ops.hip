@@ -135,8 +135,9 @@ void make_shadow(Csr &A, hipStream_t s) {
   convert(A.val32.p, A.val.p, (int64_t)m, s);
 }
 
+// solid_only: only the solid row group (the fluid rows come from the stencil launch)
 template <typename T, typename Tx, typename Ty>
-static void launch_operator(Ctx &c, const Tx *x, Ty *y, bool fluid_only, bool pressure_only = false) {
+static void launch_operator(Ctx &c, const Tx *x, Ty *y, bool fluid_only, bool solid_only = false) {
   OpArgs<T, Tx, Ty> a{};
   a.N2 = c.N2; a.Np = c.Np; a.Ns = fluid_only ? 0 : c.Ns;
   a.inv_dt = (T)(1.0 / c.dt);
@@ -152,15 +153,33 @@ static void launch_operator(Ctx &c, const Tx *x, Ty *y, bool fluid_only, bool pr
   a.x = x;
   a.y = y;
   a.fluid_only = fluid_only ? 1 : 0;
-  a.gU = pressure_only ? 0u : (unsigned)((c.N2 + kRowsPerBlock - 1) / kRowsPerBlock);
-  a.gP = (unsigned)((c.Np + kRowsPerBlock - 1) / kRowsPerBlock);
+  a.gU = solid_only ? 0u : (unsigned)((c.N2 + kRowsPerBlock - 1) / kRowsPerBlock);
+  a.gP = solid_only ? 0u : (unsigned)((c.Np + kRowsPerBlock - 1) / kRowsPerBlock);
   unsigned gS = fluid_only ? 0u : (unsigned)((c.Ns + kRowsPerBlock - 1) / kRowsPerBlock);
   hipLaunchKernelGGL((k_operator<T, Tx, Ty>), dim3(a.gU + a.gP + gS), dim3(kOpBlock), 0, c.stream, a);
   FSI_CHECK_LAUNCH();
 }
 
+// Fluid rows matrix-free (structured-grid products enabled, FP64): one tiled launch for
+// the velocity and pressure rows, then the solid row group of the fused kernel.
+static void fluid_rows_stencil(Ctx &c, const double *x, double *y, bool fluid_only) {
+  const bool cft = !fluid_only && c.CfT.rowptr.p != nullptr;
+  const double *xl = x + 2 * c.N2 + c.Np + 2 * c.Ns;
+  stencil_fluid_rows<double>(c.n, (const StencilTable<double> *)c.mgu.lv[0].stab64.p,
+                             (const DivTable<double> *)c.divtab64.p, x, y, cft ? c.CfT.rowptr.p : nullptr,
+                             cft ? c.CfT.col.p : nullptr, cft ? c.CfT.val.p : nullptr, cft ? xl : nullptr,
+                             c.Ns, c.stream);
+}
+
 template <typename T, typename Tx>
 void apply_operator(Ctx &c, const Tx *x, double *y, bool fluid_only) {
+  if constexpr (std::is_same<T, double>::value && std::is_same<Tx, double>::value) {
+    if (c.mgu.stencil) {
+      fluid_rows_stencil(c, x, y, fluid_only);
+      if (!fluid_only) launch_operator<double, double, double>(c, x, y, false, true);
+      return;
+    }
+  }
   launch_operator<T, Tx, double>(c, x, y, fluid_only);
 }
 template void apply_operator<double, double>(Ctx &, const double *, double *, bool);
@@ -175,16 +194,13 @@ template void apply_a11<double>(Ctx &, const double *, double *);
 template void apply_a11<float>(Ctx &, const float *, float *);
 
 // A11 on FP64 vectors, arithmetic and matrix values in TA (FP32: values from the shadows).
-// With the structured-grid smoother enabled, the A_f part is the matrix-free stencil
-// (velocity rows: A_f x_u - B^T x_p in one tiled launch) and the pressure rows are the
-// CSR product -B x_u (+ the pin); otherwise everything reads the assembled blocks.
+// FP64 with the structured-grid products enabled: one matrix-free tiled launch
+// (A_f stencil, B and B^T from their class tables); otherwise the assembled blocks.
 template <typename TA>
 void apply_a11_on64(Ctx &c, const double *x, double *y) {
   if constexpr (std::is_same<TA, double>::value) {
     if (c.mgu.stencil) {
-      stencil_a11_velocity<double>(c.n, (const StencilTable<double> *)c.mgu.lv[0].stab64.p,
-                                   c.BT.rowptr.p, c.BT.col.p, c.BT.val.p, x, y, c.stream);
-      launch_operator<double, double, double>(c, x, y, true, true);
+      fluid_rows_stencil(c, x, y, true);
       return;
     }
   }

@@ -26,15 +26,40 @@ struct StencilTable {
 // Neighbour counts of the classes on the triangulated grid (vertex, h-edge, v-edge, diagonal).
 constexpr int kStencilCount[4] = {19, 9, 9, 9};
 
+// Divergence blocks on the structured grid.  B^T row of an interior P2 node of class c:
+// the P1 vertices of the triangles around it (offsets from P1 node (I >> 1, J >> 1)) with
+// the pair (B_x, B_y)(k, node).  B row of a P1 node (i, j): the P2 nodes of the triangles
+// around it (lattice offsets from (2i, 2j)).  Rows of Dirichlet P2 nodes of B^T and the
+// matching columns of B are zero; so are row 0 of B and column 0 of B^T (pinned pressure).
+// Every triangle holding an interior P2 node lies in the domain, so one B row serves every
+// P1 node, boundary ones included, once the Dirichlet values of x_u are read as zero.
+constexpr int kBtMax = 7;
+constexpr int kBMax = 19;
+template <typename T>
+struct DivTable {
+  int bt_count[4];
+  int bt_off[4][kBtMax][2];
+  T bt_coef[4][kBtMax][2];
+  int b_count;
+  int b_off[kBMax][2];
+  int b_lds[kBMax];              // dJ (kTileC + 4) + dI
+  T b_coef[kBMax][2];
+};
+
 template <typename T, int MODE>
 void stencil_launch(int n, const StencilTable<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2,
                     hipStream_t s);
 
+// Fluid rows of the operator on [u_x | u_y | p] in one tiled launch:
+//   y_u = A_f x_u - B^T x_p (+ C_f^T x_lam when cft_rp is given; lam_x at xl, lam_y at xl + Ns)
+//   y_p = -B x_u, and y_p[0] = x_p[0] (pinned node)
 template <typename T>
-void stencil_a11_velocity(int n, const StencilTable<T> *tab, const int *bt_rp, const int *bt_col,
-                          const T *bt_val, const T *x, T *y, hipStream_t s);
+void stencil_fluid_rows(int n, const StencilTable<T> *tab, const DivTable<T> *dv, const T *x, T *y,
+                        const int *cft_rp, const int *cft_col, const T *cft_val, const T *xl, int64_t Ns,
+                        hipStream_t s);
 
 // Host: the tables of A_f on an n x n grid from the element matrices (assemble.hip).
 void stencil_tables(int n, double nu, double rdt, StencilTable<double> &t64, StencilTable<float> &t32);
+void div_tables(int n, DivTable<double> &t64, DivTable<float> &t32);
 
 }  // namespace fsi

@@ -22,9 +22,11 @@ struct StencilArgs {
   T *d, *y;
   int L2;                      // nodes per component (2n+1)^2
   T c1, c2;
-  // SP_A11 only: y_u = A_f x_u - B^T x_p with B^T as CSR (2 values per entry)
-  const int *bt_rp, *bt_col;
-  const T *bt_val, *xp;
+  // SP_A11 only: fluid rows on [u_x | u_y | p] (x and y hold all three; see
+  // stencil_fluid_rows), optional C_f^T x_lam on the velocity rows
+  const DivTable<T> *dv;
+  const int *cft_rp, *cft_col;
+  const T *cft_val, *xlx, *xly;
 };
 
 // Tiled kernel.  A block owns kTileR lattice rows x kTileC nodes.  Phase 1 stages x with a
@@ -120,10 +122,25 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
       a.y[a.L2 + r] = s1;
     } else if constexpr (MODE == SP_A11) {
       T t0 = s0, t1 = s1;
-      for (int k = a.bt_rp[r]; k < a.bt_rp[r + 1]; ++k) {
-        const T pj = a.xp[a.bt_col[k]];
-        t0 -= a.bt_val[2 * k] * pj;
-        t1 -= a.bt_val[2 * k + 1] * pj;
+      if (!bnd) {   // - B^T x_p; column 0 (pinned pressure) is zero
+        const DivTable<T> &dv = *a.dv;
+        const T *xp = a.x + 2 * (int64_t)a.L2;
+        const int cls = (I & 1) | ((J & 1) << 1);
+        const int pi = I >> 1, pj = J >> 1, L1 = a.n + 1;
+        for (int k = 0; k < dv.bt_count[cls]; ++k) {
+          const int q = (pj + dv.bt_off[cls][k][1]) * L1 + pi + dv.bt_off[cls][k][0];
+          const T pv = q == 0 ? T(0) : xp[q];
+          t0 -= dv.bt_coef[cls][k][0] * pv;
+          t1 -= dv.bt_coef[cls][k][1] * pv;
+        }
+      }
+      if (a.cft_rp) {
+        for (int k = a.cft_rp[r]; k < a.cft_rp[r + 1]; ++k) {
+          const T cv = a.cft_val[k];
+          const int j = a.cft_col[k];
+          t0 += cv * a.xlx[j];
+          t1 += cv * a.xly[j];
+        }
       }
       a.y[r] = t0;
       a.y[a.L2 + r] = t1;
@@ -145,6 +162,26 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
       a.y[a.L2 + r] = x1 + d1;
     }
   }
+  if constexpr (MODE == SP_A11) {
+    // phase 4: pressure rows of the P1 nodes at even lattice positions of the tile
+    // (2 rows x 64 nodes), -B x_u from the staged x tile (Dirichlet values read as zero)
+    if (tid < 2 * kWave) {
+      const int pr = tid / kWave, pc = tid % kWave;
+      const int pi = (I0 >> 1) + pc, pj = (J0 >> 1) + pr;
+      if (pi <= a.n && pj <= a.n) {
+        const DivTable<T> &dv = *a.dv;
+        const int base = (2 * pr + 2) * kTW + (2 * pc + 2);
+        T sp = 0;
+        for (int k = 0; k < dv.b_count; ++k) {
+          const int o = base + dv.b_lds[k];
+          sp += dv.b_coef[k][0] * X[0][o] + dv.b_coef[k][1] * X[1][o];
+        }
+        const int64_t q = (int64_t)pj * (a.n + 1) + pi;
+        const int64_t o2 = 2 * (int64_t)a.L2;
+        a.y[o2 + q] = q == 0 ? a.x[o2] : -sp;
+      }
+    }
+  }
 }
 
 template <typename T, int MODE>
@@ -162,22 +199,28 @@ void stencil_launch(int n, const StencilTable<T> *tab, const T *x, const T *b, T
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
   static_assert(kTileR * kWave == 256 && 2 * kWave == kTileC, "one tile row per wave, two nodes per lane");
   StencilArgs<T> a{n, tab, x, b, d, y, (2 * n + 1) * (2 * n + 1), c1, c2, nullptr, nullptr, nullptr,
-                   nullptr};
+                   nullptr, nullptr, nullptr};
   launch_tiles<T, MODE>(n, a, s);
 }
 
-// y_u = A_f x_u - B^T x_p on the fluid vector [u_x | u_y | p] (velocity rows of A11)
 template <typename T>
-void stencil_a11_velocity(int n, const StencilTable<T> *tab, const int *bt_rp, const int *bt_col,
-                          const T *bt_val, const T *x, T *y, hipStream_t s) {
+void stencil_fluid_rows(int n, const StencilTable<T> *tab, const DivTable<T> *dv, const T *x, T *y,
+                        const int *cft_rp, const int *cft_col, const T *cft_val, const T *xl, int64_t Ns,
+                        hipStream_t s) {
+  FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
+  static_assert(kTileC % 2 == 0 && kTileR % 2 == 0 && kTileC / 2 == kWave && kTileR / 2 * kWave <= 256,
+                "a tile holds 2 x 64 P1 nodes, one per thread of the first two waves");
   const int L = 2 * n + 1, L2 = L * L;
-  StencilArgs<T> a{n, tab, x, nullptr, nullptr, y, L2, T(0), T(0), bt_rp, bt_col, bt_val, x + 2 * (int64_t)L2};
+  StencilArgs<T> a{n, tab, x, nullptr, nullptr, y, L2, T(0), T(0), dv, cft_rp, cft_col, cft_val, xl,
+                   xl ? xl + Ns : nullptr};
   launch_tiles<T, SP_A11>(n, a, s);
 }
-template void stencil_a11_velocity<double>(int, const StencilTable<double> *, const int *, const int *,
-                                           const double *, const double *, double *, hipStream_t);
-template void stencil_a11_velocity<float>(int, const StencilTable<float> *, const int *, const int *,
-                                          const float *, const float *, float *, hipStream_t);
+template void stencil_fluid_rows<double>(int, const StencilTable<double> *, const DivTable<double> *,
+                                         const double *, double *, const int *, const int *, const double *,
+                                         const double *, int64_t, hipStream_t);
+template void stencil_fluid_rows<float>(int, const StencilTable<float> *, const DivTable<float> *, const float *,
+                                        float *, const int *, const int *, const float *, const float *, int64_t,
+                                        hipStream_t);
 
 template void stencil_launch<double, SP_APPLY>(int, const StencilTable<double> *, const double *, const double *,
                                                double *, double *, double, double, hipStream_t);
