@@ -15,6 +15,9 @@ namespace fsi {
 Ctx::~Ctx() {
   drop_graphs();
   if (cap_stream) hipStreamDestroy(cap_stream);
+  if (aux_stream) hipStreamDestroy(aux_stream);
+  if (ev_fork) hipEventDestroy(ev_fork);
+  if (ev_join) hipEventDestroy(ev_join);
   if (hpin) hipHostFree(hpin);
 }
 
@@ -142,6 +145,9 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     c.h_tri.assign(solid->tri, solid->tri + 3 * nt);
     c.h_xy.assign(solid->xy, solid->xy + 2 * ns);
     FSI_HIP(hipHostMalloc((void **)&c.hpin, 4096 * sizeof(double), hipHostMallocDefault));
+    FSI_HIP(hipStreamCreateWithFlags(&c.aux_stream, hipStreamNonBlocking));
+    FSI_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+    FSI_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
     fsi::build_solid(c);
     fsi::build_fluid(c);
     fsi::build_multigrid(c);

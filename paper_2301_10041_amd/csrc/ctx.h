@@ -133,6 +133,12 @@ struct Ctx {
   bool use_graphs = false;
   hipGraphExec_t pc_graph[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;   // capture only (default priority)
+  // second stream of the A11 preconditioner: the pressure part (Schur approximation) runs
+  // beside the velocity V-cycle, forked from and joined into the context stream by events
+  // (default priority; created with the context)
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool capturing = false;     // inside a graph capture: the preconditioner stays on one stream
   // inner MINRES: device-side scalar state, its own reduction buffer and solution vector
   // (allocated once: captured graphs hold these pointers), graphs per precision and phase
   DevBuf<double> ms_state, ms_red, ms_x;

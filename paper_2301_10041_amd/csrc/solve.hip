@@ -316,29 +316,41 @@ template <> const float *mp_dinv<float>(Ctx &c) { return c.Mp_dinv32.p; }
 // (measured at 1024^2: 8, 4 and 3 steps give the same outer count; 2 and 1 cost inner steps)
 constexpr int kMpSteps = 4;
 
-// z = diag(V, S^{-1}) r on [u | p]
+// z = diag(V, S^{-1}) r on [u | p].  The two blocks share no buffer: outside graph capture
+// the pressure part runs on the auxiliary stream beside the velocity V-cycle (both chains
+// are latency-bound on the coarse levels), forked after the producer of r and joined
+// before the consumer of z.  Captured graphs keep the whole preconditioner on one stream.
 template <typename T>
 static void a11_precond(Ctx &c, const T *r, T *z) {
-  hipStream_t s = c.stream;
+  const bool fork = !c.capturing;
+  hipStream_t s = c.stream, sp = fork ? c.aux_stream : c.stream;
   const int64_t N2 = c.N2, Np = c.Np;
   Prof *pf = std::is_same<T, double>::value ? &c.prof64 : &c.prof32;
+  if (fork) {
+    FSI_HIP(hipEventRecord(c.ev_fork, s));
+    FSI_HIP(hipStreamWaitEvent(sp, c.ev_fork, 0));
+  }
   T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr);
   convert(z, xu, 2 * N2, s);
   // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
   T *rp = Pr<T>::inner(c, 8).p;
-  convert(rp, r + 2 * N2, Np, s);
-  fill(rp, 1, (T)0, s);
-  T *xp = vcycle<T, 1, 1>(c.mgp, 0, rp, s);
+  convert(rp, r + 2 * N2, Np, sp);
+  fill(rp, 1, (T)0, sp);
+  T *xp = vcycle<T, 1, 1>(c.mgp, 0, rp, sp);
   T *mx = Pr<T>::inner(c, 7).p, *mx2 = mx + Np, *md = mx + 2 * Np;
   T *mres = c.mgp.stencil
                 ? chebyshev_p1<T>(c.n, (const P1Table<T> *)(std::is_same<T, double>::value ? c.mptab64.p
                                                                                           : c.mptab32.p),
-                                  0.5, 2.0, kMpSteps, rp, mx, mx2, md, true, s)
+                                  0.5, 2.0, kMpSteps, rp, mx, mx2, md, true, sp)
                 : chebyshev<T, 1, 1>(Np, c.Mp.rowptr.p, c.Mp.col.p, Pr<T>::val(c.Mp), mp_dinv<T>(c), 0.5,
-                                     2.0, kMpSteps, rp, mx, mx2, md, true, s);
-  lincomb(z + 2 * N2, mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, s);
-  hipLaunchKernelGGL(k_set_pinned<T>, dim3(1), dim3(1), 0, s, z + 2 * N2, r + 2 * N2);
+                                     2.0, kMpSteps, rp, mx, mx2, md, true, sp);
+  lincomb(z + 2 * N2, mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, sp);
+  hipLaunchKernelGGL(k_set_pinned<T>, dim3(1), dim3(1), 0, sp, z + 2 * N2, r + 2 * N2);
   FSI_CHECK_LAUNCH();
+  if (fork) {
+    FSI_HIP(hipEventRecord(c.ev_join, sp));
+    FSI_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
+  }
 }
 
 // ---------------------------------------------------------------- inner MINRES
@@ -375,15 +387,18 @@ static void a11_precond_graph(Ctx &c, const double *r, double *z) {
     hipGraph_t g = nullptr;
     FSI_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
     c.stream = c.cap_stream;
+    c.capturing = true;
     try {
       a11_precond_on64<TA>(c, c.pc_in.p, c.pc_out.p);
     } catch (...) {
       c.stream = s;
+      c.capturing = false;
       hipStreamEndCapture(c.cap_stream, &g);
       if (g) hipGraphDestroy(g);
       throw;
     }
     c.stream = s;
+    c.capturing = false;
     FSI_HIP(hipStreamEndCapture(c.cap_stream, &g));
     hipError_t e = hipGraphInstantiate(&c.pc_graph[k], g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
@@ -587,15 +602,18 @@ static int minres_a11(Ctx &c, const double *b, double *xout, double tol, int max
         hipGraph_t g = nullptr;
         FSI_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
         c.stream = c.cap_stream;
+        c.capturing = true;
         try {
           ms_iteration<TA>(c, bq, st);
         } catch (...) {
           c.stream = s;
+          c.capturing = false;
           hipStreamEndCapture(c.cap_stream, &g);
           if (g) hipGraphDestroy(g);
           throw;
         }
         c.stream = s;
+        c.capturing = false;
         FSI_HIP(hipStreamEndCapture(c.cap_stream, &g));
         hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
