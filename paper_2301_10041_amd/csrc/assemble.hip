@@ -164,6 +164,10 @@ void stencil_tables(int n, double nu, double rdt, StencilTable<double> &t64, Ste
       }
     t64.count[cls] = t32.count[cls] = cnt;
     FSI_REQUIRE(cnt == kStencilCount[cls], FSI_E_ARG, "unexpected stencil width");
+    constexpr StencilOffsets so = stencil_offsets();
+    for (int k = 0; k < cnt; ++k)
+      FSI_REQUIRE(t64.off[cls][k][0] == so.d[cls][k][0] && t64.off[cls][k][1] == so.d[cls][k][1], FSI_E_ARG,
+                  "stencil offsets differ from the compiled pattern");
   }
 }
 

@@ -216,16 +216,54 @@ static T *chebyshev_mf(First first, Step step, double lmin, double lmax, int ste
   return x;
 }
 
-// Chebyshev on A_f (stencil) and on a P1 table (L_p level or M_p) with right-hand side b
-// and direction buffer d.
+// Chebyshev on A_f (stencil) with right-hand side b and direction buffer d: the first three
+// steps from zero (pre-smoothing) or the first two from x (post-smoothing) as one
+// temporally blocked launch, further steps one launch each (same recurrence as
+// chebyshev_mf; the profile brackets the single-step launches).
 template <typename T>
 static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, double lmax, int steps,
                             const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s, Prof *prof) {
-  return chebyshev_mf<T>([&](T sc, T *xo) { p2_first<T>(n, tab, b, sc, d, xo, s); },
-                         [&](const T *xi, T *xo, T c1, T c2) {
-                           stencil_launch<T, SP_CHEB>(n, tab, xi, b, d, xo, c1, c2, s);
-                         },
-                         lmin, lmax, steps, x, x2, zero_init, s, prof);
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  auto next = [&](T &c1, T &c2) {
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    c1 = (T)(rho1 * rho);
+    c2 = (T)(2.0 * rho1 / delta);
+    rho = rho1;
+  };
+  int done = 0;
+  if (zero_init && steps >= 3) {
+    T c1a, c2a, c1b, c2b;
+    next(c1a, c2a);
+    next(c1b, c2b);
+    cheb2_pre<T>(n, tab, b, d, x, (T)(1.0 / theta), c1a, c2a, c1b, c2b, s);
+    done = 3;
+  } else if (!zero_init && steps >= 2) {
+    T c1b, c2b;
+    next(c1b, c2b);
+    cheb2_post<T>(n, tab, x, b, d, x2, (T)(1.0 / theta), c1b, c2b, s);
+    std::swap(x, x2);
+    done = 2;
+  } else if (zero_init) {
+    p2_first<T>(n, tab, b, (T)(1.0 / theta), d, x, s);
+    done = 1;
+  } else {
+    if (prof) prof->begin(s);
+    stencil_launch<T, SP_CHEB>(n, tab, x, b, d, x2, (T)0, (T)(1.0 / theta), s);
+    if (prof) prof->end(s);
+    std::swap(x, x2);
+    done = 1;
+  }
+  for (int k = done; k < steps; ++k) {
+    T c1, c2;
+    next(c1, c2);
+    if (prof) prof->begin(s);
+    stencil_launch<T, SP_CHEB>(n, tab, x, b, d, x2, c1, c2, s);
+    if (prof) prof->end(s);
+    std::swap(x, x2);
+  }
+  return x;
 }
 
 template <typename T>

@@ -26,6 +26,23 @@ struct StencilTable {
 // Neighbour counts of the classes on the triangulated grid (vertex, h-edge, v-edge, diagonal).
 constexpr int kStencilCount[4] = {19, 9, 9, 9};
 
+// The neighbour offsets (dI, dJ) of each class, in the order of the tables (dJ, then dI,
+// ascending).  They follow from the triangulation alone; the table builder checks them.
+// Kernels index them with compile-time class and neighbour, so LDS addresses become
+// instruction immediates.
+struct StencilOffsets {
+  int d[4][kStencilMax][2];
+};
+__host__ __device__ constexpr StencilOffsets stencil_offsets() {
+  return StencilOffsets{{
+      {{-2, -2}, {-1, -2}, {0, -2}, {-2, -1}, {-1, -1}, {0, -1}, {1, -1}, {-2, 0}, {-1, 0}, {0, 0},
+       {1, 0}, {2, 0}, {-1, 1}, {0, 1}, {1, 1}, {2, 1}, {0, 2}, {1, 2}, {2, 2}},
+      {{-1, -2}, {-1, -1}, {0, -1}, {-1, 0}, {0, 0}, {1, 0}, {0, 1}, {1, 1}, {1, 2}},
+      {{-2, -1}, {-1, -1}, {0, -1}, {-1, 0}, {0, 0}, {1, 0}, {0, 1}, {1, 1}, {2, 1}},
+      {{-1, -1}, {0, -1}, {1, -1}, {-1, 0}, {0, 0}, {1, 0}, {-1, 1}, {0, 1}, {1, 1}},
+  }};
+}
+
 // Divergence blocks on the structured grid.  B^T row of an interior P2 node of class c:
 // the P1 vertices of the triangles around it (offsets from P1 node (I >> 1, J >> 1)) with
 // the pair (B_x, B_y)(k, node).  B row of a P1 node (i, j): the P2 nodes of the triangles
@@ -57,6 +74,16 @@ template <typename T>
 void stencil_fluid_rows(int n, const StencilTable<T> *tab, const DivTable<T> *dv, const T *x, T *y,
                         const int *cft_rp, const int *cft_col, const T *cft_val, const T *xl, int64_t Ns,
                         hipStream_t s);
+
+// Two Chebyshev steps per launch on the A_f stencil (temporal blocking):
+// cheb2_pre : x = d = s D^{-1} b, then two steps (c1a, c2a), (c1b, c2b); writes x, d
+// cheb2_post: from x, a step with c1 = 0 (c2a) and a step (c1b, c2b); writes y, d
+template <typename T>
+void cheb2_pre(int n, const StencilTable<T> *tab, const T *b, T *d, T *x, T s, T c1a, T c2a, T c1b, T c2b,
+               hipStream_t st);
+template <typename T>
+void cheb2_post(int n, const StencilTable<T> *tab, const T *x, const T *b, T *d, T *y, T c2a, T c1b, T c2b,
+                hipStream_t st);
 
 // Host: the tables of A_f on an n x n grid from the element matrices (assemble.hip).
 void stencil_tables(int n, double nu, double rdt, StencilTable<double> &t64, StencilTable<float> &t32);

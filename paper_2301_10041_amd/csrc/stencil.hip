@@ -42,11 +42,12 @@ constexpr int kTH = kTileR + 4;
 template <typename T, int CLS>
 __device__ __forceinline__ void tile_row_products(const StencilTable<T> &tb, const T *X0, const T *X1,
                                                   int base, T &s0, T &s1) {
+  constexpr StencilOffsets so = stencil_offsets();
   s0 = 0;
   s1 = 0;
 #pragma unroll
   for (int k = 0; k < kStencilCount[CLS]; ++k) {
-    const int o = base + tb.lds[CLS][k];
+    const int o = base + so.d[CLS][k][1] * kTW + so.d[CLS][k][0];
     const T y0 = X0[o], y1 = X1[o];
     s0 += tb.coef[CLS][k][0] * y0 + tb.coef[CLS][k][1] * y1;
     s1 += tb.coef[CLS][k][2] * y0 + tb.coef[CLS][k][3] * y1;
@@ -68,18 +69,49 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
   const int I0 = (t % tiles_x) * kTileC, J0 = (t / tiles_x) * kTileR;
   const int tid = threadIdx.x;
   const StencilTable<T> &tb = *a.tab;
-  // phase 1: x tile with halo
-  for (int e = tid; e < kTH * kTW; e += 256) {
-    const int tr = e / kTW, tc = e % kTW;
-    const int I = I0 - 2 + tc, J = J0 - 2 + tr;
-    T v0 = 0, v1 = 0;
-    if (I > 0 && J > 0 && I < n2 && J < n2) {
+  // epilogue operands of this thread's nodes (row-major, coalesced), loaded first
+  constexpr int EIT = kTileR * kTileC / 256;
+  T ex[EIT][2], eb[EIT][2], ed[EIT][2];
+#pragma unroll
+  for (int q = 0; q < EIT; ++q) {
+    const int e = tid + 256 * q, I = I0 + e % kTileC, J = J0 + e / kTileC;
+    ex[q][0] = ex[q][1] = eb[q][0] = eb[q][1] = ed[q][0] = ed[q][1] = 0;
+    if (I <= n2 && J <= n2) {
       const int r = J * L + I;
-      v0 = a.x[r];
-      v1 = a.x[a.L2 + r];
+      ex[q][0] = a.x[r];
+      ex[q][1] = a.x[a.L2 + r];
+      if constexpr (MODE == SP_RESID || MODE == SP_CHEB) {
+        eb[q][0] = a.b[r];
+        eb[q][1] = a.b[a.L2 + r];
+      }
+      if constexpr (MODE == SP_CHEB) {
+        ed[q][0] = a.d[r];
+        ed[q][1] = a.d[a.L2 + r];
+      }
     }
-    X[0][e] = v0;
-    X[1][e] = v1;
+  }
+  // phase 1: x tile with halo (all loads issued before the LDS stores)
+  constexpr int NE = kTH * kTW, IT = (NE + 255) / 256;
+  T v[IT][2];
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int e = tid + 256 * q, tr = e / kTW, tc = e % kTW;
+    const int I = I0 - 2 + tc, J = J0 - 2 + tr;
+    v[q][0] = 0;
+    v[q][1] = 0;
+    if (e < NE && I > 0 && J > 0 && I < n2 && J < n2) {
+      const int r = J * L + I;
+      v[q][0] = a.x[r];
+      v[q][1] = a.x[a.L2 + r];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int e = tid + 256 * q;
+    if (e < NE) {
+      X[0][e] = v[q][0];
+      X[1][e] = v[q][1];
+    }
   }
   __syncthreads();
   // phase 2: products of the interior rows, one tile row per wave
@@ -109,13 +141,15 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
   }
   __syncthreads();
   // phase 3: epilogue, row-major and coalesced
-  for (int e = tid; e < kTileR * kTileC; e += 256) {
+#pragma unroll
+  for (int q = 0; q < EIT; ++q) {
+    const int e = tid + 256 * q;
     const int j = e / kTileC, i = e % kTileC;
     const int I = I0 + i, J = J0 + j;
     if (I > n2 || J > n2) continue;
     const int r = J * L + I;
     const bool bnd = I == 0 || J == 0 || I == n2 || J == n2;
-    const T x0 = a.x[r], x1 = a.x[a.L2 + r];
+    const T x0 = ex[q][0], x1 = ex[q][1];
     const T s0 = bnd ? x0 : S[0][e], s1 = bnd ? x1 : S[1][e];
     if constexpr (MODE == SP_APPLY) {
       a.y[r] = s0;
@@ -128,8 +162,8 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
         const int cls = (I & 1) | ((J & 1) << 1);
         const int pi = I >> 1, pj = J >> 1, L1 = a.n + 1;
         for (int k = 0; k < dv.bt_count[cls]; ++k) {
-          const int q = (pj + dv.bt_off[cls][k][1]) * L1 + pi + dv.bt_off[cls][k][0];
-          const T pv = q == 0 ? T(0) : xp[q];
+          const int pq = (pj + dv.bt_off[cls][k][1]) * L1 + pi + dv.bt_off[cls][k][0];
+          const T pv = pq == 0 ? T(0) : xp[pq];
           t0 -= dv.bt_coef[cls][k][0] * pv;
           t1 -= dv.bt_coef[cls][k][1] * pv;
         }
@@ -145,17 +179,21 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
       a.y[r] = t0;
       a.y[a.L2 + r] = t1;
     } else if constexpr (MODE == SP_RESID) {
-      a.y[r] = a.b[r] - s0;
-      a.y[a.L2 + r] = a.b[a.L2 + r] - s1;
+      a.y[r] = eb[q][0] - s0;
+      a.y[a.L2 + r] = eb[q][1] - s1;
     } else {
-      const T r0 = a.b[r] - s0, r1 = a.b[a.L2 + r] - s1;
+      const T r0 = eb[q][0] - s0, r1 = eb[q][1] - s1;
       T z0 = r0, z1 = r1;
-      if (!bnd) {
+      if (!bnd) {   // class-wise D^{-1}: scalar loads, picked per node
         const int cls = (I & 1) | ((J & 1) << 1);
-        z0 = tb.dinv[cls][0] * r0 + tb.dinv[cls][1] * r1;
-        z1 = tb.dinv[cls][2] * r0 + tb.dinv[cls][3] * r1;
+        T di[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          di[k] = cls == 0 ? tb.dinv[0][k] : cls == 1 ? tb.dinv[1][k] : cls == 2 ? tb.dinv[2][k] : tb.dinv[3][k];
+        z0 = di[0] * r0 + di[1] * r1;
+        z1 = di[2] * r0 + di[3] * r1;
       }
-      const T d0 = a.c1 * a.d[r] + a.c2 * z0, d1 = a.c1 * a.d[a.L2 + r] + a.c2 * z1;
+      const T d0 = a.c1 * ed[q][0] + a.c2 * z0, d1 = a.c1 * ed[q][1] + a.c2 * z1;
       a.d[r] = d0;
       a.d[a.L2 + r] = d1;
       a.y[r] = x0 + d0;
@@ -221,6 +259,284 @@ template void stencil_fluid_rows<double>(int, const StencilTable<double> *, cons
 template void stencil_fluid_rows<float>(int, const StencilTable<float> *, const DivTable<float> *, const float *,
                                         float *, const int *, const int *, const float *, const float *, int64_t,
                                         hipStream_t);
+
+// ---------------------------------------------------------------- two steps per launch
+// Temporal blocking of the Chebyshev smoother: two steps on a tile of kC2R x kC2W nodes.
+// x is staged with a halo of four nodes (X0), the first step is computed on the tile plus
+// a halo of two (X1, and its direction D1 on the tile), the second on the tile.  Dirichlet
+// and out-of-lattice values are stored as 0 in X0 and X1 (zero columns); Dirichlet rows
+// (identity) are stepped pointwise from global memory.  b and d are read where needed
+// (pointwise).  Modes:
+//   C2_PRE : the first step from x = 0 (x = d = s D^{-1} b) and two more: the whole
+//            pre-smoothing of a degree-3 smoother; reads b, writes x and d.
+//   C2_POST: two steps from x with the first direction coefficient c1 = 0 (no d read):
+//            the start of the post-smoothing; reads x and b, writes y and d.
+// Bytes per node: C2_PRE 6 w for three steps, C2_POST 8 w for two (w = value size,
+// two components).
+constexpr int kC2W = 124, kC2R = 4;                 // output tile (kC2W + 4 = 2 x 64 lanes)
+constexpr int kC2W0 = kC2W + 8, kC2H0 = kC2R + 8;   // x with a halo of 4
+constexpr int kC2W1 = kC2W + 4, kC2H1 = kC2R + 4;   // first step with a halo of 2
+static_assert(kC2W1 == 2 * kWave && kC2W0 == kTW, "lane layout and LDS offsets of the tables");
+
+template <typename T>
+struct Cheb2Args {
+  int n;
+  const StencilTable<T> *tab;
+  const T *x, *b;
+  T *d, *y;
+  int L2;
+  T s;                   // C2_PRE: scale of the first step
+  T c1a, c2a, c1b, c2b;  // the two stencil steps
+};
+
+// The staged tiles are stored as two planes of even and odd lattice columns
+// (X[component][parity][row][column / 2]), so a half-wave pass over nodes of one parity
+// reads consecutive words (no LDS bank conflicts).  Node at plane column h of parity PAR
+// (= CLS & 1), neighbour (dI, dJ): parity (PAR + dI) & 1, plane column h + ((PAR + dI) >> 1).
+template <typename T, int CLS, int ROWS, int HW, int NR>
+__device__ __forceinline__ void split_products(const StencilTable<T> &tb, const T *X, const int (&row)[NR], int h,
+                                               T (&s)[NR][2]) {
+  constexpr int PAR = CLS & 1;
+  constexpr int COMP = 2 * ROWS * HW;   // offset of the second component
+  constexpr StencilOffsets so = stencil_offsets();
+#pragma unroll
+  for (int q = 0; q < NR; ++q) s[q][0] = s[q][1] = 0;
+#pragma unroll
+  for (int k = 0; k < kStencilCount[CLS]; ++k) {
+    const int dI = so.d[CLS][k][0], dJ = so.d[CLS][k][1];
+    const int off = (((PAR + dI) & 1) * ROWS + dJ) * HW + ((PAR + dI) >> 1);
+    const T c0 = tb.coef[CLS][k][0], c1 = tb.coef[CLS][k][1], c2 = tb.coef[CLS][k][2], c3 = tb.coef[CLS][k][3];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int o = row[q] * HW + h + off;
+      const T y0 = X[o], y1 = X[COMP + o];
+      s[q][0] += c0 * y0 + c1 * y1;
+      s[q][1] += c2 * y0 + c3 * y1;
+    }
+  }
+}
+
+// rows of one parity class (the class is uniform over the wave: jodd is wave-uniform)
+template <typename T, int PAR, int ROWS, int HW, int NR>
+__device__ __forceinline__ void class_products(const StencilTable<T> &tb, int jodd, const T *X,
+                                               const int (&row)[NR], int h, T (&s)[NR][2]) {
+  if (jodd) split_products<T, PAR | 2, ROWS, HW, NR>(tb, X, row, h, s);
+  else split_products<T, PAR, ROWS, HW, NR>(tb, X, row, h, s);
+}
+
+enum { C2_PRE = 0, C2_POST = 1 };
+
+// Wave w owns region-1 rows w + 2 (tile row w) and one halo row (0, 1, 6 or 7); its lanes
+// hold the nodes i = 2 lane + par of those rows (region-1 column i = tile column i - 2), so
+// the tile row's b and first-step direction stay in registers for the second step.  All b
+// loads are issued before x is staged.
+template <typename T, int M>
+__global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int tiles, int band) {
+  constexpr int HW0 = kC2W0 / 2, HW1 = kC2W1 / 2;   // plane widths
+  __shared__ T X0[2 * 2 * kC2H0 * HW0];             // [component][parity][row][column / 2]
+  __shared__ T X1[2 * 2 * kC2H1 * HW1];
+  const int t = (blockIdx.x % kXcd) * band + blockIdx.x / kXcd;
+  if (t >= tiles) return;
+  const int n2 = 2 * a.n, L = n2 + 1;
+  const int64_t N = a.L2;
+  const int I0 = (t % tiles_x) * kC2W, J0 = (t / tiles_x) * kC2R;
+  const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+  const StencilTable<T> &tb = *a.tab;
+  const int rows[2] = {w < 2 ? w : w + 4, w + 2};   // halo row, tile row (region-1 rows)
+  auto inside = [&](int I, int J) { return I > 0 && J > 0 && I < n2 && J < n2; };
+  // b at the wave's region-1 nodes (0 outside the lattice)
+  T bv[2][2][2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int J = J0 - 2 + rows[q];
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const int I = I0 - 2 + 2 * lane + par;
+      bv[q][par][0] = 0;
+      bv[q][par][1] = 0;
+      if (I >= 0 && J >= 0 && I <= n2 && J <= n2) {
+        const int64_t r = (int64_t)J * L + I;
+        bv[q][par][0] = a.b[r];
+        bv[q][par][1] = a.b[N + r];
+      }
+    }
+  }
+  // phase A: x (or, from zero, the first step s D^{-1} b) with a halo of 4; all loads are
+  // issued before the first LDS store
+  constexpr int NE = kC2H0 * kC2W0, IT = (NE + 255) / 256;
+  T v[IT][2];
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int e = tid + 256 * q, tr = e / kC2W0, tc = e % kC2W0;
+    const int I = I0 - 4 + tc, J = J0 - 4 + tr;
+    v[q][0] = 0;
+    v[q][1] = 0;
+    if (e < NE && inside(I, J)) {
+      const int64_t r = (int64_t)J * L + I;
+      v[q][0] = M == C2_PRE ? a.b[r] : a.x[r];
+      v[q][1] = M == C2_PRE ? a.b[N + r] : a.x[N + r];
+    }
+  }
+  if constexpr (M == C2_PRE) {
+    // class-wise D^{-1} (scalar loads) picked per node: parity of I = parity of tc, of J = of tr
+    T dv[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dv[c][k] = tb.dinv[c][k];
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int e = tid + 256 * q, tr = e / kC2W0, tc = e % kC2W0;
+      const int c = (tc & 1) | ((tr & 1) << 1);
+      T di[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        di[k] = c == 0 ? dv[0][k] : c == 1 ? dv[1][k] : c == 2 ? dv[2][k] : dv[3][k];
+      const T b0 = v[q][0], b1 = v[q][1];
+      v[q][0] = a.s * (di[0] * b0 + di[1] * b1);
+      v[q][1] = a.s * (di[2] * b0 + di[3] * b1);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int e = tid + 256 * q, tr = e / kC2W0, tc = e % kC2W0;
+    if (e < NE) {
+      const int o = ((tc & 1) * kC2H0 + tr) * HW0 + (tc >> 1);
+      X0[o] = v[q][0];
+      X0[2 * kC2H0 * HW0 + o] = v[q][1];
+    }
+  }
+  __syncthreads();
+  // phase B: first stencil step on the tile plus a halo of 2; the wave's two rows have the
+  // same parity, so one pass per column parity covers both with one set of coefficients
+  T d1[2][2] = {{0, 0}, {0, 0}};   // tile row
+  const int jodd = __builtin_amdgcn_readfirstlane((J0 - 2 + rows[1]) & 1);
+#pragma unroll
+  for (int par = 0; par < 2; ++par) {
+    const int i = 2 * lane + par, I = I0 - 2 + i;   // I0 is even: I has the parity of i
+    const int cls = par | (jodd << 1);
+    const int xr[2] = {rows[0] + 2, rows[1] + 2};   // X0 rows; X0 column i + 2 = 2 (lane + 1) + par
+    T sp[2][2];
+    if (par) class_products<T, 1, kC2H0, HW0, 2>(tb, jodd, X0, xr, lane + 1, sp);
+    else class_products<T, 0, kC2H0, HW0, 2>(tb, jodd, X0, xr, lane + 1, sp);
+    const T *di = tb.dinv[cls];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int row = rows[q], J = J0 - 2 + row;
+      T x10 = 0, x11 = 0;
+      if (inside(I, J)) {
+        const int c0 = (par * kC2H0 + row + 2) * HW0 + lane + 1;
+        const T x00 = X0[c0], x01 = X0[2 * kC2H0 * HW0 + c0];
+        const T r0 = bv[q][par][0] - sp[q][0], r1 = bv[q][par][1] - sp[q][1];
+        const T z0 = di[0] * r0 + di[1] * r1, z1 = di[2] * r0 + di[3] * r1;
+        T e0, e1;
+        if constexpr (M == C2_PRE) {   // d = x after the first step from zero
+          e0 = a.c1a * x00 + a.c2a * z0;
+          e1 = a.c1a * x01 + a.c2a * z1;
+        } else {
+          e0 = a.c2a * z0;
+          e1 = a.c2a * z1;
+        }
+        x10 = x00 + e0;
+        x11 = x01 + e1;
+        if (q == 1) {
+          d1[par][0] = e0;
+          d1[par][1] = e1;
+        }
+      }
+      const int o1 = (par * kC2H1 + row) * HW1 + lane;   // column i = 2 lane + par
+      X1[o1] = x10;
+      X1[2 * kC2H1 * HW1 + o1] = x11;
+    }
+  }
+  __syncthreads();
+  // phase C: second step on the tile row
+  {
+    const int row = rows[1], J = J0 - 2 + row;
+    if (J <= n2) {
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        const int i = 2 * lane + par, I = I0 - 2 + i;
+        if (i < 2 || i >= 2 + kC2W || I > n2) continue;
+        const int64_t r = (int64_t)J * L + I;
+        const T b0 = bv[1][par][0], b1 = bv[1][par][1];
+        T x20, x21, d20, d21;
+        if (inside(I, J)) {
+          const int cls = par | (jodd << 1);
+          const int xr[1] = {row};
+          T sp[1][2];
+          if (par) class_products<T, 1, kC2H1, HW1, 1>(tb, jodd, X1, xr, lane, sp);
+          else class_products<T, 0, kC2H1, HW1, 1>(tb, jodd, X1, xr, lane, sp);
+          const T s0 = sp[0][0], s1 = sp[0][1];
+          const int c1 = (par * kC2H1 + row) * HW1 + lane;
+          const T r0 = b0 - s0, r1 = b1 - s1;
+          const T *di = tb.dinv[cls];
+          const T z0 = di[0] * r0 + di[1] * r1, z1 = di[2] * r0 + di[3] * r1;
+          d20 = a.c1b * d1[par][0] + a.c2b * z0;
+          d21 = a.c1b * d1[par][1] + a.c2b * z1;
+          x20 = X1[c1] + d20;
+          x21 = X1[2 * kC2H1 * HW1 + c1] + d21;
+        } else {   // Dirichlet row: the identity, stepped pointwise
+          T x00, x01, d00, d01;
+          if constexpr (M == C2_PRE) {
+            x00 = a.s * b0;
+            x01 = a.s * b1;
+            d00 = x00;
+            d01 = x01;
+          } else {
+            x00 = a.x[r];
+            x01 = a.x[N + r];
+            d00 = 0;
+            d01 = 0;
+          }
+          const T e0 = a.c1a * d00 + a.c2a * (b0 - x00), e1 = a.c1a * d01 + a.c2a * (b1 - x01);
+          const T x10 = x00 + e0, x11 = x01 + e1;
+          d20 = a.c1b * e0 + a.c2b * (b0 - x10);
+          d21 = a.c1b * e1 + a.c2b * (b1 - x11);
+          x20 = x10 + d20;
+          x21 = x11 + d21;
+        }
+        a.d[r] = d20;
+        a.d[N + r] = d21;
+        a.y[r] = x20;
+        a.y[N + r] = x21;
+      }
+    }
+  }
+}
+
+template <typename T>
+void cheb2_pre(int n, const StencilTable<T> *tab, const T *b, T *d, T *x, T s, T c1a, T c2a, T c1b, T c2b,
+               hipStream_t st) {
+  FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
+  const int L = 2 * n + 1;
+  const int tx = (L + kC2W - 1) / kC2W, ty = (L + kC2R - 1) / kC2R;
+  const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
+  Cheb2Args<T> a{n, tab, nullptr, b, d, x, L * L, s, c1a, c2a, c1b, c2b};
+  hipLaunchKernelGGL((k_cheb2<T, C2_PRE>), dim3((unsigned)(band * kXcd)), dim3(256), 0, st, a, tx, tiles, band);
+  FSI_CHECK_LAUNCH();
+}
+
+template <typename T>
+void cheb2_post(int n, const StencilTable<T> *tab, const T *x, const T *b, T *d, T *y, T c2a, T c1b, T c2b,
+                hipStream_t st) {
+  FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
+  const int L = 2 * n + 1;
+  const int tx = (L + kC2W - 1) / kC2W, ty = (L + kC2R - 1) / kC2R;
+  const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
+  Cheb2Args<T> a{n, tab, x, b, d, y, L * L, T(0), T(0), c2a, c1b, c2b};
+  hipLaunchKernelGGL((k_cheb2<T, C2_POST>), dim3((unsigned)(band * kXcd)), dim3(256), 0, st, a, tx, tiles, band);
+  FSI_CHECK_LAUNCH();
+}
+
+template void cheb2_pre<double>(int, const StencilTable<double> *, const double *, double *, double *, double,
+                                double, double, double, double, hipStream_t);
+template void cheb2_pre<float>(int, const StencilTable<float> *, const float *, float *, float *, float, float,
+                               float, float, float, hipStream_t);
+template void cheb2_post<double>(int, const StencilTable<double> *, const double *, const double *, double *,
+                                 double *, double, double, double, hipStream_t);
+template void cheb2_post<float>(int, const StencilTable<float> *, const float *, const float *, float *, float *,
+                                float, float, float, hipStream_t);
 
 template void stencil_launch<double, SP_APPLY>(int, const StencilTable<double> *, const double *, const double *,
                                                double *, double *, double, double, hipStream_t);
