@@ -237,6 +237,40 @@ void div_tables(int n, DivTable<double> &t64, DivTable<float> &t32) {
     }
     t64.b_count = t32.b_count = cnt;
   }
+  // canonical order (dJ, then dI), checked against the offsets the kernels are compiled with
+  auto sort_entries = [](int cnt, int (*off)[2], double (*coef)[2], int *lds) {
+    for (int a = 1; a < cnt; ++a)
+      for (int b = a; b > 0; --b) {
+        const bool less = off[b][1] < off[b - 1][1] || (off[b][1] == off[b - 1][1] && off[b][0] < off[b - 1][0]);
+        if (!less) break;
+        std::swap(off[b][0], off[b - 1][0]);
+        std::swap(off[b][1], off[b - 1][1]);
+        std::swap(coef[b][0], coef[b - 1][0]);
+        std::swap(coef[b][1], coef[b - 1][1]);
+        if (lds) std::swap(lds[b], lds[b - 1]);
+      }
+  };
+  constexpr DivOffsets dofs = div_offsets();
+  constexpr StencilOffsets sofs = stencil_offsets();
+  for (int c = 0; c < 4; ++c) {
+    sort_entries(t64.bt_count[c], t64.bt_off[c], t64.bt_coef[c], nullptr);
+    FSI_REQUIRE(t64.bt_count[c] == kBtCount[c], FSI_E_ARG, "unexpected B^T stencil width");
+    for (int k = 0; k < t64.bt_count[c]; ++k) {
+      FSI_REQUIRE(t64.bt_off[c][k][0] == dofs.bt[c][k][0] && t64.bt_off[c][k][1] == dofs.bt[c][k][1], FSI_E_ARG,
+                  "B^T offsets differ from the compiled pattern");
+      t32.bt_off[c][k][0] = t64.bt_off[c][k][0];
+      t32.bt_off[c][k][1] = t64.bt_off[c][k][1];
+    }
+  }
+  sort_entries(t64.b_count, t64.b_off, t64.b_coef, t64.b_lds);
+  FSI_REQUIRE(t64.b_count == kStencilCount[0], FSI_E_ARG, "unexpected B stencil width");
+  for (int k = 0; k < t64.b_count; ++k) {
+    FSI_REQUIRE(t64.b_off[k][0] == sofs.d[0][k][0] && t64.b_off[k][1] == sofs.d[0][k][1], FSI_E_ARG,
+                "B offsets differ from the compiled pattern");
+    t32.b_off[k][0] = t64.b_off[k][0];
+    t32.b_off[k][1] = t64.b_off[k][1];
+    t32.b_lds[k] = t64.b_lds[k];
+  }
   for (int c = 0; c < 4; ++c)
     for (int k = 0; k < kBtMax; ++k)
       for (int al = 0; al < 2; ++al) t32.bt_coef[c][k][al] = (float)t64.bt_coef[c][k][al];

@@ -141,8 +141,8 @@ struct Ctx {
   bool capturing = false;     // inside a graph capture: the preconditioner stays on one stream
   // inner MINRES: device-side scalar state, its own reduction buffer and solution vector
   // (allocated once: captured graphs hold these pointers), graphs per precision and phase
-  DevBuf<double> ms_state, ms_red, ms_x;
-  hipGraphExec_t ms_graph[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  DevBuf<double> ms_state, ms_red, ms_x, ms_part;
+  hipGraphExec_t ms_graph[2][6] = {};   // per precision and buffer-rotation phase
   DevBuf<double> pc_in, pc_out;
   void drop_graphs();
 

@@ -567,6 +567,21 @@ __global__ void k_ms_update(double *wn, const double *v, const double *w1, const
   }
 }
 
+// alfa = sum of the per-tile parts of v . y (one block, fixed order)
+__global__ void k_ms_alfa(const double *part, int n, MinresState *st) {
+  __shared__ double red[256 / kWave];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  acc = wave_sum(acc);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = 0.0;
+    for (int k = 0; k < 256 / kWave; ++k) b += red[k];
+    st->alfa = b;
+  }
+}
+
 // Buffers of one rotation phase (0, 1, 2).  Lanczos: r1 (old), r2 (current), y (new);
 // directions: w1 (two back, overwritten by the new one), w2, w.
 struct MsBufs {
@@ -586,6 +601,39 @@ static MsBufs ms_bufs(Ctx &c, double *x, int phase) {
   b.w = W[(phase + 2) % 3];
   b.x = x;
   return b;
+}
+
+// Buffers with the matrix-free A11 product (fused iteration below): the new Lanczos vector
+// is written over r1, so r1 and r2 alternate between two buffers and the preconditioned
+// vector always lives in the third; the directions rotate as before (period 6 overall).
+static MsBufs ms_bufs_fused(Ctx &c, double *x, int it) {
+  MsBufs b = ms_bufs(c, x, it % 3);   // directions
+  double *B0 = c.inner.v64[2].p, *B1 = c.inner.v64[3].p;
+  b.r1 = it % 2 == 0 ? B0 : B1;
+  b.r2 = it % 2 == 0 ? B1 : B0;
+  b.y = c.inner.v64[1].p;
+  return b;
+}
+
+// One inner iteration with the matrix-free A11 (FP64): the scaling v = s y, the product, the
+// first three-term update and the dot product alfa = v . y are one tiled launch (new y over
+// r1); then y -= alfa s r2, z = M y into the y buffer, beta^2 = y . z.
+template <typename TA>
+static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st) {
+  hipStream_t s = c.stream;
+  const int64_t nf = 2 * c.N2 + c.Np;
+  const unsigned g = vgrid(nf);
+  double *dv = (double *)st;
+  const int tiles = stencil_a11_minres(c.n, (const StencilTable<double> *)c.mgu.lv[0].stab64.p,
+                                       (const DivTable<double> *)c.divtab64.p, b.y, b.v, b.r1, &st->s,
+                                       &st->c_r1, c.ms_part.p, s);
+  hipLaunchKernelGGL(k_ms_alfa, dim3(1), dim3(256), 0, s, c.ms_part.p, tiles, st);
+  hipLaunchKernelGGL(k_ms_axpy, dim3(g), dim3(256), 0, s, b.r1, b.r2, st, 1, nf);
+  a11_precond_on64<TA>(c, b.r1, b.y);
+  multidot(b.r1, 0, 1, b.y, nf, dv + 1, c.ms_red, s);
+  hipLaunchKernelGGL(k_ms_step, dim3(1), dim3(1), 0, s, st);
+  hipLaunchKernelGGL(k_ms_update, dim3(g), dim3(256), 0, s, b.w1, b.v, b.w2, b.w, b.x, st, nf);
+  FSI_CHECK_LAUNCH();
 }
 
 template <typename TA>
@@ -629,10 +677,11 @@ static int minres_a11(Ctx &c, const double *b, double *xout, double tol, int max
   const int k = std::is_same<TA, double>::value ? 0 : 1;
   int it = 0;
   double *h = c.hpin;
+  const bool fused = c.mgu.stencil;   // matrix-free FP64 A11
   while (it < maxit) {
-    const int phase = it % 3;
     // the rotation: in phase p the roles are shifted by p (r2 of phase p is y of p-1, ...)
-    const MsBufs bq = ms_bufs(c, x, phase);
+    const int phase = fused ? it % 6 : it % 3;
+    const MsBufs bq = fused ? ms_bufs_fused(c, x, it) : ms_bufs(c, x, phase);
     if (graphs) {
       hipGraphExec_t &ge = c.ms_graph[k][phase];
       if (!ge) {
@@ -642,7 +691,8 @@ static int minres_a11(Ctx &c, const double *b, double *xout, double tol, int max
         c.stream = c.cap_stream;
         c.capturing = true;
         try {
-          ms_iteration<TA>(c, bq, st);
+          if (fused) ms_iteration_fused<TA>(c, bq, st);
+          else ms_iteration<TA>(c, bq, st);
         } catch (...) {
           c.stream = s;
           c.capturing = false;
@@ -658,6 +708,8 @@ static int minres_a11(Ctx &c, const double *b, double *xout, double tol, int max
         FSI_HIP(e);
       }
       FSI_HIP(hipGraphLaunch(ge, s));
+    } else if (fused) {
+      ms_iteration_fused<TA>(c, bq, st);
     } else {
       ms_iteration<TA>(c, bq, st);
     }
@@ -716,6 +768,7 @@ static void ensure_inner(Ctx &c, int prec) {
     c.ms_x.alloc(nf);
     c.ms_state.alloc(kMsDoubles);
     c.ms_red.alloc(red_blocks(nf));   // multidot with k = 1: never regrown
+    c.ms_part.alloc(stencil_tile_count(c.n));
   }
   if (prec == FSI_FP32) {
     ensure_fp32_mg(c);

@@ -52,6 +52,21 @@ __host__ __device__ constexpr StencilOffsets stencil_offsets() {
 // P1 node, boundary ones included, once the Dirichlet values of x_u are read as zero.
 constexpr int kBtMax = 7;
 constexpr int kBMax = 19;
+constexpr int kBtCount[4] = {7, 4, 4, 4};
+// Entry order of both tables: by dJ, then dI (the builder sorts and checks).  B^T offsets
+// are P1 lattice offsets from (I >> 1, J >> 1); B offsets are P2 lattice offsets from
+// (2i, 2j), the pattern of the vertex class of A_f.
+struct DivOffsets {
+  int bt[4][kBtMax][2];
+};
+__host__ __device__ constexpr DivOffsets div_offsets() {
+  return DivOffsets{{
+      {{-1, -1}, {0, -1}, {-1, 0}, {0, 0}, {1, 0}, {0, 1}, {1, 1}},
+      {{0, -1}, {0, 0}, {1, 0}, {1, 1}},
+      {{-1, 0}, {0, 0}, {0, 1}, {1, 1}},
+      {{0, 0}, {1, 0}, {0, 1}, {1, 1}},
+  }};
+}
 template <typename T>
 struct DivTable {
   int bt_count[4];
@@ -84,6 +99,14 @@ void cheb2_pre(int n, const StencilTable<T> *tab, const T *b, T *d, T *x, T s, T
 template <typename T>
 void cheb2_post(int n, const StencilTable<T> *tab, const T *x, const T *b, T *d, T *y, T c2a, T c1b, T c2b,
                 hipStream_t st);
+
+// The same launch inside the inner MINRES (FP64): v = s x, y = s (A11 x) + c r1 written over
+// r1, and one partial sum of v . y per tile in part[] (s, c read from device memory;
+// r1 read only when c != 0).  Returns the number of tiles (entries of part).
+int stencil_a11_minres(int n, const StencilTable<double> *tab, const DivTable<double> *dv, const double *x,
+                       double *v, double *r1y, const double *s_dev, const double *c_dev, double *part,
+                       hipStream_t s);
+int stencil_tile_count(int n);
 
 // Host: the tables of A_f on an n x n grid from the element matrices (assemble.hip).
 void stencil_tables(int n, double nu, double rdt, StencilTable<double> &t64, StencilTable<float> &t32);

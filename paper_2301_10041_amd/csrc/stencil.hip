@@ -27,6 +27,12 @@ struct StencilArgs {
   const DivTable<T> *dv;
   const int *cft_rp, *cft_col;
   const T *cft_val, *xlx, *xly;
+  // SP_A11 inside MINRES (ms_s set): with device scalars s = *ms_s, c = *ms_c, write
+  // v = s x and y = s (A11 x) + c r1 over r1 (ms_r1y; r1 read only where c != 0), and the
+  // block's part of v . y to ms_part[tile]
+  const double *ms_s, *ms_c;
+  T *ms_v, *ms_r1y;
+  double *ms_part;
 };
 
 // Tiled kernel.  A block owns kTileR lattice rows x kTileC nodes.  Phase 1 stages x with a
@@ -49,8 +55,22 @@ __device__ __forceinline__ void tile_row_products(const StencilTable<T> &tb, con
   for (int k = 0; k < kStencilCount[CLS]; ++k) {
     const int o = base + so.d[CLS][k][1] * kTW + so.d[CLS][k][0];
     const T y0 = X0[o], y1 = X1[o];
-    s0 += tb.coef[CLS][k][0] * y0 + tb.coef[CLS][k][1] * y1;
-    s1 += tb.coef[CLS][k][2] * y0 + tb.coef[CLS][k][3] * y1;
+    s0 = fma(tb.coef[CLS][k][1], y1, fma(tb.coef[CLS][k][0], y0, s0));
+    s1 = fma(tb.coef[CLS][k][3], y1, fma(tb.coef[CLS][k][2], y0, s1));
+  }
+}
+
+// B^T x_p of a class-CLS node from the staged pressure tile (row width kPW), base = the
+// tile position of P1 node (I >> 1, J >> 1)
+constexpr int kPW = kTileC / 2 + 2, kPH = kTileR / 2 + 2;   // P1 tile with a halo of one
+template <typename T, int CLS>
+__device__ __forceinline__ void tile_bt_products(const DivTable<T> &dv, const T *XP, int base, T &s0, T &s1) {
+  constexpr DivOffsets so = div_offsets();
+#pragma unroll
+  for (int k = 0; k < kBtCount[CLS]; ++k) {
+    const T pv = XP[base + so.bt[CLS][k][1] * kPW + so.bt[CLS][k][0]];
+    s0 = fma(-dv.bt_coef[CLS][k][0], pv, s0);
+    s1 = fma(-dv.bt_coef[CLS][k][1], pv, s1);
   }
 }
 
@@ -63,12 +83,14 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, int tiles, int band) {
   __shared__ T X[2][kTH * kTW];
   __shared__ T S[2][kTileR * kTileC];
+  __shared__ T XP[MODE == SP_A11 ? kPH * kPW : 1];   // SP_A11: x_p tile (column 0 read as 0)
   const int t = (blockIdx.x % kXcd) * band + blockIdx.x / kXcd;
   if (t >= tiles) return;
   const int n2 = 2 * a.n, L = n2 + 1;
   const int I0 = (t % tiles_x) * kTileC, J0 = (t / tiles_x) * kTileR;
   const int tid = threadIdx.x;
   const StencilTable<T> &tb = *a.tab;
+  double ms_acc = 0.0;   // SP_A11 in MINRES: this thread's part of v . y
   // epilogue operands of this thread's nodes (row-major, coalesced), loaded first
   constexpr int EIT = kTileR * kTileC / 256;
   T ex[EIT][2], eb[EIT][2], ed[EIT][2];
@@ -87,6 +109,35 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
       if constexpr (MODE == SP_CHEB) {
         ed[q][0] = a.d[r];
         ed[q][1] = a.d[a.L2 + r];
+      }
+      if constexpr (MODE == SP_A11) {   // in MINRES: r1 (ed holds it)
+        if (a.ms_s) {
+          ed[q][0] = a.ms_r1y[r];
+          ed[q][1] = a.ms_r1y[a.L2 + r];
+        }
+      }
+    }
+  }
+  // SP_A11: the pressure tile (P1 rows J0/2 - 1 .. J0/2 + 2, columns I0/2 - 1 .. I0/2 + 64)
+  // and, for the pressure rows of the tile (threads 0..127), x_p and r1 at the own node
+  T pp_x = 0, pp_r1 = 0;
+  if constexpr (MODE == SP_A11) {
+    const int64_t o2 = 2 * (int64_t)a.L2;
+    for (int e = tid; e < kPH * kPW; e += 256) {
+      const int pi = (I0 >> 1) - 1 + e % kPW, pj = (J0 >> 1) - 1 + e / kPW;
+      T pv = 0;
+      if (pi >= 0 && pj >= 0 && pi <= a.n && pj <= a.n) {
+        const int64_t q = (int64_t)pj * (a.n + 1) + pi;
+        if (q != 0) pv = a.x[o2 + q];
+      }
+      XP[e] = pv;
+    }
+    if (tid < 2 * kWave) {
+      const int pi = (I0 >> 1) + tid % kWave, pj = (J0 >> 1) + tid / kWave;
+      if (pi <= a.n && pj <= a.n) {
+        const int64_t q = (int64_t)pj * (a.n + 1) + pi;
+        pp_x = a.x[o2 + q];
+        if (a.ms_s) pp_r1 = a.ms_r1y[o2 + q];
       }
     }
   }
@@ -126,12 +177,25 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
         T s0 = 0, s1 = 0;
         const int base = (w + 2) * kTW + (i + 2);
         if (I > 0 && I < n2) {
+          // SP_A11: - B^T x_p from the pressure tile; P1 node (I >> 1, J >> 1) sits at
+          // tile row (w >> 1) + 1, column lane + 1 (I0 and J0 are even)
+          const int pbase = ((w >> 1) + 1) * kPW + lane + 1;
           if (J & 1) {
-            if (par) tile_row_products<T, 3>(tb, X[0], X[1], base, s0, s1);
-            else tile_row_products<T, 2>(tb, X[0], X[1], base, s0, s1);
+            if (par) {
+              tile_row_products<T, 3>(tb, X[0], X[1], base, s0, s1);
+              if constexpr (MODE == SP_A11) tile_bt_products<T, 3>(*a.dv, XP, pbase, s0, s1);
+            } else {
+              tile_row_products<T, 2>(tb, X[0], X[1], base, s0, s1);
+              if constexpr (MODE == SP_A11) tile_bt_products<T, 2>(*a.dv, XP, pbase, s0, s1);
+            }
           } else {
-            if (par) tile_row_products<T, 1>(tb, X[0], X[1], base, s0, s1);
-            else tile_row_products<T, 0>(tb, X[0], X[1], base, s0, s1);
+            if (par) {
+              tile_row_products<T, 1>(tb, X[0], X[1], base, s0, s1);
+              if constexpr (MODE == SP_A11) tile_bt_products<T, 1>(*a.dv, XP, pbase, s0, s1);
+            } else {
+              tile_row_products<T, 0>(tb, X[0], X[1], base, s0, s1);
+              if constexpr (MODE == SP_A11) tile_bt_products<T, 0>(*a.dv, XP, pbase, s0, s1);
+            }
           }
         }
         S[0][w * kTileC + i] = s0;
@@ -155,19 +219,7 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
       a.y[r] = s0;
       a.y[a.L2 + r] = s1;
     } else if constexpr (MODE == SP_A11) {
-      T t0 = s0, t1 = s1;
-      if (!bnd) {   // - B^T x_p; column 0 (pinned pressure) is zero
-        const DivTable<T> &dv = *a.dv;
-        const T *xp = a.x + 2 * (int64_t)a.L2;
-        const int cls = (I & 1) | ((J & 1) << 1);
-        const int pi = I >> 1, pj = J >> 1, L1 = a.n + 1;
-        for (int k = 0; k < dv.bt_count[cls]; ++k) {
-          const int pq = (pj + dv.bt_off[cls][k][1]) * L1 + pi + dv.bt_off[cls][k][0];
-          const T pv = pq == 0 ? T(0) : xp[pq];
-          t0 -= dv.bt_coef[cls][k][0] * pv;
-          t1 -= dv.bt_coef[cls][k][1] * pv;
-        }
-      }
+      T t0 = s0, t1 = s1;   // A_f x_u - B^T x_p (identity on Dirichlet rows)
       if (a.cft_rp) {
         for (int k = a.cft_rp[r]; k < a.cft_rp[r + 1]; ++k) {
           const T cv = a.cft_val[k];
@@ -176,8 +228,23 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
           t1 += cv * a.xly[j];
         }
       }
-      a.y[r] = t0;
-      a.y[a.L2 + r] = t1;
+      if (a.ms_s) {
+        const T sc = (T)*a.ms_s, cc = (T)*a.ms_c;
+        T y0 = sc * t0, y1 = sc * t1;
+        if (cc != T(0)) {
+          y0 += cc * ed[q][0];
+          y1 += cc * ed[q][1];
+        }
+        const T v0 = sc * x0, v1 = sc * x1;
+        a.ms_r1y[r] = y0;
+        a.ms_r1y[a.L2 + r] = y1;
+        a.ms_v[r] = v0;
+        a.ms_v[a.L2 + r] = v1;
+        ms_acc += (double)v0 * (double)y0 + (double)v1 * (double)y1;
+      } else {
+        a.y[r] = t0;
+        a.y[a.L2 + r] = t1;
+      }
     } else if constexpr (MODE == SP_RESID) {
       a.y[r] = eb[q][0] - s0;
       a.y[a.L2 + r] = eb[q][1] - s1;
@@ -208,15 +275,39 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
       const int pi = (I0 >> 1) + pc, pj = (J0 >> 1) + pr;
       if (pi <= a.n && pj <= a.n) {
         const DivTable<T> &dv = *a.dv;
+        constexpr StencilOffsets so = stencil_offsets();   // B rows: the vertex pattern
         const int base = (2 * pr + 2) * kTW + (2 * pc + 2);
         T sp = 0;
-        for (int k = 0; k < dv.b_count; ++k) {
-          const int o = base + dv.b_lds[k];
-          sp += dv.b_coef[k][0] * X[0][o] + dv.b_coef[k][1] * X[1][o];
+#pragma unroll
+        for (int k = 0; k < kBMax; ++k) {
+          const int o = base + so.d[0][k][1] * kTW + so.d[0][k][0];
+          sp = fma(dv.b_coef[k][1], X[1][o], fma(dv.b_coef[k][0], X[0][o], sp));
         }
         const int64_t q = (int64_t)pj * (a.n + 1) + pi;
         const int64_t o2 = 2 * (int64_t)a.L2;
-        a.y[o2 + q] = q == 0 ? a.x[o2] : -sp;
+        const T val = q == 0 ? pp_x : -sp;
+        if (a.ms_s) {
+          const T sc = (T)*a.ms_s, cc = (T)*a.ms_c;
+          T yv = sc * val;
+          if (cc != T(0)) yv += cc * pp_r1;
+          const T vv = sc * pp_x;
+          a.ms_r1y[o2 + q] = yv;
+          a.ms_v[o2 + q] = vv;
+          ms_acc += (double)vv * (double)yv;
+        } else {
+          a.y[o2 + q] = val;
+        }
+      }
+    }
+    if (a.ms_s) {   // the block's part of v . y (fixed order: deterministic)
+      __shared__ double red[256 / kWave];
+      const double wsum = wave_sum(ms_acc);
+      if (tid % kWave == 0) red[tid / kWave] = wsum;
+      __syncthreads();
+      if (tid == 0) {
+        double b = 0.0;
+        for (int k = 0; k < 256 / kWave; ++k) b += red[k];
+        a.ms_part[t] = b;
       }
     }
   }
@@ -237,7 +328,7 @@ void stencil_launch(int n, const StencilTable<T> *tab, const T *x, const T *b, T
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
   static_assert(kTileR * kWave == 256 && 2 * kWave == kTileC, "one tile row per wave, two nodes per lane");
   StencilArgs<T> a{n, tab, x, b, d, y, (2 * n + 1) * (2 * n + 1), c1, c2, nullptr, nullptr, nullptr,
-                   nullptr, nullptr, nullptr};
+                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   launch_tiles<T, MODE>(n, a, s);
 }
 
@@ -250,8 +341,25 @@ void stencil_fluid_rows(int n, const StencilTable<T> *tab, const DivTable<T> *dv
                 "a tile holds 2 x 64 P1 nodes, one per thread of the first two waves");
   const int L = 2 * n + 1, L2 = L * L;
   StencilArgs<T> a{n, tab, x, nullptr, nullptr, y, L2, T(0), T(0), dv, cft_rp, cft_col, cft_val, xl,
-                   xl ? xl + Ns : nullptr};
+                   xl ? xl + Ns : nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   launch_tiles<T, SP_A11>(n, a, s);
+}
+
+int stencil_a11_minres(int n, const StencilTable<double> *tab, const DivTable<double> *dv, const double *x,
+                       double *v, double *r1y, const double *s_dev, const double *c_dev, double *part,
+                       hipStream_t s) {
+  FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
+  const int L = 2 * n + 1, L2 = L * L;
+  StencilArgs<double> a{n, tab, x, nullptr, nullptr, nullptr, L2, 0.0, 0.0, dv, nullptr, nullptr, nullptr, nullptr,
+                        nullptr, s_dev, c_dev, v, r1y, part};
+  launch_tiles<double, SP_A11>(n, a, s);
+  const int tx = (L + kTileC - 1) / kTileC, ty = (L + kTileR - 1) / kTileR;
+  return tx * ty;
+}
+
+int stencil_tile_count(int n) {
+  const int L = 2 * n + 1;
+  return ((L + kTileC - 1) / kTileC) * ((L + kTileR - 1) / kTileR);
 }
 template void stencil_fluid_rows<double>(int, const StencilTable<double> *, const DivTable<double> *,
                                          const double *, double *, const int *, const int *, const double *,
@@ -307,11 +415,11 @@ __device__ __forceinline__ void split_products(const StencilTable<T> &tb, const 
     const int off = (((PAR + dI) & 1) * ROWS + dJ) * HW + ((PAR + dI) >> 1);
     const T c0 = tb.coef[CLS][k][0], c1 = tb.coef[CLS][k][1], c2 = tb.coef[CLS][k][2], c3 = tb.coef[CLS][k][3];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
+    for (int q = 0; q < NR; ++q) {   // FMA chains: two FMAs per coefficient pair
       const int o = row[q] * HW + h + off;
       const T y0 = X[o], y1 = X[COMP + o];
-      s[q][0] += c0 * y0 + c1 * y1;
-      s[q][1] += c2 * y0 + c3 * y1;
+      s[q][0] = fma(c1, y1, fma(c0, y0, s[q][0]));
+      s[q][1] = fma(c3, y1, fma(c2, y0, s[q][1]));
     }
   }
 }
