@@ -35,6 +35,24 @@ struct P2RestrTable {
   T w[4][kRestrMax];
 };
 
+// The fine-node offsets of the restriction classes in table order (dJ, then dI); they
+// follow from the nested triangulation alone (the table builder checks them).  Kernels
+// index them with compile-time class and entry.
+constexpr int kRestrCount[4] = {25, 9, 9, 9};
+struct RestrOffsets {
+  int d[4][25][2];
+};
+__host__ __device__ constexpr RestrOffsets restrict_offsets() {
+  return RestrOffsets{{
+      {{-3, -3}, {-2, -3}, {-1, -3}, {0, -3}, {-3, -2}, {1, -2}, {-3, -1}, {-1, -1}, {0, -1},
+       {2, -1}, {-3, 0}, {-1, 0}, {0, 0}, {1, 0}, {3, 0}, {-2, 1}, {0, 1}, {1, 1},
+       {3, 1}, {-1, 2}, {3, 2}, {0, 3}, {1, 3}, {2, 3}, {3, 3}},
+      {{-1, -2}, {-1, -1}, {0, -1}, {-1, 0}, {0, 0}, {1, 0}, {0, 1}, {1, 1}, {1, 2}},
+      {{-2, -1}, {-1, -1}, {0, -1}, {-1, 0}, {0, 0}, {1, 0}, {0, 1}, {1, 1}, {2, 1}},
+      {{-1, -1}, {0, -1}, {1, -1}, {-1, 0}, {0, 0}, {1, 0}, {-1, 1}, {0, 1}, {1, 1}},
+  }};
+}
+
 // Lattice offsets (units h/2 from the cell's lower-left node) of the six P2 nodes of
 // triangle t of a cell: T0 = (v00, v10, v11), T1 = (v00, v11, v01); vertices a, b, c
 // then edge midpoints ab, bc, ca.

@@ -150,26 +150,47 @@ void p2_prolong_add(int nf, const T *xc, T *y, hipStream_t s) {
   FSI_CHECK_LAUNCH();
 }
 
-// bc = R r = P^T r over the interior fine nodes; Dirichlet coarse rows are zero.
+// bc = R r = P^T r over the interior fine nodes; Dirichlet coarse rows are zero.  A block
+// owns 256 coarse nodes of one coarse row: waves 0-1 the even columns, waves 2-3 the odd
+// ones, so the node class is uniform over a wave (scalar weight loads, compile-time offsets).
+template <typename T, int CLS>
+__device__ __forceinline__ void restrict_sum(const P2RestrTable<T> &tb, const T *r, int64_t Nf, int L, int nf,
+                                             int I, int J, T &s0, T &s1) {
+  constexpr RestrOffsets ro = restrict_offsets();
+  s0 = 0;
+  s1 = 0;
+#pragma unroll
+  for (int k = 0; k < kRestrCount[CLS]; ++k) {
+    const int I2 = I + ro.d[CLS][k][0], J2 = J + ro.d[CLS][k][1];
+    if (I2 > 0 && J2 > 0 && I2 < 2 * nf && J2 < 2 * nf) {
+      const int64_t f = (int64_t)J2 * L + I2;
+      const T w = tb.w[CLS][k];
+      s0 = fma(w, r[f], s0);
+      s1 = fma(w, r[Nf + f], s1);
+    }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_p2_restrict(int nf, const P2RestrTable<T> *__restrict__ tabp,
-                                                     const T *__restrict__ r, T *bc) {
+                                                     const T *__restrict__ r, T *bc, int segs) {
   const int L = 2 * nf + 1, nc = nf / 2, Lc = 2 * nc + 1;
   const int64_t Nf = (int64_t)L * L, Nc = (int64_t)Lc * Lc;
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= Nc) return;
-  const int Ic = (int)(q % Lc), Jc = (int)(q / Lc);
+  const int Jc = blockIdx.x / segs, seg = blockIdx.x % segs;
+  const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 128);
+  const int Ic = seg * 256 + 2 * ((int)threadIdx.x % 128) + half;
+  if (Ic >= Lc) return;
+  const int64_t q = (int64_t)Jc * Lc + Ic;
   T s0 = 0, s1 = 0;
   if (!on_p2_boundary(Ic, Jc, nc)) {
-    const int cls = (Ic & 1) | ((Jc & 1) << 1);
     const P2RestrTable<T> &tb = *tabp;
-    const int cnt = tb.count[cls];
-    for (int k = 0; k < cnt; ++k) {
-      const int I = 2 * Ic + tb.off[cls][k][0], J = 2 * Jc + tb.off[cls][k][1];
-      if (I <= 0 || J <= 0 || I >= 2 * nf || J >= 2 * nf) continue;
-      const int64_t f = (int64_t)J * L + I;
-      s0 += tb.w[cls][k] * r[f];
-      s1 += tb.w[cls][k] * r[Nf + f];
+    const int I = 2 * Ic, J = 2 * Jc;
+    if (Jc & 1) {
+      if (half) restrict_sum<T, 3>(tb, r, Nf, L, nf, I, J, s0, s1);
+      else restrict_sum<T, 2>(tb, r, Nf, L, nf, I, J, s0, s1);
+    } else {
+      if (half) restrict_sum<T, 1>(tb, r, Nf, L, nf, I, J, s0, s1);
+      else restrict_sum<T, 0>(tb, r, Nf, L, nf, I, J, s0, s1);
     }
   }
   bc[q] = s0;
@@ -178,9 +199,9 @@ __global__ void __launch_bounds__(256) k_p2_restrict(int nf, const P2RestrTable<
 
 template <typename T>
 void p2_restrict(int nf, const P2RestrTable<T> *tab, const T *r, T *bc, hipStream_t s) {
-  const int nc = nf / 2;
-  const int64_t nodes = (int64_t)(2 * nc + 1) * (2 * nc + 1);
-  hipLaunchKernelGGL(k_p2_restrict<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, nf, tab, r, bc);
+  const int Lc = nf + 1;
+  const int segs = (Lc + 255) / 256;
+  hipLaunchKernelGGL(k_p2_restrict<T>, dim3((unsigned)(Lc * segs)), dim3(256), 0, s, nf, tab, r, bc, segs);
   FSI_CHECK_LAUNCH();
 }
 
@@ -209,6 +230,11 @@ void p2_restrict_tables(P2RestrTable<double> &t64, P2RestrTable<float> &t32) {
           }
       }
     t64.count[cls] = t32.count[cls] = cnt;
+    constexpr RestrOffsets ro = restrict_offsets();
+    FSI_REQUIRE(cnt == kRestrCount[cls], FSI_E_ARG, "unexpected restriction width");
+    for (int k = 0; k < cnt; ++k)
+      FSI_REQUIRE(t64.off[cls][k][0] == ro.d[cls][k][0] && t64.off[cls][k][1] == ro.d[cls][k][1], FSI_E_ARG,
+                  "restriction offsets differ from the compiled pattern");
   }
 }
 
