@@ -441,8 +441,9 @@ enum { C2_PRE = 0, C2_POST = 1 };
 template <typename T, int M>
 __global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int tiles, int band) {
   constexpr int HW0 = kC2W0 / 2, HW1 = kC2W1 / 2;   // plane widths
+  static_assert(kC2H1 * HW1 <= kC2H0 * HW0, "the first-step tile fits in the staged x");
   __shared__ T X0[2 * 2 * kC2H0 * HW0];             // [component][parity][row][column / 2]
-  __shared__ T X1[2 * 2 * kC2H1 * HW1];
+  T *const X1 = X0;   // the first-step tile replaces x once every wave has read it
   const int t = (blockIdx.x % kXcd) * band + blockIdx.x / kXcd;
   if (t >= tiles) return;
   const int n2 = 2 * a.n, L = n2 + 1;
@@ -518,6 +519,7 @@ __global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int 
   // phase B: first stencil step on the tile plus a halo of 2; the wave's two rows have the
   // same parity, so one pass per column parity covers both with one set of coefficients
   T d1[2][2] = {{0, 0}, {0, 0}};   // tile row
+  T x1v[2][2][2];                  // first-step values of the wave's two rows
   const int jodd = __builtin_amdgcn_readfirstlane((J0 - 2 + rows[1]) & 1);
 #pragma unroll
   for (int par = 0; par < 2; ++par) {
@@ -531,7 +533,9 @@ __global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int 
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int row = rows[q], J = J0 - 2 + row;
-      T x10 = 0, x11 = 0;
+      T &x10 = x1v[q][par][0], &x11 = x1v[q][par][1];
+      x10 = 0;
+      x11 = 0;
       if (inside(I, J)) {
         const int c0 = (par * kC2H0 + row + 2) * HW0 + lane + 1;
         const T x00 = X0[c0], x01 = X0[2 * kC2H0 * HW0 + c0];
@@ -552,11 +556,17 @@ __global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int 
           d1[par][1] = e1;
         }
       }
-      const int o1 = (par * kC2H1 + row) * HW1 + lane;   // column i = 2 lane + par
-      X1[o1] = x10;
-      X1[2 * kC2H1 * HW1 + o1] = x11;
     }
   }
+  __syncthreads();   // every wave has read x: the first-step tile goes over it
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const int o1 = (par * kC2H1 + rows[q]) * HW1 + lane;   // column i = 2 lane + par
+      X1[o1] = x1v[q][par][0];
+      X1[2 * kC2H1 * HW1 + o1] = x1v[q][par][1];
+    }
   __syncthreads();
   // phase C: second step on the tile row
   {
