@@ -239,16 +239,18 @@ int fsi_set_smoother(fsi_ctx *ctx, int kind);
  * same as without it. */
 int fsi_set_graphs(fsi_ctx *ctx, int enable);
 
-/* Measurement of the dominant kernel: the finest-level Chebyshev smoothing product on A_f
- * (2x2 blocks; d = c1 d + c2 D^{-1}(b - A_f x), y = x + d), which carries most of the
- * bytes of a step.  fsi_profile(ctx, 1) starts (and resets) timing every such launch with
- * a pair of HIP events on the context's stream; fsi_profile(ctx, 0) stops.
- * fsi_profile_read synchronises and returns, for precision prec, the number of timed
- * launches, their summed duration in milliseconds and the algorithmic bytes one launch
- * must move, with w = 8 (FP64) or 4 (FP32) bytes: stencil form 10 w N2 (x, b, d read, d
- * and y written, two components each); CSR form nnz (4 w + 4) + N2 (4 + 14 w) + 4 (values
- * and column indices once; per node the row pointer, x, b, d read and written, the
- * inverse 2x2 diagonal block and y). */
+/* Measurement of the dominant kernel, the finest-level Chebyshev smoothing on A_f
+ * (d = c1 d + c2 D^{-1}(b - A_f x), y = x + d on the 2x2-block system): with the
+ * structured-grid products (default) the launch that takes the first two post-smoothing
+ * steps at once (temporal blocking); with FSI_SMOOTH_CSR every single-step launch.
+ * fsi_profile(ctx, 1) starts (and resets) timing every such launch with a pair of HIP
+ * events on the context's stream; fsi_profile(ctx, 0) stops.  fsi_profile_read
+ * synchronises and returns, for precision prec, the number of timed launches, their summed
+ * duration in milliseconds and the algorithmic bytes one launch must move, with w = 8
+ * (FP64) or 4 (FP32) bytes: structured form 8 w N2 (x and b read, d and y written, two
+ * components each: the first step has c1 = 0 and reads no d); CSR form
+ * nnz (4 w + 4) + N2 (4 + 14 w) + 4 (values and column indices once; per node the row
+ * pointer, x, b, d read and written, the inverse 2x2 diagonal block and y). */
 int fsi_profile(fsi_ctx *ctx, int enable);
 int fsi_profile_read(fsi_ctx *ctx, int prec, int64_t *launches, double *total_ms,
                      double *bytes_per_launch);

@@ -423,7 +423,7 @@ int fsi_profile_read(fsi_ctx *ctx, int prec, int64_t *launches, double *total_ms
     if (total_ms) *total_ms = t;
     if (bytes_per_launch)
       *bytes_per_launch = c.mgu.stencil
-                              ? (double)L.nodes * 10 * w
+                              ? (double)L.nodes * 8 * w
                               : (double)L.A.nnz * (4 * w + 4) + (double)L.nodes * (4 + 14 * w) + 4.0;
   });
 }

@@ -219,7 +219,8 @@ static T *chebyshev_mf(First first, Step step, double lmin, double lmax, int ste
 // Chebyshev on A_f (stencil) with right-hand side b and direction buffer d: the first three
 // steps from zero (pre-smoothing) or the first two from x (post-smoothing) as one
 // temporally blocked launch, further steps one launch each (same recurrence as
-// chebyshev_mf; the profile brackets the single-step launches).
+// chebyshev_mf; the profile brackets the two-step post-smoothing launches, the largest
+// single kernel of a step).
 template <typename T>
 static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, double lmax, int steps,
                             const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s, Prof *prof) {
@@ -242,25 +243,23 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
   } else if (!zero_init && steps >= 2) {
     T c1b, c2b;
     next(c1b, c2b);
+    if (prof) prof->begin(s);
     cheb2_post<T>(n, tab, x, b, d, x2, (T)(1.0 / theta), c1b, c2b, s);
+    if (prof) prof->end(s);
     std::swap(x, x2);
     done = 2;
   } else if (zero_init) {
     p2_first<T>(n, tab, b, (T)(1.0 / theta), d, x, s);
     done = 1;
   } else {
-    if (prof) prof->begin(s);
     stencil_launch<T, SP_CHEB>(n, tab, x, b, d, x2, (T)0, (T)(1.0 / theta), s);
-    if (prof) prof->end(s);
     std::swap(x, x2);
     done = 1;
   }
   for (int k = done; k < steps; ++k) {
     T c1, c2;
     next(c1, c2);
-    if (prof) prof->begin(s);
     stencil_launch<T, SP_CHEB>(n, tab, x, b, d, x2, c1, c2, s);
-    if (prof) prof->end(s);
     std::swap(x, x2);
   }
   return x;
