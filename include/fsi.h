@@ -220,6 +220,32 @@ int fsi_export_pairs(fsi_ctx *ctx, int32_t *E, int32_t *T, int64_t cap, int64_t 
 int fsi_export_csr(fsi_ctx *ctx, int block, int64_t *nrows, int64_t *nnz, int32_t *width,
                    int32_t *rowptr, int32_t *col, double *val);
 
+/* Test export, host only (no context, no device): the coefficient tables of the
+ * matrix-free products on an n x n grid (fsi_set_smoother), built as the library builds
+ * them, so tests can compare them with independently assembled matrices.  rdt = rho / dt
+ * (FSI_LAT_AF only), nu the viscosity (FSI_LAT_AF only).  Output, row-major over
+ * (class, entry) with FSI_LAT_MAX_ENTRIES entries per class and unused entries zero:
+ * counts[9] entries per class; offs[9 * 81 * 2] lattice offsets (dI, dJ); vals[9 * 81 * 4].
+ *   FSI_LAT_AF: A_f = (rho/dt) M_f + K_f at interior P2 nodes, classes by parity
+ *               (bit 0: I odd, bit 1: J odd); offsets in P2 lattice units; vals = the 2x2
+ *               block (xx, xy, yx, yy).
+ *   FSI_LAT_LP, FSI_LAT_MP: P1 Laplacian with node 0 pinned (identity row, zero column) and
+ *               P1 mass; classes 3 cj + ci by position (0: first, 1: interior, 2: last index);
+ *               7 entries each at offsets (0,0), (-1,0), (1,0), (0,-1), (0,1), (-1,-1), (1,1);
+ *               vals[.][0] = coefficient (zero where the neighbour is outside the lattice).
+ *   FSI_LAT_BT: rows of B^T (Dirichlet BC, pin) at interior P2 nodes by parity class;
+ *               offsets of P1 nodes from (I >> 1, J >> 1); vals = (B_x, B_y).
+ *   FSI_LAT_B:  the B row of a P1 node (i, j) (class 0 only); offsets of P2 nodes from
+ *               (2i, 2j); vals = (B_x, B_y); Dirichlet columns are applied by the caller.
+ *   FSI_LAT_R:  P2 restriction R = P^T at interior coarse nodes by parity class; offsets of
+ *               fine nodes from (2 Ic, 2 Jc) in fine lattice units; vals[.][0] = weight.
+ * Errors: FSI_E_ARG (n outside [2, 4096], unknown table, null buffer). */
+enum fsi_lattice_table { FSI_LAT_AF = 0, FSI_LAT_LP = 1, FSI_LAT_MP = 2, FSI_LAT_BT = 3, FSI_LAT_B = 4,
+                         FSI_LAT_R = 5 };
+#define FSI_LAT_MAX_ENTRIES 81
+int fsi_export_lattice(int32_t n, double nu, double rdt, int32_t table, int32_t *counts, int32_t *offs,
+                       double *vals);
+
 /* Products inside the A11 preconditioner (both multigrid hierarchies and the pressure
  * mass solve): FSI_SMOOTH_STENCIL (default) applies them matrix-free on the structured
  * grid: A_f from four translation-invariant 2x2-block stencils (boundary rows identity,

@@ -1,9 +1,12 @@
+#include <algorithm>
 // extern "C" entry points of libfsi (declared in include/fsi.h).  Every call catches
 // the library's exceptions and returns an fsi_status; the message is kept in the context.
 #include <chrono>
 #include <cstring>
 
 #include "ctx.h"
+#include "lattice.h"
+#include "stencil.h"
 #include "kernels.h"
 
 struct fsi_ctx {
@@ -363,6 +366,92 @@ int fsi_export_pairs(fsi_ctx *ctx, int32_t *E, int32_t *T, int64_t cap, int64_t 
     if (m > 0 && E) FSI_HIP(hipMemcpyAsync(E, c.pair_E.p, m * 4, hipMemcpyDeviceToHost, c.stream));
     if (m > 0 && T) FSI_HIP(hipMemcpyAsync(T, c.pair_T.p, m * 4, hipMemcpyDeviceToHost, c.stream));
     FSI_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+int fsi_export_lattice(int32_t n, double nu, double rdt, int32_t table, int32_t *counts, int32_t *offs,
+                       double *vals) {
+  if (!counts || !offs || !vals) return FSI_E_ARG;
+  return guarded(nullptr, [&] {
+    FSI_REQUIRE(n >= 2 && n <= 4096, FSI_E_ARG, "n must be in [2, 4096]");
+    constexpr int E = FSI_LAT_MAX_ENTRIES;
+    std::fill(counts, counts + 9, 0);
+    std::fill(offs, offs + 9 * E * 2, 0);
+    std::fill(vals, vals + 9 * E * 4, 0.0);
+    switch (table) {
+      case FSI_LAT_AF: {
+        fsi::StencilTable<double> t;
+        fsi::StencilTable<float> tf;
+        fsi::stencil_tables(n, nu, rdt, t, tf);
+        for (int c = 0; c < 4; ++c) {
+          counts[c] = t.count[c];
+          for (int k = 0; k < t.count[c]; ++k) {
+            offs[(c * E + k) * 2] = t.off[c][k][0];
+            offs[(c * E + k) * 2 + 1] = t.off[c][k][1];
+            for (int q = 0; q < 4; ++q) vals[(c * E + k) * 4 + q] = t.coef[c][k][q];
+          }
+        }
+        break;
+      }
+      case FSI_LAT_LP:
+      case FSI_LAT_MP: {
+        fsi::P1Table<double> t;
+        fsi::P1Table<float> tf;
+        fsi::p1_tables(n, table == FSI_LAT_LP ? fsi::kTableLp : fsi::kTableMp, table == FSI_LAT_LP ? 1 : 0, t, tf);
+        static const int nb[fsi::kP1Nbr][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {1, 1}};
+        for (int c = 0; c < 9; ++c) {
+          counts[c] = fsi::kP1Nbr;
+          for (int k = 0; k < fsi::kP1Nbr; ++k) {
+            offs[(c * E + k) * 2] = nb[k][0];
+            offs[(c * E + k) * 2 + 1] = nb[k][1];
+            vals[(c * E + k) * 4] = t.coef[c][k];
+          }
+        }
+        break;
+      }
+      case FSI_LAT_BT:
+      case FSI_LAT_B: {
+        fsi::DivTable<double> t;
+        fsi::DivTable<float> tf;
+        fsi::div_tables(n, t, tf);
+        if (table == FSI_LAT_BT) {
+          for (int c = 0; c < 4; ++c) {
+            counts[c] = t.bt_count[c];
+            for (int k = 0; k < t.bt_count[c]; ++k) {
+              offs[(c * E + k) * 2] = t.bt_off[c][k][0];
+              offs[(c * E + k) * 2 + 1] = t.bt_off[c][k][1];
+              vals[(c * E + k) * 4] = t.bt_coef[c][k][0];
+              vals[(c * E + k) * 4 + 1] = t.bt_coef[c][k][1];
+            }
+          }
+        } else {
+          counts[0] = t.b_count;
+          for (int k = 0; k < t.b_count; ++k) {
+            offs[k * 2] = t.b_off[k][0];
+            offs[k * 2 + 1] = t.b_off[k][1];
+            vals[k * 4] = t.b_coef[k][0];
+            vals[k * 4 + 1] = t.b_coef[k][1];
+          }
+        }
+        break;
+      }
+      case FSI_LAT_R: {
+        fsi::P2RestrTable<double> t;
+        fsi::P2RestrTable<float> tf;
+        fsi::p2_restrict_tables(t, tf);
+        for (int c = 0; c < 4; ++c) {
+          counts[c] = t.count[c];
+          for (int k = 0; k < t.count[c]; ++k) {
+            offs[(c * E + k) * 2] = t.off[c][k][0];
+            offs[(c * E + k) * 2 + 1] = t.off[c][k][1];
+            vals[(c * E + k) * 4] = t.w[c][k];
+          }
+        }
+        break;
+      }
+      default:
+        throw Error(FSI_E_ARG, "unknown table id");
+    }
   });
 }
 

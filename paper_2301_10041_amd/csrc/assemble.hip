@@ -33,6 +33,7 @@ static const double kDunW[2] = {0.223381589678011, 0.109951743655322};
 
 // Layout of one element type in the device table.
 constexpr int EM_M = 0, EM_K = 36, EM_B = 180, EM_MP = 216, EM_LP = 225, EM_SIZE = 234;
+static_assert(EM_MP == kTableMp && EM_LP == kTableLp, "P1 table ids are the element-table offsets");
 
 // Lattice offsets of the six P2 nodes (a, b, c, ab, bc, ca) of the two triangles of a
 // cell, in units of h/2 from the cell's lower-left node (2i, 2j).

@@ -39,6 +39,7 @@ struct Mg {
   int comps = 1;           // unknowns per node: 2 (velocity, 2x2 blocks) or 1 (pressure)
   bool stencil = false;    // smoothing, residuals and transfers matrix-free (structured grid)
   int degree = 3;          // Chebyshev smoothing steps before and after the coarse correction
+  int degree32 = 3;        // the same for the FP32 V-cycle of the mixed-precision form
   std::vector<MgLevel> lv; // lv[0] finest
   int64_t ncoarse = 0;     // unknowns of the coarsest level
   DevBuf<double> cinv;     // dense inverse of the coarsest operator (row major)

@@ -101,7 +101,8 @@ __host__ __device__ inline int p2_prolong_weights(int I, int J, int nf, int *Ic,
   return cnt;
 }
 
-// Host table builders
+// Host table builders (which: kTableMp = pressure mass, kTableLp = pressure Laplacian)
+constexpr int kTableMp = 216, kTableLp = 225;   // offsets of the P1 blocks in the element tables
 void p1_tables(int n, int which, int pin, P1Table<double> &t64, P1Table<float> &t32);   // assemble.hip
 void p2_restrict_tables(P2RestrTable<double> &t64, P2RestrTable<float> &t32);          // lattice.hip
 

@@ -303,6 +303,7 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr)
     return x;
   }
   const double lmax = L.lmax, lmin = L.lmax / 30.0;
+  const int degree = std::is_same<T, float>::value ? mg.degree32 : mg.degree;
   const T *dinv = Pr<T>::dinv(L);
   const T *val = Pr<T>::val(L.A);
   Prof *pl = (l == 0) ? prof : nullptr;
@@ -311,9 +312,9 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr)
   if (mg.stencil) {   // matrix-free smoothing, residual and transfers
     auto smooth = [&](T *x0, T *x1, bool zero) -> T * {
       if constexpr (W == 4)
-        return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, mg.degree, b, x0, x1, d, zero, s, pl);
+        return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, pl);
       else
-        return chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, mg.degree, b, x0, x1, d, zero, s);
+        return chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s);
     };
     T *xs = smooth(x, x2, true);
     T *xo = (xs == x) ? x2 : x;
@@ -331,7 +332,7 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr)
       p1_prolong_add<T>(L.n, xc, xs, s);
     return smooth(xs, xo, false);
   }
-  T *xs = chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, mg.degree, b, x,
+  T *xs = chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b, x,
                               x2, d, true, s, pl);
   T *xo = (xs == x) ? x2 : x;
   spmv<T, W, NC, SP_RESID>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, xs, L.nodes, r, L.nodes, s, b);
@@ -340,7 +341,7 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr)
   T *xc = vcycle<T, W, NC>(mg, l + 1, bc, s);
   spmv<T, 1, NC, SP_ADD>(L.P.nrows, L.P.rowptr.p, L.P.col.p, Pr<T>::val(L.P), xc, C.nodes, xs,
                          L.nodes, s);
-  return chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, mg.degree, b,
+  return chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b,
                              xs, xo, d, false, s, pl);
 }
 

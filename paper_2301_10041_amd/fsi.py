@@ -94,6 +94,8 @@ _SIGS = {
                                    C.POINTER(C.c_int64)]),
     "fsi_export_csr": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsi_export_lattice": (C.c_int, [C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
     "fsi_profile": (C.c_int, [C.c_void_p, C.c_int]),
     "fsi_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)]),
@@ -132,6 +134,24 @@ def _stream_handle(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return C.c_void_p(stream.cuda_stream)
+
+
+LAT_AF, LAT_LP, LAT_MP, LAT_BT, LAT_B, LAT_R = 0, 1, 2, 3, 4, 5
+LAT_MAX_ENTRIES = 81
+
+
+def export_lattice(n, table, nu=1.0, rdt=0.0):
+    """Host-only export of a matrix-free coefficient table (see fsi_export_lattice):
+    returns (counts[9], offs[9, 81, 2], vals[9, 81, 4]) as numpy arrays."""
+    import numpy as np
+    counts = np.zeros(9, dtype=np.int32)
+    offs = np.zeros((9, LAT_MAX_ENTRIES, 2), dtype=np.int32)
+    vals = np.zeros((9, LAT_MAX_ENTRIES, 4), dtype=np.float64)
+    rc = lib().fsi_export_lattice(int(n), float(nu), float(rdt), int(table), counts.ctypes.data_as(C.c_void_p),
+                                  offs.ctypes.data_as(C.c_void_p), vals.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise FsiError(rc, lib().fsi_strerror(rc).decode())
+    return counts, offs, vals
 
 
 def footprint(n, n_nodes, n_tris, nu=1.0, rho=1.0, dt=0.01):
