@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512)
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run 3 plain device copies of 2 GiB (counter calibration)")

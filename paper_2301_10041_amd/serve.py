@@ -62,7 +62,7 @@ class Slot:
 
 
 class Server:
-    def __init__(self, hbm_budget=None, max_slots=8, prec=fsi.FP32, pc=fsi.PC_TRI, rtol=1e-8,
+    def __init__(self, hbm_budget=None, max_slots=16, prec=fsi.FP32, pc=fsi.PC_TRI, rtol=1e-8,
                  keep_states=False):
         import torch
         self.torch = torch
