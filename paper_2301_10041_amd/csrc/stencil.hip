@@ -8,6 +8,8 @@
 //
 // Bytes per node in the Chebyshev step: x, b, d read, d and y written (5 two-component
 // vectors); no matrix and no indices.
+#include <type_traits>
+
 #include "ctx.h"
 #include "kernels.h"
 #include "stencil.h"
@@ -381,9 +383,9 @@ template void stencil_fluid_rows<float>(int, const StencilTable<float> *, const 
 //            the start of the post-smoothing; reads x and b, writes y and d.
 // Bytes per node: C2_PRE 6 w for three steps, C2_POST 8 w for two (w = value size,
 // two components).
-constexpr int kC2W = 124, kC2R = 4;                 // output tile (kC2W + 4 = 2 x 64 lanes)
-constexpr int kC2W0 = kC2W + 8, kC2H0 = kC2R + 8;   // x with a halo of 4
-constexpr int kC2W1 = kC2W + 4, kC2H1 = kC2R + 4;   // first step with a halo of 2
+constexpr int kC2W = 124, kC2R = 8;                 // output tile (kC2W + 4 = 2 x 64 lanes)
+constexpr int kC2W0 = kC2W + 8;                     // width of x with a halo of 4
+constexpr int kC2W1 = kC2W + 4;                     // width of the first step (halo of 2)
 static_assert(kC2W1 == 2 * kWave && kC2W0 == kTW, "lane layout and LDS offsets of the tables");
 
 template <typename T>
@@ -434,12 +436,16 @@ __device__ __forceinline__ void class_products(const StencilTable<T> &tb, int jo
 
 enum { C2_PRE = 0, C2_POST = 1 };
 
-// Wave w owns region-1 rows w + 2 (tile row w) and one halo row (0, 1, 6 or 7); its lanes
-// hold the nodes i = 2 lane + par of those rows (region-1 column i = tile column i - 2), so
-// the tile row's b and first-step direction stay in registers for the second step.  All b
-// loads are issued before x is staged.
-template <typename T, int M>
-__global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int tiles, int band) {
+// A block of 64 RR threads owns a tile of RR rows.  Wave w owns region-1 row w + 2 (tile
+// row w) and, for w < 4, one halo row (0, 1, RR + 2 or RR + 3) of the same parity; its
+// lanes hold the nodes i = 2 lane + par of those rows (region-1 column i = tile column
+// i - 2), so the tile row's b and first-step direction stay in registers for the second
+// step.  All b loads are issued before x is staged.
+template <typename T, int M, int RR>
+__global__ void __launch_bounds__(64 * RR, 4) k_cheb2(Cheb2Args<T> a, int tiles_x, int tiles, int band) {
+  constexpr int NT = 64 * RR;                       // threads
+  constexpr int kC2H0 = RR + 8, kC2H1 = RR + 4;     // rows of the staged x and the first step
+  static_assert(RR >= 4 && RR % 2 == 0, "four halo rows go to the first four waves");
   constexpr int HW0 = kC2W0 / 2, HW1 = kC2W1 / 2;   // plane widths
   static_assert(kC2H1 * HW1 <= kC2H0 * HW0, "the first-step tile fits in the staged x");
   __shared__ T X0[2 * 2 * kC2H0 * HW0];             // [component][parity][row][column / 2]
@@ -448,10 +454,11 @@ __global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int 
   if (t >= tiles) return;
   const int n2 = 2 * a.n, L = n2 + 1;
   const int64_t N = a.L2;
-  const int I0 = (t % tiles_x) * kC2W, J0 = (t / tiles_x) * kC2R;
+  const int I0 = (t % tiles_x) * kC2W, J0 = (t / tiles_x) * RR;
   const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
   const StencilTable<T> &tb = *a.tab;
-  const int rows[2] = {w < 2 ? w : w + 4, w + 2};   // halo row, tile row (region-1 rows)
+  const bool halo = w < 4;                          // wave-uniform
+  const int rows[2] = {w < 2 ? w : RR + w, w + 2};  // halo row (w < 4), tile row (region-1 rows)
   auto inside = [&](int I, int J) { return I > 0 && J > 0 && I < n2 && J < n2; };
   // b at the wave's region-1 nodes (0 outside the lattice)
   T bv[2][2][2];
@@ -463,7 +470,7 @@ __global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int 
       const int I = I0 - 2 + 2 * lane + par;
       bv[q][par][0] = 0;
       bv[q][par][1] = 0;
-      if (I >= 0 && J >= 0 && I <= n2 && J <= n2) {
+      if ((q == 1 || halo) && I >= 0 && J >= 0 && I <= n2 && J <= n2) {
         const int64_t r = (int64_t)J * L + I;
         bv[q][par][0] = a.b[r];
         bv[q][par][1] = a.b[N + r];
@@ -472,11 +479,11 @@ __global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int 
   }
   // phase A: x (or, from zero, the first step s D^{-1} b) with a halo of 4; all loads are
   // issued before the first LDS store
-  constexpr int NE = kC2H0 * kC2W0, IT = (NE + 255) / 256;
+  constexpr int NE = kC2H0 * kC2W0, IT = (NE + NT - 1) / NT;
   T v[IT][2];
 #pragma unroll
   for (int q = 0; q < IT; ++q) {
-    const int e = tid + 256 * q, tr = e / kC2W0, tc = e % kC2W0;
+    const int e = tid + NT * q, tr = e / kC2W0, tc = e % kC2W0;
     const int I = I0 - 4 + tc, J = J0 - 4 + tr;
     v[q][0] = 0;
     v[q][1] = 0;
@@ -495,7 +502,7 @@ __global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int 
       for (int k = 0; k < 4; ++k) dv[c][k] = tb.dinv[c][k];
 #pragma unroll
     for (int q = 0; q < IT; ++q) {
-      const int e = tid + 256 * q, tr = e / kC2W0, tc = e % kC2W0;
+      const int e = tid + NT * q, tr = e / kC2W0, tc = e % kC2W0;
       const int c = (tc & 1) | ((tr & 1) << 1);
       T di[4];
 #pragma unroll
@@ -508,7 +515,7 @@ __global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int 
   }
 #pragma unroll
   for (int q = 0; q < IT; ++q) {
-    const int e = tid + 256 * q, tr = e / kC2W0, tc = e % kC2W0;
+    const int e = tid + NT * q, tr = e / kC2W0, tc = e % kC2W0;
     if (e < NE) {
       const int o = ((tc & 1) * kC2H0 + tr) * HW0 + (tc >> 1);
       X0[o] = v[q][0];
@@ -516,53 +523,61 @@ __global__ void __launch_bounds__(256) k_cheb2(Cheb2Args<T> a, int tiles_x, int 
     }
   }
   __syncthreads();
-  // phase B: first stencil step on the tile plus a halo of 2; the wave's two rows have the
-  // same parity, so one pass per column parity covers both with one set of coefficients
+  // phase B: first stencil step on the tile plus a halo of 2; a wave's rows have the same
+  // parity, so one pass per column parity covers them with one set of coefficients
   T d1[2][2] = {{0, 0}, {0, 0}};   // tile row
-  T x1v[2][2][2];                  // first-step values of the wave's two rows
+  T x1v[2][2][2] = {};             // first-step values of the wave's rows
   const int jodd = __builtin_amdgcn_readfirstlane((J0 - 2 + rows[1]) & 1);
+  auto phase_b = [&](auto q0_tag) {
+    constexpr int Q0 = decltype(q0_tag)::value, NR = 2 - Q0;   // rows Q0..1
 #pragma unroll
-  for (int par = 0; par < 2; ++par) {
-    const int i = 2 * lane + par, I = I0 - 2 + i;   // I0 is even: I has the parity of i
-    const int cls = par | (jodd << 1);
-    const int xr[2] = {rows[0] + 2, rows[1] + 2};   // X0 rows; X0 column i + 2 = 2 (lane + 1) + par
-    T sp[2][2];
-    if (par) class_products<T, 1, kC2H0, HW0, 2>(tb, jodd, X0, xr, lane + 1, sp);
-    else class_products<T, 0, kC2H0, HW0, 2>(tb, jodd, X0, xr, lane + 1, sp);
-    const T *di = tb.dinv[cls];
+    for (int par = 0; par < 2; ++par) {
+      const int i = 2 * lane + par, I = I0 - 2 + i;   // I0 is even: I has the parity of i
+      const int cls = par | (jodd << 1);
+      int xr[NR];                                      // X0 rows; X0 column i + 2 = 2 (lane + 1) + par
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int row = rows[q], J = J0 - 2 + row;
-      T &x10 = x1v[q][par][0], &x11 = x1v[q][par][1];
-      x10 = 0;
-      x11 = 0;
-      if (inside(I, J)) {
-        const int c0 = (par * kC2H0 + row + 2) * HW0 + lane + 1;
-        const T x00 = X0[c0], x01 = X0[2 * kC2H0 * HW0 + c0];
-        const T r0 = bv[q][par][0] - sp[q][0], r1 = bv[q][par][1] - sp[q][1];
-        const T z0 = di[0] * r0 + di[1] * r1, z1 = di[2] * r0 + di[3] * r1;
-        T e0, e1;
-        if constexpr (M == C2_PRE) {   // d = x after the first step from zero
-          e0 = a.c1a * x00 + a.c2a * z0;
-          e1 = a.c1a * x01 + a.c2a * z1;
-        } else {
-          e0 = a.c2a * z0;
-          e1 = a.c2a * z1;
-        }
-        x10 = x00 + e0;
-        x11 = x01 + e1;
-        if (q == 1) {
-          d1[par][0] = e0;
-          d1[par][1] = e1;
+      for (int k = 0; k < NR; ++k) xr[k] = rows[Q0 + k] + 2;
+      T sp[NR][2];
+      if (par) class_products<T, 1, kC2H0, HW0, NR>(tb, jodd, X0, xr, lane + 1, sp);
+      else class_products<T, 0, kC2H0, HW0, NR>(tb, jodd, X0, xr, lane + 1, sp);
+      const T *di = tb.dinv[cls];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const int q = Q0 + k, row = rows[q], J = J0 - 2 + row;
+        T &x10 = x1v[q][par][0], &x11 = x1v[q][par][1];
+        x10 = 0;
+        x11 = 0;
+        if (inside(I, J)) {
+          const int c0 = (par * kC2H0 + row + 2) * HW0 + lane + 1;
+          const T x00 = X0[c0], x01 = X0[2 * kC2H0 * HW0 + c0];
+          const T r0 = bv[q][par][0] - sp[k][0], r1 = bv[q][par][1] - sp[k][1];
+          const T z0 = di[0] * r0 + di[1] * r1, z1 = di[2] * r0 + di[3] * r1;
+          T e0, e1;
+          if constexpr (M == C2_PRE) {   // d = x after the first step from zero
+            e0 = a.c1a * x00 + a.c2a * z0;
+            e1 = a.c1a * x01 + a.c2a * z1;
+          } else {
+            e0 = a.c2a * z0;
+            e1 = a.c2a * z1;
+          }
+          x10 = x00 + e0;
+          x11 = x01 + e1;
+          if (q == 1) {
+            d1[par][0] = e0;
+            d1[par][1] = e1;
+          }
         }
       }
     }
-  }
+  };
+  if (halo) phase_b(std::integral_constant<int, 0>{});
+  else phase_b(std::integral_constant<int, 1>{});
   __syncthreads();   // every wave has read x: the first-step tile goes over it
 #pragma unroll
   for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
+      if (q == 0 && !halo) continue;
       const int o1 = (par * kC2H1 + rows[q]) * HW1 + lane;   // column i = 2 lane + par
       X1[o1] = x1v[q][par][0];
       X1[2 * kC2H1 * HW1 + o1] = x1v[q][par][1];
@@ -631,7 +646,8 @@ void cheb2_pre(int n, const StencilTable<T> *tab, const T *b, T *d, T *x, T s, T
   const int tx = (L + kC2W - 1) / kC2W, ty = (L + kC2R - 1) / kC2R;
   const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
   Cheb2Args<T> a{n, tab, nullptr, b, d, x, L * L, s, c1a, c2a, c1b, c2b};
-  hipLaunchKernelGGL((k_cheb2<T, C2_PRE>), dim3((unsigned)(band * kXcd)), dim3(256), 0, st, a, tx, tiles, band);
+  hipLaunchKernelGGL((k_cheb2<T, C2_PRE, kC2R>), dim3((unsigned)(band * kXcd)), dim3(64 * kC2R), 0, st, a, tx,
+                     tiles, band);
   FSI_CHECK_LAUNCH();
 }
 
@@ -643,7 +659,8 @@ void cheb2_post(int n, const StencilTable<T> *tab, const T *x, const T *b, T *d,
   const int tx = (L + kC2W - 1) / kC2W, ty = (L + kC2R - 1) / kC2R;
   const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
   Cheb2Args<T> a{n, tab, x, b, d, y, L * L, T(0), T(0), c2a, c1b, c2b};
-  hipLaunchKernelGGL((k_cheb2<T, C2_POST>), dim3((unsigned)(band * kXcd)), dim3(256), 0, st, a, tx, tiles, band);
+  hipLaunchKernelGGL((k_cheb2<T, C2_POST, kC2R>), dim3((unsigned)(band * kXcd)), dim3(64 * kC2R), 0, st, a, tx,
+                     tiles, band);
   FSI_CHECK_LAUNCH();
 }
 
