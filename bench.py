@@ -109,6 +109,8 @@ def run_serving(count: int, slots: int) -> dict:
     summ = serve.summarize(res)
     out = {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in summ.items()}
     out.update(slots=slots, max_inflight=srv.max_inflight, evictions=srv.evictions,
+               jobs=srv.batches, requests_per_job=round(srv.batched / max(srv.batches, 1), 2),
+               lanes={n: srv.lanes(n) for n in (32, 64, 128, 256)},
                budget_gb=round(srv.budget / 2**30, 1), wall_s=round(wall, 3),
                steps_per_s=float(f"{len(res) / wall:.6g}"), dtype="f32+f64",
                trace="512 requests, Poisson 200 req/s, n in {32,64,128,256}, m in 6..45")

@@ -211,6 +211,25 @@ int fsi_gmres_solve(fsi_ctx *ctx, const fsi_solve_opts *opts, const double *b, d
 int fsi_step(fsi_ctx *ctx, const fsi_solve_opts *opts, const double *u_n, const double *X_n,
              double *state, fsi_solve_stats *stats);
 
+/* K independent steps in lockstep (a batch of small requests): system k is
+ * fsi_step(ctxs[k], opts, u_n[k], X_n[k], state[k], &stats[k]), and its result is bitwise
+ * the result of that call.  The contexts share the fluid grid and fluid parameters (n, nu,
+ * rho, dt) and have their own solids.  Every kernel runs on ctxs[0]'s stream (the other
+ * contexts' streams are synchronised, set to it for the call and restored); the inner A11
+ * solves of all systems run as K lanes of the same launches (lane = second grid dimension)
+ * on ctxs[0]'s inner work space and with its inner and smoother settings, so a batch issues
+ * about as many launches as one step.  ctxs[0] keeps inner work space for K systems
+ * (grow-only; growing it drops its captured graphs).
+ * K: 1..FSI_MAX_LANES; ctxs: host array of K distinct contexts; u_n, X_n, state: host arrays
+ * of K device pointers (sizes as in fsi_step); stats: host array of K (may be NULL); rc: host
+ * array of K per-system statuses, FSI_OK / FSI_E_NOCONV / FSI_E_NONFINITE (may be NULL).
+ * Returns FSI_OK when every system converged, else the status of the first system that did
+ * not (its message in fsi_last_error(ctxs[0])).  Any other error (FSI_E_ARG, FSI_E_MESH,
+ * FSI_E_CAPACITY, FSI_E_HIP, ...) fails the whole batch; outputs are then unspecified. */
+#define FSI_MAX_LANES 32
+int fsi_step_batch(int32_t K, fsi_ctx *const *ctxs, const fsi_solve_opts *opts, const double *const *u_n,
+                   const double *const *X_n, double *const *state, fsi_solve_stats *stats, int32_t *rc);
+
 /* Test exports (host copies; synchronising).  fsi_export_pairs writes up to cap pieces
  * (solid triangle E, fluid triangle T) in the canonical order (by E, then cell j-major,
  * then T) and stores the total in *count.  fsi_export_csr: call with NULL arrays to get

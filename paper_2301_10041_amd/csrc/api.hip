@@ -356,6 +356,66 @@ int fsi_step(fsi_ctx *ctx, const fsi_solve_opts *opts, const double *u_n, const 
   });
 }
 
+int fsi_step_batch(int32_t K, fsi_ctx *const *ctxs, const fsi_solve_opts *opts, const double *const *u_n,
+                   const double *const *X_n, double *const *state, fsi_solve_stats *stats, int32_t *rc) {
+  if (K < 1 || K > FSI_MAX_LANES || !ctxs || !ctxs[0]) return FSI_E_ARG;
+  fsi_ctx *lead = ctxs[0];
+  return guarded(lead, [&] {
+    FSI_REQUIRE(opts && u_n && X_n && state, FSI_E_ARG, "null options or arrays");
+    std::vector<Ctx *> cs(K);
+    for (int k = 0; k < K; ++k) {
+      FSI_REQUIRE(ctxs[k] && u_n[k] && X_n[k] && state[k], FSI_E_ARG, "null context or vector in the batch");
+      cs[k] = &ctxs[k]->c;
+      for (int q = 0; q < k; ++q) FSI_REQUIRE(cs[q] != cs[k], FSI_E_ARG, "a context appears twice in the batch");
+      const Ctx &a = *cs[0], &b = *cs[k];
+      FSI_REQUIRE(a.n == b.n && a.nu == b.nu && a.rho == b.rho && a.dt == b.dt, FSI_E_ARG,
+                  "systems of a batch need the same fluid grid and parameters");
+    }
+    hipStream_t s = cs[0]->stream;
+    // every context on the leading stream for the call (their own streams drained first)
+    struct Streams {
+      std::vector<Ctx *> &cs;
+      std::vector<hipStream_t> old;
+      ~Streams() {
+        for (size_t k = 0; k < cs.size(); ++k) cs[k]->stream = old[k];
+      }
+    } streams{cs, {}};
+    for (Ctx *c : cs) {
+      streams.old.push_back(c->stream);
+      if (c->stream != s) FSI_HIP(hipStreamSynchronize(c->stream));
+    }
+    for (Ctx *c : cs) c->stream = s;
+    using clk = std::chrono::steady_clock;
+    auto t0 = clk::now();
+    for (int k = 0; k < K; ++k) fsi::assemble_coupling(*cs[k], X_n[k], true);
+    FSI_HIP(hipStreamSynchronize(s));
+    auto t1 = clk::now();
+    std::vector<const double *> b(K);
+    for (int k = 0; k < K; ++k) {
+      b[k] = cs[k]->tmpN.p;
+      fsi::build_rhs(*cs[k], u_n[k], X_n[k], cs[k]->tmpN.p);
+      fsi::fill(state[k], cs[k]->N, 0.0, s);
+    }
+    FSI_HIP(hipStreamSynchronize(s));
+    auto t2 = clk::now();
+    std::vector<fsi_solve_stats> st(K);
+    std::vector<int> rcs(K, FSI_OK);
+    fsi::gmres_solve_lanes(cs.data(), K, *opts, b.data(), state, st.data(), rcs.data());
+    FSI_HIP(hipStreamSynchronize(s));
+    auto t3 = clk::now();
+    int first = -1;
+    for (int k = 0; k < K; ++k) {
+      st[k].t_coup = std::chrono::duration<double>(t1 - t0).count();
+      st[k].t_rhs = std::chrono::duration<double>(t2 - t1).count();
+      st[k].t_solve = std::chrono::duration<double>(t3 - t2).count();
+      if (stats) stats[k] = st[k];
+      if (rc) rc[k] = rcs[k];
+      if (rcs[k] != FSI_OK && first < 0) first = k;
+    }
+    if (first >= 0) throw Error(rcs[first], cs[first]->last_error);
+  });
+}
+
 int fsi_export_pairs(fsi_ctx *ctx, int32_t *E, int32_t *T, int64_t cap, int64_t *count) {
   if (!ctx || !count) return FSI_E_ARG;
   return guarded(ctx, [&] {

@@ -2,6 +2,8 @@
 // wavefront reductions for gfx950 (64-lane wavefronts).
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -68,6 +70,21 @@ struct DevBuf {
 };
 
 constexpr int kWave = 64;
+
+// A per-lane view of a device array for kernels over K independent systems (lane = blockIdx.y):
+// lane k uses p + k s; s = 0 for data shared by every lane.  A plain pointer converts to a
+// view with s = 0, so one-system call sites are unchanged.
+template <typename T>
+struct LP {
+  T *p = nullptr;
+  int64_t s = 0;
+  LP() = default;
+  __host__ __device__ LP(T *ptr, int64_t stride = 0) : p(ptr), s(stride) {}
+  template <typename U, typename = typename std::enable_if<std::is_convertible<U *, T *>::value>::type>
+  __host__ __device__ LP(const LP<U> &o) : p(o.p), s(o.s) {}
+  __host__ __device__ T *at(int k) const { return p + (int64_t)k * s; }
+  __host__ __device__ LP operator+(int64_t o) const { return LP(p + o, s); }
+};
 
 inline unsigned grid_for(int64_t items, int block) {
   int64_t g = (items + block - 1) / block;

@@ -132,7 +132,7 @@ struct Ctx {
   // HIP graphs of the A11 preconditioner (one per precision), replayed on fixed staging
   // buffers; captured on first use, dropped when the smoother changes
   bool use_graphs = false;
-  hipGraphExec_t pc_graph[2] = {nullptr, nullptr};
+  hipGraphExec_t pc_graph[2][FSI_MAX_LANES + 1] = {};   // per precision and lane count
   hipStream_t cap_stream = nullptr;   // capture only (default priority)
   // second stream of the A11 preconditioner: the pressure part (Schur approximation) runs
   // beside the velocity V-cycle, forked from and joined into the context stream by events
@@ -143,10 +143,13 @@ struct Ctx {
   // inner MINRES: device-side scalar state, its own reduction buffer and solution vector
   // (allocated once: captured graphs hold these pointers), graphs per precision and phase
   DevBuf<double> ms_state, ms_red, ms_x, ms_part;
-  hipGraphExec_t ms_graph[2][6] = {};   // per precision and buffer-rotation phase
+  hipGraphExec_t ms_graph[2][FSI_MAX_LANES + 1][6] = {};   // per precision, lane count, rotation phase
   DevBuf<double> pc_in, pc_out;
   void drop_graphs();
 
+  // systems the inner work space holds (lockstep solves of several contexts run their A11
+  // solves on this context's lanes; lane stride = one system's vector length)
+  int lanes = 1;
   double inner_rtol = -1.0;   // < 0: default per precision
   int inner_maxit = 1000;
   int64_t inner_its_total = 0;
@@ -169,6 +172,10 @@ void build_rhs(Ctx &c, const double *u_n, const double *X_n, double *b);
 void make_shadow(Csr &A, hipStream_t s);
 // solve.hip
 void apply_precond(Ctx &c, int pc, int prec, const double *r, double *z);
+void apply_precond_lanes(Ctx &engine, Ctx *const *cs, int K, int pc, int prec, const double *const *r,
+                         double *const *z);
 void gmres_solve(Ctx &c, const fsi_solve_opts &o, const double *b, double *x, fsi_solve_stats *st);
+void gmres_solve_lanes(Ctx *const *cs, int K, const fsi_solve_opts &o, const double *const *b,
+                       double *const *x, fsi_solve_stats *st, int *rc);
 
 }  // namespace fsi

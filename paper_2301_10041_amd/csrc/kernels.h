@@ -181,15 +181,19 @@ inline void spmv(const int64_t nrows, const int *rowptr, const int *col, const T
 }
 
 // ------------------------------------------------------------------ vector kernels
+// The vector kernels below run over gridDim.y systems (lane = blockIdx.y, see LP).
 template <typename T>
-__global__ void k_fill(T *x, int64_t n, T v) {
+__global__ void k_fill(LP<T> xl, int64_t n, T v) {
+  T *x = xl.at(blockIdx.y);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     x[i] = v;
 }
 
 template <typename To, typename Ti>
-__global__ void k_convert(To *y, const Ti *x, int64_t n) {
+__global__ void k_convert(LP<To> yl, LP<const Ti> xl, int64_t n) {
+  To *y = yl.at(blockIdx.y);
+  const Ti *x = xl.at(blockIdx.y);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (To)x[i];
@@ -205,7 +209,9 @@ __global__ void k_axpby(T *y, const T *x, T a, T b, int64_t n) {
 
 // z = a x + b y
 template <typename T>
-__global__ void k_lincomb(T *z, const T *x, const T *y, T a, T b, int64_t n) {
+__global__ void k_lincomb(LP<T> zl, LP<const T> xl, LP<const T> yl, T a, T b, int64_t n) {
+  T *z = zl.at(blockIdx.y);
+  const T *x = xl.at(blockIdx.y), *y = yl.at(blockIdx.y);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     z[i] = a * x[i] + b * y[i];
@@ -219,14 +225,22 @@ inline unsigned vgrid(int64_t n) {
 }
 
 template <typename T>
+inline void fill_l(LP<T> x, int64_t n, T v, hipStream_t s, int K) {
+  hipLaunchKernelGGL(k_fill<T>, dim3(vgrid(n), K), dim3(256), 0, s, x, n, v);
+  FSI_CHECK_LAUNCH();
+}
+template <typename T>
 inline void fill(T *x, int64_t n, T v, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill<T>, dim3(vgrid(n)), dim3(256), 0, s, x, n, v);
+  fill_l(LP<T>(x), n, v, s, 1);
+}
+template <typename To, typename Ti>
+inline void convert_l(LP<To> y, LP<const Ti> x, int64_t n, hipStream_t s, int K) {
+  hipLaunchKernelGGL((k_convert<To, Ti>), dim3(vgrid(n), K), dim3(256), 0, s, y, x, n);
   FSI_CHECK_LAUNCH();
 }
 template <typename To, typename Ti>
 inline void convert(To *y, const Ti *x, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL((k_convert<To, Ti>), dim3(vgrid(n)), dim3(256), 0, s, y, x, n);
-  FSI_CHECK_LAUNCH();
+  convert_l(LP<To>(y), LP<const Ti>(x), n, s, 1);
 }
 template <typename T>
 inline void axpby(T *y, const T *x, T a, T b, int64_t n, hipStream_t s) {
@@ -234,9 +248,13 @@ inline void axpby(T *y, const T *x, T a, T b, int64_t n, hipStream_t s) {
   FSI_CHECK_LAUNCH();
 }
 template <typename T>
-inline void lincomb(T *z, const T *x, const T *y, T a, T b, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_lincomb<T>, dim3(vgrid(n)), dim3(256), 0, s, z, x, y, a, b, n);
+inline void lincomb_l(LP<T> z, LP<const T> x, LP<const T> y, T a, T b, int64_t n, hipStream_t s, int K) {
+  hipLaunchKernelGGL(k_lincomb<T>, dim3(vgrid(n), K), dim3(256), 0, s, z, x, y, a, b, n);
   FSI_CHECK_LAUNCH();
+}
+template <typename T>
+inline void lincomb(T *z, const T *x, const T *y, T a, T b, int64_t n, hipStream_t s) {
+  lincomb_l(LP<T>(z), LP<const T>(x), LP<const T>(y), a, b, n, s, 1);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -265,9 +283,12 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 template <typename TV, typename TW>
-__global__ void __launch_bounds__(kRedBlock) k_multidot_part(const TV *V, int64_t ldv, int k,
-                                                             const TW *w, int64_t n,
-                                                             double *part) {
+__global__ void __launch_bounds__(kRedBlock) k_multidot_part(LP<const TV> Vl, int64_t ldv, int k,
+                                                             LP<const TW> wl, int64_t n,
+                                                             LP<double> partl) {
+  const TV *V = Vl.at(blockIdx.y);
+  const TW *w = wl.at(blockIdx.y);
+  double *part = partl.at(blockIdx.y);
   int nb = gridDim.x;
   int64_t chunk = (n + nb - 1) / nb;
   int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk;
@@ -282,7 +303,9 @@ __global__ void __launch_bounds__(kRedBlock) k_multidot_part(const TV *V, int64_
 }
 
 // out[i] = sum_b part[i * nb + b] (one wavefront per i, fixed order)
-__global__ void k_multidot_final(const double *part, int nb, int k, double *out) {
+__global__ void k_multidot_final(LP<const double> partl, int nb, int k, LP<double> outl) {
+  const double *part = partl.at(blockIdx.y);
+  double *out = outl.at(blockIdx.y);
   int i = blockIdx.x;
   if (i >= k) return;
   double s = 0.0;
@@ -296,9 +319,22 @@ inline void multidot(const TV *V, int64_t ldv, int k, const TW *w, int64_t n, do
                      DevBuf<double> &part, hipStream_t s) {
   int nb = red_blocks(n);
   part.reserve((size_t)nb * (k > 0 ? k : 1));
-  hipLaunchKernelGGL((k_multidot_part<TV, TW>), dim3(nb), dim3(kRedBlock), 0, s, V, ldv, k, w, n,
-                     part.p);
-  hipLaunchKernelGGL(k_multidot_final, dim3(k), dim3(kWave), 0, s, part.p, nb, k, out);
+  hipLaunchKernelGGL((k_multidot_part<TV, TW>), dim3(nb), dim3(kRedBlock), 0, s, LP<const TV>(V), ldv, k,
+                     LP<const TW>(w), n, LP<double>(part.p));
+  hipLaunchKernelGGL(k_multidot_final, dim3(k), dim3(kWave), 0, s, LP<const double>(part.p), nb, k,
+                     LP<double>(out));
+  FSI_CHECK_LAUNCH();
+}
+
+// One dot product per lane (k = 1): out[lane] (lane stride of out) = V[lane] . w[lane];
+// part holds red_blocks(n) partials per lane (lane stride red_blocks(n)), allocated by the
+// caller (never regrown: captured graphs hold it).
+template <typename TV, typename TW>
+inline void dot_l(LP<const TV> V, LP<const TW> w, int64_t n, LP<double> out, double *part, hipStream_t s, int K) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_multidot_part<TV, TW>), dim3(nb, K), dim3(kRedBlock), 0, s, V, 0, 1, w, n,
+                     LP<double>(part, nb));
+  hipLaunchKernelGGL(k_multidot_final, dim3(1, K), dim3(kWave), 0, s, LP<const double>(part, nb), nb, 1, out);
   FSI_CHECK_LAUNCH();
 }
 

@@ -106,25 +106,27 @@ constexpr int kTableMp = 216, kTableLp = 225;   // offsets of the P1 blocks in t
 void p1_tables(int n, int which, int pin, P1Table<double> &t64, P1Table<float> &t32);   // assemble.hip
 void p2_restrict_tables(P2RestrTable<double> &t64, P2RestrTable<float> &t32);          // lattice.hip
 
-// Launchers (stream-ordered, no synchronisation).  Vectors are component-major with the
-// level's node count as stride.
+// Launchers (stream-ordered, no synchronisation) over K independent systems (lane =
+// blockIdx.y; each vector is a per-lane view, see LP; K = 1 for one system).  Vectors are
+// component-major with the level's node count as stride.
 template <typename T, int MODE>   // SP_APPLY, SP_RESID or SP_CHEB as for the A_f stencil
-void p1_launch(int n, const P1Table<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2,
-               hipStream_t s);
+void p1_launch(int n, const P1Table<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<T> y, T c1, T c2,
+               hipStream_t s, int K = 1);
 // d = x = scale D^{-1} b (first Chebyshev step from zero), class-wise diagonal
 template <typename T>
-void p1_first(int n, const P1Table<T> *tab, const T *b, T scale, T *d, T *x, hipStream_t s);
+void p1_first(int n, const P1Table<T> *tab, LP<const T> b, T scale, LP<T> d, LP<T> x, hipStream_t s, int K = 1);
 template <typename T>
-void p2_first(int n, const StencilTable<T> *tab, const T *b, T scale, T *d, T *x, hipStream_t s);
+void p2_first(int n, const StencilTable<T> *tab, LP<const T> b, T scale, LP<T> d, LP<T> x, hipStream_t s,
+              int K = 1);
 // y += P xc (fine grid nf; coarse vector on the nf / 2 grid); P2 has two components
 template <typename T>
-void p2_prolong_add(int nf, const T *xc, T *y, hipStream_t s);
+void p2_prolong_add(int nf, LP<const T> xc, LP<T> y, hipStream_t s, int K = 1);
 template <typename T>
-void p1_prolong_add(int nf, const T *xc, T *y, hipStream_t s);
+void p1_prolong_add(int nf, LP<const T> xc, LP<T> y, hipStream_t s, int K = 1);
 // bc = R r
 template <typename T>
-void p2_restrict(int nf, const P2RestrTable<T> *tab, const T *r, T *bc, hipStream_t s);
+void p2_restrict(int nf, const P2RestrTable<T> *tab, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
 template <typename T>
-void p1_restrict(int nf, const T *r, T *bc, hipStream_t s);
+void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
 
 }  // namespace fsi

@@ -15,10 +15,14 @@
 
 namespace fsi {
 
+// Every kernel below runs K independent systems (lane = blockIdx.y) over per-lane views (LP).
+
 // ---------------------------------------------------------------- P1 operators
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_p1(int n, const P1Table<T> *__restrict__ tabp, const T *__restrict__ x,
-                                            const T *__restrict__ b, T *d, T *y, T c1, T c2) {
+__global__ void __launch_bounds__(256) k_p1(int n, const P1Table<T> *__restrict__ tabp, LP<const T> xl,
+                                            LP<const T> bl, LP<T> dl, LP<T> yl, T c1, T c2) {
+  const T *__restrict__ x = xl.at(blockIdx.y), *__restrict__ b = bl.at(blockIdx.y);
+  T *d = dl.at(blockIdx.y), *y = yl.at(blockIdx.y);
   const int L = n + 1;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= (int64_t)L * L) return;
@@ -56,15 +60,18 @@ __global__ void __launch_bounds__(256) k_p1(int n, const P1Table<T> *__restrict_
 }
 
 template <typename T, int MODE>
-void p1_launch(int n, const P1Table<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2, hipStream_t s) {
+void p1_launch(int n, const P1Table<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<T> y, T c1, T c2,
+               hipStream_t s, int K) {
   const int64_t nodes = (int64_t)(n + 1) * (n + 1);
-  hipLaunchKernelGGL((k_p1<T, MODE>), dim3(grid_for(nodes, 256)), dim3(256), 0, s, n, tab, x, b, d, y, c1, c2);
+  hipLaunchKernelGGL((k_p1<T, MODE>), dim3(grid_for(nodes, 256), K), dim3(256), 0, s, n, tab, x, b, d, y, c1, c2);
   FSI_CHECK_LAUNCH();
 }
 
 template <typename T>
-__global__ void k_p1_first(int n, const P1Table<T> *__restrict__ tabp, const T *__restrict__ b, T scale, T *d,
-                           T *x) {
+__global__ void k_p1_first(int n, const P1Table<T> *__restrict__ tabp, LP<const T> bl, T scale, LP<T> dl,
+                           LP<T> xl) {
+  const T *__restrict__ b = bl.at(blockIdx.y);
+  T *d = dl.at(blockIdx.y), *x = xl.at(blockIdx.y);
   const int L = n + 1;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= (int64_t)L * L) return;
@@ -76,16 +83,18 @@ __global__ void k_p1_first(int n, const P1Table<T> *__restrict__ tabp, const T *
 }
 
 template <typename T>
-void p1_first(int n, const P1Table<T> *tab, const T *b, T scale, T *d, T *x, hipStream_t s) {
+void p1_first(int n, const P1Table<T> *tab, LP<const T> b, T scale, LP<T> d, LP<T> x, hipStream_t s, int K) {
   const int64_t nodes = (int64_t)(n + 1) * (n + 1);
-  hipLaunchKernelGGL(k_p1_first<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, n, tab, b, scale, d, x);
+  hipLaunchKernelGGL(k_p1_first<T>, dim3(grid_for(nodes, 256), K), dim3(256), 0, s, n, tab, b, scale, d, x);
   FSI_CHECK_LAUNCH();
 }
 
 // ---------------------------------------------------------------- P2 first Chebyshev step
 template <typename T>
-__global__ void k_p2_first(int n, const StencilTable<T> *__restrict__ tabp, const T *__restrict__ b, T scale,
-                           T *d, T *x) {
+__global__ void k_p2_first(int n, const StencilTable<T> *__restrict__ tabp, LP<const T> bl, T scale, LP<T> dl,
+                           LP<T> xl) {
+  const T *__restrict__ b = bl.at(blockIdx.y);
+  T *d = dl.at(blockIdx.y), *x = xl.at(blockIdx.y);
   const int L = 2 * n + 1;
   const int64_t N = (int64_t)L * L;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -108,9 +117,10 @@ __global__ void k_p2_first(int n, const StencilTable<T> *__restrict__ tabp, cons
 }
 
 template <typename T>
-void p2_first(int n, const StencilTable<T> *tab, const T *b, T scale, T *d, T *x, hipStream_t s) {
+void p2_first(int n, const StencilTable<T> *tab, LP<const T> b, T scale, LP<T> d, LP<T> x, hipStream_t s,
+              int K) {
   const int64_t nodes = (int64_t)(2 * n + 1) * (2 * n + 1);
-  hipLaunchKernelGGL(k_p2_first<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, n, tab, b, scale, d, x);
+  hipLaunchKernelGGL(k_p2_first<T>, dim3(grid_for(nodes, 256), K), dim3(256), 0, s, n, tab, b, scale, d, x);
   FSI_CHECK_LAUNCH();
 }
 
@@ -122,7 +132,9 @@ __device__ __forceinline__ bool on_p2_boundary(int I, int J, int n) {
 // y += P xc: coarse quadratic evaluated at the fine node; Dirichlet nodes (fine rows and
 // coarse columns) take no part.
 template <typename T>
-__global__ void __launch_bounds__(256) k_p2_prolong_add(int nf, const T *__restrict__ xc, T *y) {
+__global__ void __launch_bounds__(256) k_p2_prolong_add(int nf, LP<const T> xcl, LP<T> yl) {
+  const T *__restrict__ xc = xcl.at(blockIdx.y);
+  T *y = yl.at(blockIdx.y);
   const int L = 2 * nf + 1, nc = nf / 2, Lc = 2 * nc + 1;
   const int64_t Nf = (int64_t)L * L, Nc = (int64_t)Lc * Lc;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,9 +156,9 @@ __global__ void __launch_bounds__(256) k_p2_prolong_add(int nf, const T *__restr
 }
 
 template <typename T>
-void p2_prolong_add(int nf, const T *xc, T *y, hipStream_t s) {
+void p2_prolong_add(int nf, LP<const T> xc, LP<T> y, hipStream_t s, int K) {
   const int64_t nodes = (int64_t)(2 * nf + 1) * (2 * nf + 1);
-  hipLaunchKernelGGL(k_p2_prolong_add<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, nf, xc, y);
+  hipLaunchKernelGGL(k_p2_prolong_add<T>, dim3(grid_for(nodes, 256), K), dim3(256), 0, s, nf, xc, y);
   FSI_CHECK_LAUNCH();
 }
 
@@ -173,7 +185,9 @@ __device__ __forceinline__ void restrict_sum(const P2RestrTable<T> &tb, const T 
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_p2_restrict(int nf, const P2RestrTable<T> *__restrict__ tabp,
-                                                     const T *__restrict__ r, T *bc, int segs) {
+                                                     LP<const T> rl, LP<T> bcl, int segs) {
+  const T *__restrict__ r = rl.at(blockIdx.y);
+  T *bc = bcl.at(blockIdx.y);
   const int L = 2 * nf + 1, nc = nf / 2, Lc = 2 * nc + 1;
   const int64_t Nf = (int64_t)L * L, Nc = (int64_t)Lc * Lc;
   const int Jc = blockIdx.x / segs, seg = blockIdx.x % segs;
@@ -198,10 +212,10 @@ __global__ void __launch_bounds__(256) k_p2_restrict(int nf, const P2RestrTable<
 }
 
 template <typename T>
-void p2_restrict(int nf, const P2RestrTable<T> *tab, const T *r, T *bc, hipStream_t s) {
+void p2_restrict(int nf, const P2RestrTable<T> *tab, LP<const T> r, LP<T> bc, hipStream_t s, int K) {
   const int Lc = nf + 1;
   const int segs = (Lc + 255) / 256;
-  hipLaunchKernelGGL(k_p2_restrict<T>, dim3((unsigned)(Lc * segs)), dim3(256), 0, s, nf, tab, r, bc, segs);
+  hipLaunchKernelGGL(k_p2_restrict<T>, dim3((unsigned)(Lc * segs), K), dim3(256), 0, s, nf, tab, r, bc, segs);
   FSI_CHECK_LAUNCH();
 }
 
@@ -242,7 +256,9 @@ void p2_restrict_tables(P2RestrTable<double> &t64, P2RestrTable<float> &t32) {
 // Linear interpolation on the nested triangulation; the pinned node 0 is excluded on both
 // grids (fine row 0 and coarse column 0 are empty).
 template <typename T>
-__global__ void __launch_bounds__(256) k_p1_prolong_add(int nf, const T *__restrict__ xc, T *y) {
+__global__ void __launch_bounds__(256) k_p1_prolong_add(int nf, LP<const T> xcl, LP<T> yl) {
+  const T *__restrict__ xc = xcl.at(blockIdx.y);
+  T *y = yl.at(blockIdx.y);
   const int L = nf + 1, Lc = nf / 2 + 1;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r == 0 || r >= (int64_t)L * L) return;
@@ -260,9 +276,9 @@ __global__ void __launch_bounds__(256) k_p1_prolong_add(int nf, const T *__restr
 }
 
 template <typename T>
-void p1_prolong_add(int nf, const T *xc, T *y, hipStream_t s) {
+void p1_prolong_add(int nf, LP<const T> xc, LP<T> y, hipStream_t s, int K) {
   const int64_t nodes = (int64_t)(nf + 1) * (nf + 1);
-  hipLaunchKernelGGL(k_p1_prolong_add<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, nf, xc, y);
+  hipLaunchKernelGGL(k_p1_prolong_add<T>, dim3(grid_for(nodes, 256), K), dim3(256), 0, s, nf, xc, y);
   FSI_CHECK_LAUNCH();
 }
 
@@ -270,7 +286,9 @@ void p1_prolong_add(int nf, const T *xc, T *y, hipStream_t s) {
 // midpoints around it (weight 1/2): horizontal, vertical and the two along the cell
 // diagonals through it.
 template <typename T>
-__global__ void __launch_bounds__(256) k_p1_restrict(int nf, const T *__restrict__ r, T *bc) {
+__global__ void __launch_bounds__(256) k_p1_restrict(int nf, LP<const T> rl, LP<T> bcl) {
+  const T *__restrict__ r = rl.at(blockIdx.y);
+  T *bc = bcl.at(blockIdx.y);
   const int L = nf + 1, Lc = nf / 2 + 1;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)Lc * Lc) return;
@@ -290,25 +308,25 @@ __global__ void __launch_bounds__(256) k_p1_restrict(int nf, const T *__restrict
 }
 
 template <typename T>
-void p1_restrict(int nf, const T *r, T *bc, hipStream_t s) {
+void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K) {
   const int64_t nodes = (int64_t)(nf / 2 + 1) * (nf / 2 + 1);
-  hipLaunchKernelGGL(k_p1_restrict<T>, dim3(grid_for(nodes, 256)), dim3(256), 0, s, nf, r, bc);
+  hipLaunchKernelGGL(k_p1_restrict<T>, dim3(grid_for(nodes, 256), K), dim3(256), 0, s, nf, r, bc);
   FSI_CHECK_LAUNCH();
 }
 
 #define FSI_LATTICE_INST(T)                                                                                 \
-  template void p1_launch<T, SP_APPLY>(int, const P1Table<T> *, const T *, const T *, T *, T *, T, T,       \
-                                       hipStream_t);                                                        \
-  template void p1_launch<T, SP_RESID>(int, const P1Table<T> *, const T *, const T *, T *, T *, T, T,       \
-                                       hipStream_t);                                                        \
-  template void p1_launch<T, SP_CHEB>(int, const P1Table<T> *, const T *, const T *, T *, T *, T, T,        \
-                                      hipStream_t);                                                         \
-  template void p1_first<T>(int, const P1Table<T> *, const T *, T, T *, T *, hipStream_t);                 \
-  template void p2_first<T>(int, const StencilTable<T> *, const T *, T, T *, T *, hipStream_t);            \
-  template void p2_prolong_add<T>(int, const T *, T *, hipStream_t);                                        \
-  template void p1_prolong_add<T>(int, const T *, T *, hipStream_t);                                        \
-  template void p2_restrict<T>(int, const P2RestrTable<T> *, const T *, T *, hipStream_t);                 \
-  template void p1_restrict<T>(int, const T *, T *, hipStream_t);
+  template void p1_launch<T, SP_APPLY>(int, const P1Table<T> *, LP<const T>, LP<const T>, LP<T>, LP<T>, T, T, \
+                                       hipStream_t, int);                                                   \
+  template void p1_launch<T, SP_RESID>(int, const P1Table<T> *, LP<const T>, LP<const T>, LP<T>, LP<T>, T, T, \
+                                       hipStream_t, int);                                                   \
+  template void p1_launch<T, SP_CHEB>(int, const P1Table<T> *, LP<const T>, LP<const T>, LP<T>, LP<T>, T, T,  \
+                                      hipStream_t, int);                                                    \
+  template void p1_first<T>(int, const P1Table<T> *, LP<const T>, T, LP<T>, LP<T>, hipStream_t, int);        \
+  template void p2_first<T>(int, const StencilTable<T> *, LP<const T>, T, LP<T>, LP<T>, hipStream_t, int);   \
+  template void p2_prolong_add<T>(int, LP<const T>, LP<T>, hipStream_t, int);                               \
+  template void p1_prolong_add<T>(int, LP<const T>, LP<T>, hipStream_t, int);                               \
+  template void p2_restrict<T>(int, const P2RestrTable<T> *, LP<const T>, LP<T>, hipStream_t, int);        \
+  template void p1_restrict<T>(int, LP<const T>, LP<T>, hipStream_t, int);
 
 FSI_LATTICE_INST(double)
 FSI_LATTICE_INST(float)

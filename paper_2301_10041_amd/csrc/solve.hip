@@ -69,9 +69,11 @@ __global__ void k_dinv_first(int64_t nodes, const T *dinv, const T *b, T scale, 
 }
 
 template <typename T>
-__global__ void k_dense_mv(int m, const T *A, const T *x, T *y) {
+__global__ void k_dense_mv(int m, const T *A, const T *x, T *y) {   // lane blockIdx.y: x, y + lane m
   int r = blockIdx.x;
   if (r >= m) return;
+  x += (int64_t)blockIdx.y * m;
+  y += (int64_t)blockIdx.y * m;
   double s = 0.0;
   for (int k = threadIdx.x; k < m; k += kWave) s += (double)A[(int64_t)r * m + k] * (double)x[k];
   s = wave_sum(s);
@@ -108,8 +110,8 @@ __global__ void k_minres_update(T *wn, const T *v, const T *w1, const T *w2, T *
 }
 
 template <typename T>
-__global__ void k_set_pinned(T *z, const T *r) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) z[0] = r[0];
+__global__ void k_set_pinned(T *z, const T *r, int64_t ls) {   // lane blockIdx.y at + lane ls
+  if (threadIdx.x == 0 && blockIdx.x == 0) z[(int64_t)blockIdx.y * ls] = r[(int64_t)blockIdx.y * ls];
 }
 
 template <typename T>
@@ -223,7 +225,8 @@ static T *chebyshev_mf(First first, Step step, double lmin, double lmax, int ste
 // single kernel of a step).
 template <typename T>
 static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, double lmax, int steps,
-                            const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s, Prof *prof) {
+                            const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s, Prof *prof,
+                            int K = 1, int64_t ls = 0) {
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
@@ -233,33 +236,35 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
     c2 = (T)(2.0 * rho1 / delta);
     rho = rho1;
   };
+  const LP<const T> lb(b, ls);
+  const LP<T> ld(d, ls);
   int done = 0;
   if (zero_init && steps >= 3) {
     T c1a, c2a, c1b, c2b;
     next(c1a, c2a);
     next(c1b, c2b);
-    cheb2_pre<T>(n, tab, b, d, x, (T)(1.0 / theta), c1a, c2a, c1b, c2b, s);
+    cheb2_pre<T>(n, tab, lb, ld, LP<T>(x, ls), (T)(1.0 / theta), c1a, c2a, c1b, c2b, s, K);
     done = 3;
   } else if (!zero_init && steps >= 2) {
     T c1b, c2b;
     next(c1b, c2b);
     if (prof) prof->begin(s);
-    cheb2_post<T>(n, tab, x, b, d, x2, (T)(1.0 / theta), c1b, c2b, s);
+    cheb2_post<T>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(x2, ls), (T)(1.0 / theta), c1b, c2b, s, K);
     if (prof) prof->end(s);
     std::swap(x, x2);
     done = 2;
   } else if (zero_init) {
-    p2_first<T>(n, tab, b, (T)(1.0 / theta), d, x, s);
+    p2_first<T>(n, tab, lb, (T)(1.0 / theta), ld, LP<T>(x, ls), s, K);
     done = 1;
   } else {
-    stencil_launch<T, SP_CHEB>(n, tab, x, b, d, x2, (T)0, (T)(1.0 / theta), s);
+    stencil_launch<T, SP_CHEB>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(x2, ls), (T)0, (T)(1.0 / theta), s, K);
     std::swap(x, x2);
     done = 1;
   }
   for (int k = done; k < steps; ++k) {
     T c1, c2;
     next(c1, c2);
-    stencil_launch<T, SP_CHEB>(n, tab, x, b, d, x2, c1, c2, s);
+    stencil_launch<T, SP_CHEB>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(x2, ls), c1, c2, s, K);
     std::swap(x, x2);
   }
   return x;
@@ -267,10 +272,13 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
 
 template <typename T>
 static T *chebyshev_p1(int n, const P1Table<T> *tab, double lmin, double lmax, int steps, const T *b,
-                       T *x, T *x2, T *d, bool zero_init, hipStream_t s) {
-  return chebyshev_mf<T>([&](T sc, T *xo) { p1_first<T>(n, tab, b, sc, d, xo, s); },
+                       T *x, T *x2, T *d, bool zero_init, hipStream_t s, int K = 1, int64_t ls = 0) {
+  const LP<const T> lb(b, ls);
+  const LP<T> ld(d, ls);
+  return chebyshev_mf<T>([&](T sc, T *xo) { p1_first<T>(n, tab, lb, sc, ld, LP<T>(xo, ls), s, K); },
                          [&](const T *xi, T *xo, T c1, T c2) {
-                           p1_launch<T, SP_CHEB>(n, tab, xi, b, d, xo, c1, c2, s);
+                           p1_launch<T, SP_CHEB>(n, tab, LP<const T>(xi, ls), lb, ld, LP<T>(xo, ls), c1, c2, s,
+                                                 K);
                          },
                          lmin, lmax, steps, x, x2, zero_init, s, nullptr);
 }
@@ -293,11 +301,14 @@ template <typename T> static const P2RestrTable<T> *rtab(const Mg &mg) {
 // One V-cycle at level l for right-hand side b (comps * nodes entries, component-major).
 // Returns the level work vector that holds the result.
 template <typename T, int W, int NC>
-static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr) {
+static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr, int K = 1) {
   MgLevel &L = mg.lv[l];
   T *x = Pr<T>::w(L, 0), *x2 = Pr<T>::w(L, 4), *r = Pr<T>::w(L, 2), *d = Pr<T>::w(L, 3);
+  // K systems (matrix-free hierarchy only): lane k of every level vector at + k comps nodes
+  FSI_REQUIRE(K == 1 || mg.stencil, FSI_E_STATE, "several systems per V-cycle need the matrix-free smoother");
+  const int64_t ls = (int64_t)mg.comps * L.nodes;
   if (l + 1 == (int)mg.lv.size()) {
-    hipLaunchKernelGGL(k_dense_mv<T>, dim3((unsigned)mg.ncoarse), dim3(kWave), 0, s,
+    hipLaunchKernelGGL(k_dense_mv<T>, dim3((unsigned)mg.ncoarse, (unsigned)K), dim3(kWave), 0, s,
                        (int)mg.ncoarse, Pr<T>::cinv(mg), b, x);
     FSI_CHECK_LAUNCH();
     return x;
@@ -309,27 +320,30 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr)
   Prof *pl = (l == 0) ? prof : nullptr;
   MgLevel &C = mg.lv[l + 1];
   T *bc = Pr<T>::w(C, 1);
+  const int64_t lc = (int64_t)mg.comps * C.nodes;
   if (mg.stencil) {   // matrix-free smoothing, residual and transfers
     auto smooth = [&](T *x0, T *x1, bool zero) -> T * {
       if constexpr (W == 4)
-        return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, pl);
+        return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, pl, K, ls);
       else
-        return chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s);
+        return chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, K, ls);
     };
     T *xs = smooth(x, x2, true);
     T *xo = (xs == x) ? x2 : x;
     if constexpr (W == 4) {
-      stencil_launch<T, SP_RESID>(L.n, stab<T>(L), xs, b, nullptr, r, (T)0, (T)0, s);
-      p2_restrict<T>(L.n, rtab<T>(mg), r, bc, s);
+      stencil_launch<T, SP_RESID>(L.n, stab<T>(L), LP<const T>(xs, ls), LP<const T>(b, ls), LP<T>(), LP<T>(r, ls),
+                                  (T)0, (T)0, s, K);
+      p2_restrict<T>(L.n, rtab<T>(mg), LP<const T>(r, ls), LP<T>(bc, lc), s, K);
     } else {
-      p1_launch<T, SP_RESID>(L.n, p1tab<T>(L), xs, b, nullptr, r, (T)0, (T)0, s);
-      p1_restrict<T>(L.n, r, bc, s);
+      p1_launch<T, SP_RESID>(L.n, p1tab<T>(L), LP<const T>(xs, ls), LP<const T>(b, ls), LP<T>(), LP<T>(r, ls),
+                             (T)0, (T)0, s, K);
+      p1_restrict<T>(L.n, LP<const T>(r, ls), LP<T>(bc, lc), s, K);
     }
-    T *xc = vcycle<T, W, NC>(mg, l + 1, bc, s);
+    T *xc = vcycle<T, W, NC>(mg, l + 1, bc, s, nullptr, K);
     if constexpr (W == 4)
-      p2_prolong_add<T>(L.n, xc, xs, s);
+      p2_prolong_add<T>(L.n, LP<const T>(xc, lc), LP<T>(xs, ls), s, K);
     else
-      p1_prolong_add<T>(L.n, xc, xs, s);
+      p1_prolong_add<T>(L.n, LP<const T>(xc, lc), LP<T>(xs, ls), s, K);
     return smooth(xs, xo, false);
   }
   T *xs = chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b, x,
@@ -354,36 +368,47 @@ template <> const float *mp_dinv<float>(Ctx &c) { return c.Mp_dinv32.p; }
 // (measured at 1024^2: 8, 4 and 3 steps give the same outer count; 2 and 1 cost inner steps)
 constexpr int kMpSteps = 4;
 
-// z = diag(V, S^{-1}) r on [u | p].  The two blocks share no buffer: outside graph capture
-// the pressure part runs on the auxiliary stream beside the velocity V-cycle (both chains
-// are latency-bound on the coarse levels), forked after the producer of r and joined
-// before the consumer of z.  Captured graphs keep the whole preconditioner on one stream.
+// z = diag(V, S^{-1}) r on [u | p], for K systems at once (lane k of r and z at + k nf,
+// nf = 2 N2 + Np; K > 1 needs the matrix-free hierarchies).  The two blocks share no
+// buffer: outside graph capture the pressure part runs on the auxiliary stream beside the
+// velocity V-cycle (both chains are latency-bound on the coarse levels), forked after the
+// producer of r and joined before the consumer of z.  Captured graphs keep the whole
+// preconditioner on one stream.
 template <typename T>
-static void a11_precond(Ctx &c, const T *r, T *z) {
+static void a11_precond(Ctx &c, const T *r, T *z, int K = 1) {
   const bool fork = !c.capturing;
   hipStream_t s = c.stream, sp = fork ? c.aux_stream : c.stream;
-  const int64_t N2 = c.N2, Np = c.Np;
+  const int64_t N2 = c.N2, Np = c.Np, nf = 2 * N2 + Np;
   Prof *pf = std::is_same<T, double>::value ? &c.prof64 : &c.prof32;
   if (fork) {
     FSI_HIP(hipEventRecord(c.ev_fork, s));
     FSI_HIP(hipStreamWaitEvent(sp, c.ev_fork, 0));
   }
-  T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr);
-  convert(z, xu, 2 * N2, s);
+  T *xu;
+  if (K == 1) {
+    xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr);
+  } else {   // the finest level's right-hand side: the velocity part of each lane, contiguous
+    T *bu = Pr<T>::w(c.mgu.lv[0], 1);
+    convert_l(LP<T>(bu, 2 * N2), LP<const T>(r, nf), 2 * N2, s, K);
+    xu = vcycle<T, 4, 2>(c.mgu, 0, bu, s, nullptr, K);
+  }
+  convert_l(LP<T>(z, nf), LP<const T>(xu, 2 * N2), 2 * N2, s, K);
   // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
   T *rp = Pr<T>::inner(c, 8).p;
-  convert(rp, r + 2 * N2, Np, sp);
-  fill(rp, 1, (T)0, sp);
-  T *xp = vcycle<T, 1, 1>(c.mgp, 0, rp, sp);
-  T *mx = Pr<T>::inner(c, 7).p, *mx2 = mx + Np, *md = mx + 2 * Np;
+  convert_l(LP<T>(rp, Np), LP<const T>(r + 2 * N2, nf), Np, sp, K);
+  fill_l(LP<T>(rp, Np), 1, (T)0, sp, K);
+  T *xp = vcycle<T, 1, 1>(c.mgp, 0, rp, sp, nullptr, K);
+  // mass solve scratch: x, x2, d of every lane (3 Np each) in one inner vector
+  T *mx = Pr<T>::inner(c, 7).p, *mx2 = mx + (int64_t)K * Np, *md = mx + 2 * (int64_t)K * Np;
   T *mres = c.mgp.stencil
                 ? chebyshev_p1<T>(c.n, (const P1Table<T> *)(std::is_same<T, double>::value ? c.mptab64.p
                                                                                           : c.mptab32.p),
-                                  0.5, 2.0, kMpSteps, rp, mx, mx2, md, true, sp)
+                                  0.5, 2.0, kMpSteps, rp, mx, mx2, md, true, sp, K, Np)
                 : chebyshev<T, 1, 1>(Np, c.Mp.rowptr.p, c.Mp.col.p, Pr<T>::val(c.Mp), mp_dinv<T>(c), 0.5,
                                      2.0, kMpSteps, rp, mx, mx2, md, true, sp);
-  lincomb(z + 2 * N2, mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, sp);
-  hipLaunchKernelGGL(k_set_pinned<T>, dim3(1), dim3(1), 0, sp, z + 2 * N2, r + 2 * N2);
+  lincomb_l(LP<T>(z + 2 * N2, nf), LP<const T>(mres, Np), LP<const T>(xp, Np), (T)c.nu, (T)(c.rho / c.dt), Np,
+            sp, K);
+  hipLaunchKernelGGL(k_set_pinned<T>, dim3(1, K), dim3(1), 0, sp, z + 2 * N2, r + 2 * N2, nf);
   FSI_CHECK_LAUNCH();
   if (fork) {
     FSI_HIP(hipEventRecord(c.ev_join, sp));
@@ -394,77 +419,80 @@ static void a11_precond(Ctx &c, const T *r, T *z) {
 // ---------------------------------------------------------------- inner MINRES
 // The A11 preconditioner on FP64 vectors with arithmetic TA: FP32 runs on converted copies.
 template <typename TA>
-static void a11_precond_on64(Ctx &c, const double *r, double *z) {
+static void a11_precond_on64(Ctx &c, const double *r, double *z, int K = 1) {
   if constexpr (std::is_same<TA, double>::value) {
-    a11_precond<double>(c, r, z);
+    a11_precond<double>(c, r, z, K);
   } else {
     const int64_t nf = 2 * c.N2 + c.Np;
-    convert(c.outer.x32.p, r, nf, c.stream);
-    a11_precond<float>(c, c.outer.x32.p, c.outer.y32.p);
-    convert(z, c.outer.y32.p, nf, c.stream);
+    convert_l(LP<float>(c.outer.x32.p, nf), LP<const double>(r, nf), nf, c.stream, K);
+    a11_precond<float>(c, c.outer.x32.p, c.outer.y32.p, K);
+    convert_l(LP<double>(z, nf), LP<const float>(c.outer.y32.p, nf), nf, c.stream, K);
   }
 }
 
-// The preconditioner through a HIP graph: captured once per precision on the staging
-// buffers (a fixed sequence of kernels with fixed arguments), then replayed.  Only kernel
-// nodes are captured (copies are kernels too).
+// Capture `body` (kernel launches on c.stream) into an executable graph; the capture runs
+// on the context's capture stream (the NULL stream cannot be captured) and only records.
+template <typename Body>
+static void capture_graph(Ctx &c, hipGraphExec_t &ge, Body body) {
+  hipStream_t s = c.stream;
+  if (!c.cap_stream) FSI_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  FSI_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
+  c.stream = c.cap_stream;
+  c.capturing = true;
+  try {
+    body();
+  } catch (...) {
+    c.stream = s;
+    c.capturing = false;
+    hipStreamEndCapture(c.cap_stream, &g);
+    if (g) hipGraphDestroy(g);
+    throw;
+  }
+  c.stream = s;
+  c.capturing = false;
+  FSI_HIP(hipStreamEndCapture(c.cap_stream, &g));
+  hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  FSI_HIP(e);
+}
+
+// The preconditioner through a HIP graph: captured once per precision and lane count on the
+// staging buffers (a fixed sequence of kernels with fixed arguments), then replayed.  Only
+// kernel nodes are captured (copies are kernels too).
 template <typename TA>
-static void a11_precond_graph(Ctx &c, const double *r, double *z) {
+static void a11_precond_graph(Ctx &c, const double *r, double *z, int K) {
   hipStream_t s = c.stream;
   const int64_t nf = 2 * c.N2 + c.Np;
   const int k = std::is_same<TA, double>::value ? 0 : 1;
-  if (!c.pc_in.p) {
-    c.pc_in.alloc(nf);
-    c.pc_out.alloc(nf);
-  }
-  convert(c.pc_in.p, r, nf, s);
-  if (!c.pc_graph[k]) {
-    // capture on the context's own stream (the NULL stream cannot be captured); the
-    // capture only records, the replay below runs on the caller's stream
-    if (!c.cap_stream) FSI_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    FSI_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
-    c.stream = c.cap_stream;
-    c.capturing = true;
-    try {
-      a11_precond_on64<TA>(c, c.pc_in.p, c.pc_out.p);
-    } catch (...) {
-      c.stream = s;
-      c.capturing = false;
-      hipStreamEndCapture(c.cap_stream, &g);
-      if (g) hipGraphDestroy(g);
-      throw;
-    }
-    c.stream = s;
-    c.capturing = false;
-    FSI_HIP(hipStreamEndCapture(c.cap_stream, &g));
-    hipError_t e = hipGraphInstantiate(&c.pc_graph[k], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    FSI_HIP(e);
-  }
-  FSI_HIP(hipGraphLaunch(c.pc_graph[k], s));
-  convert(z, c.pc_out.p, nf, s);
+  convert_l(LP<double>(c.pc_in.p, nf), LP<const double>(r, nf), nf, s, K);
+  hipGraphExec_t &ge = c.pc_graph[k][K];
+  if (!ge) capture_graph(c, ge, [&] { a11_precond_on64<TA>(c, c.pc_in.p, c.pc_out.p, K); });
+  FSI_HIP(hipGraphLaunch(ge, s));
+  convert_l(LP<double>(z, nf), LP<const double>(c.pc_out.p, nf), nf, s, K);
 }
 
 template <typename TA>
-static void a11_precond_any(Ctx &c, const double *r, double *z) {
+static void a11_precond_any(Ctx &c, const double *r, double *z, int K = 1) {
   const bool profiling = c.prof64.on || c.prof32.on;
-  if (c.use_graphs && !profiling) a11_precond_graph<TA>(c, r, z);
-  else a11_precond_on64<TA>(c, r, z);
+  if (c.use_graphs && !profiling) a11_precond_graph<TA>(c, r, z, K);
+  else a11_precond_on64<TA>(c, r, z, K);
 }
 
 void Ctx::drop_graphs() {
-  for (auto &g : pc_graph)
-    if (g) {
-      hipGraphExecDestroy(g);
-      g = nullptr;
-    }
-  for (auto &row : ms_graph)
+  for (auto &row : pc_graph)
     for (auto &g : row)
       if (g) {
         hipGraphExecDestroy(g);
         g = nullptr;
       }
+  for (auto &per_k : ms_graph)
+    for (auto &row : per_k)
+      for (auto &g : row)
+        if (g) {
+          hipGraphExecDestroy(g);
+          g = nullptr;
+        }
 }
 
 // Preconditioned MINRES (Paige-Saunders recurrences) for A11 x = b from x = 0; stops when
@@ -489,8 +517,11 @@ struct MinresState {
 };
 constexpr int kMsDoubles = sizeof(MinresState) / sizeof(double);
 
+// The kernels below run K systems (lane = blockIdx.y): lane k uses st + k and vectors at
+// + k n (n = nf, the lane stride of every inner vector).
 __global__ void k_ms_init(MinresState *st, double tol) {
   if (threadIdx.x || blockIdx.x) return;
+  st += blockIdx.y;
   double b2 = st->beta2;
   double b = (b2 > 0.0 && b2 == b2) ? sqrt(b2) : 0.0;
   st->beta = st->beta1 = st->phibar = b;
@@ -507,6 +538,7 @@ __global__ void k_ms_init(MinresState *st, double tol) {
 // After the two dot products of an iteration: Givens rotation and the next coefficients.
 __global__ void k_ms_step(MinresState *st) {
   if (threadIdx.x || blockIdx.x) return;
+  st += blockIdx.y;
   if (st->done != 0.0) {
     st->apply = 0.0;
     return;
@@ -539,37 +571,43 @@ __global__ void k_ms_step(MinresState *st) {
 
 // v = s y
 __global__ void k_ms_scale(double *v, const double *y, const MinresState *st, int64_t n) {
-  const double a = st->s;
+  const int64_t o = (int64_t)blockIdx.y * n;
+  const double a = st[blockIdx.y].s;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    v[i] = a * y[i];
+    v[o + i] = a * y[o + i];
 }
 
 // y += c_r1 r1 - (alfa s) r2   (the second term after alfa is known: two launches)
 __global__ void k_ms_axpy(double *y, const double *r, const MinresState *st, int which, int64_t n) {
-  const double a = which == 0 ? st->c_r1 : -st->alfa * st->s;
+  const MinresState &q = st[blockIdx.y];
+  const double a = which == 0 ? q.c_r1 : -q.alfa * q.s;
   if (a == 0.0) return;
+  const int64_t o = (int64_t)blockIdx.y * n;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    y[i] += a * r[i];
+    y[o + i] += a * r[o + i];
 }
 
 // wn = (v - e w1 - d w2) ginv;  x += phi wn   (skipped once converged)
 __global__ void k_ms_update(double *wn, const double *v, const double *w1, const double *w2, double *x,
                             const MinresState *st, int64_t n) {
-  if (st->apply == 0.0) return;
-  const double e = st->e, d = st->d, g = st->ginv, phi = st->phi;
+  const MinresState &q = st[blockIdx.y];
+  if (q.apply == 0.0) return;
+  const double e = q.e, d = q.d, g = q.ginv, phi = q.phi;
+  const int64_t o = (int64_t)blockIdx.y * n;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const double w = (v[i] - e * w1[i] - d * w2[i]) * g;
-    wn[i] = w;
-    x[i] += phi * w;
+    const double w = (v[o + i] - e * w1[o + i] - d * w2[o + i]) * g;
+    wn[o + i] = w;
+    x[o + i] += phi * w;
   }
 }
 
-// alfa = sum of the per-tile parts of v . y (one block, fixed order)
+// alfa = sum of the per-tile parts of v . y (one block per lane, fixed order)
 __global__ void k_ms_alfa(const double *part, int n, MinresState *st) {
   __shared__ double red[256 / kWave];
+  part += (int64_t)blockIdx.y * n;
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
   acc = wave_sum(acc);
@@ -578,12 +616,13 @@ __global__ void k_ms_alfa(const double *part, int n, MinresState *st) {
   if (threadIdx.x == 0) {
     double b = 0.0;
     for (int k = 0; k < 256 / kWave; ++k) b += red[k];
-    st->alfa = b;
+    st[blockIdx.y].alfa = b;
   }
 }
 
 // Buffers of one rotation phase (0, 1, 2).  Lanczos: r1 (old), r2 (current), y (new);
-// directions: w1 (two back, overwritten by the new one), w2, w.
+// directions: w1 (two back, overwritten by the new one), w2, w.  Lane 0 of each (lane
+// stride nf).
 struct MsBufs {
   double *v, *r1, *r2, *y, *w1, *w2, *w, *x;
 };
@@ -615,27 +654,30 @@ static MsBufs ms_bufs_fused(Ctx &c, double *x, int it) {
   return b;
 }
 
-// One inner iteration with the matrix-free A11 (FP64): the scaling v = s y, the product, the
-// first three-term update and the dot product alfa = v . y are one tiled launch (new y over
-// r1); then y -= alfa s r2, z = M y into the y buffer, beta^2 = y . z.
+// One inner iteration with the matrix-free A11 (FP64) for K systems: the scaling v = s y,
+// the product, the first three-term update and the dot product alfa = v . y are one tiled
+// launch (new y over r1); then y -= alfa s r2, z = M y into the y buffer, beta^2 = y . z.
 template <typename TA>
-static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st) {
+static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st, int K) {
   hipStream_t s = c.stream;
   const int64_t nf = 2 * c.N2 + c.Np;
   const unsigned g = vgrid(nf);
   double *dv = (double *)st;
-  const int tiles = stencil_a11_minres(c.n, (const StencilTable<double> *)c.mgu.lv[0].stab64.p,
-                                       (const DivTable<double> *)c.divtab64.p, b.y, b.v, b.r1, &st->s,
-                                       &st->c_r1, c.ms_part.p, s);
-  hipLaunchKernelGGL(k_ms_alfa, dim3(1), dim3(256), 0, s, c.ms_part.p, tiles, st);
-  hipLaunchKernelGGL(k_ms_axpy, dim3(g), dim3(256), 0, s, b.r1, b.r2, st, 1, nf);
-  a11_precond_on64<TA>(c, b.r1, b.y);
-  multidot(b.r1, 0, 1, b.y, nf, dv + 1, c.ms_red, s);
-  hipLaunchKernelGGL(k_ms_step, dim3(1), dim3(1), 0, s, st);
-  hipLaunchKernelGGL(k_ms_update, dim3(g), dim3(256), 0, s, b.w1, b.v, b.w2, b.w, b.x, st, nf);
+  const int tiles = stencil_tile_count(c.n);
+  stencil_a11_minres(c.n, (const StencilTable<double> *)c.mgu.lv[0].stab64.p, (const DivTable<double> *)c.divtab64.p,
+                     LP<const double>(b.y, nf), LP<double>(b.v, nf), LP<double>(b.r1, nf),
+                     LP<const double>(&st->s, kMsDoubles), LP<const double>(&st->c_r1, kMsDoubles),
+                     LP<double>(c.ms_part.p, tiles), s, K);
+  hipLaunchKernelGGL(k_ms_alfa, dim3(1, K), dim3(256), 0, s, c.ms_part.p, tiles, st);
+  hipLaunchKernelGGL(k_ms_axpy, dim3(g, K), dim3(256), 0, s, b.r1, b.r2, st, 1, nf);
+  a11_precond_on64<TA>(c, b.r1, b.y, K);
+  dot_l(LP<const double>(b.r1, nf), LP<const double>(b.y, nf), nf, LP<double>(dv + 1, kMsDoubles), c.ms_red.p, s, K);
+  hipLaunchKernelGGL(k_ms_step, dim3(1, K), dim3(1), 0, s, st);
+  hipLaunchKernelGGL(k_ms_update, dim3(g, K), dim3(256), 0, s, b.w1, b.v, b.w2, b.w, b.x, st, nf);
   FSI_CHECK_LAUNCH();
 }
 
+// The same with the assembled A11 (one system)
 template <typename TA>
 static void ms_iteration(Ctx &c, const MsBufs &b, MinresState *st) {
   hipStream_t s = c.stream;
@@ -655,84 +697,78 @@ static void ms_iteration(Ctx &c, const MsBufs &b, MinresState *st) {
   FSI_CHECK_LAUNCH();
 }
 
+// MINRES on K systems A11 x_k = b_k in lockstep (host arrays of K device vectors; K > 1
+// needs the matrix-free A11).  Every system has its own scalar state and stops updating its
+// x once converged; the loop ends when all have.  its[k] = iterations of system k.
 template <typename TA>
-static int minres_a11(Ctx &c, const double *b, double *xout, double tol, int maxit) {
+static void minres_a11(Ctx &c, const double *const *b, double *const *xout, int K, double tol, int maxit,
+                       int *its) {
   hipStream_t s = c.stream;
   const int64_t nf = 2 * c.N2 + c.Np;
+  const bool fused = c.mgu.stencil;   // matrix-free FP64 A11
+  FSI_REQUIRE(K >= 1 && K <= c.lanes, FSI_E_ARG, "more systems than inner lanes");
+  FSI_REQUIRE(K == 1 || fused, FSI_E_STATE, "several systems per inner solve need the matrix-free smoother");
   MinresState *st = (MinresState *)c.ms_state.p;
   double *dv = (double *)st;
   double *x = c.ms_x.p;
   MsBufs b0 = ms_bufs(c, x, 0);
-  fill(x, nf, 0.0, s);
-  fill(b0.w, nf, 0.0, s);
-  fill(b0.w2, nf, 0.0, s);
+  fill_l(LP<double>(x, nf), nf, 0.0, s, K);
+  fill_l(LP<double>(b0.w, nf), nf, 0.0, s, K);
+  fill_l(LP<double>(b0.w2, nf), nf, 0.0, s, K);
   // phase 0 expects: r2 = current Lanczos vector, y = M r2
-  convert(b0.r2, b, nf, s);
-  a11_precond_any<TA>(c, b0.r2, b0.y);
-  multidot(b0.r2, 0, 1, b0.y, nf, dv + 1, c.ms_red, s);
-  hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(1), 0, s, st, tol);
+  for (int k = 0; k < K; ++k) convert(b0.r2 + k * nf, b[k], nf, s);
+  a11_precond_any<TA>(c, b0.r2, b0.y, K);
+  dot_l(LP<const double>(b0.r2, nf), LP<const double>(b0.y, nf), nf, LP<double>(dv + 1, kMsDoubles), c.ms_red.p, s,
+        K);
+  hipLaunchKernelGGL(k_ms_init, dim3(1, K), dim3(1), 0, s, st, tol);
   FSI_CHECK_LAUNCH();
   const bool graphs = c.use_graphs && !(c.prof64.on || c.prof32.on);
   const int check_every = graphs ? 8 : 1;
-  const int k = std::is_same<TA, double>::value ? 0 : 1;
+  const int pk = std::is_same<TA, double>::value ? 0 : 1;
   int it = 0;
   double *h = c.hpin;
-  const bool fused = c.mgu.stencil;   // matrix-free FP64 A11
+  auto all_done = [&]() {
+    FSI_HIP(hipMemcpyAsync(h, st, (size_t)K * kMsDoubles * sizeof(double), hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    bool done = true;
+    for (int k = 0; k < K; ++k) {
+      const MinresState *hs = (const MinresState *)h + k;
+      FSI_REQUIRE(hs->phibar == hs->phibar && hs->beta == hs->beta, FSI_E_NONFINITE,
+                  "non-finite value in the inner A11 solve");
+      done = done && hs->done != 0.0;
+    }
+    return done;
+  };
   while (it < maxit) {
     // the rotation: in phase p the roles are shifted by p (r2 of phase p is y of p-1, ...)
     const int phase = fused ? it % 6 : it % 3;
     const MsBufs bq = fused ? ms_bufs_fused(c, x, it) : ms_bufs(c, x, phase);
     if (graphs) {
-      hipGraphExec_t &ge = c.ms_graph[k][phase];
-      if (!ge) {
-        if (!c.cap_stream) FSI_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
-        hipGraph_t g = nullptr;
-        FSI_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
-        c.stream = c.cap_stream;
-        c.capturing = true;
-        try {
-          if (fused) ms_iteration_fused<TA>(c, bq, st);
+      hipGraphExec_t &ge = c.ms_graph[pk][K][phase];
+      if (!ge)
+        capture_graph(c, ge, [&] {
+          if (fused) ms_iteration_fused<TA>(c, bq, st, K);
           else ms_iteration<TA>(c, bq, st);
-        } catch (...) {
-          c.stream = s;
-          c.capturing = false;
-          hipStreamEndCapture(c.cap_stream, &g);
-          if (g) hipGraphDestroy(g);
-          throw;
-        }
-        c.stream = s;
-        c.capturing = false;
-        FSI_HIP(hipStreamEndCapture(c.cap_stream, &g));
-        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
-        FSI_HIP(e);
-      }
+        });
       FSI_HIP(hipGraphLaunch(ge, s));
     } else if (fused) {
-      ms_iteration_fused<TA>(c, bq, st);
+      ms_iteration_fused<TA>(c, bq, st, K);
     } else {
       ms_iteration<TA>(c, bq, st);
     }
     ++it;
-    if (it % check_every == 0 || it == maxit) {
-      FSI_HIP(hipMemcpyAsync(h, st, kMsDoubles * sizeof(double), hipMemcpyDeviceToHost, s));
-      FSI_HIP(hipStreamSynchronize(s));
-      const MinresState *hs = (const MinresState *)h;
-      FSI_REQUIRE(hs->phibar == hs->phibar && hs->beta == hs->beta, FSI_E_NONFINITE,
-                  "non-finite value in the inner A11 solve");
-      if (hs->done != 0.0) break;
-    }
+    if ((it % check_every == 0 || it == maxit) && all_done()) break;
   }
-  FSI_HIP(hipMemcpyAsync(h, st, kMsDoubles * sizeof(double), hipMemcpyDeviceToHost, s));
-  FSI_HIP(hipStreamSynchronize(s));
-  const MinresState *hs = (const MinresState *)h;
-  const int its = (int)hs->it;
-  convert(xout, x, nf, s);
-  if (trace_on())
-    std::fprintf(stderr, "[fsi] minres<%s> its=%d relres_est=%.3e beta=%.3e graphs=%d\n",
-                 std::is_same<TA, double>::value ? "f64" : "f32", its,
-                 hs->beta1 > 0 ? hs->phibar / hs->beta1 : 0.0, hs->beta, graphs ? 1 : 0);
-  return its;
+  all_done();
+  for (int k = 0; k < K; ++k) {
+    const MinresState *hs = (const MinresState *)h + k;
+    its[k] = (int)hs->it;
+    convert(xout[k], x + k * nf, nf, s);
+    if (trace_on())
+      std::fprintf(stderr, "[fsi] minres<%s> lane=%d/%d its=%d relres_est=%.3e beta=%.3e graphs=%d\n",
+                   std::is_same<TA, double>::value ? "f64" : "f32", k, K, its[k],
+                   hs->beta1 > 0 ? hs->phibar / hs->beta1 : 0.0, hs->beta, graphs ? 1 : 0);
+  }
 }
 
 // ---------------------------------------------------------------- A22 closed form (FP64)
@@ -760,21 +796,48 @@ static void a22_solve(Ctx &c, const double *rX, const double *rl, double *zX, do
 }
 
 // ---------------------------------------------------------------- block preconditioner
-static void ensure_inner(Ctx &c, int prec) {
+// Inner work space for K systems: the MINRES vectors and state, the V-cycle level vectors
+// and the staging of the captured preconditioner hold c.lanes systems each (lane stride =
+// one system's length).  Growing the lane count reallocates them and drops the captured
+// graphs (they hold the old addresses).
+static void ensure_inner(Ctx &c, int prec, int K = 1) {
+  FSI_REQUIRE(K >= 1 && K <= FSI_MAX_LANES, FSI_E_ARG, "lane count out of range");
   const int64_t nf = 2 * c.N2 + c.Np;
+  if (K > c.lanes) {
+    c.drop_graphs();
+    for (int i = 0; i < 9; ++i) {
+      c.inner.v64[i].release();
+      c.inner.v32[i].release();
+    }
+    for (auto *b : {&c.ms_x, &c.ms_state, &c.ms_red, &c.ms_part, &c.pc_in, &c.pc_out}) b->release();
+    c.outer.x32.release();
+    c.outer.y32.release();
+    for (Mg *mg : {&c.mgu, &c.mgp})
+      for (auto &L : mg->lv)
+        for (int i = 0; i < 5; ++i) {
+          L.w64[i].alloc((size_t)K * mg->comps * L.nodes);
+          L.w32[i].release();   // reallocated at the new size by ensure_fp32_mg
+        }
+    c.lanes = K;
+  }
+  const int64_t nl = c.lanes;
   for (int i = 0; i < 9; ++i)
-    if (!c.inner.v64[i].p) c.inner.v64[i].alloc(nf);
+    if (!c.inner.v64[i].p) c.inner.v64[i].alloc(nl * nf);
   if (!c.ms_x.p) {
-    c.ms_x.alloc(nf);
-    c.ms_state.alloc(kMsDoubles);
-    c.ms_red.alloc(red_blocks(nf));   // multidot with k = 1: never regrown
-    c.ms_part.alloc(stencil_tile_count(c.n));
+    c.ms_x.alloc(nl * nf);
+    c.ms_state.alloc(nl * kMsDoubles);
+    c.ms_red.alloc(nl * red_blocks(nf));   // dot products of one system per lane: never regrown
+    c.ms_part.alloc(nl * stencil_tile_count(c.n));
+  }
+  if (!c.pc_in.p) {
+    c.pc_in.alloc(nl * nf);
+    c.pc_out.alloc(nl * nf);
   }
   if (prec == FSI_FP32) {
     ensure_fp32_mg(c);
     for (int i = 7; i < 9; ++i)       // pressure scratch of the FP32 preconditioner
-      if (!c.inner.v32[i].p) c.inner.v32[i].alloc(nf);
-    if (!c.outer.x32.p) { c.outer.x32.alloc(nf); c.outer.y32.alloc(nf); }
+      if (!c.inner.v32[i].p) c.inner.v32[i].alloc(nl * nf);
+    if (!c.outer.x32.p) { c.outer.x32.alloc(nl * nf); c.outer.y32.alloc(nl * nf); }
     if (!c.Mp_dinv32.p) {
       c.Mp_dinv32.alloc(c.Np);
       convert(c.Mp_dinv32.p, c.Mp_dinv.p, c.Np, c.stream);
@@ -782,9 +845,6 @@ static void ensure_inner(Ctx &c, int prec) {
   }
 }
 
-// Default inner tolerances: FGMRES is flexible, and on the evaluated workloads the outer
-// iteration count with these equals the count with exact A11 solves (measured: 1e-10 and
-// 1e-4 both give 9 outer steps at 256^2 and 1024^2); FP32 MINRES stagnates near 1e-6.
 // Default inner tolerances (flexible outer GMRES: they trade outer for inner steps).
 // Measured on the 256^2 / 512^2 / 1024^2 workloads, FP64 from 1e-4 to 3e-3: outer steps
 // 9->10 / 5->5 / 9->9, step time -13% / -31% / -23%; mixed from 1e-3 to 1e-2: outer
@@ -794,39 +854,48 @@ double inner_tol(const Ctx &c, int prec) {
   return prec == FSI_FP64 ? 3e-3 : 1e-2;
 }
 
-void apply_precond(Ctx &c, int pc, int prec, const double *r, double *z) {
-  hipStream_t s = c.stream;
+// The block preconditioner on K systems: system k belongs to context cs[k] (one fluid grid
+// and fluid parameters for all); the A11 solves of all run in lockstep on the inner lanes of
+// the engine context c (one of them or another of the same grid) with its inner and smoother
+// settings, then each system's A22 part on its own context.  Every context's stream must be
+// c's for the call.
+void apply_precond_lanes(Ctx &c, Ctx *const *cs, int K, int pc, int prec, const double *const *r,
+                         double *const *z) {
   FSI_REQUIRE(pc == FSI_PC_DIAG || pc == FSI_PC_TRI, FSI_E_ARG, "unknown preconditioner");
   FSI_REQUIRE(prec == FSI_FP64 || prec == FSI_FP32 || prec == FSI_FP32_IR, FSI_E_ARG,
               "unknown precision");
   if (prec == FSI_FP32_IR) prec = FSI_FP32;
-  FSI_REQUIRE(c.have_cf || pc == FSI_PC_DIAG, FSI_E_STATE, "block-triangular needs C_f: call fsi_assemble_coupling");
-  ensure_inner(c, prec);
-  const int64_t nf = 2 * c.N2 + c.Np, ns = c.Ns;
+  for (int k = 0; k < K; ++k)
+    FSI_REQUIRE(cs[k]->have_cf || pc == FSI_PC_DIAG, FSI_E_STATE,
+                "block-triangular needs C_f: call fsi_assemble_coupling");
+  ensure_inner(c, prec, K);
   const double tol = inner_tol(c, prec);
-  int its = prec == FSI_FP64 ? minres_a11<double>(c, r, z, tol, c.inner_maxit)
-                             : minres_a11<float>(c, r, z, tol, c.inner_maxit);
-  c.inner_its_total += its;
-  const double *rX = r + nf, *rl = r + nf + 2 * ns;
-  double *zX = z + nf, *zl = z + nf + 2 * ns;
-  if (pc == FSI_PC_TRI) {
-    // r_lam - C_f z_u  (A21 z1 = [0; C_f z_u])
-    double *t = c.tmpS.p + 8 * ns;
-    spmv<double, 1, 2, SP_RESID>(ns, c.Cf.rowptr.p, c.Cf.col.p, c.Cf.val.p, z, c.N2, t, ns, s, rl);
-    rl = t;
+  int its[FSI_MAX_LANES];
+  if (prec == FSI_FP64) minres_a11<double>(c, r, z, K, tol, c.inner_maxit, its);
+  else minres_a11<float>(c, r, z, K, tol, c.inner_maxit, its);
+  for (int k = 0; k < K; ++k) {
+    Ctx &ck = *cs[k];
+    ck.inner_its_total += its[k];
+    hipStream_t s = ck.stream;
+    const int64_t nf = 2 * ck.N2 + ck.Np, ns = ck.Ns;
+    const double *rX = r[k] + nf, *rl = r[k] + nf + 2 * ns;
+    double *zX = z[k] + nf, *zl = z[k] + nf + 2 * ns;
+    if (pc == FSI_PC_TRI) {
+      // r_lam - C_f z_u  (A21 z1 = [0; C_f z_u])
+      double *t = ck.tmpS.p + 8 * ns;
+      spmv<double, 1, 2, SP_RESID>(ns, ck.Cf.rowptr.p, ck.Cf.col.p, ck.Cf.val.p, z[k], ck.N2, t, ns, s, rl);
+      rl = t;
+    }
+    a22_solve(ck, rX, rl, zX, zl);
   }
-  a22_solve(c, rX, rl, zX, zl);
+}
+
+void apply_precond(Ctx &c, int pc, int prec, const double *r, double *z) {
+  Ctx *cs[1] = {&c};
+  apply_precond_lanes(c, cs, 1, pc, prec, &r, &z);
 }
 
 // ---------------------------------------------------------------- outer FGMRES
-template <typename T>
-static double dev_dot(Ctx &c, const double *x, const double *y, int64_t n) {
-  multidot(x, 0, 1, y, n, c.dscal.p, c.red, c.stream);
-  FSI_HIP(hipMemcpyAsync(c.hpin, c.dscal.p, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-  FSI_HIP(hipStreamSynchronize(c.stream));
-  return c.hpin[0];
-}
-
 static void op_apply(Ctx &c, int prec, const double *x, double *y) {
   if (prec == FSI_FP64) apply_operator<double, double>(c, x, y, false);
   else apply_operator<float, double>(c, x, y, false);
@@ -838,78 +907,40 @@ static void residual64(Ctx &c, const double *b, const double *x, double *r) {
   axpby(r, b, 1.0, -1.0, c.N, c.stream);
 }
 
-struct CycleOut {
-  int steps;
-  double est;
+// One system of a lockstep FGMRES solve: its context, vectors, statistics and the state
+// of its current restart cycle.
+struct GmLane {
+  Ctx *c = nullptr;
+  const double *b = nullptr;
+  double *x = nullptr;
+  fsi_solve_stats S{};
+  double bnorm = 0.0, target = 0.0, rn = 0.0;
+  enum { RESID, CYCLE, DONE } state = RESID;
+  int rc = FSI_OK;
+  std::string err;
+  // restart cycle: Hessenberg columns (rotated), Givens rotations, rotated right-hand side
+  std::vector<double> H, cs, sn, g;
+  int j = 0, maxsteps = 0;
+  double est = 0.0, cyc_target = 0.0;
+  void fail(int code, const char *msg) {
+    rc = code;
+    err = msg;
+    state = DONE;
+  }
 };
 
-// One FGMRES cycle of at most `maxsteps` Arnoldi steps on A d = r0 (beta = ||r0||) with
-// operator and preconditioner in precision `prec`; adds the correction to x.
-static CycleOut fgmres_cycle(Ctx &c, int m, int pc, int op_prec, int pc_prec, const double *r0,
-                             double beta, double target, int maxsteps, double *x) {
-  hipStream_t s = c.stream;
-  const int64_t N = c.N;
-  double *V = c.outer.V.p, *Z = c.outer.Z.p, *w = c.outer.w.p;
-  lincomb(V, r0, r0, 1.0 / beta, 0.0, N, s);
-  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
-  g[0] = beta;
-  int k = 0;
-  double est = beta;
-  double *dh = c.dscal.p + 8;   // h1 (m+1), h2 (m+1), hn2
-  for (int j = 0; j < maxsteps && j < m; ++j) {
-    double *Vj = V + (int64_t)j * N, *Zj = Z + (int64_t)j * N;
-    apply_precond(c, pc, pc_prec, Vj, Zj);
-    op_apply(c, op_prec, Zj, w);
-    multidot(V, N, j + 1, w, N, dh, c.red, s);
-    hipLaunchKernelGGL(k_multiaxpy_sub, dim3(vgrid(N)), dim3(256), 0, s, w, V, N, j + 1, dh, N);
-    multidot(V, N, j + 1, w, N, dh + (m + 1), c.red, s);
-    hipLaunchKernelGGL(k_multiaxpy_sub, dim3(vgrid(N)), dim3(256), 0, s, w, V, N, j + 1, dh + (m + 1), N);
-    multidot(w, 0, 1, w, N, dh + 2 * (m + 1), c.red, s);
-    FSI_CHECK_LAUNCH();
-    FSI_HIP(hipMemcpyAsync(c.hpin, dh, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-    FSI_HIP(hipStreamSynchronize(s));
-    double *hcol = &H[(size_t)j * (m + 1)];   // column j, rows 0..j+1
-    for (int i = 0; i <= j; ++i) hcol[i] = c.hpin[i] + c.hpin[(m + 1) + i];
-    double hn = std::sqrt(c.hpin[2 * (m + 1)] > 0 ? c.hpin[2 * (m + 1)] : 0.0);
-    FSI_REQUIRE(std::isfinite(hn), FSI_E_NONFINITE, "non-finite Arnoldi vector");
-    hcol[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-      double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
-      hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
-      hcol[i] = t;
-    }
-    double den = std::hypot(hcol[j], hcol[j + 1]);
-    cs[j] = hcol[j] / den;
-    sn[j] = hcol[j + 1] / den;
-    hcol[j] = den;
-    hcol[j + 1] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    k = j + 1;
-    est = std::fabs(g[j + 1]);
-    if (est <= target || hn == 0.0) break;
-    lincomb(V + (int64_t)(j + 1) * N, w, w, 1.0 / hn, 0.0, N, s);
-  }
-  // back substitution H y = g
-  std::vector<double> y(k, 0.0);
-  for (int i = k - 1; i >= 0; --i) {
-    double t = g[i];
-    for (int q = i + 1; q < k; ++q) t -= H[(size_t)q * (m + 1) + i] * y[q];
-    y[i] = t / H[(size_t)i * (m + 1) + i];
-  }
-  if (k > 0) {
-    for (int i = 0; i < k; ++i) c.hpin[i] = y[i];
-    FSI_HIP(hipMemcpyAsync(dh, c.hpin, k * sizeof(double), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_multiaxpy_add, dim3(vgrid(N)), dim3(256), 0, s, x, Z, N, k, dh, N);
-    FSI_CHECK_LAUNCH();
-    FSI_HIP(hipStreamSynchronize(s));   // hpin is reused by the next call
-  }
-  return {k, est};
-}
-
-void gmres_solve(Ctx &c, const fsi_solve_opts &o, const double *b, double *x, fsi_solve_stats *st) {
-  hipStream_t s = c.stream;
-  FSI_REQUIRE(c.have_cf, FSI_E_STATE, "the solve needs C_f: call fsi_assemble_coupling first");
+// FGMRES on K systems in lockstep (system k on context cs[k]: same fluid grid, parameters and
+// options for all; every call runs on cs[0]'s stream, and cs[0] holds the inner lanes).  Each system follows exactly the
+// sequence of operations of a solve on its own: restarted cycles of at most `restart`
+// Arnoldi steps, each with the block preconditioner (all systems' A11 solves batched) and
+// the FP64 or FP32 operator, modified Gram-Schmidt done twice, Givens rotations on the host;
+// a system leaves the batch when its true residual meets rtol or its step budget is spent.
+// rc[k] = FSI_OK, FSI_E_NOCONV or FSI_E_NONFINITE (msg in cs[k]->last_error).
+void gmres_solve_lanes(Ctx *const *cs, int K, const fsi_solve_opts &o, const double *const *b,
+                       double *const *x, fsi_solve_stats *st, int *rc) {
+  Ctx &c0 = *cs[0];
+  hipStream_t s = c0.stream;
+  FSI_REQUIRE(K >= 1 && K <= FSI_MAX_LANES, FSI_E_ARG, "lane count out of range");
   const int m = o.restart > 0 ? o.restart : 30;
   FSI_REQUIRE(m <= 200, FSI_E_ARG, "restart length above 200");
   const int maxit = o.maxit > 0 ? o.maxit : 10000;
@@ -921,66 +952,198 @@ void gmres_solve(Ctx &c, const fsi_solve_opts &o, const double *b, double *x, fs
   const int op_prec = prec == FSI_FP32_IR ? FSI_FP32 : FSI_FP64;
   const int pc_prec = prec == FSI_FP64 ? FSI_FP64 : FSI_FP32;
   const bool refine = prec == FSI_FP32_IR;
-  // per-solve inner settings; the context's own (fsi_set_inner) come back afterwards
+  const double cyc = o.cycle_rtol > 0 ? o.cycle_rtol : 1e-5;
+  // per-solve inner settings; each context's own (fsi_set_inner) come back afterwards
   struct Restore {
-    Ctx &c;
+    Ctx *c;
     double r;
     int m;
-    ~Restore() { c.inner_rtol = r; c.inner_maxit = m; }
-  } restore{c, c.inner_rtol, c.inner_maxit};
-  if (o.inner_rtol > 0) c.inner_rtol = o.inner_rtol;
-  if (o.inner_maxit > 0) c.inner_maxit = o.inner_maxit;
-  else if (prec == FSI_FP32) c.inner_maxit = std::min(c.inner_maxit, 300);
-  const int64_t N = c.N;
-  if (c.outer.m < m || c.outer.ncap < N) {
-    const int mm = std::max(m, c.outer.m);
-    const int64_t nn = std::max(N, c.outer.ncap);
-    c.outer.V.alloc((size_t)(mm + 1) * nn);
-    c.outer.Z.alloc((size_t)mm * nn);
-    c.outer.m = mm;
-    c.outer.ncap = nn;
+    ~Restore() { c->inner_rtol = r; c->inner_maxit = m; }
+  };
+  std::vector<Restore> restore;
+  restore.reserve(K);
+  std::vector<GmLane> L(K);
+  for (int k = 0; k < K; ++k) {
+    Ctx &c = *cs[k];
+    FSI_REQUIRE(c.have_cf, FSI_E_STATE, "the solve needs C_f: call fsi_assemble_coupling first");
+    FSI_REQUIRE(c.stream == s, FSI_E_STATE, "systems of one lockstep solve share one stream");
+    restore.push_back({&c, c.inner_rtol, c.inner_maxit});
+    if (o.inner_rtol > 0) c.inner_rtol = o.inner_rtol;
+    if (o.inner_maxit > 0) c.inner_maxit = o.inner_maxit;
+    else if (prec == FSI_FP32) c.inner_maxit = std::min(c.inner_maxit, 300);
+    const int64_t N = c.N;
+    if (c.outer.m < m || c.outer.ncap < N) {
+      const int mm = std::max(m, c.outer.m);
+      const int64_t nn = std::max(N, c.outer.ncap);
+      c.outer.V.alloc((size_t)(mm + 1) * nn);
+      c.outer.Z.alloc((size_t)mm * nn);
+      c.outer.m = mm;
+      c.outer.ncap = nn;
+    }
+    c.outer.w.reserve(N);
+    c.outer.r.reserve(N);
+    c.dscal.reserve(8 + 2 * (m + 1) + 1 + 64);
+    c.inner_its_total = 0;
+    L[k].c = &c;
+    L[k].b = b[k];
+    L[k].x = x[k];
+    L[k].H.assign((size_t)(m + 1) * m, 0.0);
+    L[k].cs.assign(m, 0.0);
+    L[k].sn.assign(m, 0.0);
+    L[k].g.assign(m + 1, 0.0);
   }
-  c.outer.w.reserve(N);
-  c.outer.r.reserve(N);
-  c.dscal.reserve(8 + 2 * (m + 1) + 1 + 64);
-  c.inner_its_total = 0;
-  fsi_solve_stats S{};
-  double bnorm = std::sqrt(dev_dot<double>(c, b, b, N));
-  FSI_REQUIRE(std::isfinite(bnorm), FSI_E_NONFINITE, "non-finite right-hand side");
-  if (bnorm == 0.0) {
-    fill(x, N, 0.0, s);
-    S.converged = 1;
-    if (st) *st = S;
-    return;
+  // ||b||: one dot product per system, one synchronisation for all
+  for (auto &l : L) {
+    multidot(l.b, 0, 1, l.b, l.c->N, l.c->dscal.p, l.c->red, s);
+    FSI_HIP(hipMemcpyAsync(l.c->hpin, l.c->dscal.p, sizeof(double), hipMemcpyDeviceToHost, s));
   }
-  const double target = rtol * bnorm;
-  double *r = c.outer.r.p;
-  bool conv = false;
-  double rn = 0.0;
+  FSI_HIP(hipStreamSynchronize(s));
+  for (auto &l : L) {
+    l.bnorm = std::sqrt(l.c->hpin[0]);
+    if (!std::isfinite(l.bnorm)) {
+      l.fail(FSI_E_NONFINITE, "non-finite right-hand side");
+    } else if (l.bnorm == 0.0) {
+      fill(l.x, l.c->N, 0.0, s);
+      l.S.converged = 1;
+      l.state = GmLane::DONE;
+    }
+    l.target = rtol * l.bnorm;
+  }
+  std::vector<Ctx *> pcs;
+  std::vector<const double *> pr;
+  std::vector<double *> pz;
   while (true) {
-    residual64(c, b, x, r);
-    rn = std::sqrt(dev_dot<double>(c, r, r, N));
-    FSI_REQUIRE(std::isfinite(rn), FSI_E_NONFINITE, "non-finite residual");
-    if (rn <= target) { conv = true; break; }
-    if (S.its >= maxit) break;
-    // restart cycles toward the final target; with FP32_IR, refinement cycles that each
-    // ask the FP32 operator for a cycle_rtol reduction of the FP64 residual
-    const double cyc = o.cycle_rtol > 0 ? o.cycle_rtol : 1e-5;
-    double cyc_target = refine ? std::max(target, cyc * rn) : target;
-    CycleOut co = fgmres_cycle(c, m, o.pc, op_prec, pc_prec, r, rn, cyc_target, maxit - S.its, x);
-    if (trace_on())
-      std::fprintf(stderr, "[fsi] cycle prec=%d steps=%d rn/bn=%.3e est/bn=%.3e\n", prec, co.steps,
-                   rn / bnorm, co.est / bnorm);
-    S.its += co.steps;
-    S.restarts += 1;
-    if (refine) S.refinements += 1;
-    S.relres_est = co.est / bnorm;
+    // true residuals of the systems between cycles
+    bool any = false;
+    for (auto &l : L)
+      if (l.state == GmLane::RESID) {
+        Ctx &c = *l.c;
+        residual64(c, l.b, l.x, c.outer.r.p);
+        multidot(c.outer.r.p, 0, 1, c.outer.r.p, c.N, c.dscal.p, c.red, s);
+        FSI_HIP(hipMemcpyAsync(c.hpin, c.dscal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        any = true;
+      }
+    if (any) FSI_HIP(hipStreamSynchronize(s));
+    for (auto &l : L) {
+      if (l.state != GmLane::RESID) continue;
+      Ctx &c = *l.c;
+      l.rn = std::sqrt(c.hpin[0]);
+      if (!std::isfinite(l.rn)) { l.fail(FSI_E_NONFINITE, "non-finite residual"); continue; }
+      if (l.rn <= l.target) { l.S.converged = 1; l.state = GmLane::DONE; continue; }
+      if (l.S.its >= maxit) { l.fail(FSI_E_NOCONV, "GMRES reached maxit"); continue; }
+      // a cycle toward the final target; with FP32_IR, refinement cycles that each ask the
+      // FP32 operator for a cycle_rtol reduction of the FP64 residual
+      l.cyc_target = refine ? std::max(l.target, cyc * l.rn) : l.target;
+      l.maxsteps = maxit - l.S.its;
+      std::fill(l.H.begin(), l.H.end(), 0.0);
+      std::fill(l.g.begin(), l.g.end(), 0.0);
+      l.g[0] = l.rn;
+      l.j = 0;
+      l.est = l.rn;
+      lincomb(c.outer.V.p, c.outer.r.p, c.outer.r.p, 1.0 / l.rn, 0.0, c.N, s);
+      l.state = GmLane::CYCLE;
+    }
+    // one Arnoldi step of every system inside a cycle
+    pcs.clear();
+    pr.clear();
+    pz.clear();
+    for (auto &l : L)
+      if (l.state == GmLane::CYCLE) {
+        Ctx &c = *l.c;
+        pcs.push_back(&c);
+        pr.push_back(c.outer.V.p + (int64_t)l.j * c.N);
+        pz.push_back(c.outer.Z.p + (int64_t)l.j * c.N);
+      }
+    if (pcs.empty()) break;
+    apply_precond_lanes(c0, pcs.data(), (int)pcs.size(), o.pc, pc_prec, pr.data(), pz.data());
+    for (auto &l : L) {
+      if (l.state != GmLane::CYCLE) continue;
+      Ctx &c = *l.c;
+      const int64_t N = c.N;
+      const int j = l.j;
+      double *V = c.outer.V.p, *w = c.outer.w.p;
+      double *dh = c.dscal.p + 8;   // h1 (m+1), h2 (m+1), hn2
+      op_apply(c, op_prec, c.outer.Z.p + (int64_t)j * N, w);
+      multidot(V, N, j + 1, w, N, dh, c.red, s);
+      hipLaunchKernelGGL(k_multiaxpy_sub, dim3(vgrid(N)), dim3(256), 0, s, w, V, N, j + 1, dh, N);
+      multidot(V, N, j + 1, w, N, dh + (m + 1), c.red, s);
+      hipLaunchKernelGGL(k_multiaxpy_sub, dim3(vgrid(N)), dim3(256), 0, s, w, V, N, j + 1, dh + (m + 1), N);
+      multidot(w, 0, 1, w, N, dh + 2 * (m + 1), c.red, s);
+      FSI_CHECK_LAUNCH();
+      FSI_HIP(hipMemcpyAsync(c.hpin, dh, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    FSI_HIP(hipStreamSynchronize(s));
+    for (auto &l : L) {
+      if (l.state != GmLane::CYCLE) continue;
+      Ctx &c = *l.c;
+      const int64_t N = c.N;
+      const int j = l.j;
+      const double *hp = c.hpin;
+      double *hcol = &l.H[(size_t)j * (m + 1)];   // column j, rows 0..j+1
+      for (int i = 0; i <= j; ++i) hcol[i] = hp[i] + hp[(m + 1) + i];
+      const double hn = std::sqrt(hp[2 * (m + 1)] > 0 ? hp[2 * (m + 1)] : 0.0);
+      if (!std::isfinite(hn)) { l.fail(FSI_E_NONFINITE, "non-finite Arnoldi vector"); continue; }
+      hcol[j + 1] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double t = l.cs[i] * hcol[i] + l.sn[i] * hcol[i + 1];
+        hcol[i + 1] = -l.sn[i] * hcol[i] + l.cs[i] * hcol[i + 1];
+        hcol[i] = t;
+      }
+      const double den = std::hypot(hcol[j], hcol[j + 1]);
+      l.cs[j] = hcol[j] / den;
+      l.sn[j] = hcol[j + 1] / den;
+      hcol[j] = den;
+      hcol[j + 1] = 0.0;
+      l.g[j + 1] = -l.sn[j] * l.g[j];
+      l.g[j] = l.cs[j] * l.g[j];
+      l.est = std::fabs(l.g[j + 1]);
+      const int k = j + 1;
+      if (!(l.est <= l.cyc_target || hn == 0.0 || k >= l.maxsteps || k >= m)) {
+        lincomb(c.outer.V.p + (int64_t)k * N, c.outer.w.p, c.outer.w.p, 1.0 / hn, 0.0, N, s);
+        l.j = k;
+        continue;
+      }
+      // end of the cycle: back substitution H y = g, x += Z y
+      std::vector<double> y(k, 0.0);
+      for (int i = k - 1; i >= 0; --i) {
+        double t = l.g[i];
+        for (int q = i + 1; q < k; ++q) t -= l.H[(size_t)q * (m + 1) + i] * y[q];
+        y[i] = t / l.H[(size_t)i * (m + 1) + i];
+      }
+      // hpin holds y until the copy has run: it is rewritten only after a later synchronisation
+      for (int i = 0; i < k; ++i) c.hpin[i] = y[i];
+      double *dh = c.dscal.p + 8;
+      FSI_HIP(hipMemcpyAsync(dh, c.hpin, k * sizeof(double), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_multiaxpy_add, dim3(vgrid(N)), dim3(256), 0, s, l.x, c.outer.Z.p, N, k, dh, N);
+      FSI_CHECK_LAUNCH();
+      if (trace_on())
+        std::fprintf(stderr, "[fsi] cycle prec=%d steps=%d rn/bn=%.3e est/bn=%.3e\n", prec, k, l.rn / l.bnorm,
+                     l.est / l.bnorm);
+      l.S.its += k;
+      l.S.restarts += 1;
+      if (refine) l.S.refinements += 1;
+      l.S.relres_est = l.est / l.bnorm;
+      l.state = GmLane::RESID;
+    }
   }
-  S.converged = conv ? 1 : 0;
-  S.relres_true = rn / bnorm;
-  S.inner_its = c.inner_its_total;
+  FSI_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < K; ++k) {
+    GmLane &l = L[k];
+    if (l.bnorm > 0.0 && std::isfinite(l.bnorm)) l.S.relres_true = l.rn / l.bnorm;
+    l.S.inner_its = l.c->inner_its_total;
+    if (st) st[k] = l.S;
+    rc[k] = l.rc;
+    if (l.rc != FSI_OK) l.c->last_error = l.err;
+  }
+}
+
+void gmres_solve(Ctx &c, const fsi_solve_opts &o, const double *b, double *x, fsi_solve_stats *st) {
+  Ctx *cs[1] = {&c};
+  int rc = FSI_OK;
+  fsi_solve_stats S{};
+  gmres_solve_lanes(cs, 1, o, &b, &x, &S, &rc);
   if (st) *st = S;
-  FSI_REQUIRE(conv, FSI_E_NOCONV, "GMRES reached maxit");
+  if (rc != FSI_OK) throw Error(rc, c.last_error);
 }
 
 }  // namespace fsi

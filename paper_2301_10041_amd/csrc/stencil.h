@@ -78,9 +78,11 @@ struct DivTable {
   T b_coef[kBMax][2];
 };
 
+// Launchers run K independent systems (lane = blockIdx.y) over per-lane views (LP); the
+// vector views of one launch share one lane stride.  K = 1: one system.
 template <typename T, int MODE>
-void stencil_launch(int n, const StencilTable<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2,
-                    hipStream_t s);
+void stencil_launch(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<T> y, T c1,
+                    T c2, hipStream_t s, int K = 1);
 
 // Fluid rows of the operator on [u_x | u_y | p] in one tiled launch:
 //   y_u = A_f x_u - B^T x_p (+ C_f^T x_lam when cft_rp is given; lam_x at xl, lam_y at xl + Ns)
@@ -94,18 +96,18 @@ void stencil_fluid_rows(int n, const StencilTable<T> *tab, const DivTable<T> *dv
 // cheb2_pre : x = d = s D^{-1} b, then two steps (c1a, c2a), (c1b, c2b); writes x, d
 // cheb2_post: from x, a step with c1 = 0 (c2a) and a step (c1b, c2b); writes y, d
 template <typename T>
-void cheb2_pre(int n, const StencilTable<T> *tab, const T *b, T *d, T *x, T s, T c1a, T c2a, T c1b, T c2b,
-               hipStream_t st);
+void cheb2_pre(int n, const StencilTable<T> *tab, LP<const T> b, LP<T> d, LP<T> x, T s, T c1a, T c2a, T c1b,
+               T c2b, hipStream_t st, int K = 1);
 template <typename T>
-void cheb2_post(int n, const StencilTable<T> *tab, const T *x, const T *b, T *d, T *y, T c2a, T c1b, T c2b,
-                hipStream_t st);
+void cheb2_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<T> y, T c2a, T c1b,
+                T c2b, hipStream_t st, int K = 1);
 
 // The same launch inside the inner MINRES (FP64): v = s x, y = s (A11 x) + c r1 written over
 // r1, and one partial sum of v . y per tile in part[] (s, c read from device memory;
-// r1 read only when c != 0).  Returns the number of tiles (entries of part).
-int stencil_a11_minres(int n, const StencilTable<double> *tab, const DivTable<double> *dv, const double *x,
-                       double *v, double *r1y, const double *s_dev, const double *c_dev, double *part,
-                       hipStream_t s);
+// r1 read only when c != 0).  Returns the number of tiles (entries of part per lane).
+int stencil_a11_minres(int n, const StencilTable<double> *tab, const DivTable<double> *dv, LP<const double> x,
+                       LP<double> v, LP<double> r1y, LP<const double> s_dev, LP<const double> c_dev,
+                       LP<double> part, hipStream_t s, int K = 1);
 int stencil_tile_count(int n);
 
 // Host: the tables of A_f on an n x n grid from the element matrices (assemble.hip).

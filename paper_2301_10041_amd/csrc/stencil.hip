@@ -8,7 +8,9 @@
 //
 // Bytes per node in the Chebyshev step: x, b, d read, d and y written (5 two-component
 // vectors); no matrix and no indices.
+#include <initializer_list>
 #include <type_traits>
+#include <utility>
 
 #include "ctx.h"
 #include "kernels.h"
@@ -35,7 +37,30 @@ struct StencilArgs {
   const double *ms_s, *ms_c;
   T *ms_v, *ms_r1y;
   double *ms_part;
+  // lane strides (blockIdx.y = lane): vectors, MINRES scalars, per-tile parts.  The C_f^T
+  // term (cft_*, xlx, xly) is one system's and is not shifted.
+  int64_t lv, ls, lp;
 };
+
+// Views of lane blockIdx.y (null pointers stay null).
+template <typename P>
+__device__ __forceinline__ void lane_shift(P *&p, int64_t stride) {
+  if (p) p += (int64_t)blockIdx.y * stride;
+}
+template <typename T>
+__device__ __forceinline__ StencilArgs<T> lane_args(const StencilArgs<T> &a0) {
+  StencilArgs<T> a = a0;
+  lane_shift(a.x, a.lv);
+  lane_shift(a.b, a.lv);
+  lane_shift(a.d, a.lv);
+  lane_shift(a.y, a.lv);
+  lane_shift(a.ms_v, a.lv);
+  lane_shift(a.ms_r1y, a.lv);
+  lane_shift(a.ms_s, a.ls);
+  lane_shift(a.ms_c, a.ls);
+  lane_shift(a.ms_part, a.lp);
+  return a;
+}
 
 // Tiled kernel.  A block owns kTileR lattice rows x kTileC nodes.  Phase 1 stages x with a
 // halo of two nodes into LDS (stride-1, coalesced), storing 0 for boundary nodes and for
@@ -82,12 +107,13 @@ __device__ __forceinline__ void tile_bt_products(const DivTable<T> &dv, const T 
 constexpr int kXcd = 8;
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, int tiles, int band) {
+__global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a0, int tiles_x, int tiles, int band) {
   __shared__ T X[2][kTH * kTW];
   __shared__ T S[2][kTileR * kTileC];
   __shared__ T XP[MODE == SP_A11 ? kPH * kPW : 1];   // SP_A11: x_p tile (column 0 read as 0)
   const int t = (blockIdx.x % kXcd) * band + blockIdx.x / kXcd;
   if (t >= tiles) return;
+  const StencilArgs<T> a = lane_args(a0);
   const int n2 = 2 * a.n, L = n2 + 1;
   const int I0 = (t % tiles_x) * kTileC, J0 = (t / tiles_x) * kTileR;
   const int tid = threadIdx.x;
@@ -316,22 +342,36 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a, int tiles_x, 
 }
 
 template <typename T, int MODE>
-static void launch_tiles(int n, const StencilArgs<T> &a, hipStream_t s) {
+static void launch_tiles(int n, const StencilArgs<T> &a, hipStream_t s, int K) {
   const int L = 2 * n + 1;
   const int tx = (L + kTileC - 1) / kTileC, ty = (L + kTileR - 1) / kTileR;
   const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
-  hipLaunchKernelGGL((k_stencil<T, MODE>), dim3((unsigned)(band * kXcd)), dim3(256), 0, s, a, tx, tiles, band);
+  FSI_REQUIRE(K >= 1 && K <= 65535, FSI_E_ARG, "lane count out of range");
+  hipLaunchKernelGGL((k_stencil<T, MODE>), dim3((unsigned)(band * kXcd), (unsigned)K), dim3(256), 0, s, a, tx,
+                     tiles, band);
   FSI_CHECK_LAUNCH();
 }
 
+// One lane stride for the vectors of a launch (null views take any)
+static int64_t common_stride(std::initializer_list<std::pair<const void *, int64_t>> v, int K) {
+  int64_t s = -1;
+  for (const auto &e : v) {
+    if (!e.first) continue;
+    if (s < 0) s = e.second;
+    FSI_REQUIRE(K == 1 || e.second == s, FSI_E_ARG, "lane views of one launch need one stride");
+  }
+  return s < 0 ? 0 : s;
+}
+
 template <typename T, int MODE>
-void stencil_launch(int n, const StencilTable<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2,
-                    hipStream_t s) {
+void stencil_launch(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<T> y, T c1,
+                    T c2, hipStream_t s, int K) {
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
   static_assert(kTileR * kWave == 256 && 2 * kWave == kTileC, "one tile row per wave, two nodes per lane");
-  StencilArgs<T> a{n, tab, x, b, d, y, (2 * n + 1) * (2 * n + 1), c1, c2, nullptr, nullptr, nullptr,
-                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  launch_tiles<T, MODE>(n, a, s);
+  const int64_t lv = common_stride({{x.p, x.s}, {b.p, b.s}, {d.p, d.s}, {y.p, y.s}}, K);
+  StencilArgs<T> a{n, tab, x.p, b.p, d.p, y.p, (2 * n + 1) * (2 * n + 1), c1, c2, nullptr, nullptr, nullptr,
+                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, lv, 0, 0};
+  launch_tiles<T, MODE>(n, a, s, K);
 }
 
 template <typename T>
@@ -343,18 +383,20 @@ void stencil_fluid_rows(int n, const StencilTable<T> *tab, const DivTable<T> *dv
                 "a tile holds 2 x 64 P1 nodes, one per thread of the first two waves");
   const int L = 2 * n + 1, L2 = L * L;
   StencilArgs<T> a{n, tab, x, nullptr, nullptr, y, L2, T(0), T(0), dv, cft_rp, cft_col, cft_val, xl,
-                   xl ? xl + Ns : nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  launch_tiles<T, SP_A11>(n, a, s);
+                   xl ? xl + Ns : nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0};
+  launch_tiles<T, SP_A11>(n, a, s, 1);
 }
 
-int stencil_a11_minres(int n, const StencilTable<double> *tab, const DivTable<double> *dv, const double *x,
-                       double *v, double *r1y, const double *s_dev, const double *c_dev, double *part,
-                       hipStream_t s) {
+int stencil_a11_minres(int n, const StencilTable<double> *tab, const DivTable<double> *dv, LP<const double> x,
+                       LP<double> v, LP<double> r1y, LP<const double> s_dev, LP<const double> c_dev,
+                       LP<double> part, hipStream_t s, int K) {
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
   const int L = 2 * n + 1, L2 = L * L;
-  StencilArgs<double> a{n, tab, x, nullptr, nullptr, nullptr, L2, 0.0, 0.0, dv, nullptr, nullptr, nullptr, nullptr,
-                        nullptr, s_dev, c_dev, v, r1y, part};
-  launch_tiles<double, SP_A11>(n, a, s);
+  const int64_t lv = common_stride({{x.p, x.s}, {v.p, v.s}, {r1y.p, r1y.s}}, K);
+  const int64_t ls = common_stride({{s_dev.p, s_dev.s}, {c_dev.p, c_dev.s}}, K);
+  StencilArgs<double> a{n, tab, x.p, nullptr, nullptr, nullptr, L2, 0.0, 0.0, dv, nullptr, nullptr, nullptr, nullptr,
+                        nullptr, s_dev.p, c_dev.p, v.p, r1y.p, part.p, lv, ls, part.s};
+  launch_tiles<double, SP_A11>(n, a, s, K);
   const int tx = (L + kTileC - 1) / kTileC, ty = (L + kTileR - 1) / kTileR;
   return tx * ty;
 }
@@ -397,6 +439,7 @@ struct Cheb2Args {
   int L2;
   T s;                   // C2_PRE: scale of the first step
   T c1a, c2a, c1b, c2b;  // the two stencil steps
+  int64_t lv;            // lane stride of x, b, d, y (lane = blockIdx.y)
 };
 
 // The staged tiles are stored as two planes of even and odd lattice columns
@@ -442,7 +485,7 @@ enum { C2_PRE = 0, C2_POST = 1 };
 // i - 2), so the tile row's b and first-step direction stay in registers for the second
 // step.  All b loads are issued before x is staged.
 template <typename T, int M, int RR>
-__global__ void __launch_bounds__(64 * RR, 4) k_cheb2(Cheb2Args<T> a, int tiles_x, int tiles, int band) {
+__global__ void __launch_bounds__(64 * RR, 4) k_cheb2(Cheb2Args<T> a0, int tiles_x, int tiles, int band) {
   constexpr int NT = 64 * RR;                       // threads
   constexpr int kC2H0 = RR + 8, kC2H1 = RR + 4;     // rows of the staged x and the first step
   static_assert(RR >= 4 && RR % 2 == 0, "four halo rows go to the first four waves");
@@ -452,6 +495,11 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb2(Cheb2Args<T> a, int tiles_
   T *const X1 = X0;   // the first-step tile replaces x once every wave has read it
   const int t = (blockIdx.x % kXcd) * band + blockIdx.x / kXcd;
   if (t >= tiles) return;
+  Cheb2Args<T> a = a0;
+  lane_shift(a.x, a.lv);
+  lane_shift(a.b, a.lv);
+  lane_shift(a.d, a.lv);
+  lane_shift(a.y, a.lv);
   const int n2 = 2 * a.n, L = n2 + 1;
   const int64_t N = a.L2;
   const int I0 = (t % tiles_x) * kC2W, J0 = (t / tiles_x) * RR;
@@ -639,51 +687,53 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb2(Cheb2Args<T> a, int tiles_
 }
 
 template <typename T>
-void cheb2_pre(int n, const StencilTable<T> *tab, const T *b, T *d, T *x, T s, T c1a, T c2a, T c1b, T c2b,
-               hipStream_t st) {
+void cheb2_pre(int n, const StencilTable<T> *tab, LP<const T> b, LP<T> d, LP<T> x, T s, T c1a, T c2a, T c1b,
+               T c2b, hipStream_t st, int K) {
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
+  FSI_REQUIRE(K >= 1 && K <= 65535, FSI_E_ARG, "lane count out of range");
   const int L = 2 * n + 1;
   const int tx = (L + kC2W - 1) / kC2W, ty = (L + kC2R - 1) / kC2R;
   const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
-  Cheb2Args<T> a{n, tab, nullptr, b, d, x, L * L, s, c1a, c2a, c1b, c2b};
-  hipLaunchKernelGGL((k_cheb2<T, C2_PRE, kC2R>), dim3((unsigned)(band * kXcd)), dim3(64 * kC2R), 0, st, a, tx,
-                     tiles, band);
+  const int64_t lv = common_stride({{b.p, b.s}, {d.p, d.s}, {x.p, x.s}}, K);
+  Cheb2Args<T> a{n, tab, nullptr, b.p, d.p, x.p, L * L, s, c1a, c2a, c1b, c2b, lv};
+  hipLaunchKernelGGL((k_cheb2<T, C2_PRE, kC2R>), dim3((unsigned)(band * kXcd), (unsigned)K), dim3(64 * kC2R), 0,
+                     st, a, tx, tiles, band);
   FSI_CHECK_LAUNCH();
 }
 
 template <typename T>
-void cheb2_post(int n, const StencilTable<T> *tab, const T *x, const T *b, T *d, T *y, T c2a, T c1b, T c2b,
-                hipStream_t st) {
+void cheb2_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<T> y, T c2a, T c1b,
+                T c2b, hipStream_t st, int K) {
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
+  FSI_REQUIRE(K >= 1 && K <= 65535, FSI_E_ARG, "lane count out of range");
   const int L = 2 * n + 1;
   const int tx = (L + kC2W - 1) / kC2W, ty = (L + kC2R - 1) / kC2R;
   const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
-  Cheb2Args<T> a{n, tab, x, b, d, y, L * L, T(0), T(0), c2a, c1b, c2b};
-  hipLaunchKernelGGL((k_cheb2<T, C2_POST, kC2R>), dim3((unsigned)(band * kXcd)), dim3(64 * kC2R), 0, st, a, tx,
-                     tiles, band);
+  const int64_t lv = common_stride({{x.p, x.s}, {b.p, b.s}, {d.p, d.s}, {y.p, y.s}}, K);
+  Cheb2Args<T> a{n, tab, x.p, b.p, d.p, y.p, L * L, T(0), T(0), c2a, c1b, c2b, lv};
+  hipLaunchKernelGGL((k_cheb2<T, C2_POST, kC2R>), dim3((unsigned)(band * kXcd), (unsigned)K), dim3(64 * kC2R), 0,
+                     st, a, tx, tiles, band);
   FSI_CHECK_LAUNCH();
 }
 
-template void cheb2_pre<double>(int, const StencilTable<double> *, const double *, double *, double *, double,
-                                double, double, double, double, hipStream_t);
-template void cheb2_pre<float>(int, const StencilTable<float> *, const float *, float *, float *, float, float,
-                               float, float, float, hipStream_t);
-template void cheb2_post<double>(int, const StencilTable<double> *, const double *, const double *, double *,
-                                 double *, double, double, double, hipStream_t);
-template void cheb2_post<float>(int, const StencilTable<float> *, const float *, const float *, float *, float *,
-                                float, float, float, hipStream_t);
+#define FSI_CHEB2_INST(T)                                                                                   \
+  template void cheb2_pre<T>(int, const StencilTable<T> *, LP<const T>, LP<T>, LP<T>, T, T, T, T, T,         \
+                             hipStream_t, int);                                                             \
+  template void cheb2_post<T>(int, const StencilTable<T> *, LP<const T>, LP<const T>, LP<T>, LP<T>, T, T, T, \
+                              hipStream_t, int);
+FSI_CHEB2_INST(double)
+FSI_CHEB2_INST(float)
+#undef FSI_CHEB2_INST
 
-template void stencil_launch<double, SP_APPLY>(int, const StencilTable<double> *, const double *, const double *,
-                                               double *, double *, double, double, hipStream_t);
-template void stencil_launch<double, SP_RESID>(int, const StencilTable<double> *, const double *, const double *,
-                                               double *, double *, double, double, hipStream_t);
-template void stencil_launch<double, SP_CHEB>(int, const StencilTable<double> *, const double *, const double *,
-                                              double *, double *, double, double, hipStream_t);
-template void stencil_launch<float, SP_APPLY>(int, const StencilTable<float> *, const float *, const float *,
-                                              float *, float *, float, float, hipStream_t);
-template void stencil_launch<float, SP_RESID>(int, const StencilTable<float> *, const float *, const float *,
-                                              float *, float *, float, float, hipStream_t);
-template void stencil_launch<float, SP_CHEB>(int, const StencilTable<float> *, const float *, const float *,
-                                             float *, float *, float, float, hipStream_t);
+#define FSI_STENCIL_INST(T, M)                                                                              \
+  template void stencil_launch<T, M>(int, const StencilTable<T> *, LP<const T>, LP<const T>, LP<T>, LP<T>, T, T, \
+                                     hipStream_t, int);
+FSI_STENCIL_INST(double, SP_APPLY)
+FSI_STENCIL_INST(double, SP_RESID)
+FSI_STENCIL_INST(double, SP_CHEB)
+FSI_STENCIL_INST(float, SP_APPLY)
+FSI_STENCIL_INST(float, SP_RESID)
+FSI_STENCIL_INST(float, SP_CHEB)
+#undef FSI_STENCIL_INST
 
 }  // namespace fsi

@@ -20,6 +20,7 @@ FSI_OK, FSI_E_ARG, FSI_E_MESH, FSI_E_NOMEM, FSI_E_NOCONV, FSI_E_NONFINITE, FSI_E
 FP64, FP32, FP32_IR = 0, 1, 2
 PC_DIAG, PC_TRI = 0, 1
 SMOOTH_CSR, SMOOTH_STENCIL = 0, 1
+MAX_LANES = 32                 # FSI_MAX_LANES: systems per fsi_step_batch
 BLOCKS = dict(AF=0, MF=1, B=2, BT=3, AS=4, CS=5, CF=6, CFT=7, MP=8)
 
 
@@ -90,6 +91,9 @@ _SIGS = {
                                   C.POINTER(SolveStats)]),
     "fsi_step": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                            C.POINTER(SolveStats)]),
+    "fsi_step_batch": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(SolveOpts), C.POINTER(C.c_void_p),
+                                 C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(SolveStats),
+                                 C.POINTER(C.c_int32)]),
     "fsi_export_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                    C.POINTER(C.c_int64)]),
     "fsi_export_csr": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -177,6 +181,29 @@ class Opts:
     def c(self):
         return SolveOpts(self.restart, self.maxit, self.rtol, self.pc, self.prec, self.inner_rtol,
                          self.inner_maxit, self.cycle_rtol)
+
+
+def step_batch(ctxs, u_n, X_n, states, opts: Opts | None = None):
+    """K independent steps in lockstep (fsi_step_batch): system k is
+    ``ctxs[k].step(u_n[k], X_n[k], states[k], opts)``, bitwise, run on ctxs[0]'s stream with
+    the inner solves of all systems batched into the same launches.  Returns (stats, rcs):
+    per-system statistics dicts and statuses (FSI_OK, FSI_E_NOCONV or FSI_E_NONFINITE).
+    Raises FsiError when the batch as a whole fails."""
+    K = len(ctxs)
+    if K < 1 or K > MAX_LANES or not (len(u_n) == len(X_n) == len(states) == K):
+        raise ValueError(f"need 1..{MAX_LANES} contexts and as many vectors of each kind")
+    P = C.c_void_p * K
+    hs = P(*[c._h.value for c in ctxs])
+    us = P(*[_ptr(t).value for t in u_n])
+    xs = P(*[_ptr(t).value for t in X_n])
+    ss = P(*[_ptr(t).value for t in states])
+    st = (SolveStats * K)()
+    rcs = (C.c_int32 * K)()
+    o = (opts or Opts()).c()
+    rc = lib().fsi_step_batch(K, hs, C.byref(o), us, xs, ss, st, rcs)
+    if rc != FSI_OK and not any(r != FSI_OK for r in rcs):
+        raise FsiError(rc, lib().fsi_last_error(ctxs[0]._h).decode())
+    return [st[k].as_dict() for k in range(K)], [int(r) for r in rcs]
 
 
 class Context:

@@ -1,15 +1,19 @@
 """Request loop for independent FSI steps (continuous admission under an HBM budget).
 
-Each request is one semi-implicit step (fsi_step) on its own fluid grid and solid mesh.
-A slot is a resident libfsi context for one grid size n, with its own HIP stream; its
-fluid blocks and multigrid hierarchy stay on the device and the solid is swapped per
-request with fsi_set_solid (grow-only buffers, so a warm slot allocates nothing).
-Requests are admitted in arrival order as soon as a slot of their size is idle, or a new
-slot fits the HBM budget (idle slots of other sizes are evicted, least recently used
-first, to make room); requests that do not fit yet wait while later ones that fit go
-ahead.  Slots run concurrently (the ctypes calls release the GIL), so the work of
-different requests overlaps on the device.  Results are independent of the mix: every
-kernel is deterministic and slots share no device state.
+Each request is one semi-implicit step on its own fluid grid and solid mesh.  A slot holds
+resident libfsi contexts of one fluid grid (n, nu, rho, dt) on one HIP stream; their fluid
+blocks and multigrid hierarchies stay on the device and the solid is swapped per request
+with fsi_set_solid (grow-only buffers, so a warm slot allocates nothing).  Requests are
+admitted in arrival order as soon as a slot of their grid is idle, or a new slot fits the
+HBM budget (idle slots of other grids are evicted, least recently used first, to make
+room); requests that do not fit yet wait while later ones that fit go ahead.  A job takes
+the admitted request and up to lanes(n) - 1 more waiting requests of the same grid and runs
+them as one lockstep batch (fsi_step_batch: one launch sequence for all, the inner solves
+as lanes of the same kernels), so small systems cost about one step's launches per batch.
+Slots run concurrently (the ctypes calls release the GIL), so the work of different jobs
+overlaps on the device.  Results are independent of the mix and of the batching: every
+kernel is deterministic, a batched system's result is bitwise its result alone, and slots
+share no device state.
 """
 from __future__ import annotations
 
@@ -47,23 +51,52 @@ class Result:
 
 
 class Slot:
-    def __init__(self, sid, n, wl, stream):
+    """Resident contexts of one fluid grid on one stream (more are made as batches grow)."""
+
+    def __init__(self, sid, wl, stream, lanes=1):
         self.sid = sid
-        self.n = n
+        self.key = grid_key(wl)
+        self.n = wl.n
         self.stream = stream
-        xy, tri = wl.solid_mesh()
-        self.ctx = fsi.Context(n, xy, tri, nu=wl.nu, rho=wl.rho, dt=wl.dt, kappa=wl.kappa, stream=stream)
+        self.lanes = lanes
+        self.ctxs = [self._new_ctx(wl)]
         self.busy = False
         self.last_used = time.perf_counter()
-        self.bytes = self.ctx.sizes["device_bytes"]
+        self.bytes = self.ctxs[0].sizes["device_bytes"]
+        self.bytes_now = self.bytes
+
+    def _new_ctx(self, wl):
+        xy, tri = wl.solid_mesh()
+        return fsi.Context(wl.n, xy, tri, nu=wl.nu, rho=wl.rho, dt=wl.dt, kappa=wl.kappa, stream=self.stream)
+
+    @property
+    def ctx(self):
+        return self.ctxs[0]
+
+    def ensure(self, k, wl):
+        while len(self.ctxs) < k:
+            self.ctxs.append(self._new_ctx(wl))
+
+    def device_bytes(self):
+        return sum(c.refresh_sizes()["device_bytes"] for c in self.ctxs)
 
     def close(self):
-        self.ctx.close()
+        for c in self.ctxs:
+            c.close()
+
+
+def grid_key(wl):
+    return (wl.n, float(wl.nu), float(wl.rho), float(wl.dt))
+
+
+def default_lanes(n):
+    """Requests per lockstep batch by grid size (the small grids are launch-bound)."""
+    return 8 if n <= 64 else 4 if n <= 128 else 2
 
 
 class Server:
     def __init__(self, hbm_budget=None, max_slots=16, prec=fsi.FP32, pc=fsi.PC_TRI, rtol=1e-8,
-                 keep_states=False):
+                 keep_states=False, lanes=default_lanes):
         import torch
         self.torch = torch
         if hbm_budget is None:
@@ -73,6 +106,9 @@ class Server:
         self.max_slots = max_slots
         self.opts = fsi.Opts(restart=30, rtol=rtol, pc=pc, prec=prec)
         self.keep_states = keep_states
+        self.lanes = lanes if callable(lanes) else (lambda n, k=int(lanes): k)
+        self.batches = 0             # jobs run, and requests in them
+        self.batched = 0
         self.slots: list[Slot] = []
         self.cv = threading.Condition()
         self.reserved = 0            # bytes of live slots (estimates until measured)
@@ -97,7 +133,7 @@ class Server:
                 need = self._bytes_needed(wl)
                 if self.reserved + need > self.budget:
                     continue
-            slot = Slot(self._next_sid, wl.n, wl, torch.cuda.Stream())
+            slot = Slot(self._next_sid, wl, torch.cuda.Stream(), self.lanes(wl.n))
             self._next_sid += 1
             with self.cv:
                 self.slots.append(slot)
@@ -106,9 +142,9 @@ class Server:
     def _try_admit(self, req):
         """Called with the lock held: an idle slot of the request's size, a new slot, or
         None.  May evict idle slots of other sizes to make room."""
-        n = req.workload.n
+        key = grid_key(req.workload)
         for s in self.slots:
-            if not s.busy and s.n == n:
+            if not s.busy and s.key == key:
                 return s, False
         busy = sum(1 for s in self.slots if s.busy)
         if busy >= self.max_slots:
@@ -132,25 +168,37 @@ class Server:
         self.reserved += need
         return need, True
 
-    # -- one request on one slot -----------------------------------------------------
-    def _execute(self, slot, req, res, t0):
+    # -- one job (a lockstep batch of requests of one grid) on one slot ----------------
+    def _execute(self, slot, reqs, results, t0):
         torch = self.torch
-        wl = req.workload
-        xy, tri = wl.solid_mesh()
+        from . import inputs
+        slot.ensure(len(reqs), reqs[0].workload)
+        ctxs = slot.ctxs[:len(reqs)]
+        us, Xs, states = [], [], []
         with torch.cuda.stream(slot.stream):
-            slot.ctx.set_solid(xy, tri, kappa=wl.kappa)
-            N2 = slot.ctx.sizes["N2"]
-            N = slot.ctx.sizes["N"]
-            from . import inputs
-            u = torch.from_numpy(inputs.uniform(2 * N2, req.u_seed)).to("cuda", non_blocking=False)
-            X = torch.from_numpy(np.concatenate([xy[:, 0], xy[:, 1]])).to("cuda")
-            state = torch.zeros(N, dtype=torch.float64, device="cuda")
+            for ctx, req in zip(ctxs, reqs):
+                wl = req.workload
+                xy, tri = wl.solid_mesh()
+                ctx.set_solid(xy, tri, kappa=wl.kappa)
+                us.append(torch.from_numpy(inputs.uniform(2 * ctx.sizes["N2"], req.u_seed)).to("cuda"))
+                Xs.append(torch.from_numpy(np.concatenate([xy[:, 0], xy[:, 1]])).to("cuda"))
+                states.append(torch.zeros(ctx.sizes["N"], dtype=torch.float64, device="cuda"))
             slot.stream.synchronize()
-            res.stats = slot.ctx.step(u, X, state, self.opts)
-            host = state.cpu()
-        res.done = time.perf_counter() - t0
-        if self.keep_states:
-            res.state = host.numpy()
+            if len(reqs) == 1:
+                stats = [ctxs[0].step(us[0], Xs[0], states[0], self.opts)]
+            else:
+                stats, rcs = fsi.step_batch(ctxs, us, Xs, states, self.opts)
+                bad = [(r.rid, rc) for r, rc in zip(reqs, rcs) if rc != fsi.FSI_OK]
+                if bad:
+                    raise fsi.FsiError(bad[0][1], f"request {bad[0][0]} did not converge in its batch")
+            hosts = [st.cpu() for st in states]
+        done = time.perf_counter() - t0
+        for req, st, h in zip(reqs, stats, hosts):
+            res = results[req.rid]
+            res.stats = st
+            res.done = done
+            if self.keep_states:
+                res.state = h.numpy()
 
     def run(self, requests, realtime=True):
         """Serve the requests (sorted by arrival); returns the list of Results."""
@@ -201,6 +249,24 @@ class Server:
                         self.cv.wait(timeout=wait if wait > 0 else 0.001)
                     i, r, got, new = pick
                     pending.pop(i)
+                    # more waiting requests of the same grid join the job (arrival order), as
+                    # far as the slot's contexts or new ones that fit the budget allow
+                    key, cap = grid_key(r.workload), self.lanes(r.workload.n)
+                    have = 1 if new else len(got.ctxs)
+                    members, extra = [r], 0
+                    j = 0
+                    while len(members) < cap and j < len(pending):
+                        q = pending[j]
+                        if grid_key(q.workload) != key:
+                            j += 1
+                            continue
+                        if len(members) >= have:
+                            need_q = self._bytes_needed(q.workload)
+                            if self.reserved + extra + need_q > self.budget:
+                                break
+                            extra += need_q
+                        members.append(pending.pop(j))
+                    self.reserved += extra
                     if new:
                         sid = self._next_sid
                         self._next_sid += 1
@@ -208,26 +274,32 @@ class Server:
                     else:
                         slot = got
                         slot.busy = True
-                    state["inflight"] += 1
+                    state["inflight"] += len(members)
                     self.max_inflight = max(self.max_inflight, state["inflight"])
-                res = results[r.rid]
-                res.start = now()
+                    self.batches += 1
+                    self.batched += len(members)
+                t_start = now()
+                for q in members:
+                    results[q.rid].start = t_start
                 try:
                     if slot is None:
                         stream = torch.cuda.Stream()
-                        slot = Slot(sid, r.workload.n, r.workload, stream)
+                        slot = Slot(sid, r.workload, stream, self.lanes(r.workload.n))
                         # keep the estimate until the slot's Krylov space exists
                         slot.bytes = max(slot.bytes, got)
                         with self.cv:
                             self.reserved += slot.bytes - got
                             slot.busy = True
                             self.slots.append(slot)
-                    res.slot = slot.sid
-                    self._execute(slot, r, res, t0)
-                    slot.bytes_now = slot.ctx.refresh_sizes()["device_bytes"]
+                    with self.cv:
+                        slot.bytes += extra      # contexts the batch adds (reserved above)
+                    for q in members:
+                        results[q.rid].slot = slot.sid
+                    self._execute(slot, members, results, t0)
+                    slot.bytes_now = slot.device_bytes()
                 except Exception:
                     with self.cv:
-                        state["inflight"] -= 1
+                        state["inflight"] -= len(members)
                     raise
                 with self.cv:
                     if slot.bytes_now > slot.bytes:
@@ -235,8 +307,8 @@ class Server:
                         slot.bytes = slot.bytes_now
                     slot.busy = False
                     slot.last_used = time.perf_counter()
-                    state["inflight"] -= 1
-                    state["done"] += 1
+                    state["inflight"] -= len(members)
+                    state["done"] += len(members)
                     self.cv.notify_all()
 
         threads = [threading.Thread(target=worker, daemon=True) for _ in range(self.max_slots)]

@@ -1,0 +1,122 @@
+"""Lockstep batches of small steps (fsi_step_batch, the batched serving form): every
+system's result must equal its step alone bitwise (each system runs the same kernels; the
+inner A11 solves of all systems are lanes of one launch), across lane counts that grow
+and shrink on one leading context, with and without captured graphs, in FP64 and mixed
+precision; one batch is checked against the FP64 oracle, and batches that mix fluid
+grids or repeat a context are refused."""
+import numpy as np
+import pytest
+
+from oracle import step as ostep
+from oracle import system
+from paper_2301_10041_amd import fsi, inputs
+
+from gpu_helpers import rel, soa, to_dev, to_host, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def workloads(n, count, seed=11):
+    rng = np.random.default_rng(seed + n)
+    out = []
+    for i in range(count):
+        cx, cy = rng.uniform(0.35, 0.65, 2)
+        r = float(rng.uniform(0.08, 0.2))
+        m = int(rng.integers(3, 9))
+        axes = (r, r * float(rng.uniform(0.6, 1.0))) if rng.random() < 0.5 else None
+        out.append(inputs.Workload(f"b{n}_{i}", n, [inputs.Solid(m, (float(cx), float(cy)), r, axes)], dt=0.01,
+                                   seed=3000 + 17 * i + n))
+    return out
+
+
+def inputs_of(wl, ctx):
+    torch = torch_dev()
+    xy, _ = wl.solid_mesh()
+    u = to_dev(inputs.uniform(2 * ctx.sizes["N2"], wl.seed))
+    X = to_dev(soa(xy))
+    state = torch.zeros(ctx.sizes["N"], dtype=torch.float64, device="cuda")
+    return u, X, state
+
+
+def alone(wl, opts, graphs):
+    ctx = fsi.Context.from_workload(wl)
+    ctx.set_graphs(graphs)
+    u, X, state = inputs_of(wl, ctx)
+    st = ctx.step(u, X, state, opts)
+    out = to_host(state)
+    ctx.close()
+    return out, st
+
+
+def batch(ctxs, wls, opts):
+    ins = [inputs_of(wl, c) for wl, c in zip(wls, ctxs)]
+    stats, rcs = fsi.step_batch(ctxs, [i[0] for i in ins], [i[1] for i in ins], [i[2] for i in ins], opts)
+    return [to_host(i[2]) for i in ins], stats, rcs
+
+
+CASES = [
+    ("n16_fp64_graphs", 16, fsi.FP64, True, [4, 2, 5]),
+    ("n32_mixed_graphs", 32, fsi.FP32, True, [3, 1]),
+    ("n16_fp64_eager", 16, fsi.FP64, False, [3]),
+]
+
+
+@pytest.mark.parametrize("name,n,prec,graphs,ks", CASES, ids=[c[0] for c in CASES])
+def test_batch_equals_alone_bitwise(name, n, prec, graphs, ks):
+    torch_dev()
+    print(f"[batch {name} K={ks}]", flush=True)
+    opts = fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-8)
+    wls = workloads(n, max(ks))
+    ref = [alone(wl, opts, graphs) for wl in wls]
+    ctxs = [fsi.Context.from_workload(wl) for wl in wls]
+    for c in ctxs:
+        c.set_graphs(graphs)
+    for K in ks:   # lane counts grow and shrink on the same leading context
+        states, stats, rcs = batch(ctxs[:K], wls[:K], opts)
+        assert rcs == [fsi.FSI_OK] * K
+        for k in range(K):
+            a, sa = ref[k]
+            assert np.array_equal(states[k], a), (K, k)
+            assert stats[k]["its"] == sa["its"] and stats[k]["inner_its"] == sa["inner_its"], (K, k)
+            assert stats[k]["converged"] == 1
+        print(f"  K={K} its={[s['its'] for s in stats]} inner={[s['inner_its'] for s in stats]}", flush=True)
+    for c in ctxs:
+        c.close()
+
+
+def test_batch_matches_oracle():
+    torch_dev()
+    print("[batch oracle]", flush=True)
+    wls = workloads(16, 3, seed=5)
+    ctxs = [fsi.Context.from_workload(wl) for wl in wls]
+    states, stats, rcs = batch(ctxs, wls, fsi.Opts(prec=fsi.FP64, rtol=1e-10))
+    assert rcs == [fsi.FSI_OK] * 3
+    for wl, x in zip(wls, states):
+        S = system.FSISystem.from_workload(wl)
+        u = inputs.uniform(2 * S.lay.N2, wl.seed)
+        x_ref, _ = ostep.step(S, u, S.xy_ref, solver="direct")
+        assert rel(x, x_ref) <= 1e-7, wl.name
+    for c in ctxs:
+        c.close()
+
+
+def test_batch_refuses_mixed_grids_and_repeats():
+    torch_dev()
+    print("[batch refusals]", flush=True)
+    wa = workloads(16, 1)[0]
+    wb = workloads(32, 1)[0]
+    ca, cb = fsi.Context.from_workload(wa), fsi.Context.from_workload(wb)
+    ia, ib = inputs_of(wa, ca), inputs_of(wb, cb)
+    with pytest.raises(fsi.FsiError) as e:
+        fsi.step_batch([ca, cb], [ia[0], ib[0]], [ia[1], ib[1]], [ia[2], ib[2]])
+    assert e.value.code == fsi.FSI_E_ARG
+    with pytest.raises(fsi.FsiError) as e:
+        fsi.step_batch([ca, ca], [ia[0], ia[0]], [ia[1], ia[1]], [ia[2], ia[2]])
+    assert e.value.code == fsi.FSI_E_ARG
+    with pytest.raises(ValueError):
+        fsi.step_batch([], [], [], [])
+    # the contexts still work after a refused batch
+    st = ca.step(ia[0], ia[1], ia[2])
+    assert st["converged"] == 1
+    ca.close()
+    cb.close()
