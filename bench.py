@@ -90,7 +90,7 @@ def run_cpu_baseline(workload: str):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def run_serving(count: int, slots: int) -> dict:
+def run_serving(count: int, slots: int, per_grid: int = 2) -> dict:
     """Request loop: `count` independent mixed-precision steps arriving by a Poisson
     process at 200 req/s (grid 32..256, disk or ellipse, 216 to 12,150 triangles; request
     i draws u^n from seed 1000 + i); HBM budget = free memory - 8 GB."""
@@ -98,17 +98,18 @@ def run_serving(count: int, slots: int) -> dict:
 
     trace = inputs.request_trace(count, 200.0, seed=4)
     reqs = serve.requests_from_trace(trace)
-    srv = serve.Server(max_slots=slots, prec=fsi.FP32, pc=fsi.PC_TRI, rtol=1e-8)
-    # resident slots sized for the largest solid of the trace, two per grid size
+    srv = serve.Server(max_slots=slots, prec=fsi.FP32, pc=fsi.PC_TRI, rtol=1e-8, slots_per_grid=per_grid)
+    # resident slots sized for the largest solid of the trace, per_grid per grid size, each
+    # with a context for every lane of its batches
     warm = [inputs.Workload(f"warm{n}", n, [inputs.Solid(45, (0.5, 0.5), 0.2)], dt=0.01)
-            for n in (32, 64, 128, 256) for _ in range(2)]
+            for n in (32, 64, 128, 256) for _ in range(per_grid)]
     srv.prewarm(warm)
     t0 = time.perf_counter()
     res = srv.run(reqs)
     wall = time.perf_counter() - t0
     summ = serve.summarize(res)
     out = {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in summ.items()}
-    out.update(slots=slots, max_inflight=srv.max_inflight, evictions=srv.evictions,
+    out.update(slots=slots, slots_per_grid=per_grid, max_inflight=srv.max_inflight, evictions=srv.evictions,
                jobs=srv.batches, requests_per_job=round(srv.batched / max(srv.batches, 1), 2),
                lanes={n: srv.lanes(n) for n in (32, 64, 128, 256)},
                budget_gb=round(srv.budget / 2**30, 1), wall_s=round(wall, 3),

@@ -13,7 +13,7 @@
 //   5. per candidate cell: clip again, write (E, T) and the 3x6 local matrix of each piece
 //   6. per solid node (one wavefront): rows of C_f with a window bitmap in LDS (columns in
 //      ascending order), values summed in a fixed order
-//   7. C_f^T: counting transpose with a per-row sort (deterministic)
+//   7. C_f^T: counting transpose, then each entry moved to its rank in its row (deterministic)
 //
 // Clipping arithmetic (must be reproduced bit for bit wherever the intersection list is
 // compared): clip against x >= x_i, x <= x_{i+1}, y >= y_j, y <= y_{j+1}, then against
@@ -398,17 +398,71 @@ __global__ void k_scatter_t(int64_t nrows, const int *rowptr, const int *col, co
   }
 }
 
-__global__ void k_sort_rows(int64_t nrows, const int *rowptr, int *col, double *val) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Ordering of the transposed rows.  The scatter above places the entries of a row of
+// C_f^T in an arbitrary order (atomic slots); each entry is then moved to its rank among the
+// solid-node indices of its row (unique within a row), so the result is deterministic.
+// Rows of up to kShortRow entries are ranked by one thread; longer rows (a solid much finer
+// than the fluid grid puts thousands of solid nodes in one P2 support) are listed and ranked
+// by a workgroup each, with the row's keys staged through LDS in chunks.
+constexpr int kShortRow = 32;
+constexpr int kRankChunk = 4096;
+
+__global__ void k_rank_short(int64_t nrows, const int *rowptr, const int *tcol, const double *tval, int *col,
+                             double *val, int *long_rows) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
-  int k0 = rowptr[r], k1 = rowptr[r + 1];
-  for (int k = k0 + 1; k < k1; ++k) {
-    int c = col[k];
-    double v = val[k];
-    int p = k;
-    while (p > k0 && col[p - 1] > c) { col[p] = col[p - 1]; val[p] = val[p - 1]; --p; }
-    col[p] = c;
-    val[p] = v;
+  const int k0 = rowptr[r], k1 = rowptr[r + 1];
+  if (k1 - k0 > kShortRow) {
+    long_rows[1 + atomicAdd(&long_rows[0], 1)] = (int)r;   // list order does not matter
+    return;
+  }
+  for (int i = k0; i < k1; ++i) {
+    const int c = tcol[i];
+    int rank = 0;
+    for (int j = k0; j < k1; ++j) rank += tcol[j] < c;
+    col[k0 + rank] = c;
+    val[k0 + rank] = tval[i];
+  }
+}
+
+// One workgroup per listed row (grid-stride over the list; the count is read on the device).
+__global__ void __launch_bounds__(256) k_rank_long(const int *rowptr, const int *tcol, const double *tval, int *col,
+                                                   double *val, const int *long_rows) {
+  __shared__ int keys[kRankChunk];
+  const int count = long_rows[0];
+  for (int q = blockIdx.x; q < count; q += gridDim.x) {
+    const int r = long_rows[1 + q];
+    const int k0 = rowptr[r], k1 = rowptr[r + 1], len = k1 - k0;
+    // this thread's elements: i = k0 + threadIdx.x + 256 t (at most kRankMine per pass)
+    for (int base = 0; base < len; base += 256 * 8) {
+      int mine[8], rank[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int i = base + threadIdx.x + 256 * t;
+        mine[t] = i < len ? tcol[k0 + i] : 0;
+        rank[t] = 0;
+      }
+      for (int c0 = 0; c0 < len; c0 += kRankChunk) {
+        const int cl = min(kRankChunk, len - c0);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cl; j += 256) keys[j] = tcol[k0 + c0 + j];
+        __syncthreads();
+        for (int j = 0; j < cl; ++j) {
+          const int kj = keys[j];   // same address for the whole workgroup: broadcast
+#pragma unroll
+          for (int t = 0; t < 8; ++t) rank[t] += kj < mine[t];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int i = base + threadIdx.x + 256 * t;
+        if (i < len) {
+          col[k0 + rank[t]] = mine[t];
+          val[k0 + rank[t]] = tval[k0 + i];
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -430,7 +484,7 @@ void assemble_coupling(Ctx &c, const double *Xn, bool) {
   hipStream_t s = c.stream;
   const int64_t nt = c.Nt, ns = c.Ns;
   const int n = c.n;
-  DevBuf<int> tmp;
+  DevBuf<int> &tmp = c.scan_tmp;   // grow-only: a per-call buffer would free (and synchronise) every step
   if (!c.dflag.p) {
     c.dflag.alloc(4);
     fill(c.dflag.p, 4, 0, s);
@@ -496,10 +550,16 @@ void assemble_coupling(Ctx &c, const double *Xn, bool) {
   scan_excl(Ct.rowptr.p, Ct.rowptr.p, c.N2, tmp, s);
   Ct.col.reserve(nnz);
   Ct.val.reserve(nnz);
+  c.cft_tcol.reserve(nnz);
+  c.cft_tval.reserve(nnz);
+  c.cft_long.reserve(c.N2 + 1);
+  fill(c.cft_long.p, 1, 0, s);
   hipLaunchKernelGGL(k_scatter_t, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, Cf.rowptr.p, Cf.col.p,
-                     Cf.val.p, Ct.rowptr.p, c.cft_fill.p, Ct.col.p, Ct.val.p);
-  hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(c.N2, 256)), dim3(256), 0, s, c.N2, Ct.rowptr.p,
-                     Ct.col.p, Ct.val.p);
+                     Cf.val.p, Ct.rowptr.p, c.cft_fill.p, c.cft_tcol.p, c.cft_tval.p);
+  hipLaunchKernelGGL(k_rank_short, dim3(grid_for(c.N2, 256)), dim3(256), 0, s, c.N2, Ct.rowptr.p, c.cft_tcol.p,
+                     c.cft_tval.p, Ct.col.p, Ct.val.p, c.cft_long.p);
+  hipLaunchKernelGGL(k_rank_long, dim3(512), dim3(256), 0, s, Ct.rowptr.p, c.cft_tcol.p, c.cft_tval.p, Ct.col.p,
+                     Ct.val.p, c.cft_long.p);
   FSI_CHECK_LAUNCH();
   Cf.val32.reserve(nnz);
   Ct.val32.reserve(nnz);

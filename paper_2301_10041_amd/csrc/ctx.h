@@ -104,7 +104,11 @@ struct Ctx {
   DevBuf<int> pair_E, pair_T;
   DevBuf<double> piece_L;  // 18 per piece: (|E|/|X(E)|) int lam_l phi_j
   DevBuf<int> e_piece;     // Nt + 1: first piece of each element
-  DevBuf<int> cf_cnt, cft_cnt, cft_fill;
+  DevBuf<int> cft_fill;     // C_f^T: per-row fill counters of the scatter
+  DevBuf<int> cft_tcol;     // scattered (unordered) C_f^T rows before ranking
+  DevBuf<double> cft_tval;
+  DevBuf<int> cft_long;     // [count, rows...]: rows ranked by a workgroup each
+  DevBuf<int> scan_tmp;     // scan partials (grow-only)
   DevBuf<int> dflag;       // device error flags (mesh / capacity)
 
   // multigrid hierarchies of the preconditioner
