@@ -130,35 +130,103 @@ __device__ __forceinline__ bool on_p2_boundary(int I, int J, int n) {
 }
 
 // y += P xc: coarse quadratic evaluated at the fine node; Dirichlet nodes (fine rows and
-// coarse columns) take no part.
+// coarse columns) take no part.  An interior fine node (I, J) lies in coarse cell
+// (I >> 2, J >> 2) at the local position (I mod 4, J mod 4): one of 16 classes, each a fixed
+// set of at most six coarse nodes and weights (prolong_classes).  A wave takes the nodes of
+// one residue of I mod 4 in a fine row (lanes 4 apart), so its class is uniform and the
+// offsets and weights are compile-time constants.
+struct ProlongClass {
+  int cnt;
+  int d[6][2];    // coarse lattice offsets from (2 ci, 2 cj)
+  double w[6];    // basis values (exact binary fractions)
+};
+struct ProlongClasses {
+  ProlongClass c[16];   // index 4 (J mod 4) + (I mod 4)
+};
+__host__ __device__ constexpr ProlongClasses prolong_classes() {
+  ProlongClasses t{};
+  const int vx[2][3] = {{0, 2, 2}, {0, 2, 0}};
+  const int vy[2][3] = {{0, 0, 2}, {0, 2, 2}};
+  for (int B = 0; B < 4; ++B)
+    for (int A = 0; A < 4; ++A) {
+      ProlongClass &p = t.c[4 * B + A];
+      const double xi = 0.25 * A, eta = 0.25 * B;
+      const int tr = xi >= eta ? 0 : 1;
+      const double l0 = tr == 0 ? 1.0 - xi : 1.0 - eta, l1 = tr == 0 ? xi - eta : xi,
+                   l2 = tr == 0 ? eta : eta - xi;
+      const double phi[6] = {l0 * (2 * l0 - 1), l1 * (2 * l1 - 1), l2 * (2 * l2 - 1),
+                             4 * l0 * l1,       4 * l1 * l2,       4 * l2 * l0};
+      p.cnt = 0;
+      for (int b = 0; b < 6; ++b) {
+        if (phi[b] == 0.0) continue;
+        int dI = 0, dJ = 0;
+        if (b < 3) {
+          dI = vx[tr][b];
+          dJ = vy[tr][b];
+        } else {
+          const int e = b - 3, f = (e + 1) % 3;
+          dI = (vx[tr][e] + vx[tr][f]) / 2;
+          dJ = (vy[tr][e] + vy[tr][f]) / 2;
+        }
+        p.d[p.cnt][0] = dI;
+        p.d[p.cnt][1] = dJ;
+        p.w[p.cnt] = phi[b];
+        ++p.cnt;
+      }
+    }
+  return t;
+}
+
+template <typename T, int CLS>
+__device__ __forceinline__ void prolong_node(int ci, int cj, int nc, int Lc, int64_t Nc, const T *__restrict__ xc,
+                                             T &s0, T &s1) {
+  constexpr ProlongClasses pcs = prolong_classes();
+  constexpr ProlongClass p = pcs.c[CLS];
+  s0 = 0;
+  s1 = 0;
+#pragma unroll
+  for (int q = 0; q < p.cnt; ++q) {
+    const int Ic = 2 * ci + p.d[q][0], Jc = 2 * cj + p.d[q][1];
+    if (Ic == 0 || Jc == 0 || Ic == 2 * nc || Jc == 2 * nc) continue;
+    const int64_t k = (int64_t)Jc * Lc + Ic;
+    s0 += (T)p.w[q] * xc[k];
+    s1 += (T)p.w[q] * xc[Nc + k];
+  }
+}
+
+// Block = one fine row segment of 256 nodes; wave w takes I = base + 4 lane + w.
 template <typename T>
-__global__ void __launch_bounds__(256) k_p2_prolong_add(int nf, LP<const T> xcl, LP<T> yl) {
+__global__ void __launch_bounds__(256) k_p2_prolong_add(int nf, LP<const T> xcl, LP<T> yl, int segs) {
   const T *__restrict__ xc = xcl.at(blockIdx.y);
   T *y = yl.at(blockIdx.y);
   const int L = 2 * nf + 1, nc = nf / 2, Lc = 2 * nc + 1;
   const int64_t Nf = (int64_t)L * L, Nc = (int64_t)Lc * Lc;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= Nf) return;
-  const int I = (int)(r % L), J = (int)(r / L);
-  if (on_p2_boundary(I, J, nf)) return;
-  int Ic[6], Jc[6];
-  double w[6];
-  const int m = p2_prolong_weights(I, J, nf, Ic, Jc, w);
-  T s0 = 0, s1 = 0;
-  for (int q = 0; q < m; ++q) {
-    if (on_p2_boundary(Ic[q], Jc[q], nc)) continue;
-    const int64_t k = (int64_t)Jc[q] * Lc + Ic[q];
-    s0 += (T)w[q] * xc[k];
-    s1 += (T)w[q] * xc[Nc + k];
+  const int J = blockIdx.x / segs, seg = blockIdx.x % segs;
+  const int A = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
+  const int I = seg * 256 + 4 * ((int)threadIdx.x % kWave) + A;
+  if (I >= L || I == 0 || J == 0 || I == 2 * nf || J == 2 * nf) return;
+  const int ci = I >> 2, cj = J >> 2;
+  T s0, s1;
+  switch (4 * (J & 3) + A) {
+#define FSI_PROLONG_CASE(c) \
+  case c: prolong_node<T, c>(ci, cj, nc, Lc, Nc, xc, s0, s1); break;
+    FSI_PROLONG_CASE(0) FSI_PROLONG_CASE(1) FSI_PROLONG_CASE(2) FSI_PROLONG_CASE(3)
+    FSI_PROLONG_CASE(4) FSI_PROLONG_CASE(5) FSI_PROLONG_CASE(6) FSI_PROLONG_CASE(7)
+    FSI_PROLONG_CASE(8) FSI_PROLONG_CASE(9) FSI_PROLONG_CASE(10) FSI_PROLONG_CASE(11)
+    FSI_PROLONG_CASE(12) FSI_PROLONG_CASE(13) FSI_PROLONG_CASE(14) FSI_PROLONG_CASE(15)
+#undef FSI_PROLONG_CASE
+    default: s0 = s1 = 0;
   }
+  const int64_t r = (int64_t)J * L + I;
   y[r] += s0;
   y[Nf + r] += s1;
 }
 
 template <typename T>
 void p2_prolong_add(int nf, LP<const T> xc, LP<T> y, hipStream_t s, int K) {
-  const int64_t nodes = (int64_t)(2 * nf + 1) * (2 * nf + 1);
-  hipLaunchKernelGGL(k_p2_prolong_add<T>, dim3(grid_for(nodes, 256), K), dim3(256), 0, s, nf, xc, y);
+  const int L = 2 * nf + 1;
+  const int segs = (L + 255) / 256;
+  hipLaunchKernelGGL(k_p2_prolong_add<T>, dim3((unsigned)(L * segs), K), dim3(256), 0, s, nf, xc, y, segs);
   FSI_CHECK_LAUNCH();
 }
 
@@ -249,6 +317,18 @@ void p2_restrict_tables(P2RestrTable<double> &t64, P2RestrTable<float> &t32) {
     for (int k = 0; k < cnt; ++k)
       FSI_REQUIRE(t64.off[cls][k][0] == ro.d[cls][k][0] && t64.off[cls][k][1] == ro.d[cls][k][1], FSI_E_ARG,
                   "restriction offsets differ from the compiled pattern");
+  }
+  // the compiled prolongation classes against the interpolation they stand for
+  constexpr ProlongClasses pcs = prolong_classes();
+  for (int c = 0; c < 16; ++c) {
+    const int ci = 3, cj = 3, I = 4 * ci + (c & 3), J = 4 * cj + (c >> 2);
+    int ic[6], jc[6];
+    double w[6];
+    const int m = p2_prolong_weights(I, J, nf, ic, jc, w);
+    FSI_REQUIRE(m == pcs.c[c].cnt, FSI_E_ARG, "prolongation class width differs from the interpolation");
+    for (int q = 0; q < m; ++q)
+      FSI_REQUIRE(ic[q] == 2 * ci + pcs.c[c].d[q][0] && jc[q] == 2 * cj + pcs.c[c].d[q][1] && w[q] == pcs.c[c].w[q],
+                  FSI_E_ARG, "prolongation class differs from the interpolation");
   }
 }
 

@@ -223,10 +223,12 @@ static T *chebyshev_mf(First first, Step step, double lmin, double lmax, int ste
 // temporally blocked launch, further steps one launch each (same recurrence as
 // chebyshev_mf; the profile brackets the two-step post-smoothing launches, the largest
 // single kernel of a step).
+// out (optional, not zero_init): the last launch writes the result there instead of into a
+// ping-pong buffer (returned); used to write a V-cycle's result into the caller's vector.
 template <typename T>
 static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, double lmax, int steps,
                             const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s, Prof *prof,
-                            int K = 1, int64_t ls = 0) {
+                            int K = 1, int64_t ls = 0, T *out = nullptr) {
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
@@ -248,24 +250,30 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
   } else if (!zero_init && steps >= 2) {
     T c1b, c2b;
     next(c1b, c2b);
+    T *dst = (out && steps == 2) ? out : x2;
     if (prof) prof->begin(s);
-    cheb2_post<T>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(x2, ls), (T)(1.0 / theta), c1b, c2b, s, K);
+    cheb2_post<T>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(dst, ls), (T)(1.0 / theta), c1b, c2b, s, K);
     if (prof) prof->end(s);
-    std::swap(x, x2);
+    x2 = x;
+    x = dst;
     done = 2;
   } else if (zero_init) {
     p2_first<T>(n, tab, lb, (T)(1.0 / theta), ld, LP<T>(x, ls), s, K);
     done = 1;
   } else {
-    stencil_launch<T, SP_CHEB>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(x2, ls), (T)0, (T)(1.0 / theta), s, K);
-    std::swap(x, x2);
+    T *dst = (out && steps == 1) ? out : x2;
+    stencil_launch<T, SP_CHEB>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(dst, ls), (T)0, (T)(1.0 / theta), s, K);
+    x2 = x;
+    x = dst;
     done = 1;
   }
   for (int k = done; k < steps; ++k) {
     T c1, c2;
     next(c1, c2);
-    stencil_launch<T, SP_CHEB>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(x2, ls), c1, c2, s, K);
-    std::swap(x, x2);
+    T *dst = (out && k == steps - 1) ? out : x2;
+    stencil_launch<T, SP_CHEB>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(dst, ls), c1, c2, s, K);
+    x2 = x;
+    x = dst;
   }
   return x;
 }
@@ -300,8 +308,10 @@ template <typename T> static const P2RestrTable<T> *rtab(const Mg &mg) {
 // ---------------------------------------------------------------- V-cycle
 // One V-cycle at level l for right-hand side b (comps * nodes entries, component-major).
 // Returns the level work vector that holds the result.
+// out (optional): where the matrix-free velocity cycle writes its result (the returned
+// pointer); otherwise a level work vector.
 template <typename T, int W, int NC>
-static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr, int K = 1) {
+static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr, int K = 1, T *out = nullptr) {
   MgLevel &L = mg.lv[l];
   T *x = Pr<T>::w(L, 0), *x2 = Pr<T>::w(L, 4), *r = Pr<T>::w(L, 2), *d = Pr<T>::w(L, 3);
   // K systems (matrix-free hierarchy only): lane k of every level vector at + k comps nodes
@@ -324,7 +334,8 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
   if (mg.stencil) {   // matrix-free smoothing, residual and transfers
     auto smooth = [&](T *x0, T *x1, bool zero) -> T * {
       if constexpr (W == 4)
-        return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, pl, K, ls);
+        return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, pl, K, ls,
+                                    zero ? nullptr : out);
       else
         return chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, K, ls);
     };
@@ -384,15 +395,15 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1) {
     FSI_HIP(hipEventRecord(c.ev_fork, s));
     FSI_HIP(hipStreamWaitEvent(sp, c.ev_fork, 0));
   }
-  T *xu;
-  if (K == 1) {
-    xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr);
+  if (K == 1) {   // the cycle reads r and writes z in place (one system: no lane stride)
+    T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr, 1, z);
+    if (xu != z) convert(z, xu, 2 * N2, s);
   } else {   // the finest level's right-hand side: the velocity part of each lane, contiguous
     T *bu = Pr<T>::w(c.mgu.lv[0], 1);
     convert_l(LP<T>(bu, 2 * N2), LP<const T>(r, nf), 2 * N2, s, K);
-    xu = vcycle<T, 4, 2>(c.mgu, 0, bu, s, nullptr, K);
+    T *xu = vcycle<T, 4, 2>(c.mgu, 0, bu, s, nullptr, K);
+    convert_l(LP<T>(z, nf), LP<const T>(xu, 2 * N2), 2 * N2, s, K);
   }
-  convert_l(LP<T>(z, nf), LP<const T>(xu, 2 * N2), 2 * N2, s, K);
   // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
   T *rp = Pr<T>::inner(c, 8).p;
   convert_l(LP<T>(rp, Np), LP<const T>(r + 2 * N2, nf), Np, sp, K);
