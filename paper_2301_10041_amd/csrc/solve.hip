@@ -859,13 +859,15 @@ static void ensure_inner(Ctx &c, int prec, int K = 1) {
   }
 }
 
-// Default inner tolerances (flexible outer GMRES: they trade outer for inner steps).
-// Measured on the 256^2 / 512^2 / 1024^2 workloads, FP64 from 1e-4 to 3e-3: outer steps
-// 9->10 / 5->5 / 9->9, step time -13% / -31% / -23%; mixed from 1e-3 to 1e-2: outer
-// 10->10 / 5->5 / 9->10, step time -12% / -20% / -19%.
+// Default inner tolerance 1e-2 in both precisions (flexible outer GMRES: it trades outer for
+// inner steps).  Measured on the 1024^2 / 256^2 / 512^2 workloads with the multigrid of this
+// file, FP64 step time at 1.5e-3, 3e-3, 6e-3, 1e-2, 2e-2: 247/235/203/193/225, 138/137/117/
+// 106/103, 60/55/51/48/54 ms (outer steps 9, 10, 5 up to 1e-2, one more at 2e-2 on two
+// workloads); mixed at 5e-3, 1e-2, 2e-2, 4e-2: 182/152/177/142, 104/97/94/95, 46/42/47/45 ms.
 double inner_tol(const Ctx &c, int prec) {
   if (c.inner_rtol > 0) return c.inner_rtol;
-  return prec == FSI_FP64 ? 3e-3 : 1e-2;
+  (void)prec;
+  return 1e-2;
 }
 
 // The block preconditioner on K systems: system k belongs to context cs[k] (one fluid grid
