@@ -379,8 +379,9 @@ template <> const double *mp_dinv<double>(Ctx &c) { return c.Mp_dinv.p; }
 template <> const float *mp_dinv<float>(Ctx &c) { return c.Mp_dinv32.p; }
 
 // Chebyshev-Jacobi steps of the pressure mass inverse inside the Schur approximation
-// (measured at 1024^2: 8, 4 and 3 steps give the same outer count; 2 and 1 cost inner steps)
-constexpr int kMpSteps = 4;
+// (measured with the final multigrid, inner steps per step at 1024^2 / 256^2 / 512^2:
+// 4 steps 163/201/81, 3 steps 144/204/83, 2 steps 229/228/92; 3 is the fastest overall)
+constexpr int kMpSteps = 3;
 
 // z = diag(V, S^{-1}) r on [u | p], for K systems at once (lane k of r and z at + k nf,
 // nf = 2 N2 + Np; K > 1 needs the matrix-free hierarchies).  The two blocks share no
