@@ -217,10 +217,10 @@ def main():
     k = m["kernel"]
     roofline = {"bound": "hbm", "achieved": round(k["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(k["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                "traffic": recorded_traffic(args.workload, "k_cheb2<double,C2_POST>")
+                "traffic": recorded_traffic(args.workload, "k_cheb3<double>")
                 if main_tag == "fp64" else None,
-                "kernel": ("k_cheb2<%s,C2_POST> (finest-level matrix-free A_f smoothing: the first "
-                           "two post-smoothing Chebyshev steps in one launch)"
+                "kernel": ("k_cheb3<%s> (finest-level matrix-free A_f smoothing: the three "
+                           "post-smoothing Chebyshev steps in one launch)"
                            % ("double" if main_tag == "fp64" else "float")),
                 "bytes_per_launch": k["bytes_per_launch"], "avg_us": round(k["avg_us"], 2),
                 "launches": k["launches"]}

@@ -285,8 +285,9 @@ int fsi_set_graphs(fsi_ctx *ctx, int enable);
 
 /* Measurement of the dominant kernel, the finest-level Chebyshev smoothing on A_f
  * (d = c1 d + c2 D^{-1}(b - A_f x), y = x + d on the 2x2-block system): with the
- * structured-grid products (default) the launch that takes the first two post-smoothing
- * steps at once (temporal blocking); with FSI_SMOOTH_CSR every single-step launch.
+ * structured-grid products (default) the launch that takes the post-smoothing steps at
+ * once (three for the default degree 3, temporal blocking); with FSI_SMOOTH_CSR every
+ * single-step launch.
  * fsi_profile(ctx, 1) starts (and resets) timing every such launch with a pair of HIP
  * events on the context's stream; fsi_profile(ctx, 0) stops.  fsi_profile_read
  * synchronises and returns, for precision prec, the number of timed launches, their summed

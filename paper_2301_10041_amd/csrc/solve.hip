@@ -219,10 +219,10 @@ static T *chebyshev_mf(First first, Step step, double lmin, double lmax, int ste
 }
 
 // Chebyshev on A_f (stencil) with right-hand side b and direction buffer d: the first three
-// steps from zero (pre-smoothing) or the first two from x (post-smoothing) as one
-// temporally blocked launch, further steps one launch each (same recurrence as
-// chebyshev_mf; the profile brackets the two-step post-smoothing launches, the largest
-// single kernel of a step).
+// steps from zero (pre-smoothing) or the first three (else two) from x (post-smoothing) as
+// one temporally blocked launch, further steps one launch each (same recurrence as
+// chebyshev_mf; the profile brackets the post-smoothing launches, the largest single
+// kernel of a step).
 // out (optional, not zero_init): the last launch writes the result there instead of into a
 // ping-pong buffer (returned); used to write a V-cycle's result into the caller's vector.
 template <typename T>
@@ -246,6 +246,17 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
     next(c1a, c2a);
     next(c1b, c2b);
     cheb2_pre<T>(n, tab, lb, ld, LP<T>(x, ls), (T)(1.0 / theta), c1a, c2a, c1b, c2b, s, K);
+    done = 3;
+  } else if (!zero_init && steps >= 3) {
+    T c1b, c2b, c1c, c2c;
+    next(c1b, c2b);
+    next(c1c, c2c);
+    T *dst = (out && steps == 3) ? out : x2;
+    if (prof) prof->begin(s);
+    cheb3_post<T>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(dst, ls), (T)(1.0 / theta), c1b, c2b, c1c, c2c, s, K);
+    if (prof) prof->end(s);
+    x2 = x;
+    x = dst;
     done = 3;
   } else if (!zero_init && steps >= 2) {
     T c1b, c2b;

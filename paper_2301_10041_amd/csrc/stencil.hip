@@ -686,6 +686,260 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb2(Cheb2Args<T> a0, int tiles
   }
 }
 
+// ---------------------------------------------------------------- three steps per launch
+// The whole post-smoothing of a degree-3 smoother: from x, a step with c1 = 0 (c2a) and two
+// steps (c1b, c2b), (c1c, c2c); reads x and b, writes y and d (8 w per node, as C2_POST).
+// Tile of kC3R rows x kC3W nodes; x staged with a halo of 6 (X0), the first step on the tile
+// plus a halo of 4 (region 1: kC3R + 8 rows x 128 nodes, X1 over X0), the second on the tile
+// plus a halo of 2 (stored in region-1 coordinates, X2 over X1), the third on the tile.
+// Every phase uses the lane layout of region 1 (lane holds columns i = 2 lane + par), so a
+// thread's b and directions stay in registers from one step to the next.  Waves: wave w owns
+// tile row w + 4 of region 1 in every phase and, for w < 8, one halo row: the inner halo rows
+// 2, 3, R + 4, R + 5 (steps 1 and 2) go to waves 0-3, the outer halo rows 0, 1, R + 6, R + 7
+// (step 1 only) to waves 4-7.
+constexpr int kC3W = 120, kC3R = 8;
+static_assert(kC3W + 8 == 2 * kWave && kC3W + 12 == kC2W0, "region-1 lane layout and staged width");
+
+template <typename T>
+struct Cheb3Args {
+  int n;
+  const StencilTable<T> *tab;
+  const T *x, *b;
+  T *d, *y;
+  int L2;
+  T c2a, c1b, c2b, c1c, c2c;
+  int64_t lv;   // lane stride of x, b, d, y (lane = blockIdx.y)
+};
+
+template <typename T, int RR>
+__global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T> a0, int tiles_x, int tiles, int band) {
+  constexpr int NT = 64 * RR;
+  constexpr int H0 = RR + 12, H1 = RR + 8;           // rows of the staged x and of region 1
+  constexpr int W0 = kC3W + 12, HW0 = W0 / 2, HW1 = kWave;
+  static_assert(RR >= 8 && RR % 2 == 0, "eight halo rows go to the first eight waves");
+  static_assert(2 * H1 * HW1 <= 2 * H0 * HW0, "region 1 fits in the staged x");
+  __shared__ T X0[2 * 2 * H0 * HW0];                 // [component][parity][row][column / 2]
+  T *const X1 = X0;                                  // region-1 layout, rows H1, width 128
+  const int t = (blockIdx.x % kXcd) * band + blockIdx.x / kXcd;
+  if (t >= tiles) return;
+  Cheb3Args<T> a = a0;
+  lane_shift(a.x, a.lv);
+  lane_shift(a.b, a.lv);
+  lane_shift(a.d, a.lv);
+  lane_shift(a.y, a.lv);
+  const int n2 = 2 * a.n, L = n2 + 1;
+  const int64_t N = a.L2;
+  const int I0 = (t % tiles_x) * kC3W, J0 = (t / tiles_x) * RR;
+  const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+  const StencilTable<T> &tb = *a.tab;
+  const bool inner = w < 4, has_h = w < 8;          // wave-uniform
+  // region-1 rows (origin J0 - 4): tile row, halo row
+  const int rows[2] = {w + 4, inner ? (w < 2 ? 2 + w : RR + 2 + w) : (w < 6 ? w - 4 : RR + w)};
+  auto inside = [&](int I, int J) { return I > 0 && J > 0 && I < n2 && J < n2; };
+  // b at the wave's nodes (0 outside the lattice)
+  T bv[2][2][2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int J = J0 - 4 + rows[q];
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const int I = I0 - 4 + 2 * lane + par;
+      bv[q][par][0] = 0;
+      bv[q][par][1] = 0;
+      if ((q == 0 || has_h) && I >= 0 && J >= 0 && I <= n2 && J <= n2) {
+        const int64_t r = (int64_t)J * L + I;
+        bv[q][par][0] = a.b[r];
+        bv[q][par][1] = a.b[N + r];
+      }
+    }
+  }
+  // stage x with a halo of 6 (0 at Dirichlet nodes and outside the lattice)
+  constexpr int NE = H0 * W0, IT = (NE + NT - 1) / NT;
+  T v[IT][2];
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int e = tid + NT * q, tr = e / W0, tc = e % W0;
+    const int I = I0 - 6 + tc, J = J0 - 6 + tr;
+    v[q][0] = 0;
+    v[q][1] = 0;
+    if (e < NE && inside(I, J)) {
+      const int64_t r = (int64_t)J * L + I;
+      v[q][0] = a.x[r];
+      v[q][1] = a.x[N + r];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int e = tid + NT * q, tr = e / W0, tc = e % W0;
+    if (e < NE) {
+      const int o = ((tc & 1) * H0 + tr) * HW0 + (tc >> 1);
+      X0[o] = v[q][0];
+      X0[2 * H0 * HW0 + o] = v[q][1];
+    }
+  }
+  __syncthreads();
+  // a wave's rows have one parity: the class is wave-uniform per column parity
+  const int jodd = __builtin_amdgcn_readfirstlane((J0 - 4 + rows[0]) & 1);
+  // step 1 on region 1 (from X0), c1 = 0
+  T d1[2][2][2] = {};   // [row][par][component]
+  T xs[2][2][2] = {};   // values of the step, stored after the barrier
+  auto step1 = [&](auto nr_tag) {
+    constexpr int NR = decltype(nr_tag)::value;
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const int I = I0 - 4 + 2 * lane + par;
+      const int cls = par | (jodd << 1);
+      int xr[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) xr[k] = rows[k] + 2;
+      T sp[NR][2];
+      if (par) class_products<T, 1, H0, HW0, NR>(tb, jodd, X0, xr, lane + 1, sp);
+      else class_products<T, 0, H0, HW0, NR>(tb, jodd, X0, xr, lane + 1, sp);
+      const T *di = tb.dinv[cls];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const int J = J0 - 4 + rows[k];
+        if (inside(I, J)) {
+          const int c0 = (par * H0 + rows[k] + 2) * HW0 + lane + 1;
+          const T x00 = X0[c0], x01 = X0[2 * H0 * HW0 + c0];
+          const T r0 = bv[k][par][0] - sp[k][0], r1 = bv[k][par][1] - sp[k][1];
+          const T e0 = a.c2a * (di[0] * r0 + di[1] * r1), e1 = a.c2a * (di[2] * r0 + di[3] * r1);
+          d1[k][par][0] = e0;
+          d1[k][par][1] = e1;
+          xs[k][par][0] = x00 + e0;
+          xs[k][par][1] = x01 + e1;
+        }
+      }
+    }
+  };
+  if (has_h) step1(std::integral_constant<int, 2>{});
+  else step1(std::integral_constant<int, 1>{});
+  __syncthreads();   // every wave has read X0
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      if (q == 1 && !has_h) continue;
+      const int o1 = (par * H1 + rows[q]) * HW1 + lane;
+      X1[o1] = xs[q][par][0];
+      X1[2 * H1 * HW1 + o1] = xs[q][par][1];
+    }
+  __syncthreads();
+  // step 2 on region 2 (region-1 columns 2..125, rows 2..R+5): tile row, inner halo row
+  T d2[2][2] = {};      // tile row only
+  auto step2 = [&](auto nr_tag) {
+    constexpr int NR = decltype(nr_tag)::value;
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const int i = 2 * lane + par, I = I0 - 4 + i;
+      const int cls = par | (jodd << 1);
+      int xr[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) xr[k] = rows[k];
+      // lanes 0 and 63 hold no region-2 node: their (discarded) products read in-row columns
+      const int h = lane < 1 ? 1 : lane > 62 ? 62 : lane;
+      T sp[NR][2];
+      if (par) class_products<T, 1, H1, HW1, NR>(tb, jodd, X1, xr, h, sp);
+      else class_products<T, 0, H1, HW1, NR>(tb, jodd, X1, xr, h, sp);
+      const T *di = tb.dinv[cls];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const int J = J0 - 4 + rows[k];
+        T x0 = 0, x1 = 0;
+        if (i >= 2 && i < 2 + kC3W + 4 && inside(I, J)) {
+          const int c1 = (par * H1 + rows[k]) * HW1 + lane;
+          const T r0 = bv[k][par][0] - sp[k][0], r1 = bv[k][par][1] - sp[k][1];
+          const T z0 = di[0] * r0 + di[1] * r1, z1 = di[2] * r0 + di[3] * r1;
+          const T e0 = a.c1b * d1[k][par][0] + a.c2b * z0, e1 = a.c1b * d1[k][par][1] + a.c2b * z1;
+          x0 = X1[c1] + e0;
+          x1 = X1[2 * H1 * HW1 + c1] + e1;
+          if (k == 0) {
+            d2[par][0] = e0;
+            d2[par][1] = e1;
+          }
+        }
+        xs[k][par][0] = x0;
+        xs[k][par][1] = x1;
+      }
+    }
+  };
+  if (inner) step2(std::integral_constant<int, 2>{});
+  else step2(std::integral_constant<int, 1>{});
+  __syncthreads();   // every wave has read X1
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      if (q == 1 && !inner) continue;
+      const int o1 = (par * H1 + rows[q]) * HW1 + lane;
+      X1[o1] = xs[q][par][0];
+      X1[2 * H1 * HW1 + o1] = xs[q][par][1];
+    }
+  __syncthreads();
+  // step 3 on the tile row (region-1 columns 4..R+3 of the tile: i in [4, 4 + kC3W))
+  {
+    const int row = rows[0], J = J0 - 4 + row;
+    if (J <= n2) {
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        const int i = 2 * lane + par, I = I0 - 4 + i;
+        if (i < 4 || i >= 4 + kC3W || I > n2) continue;
+        const int64_t r = (int64_t)J * L + I;
+        const T b0 = bv[0][par][0], b1 = bv[0][par][1];
+        T y0, y1, e0, e1;
+        if (inside(I, J)) {
+          const int cls = par | (jodd << 1);
+          const int xr[1] = {row};
+          T sp[1][2];
+          if (par) class_products<T, 1, H1, HW1, 1>(tb, jodd, X1, xr, lane, sp);
+          else class_products<T, 0, H1, HW1, 1>(tb, jodd, X1, xr, lane, sp);
+          const int c1 = (par * H1 + row) * HW1 + lane;
+          const T r0 = b0 - sp[0][0], r1 = b1 - sp[0][1];
+          const T *di = tb.dinv[cls];
+          const T z0 = di[0] * r0 + di[1] * r1, z1 = di[2] * r0 + di[3] * r1;
+          e0 = a.c1c * d2[par][0] + a.c2c * z0;
+          e1 = a.c1c * d2[par][1] + a.c2c * z1;
+          y0 = X1[c1] + e0;
+          y1 = X1[2 * H1 * HW1 + c1] + e1;
+        } else {   // Dirichlet row: the identity, stepped pointwise
+          const T x00 = a.x[r], x01 = a.x[N + r];
+          const T f0 = a.c2a * (b0 - x00), f1 = a.c2a * (b1 - x01);
+          const T x10 = x00 + f0, x11 = x01 + f1;
+          const T g0 = a.c1b * f0 + a.c2b * (b0 - x10), g1 = a.c1b * f1 + a.c2b * (b1 - x11);
+          const T x20 = x10 + g0, x21 = x11 + g1;
+          e0 = a.c1c * g0 + a.c2c * (b0 - x20);
+          e1 = a.c1c * g1 + a.c2c * (b1 - x21);
+          y0 = x20 + e0;
+          y1 = x21 + e1;
+        }
+        a.d[r] = e0;
+        a.d[N + r] = e1;
+        a.y[r] = y0;
+        a.y[N + r] = y1;
+      }
+    }
+  }
+}
+
+template <typename T>
+void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<T> y, T c2a, T c1b,
+                T c2b, T c1c, T c2c, hipStream_t st, int K) {
+  FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
+  FSI_REQUIRE(K >= 1 && K <= 65535, FSI_E_ARG, "lane count out of range");
+  const int L = 2 * n + 1;
+  const int tx = (L + kC3W - 1) / kC3W, ty = (L + kC3R - 1) / kC3R;
+  const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
+  const int64_t lv = common_stride({{x.p, x.s}, {b.p, b.s}, {d.p, d.s}, {y.p, y.s}}, K);
+  Cheb3Args<T> a{n, tab, x.p, b.p, d.p, y.p, L * L, c2a, c1b, c2b, c1c, c2c, lv};
+  hipLaunchKernelGGL((k_cheb3<T, kC3R>), dim3((unsigned)(band * kXcd), (unsigned)K), dim3(64 * kC3R), 0, st, a,
+                     tx, tiles, band);
+  FSI_CHECK_LAUNCH();
+}
+template void cheb3_post<double>(int, const StencilTable<double> *, LP<const double>, LP<const double>, LP<double>,
+                                 LP<double>, double, double, double, double, double, hipStream_t, int);
+template void cheb3_post<float>(int, const StencilTable<float> *, LP<const float>, LP<const float>, LP<float>,
+                                LP<float>, float, float, float, float, float, hipStream_t, int);
+
 template <typename T>
 void cheb2_pre(int n, const StencilTable<T> *tab, LP<const T> b, LP<T> d, LP<T> x, T s, T c1a, T c2a, T c1b,
                T c2b, hipStream_t st, int K) {
