@@ -90,7 +90,7 @@ def run_cpu_baseline(workload: str):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def run_serving(count: int, slots: int, per_grid: int = 2) -> dict:
+def run_serving(count: int, slots: int, per_grid: int = 1) -> dict:
     """Request loop: `count` independent mixed-precision steps arriving by a Poisson
     process at 200 req/s (grid 32..256, disk or ellipse, 216 to 12,150 triangles; request
     i draws u^n from seed 1000 + i); HBM budget = free memory - 8 GB."""

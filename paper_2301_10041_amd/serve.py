@@ -92,7 +92,8 @@ def grid_key(wl):
 def default_lanes(n):
     """Requests per lockstep batch: 16 for every grid size of the request trace (measured on
     the 512-request trace, 32^2 to 256^2, two slots per grid: 97.6 requests/s with 16 lanes
-    everywhere, 94.8 with 8 at 256^2, 87.1 with 16/16/8/4, 71.8 with 8/8/4/2)."""
+    everywhere, 94.8 with 8 at 256^2, 87.1 with 16/16/8/4, 71.8 with 8/8/4/2; 32 lanes
+    measured no faster than 16)."""
     return 16
 
 
