@@ -120,3 +120,30 @@ def test_batch_refuses_mixed_grids_and_repeats():
     assert st["converged"] == 1
     ca.close()
     cb.close()
+
+
+def test_batch_reports_nonconvergence_per_system():
+    """A step budget too small for convergence: every system of the batch reports
+    FSI_E_NOCONV in its own status, and its last iterate equals that of the same step alone
+    (bitwise); the batch call itself does not raise."""
+    torch_dev()
+    print("[batch noconv]", flush=True)
+    opts = fsi.Opts(prec=fsi.FP64, pc=fsi.PC_TRI, rtol=1e-8, maxit=3, restart=2)
+    wls = workloads(16, 3, seed=23)
+    ref = []
+    for wl in wls:
+        ctx = fsi.Context.from_workload(wl)
+        u, X, state = inputs_of(wl, ctx)
+        with pytest.raises(fsi.FsiError) as e:
+            ctx.step(u, X, state, opts)
+        assert e.value.code == fsi.FSI_E_NOCONV
+        ref.append(to_host(state))
+        ctx.close()
+    ctxs = [fsi.Context.from_workload(wl) for wl in wls]
+    states, stats, rcs = batch(ctxs, wls, opts)
+    assert rcs == [fsi.FSI_E_NOCONV] * 3
+    for k in range(3):
+        assert stats[k]["converged"] == 0 and stats[k]["its"] == 3
+        assert np.array_equal(states[k], ref[k]), k
+    for c in ctxs:
+        c.close()
