@@ -174,7 +174,8 @@ int fsi_sizes(const fsi_ctx *ctx, fsi_sizes_t *out);
  * Xn: device, 2 Ns doubles [x | y].  info may be NULL (then no synchronisation).
  * Errors: FSI_E_MESH if some X^n(E) has area <= 0 or leaves [0,1]^2 (detected on the
  * device, reported at the next synchronising call or here when info != NULL),
- * FSI_E_CAPACITY if the pieces around one solid node span more than 5,400 P2 nodes. */
+ * FSI_E_CAPACITY if the fluid cells met by the pieces around one solid node span a box of
+ * more than 4,096 P2 lattice nodes. */
 int fsi_assemble_coupling(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *info);
 
 /* (g1, 0, 0, g2) of eq. (matrix): g1 = (rho/dt) M_f u^n with boundary rows zero (u^n is

@@ -169,6 +169,10 @@ void stencil_tables(int n, double nu, double rdt, StencilTable<double> &t64, Ste
     for (int k = 0; k < cnt; ++k)
       FSI_REQUIRE(t64.off[cls][k][0] == so.d[cls][k][0] && t64.off[cls][k][1] == so.d[cls][k][1], FSI_E_ARG,
                   "stencil offsets differ from the compiled pattern");
+    constexpr CrossZero cz = cross_zero();
+    for (int k = 0; k < cnt; ++k)
+      FSI_REQUIRE(!cz.z[cls][k] || (t64.coef[cls][k][1] == 0.0 && t64.coef[cls][k][2] == 0.0), FSI_E_ARG,
+                  "a cross coupling compiled as zero is not");
   }
 }
 

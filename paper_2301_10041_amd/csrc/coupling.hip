@@ -277,18 +277,15 @@ __global__ void k_elem_piece_off(int64_t nt, const int *cand_off, const int *pie
 __constant__ int kOffC[2][6][2] = {{{0, 0}, {2, 0}, {2, 2}, {1, 0}, {2, 1}, {1, 1}},
                                    {{0, 0}, {2, 2}, {0, 2}, {1, 1}, {1, 2}, {0, 1}}};
 
-__global__ void __launch_bounds__(kWave) k_cf_rows(int pass, int64_t ns, int n,
-                                                   const int *__restrict__ n2e_ptr,
-                                                   const int *__restrict__ n2e,
-                                                   const int *__restrict__ e_piece,
-                                                   const int *__restrict__ pair_T,
-                                                   const double *__restrict__ piece_L,
-                                                   int *cnt, const int *rowptr, int *col,
-                                                   double *val, int *flag) {
-  __shared__ int wflag[kWinCap];
-  __shared__ double wval[kWinCap];
-  int64_t l = blockIdx.x;
-  if (l >= ns) return;
+// One row: returns false (and does nothing) when the window exceeds CAP nodes.  The block is
+// one wavefront; every thread takes the same path.
+template <int CAP>
+__device__ bool cf_row(int64_t l, int pass, int n, const int *__restrict__ n2e_ptr, const int *__restrict__ n2e,
+                       const int *__restrict__ e_piece, const int *__restrict__ pair_T,
+                       const double *__restrict__ piece_L, int *cnt, const int *rowptr, int *col, double *val,
+                       int *flag) {
+  __shared__ int wflag[CAP];
+  __shared__ double wval[CAP];
   int lane = threadIdx.x;
   const int L = 2 * n + 1;
   // window of lattice nodes covered by the pieces around node l
@@ -312,16 +309,17 @@ __global__ void __launch_bounds__(kWave) k_cf_rows(int pass, int64_t ns, int n,
   }
   if (imax < 0) {              // no pieces (cannot happen for a valid map)
     if (!pass && lane == 0) cnt[l] = 0;
-    return;
+    return true;
   }
   int wI = imax - imin + 1, wJ = jmax - jmin + 1;
   int W = wI * wJ;
-  if (W > kWinCap) {
+  if (W > CAP) {
+    if (CAP < kWinCap) return false;   // left to the wide form
     if (lane == 0) {
       atomicOr(flag, DF_CAP);
       if (!pass) cnt[l] = 0;
     }
-    return;
+    return true;
   }
   for (int p = lane; p < W; p += kWave) { wflag[p] = 0; wval[p] = 0.0; }
   __syncthreads();
@@ -343,7 +341,7 @@ __global__ void __launch_bounds__(kWave) k_cf_rows(int pass, int64_t ns, int n,
     for (int p = lane; p < W; p += kWave) c += wflag[p];
     c = wave_sum(c);
     if (lane == 0) cnt[l] = c;
-    return;
+    return true;
   }
   // values: item order is fixed (adjacency, piece, local node); window position p is
   // summed by lane p % 64 only, so the order of every sum is fixed.
@@ -377,6 +375,37 @@ __global__ void __launch_bounds__(kWave) k_cf_rows(int pass, int64_t ns, int n,
       val[base + incl - 1] = bndc ? 0.0 : wval[p];
     }
     base += __shfl(incl, kWave - 1, kWave);
+  }
+  return true;
+}
+
+
+// Rows with a window of up to kWinSmall nodes (12 KB of LDS: many wavefronts per CU); the
+// others are listed (defer[0] = count) for the wide form below.
+constexpr int kWinSmall = 1024;
+__global__ void __launch_bounds__(kWave) k_cf_rows(int pass, int64_t ns, int n, const int *__restrict__ n2e_ptr,
+                                                   const int *__restrict__ n2e, const int *__restrict__ e_piece,
+                                                   const int *__restrict__ pair_T,
+                                                   const double *__restrict__ piece_L, int *cnt, const int *rowptr,
+                                                   int *col, double *val, int *flag, int *defer) {
+  const int64_t l = blockIdx.x;
+  if (l >= ns) return;
+  if (!cf_row<kWinSmall>(l, pass, n, n2e_ptr, n2e, e_piece, pair_T, piece_L, cnt, rowptr, col, val, flag) &&
+      threadIdx.x == 0)
+    defer[1 + atomicAdd(&defer[0], 1)] = (int)l;   // list order does not matter: rows are independent
+}
+
+// The listed rows with a window of up to kWinCap nodes (grid-stride over the list).
+__global__ void __launch_bounds__(kWave) k_cf_rows_wide(int pass, int n, const int *__restrict__ n2e_ptr,
+                                                        const int *__restrict__ n2e, const int *__restrict__ e_piece,
+                                                        const int *__restrict__ pair_T,
+                                                        const double *__restrict__ piece_L, int *cnt,
+                                                        const int *rowptr, int *col, double *val, int *flag,
+                                                        const int *defer) {
+  const int count = defer[0];
+  for (int q = blockIdx.x; q < count; q += gridDim.x) {
+    cf_row<kWinCap>(defer[1 + q], pass, n, n2e_ptr, n2e, e_piece, pair_T, piece_L, cnt, rowptr, col, val, flag);
+    __syncthreads();
   }
 }
 
@@ -521,9 +550,13 @@ void assemble_coupling(Ctx &c, const double *Xn, bool) {
   Cf.ncols = c.N2;
   Cf.width = 1;
   Cf.rowptr.reserve(ns + 1);
+  c.cf_defer.reserve(ns + 1);
+  fill(c.cf_defer.p, 1, 0, s);
   hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 0, ns, n, c.n2e_ptr.p, c.n2e.p,
                      c.e_piece.p, c.pair_T.p, c.piece_L.p, Cf.rowptr.p, nullptr, nullptr, nullptr,
-                     c.dflag.p);
+                     c.dflag.p, c.cf_defer.p);
+  hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 0, n, c.n2e_ptr.p, c.n2e.p, c.e_piece.p,
+                     c.pair_T.p, c.piece_L.p, Cf.rowptr.p, nullptr, nullptr, nullptr, c.dflag.p, c.cf_defer.p);
   FSI_CHECK_LAUNCH();
   scan_excl(Cf.rowptr.p, Cf.rowptr.p, ns, tmp, s);
   check_flags(c);
@@ -531,9 +564,12 @@ void assemble_coupling(Ctx &c, const double *Xn, bool) {
   Cf.nnz = nnz;
   Cf.col.reserve(nnz);
   Cf.val.reserve(nnz);
+  fill(c.cf_defer.p, 1, 0, s);
   hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 1, ns, n, c.n2e_ptr.p, c.n2e.p,
                      c.e_piece.p, c.pair_T.p, c.piece_L.p, nullptr, Cf.rowptr.p, Cf.col.p, Cf.val.p,
-                     c.dflag.p);
+                     c.dflag.p, c.cf_defer.p);
+  hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, c.e_piece.p,
+                     c.pair_T.p, c.piece_L.p, nullptr, Cf.rowptr.p, Cf.col.p, Cf.val.p, c.dflag.p, c.cf_defer.p);
   FSI_CHECK_LAUNCH();
   // C_f^T
   Csr &Ct = c.CfT;

@@ -109,6 +109,7 @@ struct Ctx {
   DevBuf<double> cft_tval;
   DevBuf<int> cft_long;     // [count, rows...]: rows ranked by a workgroup each
   DevBuf<int> scan_tmp;     // scan partials (grow-only)
+  DevBuf<int> cf_defer;     // [count, rows...]: C_f rows assembled with the wide window
   DevBuf<int> dflag;       // device error flags (mesh / capacity)
 
   // multigrid hierarchies of the preconditioner

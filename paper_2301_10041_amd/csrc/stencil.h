@@ -43,6 +43,21 @@ __host__ __device__ constexpr StencilOffsets stencil_offsets() {
   }};
 }
 
+// Entries whose cross-component couplings (xy, yx) vanish for every viscosity and time step:
+// the symmetric-gradient form couples the components only through mixed derivatives, which
+// integrate to zero for these neighbour pairs on the triangulated grid (the table builder
+// checks that both values are exactly 0).  Kernels skip their two cross products.
+struct CrossZero {
+  bool z[4][kStencilMax];
+};
+__host__ __device__ constexpr CrossZero cross_zero() {
+  CrossZero c{};
+  c.z[0][1] = c.z[0][3] = c.z[0][15] = c.z[0][17] = true;   // vertex: (-1,-2), (-2,-1), (2,1), (1,2)
+  c.z[1][0] = c.z[1][8] = true;                              // horizontal edge: (-1,-2), (1,2)
+  c.z[2][0] = c.z[2][8] = true;                              // vertical edge: (-2,-1), (2,1)
+  return c;
+}
+
 // Divergence blocks on the structured grid.  B^T row of an interior P2 node of class c:
 // the P1 vertices of the triangles around it (offsets from P1 node (I >> 1, J >> 1)) with
 // the pair (B_x, B_y)(k, node).  B row of a P1 node (i, j): the P2 nodes of the triangles

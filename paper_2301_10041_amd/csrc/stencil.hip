@@ -76,14 +76,20 @@ template <typename T, int CLS>
 __device__ __forceinline__ void tile_row_products(const StencilTable<T> &tb, const T *X0, const T *X1,
                                                   int base, T &s0, T &s1) {
   constexpr StencilOffsets so = stencil_offsets();
+  constexpr CrossZero cz = cross_zero();
   s0 = 0;
   s1 = 0;
 #pragma unroll
   for (int k = 0; k < kStencilCount[CLS]; ++k) {
     const int o = base + so.d[CLS][k][1] * kTW + so.d[CLS][k][0];
     const T y0 = X0[o], y1 = X1[o];
-    s0 = fma(tb.coef[CLS][k][1], y1, fma(tb.coef[CLS][k][0], y0, s0));
-    s1 = fma(tb.coef[CLS][k][3], y1, fma(tb.coef[CLS][k][2], y0, s1));
+    if (cz.z[CLS][k]) {   // xy = yx = 0 (fma with a zero coefficient adds nothing)
+      s0 = fma(tb.coef[CLS][k][0], y0, s0);
+      s1 = fma(tb.coef[CLS][k][3], y1, s1);
+    } else {
+      s0 = fma(tb.coef[CLS][k][1], y1, fma(tb.coef[CLS][k][0], y0, s0));
+      s1 = fma(tb.coef[CLS][k][3], y1, fma(tb.coef[CLS][k][2], y0, s1));
+    }
   }
 }
 
@@ -452,6 +458,7 @@ __device__ __forceinline__ void split_products(const StencilTable<T> &tb, const 
   constexpr int PAR = CLS & 1;
   constexpr int COMP = 2 * ROWS * HW;   // offset of the second component
   constexpr StencilOffsets so = stencil_offsets();
+  constexpr CrossZero cz = cross_zero();
 #pragma unroll
   for (int q = 0; q < NR; ++q) s[q][0] = s[q][1] = 0;
 #pragma unroll
@@ -463,8 +470,13 @@ __device__ __forceinline__ void split_products(const StencilTable<T> &tb, const 
     for (int q = 0; q < NR; ++q) {   // FMA chains: two FMAs per coefficient pair
       const int o = row[q] * HW + h + off;
       const T y0 = X[o], y1 = X[COMP + o];
-      s[q][0] = fma(c1, y1, fma(c0, y0, s[q][0]));
-      s[q][1] = fma(c3, y1, fma(c2, y0, s[q][1]));
+      if (cz.z[CLS][k]) {   // xy = yx = 0 (fma with a zero coefficient adds nothing)
+        s[q][0] = fma(c0, y0, s[q][0]);
+        s[q][1] = fma(c3, y1, s[q][1]);
+      } else {
+        s[q][0] = fma(c1, y1, fma(c0, y0, s[q][0]));
+        s[q][1] = fma(c3, y1, fma(c2, y0, s[q][1]));
+      }
     }
   }
 }

@@ -55,4 +55,7 @@ def small_workloads():
         "disk32": (inputs.WORKLOADS["disk32"], None),
         "ellipse16_rot": (inputs.small_workload(16, 5, (0.45, 0.55), semi_axes=(0.25, 0.15)), 0.4),
         "disk8_edge": (inputs.small_workload(8, 3, (0.5, 0.5), 0.25), None),
+        # solid triangles of about 8 x 8 cells: the pieces around a solid node span more than
+        # 1,024 lattice nodes (the wide-window form of the C_f rows)
+        "coarse_disk128": (inputs.small_workload(128, 3, (0.47, 0.52), 0.2), 0.3),
     }
