@@ -132,9 +132,7 @@ __device__ __forceinline__ bool on_p2_boundary(int I, int J, int n) {
 // y += P xc: coarse quadratic evaluated at the fine node; Dirichlet nodes (fine rows and
 // coarse columns) take no part.  An interior fine node (I, J) lies in coarse cell
 // (I >> 2, J >> 2) at the local position (I mod 4, J mod 4): one of 16 classes, each a fixed
-// set of at most six coarse nodes and weights (prolong_classes).  A wave takes the nodes of
-// one residue of I mod 4 in a fine row (lanes 4 apart), so its class is uniform and the
-// offsets and weights are compile-time constants.
+// set of at most six coarse nodes and weights (prolong_classes).
 struct ProlongClass {
   int cnt;
   int d[6][2];    // coarse lattice offsets from (2 ci, 2 cj)
@@ -177,24 +175,35 @@ __host__ __device__ constexpr ProlongClasses prolong_classes() {
   return t;
 }
 
-template <typename T, int CLS>
-__device__ __forceinline__ void prolong_node(int ci, int cj, int nc, int Lc, int64_t Nc, const T *__restrict__ xc,
-                                             T &s0, T &s1) {
+// One fine row segment per block, one node per thread (lanes on consecutive nodes: coalesced
+// reads and writes of y).  The row's J mod 4 = B is uniform over the block; the node's
+// I mod 4 varies with the lane, so each of the six (offset, weight) entries is selected from
+// the four compile-time classes of the row (unused entries: weight 0 at the cell's first
+// node).  Coarse Dirichlet nodes read as 0.  Sums in the order of prolong_classes.
+template <typename T, int B>
+__device__ __forceinline__ void prolong_row(int I, int J, int nc, int Lc, int64_t Nc, const T *__restrict__ xc, T &s0,
+                                            T &s1) {
   constexpr ProlongClasses pcs = prolong_classes();
-  constexpr ProlongClass p = pcs.c[CLS];
+  const int A = I & 3, ci = I >> 2, cj = J >> 2;
   s0 = 0;
   s1 = 0;
 #pragma unroll
-  for (int q = 0; q < p.cnt; ++q) {
-    const int Ic = 2 * ci + p.d[q][0], Jc = 2 * cj + p.d[q][1];
-    if (Ic == 0 || Jc == 0 || Ic == 2 * nc || Jc == 2 * nc) continue;
-    const int64_t k = (int64_t)Jc * Lc + Ic;
-    s0 += (T)p.w[q] * xc[k];
-    s1 += (T)p.w[q] * xc[Nc + k];
+  for (int q = 0; q < 6; ++q) {
+    auto pick_i = [&](int a) { return q < pcs.c[4 * B + a].cnt ? pcs.c[4 * B + a].d[q][0] : 0; };
+    auto pick_j = [&](int a) { return q < pcs.c[4 * B + a].cnt ? pcs.c[4 * B + a].d[q][1] : 0; };
+    auto pick_w = [&](int a) { return q < pcs.c[4 * B + a].cnt ? pcs.c[4 * B + a].w[q] : 0.0; };
+    const int dI = A == 0 ? pick_i(0) : A == 1 ? pick_i(1) : A == 2 ? pick_i(2) : pick_i(3);
+    const int dJ = A == 0 ? pick_j(0) : A == 1 ? pick_j(1) : A == 2 ? pick_j(2) : pick_j(3);
+    const T w = (T)(A == 0 ? pick_w(0) : A == 1 ? pick_w(1) : A == 2 ? pick_w(2) : pick_w(3));
+    const int Ic = 2 * ci + dI, Jc = 2 * cj + dJ;
+    const bool in = Ic > 0 && Jc > 0 && Ic < 2 * nc && Jc < 2 * nc;
+    const int64_t k = in ? (int64_t)Jc * Lc + Ic : 0;
+    const T v0 = in ? xc[k] : T(0), v1 = in ? xc[Nc + k] : T(0);
+    s0 += w * v0;
+    s1 += w * v1;
   }
 }
 
-// Block = one fine row segment of 256 nodes; wave w takes I = base + 4 lane + w.
 template <typename T>
 __global__ void __launch_bounds__(256) k_p2_prolong_add(int nf, LP<const T> xcl, LP<T> yl, int segs) {
   const T *__restrict__ xc = xcl.at(blockIdx.y);
@@ -202,20 +211,14 @@ __global__ void __launch_bounds__(256) k_p2_prolong_add(int nf, LP<const T> xcl,
   const int L = 2 * nf + 1, nc = nf / 2, Lc = 2 * nc + 1;
   const int64_t Nf = (int64_t)L * L, Nc = (int64_t)Lc * Lc;
   const int J = blockIdx.x / segs, seg = blockIdx.x % segs;
-  const int A = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
-  const int I = seg * 256 + 4 * ((int)threadIdx.x % kWave) + A;
+  const int I = seg * 256 + (int)threadIdx.x;
   if (I >= L || I == 0 || J == 0 || I == 2 * nf || J == 2 * nf) return;
-  const int ci = I >> 2, cj = J >> 2;
   T s0, s1;
-  switch (4 * (J & 3) + A) {
-#define FSI_PROLONG_CASE(c) \
-  case c: prolong_node<T, c>(ci, cj, nc, Lc, Nc, xc, s0, s1); break;
-    FSI_PROLONG_CASE(0) FSI_PROLONG_CASE(1) FSI_PROLONG_CASE(2) FSI_PROLONG_CASE(3)
-    FSI_PROLONG_CASE(4) FSI_PROLONG_CASE(5) FSI_PROLONG_CASE(6) FSI_PROLONG_CASE(7)
-    FSI_PROLONG_CASE(8) FSI_PROLONG_CASE(9) FSI_PROLONG_CASE(10) FSI_PROLONG_CASE(11)
-    FSI_PROLONG_CASE(12) FSI_PROLONG_CASE(13) FSI_PROLONG_CASE(14) FSI_PROLONG_CASE(15)
-#undef FSI_PROLONG_CASE
-    default: s0 = s1 = 0;
+  switch (J & 3) {
+    case 0: prolong_row<T, 0>(I, J, nc, Lc, Nc, xc, s0, s1); break;
+    case 1: prolong_row<T, 1>(I, J, nc, Lc, Nc, xc, s0, s1); break;
+    case 2: prolong_row<T, 2>(I, J, nc, Lc, Nc, xc, s0, s1); break;
+    default: prolong_row<T, 3>(I, J, nc, Lc, Nc, xc, s0, s1); break;
   }
   const int64_t r = (int64_t)J * L + I;
   y[r] += s0;
