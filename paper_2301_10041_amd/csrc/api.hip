@@ -571,9 +571,11 @@ int fsi_profile_read(fsi_ctx *ctx, int prec, int64_t *launches, double *total_ms
     const fsi::MgLevel &L = c.mgu.lv[0];
     if (launches) *launches = cnt;
     if (total_ms) *total_ms = t;
+    // FP32 form with three post-smoothing steps: the launch stores y into the FP64 output
+    const double wy = (prec == FSI_FP32 && c.mgu.degree32 == 3) ? 8.0 : w;
     if (bytes_per_launch)
       *bytes_per_launch = c.mgu.stencil
-                              ? (double)L.nodes * 8 * w
+                              ? (double)L.nodes * 2 * (3 * w + wy)
                               : (double)L.A.nnz * (4 * w + 4) + (double)L.nodes * (4 + 14 * w) + 4.0;
   });
 }

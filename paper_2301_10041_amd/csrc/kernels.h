@@ -208,13 +208,13 @@ __global__ void k_axpby(T *y, const T *x, T a, T b, int64_t n) {
 }
 
 // z = a x + b y
-template <typename T>
-__global__ void k_lincomb(LP<T> zl, LP<const T> xl, LP<const T> yl, T a, T b, int64_t n) {
-  T *z = zl.at(blockIdx.y);
+template <typename TZ, typename T>
+__global__ void k_lincomb(LP<TZ> zl, LP<const T> xl, LP<const T> yl, T a, T b, int64_t n) {   // z = a x + b y
+  TZ *z = zl.at(blockIdx.y);
   const T *x = xl.at(blockIdx.y), *y = yl.at(blockIdx.y);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    z[i] = a * x[i] + b * y[i];
+    z[i] = (TZ)(a * x[i] + b * y[i]);
 }
 
 inline unsigned vgrid(int64_t n) {
@@ -249,7 +249,14 @@ inline void axpby(T *y, const T *x, T a, T b, int64_t n, hipStream_t s) {
 }
 template <typename T>
 inline void lincomb_l(LP<T> z, LP<const T> x, LP<const T> y, T a, T b, int64_t n, hipStream_t s, int K) {
-  hipLaunchKernelGGL(k_lincomb<T>, dim3(vgrid(n), K), dim3(256), 0, s, z, x, y, a, b, n);
+  hipLaunchKernelGGL((k_lincomb<T, T>), dim3(vgrid(n), K), dim3(256), 0, s, z, x, y, a, b, n);
+  FSI_CHECK_LAUNCH();
+}
+// z = a x + b y computed in T, stored as TZ
+template <typename TZ, typename T>
+inline void lincomb_to(TZ *z, const T *x, const T *y, T a, T b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_lincomb<TZ, T>), dim3(vgrid(n)), dim3(256), 0, s, LP<TZ>(z), LP<const T>(x), LP<const T>(y), a,
+                     b, n);
   FSI_CHECK_LAUNCH();
 }
 template <typename T>

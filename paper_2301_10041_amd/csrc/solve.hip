@@ -114,6 +114,12 @@ __global__ void k_set_pinned(T *z, const T *r, int64_t ls) {   // lane blockIdx.
   if (threadIdx.x == 0 && blockIdx.x == 0) z[(int64_t)blockIdx.y * ls] = r[(int64_t)blockIdx.y * ls];
 }
 
+// z[0] = r[0] rounded through T (the value an FP32 preconditioner would pass on)
+template <typename TZ, typename T>
+__global__ void k_set_pinned_to(TZ *z, const TZ *r) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) z[0] = (TZ)(T)r[0];
+}
+
 template <typename T>
 __global__ void k_negate(T *y, const T *x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -225,10 +231,12 @@ static T *chebyshev_mf(First first, Step step, double lmin, double lmax, int ste
 // kernel of a step).
 // out (optional, not zero_init): the last launch writes the result there instead of into a
 // ping-pong buffer (returned); used to write a V-cycle's result into the caller's vector.
+// out64 (optional, FP32 arithmetic, three steps from x): the result goes to that FP64 vector
+// and the function returns nullptr.
 template <typename T>
 static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, double lmax, int steps,
                             const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s, Prof *prof,
-                            int K = 1, int64_t ls = 0, T *out = nullptr) {
+                            int K = 1, int64_t ls = 0, T *out = nullptr, double *out64 = nullptr) {
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
@@ -247,6 +255,15 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
     next(c1b, c2b);
     cheb2_pre<T>(n, tab, lb, ld, LP<T>(x, ls), (T)(1.0 / theta), c1a, c2a, c1b, c2b, s, K);
     done = 3;
+  } else if (!zero_init && steps == 3 && out64) {
+    T c1b, c2b, c1c, c2c;
+    next(c1b, c2b);
+    next(c1c, c2c);
+    if (prof) prof->begin(s);
+    cheb3_post<T, double>(n, tab, LP<const T>(x, ls), lb, ld, LP<double>(out64, ls), (T)(1.0 / theta), c1b, c2b,
+                          c1c, c2c, s, K);
+    if (prof) prof->end(s);
+    return nullptr;
   } else if (!zero_init && steps >= 3) {
     T c1b, c2b, c1c, c2c;
     next(c1b, c2b);
@@ -320,9 +337,11 @@ template <typename T> static const P2RestrTable<T> *rtab(const Mg &mg) {
 // One V-cycle at level l for right-hand side b (comps * nodes entries, component-major).
 // Returns the level work vector that holds the result.
 // out (optional): where the matrix-free velocity cycle writes its result (the returned
-// pointer); otherwise a level work vector.
+// pointer); otherwise a level work vector.  out64 (optional, FP32 cycle): an FP64 vector the
+// result goes to when the last smoothing launch can store it there (then nullptr is returned).
 template <typename T, int W, int NC>
-static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr, int K = 1, T *out = nullptr) {
+static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr, int K = 1, T *out = nullptr,
+                 double *out64 = nullptr) {
   MgLevel &L = mg.lv[l];
   T *x = Pr<T>::w(L, 0), *x2 = Pr<T>::w(L, 4), *r = Pr<T>::w(L, 2), *d = Pr<T>::w(L, 3);
   // K systems (matrix-free hierarchy only): lane k of every level vector at + k comps nodes
@@ -349,7 +368,7 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
     auto smooth = [&](T *x0, T *x1, bool zero) -> T * {
       if constexpr (W == 4)
         return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, pl, K, ls,
-                                    zero ? nullptr : out);
+                                    zero ? nullptr : out, zero ? nullptr : out64);
       else
         return chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, K, ls);
     };
@@ -400,8 +419,10 @@ constexpr int kMpSteps = 3;
 // velocity V-cycle (both chains are latency-bound on the coarse levels), forked after the
 // producer of r and joined before the consumer of z.  Captured graphs keep the whole
 // preconditioner on one stream.
+// r64, z64 (FP32 arithmetic, one system): the results are stored straight into the FP64 vector
+// z64 (z unused) and the pressure residual is read from r64 (r holds the velocity part).
 template <typename T>
-static void a11_precond(Ctx &c, const T *r, T *z, int K = 1) {
+static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 = nullptr, double *z64 = nullptr) {
   const bool fork = !c.capturing;
   hipStream_t s = c.stream, sp = fork ? c.aux_stream : c.stream;
   const int64_t N2 = c.N2, Np = c.Np, nf = 2 * N2 + Np;
@@ -410,7 +431,10 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1) {
     FSI_HIP(hipEventRecord(c.ev_fork, s));
     FSI_HIP(hipStreamWaitEvent(sp, c.ev_fork, 0));
   }
-  if (K == 1) {   // the cycle reads r and writes z in place (one system: no lane stride)
+  if (z64) {
+    T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr, 1, nullptr, z64);
+    if (xu) convert(z64, xu, 2 * N2, s);
+  } else if (K == 1) {   // the cycle reads r and writes z in place (one system: no lane stride)
     T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr, 1, z);
     if (xu != z) convert(z, xu, 2 * N2, s);
   } else {   // the finest level's right-hand side: the velocity part of each lane, contiguous
@@ -421,7 +445,8 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1) {
   }
   // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
   T *rp = Pr<T>::inner(c, 8).p;
-  convert_l(LP<T>(rp, Np), LP<const T>(r + 2 * N2, nf), Np, sp, K);
+  if (z64) convert(rp, r64 + 2 * N2, Np, sp);
+  else convert_l(LP<T>(rp, Np), LP<const T>(r + 2 * N2, nf), Np, sp, K);
   fill_l(LP<T>(rp, Np), 1, (T)0, sp, K);
   T *xp = vcycle<T, 1, 1>(c.mgp, 0, rp, sp, nullptr, K);
   // mass solve scratch: x, x2, d of every lane (3 Np each) in one inner vector
@@ -432,9 +457,14 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1) {
                                   0.5, 2.0, kMpSteps, rp, mx, mx2, md, true, sp, K, Np)
                 : chebyshev<T, 1, 1>(Np, c.Mp.rowptr.p, c.Mp.col.p, Pr<T>::val(c.Mp), mp_dinv<T>(c), 0.5,
                                      2.0, kMpSteps, rp, mx, mx2, md, true, sp);
-  lincomb_l(LP<T>(z + 2 * N2, nf), LP<const T>(mres, Np), LP<const T>(xp, Np), (T)c.nu, (T)(c.rho / c.dt), Np,
-            sp, K);
-  hipLaunchKernelGGL(k_set_pinned<T>, dim3(1, K), dim3(1), 0, sp, z + 2 * N2, r + 2 * N2, nf);
+  if (z64) {
+    lincomb_to<double, T>(z64 + 2 * N2, mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, sp);
+    hipLaunchKernelGGL((k_set_pinned_to<double, T>), dim3(1), dim3(1), 0, sp, z64 + 2 * N2, r64 + 2 * N2);
+  } else {
+    lincomb_l(LP<T>(z + 2 * N2, nf), LP<const T>(mres, Np), LP<const T>(xp, Np), (T)c.nu, (T)(c.rho / c.dt), Np,
+              sp, K);
+    hipLaunchKernelGGL(k_set_pinned<T>, dim3(1, K), dim3(1), 0, sp, z + 2 * N2, r + 2 * N2, nf);
+  }
   FSI_CHECK_LAUNCH();
   if (fork) {
     FSI_HIP(hipEventRecord(c.ev_join, sp));
@@ -443,11 +473,16 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1) {
 }
 
 // ---------------------------------------------------------------- inner MINRES
-// The A11 preconditioner on FP64 vectors with arithmetic TA: FP32 runs on converted copies.
+// The A11 preconditioner on FP64 vectors with arithmetic TA: FP32 runs on a converted copy
+// of the velocity residual (read three times by the finest level) and stores its results
+// straight into z; several systems run on converted copies of whole vectors.
 template <typename TA>
 static void a11_precond_on64(Ctx &c, const double *r, double *z, int K = 1) {
   if constexpr (std::is_same<TA, double>::value) {
     a11_precond<double>(c, r, z, K);
+  } else if (K == 1) {
+    convert(c.outer.x32.p, r, 2 * c.N2, c.stream);
+    a11_precond<float>(c, c.outer.x32.p, nullptr, 1, r, z);
   } else {
     const int64_t nf = 2 * c.N2 + c.Np;
     convert_l(LP<float>(c.outer.x32.p, nf), LP<const double>(r, nf), nf, c.stream, K);

@@ -116,9 +116,10 @@ void cheb2_pre(int n, const StencilTable<T> *tab, LP<const T> b, LP<T> d, LP<T> 
 template <typename T>
 void cheb2_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<T> y, T c2a, T c1b,
                 T c2b, hipStream_t st, int K = 1);
-// cheb3_post: from x, a step with c1 = 0 (c2a) and steps (c1b, c2b), (c1c, c2c); writes y, d
-template <typename T>
-void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<T> y, T c2a, T c1b,
+// cheb3_post: from x, a step with c1 = 0 (c2a) and steps (c1b, c2b), (c1c, c2c); writes y
+// (stored as TY: double or T) and d
+template <typename T, typename TY = T>
+void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<TY> y, T c2a, T c1b,
                 T c2b, T c1c, T c2c, hipStream_t st, int K = 1);
 
 // The same launch inside the inner MINRES (FP64): v = s x, y = s (A11 x) + c r1 written over

@@ -712,19 +712,20 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb2(Cheb2Args<T> a0, int tiles
 constexpr int kC3W = 120, kC3R = 8;
 static_assert(kC3W + 8 == 2 * kWave && kC3W + 12 == kC2W0, "region-1 lane layout and staged width");
 
-template <typename T>
-struct Cheb3Args {
+template <typename T, typename TY>
+struct Cheb3Args {   // y stored as TY (the mixed form writes FP32 results into an FP64 vector)
   int n;
   const StencilTable<T> *tab;
   const T *x, *b;
-  T *d, *y;
+  T *d;
+  TY *y;
   int L2;
   T c2a, c1b, c2b, c1c, c2c;
   int64_t lv;   // lane stride of x, b, d, y (lane = blockIdx.y)
 };
 
-template <typename T, int RR>
-__global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T> a0, int tiles_x, int tiles, int band) {
+template <typename T, int RR, typename TY>
+__global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int tiles_x, int tiles, int band) {
   constexpr int NT = 64 * RR;
   constexpr int H0 = RR + 12, H1 = RR + 8;           // rows of the staged x and of region 1
   constexpr int W0 = kC3W + 12, HW0 = W0 / 2, HW1 = kWave;
@@ -734,7 +735,7 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T> a0, int tiles
   T *const X1 = X0;                                  // region-1 layout, rows H1, width 128
   const int t = (blockIdx.x % kXcd) * band + blockIdx.x / kXcd;
   if (t >= tiles) return;
-  Cheb3Args<T> a = a0;
+  Cheb3Args<T, TY> a = a0;
   lane_shift(a.x, a.lv);
   lane_shift(a.b, a.lv);
   lane_shift(a.d, a.lv);
@@ -926,15 +927,15 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T> a0, int tiles
         }
         a.d[r] = e0;
         a.d[N + r] = e1;
-        a.y[r] = y0;
-        a.y[N + r] = y1;
+        a.y[r] = (TY)y0;
+        a.y[N + r] = (TY)y1;
       }
     }
   }
 }
 
-template <typename T>
-void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<T> y, T c2a, T c1b,
+template <typename T, typename TY>
+void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<TY> y, T c2a, T c1b,
                 T c2b, T c1c, T c2c, hipStream_t st, int K) {
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
   FSI_REQUIRE(K >= 1 && K <= 65535, FSI_E_ARG, "lane count out of range");
@@ -942,15 +943,18 @@ void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b,
   const int tx = (L + kC3W - 1) / kC3W, ty = (L + kC3R - 1) / kC3R;
   const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
   const int64_t lv = common_stride({{x.p, x.s}, {b.p, b.s}, {d.p, d.s}, {y.p, y.s}}, K);
-  Cheb3Args<T> a{n, tab, x.p, b.p, d.p, y.p, L * L, c2a, c1b, c2b, c1c, c2c, lv};
-  hipLaunchKernelGGL((k_cheb3<T, kC3R>), dim3((unsigned)(band * kXcd), (unsigned)K), dim3(64 * kC3R), 0, st, a,
-                     tx, tiles, band);
+  Cheb3Args<T, TY> a{n, tab, x.p, b.p, d.p, y.p, L * L, c2a, c1b, c2b, c1c, c2c, lv};
+  hipLaunchKernelGGL((k_cheb3<T, kC3R, TY>), dim3((unsigned)(band * kXcd), (unsigned)K), dim3(64 * kC3R), 0, st,
+                     a, tx, tiles, band);
   FSI_CHECK_LAUNCH();
 }
-template void cheb3_post<double>(int, const StencilTable<double> *, LP<const double>, LP<const double>, LP<double>,
-                                 LP<double>, double, double, double, double, double, hipStream_t, int);
-template void cheb3_post<float>(int, const StencilTable<float> *, LP<const float>, LP<const float>, LP<float>,
-                                LP<float>, float, float, float, float, float, hipStream_t, int);
+template void cheb3_post<double, double>(int, const StencilTable<double> *, LP<const double>, LP<const double>,
+                                         LP<double>, LP<double>, double, double, double, double, double, hipStream_t,
+                                         int);
+template void cheb3_post<float, float>(int, const StencilTable<float> *, LP<const float>, LP<const float>, LP<float>,
+                                       LP<float>, float, float, float, float, float, hipStream_t, int);
+template void cheb3_post<float, double>(int, const StencilTable<float> *, LP<const float>, LP<const float>,
+                                        LP<float>, LP<double>, float, float, float, float, float, hipStream_t, int);
 
 template <typename T>
 void cheb2_pre(int n, const StencilTable<T> *tab, LP<const T> b, LP<T> d, LP<T> x, T s, T c1a, T c2a, T c1b,
