@@ -1,8 +1,8 @@
 """Lockstep batches of small steps (fsi_step_batch, the batched serving form): every
 system's result must equal its step alone bitwise (each system runs the same kernels; the
 inner A11 solves of all systems are lanes of one launch), across lane counts that grow
-and shrink on one leading context, with and without captured graphs, in FP64 and mixed
-precision; one batch is checked against the FP64 oracle, and batches that mix fluid
+and shrink on one leading context, with and without captured graphs, in FP64, mixed
+precision and FP32 refinement; one batch is checked against the FP64 oracle, and batches that mix fluid
 grids or repeat a context are refused."""
 import numpy as np
 import pytest
@@ -58,6 +58,7 @@ CASES = [
     ("n16_fp64_graphs", 16, fsi.FP64, True, [4, 2, 5]),
     ("n32_mixed_graphs", 32, fsi.FP32, True, [3, 1]),
     ("n16_fp64_eager", 16, fsi.FP64, False, [3]),
+    ("n16_fp32ir_graphs", 16, fsi.FP32_IR, True, [3]),
 ]
 
 
