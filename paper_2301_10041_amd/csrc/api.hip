@@ -17,11 +17,11 @@ namespace fsi {
 
 Ctx::~Ctx() {
   drop_graphs();
-  if (cap_stream) hipStreamDestroy(cap_stream);
-  if (aux_stream) hipStreamDestroy(aux_stream);
-  if (ev_fork) hipEventDestroy(ev_fork);
-  if (ev_join) hipEventDestroy(ev_join);
-  if (hpin) hipHostFree(hpin);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  if (aux_stream) (void)hipStreamDestroy(aux_stream);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (hpin) (void)hipHostFree(hpin);
 }
 
 void Prof::begin(hipStream_t s) {
@@ -53,7 +53,7 @@ double Prof::total_ms(int64_t &launches) {
 }
 
 Prof::~Prof() {
-  for (auto e : ev) hipEventDestroy(e);
+  for (auto e : ev) (void)hipEventDestroy(e);
 }
 
 size_t Ctx::device_bytes() const {
@@ -178,7 +178,7 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
 
 void fsi_destroy(fsi_ctx *ctx) {
   if (!ctx) return;
-  hipStreamSynchronize(ctx->c.stream);
+  (void)hipStreamSynchronize(ctx->c.stream);
   delete ctx;
 }
 
@@ -209,18 +209,20 @@ int fsi_set_solid(fsi_ctx *ctx, const fsi_solid_desc *solid) {
 int fsi_set_smoother(fsi_ctx *ctx, int kind) {
   if (!ctx) return FSI_E_ARG;
   if (kind != FSI_SMOOTH_CSR && kind != FSI_SMOOTH_STENCIL) return FSI_E_ARG;
-  hipStreamSynchronize(ctx->c.stream);
-  ctx->c.drop_graphs();
-  ctx->c.mgu.stencil = ctx->c.mgp.stencil = kind == FSI_SMOOTH_STENCIL;
-  return FSI_OK;
+  return guarded(ctx, [&] {
+    FSI_HIP(hipStreamSynchronize(ctx->c.stream));   // captured graphs may still be running
+    ctx->c.drop_graphs();
+    ctx->c.mgu.stencil = ctx->c.mgp.stencil = kind == FSI_SMOOTH_STENCIL;
+  });
 }
 
 int fsi_set_graphs(fsi_ctx *ctx, int enable) {
   if (!ctx) return FSI_E_ARG;
-  hipStreamSynchronize(ctx->c.stream);
-  ctx->c.drop_graphs();
-  ctx->c.use_graphs = enable != 0;
-  return FSI_OK;
+  return guarded(ctx, [&] {
+    FSI_HIP(hipStreamSynchronize(ctx->c.stream));   // captured graphs may still be running
+    ctx->c.drop_graphs();
+    ctx->c.use_graphs = enable != 0;
+  });
 }
 
 int fsi_footprint(const fsi_fluid_desc *fluid, int64_t n_nodes, int64_t n_tris, size_t *bytes) {

@@ -61,7 +61,7 @@ struct DevBuf {
   // grow-only reallocation (contents are not preserved)
   void reserve(size_t count) { if (count > n || p == nullptr) alloc(count); }
   void release() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     n = 0;
   }
@@ -108,11 +108,5 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
-// Host-side timer on a stream (wall time between two synchronised points).
-struct StreamTimer {
-  hipEvent_t a{}, b{};
-  StreamTimer() { hipEventCreate(&a); hipEventCreate(&b); }
-  ~StreamTimer() { hipEventDestroy(a); hipEventDestroy(b); }
-};
 
 }  // namespace fsi

@@ -506,15 +506,15 @@ static void capture_graph(Ctx &c, hipGraphExec_t &ge, Body body) {
   } catch (...) {
     c.stream = s;
     c.capturing = false;
-    hipStreamEndCapture(c.cap_stream, &g);
-    if (g) hipGraphDestroy(g);
+    (void)hipStreamEndCapture(c.cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
     throw;
   }
   c.stream = s;
   c.capturing = false;
   FSI_HIP(hipStreamEndCapture(c.cap_stream, &g));
   hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   FSI_HIP(e);
 }
 
@@ -544,14 +544,14 @@ void Ctx::drop_graphs() {
   for (auto &row : pc_graph)
     for (auto &g : row)
       if (g) {
-        hipGraphExecDestroy(g);
+        (void)hipGraphExecDestroy(g);
         g = nullptr;
       }
   for (auto &per_k : ms_graph)
     for (auto &row : per_k)
       for (auto &g : row)
         if (g) {
-          hipGraphExecDestroy(g);
+          (void)hipGraphExecDestroy(g);
           g = nullptr;
         }
 }
