@@ -156,7 +156,10 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     fsi::build_fluid(c);
     fsi::build_multigrid(c);
     c.mgu.stencil = c.mgp.stencil = true;
-    c.use_graphs = c.n <= 256;   // launch-bound sizes
+    // graphs keep the preconditioner on one stream and run up to 7 frozen MINRES steps past
+    // convergence: they pay off only where launch latency dominates (measured faster at
+    // 32^2, slower from 64^2 on)
+    c.use_graphs = c.n <= 32;
     fsi::make_shadow(c.Af, c.stream);
     fsi::make_shadow(c.B, c.stream);
     fsi::make_shadow(c.BT, c.stream);
