@@ -281,7 +281,7 @@ int fsi_set_smoother(fsi_ctx *ctx, int kind);
 /* Replay the A11 preconditioner (V-cycles, Chebyshev mass solve, pressure V-cycle: about
  * 60 launches) as one captured HIP graph per precision.  Default: on for n <= 32, where
  * a step is bound by launch latency (a graph keeps the pressure part on the context's
- * stream, and the convergence check of the inner solve every 8 steps runs frozen steps
+ * stream, and the convergence check of the inner solve every 2 steps runs frozen steps
  * past convergence, so larger grids run faster without).  The graph holds kernel nodes
  * only; results are the same as without it. */
 int fsi_set_graphs(fsi_ctx *ctx, int enable);

@@ -784,7 +784,10 @@ static void minres_a11(Ctx &c, const double *const *b, double *const *xout, int 
   hipLaunchKernelGGL(k_ms_init, dim3(1, K), dim3(1), 0, s, st, tol);
   FSI_CHECK_LAUNCH();
   const bool graphs = c.use_graphs && !(c.prof64.on || c.prof32.on);
-  const int check_every = graphs ? 8 : 1;
+  // with graphs the state is read back every second step (a replay costs far more than the
+  // read-back; checking every 8 steps measured 5-12% slower at 64^2 and 128^2 from the
+  // frozen steps run past convergence)
+  const int check_every = graphs ? 2 : 1;
   const int pk = std::is_same<TA, double>::value ? 0 : 1;
   int it = 0;
   double *h = c.hpin;
