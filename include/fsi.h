@@ -295,9 +295,11 @@ int fsi_set_graphs(fsi_ctx *ctx, int enable);
  * events on the context's stream; fsi_profile(ctx, 0) stops.  fsi_profile_read
  * synchronises and returns, for precision prec, the number of timed launches, their summed
  * duration in milliseconds and the algorithmic bytes one launch must move, with w = 8
- * (FP64) or 4 (FP32) bytes: structured form 8 w N2 (x and b read, d and y written, two
- * components each: the first step has c1 = 0 and reads no d), in FP32 with three steps
- * (6 w + 16) N2 (y is stored straight into the FP64 preconditioner output); CSR form
+ * (FP64) or 4 (FP32) bytes: structured form 6 w N2 for the default degrees 2 and 3 (x and
+ * b read, y written, two components each: the first step has c1 = 0 and reads no d, and
+ * the last direction is not stored when no single step follows; 8 w N2 when one does),
+ * in FP32 with three steps (4 w + 16) N2 (y is stored straight into the FP64
+ * preconditioner output); CSR form
  * nnz (4 w + 4) + N2 (4 + 14 w) + 4 (values and column indices once; per node the row
  * pointer, x, b, d read and written, the inverse 2x2 diagonal block and y). */
 int fsi_profile(fsi_ctx *ctx, int enable);

@@ -576,11 +576,14 @@ int fsi_profile_read(fsi_ctx *ctx, int prec, int64_t *launches, double *total_ms
     const fsi::MgLevel &L = c.mgu.lv[0];
     if (launches) *launches = cnt;
     if (total_ms) *total_ms = t;
-    // FP32 form with three post-smoothing steps: the launch stores y into the FP64 output
-    const double wy = (prec == FSI_FP32 && c.mgu.degree32 == 3) ? 8.0 : w;
+    // FP32 form with three post-smoothing steps: the launch stores y into the FP64 output;
+    // the direction is stored only for the single steps after the fused launch
+    const int degree = prec == FSI_FP64 ? c.mgu.degree : c.mgu.degree32;
+    const double wy = (prec == FSI_FP32 && degree == 3) ? 8.0 : w;
+    const double wd = degree > 3 ? w : 0.0;
     if (bytes_per_launch)
       *bytes_per_launch = c.mgu.stencil
-                              ? (double)L.nodes * 2 * (3 * w + wy)
+                              ? (double)L.nodes * 2 * (2 * w + wd + wy)
                               : (double)L.A.nnz * (4 * w + 4) + (double)L.nodes * (4 + 14 * w) + 4.0;
   });
 }

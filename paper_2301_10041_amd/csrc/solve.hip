@@ -248,19 +248,21 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
   };
   const LP<const T> lb(b, ls);
   const LP<T> ld(d, ls);
+  // the fused launches store their last direction only for the single steps that follow
+  const LP<T> ld3 = steps > 3 ? ld : LP<T>();
   int done = 0;
   if (zero_init && steps >= 3) {
     T c1a, c2a, c1b, c2b;
     next(c1a, c2a);
     next(c1b, c2b);
-    cheb2_pre<T>(n, tab, lb, ld, LP<T>(x, ls), (T)(1.0 / theta), c1a, c2a, c1b, c2b, s, K);
+    cheb2_pre<T>(n, tab, lb, ld3, LP<T>(x, ls), (T)(1.0 / theta), c1a, c2a, c1b, c2b, s, K);
     done = 3;
   } else if (!zero_init && steps == 3 && out64) {
     T c1b, c2b, c1c, c2c;
     next(c1b, c2b);
     next(c1c, c2c);
     if (prof) prof->begin(s);
-    cheb3_post<T, double>(n, tab, LP<const T>(x, ls), lb, ld, LP<double>(out64, ls), (T)(1.0 / theta), c1b, c2b,
+    cheb3_post<T, double>(n, tab, LP<const T>(x, ls), lb, LP<T>(), LP<double>(out64, ls), (T)(1.0 / theta), c1b, c2b,
                           c1c, c2c, s, K);
     if (prof) prof->end(s);
     return nullptr;
@@ -270,7 +272,7 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
     next(c1c, c2c);
     T *dst = (out && steps == 3) ? out : x2;
     if (prof) prof->begin(s);
-    cheb3_post<T>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(dst, ls), (T)(1.0 / theta), c1b, c2b, c1c, c2c, s, K);
+    cheb3_post<T>(n, tab, LP<const T>(x, ls), lb, ld3, LP<T>(dst, ls), (T)(1.0 / theta), c1b, c2b, c1c, c2c, s, K);
     if (prof) prof->end(s);
     x2 = x;
     x = dst;
@@ -280,7 +282,8 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
     next(c1b, c2b);
     T *dst = (out && steps == 2) ? out : x2;
     if (prof) prof->begin(s);
-    cheb2_post<T>(n, tab, LP<const T>(x, ls), lb, ld, LP<T>(dst, ls), (T)(1.0 / theta), c1b, c2b, s, K);
+    cheb2_post<T>(n, tab, LP<const T>(x, ls), lb, steps > 2 ? ld : LP<T>(), LP<T>(dst, ls), (T)(1.0 / theta), c1b,
+                  c2b, s, K);
     if (prof) prof->end(s);
     x2 = x;
     x = dst;

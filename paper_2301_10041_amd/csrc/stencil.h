@@ -110,6 +110,7 @@ void stencil_fluid_rows(int n, const StencilTable<T> *tab, const DivTable<T> *dv
 // Two Chebyshev steps per launch on the A_f stencil (temporal blocking):
 // cheb2_pre : x = d = s D^{-1} b, then two steps (c1a, c2a), (c1b, c2b); writes x, d
 // cheb2_post: from x, a step with c1 = 0 (c2a) and a step (c1b, c2b); writes y, d
+// (all three: a null d skips the store of the last direction when no later step reads it)
 template <typename T>
 void cheb2_pre(int n, const StencilTable<T> *tab, LP<const T> b, LP<T> d, LP<T> x, T s, T c1a, T c2a, T c1b,
                T c2b, hipStream_t st, int K = 1);

@@ -689,8 +689,10 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb2(Cheb2Args<T> a0, int tiles
           x20 = x10 + d20;
           x21 = x11 + d21;
         }
-        a.d[r] = d20;
-        a.d[N + r] = d21;
+        if (a.d) {   // null when no later step reads the direction
+          a.d[r] = d20;
+          a.d[N + r] = d21;
+        }
         a.y[r] = x20;
         a.y[N + r] = x21;
       }
@@ -925,8 +927,10 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int t
           y0 = x20 + e0;
           y1 = x21 + e1;
         }
-        a.d[r] = e0;
-        a.d[N + r] = e1;
+        if (a.d) {   // null when no later step reads the direction
+          a.d[r] = e0;
+          a.d[N + r] = e1;
+        }
         a.y[r] = (TY)y0;
         a.y[N + r] = (TY)y1;
       }
