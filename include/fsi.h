@@ -299,7 +299,8 @@ int fsi_set_graphs(fsi_ctx *ctx, int enable);
  * b read, y written, two components each: the first step has c1 = 0 and reads no d, and
  * the last direction is not stored when no single step follows; 8 w N2 when one does),
  * in FP32 with three steps (4 w + 16) N2 (y is stored straight into the FP64
- * preconditioner output); CSR form
+ * preconditioner output); with three or more steps the launch also reads the coarse
+ * correction, 2 w N2c (N2c = (n + 1)^2 nodes of the next level); CSR form
  * nnz (4 w + 4) + N2 (4 + 14 w) + 4 (values and column indices once; per node the row
  * pointer, x, b, d read and written, the inverse 2x2 diagonal block and y). */
 int fsi_profile(fsi_ctx *ctx, int enable);

@@ -577,13 +577,15 @@ int fsi_profile_read(fsi_ctx *ctx, int prec, int64_t *launches, double *total_ms
     if (launches) *launches = cnt;
     if (total_ms) *total_ms = t;
     // FP32 form with three post-smoothing steps: the launch stores y into the FP64 output;
-    // the direction is stored only for the single steps after the fused launch
+    // the direction is stored only for the single steps after the fused launch, which with
+    // three or more steps also reads the coarse correction (two components, next level)
     const int degree = prec == FSI_FP64 ? c.mgu.degree : c.mgu.degree32;
     const double wy = (prec == FSI_FP32 && degree == 3) ? 8.0 : w;
     const double wd = degree > 3 ? w : 0.0;
+    const double coarse = (degree >= 3 && c.mgu.lv.size() > 1) ? (double)c.mgu.lv[1].nodes * 2 * w : 0.0;
     if (bytes_per_launch)
       *bytes_per_launch = c.mgu.stencil
-                              ? (double)L.nodes * 2 * (2 * w + wd + wy)
+                              ? (double)L.nodes * 2 * (2 * w + wd + wy) + coarse
                               : (double)L.A.nnz * (4 * w + 4) + (double)L.nodes * (4 + 14 * w) + 4.0;
   });
 }

@@ -233,10 +233,15 @@ static T *chebyshev_mf(First first, Step step, double lmin, double lmax, int ste
 // ping-pong buffer (returned); used to write a V-cycle's result into the caller's vector.
 // out64 (optional, FP32 arithmetic, three steps from x): the result goes to that FP64 vector
 // and the function returns nullptr.
+// xc (optional, at least three steps from x): the steps start from x + P xc, the coarse
+// correction of lattice n / 2 (lane stride lc) added by the fused launch.
 template <typename T>
 static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, double lmax, int steps,
                             const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s, Prof *prof,
-                            int K = 1, int64_t ls = 0, T *out = nullptr, double *out64 = nullptr) {
+                            int K = 1, int64_t ls = 0, T *out = nullptr, double *out64 = nullptr,
+                            const T *xc = nullptr, int64_t lc = 0) {
+  FSI_REQUIRE(!xc || (!zero_init && steps >= 3), FSI_E_STATE, "the coarse correction rides on the fused steps");
+  const LP<const T> lxc(xc, lc);
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
@@ -263,7 +268,7 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
     next(c1c, c2c);
     if (prof) prof->begin(s);
     cheb3_post<T, double>(n, tab, LP<const T>(x, ls), lb, LP<T>(), LP<double>(out64, ls), (T)(1.0 / theta), c1b, c2b,
-                          c1c, c2c, s, K);
+                          c1c, c2c, s, K, lxc);
     if (prof) prof->end(s);
     return nullptr;
   } else if (!zero_init && steps >= 3) {
@@ -272,7 +277,8 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
     next(c1c, c2c);
     T *dst = (out && steps == 3) ? out : x2;
     if (prof) prof->begin(s);
-    cheb3_post<T>(n, tab, LP<const T>(x, ls), lb, ld3, LP<T>(dst, ls), (T)(1.0 / theta), c1b, c2b, c1c, c2c, s, K);
+    cheb3_post<T>(n, tab, LP<const T>(x, ls), lb, ld3, LP<T>(dst, ls), (T)(1.0 / theta), c1b, c2b, c1c, c2c, s, K,
+                  lxc);
     if (prof) prof->end(s);
     x2 = x;
     x = dst;
@@ -368,14 +374,17 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
   T *bc = Pr<T>::w(C, 1);
   const int64_t lc = (int64_t)mg.comps * C.nodes;
   if (mg.stencil) {   // matrix-free smoothing, residual and transfers
-    auto smooth = [&](T *x0, T *x1, bool zero) -> T * {
+    // velocity levels with three or more post-smoothing steps: the fused launch adds the
+    // coarse correction while it stages x (no separate prolongation pass)
+    const bool fuse = W == 4 && degree >= 3;
+    auto smooth = [&](T *x0, T *x1, bool zero, const T *xcor) -> T * {
       if constexpr (W == 4)
         return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, pl, K, ls,
-                                    zero ? nullptr : out, zero ? nullptr : out64);
+                                    zero ? nullptr : out, zero ? nullptr : out64, xcor, lc);
       else
-        return chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, K, ls);
+        return (void)xcor, chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, K, ls);
     };
-    T *xs = smooth(x, x2, true);
+    T *xs = smooth(x, x2, true, nullptr);
     T *xo = (xs == x) ? x2 : x;
     if constexpr (W == 4) {
       stencil_launch<T, SP_RESID>(L.n, stab<T>(L), LP<const T>(xs, ls), LP<const T>(b, ls), LP<T>(), LP<T>(r, ls),
@@ -387,11 +396,12 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
       p1_restrict<T>(L.n, LP<const T>(r, ls), LP<T>(bc, lc), s, K);
     }
     T *xc = vcycle<T, W, NC>(mg, l + 1, bc, s, nullptr, K);
-    if constexpr (W == 4)
-      p2_prolong_add<T>(L.n, LP<const T>(xc, lc), LP<T>(xs, ls), s, K);
-    else
+    if constexpr (W == 4) {
+      if (!fuse) p2_prolong_add<T>(L.n, LP<const T>(xc, lc), LP<T>(xs, ls), s, K);
+    } else {
       p1_prolong_add<T>(L.n, LP<const T>(xc, lc), LP<T>(xs, ls), s, K);
-    return smooth(xs, xo, false);
+    }
+    return smooth(xs, xo, false, fuse ? xc : nullptr);
   }
   T *xs = chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b, x,
                               x2, d, true, s, pl);

@@ -711,6 +711,10 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb2(Cheb2Args<T> a0, int tiles
 // tile row w + 4 of region 1 in every phase and, for w < 8, one halo row: the inner halo rows
 // 2, 3, R + 4, R + 5 (steps 1 and 2) go to waves 0-3, the outer halo rows 0, 1, R + 6, R + 7
 // (step 1 only) to waves 4-7.
+// With a coarse correction xc (the V-cycle's post-smoothing), the smoothing starts from
+// x + P xc: the coarse nodes under the staged region go to LDS first and every staged
+// interior node adds the coarse quadratic evaluated there (Sec. 4 multigrid transfer: the
+// P2 interpolation of the coarse lattice, the same sums as the separate prolongation).
 constexpr int kC3W = 120, kC3R = 8;
 static_assert(kC3W + 8 == 2 * kWave && kC3W + 12 == kC2W0, "region-1 lane layout and staged width");
 
@@ -723,10 +727,44 @@ struct Cheb3Args {   // y stored as TY (the mixed form writes FP32 results into 
   TY *y;
   int L2;
   T c2a, c1b, c2b, c1c, c2c;
-  int64_t lv;   // lane stride of x, b, d, y (lane = blockIdx.y)
+  int64_t lv;    // lane stride of x, b, d, y (lane = blockIdx.y)
+  const T *xc;   // coarse correction (lattice n / 2, two components) or null
+  int64_t lc;    // its lane stride
 };
 
-template <typename T, int RR, typename TY>
+// Coarse P2 interpolation at an interior fine node (I, J) of the cell (I >> 2, J >> 2) at
+// local position (A, B) = (I mod 4, J mod 4): the six P2 basis functions of the cell's
+// triangle (lower right when A >= B, upper left otherwise) at (A / 4, B / 4); basis values
+// are multiples of 1/8, exact in float.  XC holds the coarse nodes of the staged region
+// ([row][column][component], row stride CW, origin (Ic0, Jc0) in coarse coordinates; 0 at
+// Dirichlet nodes).  Sums in the order vertices 0, 1, 2, then edges 01, 12, 20.
+template <typename T, int CW>
+__device__ __forceinline__ void prolong_lds(const T *XC, int I, int J, int Ic0, int Jc0, T &s0, T &s1) {
+  const int A = I & 3, B = J & 3;
+  const int base = (2 * (J >> 2) - Jc0) * CW + 2 * (I >> 2) - Ic0;
+  const bool lo = A >= B;
+  const float xi = 0.25f * (float)A, eta = 0.25f * (float)B;
+  const float l0 = lo ? 1.0f - xi : 1.0f - eta, l1 = lo ? xi - eta : xi, l2 = lo ? eta : eta - xi;
+  const float phi[6] = {l0 * (2.0f * l0 - 1.0f), l1 * (2.0f * l1 - 1.0f), l2 * (2.0f * l2 - 1.0f),
+                        4.0f * l0 * l1,         4.0f * l1 * l2,         4.0f * l2 * l0};
+  const int off[6] = {0,
+                      lo ? 2 : 2 * CW + 2,
+                      lo ? 2 * CW + 2 : 2 * CW,
+                      lo ? 1 : CW + 1,
+                      lo ? CW + 2 : 2 * CW + 1,
+                      CW + (lo ? 1 : 0)};
+  s0 = 0;
+  s1 = 0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const T w = (T)phi[q];
+    const int o = 2 * (base + off[q]);
+    s0 = fma(w, XC[o], s0);
+    s1 = fma(w, XC[o + 1], s1);
+  }
+}
+
+template <typename T, int RR, typename TY, bool PROL>
 __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int tiles_x, int tiles, int band) {
   constexpr int NT = 64 * RR;
   constexpr int H0 = RR + 12, H1 = RR + 8;           // rows of the staged x and of region 1
@@ -742,6 +780,7 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int t
   lane_shift(a.b, a.lv);
   lane_shift(a.d, a.lv);
   lane_shift(a.y, a.lv);
+  lane_shift(a.xc, a.lc);
   const int n2 = 2 * a.n, L = n2 + 1;
   const int64_t N = a.L2;
   const int I0 = (t % tiles_x) * kC3W, J0 = (t / tiles_x) * RR;
@@ -768,6 +807,29 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int t
       }
     }
   }
+  // coarse nodes under the staged region: coarse columns I0 / 2 - 4 .. I0 / 2 + W0 / 2 + 2,
+  // rows J0 / 2 - 4 .. J0 / 2 + RR + 4 (the cells of fine columns I0 - 6 .. I0 + W0 - 7)
+  constexpr int CW = 2 * ((W0 - 7) / 4) + 7, CH = 2 * ((RR + 5) / 4) + 7;
+  static_assert(RR % 4 == 0 && kC3W % 4 == 0, "tile origins on coarse cell corners");
+  __shared__ T XC[PROL ? 2 * CH * CW : 1];
+  const int Ic0 = I0 / 2 - 4, Jc0 = J0 / 2 - 4;
+  constexpr int NC = CH * CW, ITC = PROL ? (NC + NT - 1) / NT : 0;
+  T cv[ITC > 0 ? ITC : 1][2];
+  if constexpr (PROL) {   // loads issued before those of x; stored once they are in flight
+    const int Lc = a.n + 1, nc2 = a.n;   // coarse lattice: 2 (n / 2) + 1 nodes a side
+    const int64_t Nc = (int64_t)Lc * Lc;
+#pragma unroll
+    for (int q = 0; q < ITC; ++q) {
+      const int e = tid + NT * q, Ic = Ic0 + e % CW, Jc = Jc0 + e / CW;
+      cv[q][0] = 0;
+      cv[q][1] = 0;
+      if (e < NC && Ic > 0 && Jc > 0 && Ic < nc2 && Jc < nc2) {
+        const int64_t k = (int64_t)Jc * Lc + Ic;
+        cv[q][0] = a.xc[k];
+        cv[q][1] = a.xc[Nc + k];
+      }
+    }
+  }
   // stage x with a halo of 6 (0 at Dirichlet nodes and outside the lattice)
   constexpr int NE = H0 * W0, IT = (NE + NT - 1) / NT;
   T v[IT][2];
@@ -783,10 +845,30 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int t
       v[q][1] = a.x[N + r];
     }
   }
+  if constexpr (PROL) {
+#pragma unroll
+    for (int q = 0; q < ITC; ++q) {
+      const int e = tid + NT * q;
+      if (e < NC) {
+        XC[2 * e] = cv[q][0];
+        XC[2 * e + 1] = cv[q][1];
+      }
+    }
+    __syncthreads();   // the coarse nodes are in XC
+  }
 #pragma unroll
   for (int q = 0; q < IT; ++q) {
     const int e = tid + NT * q, tr = e / W0, tc = e % W0;
     if (e < NE) {
+      if constexpr (PROL) {
+        const int I = I0 - 6 + tc, J = J0 - 6 + tr;
+        if (inside(I, J)) {
+          T s0, s1;
+          prolong_lds<T, CW>(XC, I, J, Ic0, Jc0, s0, s1);
+          v[q][0] += s0;
+          v[q][1] += s1;
+        }
+      }
       const int o = ((tc & 1) * H0 + tr) * HW0 + (tc >> 1);
       X0[o] = v[q][0];
       X0[2 * H0 * HW0 + o] = v[q][1];
@@ -940,25 +1022,32 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int t
 
 template <typename T, typename TY>
 void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<TY> y, T c2a, T c1b,
-                T c2b, T c1c, T c2c, hipStream_t st, int K) {
+                T c2b, T c1c, T c2c, hipStream_t st, int K, LP<const T> xc) {
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
   FSI_REQUIRE(K >= 1 && K <= 65535, FSI_E_ARG, "lane count out of range");
+  FSI_REQUIRE(!xc.p || (n % 2 == 0 && n >= 4), FSI_E_ARG, "a coarse correction needs an even fluid grid");
+  FSI_REQUIRE(!xc.p || K == 1 || xc.s > 0, FSI_E_ARG, "lane views of the coarse correction need a stride");
   const int L = 2 * n + 1;
   const int tx = (L + kC3W - 1) / kC3W, ty = (L + kC3R - 1) / kC3R;
   const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
   const int64_t lv = common_stride({{x.p, x.s}, {b.p, b.s}, {d.p, d.s}, {y.p, y.s}}, K);
-  Cheb3Args<T, TY> a{n, tab, x.p, b.p, d.p, y.p, L * L, c2a, c1b, c2b, c1c, c2c, lv};
-  hipLaunchKernelGGL((k_cheb3<T, kC3R, TY>), dim3((unsigned)(band * kXcd), (unsigned)K), dim3(64 * kC3R), 0, st,
-                     a, tx, tiles, band);
+  Cheb3Args<T, TY> a{n, tab, x.p, b.p, d.p, y.p, L * L, c2a, c1b, c2b, c1c, c2c, lv, xc.p, xc.s};
+  const dim3 grid((unsigned)(band * kXcd), (unsigned)K), block(64 * kC3R);
+  if (xc.p)
+    hipLaunchKernelGGL((k_cheb3<T, kC3R, TY, true>), grid, block, 0, st, a, tx, tiles, band);
+  else
+    hipLaunchKernelGGL((k_cheb3<T, kC3R, TY, false>), grid, block, 0, st, a, tx, tiles, band);
   FSI_CHECK_LAUNCH();
 }
 template void cheb3_post<double, double>(int, const StencilTable<double> *, LP<const double>, LP<const double>,
                                          LP<double>, LP<double>, double, double, double, double, double, hipStream_t,
-                                         int);
+                                         int, LP<const double>);
 template void cheb3_post<float, float>(int, const StencilTable<float> *, LP<const float>, LP<const float>, LP<float>,
-                                       LP<float>, float, float, float, float, float, hipStream_t, int);
+                                       LP<float>, float, float, float, float, float, hipStream_t, int,
+                                       LP<const float>);
 template void cheb3_post<float, double>(int, const StencilTable<float> *, LP<const float>, LP<const float>,
-                                        LP<float>, LP<double>, float, float, float, float, float, hipStream_t, int);
+                                        LP<float>, LP<double>, float, float, float, float, float, hipStream_t, int,
+                                        LP<const float>);
 
 template <typename T>
 void cheb2_pre(int n, const StencilTable<T> *tab, LP<const T> b, LP<T> d, LP<T> x, T s, T c1a, T c2a, T c1b,
