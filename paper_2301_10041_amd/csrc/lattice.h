@@ -128,5 +128,9 @@ template <typename T>
 void p2_restrict(int nf, const P2RestrTable<T> *tab, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
 template <typename T>
 void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
+// bc = R (b - A_f x) in one launch (stencil.hip): the residual lives only in LDS
+template <typename T>
+void resid_restrict(int nf, const StencilTable<T> *tab, const P2RestrTable<T> *rtab, LP<const T> x,
+                    LP<const T> b, LP<T> bc, hipStream_t s, int K = 1);
 
 }  // namespace fsi

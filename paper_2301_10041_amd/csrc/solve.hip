@@ -386,10 +386,9 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
     };
     T *xs = smooth(x, x2, true, nullptr);
     T *xo = (xs == x) ? x2 : x;
-    if constexpr (W == 4) {
-      stencil_launch<T, SP_RESID>(L.n, stab<T>(L), LP<const T>(xs, ls), LP<const T>(b, ls), LP<T>(), LP<T>(r, ls),
-                                  (T)0, (T)0, s, K);
-      p2_restrict<T>(L.n, rtab<T>(mg), LP<const T>(r, ls), LP<T>(bc, lc), s, K);
+    if constexpr (W == 4) {   // the fine residual stays in LDS
+      (void)r;
+      resid_restrict<T>(L.n, stab<T>(L), rtab<T>(mg), LP<const T>(xs, ls), LP<const T>(b, ls), LP<T>(bc, lc), s, K);
     } else {
       p1_launch<T, SP_RESID>(L.n, p1tab<T>(L), LP<const T>(xs, ls), LP<const T>(b, ls), LP<T>(), LP<T>(r, ls),
                              (T)0, (T)0, s, K);

@@ -14,6 +14,7 @@
 
 #include "ctx.h"
 #include "kernels.h"
+#include "lattice.h"
 #include "stencil.h"
 
 namespace fsi {
@@ -1087,6 +1088,183 @@ void cheb2_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b,
 FSI_CHEB2_INST(double)
 FSI_CHEB2_INST(float)
 #undef FSI_CHEB2_INST
+
+// ---------------------------------------------------------------- residual and restriction
+// bc = R (b - A_f x) = P^T r for the multigrid descent (Sec. 4): the residual of the fine
+// nodes under a coarse tile is computed from x staged in LDS and kept in LDS for the
+// restriction sums, so r never goes to HBM (reads x and b, writes bc).  A block of 8 waves
+// owns kRRr coarse rows x kRRc coarse columns; a coarse node (Ic, Jc) gathers the interior
+// fine nodes within 3 of (2 Ic, 2 Jc), so the residual covers 2 kRRr + 5 fine rows and
+// 2 kRRc + 5 columns (region origin (2 Ic0 - 4, 2 Jc0 - 4), lanes on columns 2 lane + par as
+// in the smoothing kernels) and x is staged with 2 more on every side.  Restriction sums in
+// the order of the restriction table; residual products in the order of the stencil table.
+constexpr int kRRr = 8, kRRc = 60;
+static_assert(2 * kRRc + 8 == 2 * kWave, "residual region fits the lane layout");
+
+template <typename T>
+struct ResidRestrArgs {
+  int n;
+  const StencilTable<T> *tab;
+  const P2RestrTable<T> *rt;
+  const T *x, *b;
+  T *bc;
+  int64_t lv, lc;   // lane strides of the fine (x, b) and coarse (bc) vectors
+};
+
+template <typename T>
+__global__ void __launch_bounds__(512, 4) k_resid_restrict(ResidRestrArgs<T> a0, int tiles_x, int tiles, int band) {
+  constexpr int NT = 512;
+  constexpr int H1 = 2 * kRRr + 8;                   // residual region rows (1 .. H1 - 3 used)
+  constexpr int H0 = H1 + 2, W0 = kC2W0, HW0 = W0 / 2;
+  constexpr int RW = 2 * kWave;                      // residual region columns
+  static_assert(kRRr == 8, "one coarse row per wave");
+  __shared__ T X0[2 * 2 * H0 * HW0];                 // x: [component][parity][row][column / 2]
+  T *const R = X0;                                   // then r: [component][row][column]
+  static_assert(2 * H1 * RW <= 2 * 2 * H0 * HW0, "the residual fits over the staged x");
+  const int t = (blockIdx.x % kXcd) * band + blockIdx.x / kXcd;
+  if (t >= tiles) return;
+  ResidRestrArgs<T> a = a0;
+  lane_shift(a.x, a.lv);
+  lane_shift(a.b, a.lv);
+  lane_shift(a.bc, a.lc);
+  const int n2 = 2 * a.n, L = n2 + 1, Lc = a.n + 1;
+  const int64_t N = (int64_t)L * L, Nc = (int64_t)Lc * Lc;
+  const int Ic0 = (t % tiles_x) * kRRc, Jc0 = (t / tiles_x) * kRRr;
+  const int IR = 2 * Ic0 - 4, JR = 2 * Jc0 - 4;      // residual region origin (even)
+  const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+  const StencilTable<T> &tb = *a.tab;
+  auto inside = [&](int I, int J) { return I > 0 && J > 0 && I < n2 && J < n2; };
+  // residual rows 1 + w, 9 + w, 17 + w (the third for waves 0-4): one parity per wave
+  const bool three = w < 5;
+  const int rows[3] = {1 + w, 9 + w, 17 + w};
+  auto needed = [&](int i, int I, int J) { return i >= 1 && i < RW - 2 && inside(I, J); };
+  T bv[3][2][2];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int J = JR + rows[q];
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const int i = 2 * lane + par, I = IR + i;
+      bv[q][par][0] = 0;
+      bv[q][par][1] = 0;
+      if ((q < 2 || three) && needed(i, I, J)) {
+        const int64_t r = (int64_t)J * L + I;
+        bv[q][par][0] = a.b[r];
+        bv[q][par][1] = a.b[N + r];
+      }
+    }
+  }
+  // stage x with a halo of 2 around the residual region (0 at Dirichlet nodes and outside)
+  constexpr int NE = H0 * W0, IT = (NE + NT - 1) / NT;
+  T v[IT][2];
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int e = tid + NT * q, tr = e / W0, tc = e % W0;
+    const int I = IR - 2 + tc, J = JR - 2 + tr;
+    v[q][0] = 0;
+    v[q][1] = 0;
+    if (e < NE && inside(I, J)) {
+      const int64_t r = (int64_t)J * L + I;
+      v[q][0] = a.x[r];
+      v[q][1] = a.x[N + r];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int e = tid + NT * q, tr = e / W0, tc = e % W0;
+    if (e < NE) {
+      const int o = ((tc & 1) * H0 + tr) * HW0 + (tc >> 1);
+      X0[o] = v[q][0];
+      X0[2 * H0 * HW0 + o] = v[q][1];
+    }
+  }
+  __syncthreads();
+  const int jodd = __builtin_amdgcn_readfirstlane((JR + rows[0]) & 1);
+  // rows 0-1 of the wave together (one pass over the coefficients), then row 2
+  auto resid = [&](auto q0_tag, auto nr_tag) {   // r over b (0 where not needed: b was not read)
+    constexpr int Q0 = decltype(q0_tag)::value, NR = decltype(nr_tag)::value;
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const int i = 2 * lane + par, I = IR + i;
+      int xr[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) xr[k] = rows[Q0 + k] + 2;
+      T sp[NR][2];
+      if (par) class_products<T, 1, H0, HW0, NR>(tb, jodd, X0, xr, lane + 1, sp);
+      else class_products<T, 0, H0, HW0, NR>(tb, jodd, X0, xr, lane + 1, sp);
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+        if (needed(i, I, JR + rows[Q0 + k])) {
+          bv[Q0 + k][par][0] -= sp[k][0];
+          bv[Q0 + k][par][1] -= sp[k][1];
+        }
+    }
+  };
+  resid(std::integral_constant<int, 0>{}, std::integral_constant<int, 2>{});
+  if (three) resid(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
+  __syncthreads();   // every wave has read x: r goes over it
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (q == 2 && !three) continue;
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const int o = rows[q] * RW + 2 * lane + par;
+      R[o] = bv[q][par][0];
+      R[H1 * RW + o] = bv[q][par][1];
+    }
+  }
+  __syncthreads();
+  // restriction: wave w owns coarse row Jc0 + w; lanes 0-29 the even columns, 32-61 the odd
+  const int Jc = Jc0 + w, hi = lane >> 5, Ic = Ic0 + 2 * (lane & 31) + hi;
+  if ((lane & 31) >= kRRc / 2 || Ic >= Lc || Jc >= Lc) return;
+  T s0 = 0, s1 = 0;
+  if (!(Ic == 0 || Jc == 0 || Ic == a.n || Jc == a.n)) {
+    const P2RestrTable<T> &rt = *a.rt;
+    constexpr RestrOffsets ro = restrict_offsets();
+    const int c0 = (2 * w + 4) * RW + 2 * (Ic - Ic0) + 4;   // the coarse node's fine position
+    auto gather = [&](auto cls_tag) {
+      constexpr int CLS = decltype(cls_tag)::value;
+#pragma unroll
+      for (int k = 0; k < kRestrCount[CLS]; ++k) {
+        const int o = c0 + ro.d[CLS][k][1] * RW + ro.d[CLS][k][0];
+        const T wk = rt.w[CLS][k];
+        s0 = fma(wk, R[o], s0);
+        s1 = fma(wk, R[H1 * RW + o], s1);
+      }
+    };
+    if (Jc & 1) {
+      if (hi) gather(std::integral_constant<int, 3>{});
+      else gather(std::integral_constant<int, 2>{});
+    } else {
+      if (hi) gather(std::integral_constant<int, 1>{});
+      else gather(std::integral_constant<int, 0>{});
+    }
+  }
+  const int64_t q = (int64_t)Jc * Lc + Ic;
+  a.bc[q] = s0;
+  a.bc[Nc + q] = s1;
+}
+
+template <typename T>
+void resid_restrict(int nf, const StencilTable<T> *tab, const P2RestrTable<T> *rtab, LP<const T> x, LP<const T> b,
+                    LP<T> bc, hipStream_t s, int K) {
+  FSI_REQUIRE((int64_t)(2 * nf + 1) * (2 * nf + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
+  FSI_REQUIRE(K >= 1 && K <= 65535, FSI_E_ARG, "lane count out of range");
+  FSI_REQUIRE(nf % 2 == 0 && nf >= 4, FSI_E_ARG, "restriction needs an even fluid grid");
+  FSI_REQUIRE(K == 1 || bc.s > 0, FSI_E_ARG, "lane views of the coarse vector need a stride");
+  const int Lc = nf + 1;
+  const int tx = (Lc + kRRc - 1) / kRRc, ty = (Lc + kRRr - 1) / kRRr;
+  const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
+  const int64_t lv = common_stride({{x.p, x.s}, {b.p, b.s}}, K);
+  ResidRestrArgs<T> a{nf, tab, rtab, x.p, b.p, bc.p, lv, bc.s};
+  hipLaunchKernelGGL(k_resid_restrict<T>, dim3((unsigned)(band * kXcd), (unsigned)K), dim3(512), 0, s, a, tx, tiles,
+                     band);
+  FSI_CHECK_LAUNCH();
+}
+template void resid_restrict<double>(int, const StencilTable<double> *, const P2RestrTable<double> *,
+                                     LP<const double>, LP<const double>, LP<double>, hipStream_t, int);
+template void resid_restrict<float>(int, const StencilTable<float> *, const P2RestrTable<float> *, LP<const float>,
+                                    LP<const float>, LP<float>, hipStream_t, int);
 
 #define FSI_STENCIL_INST(T, M)                                                                              \
   template void stencil_launch<T, M>(int, const StencilTable<T> *, LP<const T>, LP<const T>, LP<T>, LP<T>, T, T, \
