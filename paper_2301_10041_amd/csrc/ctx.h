@@ -38,6 +38,7 @@ struct MgLevel {
 struct Mg {
   int comps = 1;           // unknowns per node: 2 (velocity, 2x2 blocks) or 1 (pressure)
   bool stencil = false;    // smoothing, residuals and transfers matrix-free (structured grid)
+  bool tail = true;        // velocity levels of n <= 16 in one launch (with the stencil form)
   int degree = 3;          // Chebyshev smoothing steps before and after the coarse correction
   int degree32 = 3;        // the same for the FP32 V-cycle of the mixed-precision form
   std::vector<MgLevel> lv; // lv[0] finest

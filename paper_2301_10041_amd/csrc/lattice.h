@@ -128,6 +128,33 @@ template <typename T>
 void p2_restrict(int nf, const P2RestrTable<T> *tab, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
 template <typename T>
 void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
+// The coarse end of a velocity V-cycle in one launch per system (mgtail.hip): levels
+// lv[0..nlev) (n <= kTailMaxN cells, each the next one's fine level) and the coarsest
+// level's dense inverse.  Vectors in LDS (offsets in T): level l's b at lv[l].off and x
+// right after it (2 N each, N = (2n + 1)^2), one shared direction at offd (2 N of lv[0]),
+// the coarsest b at offc and x after it (m each); lds = the total.  b and x in device
+// memory: the first level's right-hand side and result (lane stride lb).
+constexpr int kTailMax = 4, kTailDeg = 8, kTailMaxN = 16, kTailLdsMax = 65536;
+template <typename T>
+struct TailLevel {
+  int n, off;
+  const StencilTable<T> *tab;
+  T s;                                     // 1 / theta: the first step of both smoothings
+  T c1[kTailDeg - 1], c2[kTailDeg - 1];    // the later Chebyshev steps
+};
+template <typename T>
+struct TailArgs {
+  int nlev, degree;
+  TailLevel<T> lv[kTailMax];
+  int offd, offc, m, lds;
+  const P2RestrTable<T> *rt;
+  const T *cinv;
+  const T *b;
+  T *x;
+  int64_t lb;
+};
+template <typename T>
+void mg_tail(const TailArgs<T> &a, hipStream_t s, int K = 1);
 // bc = R (b - A_f x) in one launch (stencil.hip): the residual lives only in LDS
 template <typename T>
 void resid_restrict(int nf, const StencilTable<T> *tab, const P2RestrTable<T> *rtab, LP<const T> x,

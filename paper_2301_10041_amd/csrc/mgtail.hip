@@ -1,0 +1,272 @@
+// The coarse end of the velocity V-cycle in one launch per system (Sec. 4 multigrid).  On
+// levels of at most 16 x 16 cells every smoothing step, residual and transfer of the
+// separate launches costs the latency of a whole kernel while the level holds a few
+// thousand nodes; here one 1024-thread block keeps the right-hand side and iterate of every
+// remaining level in LDS and runs pre-smoothing, residual, restriction, the dense solve on
+// the coarsest level, prolongation and post-smoothing with block barriers in between.
+// The steps are those of the per-level launches: the same Chebyshev coefficients, the same
+// stencil tables and restriction weights, the coarse quadratic for the prolongation.
+//
+// Threads: four groups of 256, one per node class (vertex, horizontal edge, vertical edge,
+// diagonal: the parities of the lattice coordinates), so the stencil of a wave is uniform;
+// on a level of n <= 16 cells every class has at most 256 interior nodes, one per thread.
+// Dirichlet nodes hold 0 in every vector (a restricted right-hand side vanishes there and
+// the identity rows keep it so), so only interior nodes are stepped.
+#include "ctx.h"
+#include "kernels.h"
+#include "lattice.h"
+#include "stencil.h"
+
+namespace fsi {
+
+namespace {
+
+constexpr int kTailThreads = 1024, kTailGroup = kTailThreads / 4;
+
+// interior node of class c (I parity c & 1, J parity c >> 1) number i on a level of n cells
+__device__ __forceinline__ bool class_node(int c, int i, int n, int &I, int &J) {
+  const int pi = c & 1, pj = c >> 1;
+  const int ni = pi ? n : n - 1, nj = pj ? n : n - 1;
+  if (i >= ni * nj) return false;
+  I = (pi ? 1 : 2) + 2 * (i % ni);
+  J = (pj ? 1 : 2) + 2 * (i / ni);
+  return true;
+}
+
+// (A_f x) at node index idx of a lattice of side L (x component-major, N nodes)
+template <typename T, int CLS>
+__device__ __forceinline__ void tail_product(const StencilTable<T> &tb, const T *x, int N, int L, int idx, T &s0,
+                                             T &s1) {
+  constexpr StencilOffsets so = stencil_offsets();
+  constexpr CrossZero cz = cross_zero();
+  s0 = 0;
+  s1 = 0;
+#pragma unroll
+  for (int k = 0; k < kStencilCount[CLS]; ++k) {
+    const int o = idx + so.d[CLS][k][1] * L + so.d[CLS][k][0];
+    const T y0 = x[o], y1 = x[N + o];
+    const T c0 = tb.coef[CLS][k][0], c1 = tb.coef[CLS][k][1], c2 = tb.coef[CLS][k][2], c3 = tb.coef[CLS][k][3];
+    if (cz.z[CLS][k]) {
+      s0 = fma(c0, y0, s0);
+      s1 = fma(c3, y1, s1);
+    } else {
+      s0 = fma(c1, y1, fma(c0, y0, s0));
+      s1 = fma(c3, y1, fma(c2, y0, s1));
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void class_product(int c, const StencilTable<T> &tb, const T *x, int N, int L, int idx,
+                                              T &s0, T &s1) {
+  switch (c) {   // uniform over the wave
+    case 0: tail_product<T, 0>(tb, x, N, L, idx, s0, s1); break;
+    case 1: tail_product<T, 1>(tb, x, N, L, idx, s0, s1); break;
+    case 2: tail_product<T, 2>(tb, x, N, L, idx, s0, s1); break;
+    default: tail_product<T, 3>(tb, x, N, L, idx, s0, s1); break;
+  }
+}
+
+// restriction sum at coarse node (Ic, Jc) of class CLS from the fine residual r
+template <typename T, int CLS>
+__device__ __forceinline__ void tail_restrict(const P2RestrTable<T> &rt, const T *r, int N, int L, int Ic, int Jc,
+                                              T &s0, T &s1) {
+  constexpr RestrOffsets ro = restrict_offsets();
+  s0 = 0;
+  s1 = 0;
+  const int c = 2 * Jc * L + 2 * Ic;
+#pragma unroll
+  for (int k = 0; k < kRestrCount[CLS]; ++k) {
+    const int o = c + ro.d[CLS][k][1] * L + ro.d[CLS][k][0];
+    const T w = rt.w[CLS][k];
+    s0 = fma(w, r[o], s0);
+    s1 = fma(w, r[N + o], s1);
+  }
+}
+
+// coarse quadratic at fine node (I, J) (coarse lattice side Lc, Nc nodes): the six P2
+// basis values of the coarse cell's triangle at the local position, in the order vertices
+// 0, 1, 2, edges 01, 12, 20 (exact in float)
+template <typename T>
+__device__ __forceinline__ void tail_prolong(const T *xc, int Nc, int Lc, int I, int J, T &s0, T &s1) {
+  const int A = I & 3, B = J & 3;
+  const int base = 2 * (J >> 2) * Lc + 2 * (I >> 2);
+  const bool lo = A >= B;
+  const float xi = 0.25f * (float)A, eta = 0.25f * (float)B;
+  const float l0 = lo ? 1.0f - xi : 1.0f - eta, l1 = lo ? xi - eta : xi, l2 = lo ? eta : eta - xi;
+  const float phi[6] = {l0 * (2.0f * l0 - 1.0f), l1 * (2.0f * l1 - 1.0f), l2 * (2.0f * l2 - 1.0f),
+                        4.0f * l0 * l1,         4.0f * l1 * l2,         4.0f * l2 * l0};
+  const int off[6] = {0,
+                      lo ? 2 : 2 * Lc + 2,
+                      lo ? 2 * Lc + 2 : 2 * Lc,
+                      lo ? 1 : Lc + 1,
+                      lo ? Lc + 2 : 2 * Lc + 1,
+                      Lc + (lo ? 1 : 0)};
+  s0 = 0;
+  s1 = 0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const T w = (T)phi[q];
+    s0 = fma(w, xc[base + off[q]], s0);
+    s1 = fma(w, xc[Nc + base + off[q]], s1);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
+  extern __shared__ unsigned char tail_smem[];
+  T *sm = reinterpret_cast<T *>(tail_smem);
+  const int tid = threadIdx.x, grp = tid / kTailGroup, gi = tid % kTailGroup;
+  const T *bg = a.b + (int64_t)blockIdx.y * a.lb;
+  T *xg = a.x + (int64_t)blockIdx.y * a.lb;
+  for (int i = tid; i < a.lds; i += kTailThreads) sm[i] = T(0);
+  __syncthreads();
+  T *d = sm + a.offd;   // the direction (then residual) of the level being smoothed
+  {                     // right-hand side of the first level (interior nodes)
+    const TailLevel<T> &L0 = a.lv[0];
+    const int L = 2 * L0.n + 1, N = L * L;
+    T *b = sm + L0.off;
+    for (int c = 0; c < 4; ++c) {
+      int I, J;
+      if (grp == c && class_node(c, gi, L0.n, I, J)) {
+        const int k = J * L + I;
+        b[k] = bg[k];
+        b[N + k] = bg[N + k];
+      }
+    }
+  }
+  __syncthreads();
+  // one Chebyshev step on level l from x (first: c1 = 0, the direction is not read)
+  auto cheb_step = [&](const TailLevel<T> &lv, bool first, T c1, T c2) {
+    const int L = 2 * lv.n + 1, N = L * L;
+    T *b = sm + lv.off, *x = b + 2 * N;
+    const StencilTable<T> &tb = *lv.tab;
+    int I, J;
+    const bool mine = class_node(grp, gi, lv.n, I, J);
+    const int k = J * L + I;
+    T x0 = 0, x1 = 0, d0 = 0, d1 = 0;
+    if (mine) {
+      T s0, s1;
+      class_product<T>(grp, tb, x, N, L, k, s0, s1);
+      const T r0 = b[k] - s0, r1 = b[N + k] - s1;
+      const T *di = tb.dinv[grp];
+      const T z0 = di[0] * r0 + di[1] * r1, z1 = di[2] * r0 + di[3] * r1;
+      d0 = first ? c2 * z0 : c1 * d[k] + c2 * z0;
+      d1 = first ? c2 * z1 : c1 * d[N + k] + c2 * z1;
+      x0 = x[k] + d0;
+      x1 = x[N + k] + d1;
+    }
+    __syncthreads();
+    if (mine) {
+      x[k] = x0;
+      x[N + k] = x1;
+      d[k] = d0;
+      d[N + k] = d1;
+    }
+    __syncthreads();
+  };
+  // descent: pre-smoothing, residual, restriction
+  for (int l = 0; l < a.nlev; ++l) {
+    const TailLevel<T> &lv = a.lv[l];
+    const int L = 2 * lv.n + 1, N = L * L;
+    T *b = sm + lv.off, *x = b + 2 * N;
+    const StencilTable<T> &tb = *lv.tab;
+    {   // first step from zero: x = d = s D^{-1} b
+      int I, J;
+      if (class_node(grp, gi, lv.n, I, J)) {
+        const int k = J * L + I;
+        const T *di = tb.dinv[grp];
+        const T b0 = b[k], b1 = b[N + k];
+        const T z0 = lv.s * (di[0] * b0 + di[1] * b1), z1 = lv.s * (di[2] * b0 + di[3] * b1);
+        x[k] = d[k] = z0;
+        x[N + k] = d[N + k] = z1;
+      }
+    }
+    __syncthreads();
+    for (int j = 0; j + 1 < a.degree; ++j) cheb_step(lv, false, lv.c1[j], lv.c2[j]);
+    {   // residual over the direction (not read again before the post-smoothing)
+      int I, J;
+      if (class_node(grp, gi, lv.n, I, J)) {
+        const int k = J * L + I;
+        T s0, s1;
+        class_product<T>(grp, tb, x, N, L, k, s0, s1);
+        d[k] = b[k] - s0;
+        d[N + k] = b[N + k] - s1;
+      }
+    }
+    __syncthreads();
+    {   // restriction into the next level's right-hand side (interior coarse nodes)
+      const int nc = lv.n / 2, Lc = lv.n + 1, Nc = Lc * Lc;
+      T *bc = (l + 1 < a.nlev) ? sm + a.lv[l + 1].off : sm + a.offc;
+      int Ic, Jc;
+      if (class_node(grp, gi, nc, Ic, Jc)) {
+        const int k = Jc * Lc + Ic;
+        T s0, s1;
+        switch (grp) {
+          case 0: tail_restrict<T, 0>(*a.rt, d, N, L, Ic, Jc, s0, s1); break;
+          case 1: tail_restrict<T, 1>(*a.rt, d, N, L, Ic, Jc, s0, s1); break;
+          case 2: tail_restrict<T, 2>(*a.rt, d, N, L, Ic, Jc, s0, s1); break;
+          default: tail_restrict<T, 3>(*a.rt, d, N, L, Ic, Jc, s0, s1); break;
+        }
+        bc[k] = s0;
+        bc[Nc + k] = s1;
+      }
+    }
+    __syncthreads();
+  }
+  {   // coarsest level: x = C^{-1} b, one wave per row (sums in double, as the dense kernel)
+    const T *b = sm + a.offc;
+    T *x = sm + a.offc + a.m;
+    const int w = tid / kWave, lane = tid % kWave;
+    for (int r = w; r < a.m; r += kTailThreads / kWave) {
+      double s = 0.0;
+      for (int k = lane; k < a.m; k += kWave) s += (double)a.cinv[(int64_t)r * a.m + k] * (double)b[k];
+      s = wave_sum(s);
+      if (lane == 0) x[r] = (T)s;
+    }
+  }
+  __syncthreads();
+  // ascent: coarse correction, post-smoothing
+  for (int l = a.nlev - 1; l >= 0; --l) {
+    const TailLevel<T> &lv = a.lv[l];
+    const int L = 2 * lv.n + 1, N = L * L;
+    T *b = sm + lv.off, *x = b + 2 * N;
+    const int Lc = lv.n + 1, Nc = Lc * Lc;
+    const T *xc = (l + 1 < a.nlev) ? sm + a.lv[l + 1].off + 2 * Nc : sm + a.offc + a.m;
+    int I, J;
+    if (class_node(grp, gi, lv.n, I, J)) {
+      const int k = J * L + I;
+      T s0, s1;
+      tail_prolong<T>(xc, Nc, Lc, I, J, s0, s1);
+      x[k] += s0;
+      x[N + k] += s1;
+    }
+    __syncthreads();
+    cheb_step(lv, true, T(0), lv.s);
+    for (int j = 0; j + 1 < a.degree; ++j) cheb_step(lv, false, lv.c1[j], lv.c2[j]);
+    (void)b;
+  }
+  {   // result of the first level, Dirichlet nodes included (0)
+    const int L = 2 * a.lv[0].n + 1, N = L * L;
+    const T *x = sm + a.lv[0].off + 2 * N;
+    for (int i = tid; i < 2 * N; i += kTailThreads) xg[i] = x[i];
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void mg_tail(const TailArgs<T> &a, hipStream_t s, int K) {
+  FSI_REQUIRE(a.nlev >= 1 && a.nlev <= kTailMax && a.degree >= 1 && a.degree <= kTailDeg, FSI_E_ARG,
+              "coarse tail shape out of range");
+  FSI_REQUIRE(a.lv[0].n <= kTailMaxN, FSI_E_ARG, "coarse tail level too fine");
+  FSI_REQUIRE(K >= 1 && K <= 65535 && (K == 1 || a.lb > 0), FSI_E_ARG, "lane count out of range");
+  const int bytes = a.lds * (int)sizeof(T);
+  FSI_REQUIRE(bytes <= kTailLdsMax, FSI_E_ARG, "coarse tail exceeds the LDS of a block");
+  hipLaunchKernelGGL(k_mg_tail<T>, dim3(1, (unsigned)K), dim3(kTailThreads), bytes, s, a);
+  FSI_CHECK_LAUNCH();
+}
+template void mg_tail<double>(const TailArgs<double> &, hipStream_t, int);
+template void mg_tail<float>(const TailArgs<float> &, hipStream_t, int);
+
+}  // namespace fsi
