@@ -1097,6 +1097,7 @@ void build_multigrid(Ctx &c) {
   }
   coarse_inverse(c.mgu, s);
   coarse_inverse(c.mgp, s);
+  (void)tail_lds_limit();   // the LDS grant of the coarse-tail launch, outside any graph capture
   FSI_HIP(hipStreamSynchronize(s));
 }
 

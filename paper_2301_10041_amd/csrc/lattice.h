@@ -132,9 +132,16 @@ void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
 // lv[0..nlev) (n <= kTailMaxN cells, each the next one's fine level) and the coarsest
 // level's dense inverse.  Vectors in LDS (offsets in T): level l's b at lv[l].off and x
 // right after it (2 N each, N = (2n + 1)^2), one shared direction at offd (2 N of lv[0]),
-// the coarsest b at offc and x after it (m each); lds = the total.  b and x in device
-// memory: the first level's right-hand side and result (lane stride lb).
-constexpr int kTailMax = 4, kTailDeg = 8, kTailMaxN = 16, kTailLdsMax = 65536;
+// the coarsest b at offc and x after it (m each), then the stencil coefficients and
+// inverse diagonal blocks of every level (kTailTab each) and the restriction weights
+// (kTailRw) at offt; lds = the total.  b and x in device memory: the first level's
+// right-hand side and result (lane stride lb).
+constexpr int kTailMax = 4, kTailDeg = 8, kTailMaxN = 16, kTailDenseMax = 6 * 64;
+constexpr int kTailCoef[4] = {0, 76, 112, 148};   // class offsets of 4 coefficients per entry
+constexpr int kTailTab = 184 + 16, kTailRw = 25 + 9 + 9 + 9;
+constexpr int kTailRs[4] = {0, 25, 34, 43};       // class offsets of the restriction weights
+// Largest LDS block of the tail launch on the current device (queried once, at most 160 KiB).
+int tail_lds_limit();
 template <typename T>
 struct TailLevel {
   int n, off;
@@ -146,7 +153,7 @@ template <typename T>
 struct TailArgs {
   int nlev, degree;
   TailLevel<T> lv[kTailMax];
-  int offd, offc, m, lds;
+  int offd, offc, offt, m, lds;
   const P2RestrTable<T> *rt;
   const T *cinv;
   const T *b;

@@ -11,7 +11,10 @@
 // diagonal: the parities of the lattice coordinates), so the stencil of a wave is uniform;
 // on a level of n <= 16 cells every class has at most 256 interior nodes, one per thread.
 // Dirichlet nodes hold 0 in every vector (a restricted right-hand side vanishes there and
-// the identity rows keep it so), so only interior nodes are stepped.
+// the identity rows keep it so), so only interior nodes are stepped.  The stencil
+// coefficients, inverse diagonal blocks and restriction weights are copied to LDS first:
+// read from device memory at every step they cost a scalar-cache round trip per few
+// neighbours.
 #include "ctx.h"
 #include "kernels.h"
 #include "lattice.h"
@@ -33,10 +36,10 @@ __device__ __forceinline__ bool class_node(int c, int i, int n, int &I, int &J) 
   return true;
 }
 
-// (A_f x) at node index idx of a lattice of side L (x component-major, N nodes)
+// (A_f x) at node index idx of a lattice of side L (x component-major, N nodes); cf: the
+// level's coefficients in LDS (class CLS at kTailCoef[CLS], four per entry)
 template <typename T, int CLS>
-__device__ __forceinline__ void tail_product(const StencilTable<T> &tb, const T *x, int N, int L, int idx, T &s0,
-                                             T &s1) {
+__device__ __forceinline__ void tail_product(const T *cf, const T *x, int N, int L, int idx, T &s0, T &s1) {
   constexpr StencilOffsets so = stencil_offsets();
   constexpr CrossZero cz = cross_zero();
   s0 = 0;
@@ -45,7 +48,8 @@ __device__ __forceinline__ void tail_product(const StencilTable<T> &tb, const T 
   for (int k = 0; k < kStencilCount[CLS]; ++k) {
     const int o = idx + so.d[CLS][k][1] * L + so.d[CLS][k][0];
     const T y0 = x[o], y1 = x[N + o];
-    const T c0 = tb.coef[CLS][k][0], c1 = tb.coef[CLS][k][1], c2 = tb.coef[CLS][k][2], c3 = tb.coef[CLS][k][3];
+    const T *ck = cf + kTailCoef[CLS] + 4 * k;
+    const T c0 = ck[0], c1 = ck[1], c2 = ck[2], c3 = ck[3];
     if (cz.z[CLS][k]) {
       s0 = fma(c0, y0, s0);
       s1 = fma(c3, y1, s1);
@@ -57,20 +61,19 @@ __device__ __forceinline__ void tail_product(const StencilTable<T> &tb, const T 
 }
 
 template <typename T>
-__device__ __forceinline__ void class_product(int c, const StencilTable<T> &tb, const T *x, int N, int L, int idx,
-                                              T &s0, T &s1) {
+__device__ __forceinline__ void class_product(int c, const T *cf, const T *x, int N, int L, int idx, T &s0, T &s1) {
   switch (c) {   // uniform over the wave
-    case 0: tail_product<T, 0>(tb, x, N, L, idx, s0, s1); break;
-    case 1: tail_product<T, 1>(tb, x, N, L, idx, s0, s1); break;
-    case 2: tail_product<T, 2>(tb, x, N, L, idx, s0, s1); break;
-    default: tail_product<T, 3>(tb, x, N, L, idx, s0, s1); break;
+    case 0: tail_product<T, 0>(cf, x, N, L, idx, s0, s1); break;
+    case 1: tail_product<T, 1>(cf, x, N, L, idx, s0, s1); break;
+    case 2: tail_product<T, 2>(cf, x, N, L, idx, s0, s1); break;
+    default: tail_product<T, 3>(cf, x, N, L, idx, s0, s1); break;
   }
 }
 
-// restriction sum at coarse node (Ic, Jc) of class CLS from the fine residual r
+// restriction sum at coarse node (Ic, Jc) of class CLS from the fine residual r (weights
+// rw in LDS, class CLS at kTailRs[CLS])
 template <typename T, int CLS>
-__device__ __forceinline__ void tail_restrict(const P2RestrTable<T> &rt, const T *r, int N, int L, int Ic, int Jc,
-                                              T &s0, T &s1) {
+__device__ __forceinline__ void tail_restrict(const T *rw, const T *r, int N, int L, int Ic, int Jc, T &s0, T &s1) {
   constexpr RestrOffsets ro = restrict_offsets();
   s0 = 0;
   s1 = 0;
@@ -78,7 +81,7 @@ __device__ __forceinline__ void tail_restrict(const P2RestrTable<T> &rt, const T
 #pragma unroll
   for (int k = 0; k < kRestrCount[CLS]; ++k) {
     const int o = c + ro.d[CLS][k][1] * L + ro.d[CLS][k][0];
-    const T w = rt.w[CLS][k];
+    const T w = rw[kTailRs[CLS] + k];
     s0 = fma(w, r[o], s0);
     s1 = fma(w, r[N + o], s1);
   }
@@ -116,11 +119,33 @@ template <typename T>
 __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
   extern __shared__ unsigned char tail_smem[];
   T *sm = reinterpret_cast<T *>(tail_smem);
-  const int tid = threadIdx.x, grp = tid / kTailGroup, gi = tid % kTailGroup;
+  // the class group is uniform over a wave: scalar branches and scalar table loads
+  const int tid = threadIdx.x, grp = __builtin_amdgcn_readfirstlane(tid / kTailGroup), gi = tid % kTailGroup;
   const T *bg = a.b + (int64_t)blockIdx.y * a.lb;
   T *xg = a.x + (int64_t)blockIdx.y * a.lb;
-  for (int i = tid; i < a.lds; i += kTailThreads) sm[i] = T(0);
+  for (int i = tid; i < a.offt; i += kTailThreads) sm[i] = T(0);
+  for (int l = 0; l < a.nlev; ++l)   // coefficients (class-compact) and inverse diagonal blocks
+    for (int i = tid; i < kTailTab; i += kTailThreads) {
+      const StencilTable<T> &tb = *a.lv[l].tab;
+      T v;
+      if (i >= kTailCoef[3] + 4 * kStencilCount[3]) {
+        const int j = i - (kTailCoef[3] + 4 * kStencilCount[3]);
+        v = tb.dinv[j / 4][j % 4];
+      } else {
+        const int c = i < kTailCoef[1] ? 0 : i < kTailCoef[2] ? 1 : i < kTailCoef[3] ? 2 : 3;
+        const int j = i - kTailCoef[c];
+        v = tb.coef[c][j / 4][j % 4];
+      }
+      sm[a.offt + l * kTailTab + i] = v;
+    }
+  for (int i = tid; i < kTailRw; i += kTailThreads) {
+    const int c = i < kTailRs[1] ? 0 : i < kTailRs[2] ? 1 : i < kTailRs[3] ? 2 : 3;
+    sm[a.offt + a.nlev * kTailTab + i] = a.rt->w[c][i - kTailRs[c]];
+  }
   __syncthreads();
+  const T *rw = sm + a.offt + a.nlev * kTailTab;
+  auto coefs = [&](int l) { return (const T *)(sm + a.offt + l * kTailTab); };
+  auto dinv = [&](int l) { return (const T *)(sm + a.offt + l * kTailTab + kTailCoef[3] + 4 * kStencilCount[3]); };
   T *d = sm + a.offd;   // the direction (then residual) of the level being smoothed
   {                     // right-hand side of the first level (interior nodes)
     const TailLevel<T> &L0 = a.lv[0];
@@ -137,19 +162,19 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
   }
   __syncthreads();
   // one Chebyshev step on level l from x (first: c1 = 0, the direction is not read)
-  auto cheb_step = [&](const TailLevel<T> &lv, bool first, T c1, T c2) {
+  auto cheb_step = [&](int l, bool first, T c1, T c2) {
+    const TailLevel<T> &lv = a.lv[l];
     const int L = 2 * lv.n + 1, N = L * L;
     T *b = sm + lv.off, *x = b + 2 * N;
-    const StencilTable<T> &tb = *lv.tab;
     int I, J;
     const bool mine = class_node(grp, gi, lv.n, I, J);
     const int k = J * L + I;
     T x0 = 0, x1 = 0, d0 = 0, d1 = 0;
     if (mine) {
       T s0, s1;
-      class_product<T>(grp, tb, x, N, L, k, s0, s1);
+      class_product<T>(grp, coefs(l), x, N, L, k, s0, s1);
       const T r0 = b[k] - s0, r1 = b[N + k] - s1;
-      const T *di = tb.dinv[grp];
+      const T *di = dinv(l) + 4 * grp;
       const T z0 = di[0] * r0 + di[1] * r1, z1 = di[2] * r0 + di[3] * r1;
       d0 = first ? c2 * z0 : c1 * d[k] + c2 * z0;
       d1 = first ? c2 * z1 : c1 * d[N + k] + c2 * z1;
@@ -170,12 +195,11 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
     const TailLevel<T> &lv = a.lv[l];
     const int L = 2 * lv.n + 1, N = L * L;
     T *b = sm + lv.off, *x = b + 2 * N;
-    const StencilTable<T> &tb = *lv.tab;
     {   // first step from zero: x = d = s D^{-1} b
       int I, J;
       if (class_node(grp, gi, lv.n, I, J)) {
         const int k = J * L + I;
-        const T *di = tb.dinv[grp];
+        const T *di = dinv(l) + 4 * grp;
         const T b0 = b[k], b1 = b[N + k];
         const T z0 = lv.s * (di[0] * b0 + di[1] * b1), z1 = lv.s * (di[2] * b0 + di[3] * b1);
         x[k] = d[k] = z0;
@@ -183,13 +207,13 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
       }
     }
     __syncthreads();
-    for (int j = 0; j + 1 < a.degree; ++j) cheb_step(lv, false, lv.c1[j], lv.c2[j]);
+    for (int j = 0; j + 1 < a.degree; ++j) cheb_step(l, false, lv.c1[j], lv.c2[j]);
     {   // residual over the direction (not read again before the post-smoothing)
       int I, J;
       if (class_node(grp, gi, lv.n, I, J)) {
         const int k = J * L + I;
         T s0, s1;
-        class_product<T>(grp, tb, x, N, L, k, s0, s1);
+        class_product<T>(grp, coefs(l), x, N, L, k, s0, s1);
         d[k] = b[k] - s0;
         d[N + k] = b[N + k] - s1;
       }
@@ -203,10 +227,10 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
         const int k = Jc * Lc + Ic;
         T s0, s1;
         switch (grp) {
-          case 0: tail_restrict<T, 0>(*a.rt, d, N, L, Ic, Jc, s0, s1); break;
-          case 1: tail_restrict<T, 1>(*a.rt, d, N, L, Ic, Jc, s0, s1); break;
-          case 2: tail_restrict<T, 2>(*a.rt, d, N, L, Ic, Jc, s0, s1); break;
-          default: tail_restrict<T, 3>(*a.rt, d, N, L, Ic, Jc, s0, s1); break;
+          case 0: tail_restrict<T, 0>(rw, d, N, L, Ic, Jc, s0, s1); break;
+          case 1: tail_restrict<T, 1>(rw, d, N, L, Ic, Jc, s0, s1); break;
+          case 2: tail_restrict<T, 2>(rw, d, N, L, Ic, Jc, s0, s1); break;
+          default: tail_restrict<T, 3>(rw, d, N, L, Ic, Jc, s0, s1); break;
         }
         bc[k] = s0;
         bc[Nc + k] = s1;
@@ -214,15 +238,30 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
     }
     __syncthreads();
   }
-  {   // coarsest level: x = C^{-1} b, one wave per row (sums in double, as the dense kernel)
+  {   // coarsest level: x = C^{-1} b, one wave per row (sums in double, as the dense kernel);
+      // a wave loads kRows rows at once (coalesced, one memory round trip per batch)
+    constexpr int kRows = 4, kSeg = kTailDenseMax / kWave, NW = kTailThreads / kWave;
     const T *b = sm + a.offc;
     T *x = sm + a.offc + a.m;
     const int w = tid / kWave, lane = tid % kWave;
-    for (int r = w; r < a.m; r += kTailThreads / kWave) {
-      double s = 0.0;
-      for (int k = lane; k < a.m; k += kWave) s += (double)a.cinv[(int64_t)r * a.m + k] * (double)b[k];
-      s = wave_sum(s);
-      if (lane == 0) x[r] = (T)s;
+    for (int r0 = w; r0 < a.m; r0 += kRows * NW) {
+      T c[kRows][kSeg];
+#pragma unroll
+      for (int q = 0; q < kRows; ++q)
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+          const int r = r0 + q * NW, k = lane + kWave * j;
+          c[q][j] = (r < a.m && k < a.m) ? a.cinv[(int64_t)r * a.m + k] : T(0);
+        }
+#pragma unroll
+      for (int q = 0; q < kRows; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j)
+          if (lane + kWave * j < a.m) s += (double)c[q][j] * (double)b[lane + kWave * j];
+        s = wave_sum(s);
+        if (lane == 0 && r0 + q * NW < a.m) x[r0 + q * NW] = (T)s;
+      }
     }
   }
   __syncthreads();
@@ -242,8 +281,8 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
       x[N + k] += s1;
     }
     __syncthreads();
-    cheb_step(lv, true, T(0), lv.s);
-    for (int j = 0; j + 1 < a.degree; ++j) cheb_step(lv, false, lv.c1[j], lv.c2[j]);
+    cheb_step(l, true, T(0), lv.s);
+    for (int j = 0; j + 1 < a.degree; ++j) cheb_step(l, false, lv.c1[j], lv.c2[j]);
     (void)b;
   }
   {   // result of the first level, Dirichlet nodes included (0)
@@ -255,14 +294,35 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
 
 }  // namespace
 
+int tail_lds_limit() {
+  static int limit = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 65536;
+    v = v < 65536 ? v : v > 163840 ? 163840 : v;
+    // dynamic LDS above 64 KiB is granted per kernel
+    if (v > 65536 && (hipFuncSetAttribute((const void *)k_mg_tail<double>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, v) != hipSuccess ||
+                      hipFuncSetAttribute((const void *)k_mg_tail<float>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, v) != hipSuccess)) {
+      (void)hipGetLastError();
+      v = 65536;
+    }
+    return v;
+  }();
+  return limit;
+}
+
 template <typename T>
 void mg_tail(const TailArgs<T> &a, hipStream_t s, int K) {
   FSI_REQUIRE(a.nlev >= 1 && a.nlev <= kTailMax && a.degree >= 1 && a.degree <= kTailDeg, FSI_E_ARG,
               "coarse tail shape out of range");
   FSI_REQUIRE(a.lv[0].n <= kTailMaxN, FSI_E_ARG, "coarse tail level too fine");
+  FSI_REQUIRE(a.m <= kTailDenseMax, FSI_E_ARG, "coarsest level too large for the tail");
   FSI_REQUIRE(K >= 1 && K <= 65535 && (K == 1 || a.lb > 0), FSI_E_ARG, "lane count out of range");
   const int bytes = a.lds * (int)sizeof(T);
-  FSI_REQUIRE(bytes <= kTailLdsMax, FSI_E_ARG, "coarse tail exceeds the LDS of a block");
+  FSI_REQUIRE(bytes <= tail_lds_limit(), FSI_E_ARG, "coarse tail exceeds the LDS of a block");
   hipLaunchKernelGGL(k_mg_tail<T>, dim3(1, (unsigned)K), dim3(kTailThreads), bytes, s, a);
   FSI_CHECK_LAUNCH();
 }

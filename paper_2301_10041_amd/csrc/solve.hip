@@ -380,9 +380,12 @@ static bool tail_args(Mg &mg, int l, int degree, const T *b, T *x, int64_t ls, T
   a.offc = off;
   a.m = (int)mg.ncoarse;
   FSI_REQUIRE(a.m == 2 * (int)mg.lv[last].nodes, FSI_E_STATE, "coarsest level size");
+  if (a.m > kTailDenseMax) return false;
   off += 2 * a.m;
+  a.offt = off;
+  off += nlev * kTailTab + kTailRw;
   a.lds = off;
-  if ((int64_t)a.lds * (int64_t)sizeof(T) > kTailLdsMax) return false;
+  if ((int64_t)a.lds * (int64_t)sizeof(T) > tail_lds_limit()) return false;
   a.rt = rtab<T>(mg);
   a.cinv = Pr<T>::cinv(mg);
   a.b = b;
