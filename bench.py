@@ -219,8 +219,9 @@ def main():
                 "unit": "GB/s", "frac": round(k["achieved_gbs"] / HBM_PEAK_GBS, 4),
                 "traffic": recorded_traffic(args.workload, "k_cheb3<double>")
                 if main_tag == "fp64" else None,
-                "kernel": ("k_cheb3<%s> (finest-level matrix-free A_f smoothing: the three "
-                           "post-smoothing Chebyshev steps in one launch)"
+                "kernel": ("k_cheb3<%s> (finest-level matrix-free A_f smoothing: the coarse "
+                           "correction added while staging x, then the three post-smoothing "
+                           "Chebyshev steps, in one launch)"
                            % ("double" if main_tag == "fp64" else "float")),
                 "bytes_per_launch": k["bytes_per_launch"], "avg_us": round(k["avg_us"], 2),
                 "launches": k["launches"]}
