@@ -69,6 +69,8 @@ size_t Ctx::device_bytes() const {
   b += outer.V.bytes() + outer.Z.bytes() + outer.w.bytes() + outer.r.bytes() + outer.x32.bytes() +
        outer.y32.bytes();
   b += red.bytes() + dscal.bytes() + tmpN.bytes() + tmpS.bytes();
+  b += ms_state.bytes() + ms_red.bytes() + ms_x.bytes() + ms_part.bytes() + ms_dot.bytes() + pc_in.bytes() +
+       pc_out.bytes();
   return b;
 }
 

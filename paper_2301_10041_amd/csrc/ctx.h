@@ -149,6 +149,7 @@ struct Ctx {
   // inner MINRES: device-side scalar state, its own reduction buffer and solution vector
   // (allocated once: captured graphs hold these pointers), graphs per precision and phase
   DevBuf<double> ms_state, ms_red, ms_x, ms_part;
+  DevBuf<double> ms_dot;   // per lane: velocity tile sums, then pressure block sums of r . z
   hipGraphExec_t ms_graph[2][FSI_MAX_LANES + 1][6] = {};   // per precision, lane count, rotation phase
   DevBuf<double> pc_in, pc_out;
   void drop_graphs();

@@ -114,6 +114,31 @@ __global__ void k_set_pinned(T *z, const T *r, int64_t ls) {   // lane blockIdx.
   if (threadIdx.x == 0 && blockIdx.x == 0) z[(int64_t)blockIdx.y * ls] = r[(int64_t)blockIdx.y * ls];
 }
 
+// The pressure part of the A11 preconditioner's output with the dot product r . z of its
+// entries: z = a x + b y except z[0] = r[0] (pinned entry), and block k of kPresDotBlocks
+// stores its part of sum r z (FP64, fixed partition and order) at part[k].  Lane blockIdx.y:
+// z, r at + lane ls, x, y at + lane lx, part at + lane lp.
+constexpr int kPresDotBlocks = 256;
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock) k_pres_out_dot(T *z, const T *r, const T *x, const T *y, T a, T b,
+                                                            int64_t n, int64_t ls, int64_t lx, double *part,
+                                                            int64_t lp) {
+  z += (int64_t)blockIdx.y * ls;
+  r += (int64_t)blockIdx.y * ls;
+  x += (int64_t)blockIdx.y * lx;
+  y += (int64_t)blockIdx.y * lx;
+  const int64_t chunk = (n + kPresDotBlocks - 1) / kPresDotBlocks;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  double s = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kRedBlock) {
+    const T v = i == 0 ? r[0] : a * x[i] + b * y[i];
+    z[i] = v;
+    s += (double)r[i] * (double)v;
+  }
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * lp + blockIdx.x] = t;
+}
+
 // z[0] = r[0] rounded through T (the value an FP32 preconditioner would pass on)
 template <typename TZ, typename T>
 __global__ void k_set_pinned_to(TZ *z, const TZ *r) {
@@ -239,8 +264,9 @@ template <typename T>
 static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, double lmax, int steps,
                             const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s, Prof *prof,
                             int K = 1, int64_t ls = 0, T *out = nullptr, double *out64 = nullptr,
-                            const T *xc = nullptr, int64_t lc = 0) {
+                            const T *xc = nullptr, int64_t lc = 0, LP<double> dot = LP<double>()) {
   FSI_REQUIRE(!xc || (!zero_init && steps >= 3), FSI_E_STATE, "the coarse correction rides on the fused steps");
+  FSI_REQUIRE(!dot.p || (!zero_init && steps == 3), FSI_E_STATE, "the tile sums ride on the last fused launch");
   const LP<const T> lxc(xc, lc);
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
@@ -268,7 +294,7 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
     next(c1c, c2c);
     if (prof) prof->begin(s);
     cheb3_post<T, double>(n, tab, LP<const T>(x, ls), lb, LP<T>(), LP<double>(out64, ls), (T)(1.0 / theta), c1b, c2b,
-                          c1c, c2c, s, K, lxc);
+                          c1c, c2c, s, K, lxc, dot);
     if (prof) prof->end(s);
     return nullptr;
   } else if (!zero_init && steps >= 3) {
@@ -278,7 +304,7 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
     T *dst = (out && steps == 3) ? out : x2;
     if (prof) prof->begin(s);
     cheb3_post<T>(n, tab, LP<const T>(x, ls), lb, ld3, LP<T>(dst, ls), (T)(1.0 / theta), c1b, c2b, c1c, c2c, s, K,
-                  lxc);
+                  lxc, dot);
     if (prof) prof->end(s);
     x2 = x;
     x = dst;
@@ -400,13 +426,17 @@ static bool tail_args(Mg &mg, int l, int degree, const T *b, T *x, int64_t ls, T
 // out (optional): where the matrix-free velocity cycle writes its result (the returned
 // pointer); otherwise a level work vector.  out64 (optional, FP32 cycle): an FP64 vector the
 // result goes to when the last smoothing launch can store it there (then nullptr is returned).
+// dot (optional, level 0 of a velocity cycle with tile_dot_ok): the last launch stores the
+// per-tile sums of b . result (cheb3_dot_count(n) per lane).
 template <typename T, int W, int NC>
 static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr, int K = 1, T *out = nullptr,
-                 double *out64 = nullptr) {
+                 double *out64 = nullptr, LP<double> dot = LP<double>()) {
   MgLevel &L = mg.lv[l];
   T *x = Pr<T>::w(L, 0), *x2 = Pr<T>::w(L, 4), *r = Pr<T>::w(L, 2), *d = Pr<T>::w(L, 3);
   // K systems (matrix-free hierarchy only): lane k of every level vector at + k comps nodes
   FSI_REQUIRE(K == 1 || mg.stencil, FSI_E_STATE, "several systems per V-cycle need the matrix-free smoother");
+  FSI_REQUIRE(!dot.p || (l == 0 && W == 4 && mg.stencil && l + 1 < (int)mg.lv.size()), FSI_E_STATE,
+              "tile sums only from the finest velocity level of a matrix-free cycle");
   const int64_t ls = (int64_t)mg.comps * L.nodes;
   if (l + 1 == (int)mg.lv.size()) {
     hipLaunchKernelGGL(k_dense_mv<T>, dim3((unsigned)mg.ncoarse, (unsigned)K), dim3(kWave), 0, s,
@@ -439,7 +469,8 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
     auto smooth = [&](T *x0, T *x1, bool zero, const T *xcor) -> T * {
       if constexpr (W == 4)
         return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, pl, K, ls,
-                                    zero ? nullptr : out, zero ? nullptr : out64, xcor, lc);
+                                    zero ? nullptr : out, zero ? nullptr : out64, xcor, lc,
+                                    zero ? LP<double>() : dot);
       else
         return (void)xcor, chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, K, ls);
     };
@@ -492,8 +523,13 @@ constexpr int kMpSteps = 3;
 // preconditioner on one stream.
 // r64, z64 (FP32 arithmetic, one system): the results are stored straight into the FP64 vector
 // z64 (z unused) and the pressure residual is read from r64 (r holds the velocity part).
+// dot (FP64 form, tile_dot_ok): the launches that write z also store per-tile / per-block
+// parts of r . z: cheb3_dot_count(n) velocity tile sums, then kPresDotBlocks pressure
+// block sums, per lane (lane stride dot.s).
 template <typename T>
-static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 = nullptr, double *z64 = nullptr) {
+static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 = nullptr, double *z64 = nullptr,
+                        LP<double> dot = LP<double>()) {
+  FSI_REQUIRE(!dot.p || (std::is_same<T, double>::value && !z64), FSI_E_STATE, "fused dot in the FP64 form only");
   const bool fork = !c.capturing;
   hipStream_t s = c.stream, sp = fork ? c.aux_stream : c.stream;
   const int64_t N2 = c.N2, Np = c.Np, nf = 2 * N2 + Np;
@@ -506,12 +542,12 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
     T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr, 1, nullptr, z64);
     if (xu) convert(z64, xu, 2 * N2, s);
   } else if (K == 1) {   // the cycle reads r and writes z in place (one system: no lane stride)
-    T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr, 1, z);
+    T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr, 1, z, nullptr, dot);
     if (xu != z) convert(z, xu, 2 * N2, s);
   } else {   // the finest level's right-hand side: the velocity part of each lane, contiguous
     T *bu = Pr<T>::w(c.mgu.lv[0], 1);
     convert_l(LP<T>(bu, 2 * N2), LP<const T>(r, nf), 2 * N2, s, K);
-    T *xu = vcycle<T, 4, 2>(c.mgu, 0, bu, s, nullptr, K);
+    T *xu = vcycle<T, 4, 2>(c.mgu, 0, bu, s, nullptr, K, nullptr, nullptr, dot);
     convert_l(LP<T>(z, nf), LP<const T>(xu, 2 * N2), 2 * N2, s, K);
   }
   // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
@@ -531,6 +567,10 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
   if (z64) {
     lincomb_to<double, T>(z64 + 2 * N2, mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, sp);
     hipLaunchKernelGGL((k_set_pinned_to<double, T>), dim3(1), dim3(1), 0, sp, z64 + 2 * N2, r64 + 2 * N2);
+  } else if (dot.p) {
+    hipLaunchKernelGGL(k_pres_out_dot<T>, dim3(kPresDotBlocks, K), dim3(kRedBlock), 0, sp, z + 2 * N2, r + 2 * N2,
+                       mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, nf, Np,
+                       dot.p + cheb3_dot_count(c.n), dot.s);
   } else {
     lincomb_l(LP<T>(z + 2 * N2, nf), LP<const T>(mres, Np), LP<const T>(xp, Np), (T)c.nu, (T)(c.rho / c.dt), Np,
               sp, K);
@@ -752,6 +792,23 @@ __global__ void k_ms_alfa(const double *part, int n, MinresState *st) {
   }
 }
 
+// beta^2 = the velocity tile sums, then the pressure block sums (one 1024-thread block per
+// lane, fixed order; lane k's sums at part + k lp, its state at st + k)
+__global__ void __launch_bounds__(1024) k_ms_beta(const double *part, int nu, int np, int64_t lp, MinresState *st) {
+  __shared__ double red[1024 / kWave];
+  part += (int64_t)blockIdx.y * lp;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nu + np; i += 1024) acc += part[i];
+  acc = wave_sum(acc);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = 0.0;
+    for (int k = 0; k < 1024 / kWave; ++k) b += red[k];
+    st[blockIdx.y].beta2 = b;
+  }
+}
+
 // Buffers of one rotation phase (0, 1, 2).  Lanczos: r1 (old), r2 (current), y (new);
 // directions: w1 (two back, overwritten by the new one), w2, w.  Lane 0 of each (lane
 // stride nf).
@@ -786,6 +843,12 @@ static MsBufs ms_bufs_fused(Ctx &c, double *x, int it) {
   return b;
 }
 
+// The FP64 preconditioner can hand over r . z as tile and block sums: the velocity cycle ends
+// with the fused three-step launch on a matrix-free hierarchy of two or more levels.
+static bool tile_dot_ok(const Ctx &c) {
+  return c.mgu.stencil && c.mgu.lv.size() > 1 && c.mgu.degree == 3 && c.ms_dot.p;
+}
+
 // One inner iteration with the matrix-free A11 (FP64) for K systems: the scaling v = s y,
 // the product, the first three-term update and the dot product alfa = v . y are one tiled
 // launch (new y over r1); then y -= alfa s r2, z = M y into the y buffer, beta^2 = y . z.
@@ -802,8 +865,16 @@ static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st, int K) 
                      LP<double>(c.ms_part.p, tiles), s, K);
   hipLaunchKernelGGL(k_ms_alfa, dim3(1, K), dim3(256), 0, s, c.ms_part.p, tiles, st);
   hipLaunchKernelGGL(k_ms_axpy, dim3(g, K), dim3(256), 0, s, b.r1, b.r2, st, 1, nf);
-  a11_precond_on64<TA>(c, b.r1, b.y, K);
-  dot_l(LP<const double>(b.r1, nf), LP<const double>(b.y, nf), nf, LP<double>(dv + 1, kMsDoubles), c.ms_red.p, s, K);
+  if (std::is_same<TA, double>::value && tile_dot_ok(c)) {   // beta^2 = r . z from the writers of z
+    const int nu = cheb3_dot_count(c.n);
+    const int64_t ld = nu + kPresDotBlocks;
+    a11_precond<double>(c, b.r1, b.y, K, nullptr, nullptr, LP<double>(c.ms_dot.p, ld));
+    hipLaunchKernelGGL(k_ms_beta, dim3(1, K), dim3(1024), 0, s, c.ms_dot.p, nu, kPresDotBlocks, ld, st);
+  } else {
+    a11_precond_on64<TA>(c, b.r1, b.y, K);
+    dot_l(LP<const double>(b.r1, nf), LP<const double>(b.y, nf), nf, LP<double>(dv + 1, kMsDoubles), c.ms_red.p, s,
+          K);
+  }
   hipLaunchKernelGGL(k_ms_step, dim3(1, K), dim3(1), 0, s, st);
   hipLaunchKernelGGL(k_ms_update, dim3(g, K), dim3(256), 0, s, b.w1, b.v, b.w2, b.w, b.x, st, nf);
   FSI_CHECK_LAUNCH();
@@ -953,7 +1024,7 @@ static void ensure_inner(Ctx &c, int prec, int K = 1) {
       c.inner.v64[i].release();
       c.inner.v32[i].release();
     }
-    for (auto *b : {&c.ms_x, &c.ms_state, &c.ms_red, &c.ms_part, &c.pc_in, &c.pc_out}) b->release();
+    for (auto *b : {&c.ms_x, &c.ms_state, &c.ms_red, &c.ms_part, &c.ms_dot, &c.pc_in, &c.pc_out}) b->release();
     c.outer.x32.release();
     c.outer.y32.release();
     for (Mg *mg : {&c.mgu, &c.mgp})
@@ -972,6 +1043,7 @@ static void ensure_inner(Ctx &c, int prec, int K = 1) {
     c.ms_state.alloc(nl * kMsDoubles);
     c.ms_red.alloc(nl * red_blocks(nf));   // dot products of one system per lane: never regrown
     c.ms_part.alloc(nl * stencil_tile_count(c.n));
+    c.ms_dot.alloc(nl * (cheb3_dot_count(c.n) + kPresDotBlocks));
   }
   if (!c.pc_in.p) {
     c.pc_in.alloc(nl * nf);

@@ -120,9 +120,13 @@ void cheb2_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b,
 // cheb3_post: from x, a step with c1 = 0 (c2a) and steps (c1b, c2b), (c1c, c2c); writes y
 // (stored as TY: double or T) and d.  With xc (coarse lattice n / 2, same lane count) the
 // steps start from x + P xc (the V-cycle's coarse correction; x itself is not written).
+// With dot, tile t of lane k stores the sum over its nodes of b . y (FP64, y as stored) at
+// dot.at(k)[t] (cheb3_dot_count(n) tiles).
 template <typename T, typename TY = T>
 void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<TY> y, T c2a, T c1b,
-                T c2b, T c1c, T c2c, hipStream_t st, int K = 1, LP<const T> xc = LP<const T>());
+                T c2b, T c1c, T c2c, hipStream_t st, int K = 1, LP<const T> xc = LP<const T>(),
+                LP<double> dot = LP<double>());
+int cheb3_dot_count(int n);
 
 // The same launch inside the inner MINRES (FP64): v = s x, y = s (A11 x) + c r1 written over
 // r1, and one partial sum of v . y per tile in part[] (s, c read from device memory;

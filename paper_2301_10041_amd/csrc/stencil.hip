@@ -731,6 +731,8 @@ struct Cheb3Args {   // y stored as TY (the mixed form writes FP32 results into 
   int64_t lv;    // lane stride of x, b, d, y (lane = blockIdx.y)
   const T *xc;   // coarse correction (lattice n / 2, two components) or null
   int64_t lc;    // its lane stride
+  double *dot;   // per-tile sums of b . y over the tile's nodes (FP64), or null
+  int64_t ldot;  // their lane stride
 };
 
 // Coarse P2 interpolation at an interior fine node (I, J) of the cell (I >> 2, J >> 2) at
@@ -765,7 +767,7 @@ __device__ __forceinline__ void prolong_lds(const T *XC, int I, int J, int Ic0, 
   }
 }
 
-template <typename T, int RR, typename TY, bool PROL>
+template <typename T, int RR, typename TY, bool PROL, bool DOT>
 __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int tiles_x, int tiles, int band) {
   constexpr int NT = 64 * RR;
   constexpr int H0 = RR + 12, H1 = RR + 8;           // rows of the staged x and of region 1
@@ -782,6 +784,7 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int t
   lane_shift(a.d, a.lv);
   lane_shift(a.y, a.lv);
   lane_shift(a.xc, a.lc);
+  lane_shift(a.dot, a.ldot);
   const int n2 = 2 * a.n, L = n2 + 1;
   const int64_t N = a.L2;
   const int I0 = (t % tiles_x) * kC3W, J0 = (t / tiles_x) * RR;
@@ -975,6 +978,7 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int t
     }
   __syncthreads();
   // step 3 on the tile row (region-1 columns 4..R+3 of the tile: i in [4, 4 + kC3W))
+  double by = 0.0;   // the thread's part of b . y
   {
     const int row = rows[0], J = J0 - 4 + row;
     if (J <= n2) {
@@ -1016,14 +1020,32 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int t
         }
         a.y[r] = (TY)y0;
         a.y[N + r] = (TY)y1;
+        if constexpr (DOT) by += (double)b0 * (double)(TY)y0 + (double)b1 * (double)(TY)y1;
       }
+    }
+  }
+  if constexpr (DOT) {   // the tile's sum in a fixed order: lanes by shuffles, then waves
+    __shared__ double red[RR];
+    by = wave_sum(by);
+    if (lane == 0) red[w] = by;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < RR; ++k) s += red[k];
+      a.dot[t] = s;
     }
   }
 }
 
+int cheb3_dot_count(int n) {
+  const int L = 2 * n + 1;
+  return ((L + kC3W - 1) / kC3W) * ((L + kC3R - 1) / kC3R);
+}
+
 template <typename T, typename TY>
 void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<TY> y, T c2a, T c1b,
-                T c2b, T c1c, T c2c, hipStream_t st, int K, LP<const T> xc) {
+                T c2b, T c1c, T c2c, hipStream_t st, int K, LP<const T> xc, LP<double> dot) {
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
   FSI_REQUIRE(K >= 1 && K <= 65535, FSI_E_ARG, "lane count out of range");
   FSI_REQUIRE(!xc.p || (n % 2 == 0 && n >= 4), FSI_E_ARG, "a coarse correction needs an even fluid grid");
@@ -1032,23 +1054,28 @@ void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b,
   const int tx = (L + kC3W - 1) / kC3W, ty = (L + kC3R - 1) / kC3R;
   const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
   const int64_t lv = common_stride({{x.p, x.s}, {b.p, b.s}, {d.p, d.s}, {y.p, y.s}}, K);
-  Cheb3Args<T, TY> a{n, tab, x.p, b.p, d.p, y.p, L * L, c2a, c1b, c2b, c1c, c2c, lv, xc.p, xc.s};
+  FSI_REQUIRE(!dot.p || K == 1 || dot.s >= tiles, FSI_E_ARG, "lane stride of the tile sums too small");
+  Cheb3Args<T, TY> a{n, tab, x.p, b.p, d.p, y.p, L * L, c2a, c1b, c2b, c1c, c2c, lv, xc.p, xc.s, dot.p, dot.s};
   const dim3 grid((unsigned)(band * kXcd), (unsigned)K), block(64 * kC3R);
-  if (xc.p)
-    hipLaunchKernelGGL((k_cheb3<T, kC3R, TY, true>), grid, block, 0, st, a, tx, tiles, band);
+  if (xc.p && dot.p)
+    hipLaunchKernelGGL((k_cheb3<T, kC3R, TY, true, true>), grid, block, 0, st, a, tx, tiles, band);
+  else if (xc.p)
+    hipLaunchKernelGGL((k_cheb3<T, kC3R, TY, true, false>), grid, block, 0, st, a, tx, tiles, band);
+  else if (dot.p)
+    hipLaunchKernelGGL((k_cheb3<T, kC3R, TY, false, true>), grid, block, 0, st, a, tx, tiles, band);
   else
-    hipLaunchKernelGGL((k_cheb3<T, kC3R, TY, false>), grid, block, 0, st, a, tx, tiles, band);
+    hipLaunchKernelGGL((k_cheb3<T, kC3R, TY, false, false>), grid, block, 0, st, a, tx, tiles, band);
   FSI_CHECK_LAUNCH();
 }
 template void cheb3_post<double, double>(int, const StencilTable<double> *, LP<const double>, LP<const double>,
                                          LP<double>, LP<double>, double, double, double, double, double, hipStream_t,
-                                         int, LP<const double>);
+                                         int, LP<const double>, LP<double>);
 template void cheb3_post<float, float>(int, const StencilTable<float> *, LP<const float>, LP<const float>, LP<float>,
                                        LP<float>, float, float, float, float, float, hipStream_t, int,
-                                       LP<const float>);
+                                       LP<const float>, LP<double>);
 template void cheb3_post<float, double>(int, const StencilTable<float> *, LP<const float>, LP<const float>,
                                         LP<float>, LP<double>, float, float, float, float, float, hipStream_t, int,
-                                        LP<const float>);
+                                        LP<const float>, LP<double>);
 
 template <typename T>
 void cheb2_pre(int n, const StencilTable<T> *tab, LP<const T> b, LP<T> d, LP<T> x, T s, T c1a, T c2a, T c1b,
