@@ -115,25 +115,28 @@ __global__ void k_set_pinned(T *z, const T *r, int64_t ls) {   // lane blockIdx.
 }
 
 // The pressure part of the A11 preconditioner's output with the dot product r . z of its
-// entries: z = a x + b y except z[0] = r[0] (pinned entry), and block k of kPresDotBlocks
-// stores its part of sum r z (FP64, fixed partition and order) at part[k].  Lane blockIdx.y:
-// z, r at + lane ls, x, y at + lane lx, part at + lane lp.
+// entries: z = a x + b y computed in T and stored as TZ, except z[0] = r[0] rounded through T
+// (pinned entry), and block k of kPresDotBlocks stores its part of sum r z (FP64, fixed
+// partition and order) at part[k]; the sums take r64 in place of r when given (an FP32
+// output of the mixed form, r its FP32 copy).  Lane blockIdx.y: z, r, r64 at + lane ls, x, y
+// at + lane lx, part at + lane lp.
 constexpr int kPresDotBlocks = 256;
-template <typename T>
-__global__ void __launch_bounds__(kRedBlock) k_pres_out_dot(T *z, const T *r, const T *x, const T *y, T a, T b,
+template <typename TZ, typename T>
+__global__ void __launch_bounds__(kRedBlock) k_pres_out_dot(TZ *z, const TZ *r, const T *x, const T *y, T a, T b,
                                                             int64_t n, int64_t ls, int64_t lx, double *part,
-                                                            int64_t lp) {
+                                                            int64_t lp, const double *r64) {
   z += (int64_t)blockIdx.y * ls;
   r += (int64_t)blockIdx.y * ls;
+  if (r64) r64 += (int64_t)blockIdx.y * ls;
   x += (int64_t)blockIdx.y * lx;
   y += (int64_t)blockIdx.y * lx;
   const int64_t chunk = (n + kPresDotBlocks - 1) / kPresDotBlocks;
   const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
   double s = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kRedBlock) {
-    const T v = i == 0 ? r[0] : a * x[i] + b * y[i];
+    const TZ v = (TZ)(i == 0 ? (T)r[0] : a * x[i] + b * y[i]);
     z[i] = v;
-    s += (double)r[i] * (double)v;
+    s += (r64 ? r64[i] : (double)r[i]) * (double)v;
   }
   const double t = block_sum(s);
   if (threadIdx.x == 0) part[(int64_t)blockIdx.y * lp + blockIdx.x] = t;
@@ -264,7 +267,8 @@ template <typename T>
 static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, double lmax, int steps,
                             const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s, Prof *prof,
                             int K = 1, int64_t ls = 0, T *out = nullptr, double *out64 = nullptr,
-                            const T *xc = nullptr, int64_t lc = 0, LP<double> dot = LP<double>()) {
+                            const T *xc = nullptr, int64_t lc = 0, LP<double> dot = LP<double>(),
+                            LP<const double> b64 = LP<const double>()) {
   FSI_REQUIRE(!xc || (!zero_init && steps >= 3), FSI_E_STATE, "the coarse correction rides on the fused steps");
   FSI_REQUIRE(!dot.p || (!zero_init && steps == 3), FSI_E_STATE, "the tile sums ride on the last fused launch");
   const LP<const T> lxc(xc, lc);
@@ -294,7 +298,7 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
     next(c1c, c2c);
     if (prof) prof->begin(s);
     cheb3_post<T, double>(n, tab, LP<const T>(x, ls), lb, LP<T>(), LP<double>(out64, ls), (T)(1.0 / theta), c1b, c2b,
-                          c1c, c2c, s, K, lxc, dot);
+                          c1c, c2c, s, K, lxc, dot, b64);
     if (prof) prof->end(s);
     return nullptr;
   } else if (!zero_init && steps >= 3) {
@@ -304,7 +308,7 @@ static T *chebyshev_stencil(int n, const StencilTable<T> *tab, double lmin, doub
     T *dst = (out && steps == 3) ? out : x2;
     if (prof) prof->begin(s);
     cheb3_post<T>(n, tab, LP<const T>(x, ls), lb, ld3, LP<T>(dst, ls), (T)(1.0 / theta), c1b, c2b, c1c, c2c, s, K,
-                  lxc, dot);
+                  lxc, dot, b64);
     if (prof) prof->end(s);
     x2 = x;
     x = dst;
@@ -427,10 +431,12 @@ static bool tail_args(Mg &mg, int l, int degree, const T *b, T *x, int64_t ls, T
 // pointer); otherwise a level work vector.  out64 (optional, FP32 cycle): an FP64 vector the
 // result goes to when the last smoothing launch can store it there (then nullptr is returned).
 // dot (optional, level 0 of a velocity cycle with tile_dot_ok): the last launch stores the
-// per-tile sums of b . result (cheb3_dot_count(n) per lane).
+// per-tile sums of b . result (cheb3_dot_count(n) per lane), with b64 (FP32 cycle) in place
+// of b.
 template <typename T, int W, int NC>
 static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr, int K = 1, T *out = nullptr,
-                 double *out64 = nullptr, LP<double> dot = LP<double>()) {
+                 double *out64 = nullptr, LP<double> dot = LP<double>(),
+                 LP<const double> b64 = LP<const double>()) {
   MgLevel &L = mg.lv[l];
   T *x = Pr<T>::w(L, 0), *x2 = Pr<T>::w(L, 4), *r = Pr<T>::w(L, 2), *d = Pr<T>::w(L, 3);
   // K systems (matrix-free hierarchy only): lane k of every level vector at + k comps nodes
@@ -470,7 +476,7 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
       if constexpr (W == 4)
         return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, pl, K, ls,
                                     zero ? nullptr : out, zero ? nullptr : out64, xcor, lc,
-                                    zero ? LP<double>() : dot);
+                                    zero ? LP<double>() : dot, zero ? LP<const double>() : b64);
       else
         return (void)xcor, chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, K, ls);
     };
@@ -529,7 +535,8 @@ constexpr int kMpSteps = 3;
 template <typename T>
 static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 = nullptr, double *z64 = nullptr,
                         LP<double> dot = LP<double>()) {
-  FSI_REQUIRE(!dot.p || (std::is_same<T, double>::value && !z64), FSI_E_STATE, "fused dot in the FP64 form only");
+  FSI_REQUIRE((!dot.p || std::is_same<T, double>::value || r64), FSI_E_STATE,
+              "sums of r . z in the FP32 form need the FP64 residual");
   const bool fork = !c.capturing;
   hipStream_t s = c.stream, sp = fork ? c.aux_stream : c.stream;
   const int64_t N2 = c.N2, Np = c.Np, nf = 2 * N2 + Np;
@@ -539,7 +546,9 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
     FSI_HIP(hipStreamWaitEvent(sp, c.ev_fork, 0));
   }
   if (z64) {
-    T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr, 1, nullptr, z64);
+    T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr, 1, nullptr, z64, dot,
+                            LP<const double>(dot.p ? r64 : nullptr));
+    FSI_REQUIRE(!dot.p || !xu, FSI_E_STATE, "the sums of r . z need the direct FP64 output");
     if (xu) convert(z64, xu, 2 * N2, s);
   } else if (K == 1) {   // the cycle reads r and writes z in place (one system: no lane stride)
     T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr, 1, z, nullptr, dot);
@@ -547,7 +556,8 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
   } else {   // the finest level's right-hand side: the velocity part of each lane, contiguous
     T *bu = Pr<T>::w(c.mgu.lv[0], 1);
     convert_l(LP<T>(bu, 2 * N2), LP<const T>(r, nf), 2 * N2, s, K);
-    T *xu = vcycle<T, 4, 2>(c.mgu, 0, bu, s, nullptr, K, nullptr, nullptr, dot);
+    T *xu = vcycle<T, 4, 2>(c.mgu, 0, bu, s, nullptr, K, nullptr, nullptr, dot,
+                            LP<const double>(dot.p && r64 ? r64 : nullptr, nf));
     convert_l(LP<T>(z, nf), LP<const T>(xu, 2 * N2), 2 * N2, s, K);
   }
   // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
@@ -564,13 +574,17 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
                                   0.5, 2.0, kMpSteps, rp, mx, mx2, md, true, sp, K, Np)
                 : chebyshev<T, 1, 1>(Np, c.Mp.rowptr.p, c.Mp.col.p, Pr<T>::val(c.Mp), mp_dinv<T>(c), 0.5,
                                      2.0, kMpSteps, rp, mx, mx2, md, true, sp);
-  if (z64) {
+  if (z64 && dot.p) {
+    hipLaunchKernelGGL((k_pres_out_dot<double, T>), dim3(kPresDotBlocks, 1), dim3(kRedBlock), 0, sp, z64 + 2 * N2,
+                       r64 + 2 * N2, mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, nf, Np,
+                       dot.p + cheb3_dot_count(c.n), dot.s, nullptr);
+  } else if (z64) {
     lincomb_to<double, T>(z64 + 2 * N2, mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, sp);
     hipLaunchKernelGGL((k_set_pinned_to<double, T>), dim3(1), dim3(1), 0, sp, z64 + 2 * N2, r64 + 2 * N2);
   } else if (dot.p) {
-    hipLaunchKernelGGL(k_pres_out_dot<T>, dim3(kPresDotBlocks, K), dim3(kRedBlock), 0, sp, z + 2 * N2, r + 2 * N2,
-                       mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, nf, Np,
-                       dot.p + cheb3_dot_count(c.n), dot.s);
+    hipLaunchKernelGGL((k_pres_out_dot<T, T>), dim3(kPresDotBlocks, K), dim3(kRedBlock), 0, sp, z + 2 * N2,
+                       r + 2 * N2, mres, xp, (T)c.nu, (T)(c.rho / c.dt), Np, nf, Np,
+                       dot.p + cheb3_dot_count(c.n), dot.s, r64 ? r64 + 2 * N2 : nullptr);
   } else {
     lincomb_l(LP<T>(z + 2 * N2, nf), LP<const T>(mres, Np), LP<const T>(xp, Np), (T)c.nu, (T)(c.rho / c.dt), Np,
               sp, K);
@@ -843,10 +857,11 @@ static MsBufs ms_bufs_fused(Ctx &c, double *x, int it) {
   return b;
 }
 
-// The FP64 preconditioner can hand over r . z as tile and block sums: the velocity cycle ends
-// with the fused three-step launch on a matrix-free hierarchy of two or more levels.
-static bool tile_dot_ok(const Ctx &c) {
-  return c.mgu.stencil && c.mgu.lv.size() > 1 && c.mgu.degree == 3 && c.ms_dot.p;
+// The preconditioner can hand over r . z as tile and block sums when the velocity cycle of
+// its precision ends with the fused three-step launch on a matrix-free hierarchy of two or
+// more levels (the FP32 form for one system, on FP64 vectors).
+static bool tile_dot_ok(const Ctx &c, bool fp32) {
+  return c.mgu.stencil && c.mgu.lv.size() > 1 && (fp32 ? c.mgu.degree32 : c.mgu.degree) == 3 && c.ms_dot.p;
 }
 
 // One inner iteration with the matrix-free A11 (FP64) for K systems: the scaling v = s y,
@@ -865,10 +880,23 @@ static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st, int K) 
                      LP<double>(c.ms_part.p, tiles), s, K);
   hipLaunchKernelGGL(k_ms_alfa, dim3(1, K), dim3(256), 0, s, c.ms_part.p, tiles, st);
   hipLaunchKernelGGL(k_ms_axpy, dim3(g, K), dim3(256), 0, s, b.r1, b.r2, st, 1, nf);
-  if (std::is_same<TA, double>::value && tile_dot_ok(c)) {   // beta^2 = r . z from the writers of z
+  constexpr bool f32 = std::is_same<TA, float>::value;
+  if (tile_dot_ok(c, f32)) {   // beta^2 = r . z from the launches that write z
     const int nu = cheb3_dot_count(c.n);
     const int64_t ld = nu + kPresDotBlocks;
-    a11_precond<double>(c, b.r1, b.y, K, nullptr, nullptr, LP<double>(c.ms_dot.p, ld));
+    const LP<double> dot(c.ms_dot.p, ld);
+    if constexpr (f32) {   // the same arithmetic as a11_precond_on64<float>, sums on FP64 r
+      if (K == 1) {
+        convert(c.outer.x32.p, b.r1, 2 * c.N2, s);
+        a11_precond<float>(c, c.outer.x32.p, nullptr, 1, b.r1, b.y, dot);
+      } else {
+        convert_l(LP<float>(c.outer.x32.p, nf), LP<const double>(b.r1, nf), nf, s, K);
+        a11_precond<float>(c, c.outer.x32.p, c.outer.y32.p, K, b.r1, nullptr, dot);
+        convert_l(LP<double>(b.y, nf), LP<const float>(c.outer.y32.p, nf), nf, s, K);
+      }
+    } else {
+      a11_precond<double>(c, b.r1, b.y, K, nullptr, nullptr, dot);
+    }
     hipLaunchKernelGGL(k_ms_beta, dim3(1, K), dim3(1024), 0, s, c.ms_dot.p, nu, kPresDotBlocks, ld, st);
   } else {
     a11_precond_on64<TA>(c, b.r1, b.y, K);

@@ -121,11 +121,12 @@ void cheb2_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b,
 // (stored as TY: double or T) and d.  With xc (coarse lattice n / 2, same lane count) the
 // steps start from x + P xc (the V-cycle's coarse correction; x itself is not written).
 // With dot, tile t of lane k stores the sum over its nodes of b . y (FP64, y as stored) at
-// dot.at(k)[t] (cheb3_dot_count(n) tiles).
+// dot.at(k)[t] (cheb3_dot_count(n) tiles); with b64 the sums take that FP64 right-hand side
+// in place of b (the FP32 cycle of the mixed form).
 template <typename T, typename TY = T>
 void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<TY> y, T c2a, T c1b,
                 T c2b, T c1c, T c2c, hipStream_t st, int K = 1, LP<const T> xc = LP<const T>(),
-                LP<double> dot = LP<double>());
+                LP<double> dot = LP<double>(), LP<const double> b64 = LP<const double>());
 int cheb3_dot_count(int n);
 
 // The same launch inside the inner MINRES (FP64): v = s x, y = s (A11 x) + c r1 written over

@@ -733,6 +733,8 @@ struct Cheb3Args {   // y stored as TY (the mixed form writes FP32 results into 
   int64_t lc;    // its lane stride
   double *dot;   // per-tile sums of b . y over the tile's nodes (FP64), or null
   int64_t ldot;  // their lane stride
+  const double *b64;   // with dot: the FP64 right-hand side the sums use instead of b, or null
+  int64_t lb64;        // its lane stride
 };
 
 // Coarse P2 interpolation at an interior fine node (I, J) of the cell (I >> 2, J >> 2) at
@@ -785,6 +787,7 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int t
   lane_shift(a.y, a.lv);
   lane_shift(a.xc, a.lc);
   lane_shift(a.dot, a.ldot);
+  lane_shift(a.b64, a.lb64);
   const int n2 = 2 * a.n, L = n2 + 1;
   const int64_t N = a.L2;
   const int I0 = (t % tiles_x) * kC3W, J0 = (t / tiles_x) * RR;
@@ -1020,7 +1023,14 @@ __global__ void __launch_bounds__(64 * RR, 4) k_cheb3(Cheb3Args<T, TY> a0, int t
         }
         a.y[r] = (TY)y0;
         a.y[N + r] = (TY)y1;
-        if constexpr (DOT) by += (double)b0 * (double)(TY)y0 + (double)b1 * (double)(TY)y1;
+        if constexpr (DOT) {
+          if constexpr (std::is_same<T, double>::value) {   // b is the FP64 right-hand side
+            by += (double)b0 * (double)(TY)y0 + (double)b1 * (double)(TY)y1;
+          } else {
+            const double f0 = a.b64 ? a.b64[r] : (double)b0, f1 = a.b64 ? a.b64[N + r] : (double)b1;
+            by += f0 * (double)(TY)y0 + f1 * (double)(TY)y1;
+          }
+        }
       }
     }
   }
@@ -1045,7 +1055,8 @@ int cheb3_dot_count(int n) {
 
 template <typename T, typename TY>
 void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b, LP<T> d, LP<TY> y, T c2a, T c1b,
-                T c2b, T c1c, T c2c, hipStream_t st, int K, LP<const T> xc, LP<double> dot) {
+                T c2b, T c1c, T c2c, hipStream_t st, int K, LP<const T> xc, LP<double> dot,
+                LP<const double> b64) {
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
   FSI_REQUIRE(K >= 1 && K <= 65535, FSI_E_ARG, "lane count out of range");
   FSI_REQUIRE(!xc.p || (n % 2 == 0 && n >= 4), FSI_E_ARG, "a coarse correction needs an even fluid grid");
@@ -1055,7 +1066,10 @@ void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b,
   const int tiles = tx * ty, band = (tiles + kXcd - 1) / kXcd;
   const int64_t lv = common_stride({{x.p, x.s}, {b.p, b.s}, {d.p, d.s}, {y.p, y.s}}, K);
   FSI_REQUIRE(!dot.p || K == 1 || dot.s >= tiles, FSI_E_ARG, "lane stride of the tile sums too small");
-  Cheb3Args<T, TY> a{n, tab, x.p, b.p, d.p, y.p, L * L, c2a, c1b, c2b, c1c, c2c, lv, xc.p, xc.s, dot.p, dot.s};
+  FSI_REQUIRE(!b64.p || (dot.p && (K == 1 || b64.s > 0) && !std::is_same<T, double>::value), FSI_E_ARG,
+              "an FP64 right-hand side only for the sums of the FP32 form");
+  Cheb3Args<T, TY> a{n, tab, x.p, b.p, d.p, y.p, L * L, c2a, c1b, c2b, c1c, c2c, lv, xc.p, xc.s, dot.p, dot.s,
+                     b64.p, b64.s};
   const dim3 grid((unsigned)(band * kXcd), (unsigned)K), block(64 * kC3R);
   if (xc.p && dot.p)
     hipLaunchKernelGGL((k_cheb3<T, kC3R, TY, true, true>), grid, block, 0, st, a, tx, tiles, band);
@@ -1069,13 +1083,13 @@ void cheb3_post(int n, const StencilTable<T> *tab, LP<const T> x, LP<const T> b,
 }
 template void cheb3_post<double, double>(int, const StencilTable<double> *, LP<const double>, LP<const double>,
                                          LP<double>, LP<double>, double, double, double, double, double, hipStream_t,
-                                         int, LP<const double>, LP<double>);
+                                         int, LP<const double>, LP<double>, LP<const double>);
 template void cheb3_post<float, float>(int, const StencilTable<float> *, LP<const float>, LP<const float>, LP<float>,
                                        LP<float>, float, float, float, float, float, hipStream_t, int,
-                                       LP<const float>, LP<double>);
+                                       LP<const float>, LP<double>, LP<const double>);
 template void cheb3_post<float, double>(int, const StencilTable<float> *, LP<const float>, LP<const float>,
                                         LP<float>, LP<double>, float, float, float, float, float, hipStream_t, int,
-                                        LP<const float>, LP<double>);
+                                        LP<const float>, LP<double>, LP<const double>);
 
 template <typename T>
 void cheb2_pre(int n, const StencilTable<T> *tab, LP<const T> b, LP<T> d, LP<T> x, T s, T c1a, T c2a, T c1b,

@@ -350,7 +350,11 @@ def test_gmres_fp32_ir(pair32):
 @pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
 def test_stencil_smoother_equals_csr(pair32, prec):
     """The matrix-free A_f products of the V-cycle give the same preconditioner as the
-    assembled blocks: after one or two inner steps (isolating the V-cycle) and converged."""
+    assembled blocks: after one or two inner steps (isolating the V-cycle) and converged.
+    At 32^2 the matrix-free cycle runs every fused launch against the CSR products and
+    separate transfers: the post-smoothing launch that adds the coarse correction, the
+    residual kept in LDS and restricted in one launch, and the one-launch tail (16^2, 8^2
+    and the dense 4^2 solve)."""
     print(f"[stencil vs csr prec={prec}]", flush=True)
     S, ctx, wl = pair32
     lay = S.lay
