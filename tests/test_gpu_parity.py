@@ -380,6 +380,42 @@ def test_stencil_smoother_equals_csr(pair32, prec):
         assert rel(out[(2000, fsi.SMOOTH_STENCIL)], zref) <= 1e-9
 
 
+@pytest.mark.parametrize("n", [24, 48])
+def test_multigrid_odd_coarsest(n):
+    """Grids of 3 x 2^k cells: the velocity hierarchy ends on the odd 3^2 level (dense
+    solve), the one-launch tail starts at 12^2 and the fused post-smoothing and
+    residual-restriction launches run on the levels above.  The matrix-free cycle equals the
+    CSR one after one and two inner steps, in FP64 and FP32, and the converged FP64 inner
+    solve equals the oracle's A11 solve."""
+    print(f"[odd coarsest n={n}]", flush=True)
+    wl = inputs.small_workload(n, 4, (0.5, 0.5), 0.2)
+    S, ctx, _ = make_pair(wl)
+    nf = S.lay.nf
+    rng = np.random.default_rng(41 + n)
+    r = S.random_rhs(0, rng.uniform(-1, 1, S.lay.N))
+    torch = torch_dev()
+    rd = to_dev(r)
+    for prec in (fsi.FP64, fsi.FP32):
+        for maxit in (1, 2):
+            out = {}
+            for kind in (fsi.SMOOTH_CSR, fsi.SMOOTH_STENCIL):
+                ctx.set_smoother(kind)
+                ctx.set_inner(1e-30, maxit)
+                zd = torch.zeros_like(rd)
+                ctx.apply_precond(rd, zd, fsi.PC_DIAG, prec)
+                out[kind] = to_host(zd)
+            d = rel(out[fsi.SMOOTH_STENCIL], out[fsi.SMOOTH_CSR])
+            print(f"  prec {prec} maxit {maxit}: rel diff {d:.2e}", flush=True)
+            assert d <= (1e-12 if prec == fsi.FP64 else 1e-5)
+    ctx.set_smoother(fsi.SMOOTH_STENCIL)
+    ctx.set_inner(1e-13, 2000)
+    zd = torch.zeros_like(rd)
+    ctx.apply_precond(rd, zd, fsi.PC_DIAG, fsi.FP64)
+    assert rel(to_host(zd)[:nf], S.apply_A11_inv(r[:nf])) <= 1e-9
+    ctx.set_inner(-1.0, 1000)
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
 def test_graph_replays_equal_eager(pair32, prec):
     """The captured preconditioner graph, replayed many times with different inputs and
