@@ -123,9 +123,7 @@ template <typename T>
 void p2_prolong_add(int nf, LP<const T> xc, LP<T> y, hipStream_t s, int K = 1);
 template <typename T>
 void p1_prolong_add(int nf, LP<const T> xc, LP<T> y, hipStream_t s, int K = 1);
-// bc = R r
-template <typename T>
-void p2_restrict(int nf, const P2RestrTable<T> *tab, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
+// bc = R r (pressure levels; the velocity levels restrict in resid_restrict)
 template <typename T>
 void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
 // The coarse end of a velocity V-cycle in one launch per system (mgtail.hip): levels

@@ -7,7 +7,8 @@
 //   P1 Chebyshev step   x, b, d read; d, y written           5 w
 //   first step          b read; d, x written                 3 w per component
 //   P2 prolongation-add fine y read and written, coarse x    (2 + 1/4) w per component
-//   P2 restriction      fine r read, coarse b written        (1 + 1/4) w per component
+//   (the P2 restriction runs with the residual in resid_restrict, stencil.hip; the P2
+//   restriction weights are built here)
 #include <cstring>
 
 #include "kernels.h"
@@ -233,63 +234,6 @@ void p2_prolong_add(int nf, LP<const T> xc, LP<T> y, hipStream_t s, int K) {
   FSI_CHECK_LAUNCH();
 }
 
-// bc = R r = P^T r over the interior fine nodes; Dirichlet coarse rows are zero.  A block
-// owns 256 coarse nodes of one coarse row: waves 0-1 the even columns, waves 2-3 the odd
-// ones, so the node class is uniform over a wave (scalar weight loads, compile-time offsets).
-template <typename T, int CLS>
-__device__ __forceinline__ void restrict_sum(const P2RestrTable<T> &tb, const T *r, int64_t Nf, int L, int nf,
-                                             int I, int J, T &s0, T &s1) {
-  constexpr RestrOffsets ro = restrict_offsets();
-  s0 = 0;
-  s1 = 0;
-#pragma unroll
-  for (int k = 0; k < kRestrCount[CLS]; ++k) {
-    const int I2 = I + ro.d[CLS][k][0], J2 = J + ro.d[CLS][k][1];
-    if (I2 > 0 && J2 > 0 && I2 < 2 * nf && J2 < 2 * nf) {
-      const int64_t f = (int64_t)J2 * L + I2;
-      const T w = tb.w[CLS][k];
-      s0 = fma(w, r[f], s0);
-      s1 = fma(w, r[Nf + f], s1);
-    }
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_p2_restrict(int nf, const P2RestrTable<T> *__restrict__ tabp,
-                                                     LP<const T> rl, LP<T> bcl, int segs) {
-  const T *__restrict__ r = rl.at(blockIdx.y);
-  T *bc = bcl.at(blockIdx.y);
-  const int L = 2 * nf + 1, nc = nf / 2, Lc = 2 * nc + 1;
-  const int64_t Nf = (int64_t)L * L, Nc = (int64_t)Lc * Lc;
-  const int Jc = blockIdx.x / segs, seg = blockIdx.x % segs;
-  const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 128);
-  const int Ic = seg * 256 + 2 * ((int)threadIdx.x % 128) + half;
-  if (Ic >= Lc) return;
-  const int64_t q = (int64_t)Jc * Lc + Ic;
-  T s0 = 0, s1 = 0;
-  if (!on_p2_boundary(Ic, Jc, nc)) {
-    const P2RestrTable<T> &tb = *tabp;
-    const int I = 2 * Ic, J = 2 * Jc;
-    if (Jc & 1) {
-      if (half) restrict_sum<T, 3>(tb, r, Nf, L, nf, I, J, s0, s1);
-      else restrict_sum<T, 2>(tb, r, Nf, L, nf, I, J, s0, s1);
-    } else {
-      if (half) restrict_sum<T, 1>(tb, r, Nf, L, nf, I, J, s0, s1);
-      else restrict_sum<T, 0>(tb, r, Nf, L, nf, I, J, s0, s1);
-    }
-  }
-  bc[q] = s0;
-  bc[Nc + q] = s1;
-}
-
-template <typename T>
-void p2_restrict(int nf, const P2RestrTable<T> *tab, LP<const T> r, LP<T> bc, hipStream_t s, int K) {
-  const int Lc = nf + 1;
-  const int segs = (Lc + 255) / 256;
-  hipLaunchKernelGGL(k_p2_restrict<T>, dim3((unsigned)(Lc * segs), K), dim3(256), 0, s, nf, tab, r, bc, segs);
-  FSI_CHECK_LAUNCH();
-}
-
 // Host: the restriction weights do not depend on the level (nested uniform refinement),
 // so they are read off at interior coarse nodes of a 16 x 16 fine grid.
 void p2_restrict_tables(P2RestrTable<double> &t64, P2RestrTable<float> &t32) {
@@ -408,7 +352,6 @@ void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K) {
   template void p2_first<T>(int, const StencilTable<T> *, LP<const T>, T, LP<T>, LP<T>, hipStream_t, int);   \
   template void p2_prolong_add<T>(int, LP<const T>, LP<T>, hipStream_t, int);                               \
   template void p1_prolong_add<T>(int, LP<const T>, LP<T>, hipStream_t, int);                               \
-  template void p2_restrict<T>(int, const P2RestrTable<T> *, LP<const T>, LP<T>, hipStream_t, int);        \
   template void p1_restrict<T>(int, LP<const T>, LP<T>, hipStream_t, int);
 
 FSI_LATTICE_INST(double)
