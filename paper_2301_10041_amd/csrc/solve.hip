@@ -722,9 +722,7 @@ __global__ void k_ms_init(MinresState *st, double tol) {
 }
 
 // After the two dot products of an iteration: Givens rotation and the next coefficients.
-__global__ void k_ms_step(MinresState *st) {
-  if (threadIdx.x || blockIdx.x) return;
-  st += blockIdx.y;
+__device__ void ms_step(MinresState *st) {
   if (st->done != 0.0) {
     st->apply = 0.0;
     return;
@@ -753,6 +751,11 @@ __global__ void k_ms_step(MinresState *st) {
   st->s = beta > 0.0 ? 1.0 / beta : 0.0;
   st->c_r1 = beta > 0.0 ? -beta / oldb : 0.0;
   if (!(st->phibar > st->tol * st->beta1) || beta == 0.0 || !(alfa == alfa)) st->done = 1.0;
+}
+
+__global__ void k_ms_step(MinresState *st) {
+  if (threadIdx.x || blockIdx.x) return;
+  ms_step(st + blockIdx.y);
 }
 
 // v = s y
@@ -791,24 +794,26 @@ __global__ void k_ms_update(double *wn, const double *v, const double *w1, const
 }
 
 // alfa = sum of the per-tile parts of v . y (one block per lane, fixed order)
-__global__ void k_ms_alfa(const double *part, int n, MinresState *st) {
-  __shared__ double red[256 / kWave];
+__global__ void __launch_bounds__(1024) k_ms_alfa(const double *part, int n, MinresState *st) {
+  __shared__ double red[1024 / kWave];
   part += (int64_t)blockIdx.y * n;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  for (int i = threadIdx.x; i < n; i += 1024) acc += part[i];
   acc = wave_sum(acc);
   if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     double b = 0.0;
-    for (int k = 0; k < 256 / kWave; ++k) b += red[k];
+    for (int k = 0; k < 1024 / kWave; ++k) b += red[k];
     st[blockIdx.y].alfa = b;
   }
 }
 
 // beta^2 = the velocity tile sums, then the pressure block sums (one 1024-thread block per
-// lane, fixed order; lane k's sums at part + k lp, its state at st + k)
-__global__ void __launch_bounds__(1024) k_ms_beta(const double *part, int nu, int np, int64_t lp, MinresState *st) {
+// lane, fixed order; lane k's sums at part + k lp, its state at st + k), then the step
+// (ms_step) of that lane
+__global__ void __launch_bounds__(1024) k_ms_beta_step(const double *part, int nu, int np, int64_t lp,
+                                                       MinresState *st) {
   __shared__ double red[1024 / kWave];
   part += (int64_t)blockIdx.y * lp;
   double acc = 0.0;
@@ -820,6 +825,7 @@ __global__ void __launch_bounds__(1024) k_ms_beta(const double *part, int nu, in
     double b = 0.0;
     for (int k = 0; k < 1024 / kWave; ++k) b += red[k];
     st[blockIdx.y].beta2 = b;
+    ms_step(st + blockIdx.y);
   }
 }
 
@@ -878,7 +884,7 @@ static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st, int K) 
                      LP<const double>(b.y, nf), LP<double>(b.v, nf), LP<double>(b.r1, nf),
                      LP<const double>(&st->s, kMsDoubles), LP<const double>(&st->c_r1, kMsDoubles),
                      LP<double>(c.ms_part.p, tiles), s, K);
-  hipLaunchKernelGGL(k_ms_alfa, dim3(1, K), dim3(256), 0, s, c.ms_part.p, tiles, st);
+  hipLaunchKernelGGL(k_ms_alfa, dim3(1, K), dim3(1024), 0, s, c.ms_part.p, tiles, st);
   hipLaunchKernelGGL(k_ms_axpy, dim3(g, K), dim3(256), 0, s, b.r1, b.r2, st, 1, nf);
   constexpr bool f32 = std::is_same<TA, float>::value;
   if (tile_dot_ok(c, f32)) {   // beta^2 = r . z from the launches that write z
@@ -897,13 +903,13 @@ static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st, int K) 
     } else {
       a11_precond<double>(c, b.r1, b.y, K, nullptr, nullptr, dot);
     }
-    hipLaunchKernelGGL(k_ms_beta, dim3(1, K), dim3(1024), 0, s, c.ms_dot.p, nu, kPresDotBlocks, ld, st);
+    hipLaunchKernelGGL(k_ms_beta_step, dim3(1, K), dim3(1024), 0, s, c.ms_dot.p, nu, kPresDotBlocks, ld, st);
   } else {
     a11_precond_on64<TA>(c, b.r1, b.y, K);
     dot_l(LP<const double>(b.r1, nf), LP<const double>(b.y, nf), nf, LP<double>(dv + 1, kMsDoubles), c.ms_red.p, s,
           K);
+    hipLaunchKernelGGL(k_ms_step, dim3(1, K), dim3(1), 0, s, st);
   }
-  hipLaunchKernelGGL(k_ms_step, dim3(1, K), dim3(1), 0, s, st);
   hipLaunchKernelGGL(k_ms_update, dim3(g, K), dim3(256), 0, s, b.w1, b.v, b.w2, b.w, b.x, st, nf);
   FSI_CHECK_LAUNCH();
 }
