@@ -129,7 +129,8 @@ void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
 // The coarse end of a velocity V-cycle in one launch per system (mgtail.hip): levels
 // lv[0..nlev) (n <= kTailMaxN cells, each the next one's fine level) and the coarsest
 // level's dense inverse.  Vectors in LDS (offsets in T): level l's b at lv[l].off and x
-// right after it (2 N each, N = (2n + 1)^2), one shared direction at offd (2 N of lv[0]),
+// right after it (2 N each, N = tail_plane_entries(n)), one shared direction at offd (2 N of
+// lv[0]),
 // the coarsest b at offc and x after it (m each), then the stencil coefficients and
 // inverse diagonal blocks of every level (kTailTab each) and the restriction weights
 // (kTailRw) at offt; lds = the total.  b and x in device memory: the first level's
@@ -140,6 +141,9 @@ constexpr int kTailTab = 184 + 16, kTailRw = 25 + 9 + 9 + 9;
 constexpr int kTailRs[4] = {0, 25, 34, 43};       // class offsets of the restriction weights
 // Largest LDS block of the tail launch on the current device (queried once, at most 160 KiB).
 int tail_lds_limit();
+// Entries per component of a smoothing level of n cells in the tail's LDS: even and odd
+// column planes of n + 1 columns and 2n + 1 rows.
+inline int tail_plane_entries(int n) { return 2 * (2 * n + 1) * (n + 1); }
 template <typename T>
 struct TailLevel {
   int n, off;

@@ -11,7 +11,11 @@
 // diagonal: the parities of the lattice coordinates), so the stencil of a wave is uniform;
 // on a level of n <= 16 cells every class has at most 256 interior nodes, one per thread.
 // Dirichlet nodes hold 0 in every vector (a restricted right-hand side vanishes there and
-// the identity rows keep it so), so only interior nodes are stepped.  The stencil
+// the identity rows keep it so), so only interior nodes are stepped.  A smoothing level's
+// vectors lie in LDS as even and odd column planes ([component][parity][row][column / 2]):
+// the lanes of a wave (one class, consecutive nodes of a row) then read consecutive words,
+// without the bank conflicts of the stride-2 row-major order.  The coarsest level keeps the
+// row-major order of its dense inverse.  The stencil
 // coefficients, inverse diagonal blocks and restriction weights are copied to LDS first:
 // read from device memory at every step they cost a scalar-cache round trip per few
 // neighbours.
@@ -26,6 +30,18 @@ namespace {
 
 constexpr int kTailThreads = 1024, kTailGroup = kTailThreads / 4;
 
+// LDS layout of a smoothing level of n cells: planes of n + 1 columns
+struct TailGrid {
+  int L, HW, N;   // lattice side 2n + 1, plane width, entries per component (2 L HW)
+  __device__ int at(int I, int J) const { return ((I & 1) * L + J) * HW + (I >> 1); }
+};
+__device__ __forceinline__ TailGrid tail_grid(int n) {
+  const int L = 2 * n + 1;
+  return TailGrid{L, n + 1, 2 * L * (n + 1)};
+}
+// floor(v / 2) for the small offsets of the stencils (v >= -4)
+__host__ __device__ constexpr int half_floor(int v) { return (v + 4) / 2 - 2; }
+
 // interior node of class c (I parity c & 1, J parity c >> 1) number i on a level of n cells
 __device__ __forceinline__ bool class_node(int c, int i, int n, int &I, int &J) {
   const int pi = c & 1, pj = c >> 1;
@@ -36,17 +52,21 @@ __device__ __forceinline__ bool class_node(int c, int i, int n, int &I, int &J) 
   return true;
 }
 
-// (A_f x) at node index idx of a lattice of side L (x component-major, N nodes); cf: the
-// level's coefficients in LDS (class CLS at kTailCoef[CLS], four per entry)
+// (A_f x) at the node of LDS index idx (layout g); cf: the level's coefficients in LDS
+// (class CLS at kTailCoef[CLS], four per entry).  A neighbour (dI, dJ) of a node of column
+// parity P lies in plane (P + dI) mod 2, floor((P + dI) / 2) columns over.
 template <typename T, int CLS>
-__device__ __forceinline__ void tail_product(const T *cf, const T *x, int N, int L, int idx, T &s0, T &s1) {
+__device__ __forceinline__ void tail_product(const T *cf, const T *x, const TailGrid &g, int idx, T &s0, T &s1) {
   constexpr StencilOffsets so = stencil_offsets();
   constexpr CrossZero cz = cross_zero();
+  constexpr int P = CLS & 1;
+  const int N = g.N;
   s0 = 0;
   s1 = 0;
 #pragma unroll
   for (int k = 0; k < kStencilCount[CLS]; ++k) {
-    const int o = idx + so.d[CLS][k][1] * L + so.d[CLS][k][0];
+    const int dI = so.d[CLS][k][0], dJ = so.d[CLS][k][1];
+    const int o = idx + ((((P + dI) & 1) - P) * g.L + dJ) * g.HW + half_floor(P + dI);
     const T y0 = x[o], y1 = x[N + o];
     const T *ck = cf + kTailCoef[CLS] + 4 * k;
     const T c0 = ck[0], c1 = ck[1], c2 = ck[2], c3 = ck[3];
@@ -61,57 +81,60 @@ __device__ __forceinline__ void tail_product(const T *cf, const T *x, int N, int
 }
 
 template <typename T>
-__device__ __forceinline__ void class_product(int c, const T *cf, const T *x, int N, int L, int idx, T &s0, T &s1) {
+__device__ __forceinline__ void class_product(int c, const T *cf, const T *x, const TailGrid &g, int idx, T &s0,
+                                              T &s1) {
   switch (c) {   // uniform over the wave
-    case 0: tail_product<T, 0>(cf, x, N, L, idx, s0, s1); break;
-    case 1: tail_product<T, 1>(cf, x, N, L, idx, s0, s1); break;
-    case 2: tail_product<T, 2>(cf, x, N, L, idx, s0, s1); break;
-    default: tail_product<T, 3>(cf, x, N, L, idx, s0, s1); break;
+    case 0: tail_product<T, 0>(cf, x, g, idx, s0, s1); break;
+    case 1: tail_product<T, 1>(cf, x, g, idx, s0, s1); break;
+    case 2: tail_product<T, 2>(cf, x, g, idx, s0, s1); break;
+    default: tail_product<T, 3>(cf, x, g, idx, s0, s1); break;
   }
 }
 
 // restriction sum at coarse node (Ic, Jc) of class CLS from the fine residual r (weights
 // rw in LDS, class CLS at kTailRs[CLS])
 template <typename T, int CLS>
-__device__ __forceinline__ void tail_restrict(const T *rw, const T *r, int N, int L, int Ic, int Jc, T &s0, T &s1) {
+__device__ __forceinline__ void tail_restrict(const T *rw, const T *r, const TailGrid &g, int Ic, int Jc, T &s0,
+                                              T &s1) {
   constexpr RestrOffsets ro = restrict_offsets();
+  const int N = g.N;
   s0 = 0;
   s1 = 0;
-  const int c = 2 * Jc * L + 2 * Ic;
+  const int c = 2 * Jc * g.HW + Ic;   // fine (2 Ic, 2 Jc): even plane
 #pragma unroll
   for (int k = 0; k < kRestrCount[CLS]; ++k) {
-    const int o = c + ro.d[CLS][k][1] * L + ro.d[CLS][k][0];
+    const int dI = ro.d[CLS][k][0], dJ = ro.d[CLS][k][1];
+    const int o = c + ((dI & 1) * g.L + dJ) * g.HW + half_floor(dI);
     const T w = rw[kTailRs[CLS] + k];
     s0 = fma(w, r[o], s0);
     s1 = fma(w, r[N + o], s1);
   }
 }
 
-// coarse quadratic at fine node (I, J) (coarse lattice side Lc, Nc nodes): the six P2
-// basis values of the coarse cell's triangle at the local position, in the order vertices
-// 0, 1, 2, edges 01, 12, 20 (exact in float)
+// coarse quadratic at fine node (I, J): the six P2 basis values of the coarse cell's
+// triangle at the local position, in the order vertices 0, 1, 2, edges 01, 12, 20 (exact in
+// float).  The coarse vector xc is a smoothing level (layout gc) or, when natural, the
+// coarsest level in row-major order (side gc.L, gc.N nodes per component).
 template <typename T>
-__device__ __forceinline__ void tail_prolong(const T *xc, int Nc, int Lc, int I, int J, T &s0, T &s1) {
-  const int A = I & 3, B = J & 3;
-  const int base = 2 * (J >> 2) * Lc + 2 * (I >> 2);
+__device__ __forceinline__ void tail_prolong(const T *xc, const TailGrid &gc, bool natural, int I, int J, T &s0,
+                                             T &s1) {
+  const int A = I & 3, B = J & 3, Ib = 2 * (I >> 2), Jb = 2 * (J >> 2);
   const bool lo = A >= B;
   const float xi = 0.25f * (float)A, eta = 0.25f * (float)B;
   const float l0 = lo ? 1.0f - xi : 1.0f - eta, l1 = lo ? xi - eta : xi, l2 = lo ? eta : eta - xi;
   const float phi[6] = {l0 * (2.0f * l0 - 1.0f), l1 * (2.0f * l1 - 1.0f), l2 * (2.0f * l2 - 1.0f),
                         4.0f * l0 * l1,         4.0f * l1 * l2,         4.0f * l2 * l0};
-  const int off[6] = {0,
-                      lo ? 2 : 2 * Lc + 2,
-                      lo ? 2 * Lc + 2 : 2 * Lc,
-                      lo ? 1 : Lc + 1,
-                      lo ? Lc + 2 : 2 * Lc + 1,
-                      Lc + (lo ? 1 : 0)};
+  const int di[6] = {0, 2, lo ? 2 : 0, 1, lo ? 2 : 1, lo ? 1 : 0};
+  const int dj[6] = {0, lo ? 0 : 2, 2, lo ? 0 : 1, lo ? 1 : 2, 1};
   s0 = 0;
   s1 = 0;
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const T w = (T)phi[q];
-    s0 = fma(w, xc[base + off[q]], s0);
-    s1 = fma(w, xc[Nc + base + off[q]], s1);
+    const int Ic = Ib + di[q], Jc = Jb + dj[q];
+    const int k = natural ? Jc * gc.L + Ic : gc.at(Ic, Jc);
+    s0 = fma(w, xc[k], s0);
+    s1 = fma(w, xc[gc.N + k], s1);
   }
 }
 
@@ -149,30 +172,30 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
   T *d = sm + a.offd;   // the direction (then residual) of the level being smoothed
   {                     // right-hand side of the first level (interior nodes)
     const TailLevel<T> &L0 = a.lv[0];
-    const int L = 2 * L0.n + 1, N = L * L;
+    const TailGrid g = tail_grid(L0.n);
+    const int NG = g.L * g.L;   // nodes per component in device memory (row-major)
     T *b = sm + L0.off;
-    for (int c = 0; c < 4; ++c) {
-      int I, J;
-      if (grp == c && class_node(c, gi, L0.n, I, J)) {
-        const int k = J * L + I;
-        b[k] = bg[k];
-        b[N + k] = bg[N + k];
-      }
+    int I, J;
+    if (class_node(grp, gi, L0.n, I, J)) {
+      const int k = g.at(I, J), kg = J * g.L + I;
+      b[k] = bg[kg];
+      b[g.N + k] = bg[NG + kg];
     }
   }
   __syncthreads();
   // one Chebyshev step on level l from x (first: c1 = 0, the direction is not read)
   auto cheb_step = [&](int l, bool first, T c1, T c2) {
     const TailLevel<T> &lv = a.lv[l];
-    const int L = 2 * lv.n + 1, N = L * L;
+    const TailGrid g = tail_grid(lv.n);
+    const int N = g.N;
     T *b = sm + lv.off, *x = b + 2 * N;
     int I, J;
     const bool mine = class_node(grp, gi, lv.n, I, J);
-    const int k = J * L + I;
+    const int k = mine ? g.at(I, J) : 0;
     T x0 = 0, x1 = 0, d0 = 0, d1 = 0;
     if (mine) {
       T s0, s1;
-      class_product<T>(grp, coefs(l), x, N, L, k, s0, s1);
+      class_product<T>(grp, coefs(l), x, g, k, s0, s1);
       const T r0 = b[k] - s0, r1 = b[N + k] - s1;
       const T *di = dinv(l) + 4 * grp;
       const T z0 = di[0] * r0 + di[1] * r1, z1 = di[2] * r0 + di[3] * r1;
@@ -193,12 +216,13 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
   // descent: pre-smoothing, residual, restriction
   for (int l = 0; l < a.nlev; ++l) {
     const TailLevel<T> &lv = a.lv[l];
-    const int L = 2 * lv.n + 1, N = L * L;
+    const TailGrid g = tail_grid(lv.n);
+    const int N = g.N;
     T *b = sm + lv.off, *x = b + 2 * N;
     {   // first step from zero: x = d = s D^{-1} b
       int I, J;
       if (class_node(grp, gi, lv.n, I, J)) {
-        const int k = J * L + I;
+        const int k = g.at(I, J);
         const T *di = dinv(l) + 4 * grp;
         const T b0 = b[k], b1 = b[N + k];
         const T z0 = lv.s * (di[0] * b0 + di[1] * b1), z1 = lv.s * (di[2] * b0 + di[3] * b1);
@@ -211,29 +235,31 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
     {   // residual over the direction (not read again before the post-smoothing)
       int I, J;
       if (class_node(grp, gi, lv.n, I, J)) {
-        const int k = J * L + I;
+        const int k = g.at(I, J);
         T s0, s1;
-        class_product<T>(grp, coefs(l), x, N, L, k, s0, s1);
+        class_product<T>(grp, coefs(l), x, g, k, s0, s1);
         d[k] = b[k] - s0;
         d[N + k] = b[N + k] - s1;
       }
     }
     __syncthreads();
     {   // restriction into the next level's right-hand side (interior coarse nodes)
-      const int nc = lv.n / 2, Lc = lv.n + 1, Nc = Lc * Lc;
-      T *bc = (l + 1 < a.nlev) ? sm + a.lv[l + 1].off : sm + a.offc;
+      const int nc = lv.n / 2, Lc = lv.n + 1;
+      const bool coarsest = l + 1 == a.nlev;   // row-major, as its dense inverse
+      const TailGrid gc = coarsest ? TailGrid{Lc, 0, Lc * Lc} : tail_grid(nc);
+      T *bc = coarsest ? sm + a.offc : sm + a.lv[l + 1].off;
       int Ic, Jc;
       if (class_node(grp, gi, nc, Ic, Jc)) {
-        const int k = Jc * Lc + Ic;
+        const int k = coarsest ? Jc * Lc + Ic : gc.at(Ic, Jc);
         T s0, s1;
         switch (grp) {
-          case 0: tail_restrict<T, 0>(rw, d, N, L, Ic, Jc, s0, s1); break;
-          case 1: tail_restrict<T, 1>(rw, d, N, L, Ic, Jc, s0, s1); break;
-          case 2: tail_restrict<T, 2>(rw, d, N, L, Ic, Jc, s0, s1); break;
-          default: tail_restrict<T, 3>(rw, d, N, L, Ic, Jc, s0, s1); break;
+          case 0: tail_restrict<T, 0>(rw, d, g, Ic, Jc, s0, s1); break;
+          case 1: tail_restrict<T, 1>(rw, d, g, Ic, Jc, s0, s1); break;
+          case 2: tail_restrict<T, 2>(rw, d, g, Ic, Jc, s0, s1); break;
+          default: tail_restrict<T, 3>(rw, d, g, Ic, Jc, s0, s1); break;
         }
         bc[k] = s0;
-        bc[Nc + k] = s1;
+        bc[gc.N + k] = s1;
       }
     }
     __syncthreads();
@@ -268,15 +294,18 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
   // ascent: coarse correction, post-smoothing
   for (int l = a.nlev - 1; l >= 0; --l) {
     const TailLevel<T> &lv = a.lv[l];
-    const int L = 2 * lv.n + 1, N = L * L;
+    const TailGrid g = tail_grid(lv.n);
+    const int N = g.N;
     T *b = sm + lv.off, *x = b + 2 * N;
-    const int Lc = lv.n + 1, Nc = Lc * Lc;
-    const T *xc = (l + 1 < a.nlev) ? sm + a.lv[l + 1].off + 2 * Nc : sm + a.offc + a.m;
+    const int Lc = lv.n + 1;
+    const bool coarsest = l + 1 == a.nlev;
+    const TailGrid gc = coarsest ? TailGrid{Lc, 0, Lc * Lc} : tail_grid(lv.n / 2);
+    const T *xc = coarsest ? sm + a.offc + a.m : sm + a.lv[l + 1].off + 2 * gc.N;
     int I, J;
     if (class_node(grp, gi, lv.n, I, J)) {
-      const int k = J * L + I;
+      const int k = g.at(I, J);
       T s0, s1;
-      tail_prolong<T>(xc, Nc, Lc, I, J, s0, s1);
+      tail_prolong<T>(xc, gc, coarsest, I, J, s0, s1);
       x[k] += s0;
       x[N + k] += s1;
     }
@@ -285,10 +314,15 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
     for (int j = 0; j + 1 < a.degree; ++j) cheb_step(l, false, lv.c1[j], lv.c2[j]);
     (void)b;
   }
-  {   // result of the first level, Dirichlet nodes included (0)
-    const int L = 2 * a.lv[0].n + 1, N = L * L;
-    const T *x = sm + a.lv[0].off + 2 * N;
-    for (int i = tid; i < 2 * N; i += kTailThreads) xg[i] = x[i];
+  {   // result of the first level in row-major order, Dirichlet nodes included (0)
+    const TailGrid g = tail_grid(a.lv[0].n);
+    const int NG = g.L * g.L;
+    const T *x = sm + a.lv[0].off + 2 * g.N;
+    for (int i = tid; i < NG; i += kTailThreads) {
+      const int k = g.at(i % g.L, i / g.L);
+      xg[i] = x[k];
+      xg[NG + i] = x[g.N + k];
+    }
   }
 }
 

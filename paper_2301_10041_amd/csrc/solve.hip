@@ -391,7 +391,7 @@ static bool tail_args(Mg &mg, int l, int degree, const T *b, T *x, int64_t ls, T
     TailLevel<T> &t = a.lv[k];
     t.n = L.n;
     t.off = off;
-    off += 4 * (int)L.nodes;
+    off += 4 * tail_plane_entries(L.n);
     t.tab = stab<T>(L);
     // the coefficients of chebyshev_stencil on [lmax / 15, lmax]
     const double lmax = L.lmax, lmin = L.lmax / 15.0;
@@ -406,7 +406,7 @@ static bool tail_args(Mg &mg, int l, int degree, const T *b, T *x, int64_t ls, T
     }
   }
   a.offd = off;
-  off += 2 * (int)mg.lv[l].nodes;
+  off += 2 * tail_plane_entries(mg.lv[l].n);
   a.offc = off;
   a.m = (int)mg.ncoarse;
   FSI_REQUIRE(a.m == 2 * (int)mg.lv[last].nodes, FSI_E_STATE, "coarsest level size");
