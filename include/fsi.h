@@ -300,7 +300,9 @@ int fsi_set_graphs(fsi_ctx *ctx, int enable);
  * the last direction is not stored when no single step follows; 8 w N2 when one does),
  * in FP32 with three steps (4 w + 16) N2 (y is stored straight into the FP64
  * preconditioner output); with three or more steps the launch also reads the coarse
- * correction, 2 w N2c (N2c = (n + 1)^2 nodes of the next level); CSR form
+ * correction, 2 w N2c (N2c = (n + 1)^2 nodes of the next level).  Inside the inner MINRES
+ * the FP32 launch also reads the FP64 residual for its tile sums of r . z (16 N2 bytes,
+ * not counted here: the figure is that of the smoothing itself); CSR form
  * nnz (4 w + 4) + N2 (4 + 14 w) + 4 (values and column indices once; per node the row
  * pointer, x, b, d read and written, the inverse 2x2 diagonal block and y). */
 int fsi_profile(fsi_ctx *ctx, int enable);
