@@ -18,6 +18,7 @@
 // precision (FP32) runs the preconditioner's multigrid and Schur parts in FP32; the
 // FP32_IR variant also applies the operator in FP32 inside the Arnoldi process and wraps
 // the cycles in iterative refinement on the FP64 residual.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -1030,6 +1031,150 @@ static const double *cs_solve(Ctx &c, const double *b, double *scratch, int step
                                  steps, b, t, t2, d, true, c.stream);
 }
 
+// The same closed form for every system of a batch in one launch: one 1024-thread block per
+// system.  A_s and C_s act on each component alone, so the two components run one after the
+// other: the iterate of the current Chebyshev solve lies in LDS as two buffers of Ns entries
+// (read one, write the other), a thread's rows (at most kA22Rows) keep their right-hand side
+// and direction in registers, and the CSR rows (the shared pattern of A_s and C_s) come from
+// device memory.  Same steps as a22_solve: t = C_s^{-1} r_lam, z_X = -dt t,
+// u = r_X - A_s z_X, z_lam = -C_s^{-1} u.
+constexpr int kA22Threads = 1024, kA22Rows = 7, kA22Nnz = 8;
+struct A22Lane {
+  const int *rp, *col;
+  const double *as, *cs, *csd;     // A_s and C_s values on the S pattern; C_s inverse diagonal
+  const double *rX, *rl;
+  double *zX, *zl;
+  int ns;
+  double dt;
+};
+struct A22Args {
+  A22Lane lane[FSI_MAX_LANES];
+  int steps;
+  double theta, delta;             // Chebyshev interval of D^{-1} C_s: centre and half width
+};
+
+// sum over the CSR row [k0, k1) of val[e] x[col[e]]: the first kA22Nnz entries unrolled (their
+// loads issued together), the rest (rare on a triangle mesh) in order after them
+__device__ __forceinline__ double a22_row(const int *col, const double *val, const double *x, int k0, int k1) {
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < kA22Nnz; ++u)
+    if (k0 + u < k1) s += val[k0 + u] * x[col[k0 + u]];
+  for (int e = k0 + kA22Nnz; e < k1; ++e) s += val[e] * x[col[e]];
+  return s;
+}
+
+__global__ void __launch_bounds__(kA22Threads) k_a22_lanes(A22Args a) {
+  extern __shared__ double a22_x[];   // two buffers of ns entries
+  const A22Lane &L = a.lane[blockIdx.y];
+  const int ns = L.ns, tid = threadIdx.x;
+  int k0[kA22Rows], k1[kA22Rows];     // this thread's CSR rows (the pattern of both matrices)
+#pragma unroll
+  for (int q = 0; q < kA22Rows; ++q) {
+    const int r = tid + kA22Threads * q;
+    k0[q] = r < ns ? L.rp[r] : 0;
+    k1[q] = r < ns ? L.rp[r + 1] : 0;
+  }
+  // C_s^{-1} b by the Chebyshev steps of chebyshev<double, 1, 2> from zero (b: this thread's
+  // rows); returns the buffer holding the result
+  auto cs_solve = [&](const double (&b)[kA22Rows]) -> double * {
+    const double sigma = a.theta / a.delta;
+    double rho = 1.0 / sigma;
+    double d[kA22Rows];
+    double *x = a22_x, *x2 = a22_x + ns;
+#pragma unroll
+    for (int q = 0; q < kA22Rows; ++q) {
+      const int r = tid + kA22Threads * q;
+      if (r < ns) {
+        const double z = 1.0 / a.theta * L.csd[r] * b[q];
+        d[q] = z;
+        x[r] = z;
+      }
+    }
+    __syncthreads();
+    for (int k = 1; k < a.steps; ++k) {
+      const double rho1 = 1.0 / (2.0 * sigma - rho);
+      const double c1 = rho1 * rho, c2 = 2.0 * rho1 / a.delta;
+      rho = rho1;
+#pragma unroll
+      for (int q = 0; q < kA22Rows; ++q) {
+        const int r = tid + kA22Threads * q;
+        if (r < ns) {
+          const double s0 = a22_row(L.col, L.cs, x, k0[q], k1[q]);
+          d[q] = c1 * d[q] + c2 * (L.csd[r] * (b[q] - s0));
+          x2[r] = x[r] + d[q];
+        }
+      }
+      __syncthreads();
+      double *t = x;
+      x = x2;
+      x2 = t;
+    }
+    return x;
+  };
+  for (int c = 0; c < 2; ++c) {
+    const int64_t o = (int64_t)c * ns;
+    double b[kA22Rows];
+#pragma unroll
+    for (int q = 0; q < kA22Rows; ++q) {
+      const int r = tid + kA22Threads * q;
+      b[q] = r < ns ? L.rl[o + r] : 0.0;
+    }
+    double *t = cs_solve(b);
+    // z_X = -dt t (stored; kept in the other buffer for the A_s rows)
+    double *zx = t == a22_x ? a22_x + ns : a22_x;
+#pragma unroll
+    for (int q = 0; q < kA22Rows; ++q) {
+      const int r = tid + kA22Threads * q;
+      if (r < ns) {
+        const double tv = t[r];
+        const double z = -L.dt * tv + 0.0 * tv;
+        L.zX[o + r] = z;
+        zx[r] = z;
+      }
+    }
+    __syncthreads();
+    // u = r_X - A_s z_X
+#pragma unroll
+    for (int q = 0; q < kA22Rows; ++q) {
+      const int r = tid + kA22Threads * q;
+      if (r < ns) b[q] = L.rX[o + r] - a22_row(L.col, L.as, zx, k0[q], k1[q]);
+    }
+    __syncthreads();   // every row has read z_X: the next solve starts over both buffers
+    const double *t2 = cs_solve(b);
+#pragma unroll
+    for (int q = 0; q < kA22Rows; ++q) {
+      const int r = tid + kA22Threads * q;
+      if (r < ns) L.zl[o + r] = -t2[r];
+    }
+    __syncthreads();   // the buffers are free for the next component
+  }
+}
+
+// LDS grant of the batched closed form (device limit, at most 160 KiB), set once
+static int a22_lds_limit() {
+  static int limit = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 65536;
+    v = v < 65536 ? v : v > 163840 ? 163840 : v;
+    if (v > 65536 &&
+        hipFuncSetAttribute((const void *)k_a22_lanes, hipFuncAttributeMaxDynamicSharedMemorySize, v) != hipSuccess) {
+      (void)hipGetLastError();
+      v = 65536;
+    }
+    return v;
+  }();
+  return limit;
+}
+
+// Whether a system's solid block fits the one-launch form
+static bool a22_fits(const Ctx &c) {
+  return c.Ns >= 1 && c.Ns <= (int64_t)kA22Threads * kA22Rows &&
+         (int64_t)2 * c.Ns * (int64_t)sizeof(double) <= a22_lds_limit();   // two buffers of Ns
+}
+
 // z2 = A22^{-1} r2 on [X | lam] (4 Ns entries)
 static void a22_solve(Ctx &c, const double *rX, const double *rl, double *zX, double *zl, int steps) {
   hipStream_t s = c.stream;
@@ -1125,6 +1270,14 @@ void apply_precond_lanes(Ctx &c, Ctx *const *cs, int K, int pc, int prec, const 
   int its[FSI_MAX_LANES];
   if (prec == FSI_FP64) minres_a11<double>(c, r, z, K, tol, c.inner_maxit, its);
   else minres_a11<float>(c, r, z, K, tol, c.inner_maxit, its);
+  // the solid blocks: every system's closed form in one launch when all fit, else one by one
+  bool fit = true;
+  int ns_max = 0;
+  for (int k = 0; k < K; ++k) {
+    fit = fit && a22_fits(*cs[k]);
+    ns_max = std::max(ns_max, (int)cs[k]->Ns);
+  }
+  A22Args aa{};
   for (int k = 0; k < K; ++k) {
     Ctx &ck = *cs[k];
     ck.inner_its_total += its[k];
@@ -1138,7 +1291,18 @@ void apply_precond_lanes(Ctx &c, Ctx *const *cs, int K, int pc, int prec, const 
       spmv<double, 1, 2, SP_RESID>(ns, ck.Cf.rowptr.p, ck.Cf.col.p, ck.Cf.val.p, z[k], ck.N2, t, ns, s, rl);
       rl = t;
     }
-    a22_solve(ck, rX, rl, zX, zl, cs_steps(tol));
+    if (fit)
+      aa.lane[k] = A22Lane{ck.S.rowptr.p, ck.S.col.p, ck.S.val.p, ck.Cs.p, ck.Cs_dinv.p, rX, rl, zX, zl, (int)ns, ck.dt};
+    else
+      a22_solve(ck, rX, rl, zX, zl, cs_steps(tol));
+  }
+  if (fit) {
+    aa.steps = cs_steps(tol);
+    aa.theta = 0.5 * (2.0 + 0.5);   // C_s interval [1/2, 2] (cs_solve)
+    aa.delta = 0.5 * (2.0 - 0.5);
+    hipLaunchKernelGGL(k_a22_lanes, dim3(1, (unsigned)K), dim3(kA22Threads), (size_t)2 * ns_max * sizeof(double),
+                       c.stream, aa);
+    FSI_CHECK_LAUNCH();
   }
 }
 
