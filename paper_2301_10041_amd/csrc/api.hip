@@ -22,6 +22,7 @@ Ctx::~Ctx() {
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
   if (hpin) (void)hipHostFree(hpin);
+  if (bat_h) (void)hipHostFree(bat_h);
 }
 
 void Prof::begin(hipStream_t s) {

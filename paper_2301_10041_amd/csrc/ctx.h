@@ -130,6 +130,11 @@ struct Ctx {
   DevBuf<double> red;      // reduction partials
   DevBuf<double> dscal;    // device scalars
   double *hpin = nullptr;  // pinned host staging (hipHostMalloc)
+  // batched Arnoldi step (engine context): every system's dot products in one device buffer
+  // and one pinned host copy of them
+  DevBuf<double> bat_dh;
+  double *bat_h = nullptr;
+  size_t bat_h_n = 0;
   DevBuf<double> tmpN;     // N (operator/residual scratch)
   DevBuf<double> tmpS;     // 12 Ns (solid block scratch)
 

@@ -1323,6 +1323,62 @@ static void residual64(Ctx &c, const double *b, const double *x, double *r) {
   axpby(r, b, 1.0, -1.0, c.N, c.stream);
 }
 
+// The Gram-Schmidt reductions of one Arnoldi step for every system of a batch in one launch
+// each (lane = blockIdx.y): the same partition, order and arithmetic as multidot and
+// k_multiaxpy_sub on one system (red_blocks(n) chunks of the lane's own length), so each
+// system's numbers do not depend on the batch.
+struct ArnLane {
+  const double *V;   // Krylov basis (k vectors at stride n)
+  const double *w;   // current vector (w for the dots, updated in place by the axpy)
+  double *part;      // red_blocks(n) * k partial sums
+  double *h;         // k results
+  int64_t n;
+  int k, nb;
+};
+struct ArnArgs {
+  ArnLane l[FSI_MAX_LANES];
+};
+
+__global__ void __launch_bounds__(kRedBlock) k_arn_dot_part(ArnArgs a) {
+  const ArnLane &L = a.l[blockIdx.y];
+  if ((int)blockIdx.x >= L.nb) return;
+  const int64_t chunk = (L.n + L.nb - 1) / L.nb;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < L.n ? lo + chunk : L.n;
+  for (int i = 0; i < L.k; ++i) {
+    const double *v = L.V + (int64_t)i * L.n;
+    double s = 0.0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += kRedBlock) s += v[e] * L.w[e];
+    const double t = block_sum(s);
+    if (threadIdx.x == 0) L.part[(int64_t)i * L.nb + blockIdx.x] = t;
+  }
+}
+
+__global__ void k_arn_dot_final(ArnArgs a) {
+  const ArnLane &L = a.l[blockIdx.y];
+  const int i = blockIdx.x;
+  if (i >= L.k) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < L.nb; b += kWave) s += L.part[(int64_t)i * L.nb + b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) L.h[i] = s;
+}
+
+__global__ void k_arn_axpy_sub(ArnArgs a) {   // w -= sum_i h[i] V_i
+  const ArnLane &L = a.l[blockIdx.y];
+  double *w = const_cast<double *>(L.w);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L.n; e += (int64_t)gridDim.x * blockDim.x) {
+    double s = w[e];
+    for (int i = 0; i < L.k; ++i) s -= L.h[i] * L.V[(int64_t)i * L.n + e];
+    w[e] = s;
+  }
+}
+
+static void arn_dots(ArnArgs &a, int K, int kmax, int nbmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_arn_dot_part, dim3((unsigned)nbmax, (unsigned)K), dim3(kRedBlock), 0, s, a);
+  hipLaunchKernelGGL(k_arn_dot_final, dim3((unsigned)kmax, (unsigned)K), dim3(kWave), 0, s, a);
+  FSI_CHECK_LAUNCH();
+}
+
 // One system of a lockstep FGMRES solve: its context, vectors, statistics and the state
 // of its current restart cycle.
 struct GmLane {
@@ -1399,6 +1455,7 @@ void gmres_solve_lanes(Ctx *const *cs, int K, const fsi_solve_opts &o, const dou
     c.outer.w.reserve(N);
     c.outer.r.reserve(N);
     c.dscal.reserve(8 + 2 * (m + 1) + 1 + 64);
+    c.red.reserve((size_t)red_blocks(N) * (m + 1));   // Gram-Schmidt partial sums: no regrowth mid-solve
     c.inner_its_total = 0;
     L[k].c = &c;
     L[k].b = b[k];
@@ -1472,29 +1529,54 @@ void gmres_solve_lanes(Ctx *const *cs, int K, const fsi_solve_opts &o, const dou
       }
     if (pcs.empty()) break;
     apply_precond_lanes(c0, pcs.data(), (int)pcs.size(), o.pc, pc_prec, pr.data(), pz.data());
-    for (auto &l : L) {
-      if (l.state != GmLane::CYCLE) continue;
-      Ctx &c = *l.c;
-      const int64_t N = c.N;
-      const int j = l.j;
-      double *V = c.outer.V.p, *w = c.outer.w.p;
-      double *dh = c.dscal.p + 8;   // h1 (m+1), h2 (m+1), hn2
-      op_apply(c, op_prec, c.outer.Z.p + (int64_t)j * N, w);
-      multidot(V, N, j + 1, w, N, dh, c.red, s);
-      hipLaunchKernelGGL(k_multiaxpy_sub, dim3(vgrid(N)), dim3(256), 0, s, w, V, N, j + 1, dh, N);
-      multidot(V, N, j + 1, w, N, dh + (m + 1), c.red, s);
-      hipLaunchKernelGGL(k_multiaxpy_sub, dim3(vgrid(N)), dim3(256), 0, s, w, V, N, j + 1, dh + (m + 1), N);
-      multidot(w, 0, 1, w, N, dh + 2 * (m + 1), c.red, s);
-      FSI_CHECK_LAUNCH();
-      FSI_HIP(hipMemcpyAsync(c.hpin, dh, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    // the operator of every system, then classical Gram-Schmidt twice and the norm of w for
+    // all systems at once (h1 at 0, h2 at m + 1, |w|^2 at 2 (m + 1) of each system's slot),
+    // copied to the host in one transfer
+    const int stride = 2 * (m + 1) + 1;
+    std::vector<GmLane *> act;
+    for (auto &l : L)
+      if (l.state == GmLane::CYCLE) act.push_back(&l);
+    const int KA = (int)act.size();
+    c0.bat_dh.reserve((size_t)KA * stride);
+    if (c0.bat_h_n < (size_t)KA * stride) {
+      if (c0.bat_h) FSI_HIP(hipHostFree(c0.bat_h));
+      c0.bat_h = nullptr;
+      c0.bat_h_n = 0;
+      FSI_HIP(hipHostMalloc((void **)&c0.bat_h, (size_t)FSI_MAX_LANES * stride * sizeof(double),
+                            hipHostMallocDefault));
+      c0.bat_h_n = (size_t)FSI_MAX_LANES * stride;
     }
+    ArnArgs a1{}, a2{}, a3{};
+    int kmax = 1, nbmax = 1;
+    int64_t nmax = 1;
+    for (int q = 0; q < KA; ++q) {
+      Ctx &c = *act[q]->c;
+      const int64_t N = c.N;
+      const int j = act[q]->j, nb = red_blocks(N);
+      op_apply(c, op_prec, c.outer.Z.p + (int64_t)j * N, c.outer.w.p);
+      c.red.reserve((size_t)nb * (j + 1));
+      double *dh = c0.bat_dh.p + (int64_t)q * stride;
+      a1.l[q] = ArnLane{c.outer.V.p, c.outer.w.p, c.red.p, dh, N, j + 1, nb};
+      a2.l[q] = ArnLane{c.outer.V.p, c.outer.w.p, c.red.p, dh + (m + 1), N, j + 1, nb};
+      a3.l[q] = ArnLane{c.outer.w.p, c.outer.w.p, c.red.p, dh + 2 * (m + 1), N, 1, nb};
+      kmax = std::max(kmax, j + 1);
+      nbmax = std::max(nbmax, nb);
+      nmax = std::max(nmax, N);
+    }
+    arn_dots(a1, KA, kmax, nbmax, s);
+    hipLaunchKernelGGL(k_arn_axpy_sub, dim3(vgrid(nmax), (unsigned)KA), dim3(256), 0, s, a1);
+    arn_dots(a2, KA, kmax, nbmax, s);
+    hipLaunchKernelGGL(k_arn_axpy_sub, dim3(vgrid(nmax), (unsigned)KA), dim3(256), 0, s, a2);
+    arn_dots(a3, KA, 1, nbmax, s);
+    FSI_CHECK_LAUNCH();
+    FSI_HIP(hipMemcpyAsync(c0.bat_h, c0.bat_dh.p, (size_t)KA * stride * sizeof(double), hipMemcpyDeviceToHost, s));
     FSI_HIP(hipStreamSynchronize(s));
-    for (auto &l : L) {
-      if (l.state != GmLane::CYCLE) continue;
+    for (int q = 0; q < KA; ++q) {
+      GmLane &l = *act[q];
       Ctx &c = *l.c;
       const int64_t N = c.N;
       const int j = l.j;
-      const double *hp = c.hpin;
+      const double *hp = c0.bat_h + (int64_t)q * stride;
       double *hcol = &l.H[(size_t)j * (m + 1)];   // column j, rows 0..j+1
       for (int i = 0; i <= j; ++i) hcol[i] = hp[i] + hp[(m + 1) + i];
       const double hn = std::sqrt(hp[2 * (m + 1)] > 0 ? hp[2 * (m + 1)] : 0.0);
