@@ -779,6 +779,25 @@ __global__ void k_ms_axpy(double *y, const double *r, const MinresState *st, int
     y[o + i] += a * r[o + i];
 }
 
+// y -= (alfa s) r2 as k_ms_axpy (which = 1), then the FP32 copy of the first n32 entries
+// of y for the FP32 preconditioner (lane stride l32)
+__global__ void k_ms_axpy_f32(double *y, const double *r, const MinresState *st, int64_t n, float *y32, int64_t n32,
+                              int64_t l32) {
+  const MinresState &q = st[blockIdx.y];
+  const double a = -q.alfa * q.s;
+  const int64_t o = (int64_t)blockIdx.y * n;
+  y32 += (int64_t)blockIdx.y * l32;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = y[o + i];
+    if (a != 0.0) {
+      v += a * r[o + i];
+      y[o + i] = v;
+    }
+    if (i < n32) y32[i] = (float)v;
+  }
+}
+
 // wn = (v - e w1 - d w2) ginv;  x += phi wn   (skipped once converged)
 __global__ void k_ms_update(double *wn, const double *v, const double *w1, const double *w2, double *x,
                             const MinresState *st, int64_t n) {
@@ -886,18 +905,21 @@ static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st, int K) 
                      LP<const double>(&st->s, kMsDoubles), LP<const double>(&st->c_r1, kMsDoubles),
                      LP<double>(c.ms_part.p, tiles), s, K);
   hipLaunchKernelGGL(k_ms_alfa, dim3(1, K), dim3(1024), 0, s, c.ms_part.p, tiles, st);
-  hipLaunchKernelGGL(k_ms_axpy, dim3(g, K), dim3(256), 0, s, b.r1, b.r2, st, 1, nf);
   constexpr bool f32 = std::is_same<TA, float>::value;
-  if (tile_dot_ok(c, f32)) {   // beta^2 = r . z from the launches that write z
+  const bool dot_ok = tile_dot_ok(c, f32);
+  if (f32 && dot_ok)   // the three-term update also writes the FP32 copy the preconditioner reads
+    hipLaunchKernelGGL(k_ms_axpy_f32, dim3(g, K), dim3(256), 0, s, b.r1, b.r2, st, nf, c.outer.x32.p,
+                       K == 1 ? 2 * c.N2 : nf, nf);
+  else
+    hipLaunchKernelGGL(k_ms_axpy, dim3(g, K), dim3(256), 0, s, b.r1, b.r2, st, 1, nf);
+  if (dot_ok) {   // beta^2 = r . z from the launches that write z
     const int nu = cheb3_dot_count(c.n);
     const int64_t ld = nu + kPresDotBlocks;
     const LP<double> dot(c.ms_dot.p, ld);
     if constexpr (f32) {   // the same arithmetic as a11_precond_on64<float>, sums on FP64 r
       if (K == 1) {
-        convert(c.outer.x32.p, b.r1, 2 * c.N2, s);
         a11_precond<float>(c, c.outer.x32.p, nullptr, 1, b.r1, b.y, dot);
       } else {
-        convert_l(LP<float>(c.outer.x32.p, nf), LP<const double>(b.r1, nf), nf, s, K);
         a11_precond<float>(c, c.outer.x32.p, c.outer.y32.p, K, b.r1, nullptr, dot);
         convert_l(LP<double>(b.y, nf), LP<const float>(c.outer.y32.p, nf), nf, s, K);
       }
