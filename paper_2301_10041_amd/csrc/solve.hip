@@ -1366,12 +1366,33 @@ __global__ void __launch_bounds__(kRedBlock) k_arn_dot_part(ArnArgs a) {
   if ((int)blockIdx.x >= L.nb) return;
   const int64_t chunk = (L.n + L.nb - 1) / L.nb;
   const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < L.n ? lo + chunk : L.n;
-  for (int i = 0; i < L.k; ++i) {
-    const double *v = L.V + (int64_t)i * L.n;
-    double s = 0.0;
-    for (int64_t e = lo + threadIdx.x; e < hi; e += kRedBlock) s += v[e] * L.w[e];
-    const double t = block_sum(s);
-    if (threadIdx.x == 0) L.part[(int64_t)i * L.nb + blockIdx.x] = t;
+  // four basis vectors per pass over the chunk: w is read once per group and the four
+  // block sums share one barrier; every sum keeps the order of a single dot product
+  constexpr int G = 4;
+  __shared__ double ws[G][kRedBlock / kWave];
+  for (int i0 = 0; i0 < L.k; i0 += G) {
+    const int g = L.k - i0 < G ? L.k - i0 : G;   // uniform over the block
+    const double *v = L.V + (int64_t)i0 * L.n;
+    double s[G] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t e = lo + threadIdx.x; e < hi; e += kRedBlock) {
+      const double we = L.w[e];
+#pragma unroll
+      for (int q = 0; q < G; ++q)
+        if (q < g) s[q] += v[(int64_t)q * L.n + e] * we;
+    }
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const double t = wave_sum(s[q]);
+      if (lane == 0) ws[q][wv] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < g) {
+      double t = 0.0;
+      for (int k = 0; k < kRedBlock / kWave; ++k) t += ws[threadIdx.x][k];
+      L.part[(int64_t)(i0 + threadIdx.x) * L.nb + blockIdx.x] = t;
+    }
+    __syncthreads();
   }
 }
 

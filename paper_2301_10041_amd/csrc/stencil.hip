@@ -126,7 +126,8 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a0, int tiles_x,
   const int tid = threadIdx.x;
   const StencilTable<T> &tb = *a.tab;
   double ms_acc = 0.0;   // SP_A11 in MINRES: this thread's part of v . y
-  // epilogue operands of this thread's nodes (row-major, coalesced), loaded first
+  // epilogue operands of this thread's nodes (row-major, coalesced), loaded first; x only at
+  // Dirichlet nodes (the staged tile holds 0 there), the interior x comes from the tile
   constexpr int EIT = kTileR * kTileC / 256;
   T ex[EIT][2], eb[EIT][2], ed[EIT][2];
 #pragma unroll
@@ -135,8 +136,10 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a0, int tiles_x,
     ex[q][0] = ex[q][1] = eb[q][0] = eb[q][1] = ed[q][0] = ed[q][1] = 0;
     if (I <= n2 && J <= n2) {
       const int r = J * L + I;
-      ex[q][0] = a.x[r];
-      ex[q][1] = a.x[a.L2 + r];
+      if (I == 0 || J == 0 || I == n2 || J == n2) {
+        ex[q][0] = a.x[r];
+        ex[q][1] = a.x[a.L2 + r];
+      }
       if constexpr (MODE == SP_RESID || MODE == SP_CHEB) {
         eb[q][0] = a.b[r];
         eb[q][1] = a.b[a.L2 + r];
@@ -248,7 +251,8 @@ __global__ void __launch_bounds__(256) k_stencil(StencilArgs<T> a0, int tiles_x,
     if (I > n2 || J > n2) continue;
     const int r = J * L + I;
     const bool bnd = I == 0 || J == 0 || I == n2 || J == n2;
-    const T x0 = ex[q][0], x1 = ex[q][1];
+    const int xo = (j + 2) * kTW + (i + 2);   // the node in the staged tile
+    const T x0 = bnd ? ex[q][0] : X[0][xo], x1 = bnd ? ex[q][1] : X[1][xo];
     const T s0 = bnd ? x0 : S[0][e], s1 = bnd ? x1 : S[1][e];
     if constexpr (MODE == SP_APPLY) {
       a.y[r] = s0;
