@@ -61,7 +61,8 @@ size_t Ctx::device_bytes() const {
   size_t b = Af.bytes() + Mf.bytes() + B.bytes() + BT.bytes() + Mp.bytes() + Mp_dinv.bytes() +
              Mp_dinv32.bytes() + bnd.bytes();
   b += tri.bytes() + ref_xy.bytes() + ref_area.bytes() + n2e_ptr.bytes() + n2e.bytes() + S.bytes() +
-       Cs.bytes() + Cs32.bytes() + Cs_dinv.bytes() + Cs_dinv32.bytes();
+       Cs.bytes() + Cs32.bytes() + Cs_dinv.bytes() + Cs_dinv32.bytes() + s_ecol.bytes() + s_eas.bytes() +
+       s_ecs.bytes();
   b += Cf.bytes() + CfT.bytes() + cand_off.bytes() + piece_cnt.bytes() + pair_E.bytes() +
        pair_T.bytes() + piece_L.bytes() + e_piece.bytes() + cft_fill.bytes() + dflag.bytes() +
        cft_tcol.bytes() + cft_tval.bytes() + cft_long.bytes() + scan_tmp.bytes() + cf_defer.bytes();
@@ -83,7 +84,7 @@ static size_t estimate_bytes(int64_t n, int64_t ns, int64_t nt) {
   double fluid = zaf * (32 + 4 + 8 + 16) + 2 * zb * (16 + 4 + 8) + 9 * Np * 12 + 4 * (N2 + Np);
   double mg = fluid * 0.45 + 10 * N2 * 12 / 3;
   double krylov = 61 * N * 8 + 9 * (2 * N2 + Np) * 12 + 4 * N * 8;
-  double solid = ns * (7 * 12 * 2 + 200) + nt * 60 + 60 * ns * 12;
+  double solid = ns * (7 * 12 * 2 + 200 + 8 * 20) + nt * 60 + 60 * ns * 12;
   double cf = nt * 12 * (18 * 8 + 16) + 2 * 60 * ns * 12 + N2 * 8;
   // fixed work space (reduction partials, device scalars, pinned staging, small
   // buffers) and a 10% margin so that the estimate bounds the measured footprint

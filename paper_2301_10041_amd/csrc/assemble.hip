@@ -646,6 +646,20 @@ __global__ void k_asm_solid(int64_t ns, const int *__restrict__ n2e_ptr, const i
   }
 }
 
+// the transposed copy of the solid pattern and its two value arrays (one thread per row)
+__global__ void k_solid_ell(int64_t ns, int w, const int *rp, const int *col, const double *as, const double *cs,
+                            int *ecol, double *eas, double *ecs) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ns) return;
+  const int k0 = rp[r], k1 = rp[r + 1];
+  for (int u = 0; u < w; ++u) {
+    const bool in = k0 + u < k1;
+    ecol[(int64_t)u * ns + r] = in ? col[k0 + u] : (int)r;
+    eas[(int64_t)u * ns + r] = in ? as[k0 + u] : 0.0;
+    ecs[(int64_t)u * ns + r] = in ? cs[k0 + u] : 0.0;
+  }
+}
+
 __global__ void k_diag_inv(int64_t nrows, const int *rowptr, const int *col, const double *v,
                            double *dinv) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -725,6 +739,14 @@ void build_solid(Ctx &c) {
   c.Cs_dinv.reserve(ns);
   hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, c.S.rowptr.p,
                      c.S.col.p, c.Cs.p, c.Cs_dinv.p);
+  int ew = 1;
+  for (int64_t l = 0; l < ns; ++l) ew = std::max(ew, rp[l + 1] - rp[l]);
+  c.s_ew = ew;
+  c.s_ecol.reserve((size_t)ew * ns);
+  c.s_eas.reserve((size_t)ew * ns);
+  c.s_ecs.reserve((size_t)ew * ns);
+  hipLaunchKernelGGL(k_solid_ell, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, ew, c.S.rowptr.p, c.S.col.p,
+                     c.S.val.p, c.Cs.p, c.s_ecol.p, c.s_eas.p, c.s_ecs.p);
   FSI_CHECK_LAUNCH();
   c.Cs32.reserve(cols.size());
   convert(c.Cs32.p, c.Cs.p, (int64_t)cols.size(), s);

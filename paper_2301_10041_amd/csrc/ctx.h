@@ -95,6 +95,11 @@ struct Ctx {
   DevBuf<float> Cs32;
   DevBuf<double> Cs_dinv;  // 1 / diag(C_s)
   DevBuf<float> Cs_dinv32;
+  // the S pattern transposed for coalesced row-per-lane reads: entry u of row r at u Ns + r,
+  // rows padded to s_ew entries (column r, value 0); A_s and C_s values in the same order
+  DevBuf<int> s_ecol;
+  DevBuf<double> s_eas, s_ecs;
+  int s_ew = 0;
 
   // coupling (rebuilt by every fsi_assemble_coupling)
   bool have_cf = false;

@@ -1057,13 +1057,15 @@ static const double *cs_solve(Ctx &c, const double *b, double *scratch, int step
 // system.  A_s and C_s act on each component alone, so the two components run one after the
 // other: the iterate of the current Chebyshev solve lies in LDS as two buffers of Ns entries
 // (read one, write the other), a thread's rows (at most kA22Rows) keep their right-hand side
-// and direction in registers, and the CSR rows (the shared pattern of A_s and C_s) come from
-// device memory.  Same steps as a22_solve: t = C_s^{-1} r_lam, z_X = -dt t,
+// and direction in registers, and the rows of A_s and C_s come from device memory in the
+// transposed layout (entry u of row r at u Ns + r: the lanes of a wave, consecutive rows,
+// read consecutive words; the row-major CSR made every load of a wave touch a dozen or more
+// cache lines).  Same steps as a22_solve: t = C_s^{-1} r_lam, z_X = -dt t,
 // u = r_X - A_s z_X, z_lam = -C_s^{-1} u.
-constexpr int kA22Threads = 1024, kA22Rows = 7, kA22Nnz = 8;
+constexpr int kA22Threads = 1024, kA22Rows = 7, kA22Nnz = 7;
 struct A22Lane {
-  const int *rp, *col;
-  const double *as, *cs, *csd;     // A_s and C_s values on the S pattern; C_s inverse diagonal
+  const int *rp, *ecol;            // CSR row pointer (row lengths); transposed columns
+  const double *eas, *ecs, *csd;   // A_s and C_s values (transposed); C_s inverse diagonal
   const double *rX, *rl;
   double *zX, *zl;
   int ns;
@@ -1075,27 +1077,40 @@ struct A22Args {
   double theta, delta;             // Chebyshev interval of D^{-1} C_s: centre and half width
 };
 
-// sum over the CSR row [k0, k1) of val[e] x[col[e]]: the first kA22Nnz entries unrolled (their
-// loads issued together), the rest (rare on a triangle mesh) in order after them
-__device__ __forceinline__ double a22_row(const int *col, const double *val, const double *x, int k0, int k1) {
-  double s = 0.0;
+// s[q] = sum over the len[q] entries of row tid + kA22Threads q (in CSR order) of val x[col]
+// in the transposed layout (row stride ns): entry u of every row of the thread at a time (one
+// uniform base per entry, the loads of all rows issued together), the entries beyond
+// kA22Nnz (rare on a triangle mesh) in order after them
+__device__ __forceinline__ void a22_rows(const int *ecol, const double *eval, const double *x, int tid, int ns,
+                                         const int (&len)[kA22Rows], double (&s)[kA22Rows]) {
 #pragma unroll
-  for (int u = 0; u < kA22Nnz; ++u)
-    if (k0 + u < k1) s += val[k0 + u] * x[col[k0 + u]];
-  for (int e = k0 + kA22Nnz; e < k1; ++e) s += val[e] * x[col[e]];
-  return s;
+  for (int q = 0; q < kA22Rows; ++q) s[q] = 0.0;
+#pragma unroll
+  for (int u = 0; u < kA22Nnz; ++u) {
+    const int *cu = ecol + (size_t)u * ns;
+    const double *vu = eval + (size_t)u * ns;
+#pragma unroll
+    for (int q = 0; q < kA22Rows; ++q) {
+      const unsigned r = (unsigned)(tid + kA22Threads * q);
+      if (u < len[q]) s[q] += vu[r] * x[cu[r]];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kA22Rows; ++q) {
+    const size_t r = (size_t)(tid + kA22Threads * q);
+    for (int u = kA22Nnz; u < len[q]; ++u) s[q] += eval[(size_t)u * ns + r] * x[ecol[(size_t)u * ns + r]];
+  }
 }
 
 __global__ void __launch_bounds__(kA22Threads) k_a22_lanes(A22Args a) {
   extern __shared__ double a22_x[];   // two buffers of ns entries
   const A22Lane &L = a.lane[blockIdx.y];
   const int ns = L.ns, tid = threadIdx.x;
-  int k0[kA22Rows], k1[kA22Rows];     // this thread's CSR rows (the pattern of both matrices)
+  int len[kA22Rows];                  // lengths of this thread's rows (the pattern of both matrices)
 #pragma unroll
   for (int q = 0; q < kA22Rows; ++q) {
     const int r = tid + kA22Threads * q;
-    k0[q] = r < ns ? L.rp[r] : 0;
-    k1[q] = r < ns ? L.rp[r + 1] : 0;
+    len[q] = r < ns ? L.rp[r + 1] - L.rp[r] : 0;
   }
   // C_s^{-1} b by the Chebyshev steps of chebyshev<double, 1, 2> from zero (b: this thread's
   // rows); returns the buffer holding the result
@@ -1118,11 +1133,17 @@ __global__ void __launch_bounds__(kA22Threads) k_a22_lanes(A22Args a) {
       const double rho1 = 1.0 / (2.0 * sigma - rho);
       const double c1 = rho1 * rho, c2 = 2.0 * rho1 / a.delta;
       rho = rho1;
+      // the row stride, opaque to the compiler within the step: the entry addresses are
+      // formed in the step instead of being held, all of them, across the steps
+      int nss = ns;
+      asm volatile("" : "+s"(nss));
+      double sr[kA22Rows];
+      a22_rows(L.ecol, L.ecs, x, tid, nss, len, sr);
 #pragma unroll
       for (int q = 0; q < kA22Rows; ++q) {
         const int r = tid + kA22Threads * q;
         if (r < ns) {
-          const double s0 = a22_row(L.col, L.cs, x, k0[q], k1[q]);
+          const double s0 = sr[q];
           d[q] = c1 * d[q] + c2 * (L.csd[r] * (b[q] - s0));
           x2[r] = x[r] + d[q];
         }
@@ -1157,10 +1178,14 @@ __global__ void __launch_bounds__(kA22Threads) k_a22_lanes(A22Args a) {
     }
     __syncthreads();
     // u = r_X - A_s z_X
+    {
+      double sr[kA22Rows];
+      a22_rows(L.ecol, L.eas, zx, tid, ns, len, sr);
 #pragma unroll
-    for (int q = 0; q < kA22Rows; ++q) {
-      const int r = tid + kA22Threads * q;
-      if (r < ns) b[q] = L.rX[o + r] - a22_row(L.col, L.as, zx, k0[q], k1[q]);
+      for (int q = 0; q < kA22Rows; ++q) {
+        const int r = tid + kA22Threads * q;
+        if (r < ns) b[q] = L.rX[o + r] - sr[q];
+      }
     }
     __syncthreads();   // every row has read z_X: the next solve starts over both buffers
     const double *t2 = cs_solve(b);
@@ -1193,7 +1218,7 @@ static int a22_lds_limit() {
 
 // Whether a system's solid block fits the one-launch form
 static bool a22_fits(const Ctx &c) {
-  return c.Ns >= 1 && c.Ns <= (int64_t)kA22Threads * kA22Rows &&
+  return c.Ns >= 1 && c.Ns <= (int64_t)kA22Threads * kA22Rows && c.s_ecol.p && c.s_ew >= 1 &&
          (int64_t)2 * c.Ns * (int64_t)sizeof(double) <= a22_lds_limit();   // two buffers of Ns
 }
 
@@ -1314,7 +1339,8 @@ void apply_precond_lanes(Ctx &c, Ctx *const *cs, int K, int pc, int prec, const 
       rl = t;
     }
     if (fit)
-      aa.lane[k] = A22Lane{ck.S.rowptr.p, ck.S.col.p, ck.S.val.p, ck.Cs.p, ck.Cs_dinv.p, rX, rl, zX, zl, (int)ns, ck.dt};
+      aa.lane[k] = A22Lane{ck.S.rowptr.p, ck.s_ecol.p, ck.s_eas.p, ck.s_ecs.p, ck.Cs_dinv.p, rX, rl, zX, zl, (int)ns,
+                           ck.dt};
     else
       a22_solve(ck, rX, rl, zX, zl, cs_steps(tol));
   }
