@@ -148,3 +148,42 @@ def test_batch_reports_nonconvergence_per_system():
         assert np.array_equal(states[k], ref[k]), k
     for c in ctxs:
         c.close()
+
+
+class FanSolid(inputs.Solid):
+    """A fan of k triangles around one centre node: the centre's row of the solid pattern
+    has k + 1 entries, more than a ring mesh ever has (at most 7)."""
+
+    def __init__(self, k, center, radius):
+        super().__init__(m=1, center=center, radius=radius)
+        self.k = k
+
+    def mesh(self):
+        a = 2 * np.pi * np.arange(self.k) / self.k
+        xy = np.concatenate([[self.center], np.stack([self.center[0] + self.radius * np.cos(a),
+                                                      self.center[1] + self.radius * np.sin(a)], axis=1)])
+        tri = np.array([[0, 1 + i, 1 + (i + 1) % self.k] for i in range(self.k)], dtype=np.int32)
+        return xy, tri
+
+
+def test_batch_high_valence_solid():
+    """Solids whose centre node has 12 or 16 neighbours (rows longer than the unrolled part of
+    the batched A22 closed form): a batch equals each step alone bitwise, and the result
+    matches the oracle's direct solve."""
+    torch_dev()
+    print("[batch high valence]", flush=True)
+    wls = [inputs.Workload(f"fan{k}", 16, [FanSolid(k, (0.5 + 0.01 * k, 0.47), 0.15)], dt=0.01, seed=700 + k)
+           for k in (12, 16)]
+    opts = fsi.Opts(prec=fsi.FP64, pc=fsi.PC_TRI, rtol=1e-10)
+    ref = [alone(wl, opts, False) for wl in wls]
+    ctxs = [fsi.Context.from_workload(wl) for wl in wls]
+    states, stats, rcs = batch(ctxs, wls, opts)
+    assert rcs == [fsi.FSI_OK] * 2
+    for k, wl in enumerate(wls):
+        assert np.array_equal(states[k], ref[k][0]), wl.name
+        S = system.FSISystem.from_workload(wl)
+        u = inputs.uniform(2 * S.lay.N2, wl.seed)
+        x_ref, _ = ostep.step(S, u, S.xy_ref, solver="direct")
+        assert rel(states[k], x_ref) <= 1e-7, wl.name
+    for c in ctxs:
+        c.close()
