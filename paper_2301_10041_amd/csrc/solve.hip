@@ -1387,6 +1387,19 @@ struct ArnArgs {
   ArnLane l[FSI_MAX_LANES];
 };
 
+// this thread's parts of V_q . w for G vectors V_q = v + q n over the chunk [lo, hi) (G a
+// compile-time count: no branch between the loads, which issue together)
+template <int G>
+__device__ __forceinline__ void arn_dot_group(const double *v, const double *w, int64_t n, int64_t lo, int64_t hi,
+                                              double (&s)[4]) {
+#pragma unroll 4
+  for (int64_t e = lo + threadIdx.x; e < hi; e += kRedBlock) {
+    const double we = w[e];
+#pragma unroll
+    for (int q = 0; q < G; ++q) s[q] += v[(int64_t)q * n + e] * we;
+  }
+}
+
 __global__ void __launch_bounds__(kRedBlock) k_arn_dot_part(ArnArgs a) {
   const ArnLane &L = a.l[blockIdx.y];
   if ((int)blockIdx.x >= L.nb) return;
@@ -1400,11 +1413,11 @@ __global__ void __launch_bounds__(kRedBlock) k_arn_dot_part(ArnArgs a) {
     const int g = L.k - i0 < G ? L.k - i0 : G;   // uniform over the block
     const double *v = L.V + (int64_t)i0 * L.n;
     double s[G] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t e = lo + threadIdx.x; e < hi; e += kRedBlock) {
-      const double we = L.w[e];
-#pragma unroll
-      for (int q = 0; q < G; ++q)
-        if (q < g) s[q] += v[(int64_t)q * L.n + e] * we;
+    switch (g) {
+      case 4: arn_dot_group<4>(v, L.w, L.n, lo, hi, s); break;
+      case 3: arn_dot_group<3>(v, L.w, L.n, lo, hi, s); break;
+      case 2: arn_dot_group<2>(v, L.w, L.n, lo, hi, s); break;
+      default: arn_dot_group<1>(v, L.w, L.n, lo, hi, s); break;
     }
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
 #pragma unroll
