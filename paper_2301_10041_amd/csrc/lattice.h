@@ -133,8 +133,10 @@ void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
 // lv[0]),
 // the coarsest b at offc and x after it (m each), then the stencil coefficients and
 // inverse diagonal blocks of every level (kTailTab each) and the restriction weights
-// (kTailRw) at offt; lds = the total.  b and x in device memory: the first level's
-// right-hand side and result (lane stride lb).
+// (kTailRw) at offt; the dense inverse of the coarsest level (m x m, row-major) at offm when
+// it fits the block's LDS, else offm = -1 and it is read from device memory; lds = the
+// total.  b and x in device memory: the first level's right-hand side and result (lane
+// stride lb).
 constexpr int kTailMax = 4, kTailDeg = 8, kTailMaxN = 16, kTailDenseMax = 6 * 64;
 constexpr int kTailCoef[4] = {0, 76, 112, 148};   // class offsets of 4 coefficients per entry
 constexpr int kTailTab = 184 + 16, kTailRw = 25 + 9 + 9 + 9;
@@ -155,7 +157,7 @@ template <typename T>
 struct TailArgs {
   int nlev, degree;
   TailLevel<T> lv[kTailMax];
-  int offd, offc, offt, m, lds;
+  int offd, offc, offt, offm, m, lds;
   const P2RestrTable<T> *rt;
   const T *cinv;
   const T *b;

@@ -146,6 +146,31 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
   const int tid = threadIdx.x, grp = __builtin_amdgcn_readfirstlane(tid / kTailGroup), gi = tid % kTailGroup;
   const T *bg = a.b + (int64_t)blockIdx.y * a.lb;
   T *xg = a.x + (int64_t)blockIdx.y * a.lb;
+  // device-memory operands of the start issued first, so that their latency overlaps the
+  // clearing of the vectors and the table copies: the dense inverse (when it goes to LDS,
+  // kPre entries per thread at once) and the first level's right-hand side (stored after
+  // the clearing barrier)
+  constexpr int kPre = 12;
+  const int mm = a.offm >= 0 ? a.m * a.m : 0;
+  T pre[kPre];
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) {
+    const int i = tid + kTailThreads * q;
+    pre[q] = i < mm ? a.cinv[i] : T(0);
+  }
+  T b0v = 0, b1v = 0;
+  int bk = -1;
+  {
+    const TailGrid g = tail_grid(a.lv[0].n);
+    const int NG = g.L * g.L;   // nodes per component in device memory (row-major)
+    int I, J;
+    if (class_node(grp, gi, a.lv[0].n, I, J)) {
+      const int kg = J * g.L + I;
+      bk = g.at(I, J);
+      b0v = bg[kg];
+      b1v = bg[NG + kg];
+    }
+  }
   for (int i = tid; i < a.offt; i += kTailThreads) sm[i] = T(0);
   for (int l = 0; l < a.nlev; ++l)   // coefficients (class-compact) and inverse diagonal blocks
     for (int i = tid; i < kTailTab; i += kTailThreads) {
@@ -165,22 +190,21 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
     const int c = i < kTailRs[1] ? 0 : i < kTailRs[2] ? 1 : i < kTailRs[3] ? 2 : 3;
     sm[a.offt + a.nlev * kTailTab + i] = a.rt->w[c][i - kTailRs[c]];
   }
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) {
+    const int i = tid + kTailThreads * q;
+    if (i < mm) sm[a.offm + i] = pre[q];
+  }
+  for (int i = tid + kTailThreads * kPre; i < mm; i += kTailThreads) sm[a.offm + i] = a.cinv[i];
   __syncthreads();
   const T *rw = sm + a.offt + a.nlev * kTailTab;
   auto coefs = [&](int l) { return (const T *)(sm + a.offt + l * kTailTab); };
   auto dinv = [&](int l) { return (const T *)(sm + a.offt + l * kTailTab + kTailCoef[3] + 4 * kStencilCount[3]); };
   T *d = sm + a.offd;   // the direction (then residual) of the level being smoothed
-  {                     // right-hand side of the first level (interior nodes)
-    const TailLevel<T> &L0 = a.lv[0];
-    const TailGrid g = tail_grid(L0.n);
-    const int NG = g.L * g.L;   // nodes per component in device memory (row-major)
-    T *b = sm + L0.off;
-    int I, J;
-    if (class_node(grp, gi, L0.n, I, J)) {
-      const int k = g.at(I, J), kg = J * g.L + I;
-      b[k] = bg[kg];
-      b[g.N + k] = bg[NG + kg];
-    }
+  if (bk >= 0) {        // right-hand side of the first level (interior nodes)
+    T *b = sm + a.lv[0].off;
+    b[bk] = b0v;
+    b[tail_grid(a.lv[0].n).N + bk] = b1v;
   }
   __syncthreads();
   // one Chebyshev step on level l from x (first: c1 = 0, the direction is not read)
@@ -265,30 +289,35 @@ __global__ void __launch_bounds__(kTailThreads) k_mg_tail(TailArgs<T> a) {
     __syncthreads();
   }
   {   // coarsest level: x = C^{-1} b, one wave per row (sums in double, as the dense kernel);
-      // a wave loads kRows rows at once (coalesced, one memory round trip per batch)
+      // a wave loads kRows rows at once (coalesced, one memory round trip per batch), from
+      // LDS when the inverse was copied there
     constexpr int kRows = 4, kSeg = kTailDenseMax / kWave, NW = kTailThreads / kWave;
     const T *b = sm + a.offc;
     T *x = sm + a.offc + a.m;
     const int w = tid / kWave, lane = tid % kWave;
-    for (int r0 = w; r0 < a.m; r0 += kRows * NW) {
-      T c[kRows][kSeg];
+    auto dense = [&](const T *cm) {
+      for (int r0 = w; r0 < a.m; r0 += kRows * NW) {
+        T c[kRows][kSeg];
 #pragma unroll
-      for (int q = 0; q < kRows; ++q)
+        for (int q = 0; q < kRows; ++q)
 #pragma unroll
-        for (int j = 0; j < kSeg; ++j) {
-          const int r = r0 + q * NW, k = lane + kWave * j;
-          c[q][j] = (r < a.m && k < a.m) ? a.cinv[(int64_t)r * a.m + k] : T(0);
+          for (int j = 0; j < kSeg; ++j) {
+            const int r = r0 + q * NW, k = lane + kWave * j;
+            c[q][j] = (r < a.m && k < a.m) ? cm[(int64_t)r * a.m + k] : T(0);
+          }
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < kSeg; ++j)
+            if (lane + kWave * j < a.m) s += (double)c[q][j] * (double)b[lane + kWave * j];
+          s = wave_sum(s);
+          if (lane == 0 && r0 + q * NW < a.m) x[r0 + q * NW] = (T)s;
         }
-#pragma unroll
-      for (int q = 0; q < kRows; ++q) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < kSeg; ++j)
-          if (lane + kWave * j < a.m) s += (double)c[q][j] * (double)b[lane + kWave * j];
-        s = wave_sum(s);
-        if (lane == 0 && r0 + q * NW < a.m) x[r0 + q * NW] = (T)s;
       }
-    }
+    };
+    if (a.offm >= 0) dense(sm + a.offm);
+    else dense(a.cinv);
   }
   __syncthreads();
   // ascent: coarse correction, post-smoothing

@@ -417,6 +417,12 @@ static bool tail_args(Mg &mg, int l, int degree, const T *b, T *x, int64_t ls, T
   off += nlev * kTailTab + kTailRw;
   a.lds = off;
   if ((int64_t)a.lds * (int64_t)sizeof(T) > tail_lds_limit()) return false;
+  // the dense inverse in LDS too when it fits (loaded with the tables at the start)
+  a.offm = -1;
+  if ((int64_t)(off + (int64_t)a.m * a.m) * (int64_t)sizeof(T) <= tail_lds_limit()) {
+    a.offm = off;
+    a.lds = off + a.m * a.m;
+  }
   a.rt = rtab<T>(mg);
   a.cinv = Pr<T>::cinv(mg);
   a.b = b;
