@@ -200,6 +200,31 @@ def _its_bound(its_oracle):
     return its_oracle + max(2, math.ceil(0.1 * its_oracle))
 
 
+@pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
+def test_gmres_degenerate_rhs(pair32, prec):
+    """b = 0: the solve returns x = 0 at once (converged, no Arnoldi step) whatever x held.
+    A non-finite b: FSI_E_NONFINITE with x untouched, and the context still solves after."""
+    print(f"[gmres degenerate rhs prec={prec}]", flush=True)
+    S, ctx, wl = pair32
+    torch = torch_dev()
+    N = ctx.sizes["N"]
+    b = torch.zeros(N, dtype=torch.float64, device="cuda")
+    x = torch.full_like(b, 3.0)
+    st = ctx.gmres_solve(b, x, fsi.Opts(prec=prec))
+    assert st["converged"] == 1 and st["its"] == 0
+    assert torch.count_nonzero(x).item() == 0
+    bad = to_dev(S.random_rhs(wl.seed))
+    bad[5] = float("nan")
+    with pytest.raises(fsi.FsiError) as e:
+        ctx.gmres_solve(bad, x, fsi.Opts(prec=prec))
+    assert e.value.code == fsi.FSI_E_NONFINITE
+    assert torch.count_nonzero(x).item() == 0
+    good = S.random_rhs(wl.seed)
+    st = ctx.gmres_solve(to_dev(good), x, fsi.Opts(prec=prec))
+    assert st["converged"] == 1 and st["relres_true"] <= 1e-8
+    assert rel(S.matrix() @ to_host(x), good) <= 1e-8 * 1.0001
+
+
 @pytest.mark.parametrize("pc", ["diag", "tri"])
 def test_gmres_small_case(pair32, pc):
     print(f"[gmres {pc}]", flush=True)
