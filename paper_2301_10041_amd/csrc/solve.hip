@@ -811,8 +811,29 @@ __global__ void k_ms_update(double *wn, const double *v, const double *w1, const
   if (q.apply == 0.0) return;
   const double e = q.e, d = q.d, g = q.ginv, phi = q.phi;
   const int64_t o = (int64_t)blockIdx.y * n;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ts = (int64_t)gridDim.x * blockDim.x;
+  const bool pairs = ((reinterpret_cast<uintptr_t>(wn + o) | reinterpret_cast<uintptr_t>(v + o) |
+                       reinterpret_cast<uintptr_t>(w1 + o) | reinterpret_cast<uintptr_t>(w2 + o) |
+                       reinterpret_cast<uintptr_t>(x + o)) & 15) == 0;   // uniform over the grid row
+  int64_t i0 = 0;
+  if (pairs) {   // 16-byte accesses, two entries per thread and pass, the same arithmetic
+    const int64_t np = n / 2;
+    for (int64_t p = t0; p < np; p += ts) {
+      const double2 vv = reinterpret_cast<const double2 *>(v + o)[p];
+      const double2 a1 = reinterpret_cast<const double2 *>(w1 + o)[p];
+      const double2 a2 = reinterpret_cast<const double2 *>(w2 + o)[p];
+      double2 xx = reinterpret_cast<const double2 *>(x + o)[p];
+      double2 w;
+      w.x = (vv.x - e * a1.x - d * a2.x) * g;
+      w.y = (vv.y - e * a1.y - d * a2.y) * g;
+      reinterpret_cast<double2 *>(wn + o)[p] = w;
+      xx.x += phi * w.x;
+      xx.y += phi * w.y;
+      reinterpret_cast<double2 *>(x + o)[p] = xx;
+    }
+    i0 = 2 * np;
+  }
+  for (int64_t i = i0 + t0; i < n; i += ts) {
     const double w = (v[o + i] - e * w1[o + i] - d * w2[o + i]) * g;
     wn[o + i] = w;
     x[o + i] += phi * w;
