@@ -120,6 +120,13 @@ typedef struct {
   int32_t inner_maxit;  /* inner MINRES steps per A11 solve (default 1000; 300 in FP32) */
   double cycle_rtol;    /* FSI_FP32_IR: residual reduction asked of each FGMRES cycle
                            (default 1e-5); ignored otherwise */
+  int32_t inner_mode;   /* 0 (default): A11^{-1} by the inner MINRES solve to inner_rtol, the
+                           block inverse of the preconditioners of Sec. 5.  1: a fixed-cost
+                           inexact A11^{-1}, one application of the inner solve's own
+                           preconditioner (velocity V-cycle; minus the Schur approximation on
+                           the pressure, the sign of the Schur complement of A11), no inner
+                           Krylov steps: cheaper outer steps, more of them.  Other values:
+                           FSI_E_ARG. */
 } fsi_solve_opts;
 
 typedef struct {

@@ -169,6 +169,7 @@ struct Ctx {
   int lanes = 1;
   double inner_rtol = -1.0;   // < 0: default per precision
   int inner_maxit = 1000;
+  int inner_mode = 0;         // 1: A11^{-1} by one application of its preconditioner (no MINRES)
   int64_t inner_its_total = 0;
 
   ~Ctx();

@@ -1061,6 +1061,25 @@ static void minres_a11(Ctx &c, const double *const *b, double *const *xout, int 
   }
 }
 
+// The fixed-cost inexact A11^{-1} of K systems (host arrays of device vectors): one
+// application of the MINRES preconditioner diag(MG(A_f), S~^{-1}), with the pressure part
+// negated (A11 = [A_f -B^T; -B 0] has the Schur complement -B A_f^{-1} B^T) except the pinned
+// entry, whose row of A11 is the identity.
+template <typename TA>
+static void a11_fixed(Ctx &c, const double *const *r, double *const *z, int K) {
+  hipStream_t s = c.stream;
+  const int64_t nf = 2 * c.N2 + c.Np, nv = 2 * c.N2 + 1;
+  const MsBufs b0 = ms_bufs(c, c.ms_x.p, 0);
+  for (int k = 0; k < K; ++k) convert(b0.r2 + k * nf, r[k], nf, s);
+  a11_precond_any<TA>(c, b0.r2, b0.y, K);
+  for (int k = 0; k < K; ++k) {
+    convert(z[k], b0.y + k * nf, nv, s);
+    hipLaunchKernelGGL(k_negate<double>, dim3(vgrid(nf - nv)), dim3(256), 0, s, z[k] + nv, b0.y + k * nf + nv,
+                       nf - nv);
+  }
+  FSI_CHECK_LAUNCH();
+}
+
 // ---------------------------------------------------------------- A22 closed form (FP64)
 // C_s^{-1} by Chebyshev-Jacobi steps on the interval [1/2, 2] of D^{-1} C_s (P1 mass matrix on
 // triangles): the error falls by 1/3 per step.  The solve is taken four orders of magnitude
@@ -1342,8 +1361,15 @@ void apply_precond_lanes(Ctx &c, Ctx *const *cs, int K, int pc, int prec, const 
   ensure_inner(c, prec, K);
   const double tol = inner_tol(c, prec);
   int its[FSI_MAX_LANES];
-  if (prec == FSI_FP64) minres_a11<double>(c, r, z, K, tol, c.inner_maxit, its);
-  else minres_a11<float>(c, r, z, K, tol, c.inner_maxit, its);
+  if (c.inner_mode == 1) {   // fixed cost: one application of the inner preconditioner
+    if (prec == FSI_FP64) a11_fixed<double>(c, r, z, K);
+    else a11_fixed<float>(c, r, z, K);
+    for (int k = 0; k < K; ++k) its[k] = 0;
+  } else if (prec == FSI_FP64) {
+    minres_a11<double>(c, r, z, K, tol, c.inner_maxit, its);
+  } else {
+    minres_a11<float>(c, r, z, K, tol, c.inner_maxit, its);
+  }
   // the solid blocks: every system's closed form in one launch when all fit, else one by one
   bool fit = true;
   int ns_max = 0;
@@ -1538,8 +1564,12 @@ void gmres_solve_lanes(Ctx *const *cs, int K, const fsi_solve_opts &o, const dou
   struct Restore {
     Ctx *c;
     double r;
-    int m;
-    ~Restore() { c->inner_rtol = r; c->inner_maxit = m; }
+    int m, mode;
+    ~Restore() {
+      c->inner_rtol = r;
+      c->inner_maxit = m;
+      c->inner_mode = mode;
+    }
   };
   std::vector<Restore> restore;
   restore.reserve(K);
@@ -1548,7 +1578,9 @@ void gmres_solve_lanes(Ctx *const *cs, int K, const fsi_solve_opts &o, const dou
     Ctx &c = *cs[k];
     FSI_REQUIRE(c.have_cf, FSI_E_STATE, "the solve needs C_f: call fsi_assemble_coupling first");
     FSI_REQUIRE(c.stream == s, FSI_E_STATE, "systems of one lockstep solve share one stream");
-    restore.push_back({&c, c.inner_rtol, c.inner_maxit});
+    FSI_REQUIRE(o.inner_mode == 0 || o.inner_mode == 1, FSI_E_ARG, "unknown inner mode");
+    restore.push_back({&c, c.inner_rtol, c.inner_maxit, c.inner_mode});
+    c.inner_mode = o.inner_mode;
     if (o.inner_rtol > 0) c.inner_rtol = o.inner_rtol;
     if (o.inner_maxit > 0) c.inner_maxit = o.inner_maxit;
     else if (prec == FSI_FP32) c.inner_maxit = std::min(c.inner_maxit, 300);

@@ -57,7 +57,7 @@ class CouplingInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double), ("pc", C.c_int32),
                 ("prec", C.c_int32), ("inner_rtol", C.c_double), ("inner_maxit", C.c_int32),
-                ("cycle_rtol", C.c_double)]
+                ("cycle_rtol", C.c_double), ("inner_mode", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -177,10 +177,11 @@ class Opts:
     inner_rtol: float = 0.0
     inner_maxit: int = 0
     cycle_rtol: float = 0.0
+    inner_mode: int = 0
 
     def c(self):
         return SolveOpts(self.restart, self.maxit, self.rtol, self.pc, self.prec, self.inner_rtol,
-                         self.inner_maxit, self.cycle_rtol)
+                         self.inner_maxit, self.cycle_rtol, self.inner_mode)
 
 
 def step_batch(ctxs, u_n, X_n, states, opts: Opts | None = None):

@@ -187,3 +187,37 @@ def test_batch_high_valence_solid():
         assert rel(states[k], x_ref) <= 1e-7, wl.name
     for c in ctxs:
         c.close()
+
+
+@pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
+def test_fixed_cost_inner_mode(prec):
+    """inner_mode = 1 (A11^{-1} by one application of its preconditioner, no inner MINRES):
+    the step converges to rtol with no inner steps and more outer steps, matches the oracle's
+    direct solve, and a batch equals each step alone bitwise; other modes are refused."""
+    torch_dev()
+    print(f"[fixed-cost inner mode prec={prec}]", flush=True)
+    wls = workloads(16, 3, seed=41)
+    opts = fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-10, inner_mode=1)
+    ref = [alone(wl, opts, False) for wl in wls]
+    base = alone(wls[0], fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-10), False)
+    for (x, st) in ref:
+        assert st["converged"] == 1 and st["inner_its"] == 0 and st["relres_true"] <= 1e-10
+    assert ref[0][1]["its"] > base[1]["its"]
+    ctxs = [fsi.Context.from_workload(wl) for wl in wls]
+    states, stats, rcs = batch(ctxs, wls, opts)
+    assert rcs == [fsi.FSI_OK] * 3
+    for k, wl in enumerate(wls):
+        assert np.array_equal(states[k], ref[k][0]), wl.name
+        assert stats[k]["its"] == ref[k][1]["its"]
+    S = system.FSISystem.from_workload(wls[0])
+    u = inputs.uniform(2 * S.lay.N2, wls[0].seed)
+    x_ref, _ = ostep.step(S, u, S.xy_ref, solver="direct")
+    assert rel(states[0], x_ref) <= 1e-7
+    u0, X0, s0 = inputs_of(wls[0], ctxs[0])
+    with pytest.raises(fsi.FsiError) as e:
+        ctxs[0].step(u0, X0, s0, fsi.Opts(prec=prec, inner_mode=2))
+    assert e.value.code == fsi.FSI_E_ARG
+    st = ctxs[0].step(u0, X0, s0, fsi.Opts(prec=prec, rtol=1e-10))   # the default mode again
+    assert st["inner_its"] > 0 and st["converged"] == 1
+    for c in ctxs:
+        c.close()
