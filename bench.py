@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-fixed-cost", action="store_true",
+                    help="skip the fixed-cost inexact A11 leg (inner_mode 1)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run 3 plain device copies of 2 GiB (counter calibration)")
     args = ap.parse_args()
@@ -212,6 +214,32 @@ def main():
             t_solve_ms=1e3 * sum(s["t_solve"] for s in stats) / len(stats),
             kernel=dict(launches=launches, avg_us=1e6 * avg_s, bytes_per_launch=bpl,
                         achieved_gbs=achieved))
+    # the fixed-cost inexact A11 (inner_mode 1: one application of the inner preconditioner,
+    # no inner MINRES), timed the same way; reported beside the method's configuration
+    fixed = {}
+    if not args.no_fixed_cost:
+        for prec in precs:
+            tag = "fp64" if prec == fsi.FP64 else "mixed"
+            opts = fsi.Opts(restart=30, rtol=1e-8, pc=pc, prec=prec, inner_mode=1)
+            u = u0.clone()
+            for k in range(args.warmup):
+                ctx.step(u, Xs[k], state, opts)
+                u.copy_(state[:2 * N2])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            stats = []
+            for k in range(args.warmup, total):
+                st = ctx.step(u, Xs[k], state, opts)
+                u.copy_(state[:2 * N2])
+                stats.append(st)
+                print(f"[bench fixed-cost {tag}] step {k}: its={st['its']} relres={st['relres_true']:.2e} "
+                      f"solve={st['t_solve']:.3f}s", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            dt_total = time.perf_counter() - t0
+            fixed[tag] = dict(value=float(f"{args.steps / dt_total:.6g}"),
+                              ms_per_step=round(1e3 * dt_total / args.steps, 2),
+                              its=[s["its"] for s in stats],
+                              relres_true=float(f"{max(s['relres_true'] for s in stats):.6g}"))
     main_tag = "fp64" if "fp64" in res else "mixed"
     m = res[main_tag]
     k = m["kernel"]
@@ -243,6 +271,10 @@ def main():
         out[tag] = {kk: (float(f"{v:.6g}") if isinstance(v, float) else v) for kk, v in r.items()}
     if "fp64" in res and "mixed" in res:
         out["mixed_speedup"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
+    if fixed:
+        out["fixed_cost_a11"] = dict(fixed, note="A11^{-1} by one application of its preconditioner "
+                                                 "(inner_mode 1), no inner MINRES: more outer steps than "
+                                                 "with the block inverses, so not the method's configuration")
     ctx.close()
     del state, Xs, u0
     torch.cuda.empty_cache()
