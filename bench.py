@@ -142,8 +142,8 @@ def main():
         print(json.dumps(cpu_baseline_leg(args.workload)))
         return 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
-        print("bench.py: multi-GPU runs are not part of this build (one GPU only)", file=sys.stderr)
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
+        print("bench.py: one GPU only (the multi-GPU partition is a design, not implemented)", file=sys.stderr)
         return 2
 
     import numpy as np
