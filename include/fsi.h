@@ -185,6 +185,26 @@ int fsi_sizes(const fsi_ctx *ctx, fsi_sizes_t *out);
  * more than 4,096 P2 lattice nodes. */
 int fsi_assemble_coupling(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *info);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * allocation): fsi_assemble_coupling without any device allocation or release.  It builds the
+ * same C_f(X^n) and C_f^T, bitwise, but carves every work array of the assembly (candidate
+ * offsets, piece counters, scan partials, the piece list with its local matrices, transpose
+ * staging and counters, deferred-row lists, error flags) from one static device array of
+ * FSI_COUPLING_SCRATCH_BYTES per GPU, whose address the library takes once per device in
+ * fsi_create.  Outputs go to the context's coupling storage: reserved by fsi_create and
+ * fsi_set_solid for 64 entries per solid node, grown only by fsi_assemble_coupling.
+ * Xn, info: as fsi_assemble_coupling.  The call synchronises the context's stream (it reads
+ * the piece and entry counts), like fsi_assemble_coupling.
+ * Errors: those of fsi_assemble_coupling, and FSI_E_CAPACITY when the work space exceeds the
+ * scratch array or C_f has more entries than the context's storage holds (nothing is
+ * allocated; the context then has no C_f until the next successful assembly).
+ * The scratch array is shared by every context on the GPU and keeps the last call's contents:
+ * calls that overlap on one GPU (other streams or host threads) race, so the caller
+ * serialises them.  fsi_export_pairs after this call returns FSI_E_STATE (the piece list stays
+ * in the scratch array). */
+#define FSI_COUPLING_SCRATCH_BYTES (32u << 20)
+int fsi_assemble_coupling_noalloc(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *info);
+
 /* (g1, 0, 0, g2) of eq. (matrix): g1 = (rho/dt) M_f u^n with boundary rows zero (u^n is
  * taken as zero on the boundary), g2 = -(1/dt) C_s X^n.  u_n: device 2 N2, X_n: device
  * 2 Ns, b: device N. */

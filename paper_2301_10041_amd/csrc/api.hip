@@ -150,6 +150,8 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     c.N = 2 * c.N2 + c.Np + 4 * ns;
     c.stream = (hipStream_t)hip_stream;
     c.budget = hbm_budget;
+    FSI_HIP(hipGetDevice(&c.device));
+    fsi::coupling_scratch_init(c.device);
     c.h_tri.assign(solid->tri, solid->tri + 3 * nt);
     c.h_xy.assign(solid->xy, solid->xy + 2 * ns);
     FSI_HIP(hipHostMalloc((void **)&c.hpin, 4096 * sizeof(double), hipHostMallocDefault));
@@ -170,6 +172,7 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     fsi::make_shadow(c.S, c.stream);
     c.tmpN.reserve(c.N);
     c.tmpS.reserve(12 * ns);
+    fsi::reserve_coupling(c);
     c.dscal.alloc(512);
     FSI_HIP(hipStreamSynchronize(c.stream));
     if (hbm_budget)
@@ -209,6 +212,7 @@ int fsi_set_solid(fsi_ctx *ctx, const fsi_solid_desc *solid) {
     fsi::make_shadow(c.S, c.stream);
     c.tmpN.reserve(c.N);
     c.tmpS.reserve(12 * ns);
+    fsi::reserve_coupling(c);
     FSI_HIP(hipStreamSynchronize(c.stream));
   });
 }
@@ -265,6 +269,19 @@ int fsi_assemble_coupling(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *inf
   return guarded(ctx, [&] {
     FSI_REQUIRE(Xn, FSI_E_ARG, "null X^n");
     fsi::assemble_coupling(ctx->c, Xn, info != nullptr);
+    if (info) {
+      FSI_HIP(hipStreamSynchronize(ctx->c.stream));
+      info->n_pairs = ctx->c.n_pairs;
+      info->nnz = ctx->c.Cf.nnz;
+    }
+  });
+}
+
+int fsi_assemble_coupling_noalloc(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *info) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    FSI_REQUIRE(Xn, FSI_E_ARG, "null X^n");
+    fsi::assemble_coupling_noalloc(ctx->c, Xn);
     if (info) {
       FSI_HIP(hipStreamSynchronize(ctx->c.stream));
       info->n_pairs = ctx->c.n_pairs;
@@ -431,6 +448,8 @@ int fsi_export_pairs(fsi_ctx *ctx, int32_t *E, int32_t *T, int64_t cap, int64_t 
   return guarded(ctx, [&] {
     Ctx &c = ctx->c;
     FSI_REQUIRE(c.have_cf, FSI_E_STATE, "call fsi_assemble_coupling first");
+    FSI_REQUIRE(c.pairs_kept, FSI_E_STATE,
+                "the allocation-free assembly keeps no piece list: call fsi_assemble_coupling");
     *count = c.n_pairs;
     int64_t m = std::min<int64_t>(cap, c.n_pairs);
     if (m > 0 && E) FSI_HIP(hipMemcpyAsync(E, c.pair_E.p, m * 4, hipMemcpyDeviceToHost, c.stream));

@@ -23,6 +23,8 @@
 // area from vertex 0 exceeds 5e-11 h^2.  This file is compiled with -ffp-contract=off so
 // that no product is fused into an addition.
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "ctx.h"
 #include "kernels.h"
@@ -502,74 +504,131 @@ static int read_int(const int *d, hipStream_t s) {
   return h;
 }
 
-static void check_flags(Ctx &c) {
-  int f = read_int(c.dflag.p, c.stream);
-  if (f) fill(c.dflag.p, 1, 0, c.stream);
+static void check_flags(int *flag, hipStream_t s) {
+  int f = read_int(flag, s);
+  if (f) fill(flag, 1, 0, s);
   FSI_REQUIRE(!(f & DF_MESH), FSI_E_MESH, "X^n maps a solid triangle to a degenerate/inverted triangle or outside [0,1]^2");
   FSI_REQUIRE(!(f & DF_CAP), FSI_E_CAPACITY, "coupling pieces around one solid node span more than 4096 P2 nodes");
 }
 
-void assemble_coupling(Ctx &c, const double *Xn, bool) {
+// Where one assembly keeps its work arrays and finds its outputs.
+//  GrowWork: the context's grow-only buffers (fsi_assemble_coupling).
+//  ArenaWork: consecutive 256-byte aligned pieces of the per-device static array below
+//  (fsi_assemble_coupling_noalloc); the outputs must fit the context's coupling storage.
+struct GrowWork {
+  Ctx &c;
+  int *flags() {
+    if (!c.dflag.p) {
+      c.dflag.alloc(4);
+      fill(c.dflag.p, 4, 0, c.stream);
+    }
+    return c.dflag.p;
+  }
+  template <typename T>
+  T *work(DevBuf<T> &b, int64_t n, const char *) {
+    b.reserve((size_t)n);
+    return b.p;
+  }
+  int *scan(int64_t n) {
+    c.scan_tmp.reserve((size_t)scan_tmp_len(n));
+    return c.scan_tmp.p;
+  }
+  template <typename T>
+  T *out(DevBuf<T> &b, int64_t n, const char *) {
+    b.reserve((size_t)n);
+    return b.p;
+  }
+};
+
+struct ArenaWork {
+  Ctx &c;
+  unsigned char *base;
+  size_t cap, used;
+  template <typename T>
+  T *carve(int64_t n, const char *what) {
+    const size_t bytes = (((size_t)(n > 0 ? n : 1) * sizeof(T)) + 255) & ~(size_t)255;
+    FSI_REQUIRE(used + bytes <= cap, FSI_E_CAPACITY,
+                std::string("allocation-free coupling assembly: the work space (") + what + " and before it: " +
+                    std::to_string(used + bytes) + " bytes) exceeds the " + std::to_string(cap >> 20) +
+                    " MiB scratch array; use fsi_assemble_coupling");
+    T *p = (T *)(base + used);
+    used += bytes;
+    return p;
+  }
+  int *flags() {
+    int *f = carve<int>(4, "error flags");
+    fill(f, 4, 0, c.stream);   // the array keeps the previous call's contents
+    return f;
+  }
+  template <typename T>
+  T *work(DevBuf<T> &, int64_t n, const char *what) { return carve<T>(n, what); }
+  int *scan(int64_t n) { return carve<int>(scan_tmp_len(n), "scan partials"); }
+  template <typename T>
+  T *out(DevBuf<T> &b, int64_t n, const char *what) {
+    FSI_REQUIRE(b.p && (int64_t)b.n >= n, FSI_E_CAPACITY,
+                std::string("allocation-free coupling assembly: ") + what + " needs " + std::to_string(n) +
+                    " entries, the context's coupling storage holds " + std::to_string(b.p ? b.n : 0) +
+                    "; fsi_assemble_coupling grows it");
+    return b.p;
+  }
+};
+
+template <typename Work>
+static void assemble(Ctx &c, const double *Xn, Work &w) {
   hipStream_t s = c.stream;
   const int64_t nt = c.Nt, ns = c.Ns;
   const int n = c.n;
-  DevBuf<int> &tmp = c.scan_tmp;   // grow-only: a per-call buffer would free (and synchronise) every step
-  if (!c.dflag.p) {
-    c.dflag.alloc(4);
-    fill(c.dflag.p, 4, 0, s);
-  }
   c.have_cf = false;
-  c.cand_off.reserve(nt + 1);
-  hipLaunchKernelGGL(k_cand_count, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, ns, n, Xn, c.tri.p,
-                     c.cand_off.p, c.dflag.p);
+  c.pairs_kept = false;
+  int *flag = w.flags();
+  int *cand_off = w.work(c.cand_off, nt + 1, "candidate offsets");
+  hipLaunchKernelGGL(k_cand_count, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, ns, n, Xn, c.tri.p, cand_off,
+                     flag);
   FSI_CHECK_LAUNCH();
-  scan_excl(c.cand_off.p, c.cand_off.p, nt, tmp, s);
-  check_flags(c);
-  int ncand = read_int(c.cand_off.p + nt, s);
+  scan_excl(cand_off, cand_off, nt, w.scan(nt), s);
+  check_flags(flag, s);
+  const int ncand = read_int(cand_off + nt, s);
   c.n_cand = ncand;
-  c.piece_cnt.reserve(ncand + 1);
-  hipLaunchKernelGGL(k_clip_count, dim3(grid_for(ncand, 128)), dim3(128), 0, s, (int64_t)ncand, nt,
-                     ns, n, Xn, c.tri.p, c.cand_off.p, c.piece_cnt.p);
+  int *piece_off = w.work(c.piece_cnt, (int64_t)ncand + 1, "piece counters");
+  hipLaunchKernelGGL(k_clip_count, dim3(grid_for(ncand, 128)), dim3(128), 0, s, (int64_t)ncand, nt, ns, n, Xn,
+                     c.tri.p, cand_off, piece_off);
   FSI_CHECK_LAUNCH();
-  scan_excl(c.piece_cnt.p, c.piece_cnt.p, ncand, tmp, s);
-  int npieces = read_int(c.piece_cnt.p + ncand, s);
+  scan_excl(piece_off, piece_off, ncand, w.scan(ncand), s);
+  const int npieces = read_int(piece_off + ncand, s);
   c.n_pairs = npieces;
-  c.pair_E.reserve(npieces);
-  c.pair_T.reserve(npieces);
-  c.piece_L.reserve(18 * (size_t)npieces);
-  hipLaunchKernelGGL(k_clip_emit, dim3(grid_for(ncand, 128)), dim3(128), 0, s, (int64_t)ncand, nt,
-                     ns, n, Xn, c.tri.p, c.ref_area.p, c.cand_off.p, c.piece_cnt.p, c.pair_E.p,
-                     c.pair_T.p, c.piece_L.p);
-  c.e_piece.reserve(nt + 1);
-  hipLaunchKernelGGL(k_elem_piece_off, dim3(grid_for(nt + 1, 256)), dim3(256), 0, s, nt,
-                     c.cand_off.p, c.piece_cnt.p, c.e_piece.p);
+  int *pair_E = w.work(c.pair_E, npieces, "piece list");
+  int *pair_T = w.work(c.pair_T, npieces, "piece list");
+  double *piece_L = w.work(c.piece_L, 18 * (int64_t)npieces, "piece matrices");
+  hipLaunchKernelGGL(k_clip_emit, dim3(grid_for(ncand, 128)), dim3(128), 0, s, (int64_t)ncand, nt, ns, n, Xn,
+                     c.tri.p, c.ref_area.p, cand_off, piece_off, pair_E, pair_T, piece_L);
+  int *e_piece = w.work(c.e_piece, nt + 1, "element piece offsets");
+  hipLaunchKernelGGL(k_elem_piece_off, dim3(grid_for(nt + 1, 256)), dim3(256), 0, s, nt, cand_off, piece_off,
+                     e_piece);
   FSI_CHECK_LAUNCH();
   // rows of C_f
   Csr &Cf = c.Cf;
   Cf.nrows = ns;
   Cf.ncols = c.N2;
   Cf.width = 1;
-  Cf.rowptr.reserve(ns + 1);
-  c.cf_defer.reserve(ns + 1);
-  fill(c.cf_defer.p, 1, 0, s);
-  hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 0, ns, n, c.n2e_ptr.p, c.n2e.p,
-                     c.e_piece.p, c.pair_T.p, c.piece_L.p, Cf.rowptr.p, nullptr, nullptr, nullptr,
-                     c.dflag.p, c.cf_defer.p);
-  hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 0, n, c.n2e_ptr.p, c.n2e.p, c.e_piece.p,
-                     c.pair_T.p, c.piece_L.p, Cf.rowptr.p, nullptr, nullptr, nullptr, c.dflag.p, c.cf_defer.p);
+  int *cf_rp = w.out(Cf.rowptr, ns + 1, "the C_f row pointers");
+  int *defer = w.work(c.cf_defer, ns + 1, "deferred rows");
+  fill(defer, 1, 0, s);
+  hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 0, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece,
+                     pair_T, piece_L, cf_rp, nullptr, nullptr, nullptr, flag, defer);
+  hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 0, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
+                     piece_L, cf_rp, nullptr, nullptr, nullptr, flag, defer);
   FSI_CHECK_LAUNCH();
-  scan_excl(Cf.rowptr.p, Cf.rowptr.p, ns, tmp, s);
-  check_flags(c);
-  int nnz = read_int(Cf.rowptr.p + ns, s);
+  scan_excl(cf_rp, cf_rp, ns, w.scan(ns), s);
+  check_flags(flag, s);
+  const int nnz = read_int(cf_rp + ns, s);
   Cf.nnz = nnz;
-  Cf.col.reserve(nnz);
-  Cf.val.reserve(nnz);
-  fill(c.cf_defer.p, 1, 0, s);
-  hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 1, ns, n, c.n2e_ptr.p, c.n2e.p,
-                     c.e_piece.p, c.pair_T.p, c.piece_L.p, nullptr, Cf.rowptr.p, Cf.col.p, Cf.val.p,
-                     c.dflag.p, c.cf_defer.p);
-  hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, c.e_piece.p,
-                     c.pair_T.p, c.piece_L.p, nullptr, Cf.rowptr.p, Cf.col.p, Cf.val.p, c.dflag.p, c.cf_defer.p);
+  int *cf_col = w.out(Cf.col, nnz, "C_f");
+  double *cf_val = w.out(Cf.val, nnz, "C_f");
+  fill(defer, 1, 0, s);
+  hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 1, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece,
+                     pair_T, piece_L, nullptr, cf_rp, cf_col, cf_val, flag, defer);
+  hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
+                     piece_L, nullptr, cf_rp, cf_col, cf_val, flag, defer);
   FSI_CHECK_LAUNCH();
   // C_f^T
   Csr &Ct = c.CfT;
@@ -577,31 +636,88 @@ void assemble_coupling(Ctx &c, const double *Xn, bool) {
   Ct.ncols = ns;
   Ct.width = 1;
   Ct.nnz = nnz;
-  Ct.rowptr.reserve(c.N2 + 1);
-  c.cft_fill.reserve(c.N2);
-  fill(Ct.rowptr.p, c.N2 + 1, 0, s);
-  fill(c.cft_fill.p, c.N2, 0, s);
-  hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256)), dim3(256), 0, s, (int64_t)nnz, Cf.col.p,
-                     Ct.rowptr.p);
-  scan_excl(Ct.rowptr.p, Ct.rowptr.p, c.N2, tmp, s);
-  Ct.col.reserve(nnz);
-  Ct.val.reserve(nnz);
-  c.cft_tcol.reserve(nnz);
-  c.cft_tval.reserve(nnz);
-  c.cft_long.reserve(c.N2 + 1);
-  fill(c.cft_long.p, 1, 0, s);
-  hipLaunchKernelGGL(k_scatter_t, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, Cf.rowptr.p, Cf.col.p,
-                     Cf.val.p, Ct.rowptr.p, c.cft_fill.p, c.cft_tcol.p, c.cft_tval.p);
-  hipLaunchKernelGGL(k_rank_short, dim3(grid_for(c.N2, 256)), dim3(256), 0, s, c.N2, Ct.rowptr.p, c.cft_tcol.p,
-                     c.cft_tval.p, Ct.col.p, Ct.val.p, c.cft_long.p);
-  hipLaunchKernelGGL(k_rank_long, dim3(512), dim3(256), 0, s, Ct.rowptr.p, c.cft_tcol.p, c.cft_tval.p, Ct.col.p,
-                     Ct.val.p, c.cft_long.p);
+  int *ct_rp = w.out(Ct.rowptr, c.N2 + 1, "the C_f^T row pointers");
+  int *ct_fill = w.work(c.cft_fill, c.N2, "transpose fill counters");
+  fill(ct_rp, c.N2 + 1, 0, s);
+  fill(ct_fill, c.N2, 0, s);
+  hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256)), dim3(256), 0, s, (int64_t)nnz, cf_col, ct_rp);
+  scan_excl(ct_rp, ct_rp, c.N2, w.scan(c.N2), s);
+  int *ct_col = w.out(Ct.col, nnz, "C_f^T");
+  double *ct_val = w.out(Ct.val, nnz, "C_f^T");
+  int *tcol = w.work(c.cft_tcol, nnz, "transpose staging");
+  double *tval = w.work(c.cft_tval, nnz, "transpose staging");
+  int *long_rows = w.work(c.cft_long, c.N2 + 1, "long transposed rows");
+  fill(long_rows, 1, 0, s);
+  hipLaunchKernelGGL(k_scatter_t, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, cf_rp, cf_col, cf_val, ct_rp,
+                     ct_fill, tcol, tval);
+  hipLaunchKernelGGL(k_rank_short, dim3(grid_for(c.N2, 256)), dim3(256), 0, s, c.N2, ct_rp, tcol, tval, ct_col,
+                     ct_val, long_rows);
+  hipLaunchKernelGGL(k_rank_long, dim3(512), dim3(256), 0, s, ct_rp, tcol, tval, ct_col, ct_val, long_rows);
   FSI_CHECK_LAUNCH();
-  Cf.val32.reserve(nnz);
-  Ct.val32.reserve(nnz);
-  convert(Cf.val32.p, Cf.val.p, nnz, s);
-  convert(Ct.val32.p, Ct.val.p, nnz, s);
+  float *cf32 = w.out(Cf.val32, nnz, "the FP32 copy of C_f");
+  float *ct32 = w.out(Ct.val32, nnz, "the FP32 copy of C_f^T");
+  convert(cf32, cf_val, nnz, s);
+  convert(ct32, ct_val, nnz, s);
   c.have_cf = true;
+}
+
+void assemble_coupling(Ctx &c, const double *Xn, bool) {
+  GrowWork w{c};
+  assemble(c, Xn, w);
+  c.pairs_kept = true;
+}
+
+// Coupling storage reserved with the solid (grow-only): row pointers and room for
+// kCfPerNode entries per solid node in C_f, C_f^T and their FP32 copies, so that the
+// allocation-free assembly can run on a context that has never assembled before.
+constexpr int64_t kCfPerNode = 64;
+void reserve_coupling(Ctx &c) {
+  const size_t e = (size_t)(kCfPerNode * c.Ns);
+  c.Cf.rowptr.reserve(c.Ns + 1);
+  c.CfT.rowptr.reserve(c.N2 + 1);
+  c.Cf.col.reserve(e);
+  c.Cf.val.reserve(e);
+  c.Cf.val32.reserve(e);
+  c.CfT.col.reserve(e);
+  c.CfT.val.reserve(e);
+  c.CfT.val32.reserve(e);
+}
+
+// ---- the allocation-free form: one static work array per GPU
+// Every context on a GPU shares that GPU's copy; it keeps the last call's contents.  Host
+// code uses the device address taken once per device at set-up, never the symbol itself.
+static __device__ __align__(256) unsigned char scratch[FSI_COUPLING_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kMaxDevices] = {};
+static hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Called by fsi_create with the context's device current; takes the address once per device.
+void coupling_scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[dev] || g_scratch_err[dev] != hipSuccess) return;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) g_scratch_ptr[dev] = (unsigned char *)p;
+  else g_scratch_err[dev] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+}
+
+void assemble_coupling_noalloc(Ctx &c, const double *Xn) {
+  FSI_REQUIRE(c.device >= 0 && c.device < kMaxDevices, FSI_E_HIP, "context device out of range");
+  unsigned char *base = nullptr;
+  hipError_t err = hipSuccess;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    base = g_scratch_ptr[c.device];
+    err = g_scratch_err[c.device];
+  }
+  FSI_REQUIRE(base, FSI_E_HIP,
+              std::string("no device address of the coupling scratch array: ") +
+                  (err != hipSuccess ? hipGetErrorString(err) : "not initialised on this device"));
+  ArenaWork w{c, base, (size_t)FSI_COUPLING_SCRATCH_BYTES, 0};
+  assemble(c, Xn, w);
 }
 
 }  // namespace fsi

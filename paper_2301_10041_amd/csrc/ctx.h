@@ -64,6 +64,7 @@ struct Prof {
 struct Ctx {
   // problem
   int n = 0;
+  int device = 0;          // HIP device of the context (current at fsi_create)
   double nu = 1, rho = 1, dt = 0.01, kappa = 10;
   int64_t N2 = 0, Np = 0, Ns = 0, Nt = 0, N = 0;
   hipStream_t stream = nullptr;
@@ -103,6 +104,7 @@ struct Ctx {
 
   // coupling (rebuilt by every fsi_assemble_coupling)
   bool have_cf = false;
+  bool pairs_kept = false; // the piece list (pair_E, pair_T) is in the context's buffers
   Csr Cf, CfT;
   int64_t n_pairs = 0, n_cand = 0;
   DevBuf<int> cand_off;    // Nt + 1
@@ -183,6 +185,9 @@ void build_solid(Ctx &c);
 void build_multigrid(Ctx &c);
 // coupling.hip
 void assemble_coupling(Ctx &c, const double *Xn, bool sync_check);
+void assemble_coupling_noalloc(Ctx &c, const double *Xn);
+void reserve_coupling(Ctx &c);
+void coupling_scratch_init(int dev);
 // ops.hip (operator of eq. (matrix) and its pieces)
 template <typename T, typename Tx>
 void apply_operator(Ctx &c, const Tx *x, double *y, bool fluid_only);

@@ -86,16 +86,24 @@ __global__ void k_scan_final(const int *in, int64_t n, const int *bsum, int *out
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = bsum[gridDim.x];
 }
 
-// `in` and `out` may alias.  `tmp` holds the tile sums.  Returns nothing: the total is
-// out[n] on the device.
-inline void scan_excl(const int *in, int *out, int64_t n, DevBuf<int> &tmp, hipStream_t s) {
-  int nb = (int)((n + kScanTile - 1) / kScanTile);
-  if (nb < 1) nb = 1;
-  tmp.reserve(nb + 1);
-  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(kScanBlock), 0, s, in, n, tmp.p);
-  hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kScanBlock), 0, s, tmp.p, nb);
-  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBlock), 0, s, in, n, tmp.p, out);
+// Tile sums a scan of n items needs (scan_tmp_len(n) ints of work space).
+inline int64_t scan_tmp_len(int64_t n) {
+  int64_t nb = (n + kScanTile - 1) / kScanTile;
+  return (nb < 1 ? 1 : nb) + 1;
+}
+
+// `in` and `out` may alias.  `tmp` holds the tile sums (at least scan_tmp_len(n) ints).
+// Returns nothing: the total is out[n] on the device.
+inline void scan_excl(const int *in, int *out, int64_t n, int *tmp, hipStream_t s) {
+  const int nb = (int)(scan_tmp_len(n) - 1);
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(kScanBlock), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kScanBlock), 0, s, tmp, nb);
+  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBlock), 0, s, in, n, tmp, out);
   FSI_CHECK_LAUNCH();
+}
+inline void scan_excl(const int *in, int *out, int64_t n, DevBuf<int> &tmp, hipStream_t s) {
+  tmp.reserve(scan_tmp_len(n));
+  scan_excl(in, out, n, tmp.p, s);
 }
 
 // ------------------------------------------------------------------ sparse products

@@ -21,6 +21,7 @@ FP64, FP32, FP32_IR = 0, 1, 2
 PC_DIAG, PC_TRI = 0, 1
 SMOOTH_CSR, SMOOTH_STENCIL = 0, 1
 MAX_LANES = 32                 # FSI_MAX_LANES: systems per fsi_step_batch
+COUPLING_SCRATCH_BYTES = 32 << 20   # FSI_COUPLING_SCRATCH_BYTES
 BLOCKS = dict(AF=0, MF=1, B=2, BT=3, AS=4, CS=5, CF=6, CFT=7, MP=8)
 
 
@@ -83,6 +84,7 @@ _SIGS = {
     "fsi_footprint": (C.c_int, [C.POINTER(FluidDesc), C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "fsi_sizes": (C.c_int, [C.c_void_p, C.POINTER(Sizes)]),
     "fsi_assemble_coupling": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(CouplingInfo)]),
+    "fsi_assemble_coupling_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(CouplingInfo)]),
     "fsi_build_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fsi_apply_operator": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "fsi_apply_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
@@ -277,6 +279,13 @@ class Context:
     def assemble_coupling(self, Xn, sync=True):
         info = CouplingInfo()
         self._check(lib().fsi_assemble_coupling(self._h, _ptr(Xn), C.byref(info) if sync else None))
+        return dict(n_pairs=info.n_pairs, nnz=info.nnz)
+
+    def assemble_coupling_noalloc(self, Xn, sync=True):
+        """fsi_assemble_coupling_noalloc: the same C_f with no device allocation (work space in the
+        library's per-GPU static array; overlapping calls on one GPU race)."""
+        info = CouplingInfo()
+        self._check(lib().fsi_assemble_coupling_noalloc(self._h, _ptr(Xn), C.byref(info) if sync else None))
         return dict(n_pairs=info.n_pairs, nnz=info.nnz)
 
     def build_rhs(self, u_n, X_n, b):
