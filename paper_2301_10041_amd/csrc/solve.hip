@@ -1333,15 +1333,20 @@ static void ensure_inner(Ctx &c, int prec, int K = 1) {
   }
 }
 
-// Default inner tolerance 1e-2 in both precisions (flexible outer GMRES: it trades outer for
-// inner steps).  Measured on the 1024^2 / 256^2 / 512^2 workloads with the multigrid of this
-// file, FP64 step time at 1.5e-3, 3e-3, 6e-3, 1e-2, 2e-2: 247/235/203/193/225, 138/137/117/
-// 106/103, 60/55/51/48/54 ms (outer steps 9, 10, 5 up to 1e-2, one more at 2e-2 on two
-// workloads); mixed at 5e-3, 1e-2, 2e-2, 4e-2: 182/152/177/142, 104/97/94/95, 46/42/47/45 ms.
-double inner_tol(const Ctx &c, int prec) {
-  if (c.inner_rtol > 0) return c.inner_rtol;
+// Default inner tolerance (flexible outer GMRES: it trades outer for inner steps).
+// Block-triangular: 1e-2 in both precisions.  Measured on the 1024^2 / 256^2 / 512^2
+// workloads with the multigrid of this file, FP64 step time at 1.5e-3, 3e-3, 6e-3, 1e-2,
+// 2e-2: 247/235/203/193/225, 138/137/117/106/103, 60/55/51/48/54 ms (outer steps 9, 10, 5 up
+// to 1e-2, one more at 2e-2 on two workloads); mixed at 5e-3, 1e-2, 2e-2, 4e-2:
+// 182/152/177/142, 104/97/94/95, 46/42/47/45 ms.  Its outer counts equal the exact-block
+// counts (10, 11, 14 at 32^2, 128^2, 256^2) at 1e-2 already.
+// Block-diagonal: 1e-3.  Its outer counts react more to the inexact A11: against the
+// exact-block counts 16 / 16 / 20 at 32^2 / 128^2 / 256^2 it takes 16 / 20 / 24 at 1e-2,
+// 16 / 18 / 24 at 5e-3 and 16 / 18 / 22 at 1e-3 and at 3e-4 (+5% time against 1e-2).
+double inner_tol(const Ctx &c, int prec, int pc) {
   (void)prec;
-  return 1e-2;
+  if (c.inner_rtol > 0) return c.inner_rtol;
+  return pc == FSI_PC_DIAG ? 1e-3 : 1e-2;
 }
 
 // The block preconditioner on K systems: system k belongs to context cs[k] (one fluid grid
@@ -1359,7 +1364,7 @@ void apply_precond_lanes(Ctx &c, Ctx *const *cs, int K, int pc, int prec, const 
     FSI_REQUIRE(cs[k]->have_cf || pc == FSI_PC_DIAG, FSI_E_STATE,
                 "block-triangular needs C_f: call fsi_assemble_coupling");
   ensure_inner(c, prec, K);
-  const double tol = inner_tol(c, prec);
+  const double tol = inner_tol(c, prec, pc);
   int its[FSI_MAX_LANES];
   if (c.inner_mode == 1) {   // fixed cost: one application of the inner preconditioner
     if (prec == FSI_FP64) a11_fixed<double>(c, r, z, K);

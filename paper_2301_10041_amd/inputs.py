@@ -138,6 +138,11 @@ WORKLOADS = {
                            dt=0.01, seed=1),
     # 512^2 fluid, disk R=0.2, 40,344 triangles, rotation 0.1 rad/s, dt=1e-3, 100 steps
     "rotdisk512": Workload("rotdisk512", 512, [Solid(82, (0.5, 0.5), 0.2)], dt=1e-3, seed=2),
+    # the 1024^2 two-disk geometry on a 128^2 grid (ring count scaled with the grid: m = 14,
+    # 1,176 triangles per disk), seed 3: the mid-size parity case and the CPU baseline sample
+    "twodisk128": Workload("twodisk128", 128,
+                           [Solid(14, (0.3, 0.5), 0.1), Solid(14, (0.7, 0.5), 0.1)],
+                           dt=0.01, seed=3),
     # 1024^2 fluid, two disks R=0.1 at (0.3,0.5), (0.7,0.5), 75,264 triangles each, seed 3
     "twodisk1024": Workload("twodisk1024", 1024,
                             [Solid(112, (0.3, 0.5), 0.1), Solid(112, (0.7, 0.5), 0.1)],

@@ -59,3 +59,48 @@ def small_workloads():
         # 1,024 lattice nodes (the wide-window form of the C_f rows)
         "coarse_disk128": (inputs.small_workload(128, 3, (0.47, 0.52), 0.2), 0.3),
     }
+
+
+def block_errors(S, x, x_ref):
+    """Relative errors of x against x_ref (the oracle's) per block of the unknown vector and
+    over the whole vector: u (both components), p with its mean removed (weights: the row
+    sums of the P1 pressure mass, i.e. the integrals of the basis functions), X and lam (both
+    components).  For each: 'l2' = ||x - x_ref||_2 / ||x_ref||_2 and 'max' = max |x - x_ref| /
+    max |x_ref| (element by element against the block's largest entry)."""
+    lay = S.lay
+    sl = lay.slices()
+    x = np.asarray(x, dtype=np.float64)
+    x_ref = np.asarray(x_ref, dtype=np.float64)
+    w = np.asarray(S.F["Mp"].sum(axis=1)).ravel()
+
+    def mean_free(p):
+        return p - (w @ p) / w.sum()
+
+    parts = {
+        "u": (np.concatenate([x[sl["ux"]], x[sl["uy"]]]), np.concatenate([x_ref[sl["ux"]], x_ref[sl["uy"]]])),
+        "p": (mean_free(x[sl["p"]]), mean_free(x_ref[sl["p"]])),
+        "X": (np.concatenate([x[sl["Xx"]], x[sl["Xy"]]]), np.concatenate([x_ref[sl["Xx"]], x_ref[sl["Xy"]]])),
+        "lam": (np.concatenate([x[sl["lx"]], x[sl["ly"]]]), np.concatenate([x_ref[sl["lx"]], x_ref[sl["ly"]]])),
+        "all": (x, x_ref),
+    }
+    out = {}
+    for k, (a, b) in parts.items():
+        d = a - b
+        nb = np.linalg.norm(b)
+        mb = np.abs(b).max() if b.size else 0.0
+        out[k] = {"l2": float(np.linalg.norm(d) / (nb if nb > 0 else 1.0)),
+                  "max": float(np.abs(d).max() / (mb if mb > 0 else 1.0)) if d.size else 0.0}
+    return out
+
+
+def fmt_errors(e):
+    return " ".join(f"{k}:{v['l2']:.1e}/{v['max']:.1e}" for k, v in e.items())
+
+
+def assert_block_parity(S, x, x_ref, tol=1e-8, label=""):
+    """Every block's 2-norm and element-max relative error within tol (printed)."""
+    e = block_errors(S, x, x_ref)
+    print(f"  {label} per-block err (l2/max) {fmt_errors(e)}", flush=True)
+    for k, v in e.items():
+        assert v["l2"] <= tol and v["max"] <= tol, (label, k, v)
+    return e

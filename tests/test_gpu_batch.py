@@ -11,7 +11,7 @@ from oracle import step as ostep
 from oracle import system
 from paper_2301_10041_amd import fsi, inputs
 
-from gpu_helpers import rel, soa, to_dev, to_host, torch_dev
+from gpu_helpers import assert_block_parity, rel, soa, to_dev, to_host, torch_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -96,7 +96,7 @@ def test_batch_matches_oracle():
         S = system.FSISystem.from_workload(wl)
         u = inputs.uniform(2 * S.lay.N2, wl.seed)
         x_ref, _ = ostep.step(S, u, S.xy_ref, solver="direct")
-        assert rel(x, x_ref) <= 1e-7, wl.name
+        assert_block_parity(S, x, x_ref, 1e-8, wl.name)
     for c in ctxs:
         c.close()
 
@@ -184,7 +184,7 @@ def test_batch_high_valence_solid():
         S = system.FSISystem.from_workload(wl)
         u = inputs.uniform(2 * S.lay.N2, wl.seed)
         x_ref, _ = ostep.step(S, u, S.xy_ref, solver="direct")
-        assert rel(states[k], x_ref) <= 1e-7, wl.name
+        assert_block_parity(S, states[k], x_ref, 1e-8, wl.name)
     for c in ctxs:
         c.close()
 
@@ -212,7 +212,7 @@ def test_fixed_cost_inner_mode(prec):
     S = system.FSISystem.from_workload(wls[0])
     u = inputs.uniform(2 * S.lay.N2, wls[0].seed)
     x_ref, _ = ostep.step(S, u, S.xy_ref, solver="direct")
-    assert rel(states[0], x_ref) <= 1e-7
+    assert_block_parity(S, states[0], x_ref, 1e-8, "fixed-cost")
     u0, X0, s0 = inputs_of(wls[0], ctxs[0])
     with pytest.raises(fsi.FsiError) as e:
         ctxs[0].step(u0, X0, s0, fsi.Opts(prec=prec, inner_mode=2))

@@ -1,7 +1,8 @@
 """Serving form: independent FSI steps of different sizes admitted continuously under an
 HBM budget.  Each result must be the same alone and in the mix (bitwise: every kernel
-is deterministic and slots share no device state), agree with the FP64 oracle within the
-mixed-precision bar, and a tight budget must queue requests rather than fail."""
+is deterministic and slots share no device state), agree with the FP64 oracle to 1e-8 in
+every block (the parity runs solve to rtol 1e-10, mixed precision), and a tight budget
+must queue requests rather than fail."""
 import numpy as np
 import pytest
 
@@ -9,7 +10,9 @@ from oracle import step as ostep
 from oracle import system
 from paper_2301_10041_amd import fsi, inputs, serve
 
-from gpu_helpers import rel, torch_dev
+from gpu_helpers import assert_block_parity, torch_dev
+
+RTOL = 1e-10   # parity runs: the solution error stays below 1e-8 per block
 
 pytestmark = pytest.mark.gpu
 
@@ -36,7 +39,7 @@ def small_trace(count=10, seed=7):
 def mixed_run():
     torch_dev()
     reqs = small_trace()
-    srv = serve.Server(max_slots=4, keep_states=True)
+    srv = serve.Server(max_slots=4, keep_states=True, rtol=RTOL)
     res = srv.run(reqs)
     stats = dict(max_inflight=srv.max_inflight, slots=len(srv.slots))
     srv.close()
@@ -55,7 +58,7 @@ def test_all_served_and_converged(mixed_run):
 def test_alone_equals_mix_bitwise(mixed_run):
     reqs, res, _ = mixed_run
     for q, r in zip(reqs, res):
-        alone = serve.Server(max_slots=1, keep_states=True)
+        alone = serve.Server(max_slots=1, keep_states=True, rtol=RTOL)
         [a] = alone.run([serve.Request(q.rid, 0.0, q.workload, q.u_seed)], realtime=False)
         alone.close()
         assert np.array_equal(a.state, r.state), q.rid
@@ -67,7 +70,7 @@ def test_mixed_results_match_oracle(mixed_run):
         S = system.FSISystem.from_workload(q.workload)
         u = inputs.uniform(2 * S.lay.N2, q.u_seed)
         x_ref, _ = ostep.step(S, u, S.xy_ref, solver="direct")
-        assert rel(r.state, x_ref) <= 1e-7, q.rid
+        assert_block_parity(S, r.state, x_ref, 1e-8, f"request {q.rid}")
 
 
 def _footprint(q):
