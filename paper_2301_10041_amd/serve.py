@@ -119,6 +119,7 @@ class Server:
         self.max_inflight = 0
         self.evictions = 0
         self._next_sid = 0
+        self._pending = {}           # grid key -> slots admitted but not yet built (outside the lock)
 
     # -- admission ---------------------------------------------------------------
     def _bytes_needed(self, wl):
@@ -154,7 +155,8 @@ class Server:
         for s in self.slots:
             if not s.busy and s.key == key:
                 return s, False
-        if self.slots_per_grid is not None and sum(1 for s in self.slots if s.key == key) >= self.slots_per_grid:
+        if self.slots_per_grid is not None and (sum(1 for s in self.slots if s.key == key) +
+                                                self._pending.get(key, 0)) >= self.slots_per_grid:
             return None, False
         busy = sum(1 for s in self.slots if s.busy)
         if busy >= self.max_slots:
@@ -176,6 +178,7 @@ class Server:
             v.close()
             self.evictions += 1
         self.reserved += need
+        self._pending[key] = self._pending.get(key, 0) + 1   # until the new slot is registered
         return need, True
 
     # -- one job (a lockstep batch of requests of one grid) on one slot ----------------
@@ -293,14 +296,21 @@ class Server:
                     results[q.rid].start = t_start
                 try:
                     if slot is None:
-                        stream = torch.cuda.Stream()
-                        slot = Slot(sid, r.workload, stream, self.lanes(r.workload.n))
+                        try:
+                            stream = torch.cuda.Stream()
+                            slot = Slot(sid, r.workload, stream, self.lanes(r.workload.n))
+                        except Exception:
+                            with self.cv:
+                                self._pending[key] -= 1
+                                self.reserved -= got
+                            raise
                         # keep the estimate until the slot's Krylov space exists
                         slot.bytes = max(slot.bytes, got)
                         with self.cv:
                             self.reserved += slot.bytes - got
                             slot.busy = True
                             self.slots.append(slot)
+                            self._pending[key] -= 1
                     with self.cv:
                         slot.bytes += extra      # contexts the batch adds (reserved above)
                     for q in members:
