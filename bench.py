@@ -1,25 +1,39 @@
 #!/usr/bin/env python3
-"""FSI time steps per second on one MI355X: FP64 and mixed precision.
+"""FSI time steps per second on one MI355X: FP64 and mixed precision, every workload.
 
-A step is one call of fsi_step: C_f(X^n) re-clipped and reassembled for the current
-solid position, the right-hand side, and the right-preconditioned FGMRES solve of the
-saddle-point system (block-triangular preconditioner, rtol 1e-8).  Default workload:
-1024 x 1024 P2/P1 fluid (8.4M velocity unknowns) with two disks of radius 0.1 at
-(0.3, 0.5) and (0.7, 0.5), 75,264 P1 triangles each; u^n ~ U[-1, 1] (seed 3), X^n the
-reference mesh rotated about (0.5, 0.5) at 0.1 rad/s (one new position per step);
-u^{n+1} of each step is u^n of the next (a time loop).
+A step is one call of fsi_step: C_f(X^n) re-clipped and reassembled for the current solid
+position, the right-hand side, and the right-preconditioned FGMRES solve of the saddle-point
+system (block-triangular preconditioner, rtol 1e-8).  Headline workload: 1024 x 1024 P2/P1
+fluid (8.4M velocity unknowns) with two disks of radius 0.1 at (0.3, 0.5) and (0.7, 0.5),
+75,264 P1 triangles each; u^n ~ U[-1, 1] (seed 3), X^n the reference mesh rotated about
+(0.5, 0.5) at 0.1 rad/s (one new position per step); u^{n+1} of each step is u^n of the next.
 Inputs are synthetic and resident in HBM before the timed region.
 
-Prints one JSON line.  `value` is FP64 steps/s; the `mixed` object holds the same
-measurement with FP32 SpMV and inner solves (FP64 Arnoldi, residuals and clipping).
+Prints one JSON line.  `value` is FP64 steps/s at 1024^2.  Beside it:
+  mixed      the same time loop with the inner block solves (multigrid V-cycles, mass and
+             Schur solves) in FP32 with FP32 accumulation; FP64 operator, Arnoldi process,
+             inner Krylov recurrence, residuals and clipping (FSI_FP32);
+  fp32_ir    the operator of the Arnoldi process in FP32 as well, with refinement on the FP64
+             residual (FSI_FP32_IR);
+  fixed_cost_a11  the fixed-cost inexact A11 option (inner_mode 1);
+  step_roofline   algorithmic bytes of a step (model below, from the measured outer and inner
+             step counts) against the step time and 8 TB/s;
+  configs    the CPU-fast 32^2 case (both preconditioners), the 256^2 ellipse (both
+             preconditioners), the 512^2 rotating-disk time loop (100 steps, dt 1e-3);
+  serving    the 512-request trace in mixed precision and in FP64;
+  accuracy   per-run errors against the FP64 oracle (computed in the oracle leg);
+  cpu_baseline / cpu_serving  the oracle on the host's cores (bounded samples).
+The oracle runs only in the oracle leg, a separate process started at the end.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -28,43 +42,267 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 OMEGA = 0.1                # rad/s, prescribed rotation of the solid
+CPU_SHARE = 16             # host cores of one GPU's share on the GPU machine (oracle worker pool)
 
 
-def cpu_baseline_leg(workload: str) -> dict:
-    """Oracle (FP64, SciPy direct solve) on a bounded sample of the workload's shape,
-    single-threaded; scaled by the unknown count to the full workload (the sparse direct
-    solve grows faster than linearly, so the scaled rate is an upper bound for the CPU)."""
+def _f(v, d=6):
+    return float(f"{v:.{d}g}") if isinstance(v, float) else v
+
+
+def _round(obj):
+    if isinstance(obj, dict):
+        return {k: _round(v) for k, v in obj.items()}
+    if isinstance(obj, list):
+        return [_round(v) for v in obj]
+    return _f(obj)
+
+
+# ------------------------------------------------------------------------------------------
+# algorithmic bytes of one step (model of the kernels the step launches)
+# ------------------------------------------------------------------------------------------
+def _levels(n, stop):
+    out = []
+    while n > stop:
+        out.append(n)
+        n //= 2
+    return out, n
+
+
+def inner_step_bytes(n, prec):
+    """Bytes one inner MINRES step must move (one A11 product with the Lanczos and update
+    vectors, one application of diag(V, S^{-1})), per kernel of the matrix-free path, with
+    w = 8 (FP64) or 4 (FP32 preconditioner):
+      velocity V-cycle, per level above the one-launch tail (cells > 16): pre-smoothing 4w N2_l
+        (b read, x written, two components), residual + restriction 4w N2_l + 2w N2_{l+1},
+        post-smoothing with the coarse correction 6w N2_l + 2w N2_{l+1};
+      tail: 4w N2 of its first level + the dense coarsest inverse (162^2 w);
+      pressure V-cycle (P1), per level above the 4^2 dense level: first step 3w, one more
+        Chebyshev step 5w, residual 3w, restriction w + w coarse, prolongation 2w + w coarse,
+        two post steps 10w per node; dense 25^2 w;
+      pressure mass solve 13w Np, pressure residual copy (8 + w) Np, output (2w + 16) Np;
+      A11 product with the fused MINRES updates (FP64): 64 N2 + 32 Np;
+      remaining MINRES vector work: 10 vectors of nf = 2 N2 + Np doubles;
+      FP32 form: the velocity residual converted (24 N2), the finest post-smoothing writes the
+        FP64 output ((4w + 16) N2 instead of 6w N2) and reads the FP64 residual for the sums of
+        r . z (16 N2)."""
+    w = 8 if prec == "fp64" else 4
+    N2 = lambda m: (2 * m + 1) ** 2
+    Np = lambda m: (m + 1) ** 2
+    full, tail = _levels(n, 16)
+    b = 0.0
+    for k, m in enumerate(full):
+        post = 6 * w * N2(m)
+        if k == 0 and prec != "fp64":
+            post = (4 * w + 16) * N2(m) + 16 * N2(m)
+        b += 4 * w * N2(m) + (4 * w * N2(m) + 2 * w * N2(m // 2)) + post + 2 * w * N2(m // 2)
+    b += 4 * w * N2(tail) + 162 * 162 * w
+    pfull, _ = _levels(n, 4)
+    for m in pfull:
+        b += 24 * w * Np(m) + 2 * w * Np(m // 2)
+    b += 25 * 25 * w
+    b += 13 * w * Np(n) + (8 + w) * Np(n) + (2 * w + 16) * Np(n)
+    b += 64 * N2(n) + 32 * Np(n)
+    b += 10 * 8 * (2 * N2(n) + Np(n))
+    if prec != "fp64":
+        b += 24 * N2(n)
+    return b
+
+
+def step_bytes(n, Ns, nnz_s, nnz_cf, n_pairs, its, inner_its, restarts, prec, pc, cs_steps=13):
+    """Algorithmic bytes of one step (C_f assembly, right-hand side, the outer FGMRES with its
+    inner solves), w = 8 for every outer vector:
+      C_f: the piece list and 3 x 6 matrices written and read (2 x 152 B per piece), C_f and
+        C_f^T written, ranked and read (4 x 12 B per entry);
+      g1 = (rho/dt) M_f u^n: the P2 pattern (46 n^2 entries, 12 B) and two components in and out;
+      per outer step j: the operator (matrix-free fluid rows 32 N2 + 16 Np, C_f^T and C_f
+        entries 12 B each twice, the solid rows 20 B per entry of the solid pattern and 8
+        vectors of Ns), A22 by two C_s Chebyshev solves of cs_steps steps (12 B per entry and
+        6 vectors of Ns per step) and one A_s product, the block-triangular C_f product, the
+        two Gram-Schmidt passes 16 (j + 1) N + 24 N and the normalisation 16 N;
+      inner steps: inner_step_bytes each, plus one more preconditioner application per
+        outer step (the start of MINRES);
+      per restart: the update x += Z y ((k + 1) N 8) and the FP64 true residual (operator + 3N 8)."""
+    N2, Np = (2 * n + 1) ** 2, (n + 1) ** 2
+    N = 2 * N2 + Np + 4 * Ns
+    b = 2 * 152 * n_pairs + 4 * 12 * nnz_cf
+    b += (46 * n * n) * 12 + 4 * 8 * N2
+    op = 32 * N2 + 16 * Np + 2 * 12 * nnz_cf + 20 * nnz_s + 8 * 8 * Ns
+    a22 = 2 * cs_steps * (12 * nnz_s + 6 * 8 * Ns) + 12 * nnz_s + 6 * 8 * Ns
+    cf = 12 * nnz_cf + 2 * 8 * Ns if pc == "tri" else 0
+    m = 30
+    for j in range(its):
+        jj = j % m
+        b += op + a22 + cf + 16 * (jj + 1) * N + 24 * N + 16 * N
+    b += inner_its * inner_step_bytes(n, prec)
+    b += its * (inner_step_bytes(n, prec) - 64 * N2 - 32 * Np - 10 * 8 * (2 * N2 + Np))
+    b += restarts * ((min(its, m) + 1) * N * 8 + op + 3 * N * 8)
+    return b
+
+
+# ------------------------------------------------------------------------------------------
+# the oracle leg (a separate process; the only part of this file that runs the oracle)
+# ------------------------------------------------------------------------------------------
+def _cpu_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(nproc=os.cpu_count(), cpu_model=model)
+
+
+def _oracle_step(wl, X, u):
+    """One oracle step in the paper's phases (one core): T_setup (assembly and the exact block
+    factorisations of A11 and A22, once), T_coup (C_f clipping and integration), T_sol
+    (GMRES(30) with the exact block-triangular preconditioner to rtol 1e-8).  Returns the
+    system, the right-hand side, the solution and the phase record."""
+    from oracle import gmres, system
+    t0 = time.perf_counter()
+    S = system.FSISystem.from_workload(wl)
+    t1 = time.perf_counter()
+    S.set_position(X)
+    t2 = time.perf_counter()
+    S._factor()          # A11 and A22 do not depend on X^n: factorised once (setup)
+    t3 = time.perf_counter()
+    b = S.rhs(u, X)
+    A = S.matrix()
+    x, info = gmres.gmres(lambda v: A @ v, b, precond=lambda r: S.apply_precond(r, "tri"), restart=30, rtol=1e-8)
+    t4 = time.perf_counter()
+    ph = dict(T_setup_s=(t1 - t0) + (t3 - t2), T_coup_s=t2 - t1, T_sol_s=t4 - t3, its=info["its"], N=S.lay.N)
+    return S, A, b, x, ph
+
+
+def _errs(S, x, xs):
+    """||x - x*|| / ||x*|| over the whole vector and per block (u, mean-free p, X, lam)."""
+    import numpy as np
+    sl = S.lay.slices()
+    w = np.asarray(S.F["Mp"].sum(axis=1)).ravel()
+    mf = lambda p: p - (w @ p) / w.sum()
+    cat = lambda v, a, b: np.concatenate([v[sl[a]], v[sl[b]]])
+    parts = {"u": (cat(x, "ux", "uy"), cat(xs, "ux", "uy")), "p": (mf(x[sl["p"]]), mf(xs[sl["p"]])),
+             "X": (cat(x, "Xx", "Xy"), cat(xs, "Xx", "Xy")), "lam": (cat(x, "lx", "ly"), cat(xs, "lx", "ly"))}
+    res = {"all": float(np.linalg.norm(x - xs) / np.linalg.norm(xs))}
+    for k, (a, b) in parts.items():
+        res[k] = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    return res
+
+
+def oracle_leg(args) -> dict:
+    """The oracle on the host (one core per solve): the CPU baseline of the headline metric,
+    the CPU serving baseline and the accuracy of the GPU results saved by the main process.
+
+    cpu_baseline: one step of the two-disk geometry at 128^2 (the headline geometry with the
+      ring count scaled with the grid) in the paper's phases; steps/s = 1 / (T_coup + T_sol),
+      scaled to the full workload by the unknown ratio (extrapolated: the exact block solves
+      grow faster than linearly, so the scaled rate bounds the CPU from above).
+    cpu_serving: the 512-request trace through a first-come first-served pool of 16 oracle
+      workers (the host cores of one GPU's share), with per-size service times: one request
+      of 32^2 and of 64^2 solved, the 128^2 step above, 256^2 extrapolated by the 64 -> 128
+      growth (modelled, not run).
+    accuracy: eps = ||x - x*|| / ||x*||, whole vector and per block, of the GPU results at
+      32^2 (x* the direct solve) and of the 128^2 two-disk step (x* the oracle's GMRES continued
+      to the residual floor from the rtol 1e-8 solution); at 1024^2 the largest residual
+      |b_i - (A x)_i| / ||b|| on the oracle's own rows at sampled unknowns."""
     import numpy as np
 
-    from oracle import step as ostep
-    from oracle import system
+    from oracle import gmres, sampled, system
     from paper_2301_10041_amd import inputs
-
-    full = inputs.WORKLOADS[workload]
-    # same geometry, fluid 128^2 and ring count scaled by the same factor as the grid
-    f = full.n // 128
-    sample = inputs.Workload(f"{workload}_sample128", 128,
-                             [inputs.Solid(max(2, s.m // f), s.center, s.radius, s.semi_axes)
-                              for s in full.solids], nu=full.nu, rho=full.rho, kappa=full.kappa,
-                             dt=full.dt, seed=full.seed)
-    S = system.FSISystem.from_workload(sample)
-    lay = S.lay
-    u = inputs.uniform(2 * lay.N2, sample.seed)
-    steps = 1
-    t0 = time.perf_counter()
-    for k in range(steps):
-        X = inputs.rotation(S.xy_ref, (0.5, 0.5), OMEGA * k * sample.dt)
-        ostep.step(S, u, X, solver="direct")
-    t = (time.perf_counter() - t0) / steps
+    out = {}
+    data = np.load(args.accuracy_in) if args.accuracy_in else None
+    full = inputs.WORKLOADS[args.workload]
+    wl = inputs.WORKLOADS["twodisk128"]
+    X = inputs.rotation(wl.solid_mesh()[0], (0.5, 0.5), OMEGA * wl.dt)
+    u = inputs.uniform(2 * (2 * wl.n + 1) ** 2, wl.seed)
+    S, A, b, x8, ph = _oracle_step(wl, X, u)
+    t = ph["T_coup_s"] + ph["T_sol_s"]
     n_full = full.sizes()["N"]
-    scale = n_full / lay.N
-    return {"value": 1.0 / (t * scale), "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} oracle steps (C_f clipping + sparse direct solve) of the same two-disk "
-                      f"geometry at 128^2 fluid ({lay.N} unknowns, {t:.2f} s/step), scaled by the "
-                      f"unknown ratio {scale:.1f} to {n_full} unknowns",
-            "sample_s_per_step": t}
+    scale = n_full / ph["N"]
+    cb = {"value": 1.0 / (t * scale), "unit": "steps/s", "cores": 1, "kind": "oracle",
+          "sample": f"one oracle step (C_f clipping, exact-block GMRES(30) to rtol 1e-8, block-triangular) of the "
+                    f"two-disk geometry at 128^2 fluid ({ph['N']} unknowns, {ph['its']} its, {t:.2f} s/step "
+                    f"after {ph['T_setup_s']:.1f} s of setup), scaled by the unknown ratio {scale:.1f} to "
+                    f"{n_full} unknowns (extrapolated)",
+          "sample_steps_per_s": 1.0 / t}
+    cb.update(ph)
+    cb.update(_cpu_info())
+    out["cpu_baseline"] = cb
+    acc = {}
+    if data is not None:
+        xs, info = gmres.gmres(lambda v: A @ v, b, precond=lambda r: S.apply_precond(r, "tri"), x0=x8, restart=30,
+                               rtol=5e-12, maxit=200)
+        acc["twodisk128"] = {k[len("twodisk128_"):]: _errs(S, data[k], xs) for k in data.files
+                             if k.startswith("twodisk128_")}
+        acc["twodisk128"]["reference"] = f"oracle GMRES to relres {info['relres']:.1e}"
+        w32 = inputs.WORKLOADS["disk32"]
+        S32 = system.FSISystem.from_workload(w32)
+        S32.set_position(S32.xy_ref)
+        xs32 = S32.solve_direct(S32.random_rhs(w32.seed))
+        acc["disk32"] = {k[len("disk32_"):]: _errs(S32, data[k], xs32) for k in data.files if k.startswith("disk32_")}
+        if "big_fp64" in data.files:
+            wb = inputs.WORKLOADS["twodisk1024"]
+            xy, tri = wb.solid_mesh()
+            rng = np.random.default_rng(17)
+            vel, prs, sol = sampled.sample_rows(wb.n, inputs.rotation(xy, (0.5, 0.5), 0.0), tri, xy.shape[0], rng)
+            X0 = inputs.rotation(xy, (0.5, 0.5), 0.0)   # the first step's position, as the GPU leg makes it
+            ss = sampled.SampledSystem(wb.n, xy, tri, X0, vel, prs, sol, wb.nu, wb.rho, wb.dt, wb.kappa)
+            ub = data["big_u"]
+            big = {"rows": 2 * len(vel) + len(prs) + 4 * len(sol)}
+            for tag in ("fp64", "mixed", "fp32_ir"):
+                if f"big_{tag}" in data.files:
+                    res = ss.residual(data[f"big_{tag}"], ub)
+                    big[f"sampled_residual_{tag}"] = max(abs(v) for v in res.values()) / float(data["big_bnorm"])
+            acc["twodisk1024"] = big
+        out["accuracy"] = acc
+    if not args.no_cpu_baseline:
+        trace = inputs.request_trace(args.serve_requests, 200.0, seed=4)
+        svc = {}
+        for n in (32, 64):
+            w = next(q for _, q in trace if q.n == n)
+            xy, _ = w.solid_mesh()
+            t0 = time.perf_counter()
+            _oracle_step(w, xy, inputs.uniform(2 * (2 * n + 1) ** 2, w.seed))
+            svc[n] = time.perf_counter() - t0
+        svc[128] = ph["T_setup_s"] + t
+        svc[256] = svc[128] * (svc[128] / svc[64])
+        free = [0.0] * CPU_SHARE
+        lat = []
+        for ta, w in trace:
+            k = min(range(CPU_SHARE), key=lambda i: free[i])
+            free[k] = max(ta, free[k]) + svc[w.n]
+            lat.append(free[k] - ta)
+        lat = np.array(lat)
+        out["cpu_serving"] = {"throughput_req_s": len(trace) / (max(free) - trace[0][0]),
+                              "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                              "p99_ms": float(np.percentile(lat, 99) * 1e3), "workers": CPU_SHARE,
+                              "service_s": {str(k): v for k, v in svc.items()}, "kind": "oracle",
+                              "sample": "one oracle request (setup, clipping, exact-block GMRES) per grid size 32 and "
+                                        "64 solved, 128 from the baseline step, 256 extrapolated (x the 64->128 "
+                                        "growth); the trace replayed through a FIFO pool of 16 workers with those "
+                                        "service times (modelled)"}
+    return out
 
 
+def run_oracle_leg(workload, accuracy_path, serve_requests, no_cpu_baseline):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-leg", "--workload", workload,
+           "--serve-requests", str(serve_requests)]
+    if accuracy_path:
+        cmd += ["--accuracy-in", accuracy_path]
+    if no_cpu_baseline:
+        cmd += ["--no-cpu-baseline"]
+    print("[bench] oracle leg (cpu baseline and accuracy) ...", file=sys.stderr, flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
+    if r.returncode != 0:
+        return {"error": r.stderr[-800:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+# ------------------------------------------------------------------------------------------
+# GPU legs
+# ------------------------------------------------------------------------------------------
 def recorded_traffic(workload: str, kernel_key: str):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
     record (profiles/traffic.json), or None when the record is for another workload or
@@ -81,24 +319,22 @@ def recorded_traffic(workload: str, kernel_key: str):
         return None
 
 
-def run_cpu_baseline(workload: str):
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--workload", workload]
-    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=600)
-    if r.returncode != 0:
-        return {"error": r.stderr[-500:]}
-    return json.loads(r.stdout.strip().splitlines()[-1])
+def golden_its():
+    try:
+        return json.load(open(os.path.join(ROOT, "tests", "golden", "its.json")))
+    except (OSError, ValueError):
+        return {}
 
 
-def run_serving(count: int, slots: int, per_grid: int = 1) -> dict:
-    """Request loop: `count` independent mixed-precision steps arriving by a Poisson
-    process at 200 req/s (grid 32..256, disk or ellipse, 216 to 12,150 triangles; request
-    i draws u^n from seed 1000 + i); HBM budget = free memory - 8 GB."""
+def run_serving(count: int, slots: int, prec, per_grid: int = 1) -> dict:
+    """Request loop: `count` independent steps arriving by a Poisson process at 200 req/s
+    (grid 32..256, disk or ellipse, 216 to 12,150 triangles; request i draws u^n from seed
+    1000 + i) in the given precision; HBM budget = free memory - 8 GB."""
     from paper_2301_10041_amd import fsi, inputs, serve
 
     trace = inputs.request_trace(count, 200.0, seed=4)
     reqs = serve.requests_from_trace(trace)
-    srv = serve.Server(max_slots=slots, prec=fsi.FP32, pc=fsi.PC_TRI, rtol=1e-8, slots_per_grid=per_grid)
+    srv = serve.Server(max_slots=slots, prec=prec, pc=fsi.PC_TRI, rtol=1e-8, slots_per_grid=per_grid)
     # resident slots sized for the largest solid of the trace, per_grid per grid size, each
     # with a context for every lane of its batches
     warm = [inputs.Workload(f"warm{n}", n, [inputs.Solid(45, (0.5, 0.5), 0.2)], dt=0.01)
@@ -108,38 +344,182 @@ def run_serving(count: int, slots: int, per_grid: int = 1) -> dict:
     res = srv.run(reqs)
     wall = time.perf_counter() - t0
     summ = serve.summarize(res)
-    out = {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in summ.items()}
+    out = dict(summ)
     out.update(slots=slots, slots_per_grid=per_grid, max_inflight=srv.max_inflight, evictions=srv.evictions,
                jobs=srv.batches, requests_per_job=round(srv.batched / max(srv.batches, 1), 2),
                lanes={n: srv.lanes(n) for n in (32, 64, 128, 256)},
                budget_gb=round(srv.budget / 2**30, 1), wall_s=round(wall, 3),
-               steps_per_s=float(f"{len(res) / wall:.6g}"), dtype="f32+f64",
-               trace="512 requests, Poisson 200 req/s, n in {32,64,128,256}, m in 6..45")
+               steps_per_s=len(res) / wall, dtype="f64" if prec == fsi.FP64 else "f32+f64",
+               trace=f"{count} requests, Poisson 200 req/s, n in {{32,64,128,256}}, m in 6..45")
     srv.close()
+    return out
+
+
+def time_loop(ctx, u0, Xs, N2, opts, warmup, steps, tag, profile=False, keep_first=False):
+    """fsi_step over positions Xs (u^{n+1} of each step is u^n of the next); returns the
+    timing record and (optionally) the state after the first step."""
+    import torch
+    u = u0.clone()
+    N = ctx.sizes["N"]
+    state = torch.zeros(N, dtype=torch.float64, device=u0.device)
+    first = None
+    for k in range(warmup):
+        st = ctx.step(u, Xs[k], state, opts)
+        if k == 0 and keep_first:
+            first = state.cpu().numpy()
+        u.copy_(state[:2 * N2])
+        print(f"[bench {tag}] warmup {k}: its={st['its']} inner={st['inner_its']} "
+              f"relres={st['relres_true']:.2e} t={st['t_coup'] + st['t_rhs'] + st['t_solve']:.3f}s",
+              file=sys.stderr, flush=True)
+    if profile:
+        ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(warmup, warmup + steps):
+        st = ctx.step(u, Xs[k], state, opts)
+        u.copy_(state[:2 * N2])
+        stats.append(st)
+        print(f"[bench {tag}] step {k}: its={st['its']} inner={st['inner_its']} refin={st['refinements']} "
+              f"relres={st['relres_true']:.2e} coup={st['t_coup']:.4f}s solve={st['t_solve']:.3f}s",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt_total = time.perf_counter() - t0
+    rec = dict(value=steps / dt_total, ms_per_step=1e3 * dt_total / steps,
+               its=[s["its"] for s in stats], inner_its=[s["inner_its"] for s in stats],
+               restarts=[s["restarts"] for s in stats],
+               relres_true=max(s["relres_true"] for s in stats),
+               t_coup_ms=1e3 * sum(s["t_coup"] for s in stats) / len(stats),
+               t_solve_ms=1e3 * sum(s["t_solve"] for s in stats) / len(stats))
+    if profile:
+        prec = opts.prec if opts.prec != 2 else 1
+        launches, kern_ms, bpl = ctx.profile_read(prec)
+        ctx.profile(False)
+        avg_s = kern_ms / max(launches, 1) / 1e3
+        rec["kernel"] = dict(launches=launches, avg_us=1e6 * avg_s, bytes_per_launch=bpl,
+                             achieved_gbs=bpl / avg_s / 1e9 if launches else 0.0)
+    return rec, first
+
+
+def step_roofline(ctx, n, rec, prec, pc):
+    sz = ctx.refresh_sizes()
+    its = rec["its"]
+    inner = rec["inner_its"]
+    rs = rec["restarts"]
+    bs = [step_bytes(n, sz["Ns"], sz["nnz_s"], sz["nnz_Cf"], sz["n_pairs"], i, k, r, prec, pc)
+          for i, k, r in zip(its, inner, rs)]
+    b = sum(bs) / len(bs)
+    gbs = b / (rec["ms_per_step"] * 1e-3) / 1e9
+    return dict(bytes_per_step=b, achieved_gbs=gbs, peak=HBM_PEAK_GBS, frac=gbs / HBM_PEAK_GBS,
+                roofline_ms=b / (HBM_PEAK_GBS * 1e9) * 1e3, ms_per_step=rec["ms_per_step"],
+                its_mean=sum(its) / len(its), inner_its_mean=sum(inner) / len(inner))
+
+
+def config_legs(args, fsi, inputs, torch, dev, save):
+    """The other workloads: 32^2 (both preconditioners), 256^2 ellipse (both), 512^2 rotating
+    disk time loop (100 steps)."""
+    import numpy as np
+    gold = golden_its()
+    out = {}
+
+    def vec(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    def dirichlet_zeroed(b, n):
+        L = 2 * n + 1
+        I, J = np.meshgrid(np.arange(L), np.arange(L), indexing="xy")
+        bnd = ((I == 0) | (J == 0) | (I == 2 * n) | (J == 2 * n)).ravel()
+        N2 = L * L
+        b = b.copy()
+        b[:N2][bnd] = 0.0
+        b[N2:2 * N2][bnd] = 0.0
+        b[2 * N2] = 0.0
+        return b
+
+    for name, reps in (("disk32", 5), ("ellipse256", 3)):
+        wl = inputs.WORKLOADS[name]
+        xy, tri = wl.solid_mesh()
+        ctx = fsi.Context.from_workload(wl)
+        N = ctx.sizes["N"]
+        ctx.assemble_coupling(vec(np.concatenate([xy[:, 0], xy[:, 1]])))
+        b = vec(dirichlet_zeroed(inputs.uniform(N, wl.seed), wl.n))
+        rec = {"n": wl.n, "unknowns": N, "solid_triangles": int(tri.shape[0])}
+        for pcn in ("diag", "tri"):
+            for tag, prec in (("fp64", fsi.FP64), ("mixed", fsi.FP32)):
+                opts = fsi.Opts(pc=fsi.PC_TRI if pcn == "tri" else fsi.PC_DIAG, prec=prec, rtol=1e-8)
+                x = torch.zeros(N, dtype=torch.float64, device=dev)
+                ctx.gmres_solve(b, x, opts)
+                ts = []
+                for _ in range(reps):
+                    x.zero_()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st = ctx.gmres_solve(b, x, opts)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                ms = 1e3 * sorted(ts)[len(ts) // 2]
+                sz = ctx.refresh_sizes()
+                bb = step_bytes(wl.n, sz["Ns"], sz["nnz_s"], sz["nnz_Cf"], 0, st["its"], st["inner_its"],
+                                st["restarts"], tag, pcn)
+                r = dict(its=st["its"], its_oracle=gold.get(name, {}).get(pcn, {}).get("its"),
+                         inner_its=st["inner_its"], solve_ms=ms, relres_true=st["relres_true"],
+                         alg_gbs=bb / (ms * 1e-3) / 1e9, hbm_frac=bb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                rec[f"{pcn}_{tag}"] = r
+                if name == "disk32":
+                    save[f"disk32_{pcn}_{tag}"] = x.cpu().numpy()
+                print(f"[bench {name} {pcn} {tag}] its={st['its']} (oracle {r['its_oracle']}) solve={ms:.1f} ms",
+                      file=sys.stderr, flush=True)
+        ctx.close()
+        out[name] = rec
+    # the 512^2 time loop: 100 steps of dt 1e-3, prescribed rotation, u^0 = 0
+    wl = inputs.WORKLOADS["rotdisk512"]
+    xy, tri = wl.solid_mesh()
+    ctx = fsi.Context.from_workload(wl)
+    N2 = ctx.sizes["N2"]
+    steps = args.loop_steps
+    Xs = [vec(np.concatenate(list(inputs.rotation(xy, (0.5, 0.5), OMEGA * k * wl.dt).T))) for k in range(steps + 1)]
+    rec = {"n": wl.n, "unknowns": ctx.sizes["N"], "solid_triangles": int(tri.shape[0]), "steps": steps,
+           "dt": wl.dt}
+    u0 = torch.zeros(2 * N2, dtype=torch.float64, device=dev)
+    for tag, prec in (("fp64", fsi.FP64), ("mixed", fsi.FP32)):
+        opts = fsi.Opts(pc=fsi.PC_TRI, prec=prec, rtol=1e-8)
+        r, _ = time_loop(ctx, u0, Xs, N2, opts, 1, steps, f"rotdisk512 {tag}")
+        rec[tag] = dict(steps_per_s=r["value"], ms_per_step=r["ms_per_step"], t_coup_ms=r["t_coup_ms"],
+                        t_sol_ms=r["t_solve_ms"], its_mean=sum(r["its"]) / steps,
+                        its_max=max(r["its"]), inner_its_mean=sum(r["inner_its"]) / steps,
+                        relres_true_max=r["relres_true"])
+    if "rotdisk512_step0" in gold:
+        rec["its_oracle_step0"] = gold["rotdisk512_step0"]["tri"]["its"]
+    ctx.close()
+    out["rotdisk512"] = rec
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="twodisk1024")
-    ap.add_argument("--prec", choices=["both", "fp64", "fp32"], default="both")
     ap.add_argument("--pc", choices=["tri", "diag"], default="tri")
+    ap.add_argument("--loop-steps", type=int, default=100, help="steps of the 512^2 time loop")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-baseline-only", action="store_true")
+    ap.add_argument("--no-oracle", action="store_true", help="skip the whole oracle leg")
+    ap.add_argument("--oracle-leg", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--accuracy-in", default="", help=argparse.SUPPRESS)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-fixed-cost", action="store_true",
                     help="skip the fixed-cost inexact A11 leg (inner_mode 1)")
+    ap.add_argument("--no-ir", action="store_true", help="skip the FP32-refinement leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run 3 plain device copies of 2 GiB (counter calibration)")
     args = ap.parse_args()
 
-    if args.cpu_baseline_only:
-        print(json.dumps(cpu_baseline_leg(args.workload)))
+    if args.oracle_leg:
+        print(json.dumps(oracle_leg(args)))
         return 0
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
@@ -174,114 +554,106 @@ def main():
     for k in range(total):
         X = inputs.rotation(xy, (0.5, 0.5), OMEGA * k * wl.dt)
         Xs.append(torch.from_numpy(np.concatenate([X[:, 0], X[:, 1]])).to(dev))
-    state = torch.zeros(N, dtype=torch.float64, device=dev)
     pc = fsi.PC_TRI if args.pc == "tri" else fsi.PC_DIAG
-    precs = {"both": [fsi.FP64, fsi.FP32], "fp64": [fsi.FP64], "fp32": [fsi.FP32]}[args.prec]
+    save = {}
     res = {}
-    for prec in precs:
-        tag = "fp64" if prec == fsi.FP64 else "mixed"
+    forms = [("fp64", fsi.FP64), ("mixed", fsi.FP32)] + ([] if args.no_ir else [("fp32_ir", fsi.FP32_IR)])
+    for tag, prec in forms:
         opts = fsi.Opts(restart=30, rtol=1e-8, pc=pc, prec=prec)
-        # time loop: u^{n+1} of each step is u^n of the next (reset per precision)
-        u = u0.clone()
-        for k in range(args.warmup):
-            st = ctx.step(u, Xs[k], state, opts)
-            u.copy_(state[:2 * N2])
-            print(f"[bench {tag}] warmup {k}: its={st['its']} inner={st['inner_its']} "
-                  f"relres={st['relres_true']:.2e} t={st['t_coup'] + st['t_rhs'] + st['t_solve']:.3f}s",
-                  file=sys.stderr, flush=True)
-        ctx.profile(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        stats = []
-        for k in range(args.warmup, total):
-            st = ctx.step(u, Xs[k], state, opts)
-            u.copy_(state[:2 * N2])
-            stats.append(st)
-            print(f"[bench {tag}] step {k}: its={st['its']} inner={st['inner_its']} "
-                  f"relres={st['relres_true']:.2e} coup={st['t_coup']:.4f}s solve={st['t_solve']:.3f}s",
-                  file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        dt_total = time.perf_counter() - t0
-        launches, kern_ms, bpl = ctx.profile_read(prec)
-        ctx.profile(False)
-        avg_s = kern_ms / max(launches, 1) / 1e3
-        achieved = bpl / avg_s / 1e9 if launches else 0.0
-        res[tag] = dict(
-            value=args.steps / dt_total, ms_per_step=1e3 * dt_total / args.steps,
-            its=[s["its"] for s in stats], inner_its=[s["inner_its"] for s in stats],
-            relres_true=max(s["relres_true"] for s in stats),
-            t_coup_ms=1e3 * sum(s["t_coup"] for s in stats) / len(stats),
-            t_solve_ms=1e3 * sum(s["t_solve"] for s in stats) / len(stats),
-            kernel=dict(launches=launches, avg_us=1e6 * avg_s, bytes_per_launch=bpl,
-                        achieved_gbs=achieved))
+        rec, first = time_loop(ctx, u0, Xs, N2, opts, args.warmup, args.steps, tag, profile=tag != "fp32_ir",
+                               keep_first=True)
+        res[tag] = rec
+        if first is not None and args.workload == "twodisk1024":
+            save[f"big_{tag}"] = first
+    if args.workload == "twodisk1024" and "big_fp64" in save:
+        # the first step of every form has the same inputs: u^0 and X^0
+        b = torch.zeros(N, dtype=torch.float64, device=dev)
+        ctx.assemble_coupling(Xs[0])
+        ctx.build_rhs(u0, Xs[0], b)
+        save["big_u"] = u0.cpu().numpy()
+        save["big_bnorm"] = np.array(float(torch.linalg.norm(b)))
+        ref = save["big_fp64"]
+        for tag in ("mixed", "fp32_ir"):
+            if f"big_{tag}" in save:
+                res[tag]["vs_fp64_first_step"] = float(np.linalg.norm(save[f"big_{tag}"] - ref) / np.linalg.norm(ref))
+        del b
+    sroof = {tag: step_roofline(ctx, wl.n, res[tag], "fp64" if tag == "fp64" else "fp32", args.pc)
+             for tag in res}
     # the fixed-cost inexact A11 (inner_mode 1: one application of the inner preconditioner,
     # no inner MINRES), timed the same way; reported beside the method's configuration
     fixed = {}
     if not args.no_fixed_cost:
-        for prec in precs:
-            tag = "fp64" if prec == fsi.FP64 else "mixed"
+        for tag, prec in (("fp64", fsi.FP64), ("mixed", fsi.FP32)):
             opts = fsi.Opts(restart=30, rtol=1e-8, pc=pc, prec=prec, inner_mode=1)
-            u = u0.clone()
-            for k in range(args.warmup):
-                ctx.step(u, Xs[k], state, opts)
-                u.copy_(state[:2 * N2])
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            stats = []
-            for k in range(args.warmup, total):
-                st = ctx.step(u, Xs[k], state, opts)
-                u.copy_(state[:2 * N2])
-                stats.append(st)
-                print(f"[bench fixed-cost {tag}] step {k}: its={st['its']} relres={st['relres_true']:.2e} "
-                      f"solve={st['t_solve']:.3f}s", file=sys.stderr, flush=True)
-            torch.cuda.synchronize()
-            dt_total = time.perf_counter() - t0
-            fixed[tag] = dict(value=float(f"{args.steps / dt_total:.6g}"),
-                              ms_per_step=round(1e3 * dt_total / args.steps, 2),
-                              its=[s["its"] for s in stats],
-                              relres_true=float(f"{max(s['relres_true'] for s in stats):.6g}"))
-    main_tag = "fp64" if "fp64" in res else "mixed"
-    m = res[main_tag]
+            r, _ = time_loop(ctx, u0, Xs, N2, opts, args.warmup, args.steps, f"fixed-cost {tag}")
+            fixed[tag] = dict(value=r["value"], ms_per_step=r["ms_per_step"], its=r["its"],
+                              relres_true=r["relres_true"])
+    ctx.close()
+    del Xs, u0
+    torch.cuda.empty_cache()
+    # the two-disk geometry at 128^2: steps checked against the oracle's direct solve
+    wl128 = inputs.WORKLOADS["twodisk128"]
+    ctx128 = fsi.Context.from_workload(wl128)
+    xy128, _ = wl128.solid_mesh()
+    X128 = inputs.rotation(xy128, (0.5, 0.5), OMEGA * wl128.dt)
+    X128d = torch.from_numpy(np.concatenate([X128[:, 0], X128[:, 1]])).to(dev)
+    u128 = torch.from_numpy(inputs.uniform(2 * ctx128.sizes["N2"], wl128.seed)).to(dev)
+    for tag, prec in forms:
+        s128 = torch.zeros(ctx128.sizes["N"], dtype=torch.float64, device=dev)
+        ctx128.step(u128, X128d, s128, fsi.Opts(pc=pc, prec=prec, rtol=1e-8))
+        save[f"twodisk128_{tag}"] = s128.cpu().numpy()
+    ctx128.close()
+
+    configs = {} if args.no_configs else config_legs(args, fsi, inputs, torch, dev, save)
+    m = res["fp64"]
     k = m["kernel"]
     roofline = {"bound": "hbm", "achieved": round(k["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(k["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                "traffic": recorded_traffic(args.workload, "k_cheb3<double>")
-                if main_tag == "fp64" else None,
-                "kernel": ("k_cheb3<%s> (finest-level matrix-free A_f smoothing: the coarse "
-                           "correction added while staging x, then the three post-smoothing "
-                           "Chebyshev steps, in one launch)"
-                           % ("double" if main_tag == "fp64" else "float")),
+                "traffic": recorded_traffic(args.workload, "k_cheb3<double>"),
+                "kernel": "k_cheb3<double> (finest-level matrix-free A_f smoothing: the coarse correction added "
+                          "while staging x, then the three post-smoothing Chebyshev steps, in one launch)",
                 "bytes_per_launch": k["bytes_per_launch"], "avg_us": round(k["avg_us"], 2),
                 "launches": k["launches"]}
     out = {
         "metric": "FSI time-steps/s at 1024^2 fluid (FP64 vs mixed) + batched p50/p99 latency",
-        "value": float(f"{m['value']:.6g}"), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "value": _f(m["value"]), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(m["ms_per_step"], 2), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if main_tag == "fp64" else "f32+f64",
-        "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl.n}^2 P2/P1 fluid, "
                                f"{len(wl.solids)} disk(s), {sz['Nt']} P1 solid triangles, "
                                f"{N} unknowns, block-{args.pc} FGMRES(30) rtol 1e-8",
                    "n": wl.n, "unknowns": N, "solid_triangles": sz["Nt"], "pc": args.pc,
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "step_roofline": dict(sroof, model="bench.step_bytes: per-kernel algorithmic bytes x launches of a step, "
+                                           "from the measured outer and inner step counts"),
         "setup_s": round(t_setup, 3),
     }
     for tag, r in res.items():
-        out[tag] = {kk: (float(f"{v:.6g}") if isinstance(v, float) else v) for kk, v in r.items()}
-    if "fp64" in res and "mixed" in res:
-        out["mixed_speedup"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
+        out[tag] = _round(r)
+    out["mixed_speedup"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
+    if "fp32_ir" in res:
+        out["fp32_ir_speedup"] = round(res["fp32_ir"]["value"] / res["fp64"]["value"], 3)
     if fixed:
-        out["fixed_cost_a11"] = dict(fixed, note="A11^{-1} by one application of its preconditioner "
-                                                 "(inner_mode 1), no inner MINRES: more outer steps than "
-                                                 "with the block inverses, so not the method's configuration")
-    ctx.close()
-    del state, Xs, u0
-    torch.cuda.empty_cache()
+        out["fixed_cost_a11"] = _round(dict(fixed, note="A11^{-1} by one application of its preconditioner "
+                                                        "(inner_mode 1), no inner MINRES: more outer steps than "
+                                                        "with the block inverses, so not the method's configuration"))
+    if configs:
+        out["configs"] = _round(configs)
     if not args.no_serve:
-        out["serving"] = run_serving(args.serve_requests, args.serve_slots)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = run_cpu_baseline(args.workload)
+        out["serving"] = {"mixed": _round(run_serving(args.serve_requests, args.serve_slots, fsi.FP32)),
+                          "fp64": _round(run_serving(args.serve_requests, args.serve_slots, fsi.FP64))}
+    if not args.no_oracle:
+        with tempfile.TemporaryDirectory() as td:
+            path = os.path.join(td, "gpu_results.npz")
+            np.savez(path, **save)
+            leg = run_oracle_leg(args.workload, path, args.serve_requests, args.no_cpu_baseline)
+        for key in ("cpu_baseline", "cpu_serving", "accuracy"):
+            if key in leg:
+                out[key] = _round(leg[key])
+        if "error" in leg:
+            out["oracle_leg_error"] = leg["error"]
+    out["step_roofline"] = _round(out["step_roofline"])
     print(json.dumps(out))
     return 0
 

@@ -3,13 +3,14 @@ disk, 1024^2 two disks: the bench configuration), where the oracle cannot assemb
 solve the whole system.  Sampled outputs that the oracle computes one by one:
 intersection pieces of sampled solid triangles (bit-exact), sampled rows of C_f
 (bit-exact pattern), sampled rows of A_f, M_f, B and B^T, sampled rows of the operator
-on a random vector, and the residual of the GPU's step solution on sampled rows."""
+on a random vector, and the residual of the GPU's step solution on sampled rows, with the
+right-hand side and the operator rows both the oracle's (oracle.sampled)."""
 import zlib
 
 import numpy as np
 import pytest
 
-from oracle import coupling, fluid, solid
+from oracle import coupling, fluid, sampled
 from paper_2301_10041_amd import fsi, inputs
 
 from gpu_helpers import soa, to_dev, to_host, torch_dev
@@ -98,109 +99,35 @@ def test_sampled_fluid_rows(full):
         assert np.abs(val[rp[r]:rp[r + 1]] - np.array(list(BTref[r].values()))).max() <= 1e-13 / n
 
 
-def _oracle_rows(full, vel_rows, p_rows, s_nodes):
-    """Oracle rows of the operator at sampled velocity, pressure and solid rows, as
-    functions of a full vector x (FP64)."""
-    wl, xy, tri, X, n2e = (full[k] for k in ("wl", "xy", "tri", "X", "n2e"))
-    n = wl.n
-    L = 2 * n + 1
-    N2, Np, Ns = L * L, (n + 1) ** 2, xy.shape[0]
-    A, M = fluid.rows_Af(n, vel_rows, wl.nu, wl.rho, wl.dt)
-    BT = fluid.rows_BT(n, vel_rows)
-    B = fluid.rows_B(n, p_rows)
-    # C_f^T rows at the sampled velocity nodes: the solid triangles whose bounding box meets
-    # the cells around the node
-    P = X[tri]
-    lo, hi = P.min(axis=1), P.max(axis=1)
-    cols_of = {}
-    for r in vel_rows:
-        I, J = r % L, r // L
-        x0, x1 = (max(I - 2, 0)) / (2 * n), (min(I + 2, 2 * n)) / (2 * n)
-        y0, y1 = (max(J - 2, 0)) / (2 * n), (min(J + 2, 2 * n)) / (2 * n)
-        hit = np.nonzero((hi[:, 0] >= x0) & (lo[:, 0] <= x1) & (hi[:, 1] >= y0) & (lo[:, 1] <= y1))[0]
-        cols_of[r] = hit
-    els = sorted({int(e) for h in cols_of.values() for e in h} | set(_star(n2e, s_nodes)))
-    Cf, _ = coupling.assemble(X, xy, tri[els], n) if els else (None, None)
-    CfT = Cf.T.tocsr() if Cf is not None else None
-    S = solid.assemble(xy, tri[_star(n2e, s_nodes)], wl.kappa)
-    inv_dt = 1.0 / wl.dt
-
-    def apply(x):
-        ux, uy, p = x[:N2], x[N2:2 * N2], x[2 * N2:2 * N2 + Np]
-        Xx, Xy = x[2 * N2 + Np:2 * N2 + Np + Ns], x[2 * N2 + Np + Ns:2 * N2 + Np + 2 * Ns]
-        lx, ly = x[2 * N2 + Np + 2 * Ns:2 * N2 + Np + 3 * Ns], x[2 * N2 + Np + 3 * Ns:]
-        out = {}
-        for r in vel_rows:
-            sx = sum(v[0] * ux[c] + v[1] * uy[c] for c, v in A[r].items())
-            sy = sum(v[2] * ux[c] + v[3] * uy[c] for c, v in A[r].items())
-            sx -= sum(v[0] * p[c] for c, v in BT[r].items())
-            sy -= sum(v[1] * p[c] for c, v in BT[r].items())
-            if CfT is not None:
-                cs, vs = CfT.indices[CfT.indptr[r]:CfT.indptr[r + 1]], CfT.data[CfT.indptr[r]:CfT.indptr[r + 1]]
-                sx += vs @ lx[cs]
-                sy += vs @ ly[cs]
-            out[("ux", r)] = sx
-            out[("uy", r)] = sy
-        for k in p_rows:
-            s = -sum(v[0] * ux[c] + v[1] * uy[c] for c, v in B[k].items())
-            out[("p", k)] = s + (p[0] if k == 0 else 0.0)
-        As, Cs = S["As"].tocsr(), S["Ms"].tocsr()
-        for l in s_nodes:
-            sl = slice(As.indptr[l], As.indptr[l + 1])
-            cc = As.indices[sl]
-            out[("Xx", l)] = As.data[sl] @ Xx[cc] - Cs.data[sl] @ lx[cc]
-            out[("Xy", l)] = As.data[sl] @ Xy[cc] - Cs.data[sl] @ ly[cc]
-            fc, fv = Cf.indices[Cf.indptr[l]:Cf.indptr[l + 1]], Cf.data[Cf.indptr[l]:Cf.indptr[l + 1]]
-            out[("lx", l)] = fv @ ux[fc] - inv_dt * (Cs.data[sl] @ Xx[cc])
-            out[("ly", l)] = fv @ uy[fc] - inv_dt * (Cs.data[sl] @ Xy[cc])
-        return out
-
-    return apply
-
-
-def _index(full, key):
-    wl, xy = full["wl"], full["xy"]
-    n = wl.n
-    N2, Np, Ns = (2 * n + 1) ** 2, (n + 1) ** 2, xy.shape[0]
-    off = dict(ux=0, uy=N2, p=2 * N2, Xx=2 * N2 + Np, Xy=2 * N2 + Np + Ns, lx=2 * N2 + Np + 2 * Ns,
-               ly=2 * N2 + Np + 3 * Ns)
-    return off[key[0]] + key[1]
-
-
-def _samples(full):
+def _sampled(full):
+    """The oracle's rows of eq. (matrix) at seeded sampled rows (oracle.sampled)."""
     wl, xy, tri, X, rng = (full[k] for k in ("wl", "xy", "tri", "X", "rng"))
-    n = wl.n
-    L = 2 * n + 1
-    # velocity rows: random ones plus nodes under the solid (non-empty C_f^T rows)
-    cen = X[tri].mean(axis=1)
-    under = [int(round(c[1] * 2 * n)) * L + int(round(c[0] * 2 * n)) for c in cen[rng.choice(len(cen), 20)]]
-    vel = sorted(set(rng.choice(L * L, 60, replace=False).tolist()) | set(under))
-    prs = sorted(set(rng.choice((n + 1) ** 2, 40, replace=False).tolist()) | {0})
-    sol = sorted(rng.choice(xy.shape[0], 25, replace=False).tolist())
-    return vel, prs, sol
+    vel, prs, sol = sampled.sample_rows(wl.n, X, tri, xy.shape[0], rng)
+    return sampled.SampledSystem(wl.n, xy, tri, X, vel, prs, sol, wl.nu, wl.rho, wl.dt, wl.kappa)
 
 
 def test_sampled_operator_rows(full):
     ctx = full["ctx"]
-    vel, prs, sol = _samples(full)
-    apply = _oracle_rows(full, vel, prs, sol)
+    ss = _sampled(full)
     N = ctx.sizes["N"]
     x = full["rng"].uniform(-1, 1, N)
     torch = torch_dev()
     y = torch.zeros(N, dtype=torch.float64, device="cuda")
     ctx.apply_operator(to_dev(x), y, fsi.FP64)
     y = to_host(y)
-    ref = apply(x)
+    ref = ss.apply(x)
     scale = max(abs(v) for v in ref.values())
     for key, v in ref.items():
-        assert abs(y[_index(full, key)] - v) <= 1e-12 * scale, key
+        assert abs(y[ss.index(key)] - v) <= 1e-12 * scale, key
 
 
 @pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
 def test_step_residual_on_sampled_rows(full, prec):
-    """The GPU step solution satisfies the oracle's equations on sampled rows to the
-    solve tolerance: |b_i - (A x)_i| <= 1e-8 ||b||_2."""
-    wl, xy, ctx = full["wl"], full["xy"], full["ctx"]
+    """The GPU step solution satisfies the oracle's equations on sampled rows to the solve
+    tolerance: |b_i - (A x)_i| <= 1e-8 ||b||_2, with b_i and (A x)_i the oracle's rows (the
+    GPU's right-hand side is checked against the oracle's on the same rows: g1 on velocity
+    rows, zero on pressure and X rows, g2 on lam rows)."""
+    wl, ctx = full["wl"], full["ctx"]
     N, N2 = ctx.sizes["N"], ctx.sizes["N2"]
     u = inputs.uniform(2 * N2, wl.seed)
     torch = torch_dev()
@@ -212,17 +139,14 @@ def test_step_residual_on_sampled_rows(full, prec):
     b = torch.zeros(N, dtype=torch.float64, device="cuda")
     ctx.build_rhs(to_dev(u), to_dev(soa(full["X"])), b)
     b = to_host(b)
-    vel, prs, sol = _samples(full)
-    apply = _oracle_rows(full, vel, prs, sol)
-    # the oracle's right-hand side on the sampled rows
-    n = wl.n
-    L = 2 * n + 1
-    _, M = fluid.rows_Af(n, vel, wl.nu, wl.rho, wl.dt)
-    bnd = fluid.boundary_p2(n)
-    for r in vel:
-        for comp, key in ((0, "ux"), (1, "uy")):
-            g = 0.0 if bnd[r] else (wl.rho / wl.dt) * sum(m * (0.0 if bnd[c] else u[comp * N2 + c]) for c, m in M[r].items())
-            assert abs(b[_index(full, (key, r))] - g) <= 1e-12 * max(1.0, abs(g))
+    ss = _sampled(full)
+    b_ref = ss.rhs(u)
+    bscale = max(abs(v) for v in b_ref.values())
+    for key, g in b_ref.items():
+        assert abs(b[ss.index(key)] - g) <= 1e-12 * bscale, key
     bn = np.linalg.norm(b)
-    for key, v in apply(x).items():
-        assert abs(b[_index(full, key)] - v) <= 1e-8 * bn, key
+    res = ss.residual(x, u)
+    worst = max(abs(v) for v in res.values()) / bn
+    print(f"  sampled-row residual (oracle rows) max |b_i - (A x)_i| / ||b|| = {worst:.2e}", flush=True)
+    for key, v in res.items():
+        assert abs(v) <= 1e-8 * bn, key

@@ -249,3 +249,29 @@ def test_direct_solve_refinement_reaches_rounding_level():
     assert info["converged"]
     assert np.abs(x - xs).max() <= 1e-12 * np.abs(xs).max()
     assert np.abs(x - x0).max() > 10 * np.abs(x - xs).max()   # the refinement is what gets there
+
+
+def test_sampled_rows_equal_whole_system():
+    """oracle.sampled (rows of eq. (matrix) built around sampled nodes, for grids too large to
+    assemble whole) against the rows of the whole assembled system and right-hand side."""
+    from oracle import sampled
+    wl = inputs.small_workload(16, 5, (0.47, 0.52), 0.22)
+    S = system.FSISystem.from_workload(wl)
+    X = inputs.rotation(S.xy_ref, (0.47, 0.52), 0.3)
+    S.set_position(X)
+    rng = np.random.default_rng(4)
+    vel, prs, sol = sampled.sample_rows(wl.n, X, S.tri, S.lay.Ns, rng, n_vel=80, n_p=30, n_s=20, n_under=30)
+    ss = sampled.SampledSystem(wl.n, S.xy_ref, S.tri, X, vel, prs, sol, wl.nu, wl.rho, wl.dt, wl.kappa)
+    A = S.matrix()
+    x = rng.uniform(-1, 1, S.lay.N)
+    u = rng.uniform(-1, 1, 2 * S.lay.N2)
+    y, b = A @ x, S.rhs(u, X)
+    got, gb = ss.apply(x), ss.rhs(u)
+    scale = np.abs(y).max()
+    assert len(got) == 2 * len(vel) + len(prs) + 4 * len(sol)
+    for key, v in got.items():
+        i = ss.index(key)
+        assert abs(v - y[i]) <= 1e-12 * scale, key
+        assert abs(gb[key] - b[i]) <= 1e-12 * np.abs(b).max(), key
+    # some sampled velocity rows have C_f^T entries (the rows under the solid)
+    assert any(ss.CfT.indptr[r + 1] > ss.CfT.indptr[r] for r in vel)
