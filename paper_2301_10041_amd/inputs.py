@@ -70,6 +70,32 @@ def ring_disk(m: int, center=(0.5, 0.5), radius: float = 0.2, semi_axes=None):
     return xy, tri
 
 
+def bar_mesh(nx: int, ny: int, x0=0.0, x1=0.4, y0=0.45, y1=0.55):
+    """P1 mesh of the rectangle [x0, x1] x [y0, y1] (the bar of the nonlinear test, Sec. 6.2):
+    nx x ny cells, each split along (i, j) -> (i + 1, j + 1) into two counter-clockwise
+    triangles.  Node (i, j) has index j (nx + 1) + i.  Returns ``(xy, tri)``."""
+    xs = x0 + (x1 - x0) * np.arange(nx + 1) / nx
+    ys = y0 + (y1 - y0) * np.arange(ny + 1) / ny
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    tris = []
+    for j in range(ny):
+        for i in range(nx):
+            a, b = j * (nx + 1) + i, j * (nx + 1) + i + 1
+            c, d = (j + 1) * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i
+            tris.append((a, b, c))
+            tris.append((a, c, d))
+    return xy, np.asarray(tris, dtype=np.int32)
+
+
+def bent(xy: np.ndarray, amp: float, length: float = 0.4) -> np.ndarray:
+    """A released position of the bar: every point moved down by amp (s_x / length)^2 (a
+    bending that leaves the clamped-looking left end in place)."""
+    out = xy.copy()
+    out[:, 1] = xy[:, 1] - amp * (xy[:, 0] / length) ** 2
+    return out
+
+
 def uniform(n: int, seed: int) -> np.ndarray:
     """``n`` float64 values uniform in [-1, 1) from ``numpy.random.default_rng(seed)``."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, n)
@@ -96,6 +122,16 @@ class Solid:
 
     def mesh(self):
         return ring_disk(self.m, self.center, self.radius, self.semi_axes)
+
+
+@dataclass
+class Bar(Solid):
+    """The bar [0, 0.4] x [0.45, 0.55] of the nonlinear test with nx x ny cells."""
+    nx: int = 16
+    ny: int = 4
+
+    def mesh(self):
+        return bar_mesh(self.nx, self.ny)
 
 
 @dataclass
