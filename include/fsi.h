@@ -151,7 +151,9 @@ enum fsi_block {
   FSI_BLK_CS = 5,   /* C_s: width 1, solid pattern */
   FSI_BLK_CF = 6,   /* C_f(X^n): width 1, rows solid nodes, columns P2 nodes */
   FSI_BLK_CFT = 7,  /* C_f^T: width 1, rows P2 nodes, columns solid nodes */
-  FSI_BLK_MP = 8    /* pressure mass (used by the preconditioner): width 1, P1-P1 */
+  FSI_BLK_MP = 8,   /* pressure mass (used by the preconditioner): width 1, P1-P1 */
+  FSI_BLK_KT = 9    /* solid tangent K(X) of the last fsi_solid_tangent: width 4 (xx, xy, yx, yy) on
+                       the solid pattern; FSI_E_STATE before one */
 };
 
 /* Build the time-independent blocks (Sec. 4: A_f, B, A_s, C_s), the multigrid
@@ -257,6 +259,57 @@ int fsi_step(fsi_ctx *ctx, const fsi_solve_opts *opts, const double *u_n, const 
 #define FSI_MAX_LANES 32
 int fsi_step_batch(int32_t K, fsi_ctx *const *ctxs, const fsi_solve_opts *opts, const double *const *u_n,
                    const double *const *X_n, double *const *state, fsi_solve_stats *stats, int32_t *rc);
+
+/* ---- nonlinear solid (Sec. 4, last paragraph: a nonlinear law P(F) is solved by Newton's
+ * method; Sec. 6.2: the exponential law of the nonlinear test).
+ * FSI_LAW_LINEAR: P(F) = kappa F (kappa of the solid descriptor), the law of eq. (matrix).
+ * FSI_LAW_EXP: W(F) = (gamma / (2 eta)) exp(eta (tr F^T F - 2)), P(F) = dW/dF =
+ *   gamma exp(eta (|F|^2 - 2)) F (the paper's gamma = 1.333, eta = 9.242; eta = 0 is the linear
+ *   law with kappa = gamma).
+ * The solid row of a step becomes (P(F_h^{n+1}), grad_s Y_h)_B - (lam_h^{n+1}, Y_h)_B = (f, Y_h):
+ * with P1 triangles the residual R(X)_{l,a} = sum_E |E| P_ab(F_E) (grad chi_l)_b and its tangent
+ * K(X) = dR/dX (2 x 2 blocks on the solid pattern) replace A_s X and A_s.  Vectors [x | y]. */
+enum fsi_law { FSI_LAW_LINEAR = 0, FSI_LAW_EXP = 1 };
+
+/* Select the solid law of the context (default FSI_LAW_LINEAR).  gamma > 0, eta >= 0 for
+ * FSI_LAW_EXP (ignored for the linear law).  Errors: FSI_E_ARG. */
+int fsi_set_law(fsi_ctx *ctx, int law, double gamma, double eta);
+
+/* R(X) of the context's law at the solid position X (device, 2 Ns) into R (device, 2 Ns).
+ * Errors: FSI_E_ARG. */
+int fsi_solid_residual(fsi_ctx *ctx, const double *X, double *R);
+
+/* Assemble the tangent K(X) (X device, 2 Ns) and use it in place of A_s in fsi_apply_operator,
+ * fsi_apply_precond, fsi_gmres_solve and fsi_step (the Jacobian of a Newton iteration) until the
+ * next call; X = NULL returns to A_s.  Batched steps (fsi_step_batch) always use A_s. */
+int fsi_solid_tangent(fsi_ctx *ctx, const double *X);
+
+typedef struct {
+  double rtol;      /* stop when ||G(x_k)|| <= rtol ||G(x_0)|| (Sec. 6: 1e-6) */
+  int32_t maxit;    /* Newton iterations at most (default 50) */
+} fsi_newton_opts;
+
+typedef struct {
+  int32_t nit;          /* Newton iterations (Jacobian solves) */
+  int32_t converged;
+  int32_t its_total;    /* outer GMRES steps summed over the Jacobian solves */
+  int64_t inner_its;    /* inner MINRES steps, summed */
+  double res0, res;     /* ||G(x_0)||, ||G(x_nit)|| */
+  double t_coup, t_res, t_solve;   /* seconds: C_f assembly, residuals, Jacobian solves */
+} fsi_newton_stats;
+
+/* One step of Problem 3 with the context's law by Newton's method (Sec. 4): the system
+ * G(x) = 0, eq. (matrix) with A_s X replaced by R(X), C_f(X^n) assembled once, right-hand side
+ * (g1, 0, f_X, g2); each iteration solves J(x_k) d = -G(x_k) with J the matrix of eq. (matrix)
+ * whose A_s block is K(X_k), by fsi_gmres_solve with opts (the Jacobian tolerance opts->rtol,
+ * Sec. 6: 1e-8), and sets x_{k+1} = x_k + d, until ||G(x_k)|| <= nopts->rtol ||G(x_0)||.
+ * u_n: device 2 N2; X_n: device 2 Ns; f_X: device 2 Ns load on the solid nodes, or NULL;
+ * state: device N, in: the initial guess x_0 (e.g. (u^n, 0, X^n, 0) or the previous step), out:
+ * x at n+1.  The solid block returns to what it was before the call.  stats may be NULL.
+ * Errors: FSI_E_NOCONV (Newton or a Jacobian solve did not converge; state holds the last
+ * iterate), FSI_E_NONFINITE, FSI_E_MESH, FSI_E_ARG. */
+int fsi_newton_step(fsi_ctx *ctx, const fsi_solve_opts *opts, const fsi_newton_opts *nopts, const double *u_n,
+                    const double *X_n, const double *f_X, double *state, fsi_newton_stats *stats);
 
 /* Test exports (host copies; synchronising).  fsi_export_pairs writes up to cap pieces
  * (solid triangle E, fluid triangle T) in the canonical order (by E, then cell j-major,

@@ -2,6 +2,7 @@
 // extern "C" entry points of libfsi (declared in include/fsi.h).  Every call catches
 // the library's exceptions and returns an fsi_status; the message is kept in the context.
 #include <chrono>
+#include <cmath>
 #include <cstring>
 
 #include "ctx.h"
@@ -208,6 +209,8 @@ int fsi_set_solid(fsi_ctx *ctx, const fsi_solid_desc *solid) {
     c.N = 2 * c.N2 + c.Np + 4 * ns;
     c.h_tri.assign(solid->tri, solid->tri + 3 * nt);
     c.h_xy.assign(solid->xy, solid->xy + 2 * ns);
+    c.use_kt = false;   // a tangent of the previous solid no longer fits its pattern
+    c.Kt.release();
     fsi::build_solid(c);
     fsi::make_shadow(c.S, c.stream);
     c.tmpN.reserve(c.N);
@@ -443,6 +446,58 @@ int fsi_step_batch(int32_t K, fsi_ctx *const *ctxs, const fsi_solve_opts *opts, 
   });
 }
 
+int fsi_set_law(fsi_ctx *ctx, int law, double gamma, double eta) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    FSI_REQUIRE(law == FSI_LAW_LINEAR || law == FSI_LAW_EXP, FSI_E_ARG, "unknown solid law");
+    if (law == FSI_LAW_EXP)
+      FSI_REQUIRE(gamma > 0.0 && eta >= 0.0 && std::isfinite(gamma) && std::isfinite(eta), FSI_E_ARG,
+                  "the exponential law needs gamma > 0 and eta >= 0");
+    ctx->c.law = law;
+    ctx->c.law_gamma = gamma;
+    ctx->c.law_eta = eta;
+  });
+}
+
+int fsi_solid_residual(fsi_ctx *ctx, const double *X, double *R) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    FSI_REQUIRE(X && R && X != R, FSI_E_ARG, "null or aliased vectors");
+    fsi::solid_law(ctx->c, X, R, false);
+  });
+}
+
+int fsi_solid_tangent(fsi_ctx *ctx, const double *X) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    if (!X) {
+      ctx->c.use_kt = false;
+      return;
+    }
+    fsi::solid_law(ctx->c, X, nullptr, true);
+  });
+}
+
+int fsi_newton_step(fsi_ctx *ctx, const fsi_solve_opts *opts, const fsi_newton_opts *nopts, const double *u_n,
+                    const double *X_n, const double *f_X, double *state, fsi_newton_stats *stats) {
+  if (!ctx) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    FSI_REQUIRE(opts && nopts && u_n && X_n && state, FSI_E_ARG, "null options or vectors");
+    fsi_newton_stats st{};
+    int rc = FSI_OK;
+    try {
+      fsi::newton_step(ctx->c, *opts, *nopts, u_n, X_n, f_X, state, &st);
+    } catch (const Error &e) {
+      if (e.code != FSI_E_NOCONV) throw;
+      rc = e.code;
+      ctx->c.last_error = e.what();
+    }
+    FSI_HIP(hipStreamSynchronize(ctx->c.stream));
+    if (stats) *stats = st;
+    if (rc != FSI_OK) throw Error(rc, ctx->c.last_error);
+  });
+}
+
 int fsi_export_pairs(fsi_ctx *ctx, int32_t *E, int32_t *T, int64_t cap, int64_t *count) {
   if (!ctx || !count) return FSI_E_ARG;
   return guarded(ctx, [&] {
@@ -562,6 +617,9 @@ int fsi_export_csr(fsi_ctx *ctx, int block, int64_t *nrows, int64_t *nnz, int32_
       case FSI_BLK_CF: A = &c.Cf; v = c.Cf.val.p; w = 1; break;
       case FSI_BLK_CFT: A = &c.CfT; v = c.CfT.val.p; w = 1; break;
       case FSI_BLK_MP: A = &c.Mp; v = c.Mp.val.p; w = 1; break;
+      case FSI_BLK_KT:
+        FSI_REQUIRE(c.Kt.p, FSI_E_STATE, "no solid tangent: call fsi_solid_tangent");
+        A = &c.S; v = c.Kt.p; w = 4; break;
       default: throw Error(FSI_E_ARG, "unknown block id");
     }
     if (block == FSI_BLK_CF || block == FSI_BLK_CFT)

@@ -145,6 +145,16 @@ struct Ctx {
   DevBuf<double> tmpN;     // N (operator/residual scratch)
   DevBuf<double> tmpS;     // 12 Ns (solid block scratch)
 
+  // nonlinear solid (hyper.hip): the law, and its tangent K(X) on the solid pattern (2 x 2
+  // blocks xx, xy, yx, yy) used in place of A_s by the operator and the preconditioners while
+  // use_kt is set; Newton work vectors
+  int law = FSI_LAW_LINEAR;
+  double law_gamma = 0.0, law_eta = 0.0;
+  bool use_kt = false;
+  DevBuf<double> Kt;
+  DevBuf<float> Kt32;
+  DevBuf<double> nl_b, nl_r, nl_d, nl_R;
+
   Prof prof64, prof32;        // finest-level Chebyshev product on A_f
 
   // HIP graphs of the A11 preconditioner (one per precision), replayed on fixed staging
@@ -198,6 +208,10 @@ void apply_precond(Ctx &c, int pc, int prec, const double *r, double *z);
 void apply_precond_lanes(Ctx &engine, Ctx *const *cs, int K, int pc, int prec, const double *const *r,
                          double *const *z);
 void gmres_solve(Ctx &c, const fsi_solve_opts &o, const double *b, double *x, fsi_solve_stats *st);
+// hyper.hip
+void solid_law(Ctx &c, const double *X, double *R, bool tangent);
+void newton_step(Ctx &c, const fsi_solve_opts &o, const fsi_newton_opts &no, const double *u_n, const double *X_n,
+                 const double *f_X, double *x, fsi_newton_stats *st);
 void gmres_solve_lanes(Ctx *const *cs, int K, const fsi_solve_opts &o, const double *const *b,
                        double *const *x, fsi_solve_stats *st, int *rc);
 

@@ -32,6 +32,7 @@ struct OpArgs {
   const int *b_rp, *b_col; const T *b_val;
   // solid pattern: A_s, C_s; C_f
   const int *s_rp, *s_col; const T *as_val, *cs_val;
+  const T *kt_val;   // non-null: the solid tangent (2 x 2 blocks) in place of A_s
   const int *cf_rp, *cf_col; const T *cf_val;
   const Tx *x;
   Ty *y;
@@ -97,9 +98,16 @@ __global__ void __launch_bounds__(kOpBlock) k_operator(OpArgs<T, Tx, Ty> a) {
   T aXx = 0, aXy = 0, cLx = 0, cLy = 0, cXx = 0, cXy = 0, fx = 0, fy = 0;
   for (int k = a.s_rp[l] + lane; k < a.s_rp[l + 1]; k += kG) {
     int j = a.s_col[k];
-    T as = a.as_val[k], cs = a.cs_val[k];
+    T cs = a.cs_val[k];
     T Xx = (T)xXx[j], Xy = (T)xXy[j];
-    aXx += as * Xx; aXy += as * Xy;
+    if (a.kt_val) {
+      const T *kt = a.kt_val + 4 * (int64_t)k;
+      aXx += kt[0] * Xx + kt[1] * Xy;
+      aXy += kt[2] * Xx + kt[3] * Xy;
+    } else {
+      T as = a.as_val[k];
+      aXx += as * Xx; aXy += as * Xy;
+    }
     cXx += cs * Xx; cXy += cs * Xy;
     cLx += cs * (T)xlx[j]; cLy += cs * (T)xly[j];
   }
@@ -148,6 +156,7 @@ static void launch_operator(Ctx &c, const Tx *x, Ty *y, bool fluid_only, bool so
     a.cft_rp = c.CfT.rowptr.p; a.cft_col = c.CfT.col.p; a.cft_val = vals<T>(c.CfT);
     a.s_rp = c.S.rowptr.p; a.s_col = c.S.col.p; a.as_val = vals<T>(c.S);
     a.cs_val = std::is_same<T, double>::value ? (const T *)c.Cs.p : (const T *)c.Cs32.p;
+    a.kt_val = !c.use_kt ? nullptr : std::is_same<T, double>::value ? (const T *)c.Kt.p : (const T *)c.Kt32.p;
     a.cf_rp = c.Cf.rowptr.p; a.cf_col = c.Cf.col.p; a.cf_val = vals<T>(c.Cf);
   }
   a.x = x;

@@ -1275,8 +1275,10 @@ static void a22_solve(Ctx &c, const double *rX, const double *rl, double *zX, do
   double *scr = c.tmpS.p, *u = c.tmpS.p + 6 * ns;
   const double *t = cs_solve(c, rl, scr, steps);
   lincomb(zX, t, t, -c.dt, 0.0, 2 * ns, s);
-  // u = r_X - A_s z_X;  z_lam = C_s^{-1} (A_s z_X - r_X) = -C_s^{-1} u
-  spmv<double, 1, 2, SP_RESID>(ns, c.S.rowptr.p, c.S.col.p, c.S.val.p, zX, ns, u, ns, s, rX);
+  // u = r_X - A_s z_X;  z_lam = C_s^{-1} (A_s z_X - r_X) = -C_s^{-1} u  (the tangent of the
+  // nonlinear solid in place of A_s while it is set: 2 x 2 blocks)
+  if (c.use_kt) spmv<double, 4, 2, SP_RESID>(ns, c.S.rowptr.p, c.S.col.p, c.Kt.p, zX, ns, u, ns, s, rX);
+  else spmv<double, 1, 2, SP_RESID>(ns, c.S.rowptr.p, c.S.col.p, c.S.val.p, zX, ns, u, ns, s, rX);
   const double *t2 = cs_solve(c, u, scr, steps);
   hipLaunchKernelGGL(k_negate<double>, dim3(vgrid(2 * ns)), dim3(256), 0, s, zl, t2, 2 * ns);
   FSI_CHECK_LAUNCH();
@@ -1379,7 +1381,7 @@ void apply_precond_lanes(Ctx &c, Ctx *const *cs, int K, int pc, int prec, const 
   bool fit = true;
   int ns_max = 0;
   for (int k = 0; k < K; ++k) {
-    fit = fit && a22_fits(*cs[k]);
+    fit = fit && a22_fits(*cs[k]) && !cs[k]->use_kt;
     ns_max = std::max(ns_max, (int)cs[k]->Ns);
   }
   A22Args aa{};

@@ -22,7 +22,9 @@ PC_DIAG, PC_TRI = 0, 1
 SMOOTH_CSR, SMOOTH_STENCIL = 0, 1
 MAX_LANES = 32                 # FSI_MAX_LANES: systems per fsi_step_batch
 COUPLING_SCRATCH_BYTES = 32 << 20   # FSI_COUPLING_SCRATCH_BYTES
-BLOCKS = dict(AF=0, MF=1, B=2, BT=3, AS=4, CS=5, CF=6, CFT=7, MP=8)
+BLOCKS = dict(AF=0, MF=1, B=2, BT=3, AS=4, CS=5, CF=6, CFT=7, MP=8, KT=9)
+LAW_LINEAR, LAW_EXP = 0, 1
+GAMMA, ETA = 1.333, 9.242      # the exponential law of the nonlinear test
 
 
 class FsiLibraryMissing(RuntimeError):
@@ -71,6 +73,19 @@ class SolveStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class NewtonOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32)]
+
+
+class NewtonStats(C.Structure):
+    _fields_ = [("nit", C.c_int32), ("converged", C.c_int32), ("its_total", C.c_int32), ("inner_its", C.c_int64),
+                ("res0", C.c_double), ("res", C.c_double), ("t_coup", C.c_double), ("t_res", C.c_double),
+                ("t_solve", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 _SIGS = {
@@ -96,6 +111,11 @@ _SIGS = {
     "fsi_step_batch": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(SolveOpts), C.POINTER(C.c_void_p),
                                  C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(SolveStats),
                                  C.POINTER(C.c_int32)]),
+    "fsi_set_law": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_double]),
+    "fsi_solid_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsi_solid_tangent": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fsi_newton_step": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.POINTER(NewtonOpts), C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.POINTER(NewtonStats)]),
     "fsi_export_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                    C.POINTER(C.c_int64)]),
     "fsi_export_csr": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -318,6 +338,30 @@ class Context:
         st = SolveStats()
         o = (opts or Opts()).c()
         self._check(lib().fsi_step(self._h, C.byref(o), _ptr(u_n), _ptr(X_n), _ptr(state), C.byref(st)))
+        return st.as_dict()
+
+    def set_law(self, law, gamma=GAMMA, eta=ETA):
+        """Solid law: LAW_LINEAR (P = kappa F) or LAW_EXP (the exponential law of the nonlinear test)."""
+        self._check(lib().fsi_set_law(self._h, int(law), float(gamma), float(eta)))
+
+    def solid_residual(self, X, R):
+        """R(X) of the context's law (X, R: device 2 Ns)."""
+        self._check(lib().fsi_solid_residual(self._h, _ptr(X), _ptr(R)))
+
+    def solid_tangent(self, X=None):
+        """Use the tangent K(X) in place of A_s (None: back to A_s)."""
+        self._check(lib().fsi_solid_tangent(self._h, None if X is None else _ptr(X)))
+
+    def newton_step(self, u_n, X_n, state, opts: Opts | None = None, rtol=1e-6, maxit=50, f_X=None,
+                    raise_noconv=True):
+        """One Newton step (fsi_newton_step); state holds the initial guess on entry."""
+        st = NewtonStats()
+        o = (opts or Opts()).c()
+        no = NewtonOpts(float(rtol), int(maxit))
+        rc = lib().fsi_newton_step(self._h, C.byref(o), C.byref(no), _ptr(u_n), _ptr(X_n),
+                                   None if f_X is None else _ptr(f_X), _ptr(state), C.byref(st))
+        if rc != FSI_OK and (raise_noconv or rc != FSI_E_NOCONV):
+            self._check(rc)
         return st.as_dict()
 
     def profile(self, enable=True):
