@@ -19,7 +19,8 @@ Prints one JSON line.  `value` is FP64 steps/s at 1024^2.  Beside it:
   step_roofline   algorithmic bytes of a step (model below, from the measured outer and inner
              step counts) against the step time and 8 TB/s;
   configs    the CPU-fast 32^2 case (both preconditioners), the 256^2 ellipse (both
-             preconditioners), the 512^2 rotating-disk time loop (100 steps, dt 1e-3);
+             preconditioners), the 512^2 rotating-disk time loop (100 steps, dt 1e-3), the
+             nonlinear bar at 256^2 (Newton, the paper's exponential law);
   serving    the 512-request trace in mixed precision and in FP64;
   accuracy   per-run errors against the FP64 oracle (computed in the oracle leg);
   cpu_baseline / cpu_serving  the oracle on the host's cores (bounded samples).
@@ -488,11 +489,57 @@ def config_legs(args, fsi, inputs, torch, dev, save):
                         t_sol_ms=r["t_solve_ms"], its_mean=sum(r["its"]) / steps,
                         its_max=max(r["its"]), inner_its_mean=sum(r["inner_its"]) / steps,
                         relres_true_max=r["relres_true"])
-    if "rotdisk512_step0" in gold:
-        rec["its_oracle_step0"] = gold["rotdisk512_step0"]["tri"]["its"]
     ctx.close()
     out["rotdisk512"] = rec
+    out["bar256_nonlinear"] = nonlinear_leg(args, fsi, inputs, torch, dev)
     return out
+
+
+def nonlinear_leg(args, fsi, inputs, torch, dev):
+    """The nonlinear solid (the exponential law of the paper's nonlinear test, Newton's method):
+    the bar on a 256^2 grid released from a bent position (u^0 = 0), Newton to a 1e-6 residual
+    reduction with the Jacobian systems to rtol 1e-8 (Sec. 6), each step's solution the next
+    step's initial guess, u^n and X^n; the columns of the paper's nonlinear tables per step: T_coup,
+    T_sol (Jacobian solves), Newton iterations and GMRES steps per Newton iteration."""
+    import numpy as np
+    wl = inputs.WORKLOADS["bar256"]
+    xy, tri = wl.solid_mesh()
+    ctx = fsi.Context.from_workload(wl)
+    ctx.set_law(fsi.LAW_EXP, fsi.GAMMA, fsi.ETA)
+    N, N2, Ns = ctx.sizes["N"], ctx.sizes["N2"], ctx.sizes["Ns"]
+    off = N - 4 * Ns
+    X0 = inputs.bent(xy, 0.04, x0=wl.solids[0].x0)
+    rec = {"n": wl.n, "unknowns": N, "solid_triangles": int(tri.shape[0]), "dt": wl.dt, "law": "exp",
+           "gamma": fsi.GAMMA, "eta": fsi.ETA, "steps": args.nl_steps}
+    for tag, prec in (("fp64", fsi.FP64), ("mixed", fsi.FP32)):
+        state = torch.zeros(N, dtype=torch.float64, device=dev)
+        state[off:off + Ns] = torch.from_numpy(X0[:, 0]).to(dev)
+        state[off + Ns:off + 2 * Ns] = torch.from_numpy(X0[:, 1]).to(dev)
+        opts = fsi.Opts(pc=fsi.PC_TRI, prec=prec, rtol=1e-8)
+        stats = []
+        t0 = None
+        for k in range(args.nl_steps + 1):
+            if k == 1:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            u = state[:2 * N2].clone()
+            X = state[off:off + 2 * Ns].clone()
+            st = ctx.newton_step(u, X, state, opts, rtol=1e-6)
+            if k >= 1:
+                stats.append(st)
+            print(f"[bench bar256 {tag}] step {k}: nit={st['nit']} its={st['its_total']} "
+                  f"res={st['res'] / max(st['res0'], 1e-300):.1e} coup={st['t_coup']:.4f}s solve={st['t_solve']:.3f}s",
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt_total = time.perf_counter() - t0
+        nit = sum(s["nit"] for s in stats)
+        rec[tag] = dict(steps_per_s=len(stats) / dt_total, ms_per_step=1e3 * dt_total / len(stats),
+                        nit_mean=nit / len(stats), its_per_newton=sum(s["its_total"] for s in stats) / max(nit, 1),
+                        t_coup_ms=1e3 * sum(s["t_coup"] for s in stats) / len(stats),
+                        t_sol_ms=1e3 * sum(s["t_solve"] for s in stats) / max(nit, 1),
+                        res_reduction_max=max(s["res"] / max(s["res0"], 1e-300) for s in stats))
+    ctx.close()
+    return rec
 
 
 def main():
@@ -503,6 +550,7 @@ def main():
     ap.add_argument("--workload", default="twodisk1024")
     ap.add_argument("--pc", choices=["tri", "diag"], default="tri")
     ap.add_argument("--loop-steps", type=int, default=100, help="steps of the 512^2 time loop")
+    ap.add_argument("--nl-steps", type=int, default=10, help="steps of the nonlinear bar loop")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true", help="skip the whole oracle leg")
     ap.add_argument("--oracle-leg", action="store_true", help=argparse.SUPPRESS)

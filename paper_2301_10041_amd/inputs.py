@@ -88,11 +88,11 @@ def bar_mesh(nx: int, ny: int, x0=0.0, x1=0.4, y0=0.45, y1=0.55):
     return xy, np.asarray(tris, dtype=np.int32)
 
 
-def bent(xy: np.ndarray, amp: float, length: float = 0.4) -> np.ndarray:
-    """A released position of the bar: every point moved down by amp (s_x / length)^2 (a
-    bending that leaves the clamped-looking left end in place)."""
+def bent(xy: np.ndarray, amp: float, length: float = 0.4, x0: float = 0.0) -> np.ndarray:
+    """A released position of the bar: every point moved down by amp ((s_x - x0) / length)^2 (a
+    bending that leaves the left end in place)."""
     out = xy.copy()
-    out[:, 1] = xy[:, 1] - amp * (xy[:, 0] / length) ** 2
+    out[:, 1] = xy[:, 1] - amp * ((xy[:, 0] - x0) / length) ** 2
     return out
 
 
@@ -126,12 +126,14 @@ class Solid:
 
 @dataclass
 class Bar(Solid):
-    """The bar [0, 0.4] x [0.45, 0.55] of the nonlinear test with nx x ny cells."""
+    """The bar [x0, x0 + 0.4] x [0.45, 0.55] of the nonlinear test with nx x ny cells (x0 = 0 is
+    the paper's position against the wall)."""
     nx: int = 16
     ny: int = 4
+    x0: float = 0.0
 
     def mesh(self):
-        return bar_mesh(self.nx, self.ny)
+        return bar_mesh(self.nx, self.ny, self.x0, self.x0 + 0.4)
 
 
 @dataclass
@@ -179,11 +181,23 @@ WORKLOADS = {
     "twodisk128": Workload("twodisk128", 128,
                            [Solid(14, (0.3, 0.5), 0.1), Solid(14, (0.7, 0.5), 0.1)],
                            dt=0.01, seed=3),
+    # the 512^2 rotating-disk time loop on a 256^2 grid (ring count scaled with the grid: m = 41,
+    # 10,086 triangles), dt = 1e-3: the size at which the oracle's exact block factorisations of
+    # the time loop still fit the host (its first-step iteration count)
+    "rotdisk256": Workload("rotdisk256", 256, [Solid(41, (0.5, 0.5), 0.2)], dt=1e-3, seed=2),
     # 1024^2 fluid, two disks R=0.1 at (0.3,0.5), (0.7,0.5), 75,264 triangles each, seed 3
     "twodisk1024": Workload("twodisk1024", 1024,
                             [Solid(112, (0.3, 0.5), 0.1), Solid(112, (0.7, 0.5), 0.1)],
                             dt=0.01, seed=3),
 }
+
+
+# the nonlinear test's bar (Sec. 6.2: 0.4 x 0.1, nu = 0.2, rho = 1, dt = 0.002) on a 256^2 grid
+# with solid cells of the fluid cell size (102 x 26 cells, 5,304 triangles), moved 0.05 off the
+# wall x = 0 (the clipping needs X^n(B) inside the square and nothing holds the left end on the
+# wall), released from a bent position with u^0 = 0
+WORKLOADS["bar256"] = Workload("bar256", 256, [Bar(m=0, center=(0.25, 0.5), nx=102, ny=26, x0=0.05)], nu=0.2,
+                               rho=1.0, kappa=1.333, dt=0.002, seed=5)
 
 
 def small_workload(n: int, m: int, center=(0.5, 0.5), radius=0.2, semi_axes=None,
