@@ -491,6 +491,22 @@ def config_legs(args, fsi, inputs, torch, dev, save):
                         relres_true_max=r["relres_true"])
     ctx.close()
     out["rotdisk512"] = rec
+    # the first step of the same loop at 256^2, where the oracle's counts exist
+    if "rotdisk256_step0" in gold:
+        wl = inputs.WORKLOADS["rotdisk256"]
+        xy, _ = wl.solid_mesh()
+        ctx = fsi.Context.from_workload(wl)
+        X = vec(np.concatenate([xy[:, 0], xy[:, 1]]))
+        u0 = torch.zeros(2 * ctx.sizes["N2"], dtype=torch.float64, device=dev)
+        s = torch.zeros(ctx.sizes["N"], dtype=torch.float64, device=dev)
+        r = {}
+        for pcn in ("diag", "tri"):
+            for tag, prec in (("fp64", fsi.FP64), ("mixed", fsi.FP32)):
+                st = ctx.step(u0, X, s, fsi.Opts(pc=fsi.PC_TRI if pcn == "tri" else fsi.PC_DIAG, prec=prec))
+                r[f"{pcn}_{tag}"] = dict(its=st["its"], its_oracle=gold["rotdisk256_step0"][pcn]["its"],
+                                         solve_ms=1e3 * st["t_solve"])
+        ctx.close()
+        out["rotdisk256_step0"] = r
     out["bar256_nonlinear"] = nonlinear_leg(args, fsi, inputs, torch, dev)
     return out
 
@@ -562,6 +578,8 @@ def main():
     ap.add_argument("--no-fixed-cost", action="store_true",
                     help="skip the fixed-cost inexact A11 leg (inner_mode 1)")
     ap.add_argument("--no-ir", action="store_true", help="skip the FP32-refinement leg")
+    ap.add_argument("--forms", default="fp64,mixed,fp32_ir",
+                    help="headline forms to time (comma list of fp64, mixed, fp32_ir; profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run 3 plain device copies of 2 GiB (counter calibration)")
     args = ap.parse_args()
@@ -605,7 +623,10 @@ def main():
     pc = fsi.PC_TRI if args.pc == "tri" else fsi.PC_DIAG
     save = {}
     res = {}
-    forms = [("fp64", fsi.FP64), ("mixed", fsi.FP32)] + ([] if args.no_ir else [("fp32_ir", fsi.FP32_IR)])
+    want = set(args.forms.split(","))
+    forms = [(t, p) for t, p in (("fp64", fsi.FP64), ("mixed", fsi.FP32), ("fp32_ir", fsi.FP32_IR))
+             if t in want and not (t == "fp32_ir" and args.no_ir)]
+    assert forms and forms[0][0] == "fp64", "the headline needs the fp64 form"
     for tag, prec in forms:
         opts = fsi.Opts(restart=30, rtol=1e-8, pc=pc, prec=prec)
         rec, first = time_loop(ctx, u0, Xs, N2, opts, args.warmup, args.steps, tag, profile=tag != "fp32_ir",
@@ -631,7 +652,7 @@ def main():
     # no inner MINRES), timed the same way; reported beside the method's configuration
     fixed = {}
     if not args.no_fixed_cost:
-        for tag, prec in (("fp64", fsi.FP64), ("mixed", fsi.FP32)):
+        for tag, prec in [f for f in forms if f[0] != "fp32_ir"]:
             opts = fsi.Opts(restart=30, rtol=1e-8, pc=pc, prec=prec, inner_mode=1)
             r, _ = time_loop(ctx, u0, Xs, N2, opts, args.warmup, args.steps, f"fixed-cost {tag}")
             fixed[tag] = dict(value=r["value"], ms_per_step=r["ms_per_step"], its=r["its"],
@@ -679,7 +700,8 @@ def main():
     }
     for tag, r in res.items():
         out[tag] = _round(r)
-    out["mixed_speedup"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
+    if "mixed" in res:
+        out["mixed_speedup"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
     if "fp32_ir" in res:
         out["fp32_ir_speedup"] = round(res["fp32_ir"]["value"] / res["fp64"]["value"], 3)
     if fixed:

@@ -92,7 +92,7 @@ def _dirichlet_zeroed(b, n):
 
 
 ITS_CASES = [(case, pc, prec) for case, pcs in (("disk32", ("diag", "tri")), ("twodisk128", ("diag", "tri")),
-                                                ("ellipse256", ("diag", "tri")))
+                                                ("ellipse256", ("diag", "tri")), ("rotdisk256_step0", ("diag", "tri")))
              for pc in pcs for prec in ("fp64", "mixed")]
 
 
