@@ -62,7 +62,7 @@ enum fsi_status {
   FSI_E_NOCONV = -4,     /* Krylov solve reached maxit */
   FSI_E_NONFINITE = -5,  /* NaN/Inf met in a residual */
   FSI_E_HIP = -6,        /* HIP runtime error */
-  FSI_E_CAPACITY = -7,   /* a fixed per-row limit of the coupling assembly was exceeded */
+  FSI_E_CAPACITY = -7,   /* a fixed capacity was exceeded (the allocation-free coupling assembly) */
   FSI_E_STATE = -8       /* call order: e.g. operator apply before fsi_assemble_coupling */
 };
 
@@ -182,17 +182,19 @@ int fsi_sizes(const fsi_ctx *ctx, fsi_sizes_t *out);
  * X^n(E) are clipped (Sutherland-Hodgman) with the fluid triangles of the cells in their
  * bounding box; each kept piece is integrated exactly (the integrand is cubic).
  * Xn: device, 2 Ns doubles [x | y].  info may be NULL (then no synchronisation).
+ * Each C_f row (solid node) is assembled in a window of the P2 lattice nodes its pieces touch:
+ * in LDS up to 4,096 nodes, in device memory above (a solid much coarser than the fluid
+ * grid; one wavefront per such row), with the same fixed order of the sums.
  * Errors: FSI_E_MESH if some X^n(E) has area <= 0 or leaves [0,1]^2 (detected on the
- * device, reported at the next synchronising call or here when info != NULL),
- * FSI_E_CAPACITY if the fluid cells met by the pieces around one solid node span a box of
- * more than 4,096 P2 lattice nodes. */
+ * device, reported at the next synchronising call or here when info != NULL). */
 int fsi_assemble_coupling(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *info);
 
 /* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
  * allocation): fsi_assemble_coupling without any device allocation or release.  It builds the
  * same C_f(X^n) and C_f^T, bitwise, but carves every work array of the assembly (candidate
  * offsets, piece counters, scan partials, the piece list with its local matrices, transpose
- * staging and counters, deferred-row lists, error flags) from one static device array of
+ * staging and counters, deferred-row lists, the device-memory window of rows above 4,096
+ * lattice nodes, error flags) from one static device array of
  * FSI_COUPLING_SCRATCH_BYTES per GPU, whose address the library takes once per device in
  * fsi_create.  Outputs go to the context's coupling storage: reserved by fsi_create and
  * fsi_set_solid for 64 entries per solid node, grown only by fsi_assemble_coupling.

@@ -66,7 +66,7 @@ size_t Ctx::device_bytes() const {
        s_ecs.bytes();
   b += Cf.bytes() + CfT.bytes() + cand_off.bytes() + piece_cnt.bytes() + pair_E.bytes() +
        pair_T.bytes() + piece_L.bytes() + e_piece.bytes() + cft_fill.bytes() + dflag.bytes() +
-       cft_tcol.bytes() + cft_tval.bytes() + cft_long.bytes() + scan_tmp.bytes() + cf_defer.bytes();
+       cft_tcol.bytes() + cft_tval.bytes() + cft_long.bytes() + scan_tmp.bytes() + cf_defer.bytes() + cf_huge.bytes() + cf_wflag.bytes() + cf_wval.bytes();
   b += mgu.bytes() + mgp.bytes();
   for (int i = 0; i < 9; ++i) b += inner.v64[i].bytes() + inner.v32[i].bytes();
   b += outer.V.bytes() + outer.Z.bytes() + outer.w.bytes() + outer.r.bytes() + outer.x32.bytes() +

@@ -32,9 +32,9 @@
 namespace fsi {
 
 constexpr int kMaxPoly = 12;       // a triangle clipped by 5 half-planes has <= 8 vertices
-constexpr int kWinCap = 4096;      // LDS window of P2 nodes per C_f row (64 x 64)
+constexpr int kWinCap = 4096;      // LDS window of P2 nodes per C_f row (64 x 64); larger ones in device memory
 
-enum { DF_MESH = 1, DF_CAP = 2 };
+enum { DF_MESH = 1 };
 
 struct Pt {
   double x, y;
@@ -280,14 +280,21 @@ __constant__ int kOffC[2][6][2] = {{{0, 0}, {2, 0}, {2, 2}, {1, 0}, {2, 1}, {1, 
                                    {{0, 0}, {2, 2}, {0, 2}, {1, 1}, {1, 2}, {0, 1}}};
 
 // One row: returns false (and does nothing) when the window exceeds CAP nodes.  The block is
-// one wavefront; every thread takes the same path.
+// one wavefront; every thread takes the same path.  The window is in LDS (CAP > 0), or, with
+// CAP = 0, in device memory at gflag / gval (room for the row's window; each window position
+// is written by one lane only after the marking pass, so the sums keep their fixed order).
+// Rows whose window exceeds kWinCap (the wide form) are listed in huge = [count, largest
+// window, rows...] for the device-memory form.
 template <int CAP>
 __device__ bool cf_row(int64_t l, int pass, int n, const int *__restrict__ n2e_ptr, const int *__restrict__ n2e,
                        const int *__restrict__ e_piece, const int *__restrict__ pair_T,
                        const double *__restrict__ piece_L, int *cnt, const int *rowptr, int *col, double *val,
-                       int *flag) {
-  __shared__ int wflag[CAP];
-  __shared__ double wval[CAP];
+                       int *flag, int *huge = nullptr, int *gflag = nullptr, double *gval = nullptr) {
+  constexpr int SCAP = CAP > 0 ? CAP : 1;
+  __shared__ int sflag[SCAP];
+  __shared__ double sval[SCAP];
+  int *wflag = CAP > 0 ? sflag : gflag;
+  double *wval = CAP > 0 ? sval : gval;
   int lane = threadIdx.x;
   const int L = 2 * n + 1;
   // window of lattice nodes covered by the pieces around node l
@@ -315,11 +322,11 @@ __device__ bool cf_row(int64_t l, int pass, int n, const int *__restrict__ n2e_p
   }
   int wI = imax - imin + 1, wJ = jmax - jmin + 1;
   int W = wI * wJ;
-  if (W > CAP) {
+  if (CAP > 0 && W > CAP) {
     if (CAP < kWinCap) return false;   // left to the wide form
-    if (lane == 0) {
-      atomicOr(flag, DF_CAP);
-      if (!pass) cnt[l] = 0;
+    if (!pass && lane == 0) {          // left to the device-memory form (listed once)
+      huge[2 + atomicAdd(&huge[0], 1)] = (int)l;
+      atomicMax(&huge[1], W);
     }
     return true;
   }
@@ -397,16 +404,35 @@ __global__ void __launch_bounds__(kWave) k_cf_rows(int pass, int64_t ns, int n, 
     defer[1 + atomicAdd(&defer[0], 1)] = (int)l;   // list order does not matter: rows are independent
 }
 
-// The listed rows with a window of up to kWinCap nodes (grid-stride over the list).
+// The listed rows with a window of up to kWinCap nodes (grid-stride over the list); larger
+// windows are listed in huge.
 __global__ void __launch_bounds__(kWave) k_cf_rows_wide(int pass, int n, const int *__restrict__ n2e_ptr,
                                                         const int *__restrict__ n2e, const int *__restrict__ e_piece,
                                                         const int *__restrict__ pair_T,
                                                         const double *__restrict__ piece_L, int *cnt,
                                                         const int *rowptr, int *col, double *val, int *flag,
-                                                        const int *defer) {
+                                                        const int *defer, int *huge) {
   const int count = defer[0];
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
-    cf_row<kWinCap>(defer[1 + q], pass, n, n2e_ptr, n2e, e_piece, pair_T, piece_L, cnt, rowptr, col, val, flag);
+    cf_row<kWinCap>(defer[1 + q], pass, n, n2e_ptr, n2e, e_piece, pair_T, piece_L, cnt, rowptr, col, val, flag,
+                    huge);
+    __syncthreads();
+  }
+}
+
+// The rows with windows above kWinCap nodes (a solid much coarser than the fluid grid), one
+// after another on one wavefront, each with its window in device memory (flags, values: the
+// largest window listed, huge[1] entries each).
+__global__ void __launch_bounds__(kWave) k_cf_rows_huge(int pass, int n, const int *__restrict__ n2e_ptr,
+                                                        const int *__restrict__ n2e, const int *__restrict__ e_piece,
+                                                        const int *__restrict__ pair_T,
+                                                        const double *__restrict__ piece_L, int *cnt,
+                                                        const int *rowptr, int *col, double *val, int *flag,
+                                                        const int *huge, int *gflag, double *gval) {
+  const int count = huge[0];
+  for (int q = 0; q < count; ++q) {
+    cf_row<0>(huge[2 + q], pass, n, n2e_ptr, n2e, e_piece, pair_T, piece_L, cnt, rowptr, col, val, flag, nullptr,
+              gflag, gval);
     __syncthreads();
   }
 }
@@ -508,7 +534,6 @@ static void check_flags(int *flag, hipStream_t s) {
   int f = read_int(flag, s);
   if (f) fill(flag, 1, 0, s);
   FSI_REQUIRE(!(f & DF_MESH), FSI_E_MESH, "X^n maps a solid triangle to a degenerate/inverted triangle or outside [0,1]^2");
-  FSI_REQUIRE(!(f & DF_CAP), FSI_E_CAPACITY, "coupling pieces around one solid node span more than 4096 P2 nodes");
 }
 
 // Where one assembly keeps its work arrays and finds its outputs.
@@ -612,12 +637,27 @@ static void assemble(Ctx &c, const double *Xn, Work &w) {
   Cf.width = 1;
   int *cf_rp = w.out(Cf.rowptr, ns + 1, "the C_f row pointers");
   int *defer = w.work(c.cf_defer, ns + 1, "deferred rows");
+  int *huge = w.work(c.cf_huge, ns + 2, "rows with large windows");
   fill(defer, 1, 0, s);
+  fill(huge, 2, 0, s);
   hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 0, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece,
                      pair_T, piece_L, cf_rp, nullptr, nullptr, nullptr, flag, defer);
   hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 0, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
-                     piece_L, cf_rp, nullptr, nullptr, nullptr, flag, defer);
+                     piece_L, cf_rp, nullptr, nullptr, nullptr, flag, defer, huge);
   FSI_CHECK_LAUNCH();
+  // rows whose window exceeds the LDS form: a device-memory window of the largest size
+  int hcnt[2] = {0, 0};
+  FSI_HIP(hipMemcpyAsync(hcnt, huge, sizeof(hcnt), hipMemcpyDeviceToHost, s));
+  FSI_HIP(hipStreamSynchronize(s));
+  int *gflag = nullptr;
+  double *gval = nullptr;
+  if (hcnt[0] > 0) {
+    gflag = w.work(c.cf_wflag, hcnt[1], "the large window");
+    gval = w.work(c.cf_wval, hcnt[1], "the large window");
+    hipLaunchKernelGGL(k_cf_rows_huge, dim3(1), dim3(kWave), 0, s, 0, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
+                       piece_L, cf_rp, nullptr, nullptr, nullptr, flag, huge, gflag, gval);
+    FSI_CHECK_LAUNCH();
+  }
   scan_excl(cf_rp, cf_rp, ns, w.scan(ns), s);
   check_flags(flag, s);
   const int nnz = read_int(cf_rp + ns, s);
@@ -628,7 +668,10 @@ static void assemble(Ctx &c, const double *Xn, Work &w) {
   hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 1, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece,
                      pair_T, piece_L, nullptr, cf_rp, cf_col, cf_val, flag, defer);
   hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
-                     piece_L, nullptr, cf_rp, cf_col, cf_val, flag, defer);
+                     piece_L, nullptr, cf_rp, cf_col, cf_val, flag, defer, huge);
+  if (hcnt[0] > 0)
+    hipLaunchKernelGGL(k_cf_rows_huge, dim3(1), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
+                       piece_L, nullptr, cf_rp, cf_col, cf_val, flag, huge, gflag, gval);
   FSI_CHECK_LAUNCH();
   // C_f^T
   Csr &Ct = c.CfT;

@@ -118,6 +118,9 @@ struct Ctx {
   DevBuf<int> cft_long;     // [count, rows...]: rows ranked by a workgroup each
   DevBuf<int> scan_tmp;     // scan partials (grow-only)
   DevBuf<int> cf_defer;     // [count, rows...]: C_f rows assembled with the wide window
+  DevBuf<int> cf_huge;      // [count, largest window, rows...]: rows with a device-memory window
+  DevBuf<int> cf_wflag;     // that window (grow-only)
+  DevBuf<double> cf_wval;
   DevBuf<int> dflag;       // device error flags (mesh / capacity)
 
   // multigrid hierarchies of the preconditioner

@@ -58,6 +58,9 @@ def small_workloads():
         # solid triangles of about 8 x 8 cells: the pieces around a solid node span more than
         # 1,024 lattice nodes (the wide-window form of the C_f rows)
         "coarse_disk128": (inputs.small_workload(128, 3, (0.47, 0.52), 0.2), 0.3),
+        # 24 triangles of about 16 x 16 cells: windows of up to 130 x 130 lattice nodes, above the
+        # 4,096 of the LDS form (the device-memory window)
+        "huge_window128": (inputs.small_workload(128, 2, (0.47, 0.52), 0.3), 0.2),
     }
 
 

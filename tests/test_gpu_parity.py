@@ -295,6 +295,29 @@ def test_step_against_oracle():
     ctx.close()
 
 
+def test_step_solid_with_large_windows():
+    """A solid much coarser than the fluid grid (C_f rows whose pieces span windows above the
+    4,096 lattice nodes of the LDS form, assembled in device memory): a step within 1e-8 of the
+    oracle's direct solve in every block.  The solve runs to rtol 1e-12: this coupling (up to
+    5,080 entries in a row of C_f) amplifies the residual of an rtol-1e-10 solve to 4e-8 in u and
+    3e-7 in p, element by element."""
+    print("[step large windows]", flush=True)
+    wl, angle = small_workloads()["huge_window128"]
+    S = system.FSISystem.from_workload(wl)
+    lay = S.lay
+    X = _positions("huge_window128", S, angle)
+    u = inputs.uniform(2 * lay.N2, 77)
+    from oracle import step as ostep
+    x_ref, _ = ostep.step(S, u, X, solver="direct")
+    ctx = fsi.Context.from_workload(wl)
+    torch = torch_dev()
+    out = torch.zeros(lay.N, dtype=torch.float64, device="cuda")
+    st = ctx.step(to_dev(u), to_dev(soa(X)), out, fsi.Opts(pc=fsi.PC_TRI, rtol=1e-12))
+    assert st["converged"]
+    assert_block_parity(S, to_host(out), x_ref, 1e-8, "large windows")
+    ctx.close()
+
+
 def test_error_paths():
     print("[errors]", flush=True)
     wl = inputs.small_workload(8, 2, (0.5, 0.5), 0.2)
