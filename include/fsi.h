@@ -117,7 +117,7 @@ typedef struct {
   int32_t pc;           /* fsi_pc */
   int32_t prec;         /* fsi_prec */
   double inner_rtol;    /* relative tolerance of the inner A11 solve (0: default, 1e-2 with the
-                           block-triangular, 1e-3 with the block-diagonal preconditioner) */
+                           block-triangular, 1e-6 with the block-diagonal preconditioner) */
   int32_t inner_maxit;  /* inner MINRES steps per A11 solve (default 1000; 300 in FP32) */
   double cycle_rtol;    /* FSI_FP32_IR: residual reduction asked of each FGMRES cycle
                            (default 1e-5); ignored otherwise */

@@ -1342,13 +1342,15 @@ static void ensure_inner(Ctx &c, int prec, int K = 1) {
 // to 1e-2, one more at 2e-2 on two workloads); mixed at 5e-3, 1e-2, 2e-2, 4e-2:
 // 182/152/177/142, 104/97/94/95, 46/42/47/45 ms.  Its outer counts equal the exact-block
 // counts (10, 11, 14 at 32^2, 128^2, 256^2) at 1e-2 already.
-// Block-diagonal: 1e-3.  Its outer counts react more to the inexact A11: against the
-// exact-block counts 16 / 16 / 20 at 32^2 / 128^2 / 256^2 it takes 16 / 20 / 24 at 1e-2,
-// 16 / 18 / 24 at 5e-3 and 16 / 18 / 22 at 1e-3 and at 3e-4 (+5% time against 1e-2).
+// Block-diagonal: 1e-6.  Its outer counts react much more to the inexact A11.  Against the
+// exact-block counts 16 / 16 / 20 (random right-hand sides at 32^2 / 128^2 / 256^2) and 4 (the
+// first step of the rotating disk at 256^2) it takes 16 / 18 / 22 / 8 at 1e-3, 16 / 16 / 20 / 6
+// at 1e-4 and 1e-5, and 16 / 16 / 20 / 4 at 1e-6.  Time at 1e-6 against 1e-3: +23%, +23%,
+// +25% on the random right-hand sides, -27% on the time step.
 double inner_tol(const Ctx &c, int prec, int pc) {
   (void)prec;
   if (c.inner_rtol > 0) return c.inner_rtol;
-  return pc == FSI_PC_DIAG ? 1e-3 : 1e-2;
+  return pc == FSI_PC_DIAG ? 1e-6 : 1e-2;
 }
 
 // The block preconditioner on K systems: system k belongs to context cs[k] (one fluid grid
