@@ -1293,6 +1293,7 @@ static void ensure_inner(Ctx &c, int prec, int K = 1) {
   FSI_REQUIRE(K >= 1 && K <= FSI_MAX_LANES, FSI_E_ARG, "lane count out of range");
   const int64_t nf = 2 * c.N2 + c.Np;
   if (K > c.lanes) {
+    FSI_HIP(hipStreamSynchronize(c.stream));   // captured graphs may still be running
     c.drop_graphs();
     for (int i = 0; i < 9; ++i) {
       c.inner.v64[i].release();
