@@ -82,7 +82,9 @@ def inner_step_bytes(n, prec):
         two post steps 10w per node; dense 25^2 w;
       pressure mass solve 13w Np, pressure residual copy (8 + w) Np, output (2w + 16) Np;
       A11 product with the fused MINRES updates (FP64): 64 N2 + 32 Np;
-      remaining MINRES vector work: 10 vectors of nf = 2 N2 + Np doubles;
+      remaining MINRES vector work: 4 vectors of nf = 2 N2 + Np doubles (the second
+        three-term update, 3; the directions and the iterate are formed once per block of
+        stored Lanczos vectors, counted in step_bytes);
       FP32 form: the velocity residual converted (24 N2), the finest post-smoothing writes the
         FP64 output ((4w + 16) N2 instead of 6w N2) and reads the FP64 residual for the sums of
         r . z (16 N2)."""
@@ -103,7 +105,7 @@ def inner_step_bytes(n, prec):
     b += 25 * 25 * w
     b += 13 * w * Np(n) + (8 + w) * Np(n) + (2 * w + 16) * Np(n)
     b += 64 * N2(n) + 32 * Np(n)
-    b += 10 * 8 * (2 * N2(n) + Np(n))
+    b += 4 * 8 * (2 * N2(n) + Np(n))
     if prec != "fp64":
         b += 24 * N2(n)
     return b
@@ -121,7 +123,8 @@ def step_bytes(n, Ns, nnz_s, nnz_cf, n_pairs, its, inner_its, restarts, prec, pc
         6 vectors of Ns per step) and one A_s product, the block-triangular C_f product, the
         two Gram-Schmidt passes 16 (j + 1) N + 24 N and the normalisation 16 N;
       inner steps: inner_step_bytes each, plus one more preconditioner application per
-        outer step (the start of MINRES);
+        outer step (the start of MINRES), and the iterate formed from the stored Lanczos
+        vectors (each read once, the iterate written: (inner steps + 1) nf 8 per solve);
       per restart: the update x += Z y ((k + 1) N 8) and the FP64 true residual (operator + 3N 8)."""
     N2, Np = (2 * n + 1) ** 2, (n + 1) ** 2
     N = 2 * N2 + Np + 4 * Ns
@@ -135,7 +138,8 @@ def step_bytes(n, Ns, nnz_s, nnz_cf, n_pairs, its, inner_its, restarts, prec, pc
         jj = j % m
         b += op + a22 + cf + 16 * (jj + 1) * N + 24 * N + 16 * N
     b += inner_its * inner_step_bytes(n, prec)
-    b += its * (inner_step_bytes(n, prec) - 64 * N2 - 32 * Np - 10 * 8 * (2 * N2 + Np))
+    b += its * (inner_step_bytes(n, prec) - 64 * N2 - 32 * Np - 4 * 8 * (2 * N2 + Np))
+    b += (inner_its + its) * 8 * (2 * N2 + Np)
     b += restarts * ((min(its, m) + 1) * N * 8 + op + 3 * N * 8)
     return b
 

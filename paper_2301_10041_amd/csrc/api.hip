@@ -72,7 +72,8 @@ size_t Ctx::device_bytes() const {
   b += outer.V.bytes() + outer.Z.bytes() + outer.w.bytes() + outer.r.bytes() + outer.x32.bytes() +
        outer.y32.bytes();
   b += red.bytes() + dscal.bytes() + tmpN.bytes() + tmpS.bytes();
-  b += ms_state.bytes() + ms_red.bytes() + ms_x.bytes() + ms_part.bytes() + ms_dot.bytes() + pc_in.bytes() +
+  b += ms_state.bytes() + ms_red.bytes() + ms_x.bytes() + ms_part.bytes() + ms_dot.bytes() + ms_vh.bytes() +
+       ms_hist.bytes() + ms_coef.bytes() + pc_in.bytes() +
        pc_out.bytes();
   return b;
 }
@@ -84,7 +85,8 @@ static size_t estimate_bytes(int64_t n, int64_t ns, int64_t nt) {
   double zaf = 46 * n2, zb = 19 * n2, N2 = 4 * n2, Np = n2, N = 2 * N2 + Np + 4 * ns;
   double fluid = zaf * (32 + 4 + 8 + 16) + 2 * zb * (16 + 4 + 8) + 9 * Np * 12 + 4 * (N2 + Np);
   double mg = fluid * 0.45 + 10 * N2 * 12 / 3;
-  double krylov = 61 * N * 8 + 9 * (2 * N2 + Np) * 12 + 4 * N * 8;
+  double krylov = 61 * N * 8 + 9 * (2 * N2 + Np) * 12 + 4 * N * 8 +
+                  std::min(32 * (2 * N2 + Np) * 8, (double)(2ll << 30));   // MINRES Lanczos block
   double solid = ns * (7 * 12 * 2 + 200 + 8 * 20) + nt * 60 + 60 * ns * 12;
   double cf = nt * 12 * (18 * 8 + 16) + 2 * 60 * ns * 12 + N2 * 8;
   // fixed work space (reduction partials, device scalars, pinned staging, small

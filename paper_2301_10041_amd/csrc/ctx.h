@@ -175,6 +175,10 @@ struct Ctx {
   // (allocated once: captured graphs hold these pointers), graphs per precision and phase
   DevBuf<double> ms_state, ms_red, ms_x, ms_part;
   DevBuf<double> ms_dot;   // per lane: velocity tile sums, then pressure block sums of r . z
+  // the Lanczos vectors of the current block of iterations ([slot][lane][nf], ms_B slots),
+  // the recorded direction scalars ([lane][slot][5]) and the combination coefficients
+  DevBuf<double> ms_vh, ms_hist, ms_coef;
+  int ms_B = 0;
   hipGraphExec_t ms_graph[2][FSI_MAX_LANES + 1][6] = {};   // per precision, lane count, rotation phase
   DevBuf<double> pc_in, pc_out;
   void drop_graphs();

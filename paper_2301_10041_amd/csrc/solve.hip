@@ -697,17 +697,28 @@ void Ctx::drop_graphs() {
 // are not smooth-dominated and FP32 arithmetic costs the preconditioner nothing.
 //
 // The scalar recurrence runs on the device (one thread), so an iteration is a fixed
-// sequence of kernels: on small grids it is replayed as a captured graph (three graphs,
-// one per rotation of the Lanczos and direction buffers) and the host looks at the
-// convergence flag every few iterations.  Once converged, a flag freezes x, so the result
-// does not depend on how often the host checks.
+// sequence of kernels: on small grids it is replayed as a captured graph (one per rotation
+// of the Lanczos buffers) and the host looks at the convergence flag every few iterations.
+//
+// Directions and iterate in blocks.  The recurrence w_j = (v_j - e_j w_{j-2} - d_j w_{j-1})
+// / gamma_j, x += phi_j w_j is not applied vector by vector each iteration (six vector passes
+// per iteration).  Each iteration stores its Lanczos vector v_j in a slot of a block of up to
+// ms_B vectors and records (e_j, d_j, 1/gamma_j, phi_j); after ms_B iterations, and at the
+// end, the same recurrence is run on coefficient vectors over the basis (v slots, w_{k0-1},
+// w_{k0}) and one pass forms x, w_{k-1} and w_k as those combinations (ms_B + 3 reads and 3
+// writes per block).  Once converged, a lane records no more updates, so its x does not
+// depend on how often the host checks, nor on the other lanes of a batch.
 struct MinresState {
   double alfa, beta2;                         // dot products of the iteration
   double beta, oldb, dbar, epsln, phibar, cs, sn, beta1, tol;
   double s, c_r1;                             // 1 / beta, -beta / oldb
   double e, d, ginv, phi;                     // direction update
   double it, done, apply;                     // iterations; converged; update valid
+  double slot;                                // slot of this iteration's Lanczos vector
 };
+constexpr int kMsRec = 5;                     // recorded per iteration: e, d, 1/gamma, phi, applied
+constexpr int kMsBMax = 32;                   // Lanczos vectors per block at most
+static_assert(kMsBMax + 2 <= kWave, "one wave computes the coefficients of a block");
 constexpr int kMsDoubles = sizeof(MinresState) / sizeof(double);
 
 // The kernels below run K systems (lane = blockIdx.y): lane k uses st + k and vectors at
@@ -726,12 +737,19 @@ __global__ void k_ms_init(MinresState *st, double tol) {
   st->it = 0.0;
   st->done = b > 0.0 ? 0.0 : 1.0;
   st->apply = 0.0;
+  st->slot = 0.0;
 }
 
-// After the two dot products of an iteration: Givens rotation and the next coefficients.
-__device__ void ms_step(MinresState *st) {
+// After the two dot products of an iteration: Givens rotation and the next coefficients,
+// recorded in slot st->slot of the lane's history (B slots of kMsRec; the host starts a new
+// block before the slots run out, and a slot out of range records nothing).
+__device__ void ms_step(MinresState *st, double *hist, int B) {
+  const int sl = (int)st->slot;
+  double *h = (sl >= 0 && sl < B) ? hist + kMsRec * sl : nullptr;
+  st->slot += 1.0;
   if (st->done != 0.0) {
     st->apply = 0.0;
+    if (h) h[4] = 0.0;
     return;
   }
   const double alfa = st->alfa, nb2 = st->beta2;
@@ -752,6 +770,13 @@ __device__ void ms_step(MinresState *st) {
   st->d = delta;
   st->ginv = 1.0 / gamma;
   st->apply = 1.0;
+  if (h) {
+    h[0] = st->e;
+    h[1] = st->d;
+    h[2] = st->ginv;
+    h[3] = st->phi;
+    h[4] = 1.0;
+  }
   st->it += 1.0;
   st->oldb = oldb;
   st->beta = beta;
@@ -760,18 +785,26 @@ __device__ void ms_step(MinresState *st) {
   if (!(st->phibar > st->tol * st->beta1) || beta == 0.0 || !(alfa == alfa)) st->done = 1.0;
 }
 
-__global__ void k_ms_step(MinresState *st) {
+__global__ void k_ms_step(MinresState *st, double *hist, int B) {
   if (threadIdx.x || blockIdx.x) return;
-  ms_step(st + blockIdx.y);
+  ms_step(st + blockIdx.y, hist + (int64_t)blockIdx.y * kMsRec * B, B);
 }
 
-// v = s y
-__global__ void k_ms_scale(double *v, const double *y, const MinresState *st, int64_t n) {
+// v = s y, also stored in slot st->slot of the Lanczos block vh (slot stride vs; the slot is
+// clamped to [0, B - 1])
+__global__ void k_ms_scale(double *v, const double *y, const MinresState *st, int64_t n, double *vh, int64_t vs,
+                           int B) {
   const int64_t o = (int64_t)blockIdx.y * n;
   const double a = st[blockIdx.y].s;
+  int sl = (int)st[blockIdx.y].slot;
+  sl = sl < 0 ? 0 : sl >= B ? B - 1 : sl;
+  double *h = vh + (int64_t)sl * vs + o;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    v[o + i] = a * y[o + i];
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double t = a * y[o + i];
+    v[o + i] = t;
+    h[i] = t;
+  }
 }
 
 // y += c_r1 r1 - (alfa s) r2   (the second term after alfa is known: two launches)
@@ -804,39 +837,83 @@ __global__ void k_ms_axpy_f32(double *y, const double *r, const MinresState *st,
   }
 }
 
-// wn = (v - e w1 - d w2) ginv;  x += phi wn   (skipped once converged)
-__global__ void k_ms_update(double *wn, const double *v, const double *w1, const double *w2, double *x,
-                            const MinresState *st, int64_t n) {
-  const MinresState &q = st[blockIdx.y];
-  if (q.apply == 0.0) return;
-  const double e = q.e, d = q.d, g = q.ginv, phi = q.phi;
-  const int64_t o = (int64_t)blockIdx.y * n;
-  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ts = (int64_t)gridDim.x * blockDim.x;
-  const bool pairs = ((reinterpret_cast<uintptr_t>(wn + o) | reinterpret_cast<uintptr_t>(v + o) |
-                       reinterpret_cast<uintptr_t>(w1 + o) | reinterpret_cast<uintptr_t>(w2 + o) |
-                       reinterpret_cast<uintptr_t>(x + o)) & 15) == 0;   // uniform over the grid row
-  int64_t i0 = 0;
-  if (pairs) {   // 16-byte accesses, two entries per thread and pass, the same arithmetic
-    const int64_t np = n / 2;
-    for (int64_t p = t0; p < np; p += ts) {
-      const double2 vv = reinterpret_cast<const double2 *>(v + o)[p];
-      const double2 a1 = reinterpret_cast<const double2 *>(w1 + o)[p];
-      const double2 a2 = reinterpret_cast<const double2 *>(w2 + o)[p];
-      double2 xx = reinterpret_cast<const double2 *>(x + o)[p];
-      double2 w;
-      w.x = (vv.x - e * a1.x - d * a2.x) * g;
-      w.y = (vv.y - e * a1.y - d * a2.y) * g;
-      reinterpret_cast<double2 *>(wn + o)[p] = w;
-      xx.x += phi * w.x;
-      xx.y += phi * w.y;
-      reinterpret_cast<double2 *>(x + o)[p] = xx;
+// Coefficients of a block of m iterations (block = lane): the direction recurrence run on
+// coefficient vectors over the basis (v slot 0 .. m - 1, w_{k0-1}, w_{k0}), stopping at the
+// first slot the lane did not apply; thread k follows coefficient k (the recurrence acts on
+// each coefficient alone).  Writes, per lane at coef + lane (1 + 3 (B + 2)): the number of
+// applied slots, then the coefficients of the x increment, of the new w_{k-1} and of the new
+// w_k (m + 2 each, at stride B + 2).  Resets the lane's slot.
+__global__ void k_ms_coef(const double *hist, int B, int m, double *coef, MinresState *st) {
+  const int lane = blockIdx.x, k = threadIdx.x, nb = m + 2;
+  const double *h = hist + (int64_t)lane * kMsRec * B;
+  double *cf = coef + (int64_t)lane * (1 + 3 * (B + 2));
+  if (k < nb) {
+    double w2 = k == m ? 1.0 : 0.0, w1 = k == m + 1 ? 1.0 : 0.0, cx = 0.0;
+    int applied = 0;
+    for (int i = 0; i < m; ++i) {
+      const double *r = h + kMsRec * i;
+      if (r[4] == 0.0) break;
+      const double e = r[0], d = r[1], g = r[2], phi = r[3];
+      const double wn = ((k == i ? 1.0 : 0.0) - e * w2 - d * w1) * g;
+      cx += phi * wn;
+      w2 = w1;
+      w1 = wn;
+      ++applied;
     }
-    i0 = 2 * np;
+    cf[1 + k] = cx;
+    cf[1 + (B + 2) + k] = w2;
+    cf[1 + 2 * (B + 2) + k] = w1;
+    if (k == 0) {
+      cf[0] = (double)applied;
+      st[lane].slot = 0.0;
+    }
   }
-  for (int64_t i = i0 + t0; i < n; i += ts) {
-    const double w = (v[o + i] - e * w1[o + i] - d * w2[o + i]) * g;
-    wn[o + i] = w;
-    x[o + i] += phi * w;
+}
+
+// x += the block's increment; unless last, w_{k-1} and w_k over W2 and W1 (in place: every
+// output entry depends only on the same entry of the inputs).  first: x, W2 and W1 are zero
+// and not read.  A lane with no applied slot is left as it is.  Sums in slot order, then
+// W2, W1.
+__global__ void k_ms_combine(double *x, double *W2, double *W1, const double *vh, int64_t vs, const double *coef,
+                             int B, int m, int64_t n, int first, int last) {
+  const double *cf = coef + (int64_t)blockIdx.y * (1 + 3 * (B + 2));
+  const int ma = (int)cf[0];
+  if (ma == 0) return;
+  const double *cx = cf + 1, *ca = cf + 1 + (B + 2), *cb = cf + 1 + 2 * (B + 2);
+  const int64_t o = (int64_t)blockIdx.y * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double ax = first ? 0.0 : x[o + i], aa = 0.0, ab = 0.0;
+    const double *p = vh + o + i;
+    int k = 0;
+    for (; k + 8 <= ma; k += 8) {   // eight independent loads in flight, sums in slot order
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(k + u) * vs];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        ax += cx[k + u] * v[u];
+        aa += ca[k + u] * v[u];
+        ab += cb[k + u] * v[u];
+      }
+    }
+    for (; k < ma; ++k) {
+      const double v = p[(int64_t)k * vs];
+      ax += cx[k] * v;
+      aa += ca[k] * v;
+      ab += cb[k] * v;
+    }
+    if (!first) {
+      const double w2 = W2[o + i], w1 = W1[o + i];
+      ax += cx[m] * w2 + cx[m + 1] * w1;
+      aa += ca[m] * w2 + ca[m + 1] * w1;
+      ab += cb[m] * w2 + cb[m + 1] * w1;
+    }
+    x[o + i] = ax;
+    if (!last) {
+      W2[o + i] = aa;
+      W1[o + i] = ab;
+    }
   }
 }
 
@@ -860,7 +937,7 @@ __global__ void __launch_bounds__(1024) k_ms_alfa(const double *part, int n, Min
 // lane, fixed order; lane k's sums at part + k lp, its state at st + k), then the step
 // (ms_step) of that lane
 __global__ void __launch_bounds__(1024) k_ms_beta_step(const double *part, int nu, int np, int64_t lp,
-                                                       MinresState *st) {
+                                                       MinresState *st, double *hist, int B) {
   __shared__ double red[1024 / kWave];
   part += (int64_t)blockIdx.y * lp;
   double acc = 0.0;
@@ -872,37 +949,36 @@ __global__ void __launch_bounds__(1024) k_ms_beta_step(const double *part, int n
     double b = 0.0;
     for (int k = 0; k < 1024 / kWave; ++k) b += red[k];
     st[blockIdx.y].beta2 = b;
-    ms_step(st + blockIdx.y);
+    ms_step(st + blockIdx.y, hist + (int64_t)blockIdx.y * kMsRec * B, B);
   }
 }
 
-// Buffers of one rotation phase (0, 1, 2).  Lanczos: r1 (old), r2 (current), y (new);
-// directions: w1 (two back, overwritten by the new one), w2, w.  Lane 0 of each (lane
+// Buffers of one rotation phase (0, 1, 2).  Lanczos: r1 (old), r2 (current), y (new); v the
+// scaled vector (assembled-A11 form; the matrix-free form writes it straight into the block);
+// W2, W1 the directions w_{k0-1}, w_{k0} carried between blocks.  Lane 0 of each (lane
 // stride nf).
 struct MsBufs {
-  double *v, *r1, *r2, *y, *w1, *w2, *w, *x;
+  double *v, *r1, *r2, *y, *W2, *W1, *x;
 };
 
 static MsBufs ms_bufs(Ctx &c, double *x, int phase) {
   double *B[3] = {c.inner.v64[2].p, c.inner.v64[3].p, c.inner.v64[1].p};   // r1, r2, y at phase 0
-  double *W[3] = {c.inner.v64[5].p, c.inner.v64[6].p, c.inner.v64[4].p};   // w1, w2, w at phase 0
   MsBufs b;
   b.v = c.inner.v64[0].p;
   b.r1 = B[phase % 3];
   b.r2 = B[(phase + 1) % 3];
   b.y = B[(phase + 2) % 3];
-  b.w1 = W[phase % 3];
-  b.w2 = W[(phase + 1) % 3];
-  b.w = W[(phase + 2) % 3];
+  b.W2 = c.inner.v64[4].p;
+  b.W1 = c.inner.v64[5].p;
   b.x = x;
   return b;
 }
 
 // Buffers with the matrix-free A11 product (fused iteration below): the new Lanczos vector
 // is written over r1, so r1 and r2 alternate between two buffers and the preconditioned
-// vector always lives in the third; the directions rotate as before (period 6 overall).
+// vector always lives in the third (period 2).
 static MsBufs ms_bufs_fused(Ctx &c, double *x, int it) {
-  MsBufs b = ms_bufs(c, x, it % 3);   // directions
+  MsBufs b = ms_bufs(c, x, 0);
   double *B0 = c.inner.v64[2].p, *B1 = c.inner.v64[3].p;
   b.r1 = it % 2 == 0 ? B0 : B1;
   b.r2 = it % 2 == 0 ? B1 : B0;
@@ -928,8 +1004,9 @@ static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st, int K) 
   double *dv = (double *)st;
   const int tiles = stencil_tile_count(c.n);
   stencil_a11_minres(c.n, (const StencilTable<double> *)c.mgu.lv[0].stab64.p, (const DivTable<double> *)c.divtab64.p,
-                     LP<const double>(b.y, nf), LP<double>(b.v, nf), LP<double>(b.r1, nf),
+                     LP<const double>(b.y, nf), LP<double>(c.ms_vh.p, nf), LP<double>(b.r1, nf),
                      LP<const double>(&st->s, kMsDoubles), LP<const double>(&st->c_r1, kMsDoubles),
+                     LP<const double>(&st->slot, kMsDoubles), (int64_t)c.lanes * nf, c.ms_B,
                      LP<double>(c.ms_part.p, tiles), s, K);
   hipLaunchKernelGGL(k_ms_alfa, dim3(1, K), dim3(1024), 0, s, c.ms_part.p, tiles, st);
   constexpr bool f32 = std::is_same<TA, float>::value;
@@ -953,14 +1030,14 @@ static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st, int K) 
     } else {
       a11_precond<double>(c, b.r1, b.y, K, nullptr, nullptr, dot);
     }
-    hipLaunchKernelGGL(k_ms_beta_step, dim3(1, K), dim3(1024), 0, s, c.ms_dot.p, nu, kPresDotBlocks, ld, st);
+    hipLaunchKernelGGL(k_ms_beta_step, dim3(1, K), dim3(1024), 0, s, c.ms_dot.p, nu, kPresDotBlocks, ld, st,
+                       c.ms_hist.p, c.ms_B);
   } else {
     a11_precond_on64<TA>(c, b.r1, b.y, K);
     dot_l(LP<const double>(b.r1, nf), LP<const double>(b.y, nf), nf, LP<double>(dv + 1, kMsDoubles), c.ms_red.p, s,
           K);
-    hipLaunchKernelGGL(k_ms_step, dim3(1, K), dim3(1), 0, s, st);
+    hipLaunchKernelGGL(k_ms_step, dim3(1, K), dim3(1), 0, s, st, c.ms_hist.p, c.ms_B);
   }
-  hipLaunchKernelGGL(k_ms_update, dim3(g, K), dim3(256), 0, s, b.w1, b.v, b.w2, b.w, b.x, st, nf);
   FSI_CHECK_LAUNCH();
 }
 
@@ -971,7 +1048,8 @@ static void ms_iteration(Ctx &c, const MsBufs &b, MinresState *st) {
   const int64_t nf = 2 * c.N2 + c.Np;
   const unsigned g = vgrid(nf);
   double *dv = (double *)st;   // alfa at 0, beta2 at 1
-  hipLaunchKernelGGL(k_ms_scale, dim3(g), dim3(256), 0, s, b.v, b.y, st, nf);
+  hipLaunchKernelGGL(k_ms_scale, dim3(g), dim3(256), 0, s, b.v, b.y, st, nf, c.ms_vh.p, (int64_t)c.lanes * nf,
+                     c.ms_B);
   apply_a11_on64<double>(c, b.v, b.y);
   hipLaunchKernelGGL(k_ms_axpy, dim3(g), dim3(256), 0, s, b.y, b.r1, st, 0, nf);
   multidot(b.v, 0, 1, b.y, nf, dv, c.ms_red, s);
@@ -979,8 +1057,7 @@ static void ms_iteration(Ctx &c, const MsBufs &b, MinresState *st) {
   // new Lanczos vector is b.y: precondition it into the buffer of r1 (no longer needed)
   a11_precond_on64<TA>(c, b.y, b.r1);
   multidot(b.y, 0, 1, b.r1, nf, dv + 1, c.ms_red, s);
-  hipLaunchKernelGGL(k_ms_step, dim3(1), dim3(1), 0, s, st);
-  hipLaunchKernelGGL(k_ms_update, dim3(g), dim3(256), 0, s, b.w1, b.v, b.w2, b.w, b.x, st, nf);
+  hipLaunchKernelGGL(k_ms_step, dim3(1), dim3(1), 0, s, st, c.ms_hist.p, c.ms_B);
   FSI_CHECK_LAUNCH();
 }
 
@@ -1000,8 +1077,6 @@ static void minres_a11(Ctx &c, const double *const *b, double *const *xout, int 
   double *x = c.ms_x.p;
   MsBufs b0 = ms_bufs(c, x, 0);
   fill_l(LP<double>(x, nf), nf, 0.0, s, K);
-  fill_l(LP<double>(b0.w, nf), nf, 0.0, s, K);
-  fill_l(LP<double>(b0.w2, nf), nf, 0.0, s, K);
   // phase 0 expects: r2 = current Lanczos vector, y = M r2
   for (int k = 0; k < K; ++k) convert(b0.r2 + k * nf, b[k], nf, s);
   a11_precond_any<TA>(c, b0.r2, b0.y, K);
@@ -1015,7 +1090,18 @@ static void minres_a11(Ctx &c, const double *const *b, double *const *xout, int 
   // frozen steps run past convergence)
   const int check_every = graphs ? 2 : 1;
   const int pk = std::is_same<TA, double>::value ? 0 : 1;
-  int it = 0;
+  int it = 0, k0 = 0;   // iterations done; iterations before the current block
+  const int B = c.ms_B;
+  // x (and, unless last, the carried directions) from the block of iterations k0 .. it - 1
+  auto flush = [&](bool last) {
+    const int m = it - k0;
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_ms_coef, dim3(K), dim3(kWave), 0, s, c.ms_hist.p, B, m, c.ms_coef.p, st);
+    hipLaunchKernelGGL(k_ms_combine, dim3((unsigned)((nf + 255) / 256), K), dim3(256), 0, s, x, b0.W2, b0.W1,
+                       c.ms_vh.p, (int64_t)c.lanes * nf, c.ms_coef.p, B, m, nf, k0 == 0 ? 1 : 0, last ? 1 : 0);
+    FSI_CHECK_LAUNCH();
+    k0 = it;
+  };
   double *h = c.hpin;
   auto all_done = [&]() {
     FSI_HIP(hipMemcpyAsync(h, st, (size_t)K * kMsDoubles * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1031,7 +1117,7 @@ static void minres_a11(Ctx &c, const double *const *b, double *const *xout, int 
   };
   while (it < maxit) {
     // the rotation: in phase p the roles are shifted by p (r2 of phase p is y of p-1, ...)
-    const int phase = fused ? it % 6 : it % 3;
+    const int phase = fused ? it % 2 : it % 3;
     const MsBufs bq = fused ? ms_bufs_fused(c, x, it) : ms_bufs(c, x, phase);
     if (graphs) {
       hipGraphExec_t &ge = c.ms_graph[pk][K][phase];
@@ -1047,8 +1133,10 @@ static void minres_a11(Ctx &c, const double *const *b, double *const *xout, int 
       ms_iteration<TA>(c, bq, st);
     }
     ++it;
+    if (it - k0 == B) flush(false);
     if ((it % check_every == 0 || it == maxit) && all_done()) break;
   }
+  flush(true);
   all_done();
   for (int k = 0; k < K; ++k) {
     const MinresState *hs = (const MinresState *)h + k;
@@ -1299,7 +1387,9 @@ static void ensure_inner(Ctx &c, int prec, int K = 1) {
       c.inner.v64[i].release();
       c.inner.v32[i].release();
     }
-    for (auto *b : {&c.ms_x, &c.ms_state, &c.ms_red, &c.ms_part, &c.ms_dot, &c.pc_in, &c.pc_out}) b->release();
+    for (auto *b : {&c.ms_x, &c.ms_state, &c.ms_red, &c.ms_part, &c.ms_dot, &c.pc_in, &c.pc_out, &c.ms_vh,
+                    &c.ms_hist, &c.ms_coef})
+      b->release();
     c.outer.x32.release();
     c.outer.y32.release();
     for (Mg *mg : {&c.mgu, &c.mgp})
@@ -1313,6 +1403,13 @@ static void ensure_inner(Ctx &c, int prec, int K = 1) {
   const int64_t nl = c.lanes;
   for (int i = 0; i < 9; ++i)
     if (!c.inner.v64[i].p) c.inner.v64[i].alloc(nl * nf);
+  if (!c.ms_vh.p) {   // Lanczos block: at most kMsBMax vectors per lane, 2 GiB over all lanes
+    const int64_t fit = (int64_t(2) << 30) / (8 * nl * nf);
+    c.ms_B = (int)std::max<int64_t>(4, std::min<int64_t>(kMsBMax, fit));
+    c.ms_vh.alloc((size_t)c.ms_B * nl * nf);
+    c.ms_hist.alloc((size_t)nl * kMsRec * c.ms_B);
+    c.ms_coef.alloc((size_t)nl * (1 + 3 * (c.ms_B + 2)));
+  }
   if (!c.ms_x.p) {
     c.ms_x.alloc(nl * nf);
     c.ms_state.alloc(nl * kMsDoubles);

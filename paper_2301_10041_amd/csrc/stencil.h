@@ -131,10 +131,13 @@ int cheb3_dot_count(int n);
 
 // The same launch inside the inner MINRES (FP64): v = s x, y = s (A11 x) + c r1 written over
 // r1, and one partial sum of v . y per tile in part[] (s, c read from device memory;
-// r1 read only when c != 0).  Returns the number of tiles (entries of part per lane).
+// r1 read only when c != 0).  v goes to slot *slot_dev (a device scalar, clamped to
+// [0, nslot - 1]) of the Lanczos block: v.p + slot vs + lane v.s.  Returns the number of
+// tiles (entries of part per lane).
 int stencil_a11_minres(int n, const StencilTable<double> *tab, const DivTable<double> *dv, LP<const double> x,
                        LP<double> v, LP<double> r1y, LP<const double> s_dev, LP<const double> c_dev,
-                       LP<double> part, hipStream_t s, int K = 1);
+                       LP<const double> slot_dev, int64_t vs, int nslot, LP<double> part, hipStream_t s,
+                       int K = 1);
 int stencil_tile_count(int n);
 
 // Host: the tables of A_f on an n x n grid from the element matrices (assemble.hip).

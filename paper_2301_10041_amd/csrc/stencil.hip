@@ -41,6 +41,11 @@ struct StencilArgs {
   // lane strides (blockIdx.y = lane): vectors, MINRES scalars, per-tile parts.  The C_f^T
   // term (cft_*, xlx, xly) is one system's and is not shifted.
   int64_t lv, ls, lp;
+  // in MINRES: ms_v is the base of the Lanczos block; v goes to slot *ms_slot (a device
+  // scalar of the lane's state, clamped to [0, ms_nslot - 1]) at stride ms_vs
+  const double *ms_slot;
+  int64_t ms_vs;
+  int ms_nslot;
 };
 
 // Views of lane blockIdx.y (null pointers stay null).
@@ -60,6 +65,12 @@ __device__ __forceinline__ StencilArgs<T> lane_args(const StencilArgs<T> &a0) {
   lane_shift(a.ms_s, a.ls);
   lane_shift(a.ms_c, a.ls);
   lane_shift(a.ms_part, a.lp);
+  lane_shift(a.ms_slot, a.ls);
+  if (a.ms_slot) {
+    int sl = (int)*a.ms_slot;
+    sl = sl < 0 ? 0 : sl >= a.ms_nslot ? a.ms_nslot - 1 : sl;
+    a.ms_v += (int64_t)sl * a.ms_vs;
+  }
   return a;
 }
 
@@ -400,13 +411,14 @@ void stencil_fluid_rows(int n, const StencilTable<T> *tab, const DivTable<T> *dv
 
 int stencil_a11_minres(int n, const StencilTable<double> *tab, const DivTable<double> *dv, LP<const double> x,
                        LP<double> v, LP<double> r1y, LP<const double> s_dev, LP<const double> c_dev,
-                       LP<double> part, hipStream_t s, int K) {
+                       LP<const double> slot_dev, int64_t vs, int nslot, LP<double> part, hipStream_t s, int K) {
   FSI_REQUIRE((int64_t)(2 * n + 1) * (2 * n + 1) < INT32_MAX, FSI_E_ARG, "grid too large for 32-bit stencil indices");
+  FSI_REQUIRE(slot_dev.p && nslot >= 1, FSI_E_ARG, "the Lanczos block needs a slot index and at least one slot");
   const int L = 2 * n + 1, L2 = L * L;
   const int64_t lv = common_stride({{x.p, x.s}, {v.p, v.s}, {r1y.p, r1y.s}}, K);
-  const int64_t ls = common_stride({{s_dev.p, s_dev.s}, {c_dev.p, c_dev.s}}, K);
+  const int64_t ls = common_stride({{s_dev.p, s_dev.s}, {c_dev.p, c_dev.s}, {slot_dev.p, slot_dev.s}}, K);
   StencilArgs<double> a{n, tab, x.p, nullptr, nullptr, nullptr, L2, 0.0, 0.0, dv, nullptr, nullptr, nullptr, nullptr,
-                        nullptr, s_dev.p, c_dev.p, v.p, r1y.p, part.p, lv, ls, part.s};
+                        nullptr, s_dev.p, c_dev.p, v.p, r1y.p, part.p, lv, ls, part.s, slot_dev.p, vs, nslot};
   launch_tiles<double, SP_A11>(n, a, s, K);
   const int tx = (L + kTileC - 1) / kTileC, ty = (L + kTileR - 1) / kTileR;
   return tx * ty;
