@@ -15,7 +15,10 @@ Prints one JSON line.  `value` is FP64 steps/s at 1024^2.  Beside it:
              inner Krylov recurrence, residuals and clipping (FSI_FP32);
   fp32_ir    the operator of the Arnoldi process in FP32 as well, with refinement on the FP64
              residual (FSI_FP32_IR);
-  fixed_cost_a11  the fixed-cost inexact A11 option (inner_mode 1);
+  inner_forms  the other inner A11 forms at 1024^2, FP64 and mixed: the fixed-cost
+             block-diagonal (one application of the MINRES preconditioner) and
+             block-triangular (two stationary cycles) forms, and GMRES with the
+             block-triangular approximation in the weighted norm;
   step_roofline   algorithmic bytes of a step (model below, from the measured outer and inner
              step counts) against the step time and 8 TB/s;
   configs    the CPU-fast 32^2 case (both preconditioners), the 256^2 ellipse (both
@@ -580,7 +583,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-fixed-cost", action="store_true",
-                    help="skip the fixed-cost inexact A11 leg (inner_mode 1)")
+                    help="skip the other inner A11 forms (fixed-cost and inner GMRES)")
     ap.add_argument("--no-ir", action="store_true", help="skip the FP32-refinement leg")
     ap.add_argument("--forms", default="fp64,mixed,fp32_ir",
                     help="headline forms to time (comma list of fp64, mixed, fp32_ir; profiling runs)")
@@ -652,15 +655,22 @@ def main():
         del b
     sroof = {tag: step_roofline(ctx, wl.n, res[tag], "fp64" if tag == "fp64" else "fp32", args.pc)
              for tag in res}
-    # the fixed-cost inexact A11 (inner_mode 1: one application of the inner preconditioner,
-    # no inner MINRES), timed the same way; reported beside the method's configuration
+    # the other inner A11 forms, timed the same way; reported beside the method's configuration
     fixed = {}
     if not args.no_fixed_cost:
-        for tag, prec in [f for f in forms if f[0] != "fp32_ir"]:
-            opts = fsi.Opts(restart=30, rtol=1e-8, pc=pc, prec=prec, inner_mode=1)
-            r, _ = time_loop(ctx, u0, Xs, N2, opts, args.warmup, args.steps, f"fixed-cost {tag}")
-            fixed[tag] = dict(value=r["value"], ms_per_step=r["ms_per_step"], its=r["its"],
-                              relres_true=r["relres_true"])
+        for form, mode, cycles in (("fixed_diag", fsi.INNER_FIXED_DIAG, 0), ("fixed_tri_2", fsi.INNER_FIXED_TRI, 2),
+                                   ("gmres_tri", fsi.INNER_GMRES, 0)):
+            fixed[form] = {}
+            for tag, prec in [f for f in forms if f[0] != "fp32_ir"]:
+                opts = fsi.Opts(restart=30, rtol=1e-8, pc=pc, prec=prec, inner_mode=mode, inner_cycles=cycles)
+                r, first = time_loop(ctx, u0, Xs, N2, opts, args.warmup, args.steps, f"{form} {tag}",
+                                     keep_first=True)
+                rec = dict(value=r["value"], ms_per_step=r["ms_per_step"], its=r["its"],
+                           inner_its=r["inner_its"], relres_true=r["relres_true"])
+                if "big_fp64" in save and first is not None:
+                    rec["vs_fp64_first_step"] = float(np.linalg.norm(first - save["big_fp64"]) /
+                                                      np.linalg.norm(save["big_fp64"]))
+                fixed[form][tag] = rec
     ctx.close()
     del Xs, u0
     torch.cuda.empty_cache()
@@ -709,9 +719,10 @@ def main():
     if "fp32_ir" in res:
         out["fp32_ir_speedup"] = round(res["fp32_ir"]["value"] / res["fp64"]["value"], 3)
     if fixed:
-        out["fixed_cost_a11"] = _round(dict(fixed, note="A11^{-1} by one application of its preconditioner "
-                                                        "(inner_mode 1), no inner MINRES: more outer steps than "
-                                                        "with the block inverses, so not the method's configuration"))
+        out["inner_forms"] = _round(dict(
+            fixed, note="A11^{-1} other than by the inner MINRES: the fixed-cost forms take more outer steps than "
+                        "the block inverses (outside the iteration bar), the inner GMRES more inner steps at this "
+                        "size; vs_fp64_first_step: distance of the first step's solution from the headline's"))
     if configs:
         out["configs"] = _round(configs)
     if not args.no_serve:

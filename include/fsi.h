@@ -110,6 +110,24 @@ typedef struct {
   int64_t nnz;      /* entries of the scalar C_f pattern */
 } fsi_coupling_info;
 
+/* The inner A11^{-1} (the paper inverts A11 exactly with a direct solver; here A11 =
+ * [A_f, -B^T; -B, 0] is solved iteratively to inner_rtol, the outer solve being flexible, or
+ * approximated at a fixed cost).  The building blocks: V, one P2 geometric-multigrid V-cycle
+ * on A_f; S~^{-1} = nu M_p^{-1} + (rho/dt) L_p^{-1}, the Cahouet-Chabard approximation of the
+ * inverse Schur complement (B A_f^{-1} B^T)^{-1}.
+ *   FSI_INNER_MINRES (default): MINRES to inner_rtol (its preconditioned residual estimate)
+ *     with the symmetric positive definite block-diagonal diag(V, S~^{-1}).
+ *   FSI_INNER_GMRES: right-preconditioned restarted GMRES on A11 to
+ *     ||D (r - A11 z)|| <= inner_rtol ||D r||, with the block upper-triangular approximation
+ *     P^{-1}: z_p = -S~^{-1} r_p, z_u = V (r_u + B^T z_p) (the pinned pressure row: the
+ *     identity); D weights the pressure rows by sqrt(a_u s_p), a_u the diagonal scale of
+ *     A_f and s_p that of S~^{-1}, so that the norm weighs both blocks like MINRES's.
+ *   FSI_INNER_FIXED_DIAG: one application of diag(V, -S~^{-1}), no inner Krylov steps.
+ *   FSI_INNER_FIXED_TRI: inner_cycles steps of the stationary iteration
+ *     z <- z + P^{-1} (r - A11 z) from z = 0, no inner Krylov steps.
+ * The fixed-cost forms take more outer steps than the oracle's exact blocks. */
+enum fsi_inner { FSI_INNER_MINRES = 0, FSI_INNER_FIXED_DIAG = 1, FSI_INNER_FIXED_TRI = 2, FSI_INNER_GMRES = 3 };
+
 typedef struct {
   int32_t restart;      /* outer FGMRES restart length m (default 30) */
   int32_t maxit;        /* outer Arnoldi steps over all restarts (default 10000) */
@@ -118,16 +136,13 @@ typedef struct {
   int32_t prec;         /* fsi_prec */
   double inner_rtol;    /* relative tolerance of the inner A11 solve (0: default, 1e-2 with the
                            block-triangular, 1e-6 with the block-diagonal preconditioner) */
-  int32_t inner_maxit;  /* inner MINRES steps per A11 solve (default 1000; 300 in FP32) */
+  int32_t inner_maxit;  /* inner Krylov steps per A11 solve (default 1000; 300 in FP32) */
   double cycle_rtol;    /* FSI_FP32_IR: residual reduction asked of each FGMRES cycle
                            (default 1e-5); ignored otherwise */
-  int32_t inner_mode;   /* 0 (default): A11^{-1} by the inner MINRES solve to inner_rtol, the
-                           block inverse of the preconditioners of Sec. 5.  1: a fixed-cost
-                           inexact A11^{-1}, one application of the inner solve's own
-                           preconditioner (velocity V-cycle; minus the Schur approximation on
-                           the pressure, the sign of the Schur complement of A11), no inner
-                           Krylov steps: cheaper outer steps, more of them.  Other values:
-                           FSI_E_ARG. */
+  int32_t inner_mode;   /* fsi_inner: how A11^{-1} is applied inside the block
+                           preconditioners of Sec. 5.  Other values: FSI_E_ARG. */
+  int32_t inner_cycles; /* FSI_INNER_FIXED_TRI: cycles per A11 application (0: 1; at most 100,
+                           else FSI_E_ARG); ignored otherwise */
 } fsi_solve_opts;
 
 typedef struct {
@@ -223,12 +238,16 @@ int fsi_build_rhs(fsi_ctx *ctx, const double *u_n, const double *X_n, double *b)
 int fsi_apply_operator(fsi_ctx *ctx, int prec, const double *x, double *y);
 
 /* z = P^{-1} r, P = diag(A11, A22) or [[A11, 0], [A21, A22]] (Sec. 5).  A22^{-1} in
- * closed form (two solid mass solves and one A_s product); A11^{-1} by an inner MINRES
- * solve to the context's inner tolerance (fsi_set_inner), preconditioned by a P2
- * geometric multigrid V-cycle on A_f and a Cahouet-Chabard pressure approximation.
- * r, z: device N (no aliasing). */
+ * closed form (two solid mass solves and one A_s product); A11^{-1} by the context's inner
+ * mode (fsi_set_inner_mode, default FSI_INNER_MINRES) to its inner tolerance
+ * (fsi_set_inner).  r, z: device N (no aliasing). */
 int fsi_apply_precond(fsi_ctx *ctx, int pc, int prec, const double *r, double *z);
+/* The context's inner tolerance (<= 0: the default of the preconditioner) and step limit
+ * (0: unchanged; negative: FSI_E_ARG). */
 int fsi_set_inner(fsi_ctx *ctx, double inner_rtol, int32_t inner_maxit);
+/* The context's inner mode (fsi_inner) and FSI_INNER_FIXED_TRI cycles (0: 1; at most 100),
+ * used by fsi_apply_precond; a solve takes both from its options.  Errors: FSI_E_ARG. */
+int fsi_set_inner_mode(fsi_ctx *ctx, int32_t mode, int32_t cycles);
 
 /* Right-preconditioned flexible GMRES(m) on eq. (matrix) from the initial guess in x,
  * stopping when ||b - A x||_2 <= rtol ||b||_2 (Sec. 6, recomputed in FP64); precision

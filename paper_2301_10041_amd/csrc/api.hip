@@ -24,6 +24,7 @@ Ctx::~Ctx() {
   if (ev_join) (void)hipEventDestroy(ev_join);
   if (hpin) (void)hipHostFree(hpin);
   if (bat_h) (void)hipHostFree(bat_h);
+  if (gi_h) (void)hipHostFree(gi_h);
 }
 
 void Prof::begin(hipStream_t s) {
@@ -73,7 +74,8 @@ size_t Ctx::device_bytes() const {
        outer.y32.bytes();
   b += red.bytes() + dscal.bytes() + tmpN.bytes() + tmpS.bytes();
   b += ms_state.bytes() + ms_red.bytes() + ms_x.bytes() + ms_part.bytes() + ms_dot.bytes() + ms_vh.bytes() +
-       ms_hist.bytes() + ms_coef.bytes() + pc_in.bytes() +
+       ms_hist.bytes() + ms_coef.bytes() + gi_V.bytes() + gi_Z.bytes() + gi_part.bytes() + gi_dh.bytes() +
+       gi_sc.bytes() + pc_in.bytes() +
        pc_out.bytes();
   return b;
 }
@@ -328,6 +330,14 @@ int fsi_set_inner(fsi_ctx *ctx, double inner_rtol, int32_t inner_maxit) {
   if (inner_maxit < 0) return FSI_E_ARG;
   ctx->c.inner_rtol = inner_rtol;
   if (inner_maxit > 0) ctx->c.inner_maxit = inner_maxit;
+  return FSI_OK;
+}
+
+int fsi_set_inner_mode(fsi_ctx *ctx, int32_t mode, int32_t cycles) {
+  if (!ctx) return FSI_E_ARG;
+  if (mode < FSI_INNER_MINRES || mode > FSI_INNER_GMRES || cycles < 0 || cycles > 100) return FSI_E_ARG;
+  ctx->c.inner_mode = mode;
+  ctx->c.inner_cycles = cycles > 0 ? cycles : 1;
   return FSI_OK;
 }
 

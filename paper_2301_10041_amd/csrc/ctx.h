@@ -179,6 +179,11 @@ struct Ctx {
   // the recorded direction scalars ([lane][slot][5]) and the combination coefficients
   DevBuf<double> ms_vh, ms_hist, ms_coef;
   int ms_B = 0;
+  // inner GMRES (FSI_INNER_GMRES): basis, preconditioned vectors, reduction partials, device
+  // results, scalars; pinned host staging
+  DevBuf<double> gi_V, gi_Z, gi_part, gi_dh, gi_sc;
+  double *gi_h = nullptr;
+  double gi_wp = 0.0;   // weight of the pressure rows in its residual norm (set on first use)
   hipGraphExec_t ms_graph[2][FSI_MAX_LANES + 1][6] = {};   // per precision, lane count, rotation phase
   DevBuf<double> pc_in, pc_out;
   void drop_graphs();
@@ -188,7 +193,8 @@ struct Ctx {
   int lanes = 1;
   double inner_rtol = -1.0;   // < 0: default per precision
   int inner_maxit = 1000;
-  int inner_mode = 0;         // 1: A11^{-1} by one application of its preconditioner (no MINRES)
+  int inner_mode = FSI_INNER_MINRES;  // fsi_inner: how A11^{-1} is applied
+  int inner_cycles = 1;               // FSI_INNER_FIXED_TRI: stationary cycles
   int64_t inner_its_total = 0;
 
   ~Ctx();

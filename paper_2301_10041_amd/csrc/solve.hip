@@ -539,12 +539,16 @@ constexpr int kMpSteps = 3;
 // dot (FP64 form, tile_dot_ok): the launches that write z also store per-tile / per-block
 // parts of r . z: cheb3_dot_count(n) velocity tile sums, then kPresDotBlocks pressure
 // block sums, per lane (lane stride dot.s).
+// part: PC_BOTH, or only the velocity cycle (PC_VEL) or only the pressure part (PC_PRES); the
+// other part of z is left as it is.
+enum { PC_BOTH = 0, PC_VEL = 1, PC_PRES = 2 };
 template <typename T>
 static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 = nullptr, double *z64 = nullptr,
-                        LP<double> dot = LP<double>()) {
+                        LP<double> dot = LP<double>(), int part = PC_BOTH) {
   FSI_REQUIRE((!dot.p || std::is_same<T, double>::value || r64), FSI_E_STATE,
               "sums of r . z in the FP32 form need the FP64 residual");
-  const bool fork = !c.capturing;
+  FSI_REQUIRE(!dot.p || part == PC_BOTH, FSI_E_STATE, "the sums of r . z need both parts");
+  const bool fork = !c.capturing && part == PC_BOTH;
   hipStream_t s = c.stream, sp = fork ? c.aux_stream : c.stream;
   const int64_t N2 = c.N2, Np = c.Np, nf = 2 * N2 + Np;
   Prof *pf = std::is_same<T, double>::value ? &c.prof64 : &c.prof32;
@@ -552,7 +556,9 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
     FSI_HIP(hipEventRecord(c.ev_fork, s));
     FSI_HIP(hipStreamWaitEvent(sp, c.ev_fork, 0));
   }
-  if (z64) {
+  if (part == PC_PRES) {
+    // the velocity cycle is not run
+  } else if (z64) {
     T *xu = vcycle<T, 4, 2>(c.mgu, 0, r, s, pf->on ? pf : nullptr, 1, nullptr, z64, dot,
                             LP<const double>(dot.p ? r64 : nullptr));
     FSI_REQUIRE(!dot.p || !xu, FSI_E_STATE, "the sums of r . z need the direct FP64 output");
@@ -566,6 +572,10 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
     T *xu = vcycle<T, 4, 2>(c.mgu, 0, bu, s, nullptr, K, nullptr, nullptr, dot,
                             LP<const double>(dot.p && r64 ? r64 : nullptr, nf));
     convert_l(LP<T>(z, nf), LP<const T>(xu, 2 * N2), 2 * N2, s, K);
+  }
+  if (part == PC_VEL) {
+    FSI_CHECK_LAUNCH();
+    return;
   }
   // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
   T *rp = Pr<T>::inner(c, 8).p;
@@ -609,17 +619,20 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
 // of the velocity residual (read three times by the finest level) and stores its results
 // straight into z; several systems run on converted copies of whole vectors.
 template <typename TA>
-static void a11_precond_on64(Ctx &c, const double *r, double *z, int K = 1) {
+static void a11_precond_on64(Ctx &c, const double *r, double *z, int K = 1, int part = PC_BOTH) {
   if constexpr (std::is_same<TA, double>::value) {
-    a11_precond<double>(c, r, z, K);
+    a11_precond<double>(c, r, z, K, nullptr, nullptr, LP<double>(), part);
   } else if (K == 1) {
-    convert(c.outer.x32.p, r, 2 * c.N2, c.stream);
-    a11_precond<float>(c, c.outer.x32.p, nullptr, 1, r, z);
+    if (part != PC_PRES) convert(c.outer.x32.p, r, 2 * c.N2, c.stream);
+    a11_precond<float>(c, c.outer.x32.p, nullptr, 1, r, z, LP<double>(), part);
   } else {
-    const int64_t nf = 2 * c.N2 + c.Np;
+    const int64_t nf = 2 * c.N2 + c.Np, nv = 2 * c.N2;
     convert_l(LP<float>(c.outer.x32.p, nf), LP<const double>(r, nf), nf, c.stream, K);
-    a11_precond<float>(c, c.outer.x32.p, c.outer.y32.p, K);
-    convert_l(LP<double>(z, nf), LP<const float>(c.outer.y32.p, nf), nf, c.stream, K);
+    a11_precond<float>(c, c.outer.x32.p, c.outer.y32.p, K, nullptr, nullptr, LP<double>(), part);
+    if (part != PC_PRES)
+      convert_l(LP<double>(z, nf), LP<const float>(c.outer.y32.p, nf), nv, c.stream, K);
+    if (part != PC_VEL)
+      convert_l(LP<double>(z + nv, nf), LP<const float>(c.outer.y32.p + nv, nf), nf - nv, c.stream, K);
   }
 }
 
@@ -1168,6 +1181,52 @@ static void a11_fixed(Ctx &c, const double *const *r, double *const *z, int K) {
   FSI_CHECK_LAUNCH();
 }
 
+// The fixed-cost block-triangular A11^{-1} (FSI_INNER_FIXED_TRI): `cycles` steps of the stationary
+// iteration z <- z + P^{-1} (r - A11 z) from z = 0 with the block upper-triangular
+// approximation of A11 = [A_f, -B^T; -B, 0] (pinned row: the identity),
+//   P = [V^{-1}, -B^T; 0, -S~]:  z_p = -S~^{-1} r_p (the pinned entry: r_p),
+//                                z_u = V (r_u + B^T z_p),
+// V one velocity V-cycle and S~^{-1} the Cahouet-Chabard approximation of the MINRES
+// preconditioner.  With exact blocks every eigenvalue of P^{-1} A11 is 1 (the block
+// factorisation of A11), so the iteration converges; the block-diagonal form does not (its
+// preconditioned A11 has the eigenvalues 1 and (1 +- i sqrt 3) / 2).  The pressure part
+// runs before the velocity cycle, on one stream.
+template <typename TA>
+static void a11_tri_apply(Ctx &c, const double *r, double *z, double *q, double *y, int K) {
+  hipStream_t s = c.stream;
+  const int64_t nf = 2 * c.N2 + c.Np, nv = 2 * c.N2 + 1;
+  a11_precond_on64<TA>(c, r, z, K, PC_PRES);   // z_p = S~^{-1} r_p, z_p[pin] = r_p[pin]
+  for (int k = 0; k < K; ++k) {
+    double *zk = z + k * nf, *qk = q + k * nf;
+    hipLaunchKernelGGL(k_negate<double>, dim3(vgrid(nf - nv)), dim3(256), 0, s, zk + nv, zk + nv, nf - nv);
+    // r_u + B^T z_p = r_u - (A11 [0; z_p])_u
+    fill(qk, 2 * c.N2, 0.0, s);
+    convert(qk + 2 * c.N2, zk + 2 * c.N2, c.Np, s);
+    apply_a11_on64<double>(c, qk, y + k * nf);
+  }
+  lincomb_l(LP<double>(q, nf), LP<const double>(r, nf), LP<const double>(y, nf), 1.0, -1.0, 2 * c.N2, s, K);
+  a11_precond_on64<TA>(c, q, z, K, PC_VEL);    // z_u = V (r_u + B^T z_p)
+  FSI_CHECK_LAUNCH();
+}
+
+template <typename TA>
+static void a11_fixed_tri(Ctx &c, const double *const *r, double *const *z, int K, int cycles) {
+  hipStream_t s = c.stream;
+  const int64_t nf = 2 * c.N2 + c.Np;
+  double *R = c.inner.v64[2].p, *Z = c.inner.v64[3].p, *T = c.inner.v64[4].p, *D = c.inner.v64[5].p;
+  double *Q = c.inner.v64[0].p, *Y = c.inner.v64[1].p;
+  for (int k = 0; k < K; ++k) convert(R + k * nf, r[k], nf, s);
+  a11_tri_apply<TA>(c, R, Z, Q, Y, K);
+  for (int cyc = 1; cyc < cycles; ++cyc) {
+    for (int k = 0; k < K; ++k) apply_a11_on64<double>(c, Z + k * nf, Y + k * nf);
+    lincomb_l(LP<double>(T, nf), LP<const double>(R, nf), LP<const double>(Y, nf), 1.0, -1.0, nf, s, K);
+    a11_tri_apply<TA>(c, T, D, Q, Y, K);
+    lincomb_l(LP<double>(Z, nf), LP<const double>(Z, nf), LP<const double>(D, nf), 1.0, 1.0, nf, s, K);
+  }
+  for (int k = 0; k < K; ++k) convert(z[k], Z + k * nf, nf, s);
+  FSI_CHECK_LAUNCH();
+}
+
 // ---------------------------------------------------------------- A22 closed form (FP64)
 // C_s^{-1} by Chebyshev-Jacobi steps on the interval [1/2, 2] of D^{-1} C_s (P1 mass matrix on
 // triangles): the error falls by 1/3 per step.  The solve is taken four orders of magnitude
@@ -1445,11 +1504,44 @@ static void ensure_inner(Ctx &c, int prec, int K = 1) {
 // first step of the rotating disk at 256^2) it takes 16 / 18 / 22 / 8 at 1e-3, 16 / 16 / 20 / 6
 // at 1e-4 and 1e-5, and 16 / 16 / 20 / 4 at 1e-6.  Time at 1e-6 against 1e-3: +23%, +23%,
 // +25% on the random right-hand sides, -27% on the time step.
+// Weight of the pressure rows in the residual norm of the inner GMRES: the ratio of the scales
+// of the two diagonal blocks of the block-diagonal approximation diag(A_f^{-1}, S~^{-1}), so
+// that ||D r|| behaves like the norm MINRES uses.  w = sqrt(a_u s_p): a_u the mean diagonal of
+// A_f at interior nodes (the four classes' 2 x 2 blocks), s_p = nu / m_p + (rho/dt) / l_p with
+// m_p and l_p the interior diagonals of the P1 mass and Laplacian (the Cahouet-Chabard
+// scale).  About 2 n with nu = 1, rho/dt = 100.  Without it (w = 1) the inner solves at 1e-2
+// leave the divergence rows, whose entries are O(h) times smaller, nearly unconverged: at
+// 128^2 the step at rtol 1e-8 was 3.5e-7 (u) and 1.3e-6 (p) away from the oracle, against
+// 1.5e-9 and 5.6e-9 with w = n (4 n and 16 n: the same errors, more inner steps).
+double inner_pressure_weight(Ctx &c) {
+  if (c.gi_wp > 0) return c.gi_wp;
+  StencilTable<double> a;
+  StencilTable<float> af;
+  stencil_tables(c.n, c.nu, c.rho / c.dt, a, af);
+  double au = 0.0;
+  for (int k = 0; k < 4; ++k) {   // the diagonal of the inverse of each class's D^{-1} block
+    const double *d = a.dinv[k];
+    const double det = d[0] * d[3] - d[1] * d[2];
+    au += 0.25 * 0.5 * (d[0] + d[3]) / det;
+  }
+  P1Table<double> mp, lp;
+  P1Table<float> f;
+  p1_tables(c.n, kTableMp, 0, mp, f);
+  p1_tables(c.n, kTableLp, 0, lp, f);
+  const double sp = c.nu * mp.dinv[4] + (c.rho / c.dt) * lp.dinv[4];
+  FSI_REQUIRE(au > 0 && sp > 0, FSI_E_STATE, "non-positive diagonal scales");
+  c.gi_wp = std::sqrt(au * sp);
+  return c.gi_wp;
+}
+
 double inner_tol(const Ctx &c, int prec, int pc) {
   (void)prec;
   if (c.inner_rtol > 0) return c.inner_rtol;
   return pc == FSI_PC_DIAG ? 1e-6 : 1e-2;
 }
+
+template <typename TA>
+static void gmres_a11(Ctx &c, const double *const *b, double *const *xout, int K, double tol, int maxit, int *its);
 
 // The block preconditioner on K systems: system k belongs to context cs[k] (one fluid grid
 // and fluid parameters for all); the A11 solves of all run in lockstep on the inner lanes of
@@ -1468,11 +1560,18 @@ void apply_precond_lanes(Ctx &c, Ctx *const *cs, int K, int pc, int prec, const 
   ensure_inner(c, prec, K);
   const double tol = inner_tol(c, prec, pc);
   int its[FSI_MAX_LANES];
-  if (c.inner_mode == 1) {   // fixed cost: one application of the inner preconditioner
+  if (c.inner_mode == FSI_INNER_FIXED_DIAG) {   // one application of the MINRES preconditioner
     if (prec == FSI_FP64) a11_fixed<double>(c, r, z, K);
     else a11_fixed<float>(c, r, z, K);
     for (int k = 0; k < K; ++k) its[k] = 0;
-  } else if (prec == FSI_FP64) {
+  } else if (c.inner_mode == FSI_INNER_FIXED_TRI) {   // block-triangular stationary cycles
+    if (prec == FSI_FP64) a11_fixed_tri<double>(c, r, z, K, c.inner_cycles);
+    else a11_fixed_tri<float>(c, r, z, K, c.inner_cycles);
+    for (int k = 0; k < K; ++k) its[k] = 0;
+  } else if (c.inner_mode == FSI_INNER_GMRES) {   // GMRES, block-triangular approximation
+    if (prec == FSI_FP64) gmres_a11<double>(c, r, z, K, tol, c.inner_maxit, its);
+    else gmres_a11<float>(c, r, z, K, tol, c.inner_maxit, its);
+  } else if (prec == FSI_FP64) {   // the default: MINRES, block-diagonal SPD preconditioner
     minres_a11<double>(c, r, z, K, tol, c.inner_maxit, its);
   } else {
     minres_a11<float>(c, r, z, K, tol, c.inner_maxit, its);
@@ -1536,12 +1635,13 @@ static void residual64(Ctx &c, const double *b, const double *x, double *r) {
 // k_multiaxpy_sub on one system (red_blocks(n) chunks of the lane's own length), so each
 // system's numbers do not depend on the batch.
 struct ArnLane {
-  const double *V;   // Krylov basis (k vectors at stride n)
+  const double *V;   // Krylov basis (k vectors at stride ldv, n when ldv is 0)
   const double *w;   // current vector (w for the dots, updated in place by the axpy)
   double *part;      // red_blocks(n) * k partial sums
   double *h;         // k results
   int64_t n;
   int k, nb;
+  int64_t ldv;
 };
 struct ArnArgs {
   ArnLane l[FSI_MAX_LANES];
@@ -1550,13 +1650,13 @@ struct ArnArgs {
 // this thread's parts of V_q . w for G vectors V_q = v + q n over the chunk [lo, hi) (G a
 // compile-time count: no branch between the loads, which issue together)
 template <int G>
-__device__ __forceinline__ void arn_dot_group(const double *v, const double *w, int64_t n, int64_t lo, int64_t hi,
+__device__ __forceinline__ void arn_dot_group(const double *v, const double *w, int64_t ldv, int64_t lo, int64_t hi,
                                               double (&s)[4]) {
 #pragma unroll 4
   for (int64_t e = lo + threadIdx.x; e < hi; e += kRedBlock) {
     const double we = w[e];
 #pragma unroll
-    for (int q = 0; q < G; ++q) s[q] += v[(int64_t)q * n + e] * we;
+    for (int q = 0; q < G; ++q) s[q] += v[(int64_t)q * ldv + e] * we;
   }
 }
 
@@ -1569,15 +1669,16 @@ __global__ void __launch_bounds__(kRedBlock) k_arn_dot_part(ArnArgs a) {
   // block sums share one barrier; every sum keeps the order of a single dot product
   constexpr int G = 4;
   __shared__ double ws[G][kRedBlock / kWave];
+  const int64_t ldv = L.ldv ? L.ldv : L.n;
   for (int i0 = 0; i0 < L.k; i0 += G) {
     const int g = L.k - i0 < G ? L.k - i0 : G;   // uniform over the block
-    const double *v = L.V + (int64_t)i0 * L.n;
+    const double *v = L.V + (int64_t)i0 * ldv;
     double s[G] = {0.0, 0.0, 0.0, 0.0};
     switch (g) {
-      case 4: arn_dot_group<4>(v, L.w, L.n, lo, hi, s); break;
-      case 3: arn_dot_group<3>(v, L.w, L.n, lo, hi, s); break;
-      case 2: arn_dot_group<2>(v, L.w, L.n, lo, hi, s); break;
-      default: arn_dot_group<1>(v, L.w, L.n, lo, hi, s); break;
+      case 4: arn_dot_group<4>(v, L.w, ldv, lo, hi, s); break;
+      case 3: arn_dot_group<3>(v, L.w, ldv, lo, hi, s); break;
+      case 2: arn_dot_group<2>(v, L.w, ldv, lo, hi, s); break;
+      default: arn_dot_group<1>(v, L.w, ldv, lo, hi, s); break;
     }
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
 #pragma unroll
@@ -1608,9 +1709,10 @@ __global__ void k_arn_dot_final(ArnArgs a) {
 __global__ void k_arn_axpy_sub(ArnArgs a) {   // w -= sum_i h[i] V_i
   const ArnLane &L = a.l[blockIdx.y];
   double *w = const_cast<double *>(L.w);
+  const int64_t ldv = L.ldv ? L.ldv : L.n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L.n; e += (int64_t)gridDim.x * blockDim.x) {
     double s = w[e];
-    for (int i = 0; i < L.k; ++i) s -= L.h[i] * L.V[(int64_t)i * L.n + e];
+    for (int i = 0; i < L.k; ++i) s -= L.h[i] * L.V[(int64_t)i * ldv + e];
     w[e] = s;
   }
 }
@@ -1619,6 +1721,215 @@ static void arn_dots(ArnArgs &a, int K, int kmax, int nbmax, hipStream_t s) {
   hipLaunchKernelGGL(k_arn_dot_part, dim3((unsigned)nbmax, (unsigned)K), dim3(kRedBlock), 0, s, a);
   hipLaunchKernelGGL(k_arn_dot_final, dim3((unsigned)kmax, (unsigned)K), dim3(kWave), 0, s, a);
   FSI_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------- inner GMRES on A11
+// A11^{-1} of K systems (FSI_INNER_GMRES) by right-preconditioned restarted GMRES with
+// the block upper-triangular approximation P of a11_tri_apply (one cycle, a fixed linear
+// operator) to ||D (b - A11 x)|| <= tol ||D b||, from x = 0, with D = diag(I, w I) weighting
+// the pressure rows (inner_pressure_weight): GMRES runs on D A11 D^{-1} with the
+// preconditioner D P^{-1} D^{-1}.  The spectrum of P^{-1} A11 is that of the Schur
+// approximation's S~^{-1} S (real, in (0, 1]) perturbed by the velocity cycle, where a Krylov
+// method gains far more per step than the stationary cycles and than MINRES with the
+// block-diagonal preconditioner (which must treat both signs of the saddle-point spectrum).
+// Arnoldi with two classical Gram-Schmidt passes (the kernels of the outer solve); the
+// Hessenberg least-squares problem on the host, one synchronisation per step for all
+// systems.  Basis V_j and preconditioned vectors Z_j = P^{-1} V_j of all lanes stored
+// [j][lane][nf]; x += Z y once a lane converges or its cycle ends.  Every lane follows its
+// own sequence of operations, so its result does not depend on the batch.
+constexpr int kGiM = 20;   // inner restart length
+
+__global__ void k_lane_scale(double *v, const double *w, const double *scale, int64_t n) {
+  const double a = scale[blockIdx.y];
+  const int64_t o = (int64_t)blockIdx.y * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[o + i] = a * w[o + i];
+}
+
+// dst = src with entries [off, n) of every lane scaled by a (dst may be src)
+__global__ void k_lane_scale_tail(double *dst, const double *src, int64_t n, int64_t off, double a) {
+  const int64_t o = (int64_t)blockIdx.y * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[o + i] = i >= off ? a * src[o + i] : src[o + i];
+}
+
+// x_lane += sum_{i < count} y_i Z_i (lane's coefficients at coef + lane cs: count, y_0, ...)
+__global__ void k_lane_combine(double *x, const double *Z, int64_t ldz, const double *coef, int cs, int64_t n) {
+  const double *cf = coef + (int64_t)blockIdx.y * cs;
+  const int cnt = (int)cf[0];
+  if (cnt == 0) return;
+  const int64_t o = (int64_t)blockIdx.y * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double a = x[o + i];
+    for (int k = 0; k < cnt; ++k) a += cf[1 + k] * Z[(int64_t)k * ldz + o + i];
+    x[o + i] = a;
+  }
+}
+
+double inner_pressure_weight(Ctx &c);
+
+template <typename TA>
+static void gmres_a11(Ctx &c, const double *const *b, double *const *xout, int K, double tol, int maxit, int *its) {
+  hipStream_t s = c.stream;
+  const double wp = inner_pressure_weight(c);
+  const int64_t nf = 2 * c.N2 + c.Np, L = c.lanes, ld = L * nf;
+  const int m = std::max(1, std::min(kGiM, maxit));
+  const int nb = red_blocks(nf), st = 2 * (m + 1) + 1, cs = m + 1;
+  c.gi_V.reserve((size_t)(m + 1) * ld);
+  c.gi_Z.reserve((size_t)m * ld);
+  c.gi_part.reserve((size_t)L * nb * (m + 1));
+  c.gi_dh.reserve((size_t)L * st);
+  c.gi_sc.reserve((size_t)L * (cs + 1));
+  if (!c.gi_h) FSI_HIP(hipHostMalloc((void **)&c.gi_h, (size_t)FSI_MAX_LANES * (st + cs + 1) * 2 * sizeof(double),
+                                     hipHostMallocDefault));
+  double *hd = c.gi_h;                                       // device -> host results
+  double *hu = c.gi_h + (size_t)FSI_MAX_LANES * (st + cs + 1);   // host -> device scalars
+  double *X = c.inner.v64[3].p, *Bv = c.inner.v64[2].p, *R = c.inner.v64[4].p;
+  double *Q = c.inner.v64[0].p, *Y = c.inner.v64[1].p;
+  double *V = c.gi_V.p, *Z = c.gi_Z.p, *scale = c.gi_sc.p, *coef = c.gi_sc.p + L;
+  fill_l(LP<double>(X, nf), nf, 0.0, s, K);
+  for (int k = 0; k < K; ++k) convert(Bv + k * nf, b[k], nf, s);
+  const int64_t pofs = 2 * c.N2;   // the pressure rows, weighted by wp in the residual norm
+  auto weigh = [&](double *dst, const double *src, double a) {
+    hipLaunchKernelGGL(k_lane_scale_tail, dim3(vgrid(nf), K), dim3(256), 0, s, dst, src, nf, pofs, a);
+  };
+  // per-lane norms (or h columns) of the vectors w_q: k = 1 dots into gi_dh + q st + off
+  auto norms = [&](const double *w, int off) {
+    ArnArgs a{};
+    for (int q = 0; q < K; ++q)
+      a.l[q] = ArnLane{w + q * nf, w + q * nf, c.gi_part.p + (int64_t)q * nb * (m + 1), c.gi_dh.p + q * st + off, nf,
+                       1, nb, 0};
+    arn_dots(a, K, 1, nb, s);
+  };
+  auto fetch = [&]() {
+    FSI_HIP(hipMemcpyAsync(hd, c.gi_dh.p, (size_t)K * st * sizeof(double), hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+  };
+  // the H2D copies read hu asynchronously: it is rewritten only after a later synchronisation
+  auto scale_lanes = [&](double *dst, const double *src, const std::vector<double> &a) {
+    for (int q = 0; q < K; ++q) hu[q] = a[q];
+    FSI_HIP(hipMemcpyAsync(scale, hu, (size_t)K * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_lane_scale, dim3(vgrid(nf), K), dim3(256), 0, s, dst, src, scale, nf);
+  };
+  weigh(R, Bv, wp);
+  norms(R, 2 * (m + 1));
+  fetch();
+  std::vector<double> bnorm(K), beta(K), sc(K);
+  std::vector<int> done(K, 0), total(K, 0);
+  for (int q = 0; q < K; ++q) {
+    const double b2 = hd[q * st + 2 * (m + 1)];
+    FSI_REQUIRE(std::isfinite(b2), FSI_E_NONFINITE, "non-finite right-hand side of the inner A11 solve");
+    bnorm[q] = std::sqrt(b2 > 0 ? b2 : 0.0);
+    done[q] = bnorm[q] == 0.0;
+    beta[q] = bnorm[q];
+  }
+  std::vector<double> H((size_t)K * (m + 1) * m), gs((size_t)K * (m + 1)), cosv((size_t)K * m), sinv((size_t)K * m);
+  std::vector<int> steps(K), act(K);
+  bool first = true;
+  auto any = [](const std::vector<int> &v) {
+    for (int x : v) if (x) return true;
+    return false;
+  };
+  while (true) {
+    for (int q = 0; q < K; ++q) act[q] = !done[q] && total[q] < maxit;
+    if (!any(act)) break;
+    // V_0 = r / ||r||, r = D (b - A11 x) (D b on the first cycle)
+    const double *r0 = R;
+    if (!first) {
+      for (int q = 0; q < K; ++q) apply_a11_on64<double>(c, X + q * nf, Y + q * nf);
+      lincomb_l(LP<double>(R, nf), LP<const double>(Bv, nf), LP<const double>(Y, nf), 1.0, -1.0, nf, s, K);
+      weigh(R, R, wp);
+      norms(R, 2 * (m + 1));
+      fetch();
+      for (int q = 0; q < K; ++q) {
+        const double r2 = hd[q * st + 2 * (m + 1)];
+        FSI_REQUIRE(std::isfinite(r2), FSI_E_NONFINITE, "non-finite residual in the inner A11 solve");
+        beta[q] = std::sqrt(r2 > 0 ? r2 : 0.0);
+        if (act[q] && beta[q] <= tol * bnorm[q]) { act[q] = 0; done[q] = 1; }
+      }
+      if (!any(act)) break;
+    }
+    first = false;
+    for (int q = 0; q < K; ++q) {
+      sc[q] = act[q] && beta[q] > 0 ? 1.0 / beta[q] : 0.0;
+      std::fill(gs.begin() + (size_t)q * (m + 1), gs.begin() + (size_t)(q + 1) * (m + 1), 0.0);
+      gs[(size_t)q * (m + 1)] = beta[q];
+      steps[q] = 0;
+    }
+    scale_lanes(V, r0, sc);
+    std::vector<int> run = act;   // lanes still stepping in this cycle
+    for (int j = 0; j < m && any(run); ++j) {
+      double *Vj = V + (int64_t)j * ld, *Zj = Z + (int64_t)j * ld, *W = V + (int64_t)(j + 1) * ld;
+      weigh(R, Vj, 1.0 / wp);   // Z_j = P^{-1} D^{-1} V_j, W = D A11 Z_j
+      a11_tri_apply<TA>(c, R, Zj, Q, Y, K);
+      for (int q = 0; q < K; ++q) apply_a11_on64<double>(c, Zj + q * nf, W + q * nf);
+      weigh(W, W, wp);
+      ArnArgs a1{}, a2{};
+      for (int q = 0; q < K; ++q) {
+        double *part = c.gi_part.p + (int64_t)q * nb * (m + 1), *dh = c.gi_dh.p + q * st;
+        a1.l[q] = ArnLane{V + q * nf, W + q * nf, part, dh, nf, j + 1, nb, ld};
+        a2.l[q] = ArnLane{V + q * nf, W + q * nf, part, dh + (m + 1), nf, j + 1, nb, ld};
+      }
+      arn_dots(a1, K, j + 1, nb, s);
+      hipLaunchKernelGGL(k_arn_axpy_sub, dim3(vgrid(nf), (unsigned)K), dim3(256), 0, s, a1);
+      arn_dots(a2, K, j + 1, nb, s);
+      hipLaunchKernelGGL(k_arn_axpy_sub, dim3(vgrid(nf), (unsigned)K), dim3(256), 0, s, a2);
+      norms(W, 2 * (m + 1));
+      FSI_CHECK_LAUNCH();
+      fetch();
+      for (int q = 0; q < K; ++q) {
+        sc[q] = 0.0;
+        if (!run[q]) continue;
+        const double *hp = hd + q * st;
+        double *hc = &H[((size_t)q * m + j) * (m + 1)];   // column j of lane q
+        for (int i = 0; i <= j; ++i) hc[i] = hp[i] + hp[(m + 1) + i];
+        const double hn = std::sqrt(hp[2 * (m + 1)] > 0 ? hp[2 * (m + 1)] : 0.0);
+        FSI_REQUIRE(std::isfinite(hn), FSI_E_NONFINITE, "non-finite vector in the inner A11 solve");
+        hc[j + 1] = hn;
+        double *cq = &cosv[(size_t)q * m], *sq = &sinv[(size_t)q * m], *g = &gs[(size_t)q * (m + 1)];
+        for (int i = 0; i < j; ++i) {
+          const double t = cq[i] * hc[i] + sq[i] * hc[i + 1];
+          hc[i + 1] = -sq[i] * hc[i] + cq[i] * hc[i + 1];
+          hc[i] = t;
+        }
+        const double den = std::hypot(hc[j], hc[j + 1]);
+        cq[j] = den > 0 ? hc[j] / den : 1.0;
+        sq[j] = den > 0 ? hc[j + 1] / den : 0.0;
+        hc[j] = den;
+        hc[j + 1] = 0.0;
+        g[j + 1] = -sq[j] * g[j];
+        g[j] = cq[j] * g[j];
+        steps[q] = j + 1;
+        ++total[q];
+        const bool conv = std::fabs(g[j + 1]) <= tol * bnorm[q] || hn == 0.0;
+        if (conv) done[q] = 1;
+        if (conv || total[q] >= maxit) run[q] = 0;
+        else sc[q] = 1.0 / hn;
+      }
+      if (j + 1 < m && any(run)) scale_lanes(W, W, sc);
+    }
+    // x += Z y for every lane that stepped in this cycle, y from the triangular system
+    for (int q = 0; q < K; ++q) {
+      double *cf = hu + K + (size_t)q * cs;
+      const int k = act[q] ? steps[q] : 0;
+      cf[0] = (double)k;
+      const double *g = &gs[(size_t)q * (m + 1)];
+      for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int l = i + 1; l < k; ++l) t -= H[((size_t)q * m + l) * (m + 1) + i] * cf[1 + l];
+        const double d = H[((size_t)q * m + i) * (m + 1) + i];
+        cf[1 + i] = d != 0.0 ? t / d : 0.0;
+      }
+    }
+    FSI_HIP(hipMemcpyAsync(coef, hu + K, (size_t)K * cs * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_lane_combine, dim3(vgrid(nf), K), dim3(256), 0, s, X, Z, ld, coef, cs, nf);
+    FSI_CHECK_LAUNCH();
+    FSI_HIP(hipStreamSynchronize(s));   // hu is reused by the next cycle
+  }
+  for (int k = 0; k < K; ++k) {
+    its[k] = total[k];
+    convert(xout[k], X + k * nf, nf, s);
+  }
 }
 
 // One system of a lockstep FGMRES solve: its context, vectors, statistics and the state
@@ -1671,11 +1982,12 @@ void gmres_solve_lanes(Ctx *const *cs, int K, const fsi_solve_opts &o, const dou
   struct Restore {
     Ctx *c;
     double r;
-    int m, mode;
+    int m, mode, cycles;
     ~Restore() {
       c->inner_rtol = r;
       c->inner_maxit = m;
       c->inner_mode = mode;
+      c->inner_cycles = cycles;
     }
   };
   std::vector<Restore> restore;
@@ -1685,9 +1997,12 @@ void gmres_solve_lanes(Ctx *const *cs, int K, const fsi_solve_opts &o, const dou
     Ctx &c = *cs[k];
     FSI_REQUIRE(c.have_cf, FSI_E_STATE, "the solve needs C_f: call fsi_assemble_coupling first");
     FSI_REQUIRE(c.stream == s, FSI_E_STATE, "systems of one lockstep solve share one stream");
-    FSI_REQUIRE(o.inner_mode == 0 || o.inner_mode == 1, FSI_E_ARG, "unknown inner mode");
-    restore.push_back({&c, c.inner_rtol, c.inner_maxit, c.inner_mode});
+    FSI_REQUIRE(o.inner_mode >= FSI_INNER_MINRES && o.inner_mode <= FSI_INNER_GMRES, FSI_E_ARG,
+                "unknown inner mode");
+    FSI_REQUIRE(o.inner_cycles >= 0 && o.inner_cycles <= 100, FSI_E_ARG, "inner cycles out of range");
+    restore.push_back({&c, c.inner_rtol, c.inner_maxit, c.inner_mode, c.inner_cycles});
     c.inner_mode = o.inner_mode;
+    c.inner_cycles = o.inner_cycles > 0 ? o.inner_cycles : 1;
     if (o.inner_rtol > 0) c.inner_rtol = o.inner_rtol;
     if (o.inner_maxit > 0) c.inner_maxit = o.inner_maxit;
     else if (prec == FSI_FP32) c.inner_maxit = std::min(c.inner_maxit, 300);

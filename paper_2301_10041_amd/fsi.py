@@ -19,6 +19,9 @@ FSI_OK, FSI_E_ARG, FSI_E_MESH, FSI_E_NOMEM, FSI_E_NOCONV, FSI_E_NONFINITE, FSI_E
     FSI_E_CAPACITY, FSI_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FP64, FP32, FP32_IR = 0, 1, 2
 PC_DIAG, PC_TRI = 0, 1
+# inner A11 modes (fsi_inner): MINRES with the block-diagonal approximation (default), the
+# fixed-cost block-diagonal and block-triangular forms, GMRES with the block-triangular one
+INNER_MINRES, INNER_FIXED_DIAG, INNER_FIXED_TRI, INNER_GMRES = 0, 1, 2, 3
 SMOOTH_CSR, SMOOTH_STENCIL = 0, 1
 MAX_LANES = 32                 # FSI_MAX_LANES: systems per fsi_step_batch
 COUPLING_SCRATCH_BYTES = 32 << 20   # FSI_COUPLING_SCRATCH_BYTES
@@ -60,7 +63,8 @@ class CouplingInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double), ("pc", C.c_int32),
                 ("prec", C.c_int32), ("inner_rtol", C.c_double), ("inner_maxit", C.c_int32),
-                ("cycle_rtol", C.c_double), ("inner_mode", C.c_int32)]
+                ("cycle_rtol", C.c_double), ("inner_mode", C.c_int32),
+                ("inner_cycles", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -104,6 +108,7 @@ _SIGS = {
     "fsi_apply_operator": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "fsi_apply_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
     "fsi_set_inner": (C.c_int, [C.c_void_p, C.c_double, C.c_int32]),
+    "fsi_set_inner_mode": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "fsi_gmres_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
                                   C.POINTER(SolveStats)]),
     "fsi_step": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -200,10 +205,11 @@ class Opts:
     inner_maxit: int = 0
     cycle_rtol: float = 0.0
     inner_mode: int = 0
+    inner_cycles: int = 0
 
     def c(self):
         return SolveOpts(self.restart, self.maxit, self.rtol, self.pc, self.prec, self.inner_rtol,
-                         self.inner_maxit, self.cycle_rtol, self.inner_mode)
+                         self.inner_maxit, self.cycle_rtol, self.inner_mode, self.inner_cycles)
 
 
 def step_batch(ctxs, u_n, X_n, states, opts: Opts | None = None):
@@ -325,6 +331,10 @@ class Context:
 
     def set_inner(self, rtol, maxit=0):
         self._check(lib().fsi_set_inner(self._h, float(rtol), int(maxit)))
+
+    def set_inner_mode(self, mode, cycles=0):
+        """The context's inner A11 mode (INNER_*) for apply_precond; solves take theirs from Opts."""
+        self._check(lib().fsi_set_inner_mode(self._h, int(mode), int(cycles)))
 
     def gmres_solve(self, b, x, opts: Opts | None = None, raise_noconv=True):
         st = SolveStats()

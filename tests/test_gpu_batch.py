@@ -62,11 +62,15 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("inner", [fsi.INNER_MINRES, fsi.INNER_GMRES], ids=["minres", "gmres"])
 @pytest.mark.parametrize("name,n,prec,graphs,ks", CASES, ids=[c[0] for c in CASES])
-def test_batch_equals_alone_bitwise(name, n, prec, graphs, ks):
+def test_batch_equals_alone_bitwise(name, n, prec, graphs, ks, inner):
+    """Each system of a lockstep batch equals its step alone bitwise, for lane counts that grow
+    and shrink on one context, with the inner MINRES (whose iterations replay captured graphs
+    when graphs are on) and the inner GMRES (no graphs)."""
     torch_dev()
-    print(f"[batch {name} K={ks}]", flush=True)
-    opts = fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-8)
+    print(f"[batch {name} inner {inner} K={ks}]", flush=True)
+    opts = fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-8, inner_mode=inner)
     wls = workloads(n, max(ks))
     ref = [alone(wl, opts, graphs) for wl in wls]
     ctxs = [fsi.Context.from_workload(wl) for wl in wls]
@@ -191,13 +195,14 @@ def test_batch_high_valence_solid():
 
 @pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
 def test_fixed_cost_inner_mode(prec):
-    """inner_mode = 1 (A11^{-1} by one application of its preconditioner, no inner MINRES):
+    """FSI_INNER_FIXED_DIAG (A11^{-1} by one application of the block-diagonal inner
+    preconditioner, no inner Krylov steps):
     the step converges to rtol with no inner steps and more outer steps, matches the oracle's
     direct solve, and a batch equals each step alone bitwise; other modes are refused."""
     torch_dev()
     print(f"[fixed-cost inner mode prec={prec}]", flush=True)
     wls = workloads(16, 3, seed=41)
-    opts = fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-10, inner_mode=1)
+    opts = fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-10, inner_mode=fsi.INNER_FIXED_DIAG)
     ref = [alone(wl, opts, False) for wl in wls]
     base = alone(wls[0], fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-10), False)
     for (x, st) in ref:
@@ -214,10 +219,49 @@ def test_fixed_cost_inner_mode(prec):
     x_ref, _ = ostep.step(S, u, S.xy_ref, solver="direct")
     assert_block_parity(S, states[0], x_ref, 1e-8, "fixed-cost")
     u0, X0, s0 = inputs_of(wls[0], ctxs[0])
-    with pytest.raises(fsi.FsiError) as e:
-        ctxs[0].step(u0, X0, s0, fsi.Opts(prec=prec, inner_mode=2))
-    assert e.value.code == fsi.FSI_E_ARG
+    for bad in (fsi.Opts(prec=prec, inner_mode=4), fsi.Opts(prec=prec, inner_mode=fsi.INNER_FIXED_TRI, inner_cycles=101)):
+        with pytest.raises(fsi.FsiError) as e:
+            ctxs[0].step(u0, X0, s0, bad)
+        assert e.value.code == fsi.FSI_E_ARG
     st = ctxs[0].step(u0, X0, s0, fsi.Opts(prec=prec, rtol=1e-10))   # the default mode again
     assert st["inner_its"] > 0 and st["converged"] == 1
     for c in ctxs:
         c.close()
+
+
+@pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
+def test_fixed_cost_block_triangular(prec):
+    """FSI_INNER_FIXED_TRI (A11^{-1} by stationary cycles with the block upper-triangular
+    approximation, the pressure part before the velocity cycle): the step converges with no
+    inner steps and matches the oracle's direct solve per block; one cycle takes fewer outer
+    steps than the block-diagonal fixed-cost form, two cycles fewer still; a batch equals each
+    step alone bitwise."""
+    torch_dev()
+    print(f"[fixed-cost block-triangular prec={prec}]", flush=True)
+    wls = workloads(16, 3, seed=41)
+    # rtol 1e-11: at 1e-10 the largest pressure entry was 1.2e-8 off (2-norm 4e-9)
+    o1 = fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-11, inner_mode=fsi.INNER_FIXED_TRI, inner_cycles=1)
+    o2 = fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-11, inner_mode=fsi.INNER_FIXED_TRI, inner_cycles=2)
+    ref = [alone(wl, o1, False) for wl in wls]
+    diag = alone(wls[0], fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-11, inner_mode=fsi.INNER_FIXED_DIAG), False)
+    two = alone(wls[0], o2, False)
+    for (x, st) in ref + [two]:
+        assert st["converged"] == 1 and st["inner_its"] == 0 and st["relres_true"] <= 1e-11
+    print(f"  outer its: block-diagonal {diag[1]['its']}, block-triangular 1 cycle {ref[0][1]['its']}, "
+          f"2 cycles {two[1]['its']}", flush=True)
+    assert ref[0][1]["its"] < diag[1]["its"]
+    assert two[1]["its"] < ref[0][1]["its"]
+    ctxs = [fsi.Context.from_workload(wl) for wl in wls]
+    states, stats, rcs = batch(ctxs, wls, o1)
+    assert rcs == [fsi.FSI_OK] * 3
+    for k, wl in enumerate(wls):
+        assert np.array_equal(states[k], ref[k][0]), wl.name
+        assert stats[k]["its"] == ref[k][1]["its"]
+    for c in ctxs:
+        c.close()
+    S = system.FSISystem.from_workload(wls[0])
+    u = inputs.uniform(2 * S.lay.N2, wls[0].seed)
+    x_ref, _ = ostep.step(S, u, S.xy_ref, solver="direct")
+    assert_block_parity(S, ref[0][0], x_ref, 1e-8, "block-triangular 1 cycle")
+    assert_block_parity(S, two[0], x_ref, 1e-8, "block-triangular 2 cycles")
+

@@ -54,18 +54,25 @@ def twodisk128():
     ctx.close()
 
 
-@pytest.mark.parametrize("pc", ["diag", "tri"])
-@pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
-def test_step_twodisk128_against_oracle(twodisk128, pc, prec):
-    print(f"[step twodisk128 pc={pc} prec={prec}]", flush=True)
+STEP128 = [("diag", fsi.FP64, fsi.INNER_MINRES), ("diag", fsi.FP32, fsi.INNER_MINRES),
+           ("tri", fsi.FP64, fsi.INNER_MINRES), ("tri", fsi.FP32, fsi.INNER_MINRES),
+           ("tri", fsi.FP64, fsi.INNER_GMRES), ("tri", fsi.FP32, fsi.INNER_GMRES)]
+
+
+@pytest.mark.parametrize("pc,prec,inner", STEP128, ids=[f"{p}-{q}-{m}" for p, q, m in STEP128])
+def test_step_twodisk128_against_oracle(twodisk128, pc, prec, inner):
+    """A whole step of the two-disk geometry at 128^2 against the oracle's refined direct solve,
+    per block within 1e-8: both preconditioners and precisions with the inner MINRES, and the
+    block-triangular one with the inner GMRES of the weighted norm."""
+    print(f"[step twodisk128 pc={pc} prec={prec} inner={inner}]", flush=True)
     torch = torch_dev()
     wl, S, u, X, x_ref, ctx = twodisk128
     out = torch.zeros(S.lay.N, dtype=torch.float64, device="cuda")
-    opts = fsi.Opts(pc=fsi.PC_TRI if pc == "tri" else fsi.PC_DIAG, prec=prec, rtol=1e-10)
+    opts = fsi.Opts(pc=fsi.PC_TRI if pc == "tri" else fsi.PC_DIAG, prec=prec, rtol=1e-10, inner_mode=inner)
     st = ctx.step(to_dev(u), to_dev(soa(X)), out, opts)
     print(f"  its {st['its']} inner {st['inner_its']} relres {st['relres_true']:.2e}", flush=True)
     assert st["converged"] and st["relres_true"] <= 1e-10
-    assert_block_parity(S, to_host(out), x_ref, 1e-8, f"twodisk128 {pc} prec={prec}")
+    assert_block_parity(S, to_host(out), x_ref, 1e-8, f"twodisk128 {pc} prec={prec} inner={inner}")
 
 
 def _golden():
@@ -172,3 +179,34 @@ def test_batch4_equals_alone_midsize(n, prec):
     print(f"  its {[s['its'] for s in stats]} inner {[s['inner_its'] for s in stats]}", flush=True)
     for c in ctxs:
         c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_block_triangular_cycles_approach_the_exact_block_count(prec):
+    """FSI_INNER_FIXED_TRI with many cycles: the stationary block-triangular iteration converges to
+    A11^{-1} r, so the outer count reaches the oracle's exact-block count (the iteration bar);
+    a wrong sign or block in the iteration would diverge or stall instead."""
+    gold = _golden()
+    rec = gold["disk32"]
+    ref_its = rec["tri"]["its"]
+    print(f"[block-triangular cycles disk32 {prec}: oracle {ref_its}]", flush=True)
+    torch = torch_dev()
+    wl = inputs.WORKLOADS["disk32"]
+    xy, _ = wl.solid_mesh()
+    ctx = fsi.Context.from_workload(wl)
+    N = ctx.sizes["N"]
+    ctx.assemble_coupling(to_dev(soa(xy)))
+    b = to_dev(_dirichlet_zeroed(inputs.uniform(N, wl.seed), wl.n))
+    q = fsi.FP64 if prec == "fp64" else fsi.FP32
+    its = []
+    for cycles in (1, 4, 40):
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        st = ctx.gmres_solve(b, x, fsi.Opts(pc=fsi.PC_TRI, prec=q, rtol=1e-8, inner_mode=fsi.INNER_FIXED_TRI,
+                                                inner_cycles=cycles))
+        assert st["converged"] and st["relres_true"] <= 1e-8
+        its.append(st["its"])
+    ctx.close()
+    print(f"  outer its for 1, 4, 40 cycles: {its}", flush=True)
+    assert its[0] > its[1] >= its[2]
+    assert its[2] <= _its_bound(ref_its)
+

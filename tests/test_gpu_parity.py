@@ -176,9 +176,16 @@ def test_rhs(pair32):
     assert rel(to_host(b), b_ref) <= 1e-13
 
 
-def test_precond_blocks(pair32):
-    print("[precond]", flush=True)
+INNER_MODES = pytest.mark.parametrize("inner", [fsi.INNER_MINRES, fsi.INNER_GMRES], ids=["minres", "gmres"])
+
+
+@INNER_MODES
+def test_precond_blocks(pair32, inner):
+    """Both block preconditioners with tight inner solves (inner MINRES, the default, and inner
+    GMRES with the block-triangular approximation) against the oracle's exact blocks."""
+    print(f"[precond inner {inner}]", flush=True)
     S, ctx, wl = pair32
+    ctx.set_inner_mode(inner)
     lay = S.lay
     nf = lay.nf
     rng = np.random.default_rng(13)
@@ -198,6 +205,7 @@ def test_precond_blocks(pair32):
     zref = S.apply_precond(r, "tri")
     assert rel(zt, zref) <= 1e-9
     ctx.set_inner(-1.0, 1000)
+    ctx.set_inner_mode(fsi.INNER_MINRES)
 
 
 def _its_bound(its_oracle):
@@ -409,16 +417,18 @@ def test_gmres_fp32_ir(pair32):
     assert_block_parity(S, to_host(xd), xs, 1e-8, "fp32-ir tri")
 
 
+@INNER_MODES
 @pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
-def test_stencil_smoother_equals_csr(pair32, prec):
+def test_stencil_smoother_equals_csr(pair32, prec, inner):
     """The matrix-free A_f products of the V-cycle give the same preconditioner as the
     assembled blocks: after one or two inner steps (isolating the V-cycle) and converged.
     At 32^2 the matrix-free cycle runs every fused launch against the CSR products and
     separate transfers: the post-smoothing launch that adds the coarse correction, the
     residual kept in LDS and restricted in one launch, and the one-launch tail (16^2, 8^2
     and the dense 4^2 solve)."""
-    print(f"[stencil vs csr prec={prec}]", flush=True)
+    print(f"[stencil vs csr prec={prec} inner {inner}]", flush=True)
     S, ctx, wl = pair32
+    ctx.set_inner_mode(inner)
     lay = S.lay
     rng = np.random.default_rng(31)
     r = S.random_rhs(0, rng.uniform(-1, 1, lay.N))
@@ -437,6 +447,7 @@ def test_stencil_smoother_equals_csr(pair32, prec):
         assert d <= (1e-12 if prec == fsi.FP64 else 1e-5)
     ctx.set_smoother(fsi.SMOOTH_STENCIL)
     ctx.set_inner(-1.0, 1000)
+    ctx.set_inner_mode(fsi.INNER_MINRES)
     if prec == fsi.FP64:
         zref = S.apply_precond(r, "tri")
         assert rel(out[(2000, fsi.SMOOTH_STENCIL)], zref) <= 1e-9
@@ -483,12 +494,14 @@ def test_multigrid_tiles_and_odd_coarsest(n):
 
 @pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
 def test_graph_replays_equal_eager(pair32, prec):
-    """The captured preconditioner graph, replayed many times with different inputs and
-    with eager work and synchronisations in between, gives the eager result bitwise."""
+    """The captured preconditioner graph (of the inner MINRES, the inner mode that replays
+    graphs), replayed many times with different inputs and with eager work and
+    synchronisations in between, gives the eager result bitwise."""
     print(f"[graph replays prec={prec}]", flush=True)
     S, ctx, wl = pair32
     lay = S.lay
     torch = torch_dev()
+    ctx.set_inner_mode(fsi.INNER_MINRES)
     rng = np.random.default_rng(41)
     rs = [to_dev(S.random_rhs(0, rng.uniform(-1, 1, lay.N))) for _ in range(3)]
     eager = []
@@ -509,9 +522,10 @@ def test_graph_replays_equal_eager(pair32, prec):
             ctx.apply_operator(rd, y)
     b = to_dev(S.random_rhs(wl.seed))
     x1 = torch.zeros_like(b)
-    ctx.gmres_solve(b, x1, fsi.Opts(pc=fsi.PC_TRI, prec=prec))
+    ctx.gmres_solve(b, x1, fsi.Opts(pc=fsi.PC_TRI, prec=prec, inner_mode=fsi.INNER_MINRES))
     ctx.set_graphs(False)
     x0 = torch.zeros_like(b)
-    ctx.gmres_solve(b, x0, fsi.Opts(pc=fsi.PC_TRI, prec=prec))
+    ctx.gmres_solve(b, x0, fsi.Opts(pc=fsi.PC_TRI, prec=prec, inner_mode=fsi.INNER_MINRES))
     assert np.array_equal(to_host(x0), to_host(x1))
     ctx.set_graphs(True)
+    ctx.set_inner_mode(fsi.INNER_MINRES)
