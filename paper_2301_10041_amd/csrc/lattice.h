@@ -126,6 +126,30 @@ void p1_prolong_add(int nf, LP<const T> xc, LP<T> y, hipStream_t s, int K = 1);
 // bc = R r (pressure levels; the velocity levels restrict in resid_restrict)
 template <typename T>
 void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K = 1);
+// S Chebyshev steps on a P1 operator in one launch (lattice.hip, k_p1_multi): from zero or
+// from x, the result to y or combined into the Schur output z = a x + b2 w (pinned entry
+// r[0], per-tile parts of sum r z).  Lane strides: lb for b, x, y, w; lz for z, r, r64; lp
+// for part (p1_multi_tiles(n) parts per lane).
+constexpr int kP1T = 16, kP1C = 64;   // tile rows and columns (256 threads)
+enum { P1_OUT_X = 0, P1_OUT_SCHUR = 1 };
+template <typename T, typename TZ>
+struct P1MultiArgs {
+  int n;
+  const P1Table<T> *tab;
+  const T *b, *x;
+  T *y;
+  T c1[3], c2[3];   // step k: d = c1[k] d + c2[k] D^{-1} (b - A x); from zero c2[0] scales D^{-1} b
+  TZ *z;
+  const TZ *r;
+  const double *r64;
+  const T *w;
+  T a, b2;
+  double *part;
+  int64_t lb, lz, lp;
+};
+int p1_multi_tiles(int n);
+template <typename T, typename TZ, int S, bool ZERO, int OUT>
+void p1_multi(const P1MultiArgs<T, TZ> &a, hipStream_t s, int K = 1);
 // The coarse end of a velocity V-cycle in one launch per system (mgtail.hip): levels
 // lv[0..nlev) (n <= kTailMaxN cells, each the next one's fine level) and the coarsest
 // level's dense inverse.  Vectors in LDS (offsets in T): level l's b at lv[l].off and x

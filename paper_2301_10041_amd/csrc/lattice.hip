@@ -341,6 +341,134 @@ void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K) {
   FSI_CHECK_LAUNCH();
 }
 
+// ---------------------------------------------------------------- P1 Chebyshev steps in one launch
+// S steps of the Chebyshev recurrence of chebyshev_p1 on a P1 operator in one launch, on a
+// tile of kP1T rows x kP1C nodes: from zero the first step is pointwise (x = d = c2[0]
+// D^{-1} b), else the first step starts from x with the direction coefficient c1[0] = 0.  The
+// right-hand side (and x) are staged with a halo of S - 1 (S from x); step k runs on the tile
+// plus a halo of S - 1 - k, reading x from LDS and writing the next x to the other LDS buffer;
+// b and the direction of a node stay in the registers of the thread that owns it.  The
+// products keep the order of sums of k_p1 (and its boundary classes, pinned row and column).
+// OUT: the result to y (P1_OUT_X), or (P1_OUT_SCHUR) z = a x + b2 w, the pinned entry r[0]
+// (rounded through T), and per tile the part of the sum of r z (r64 when given), the output
+// stage of the Cahouet-Chabard approximation (x the mass solve, w the Laplacian cycle).
+template <typename T, typename TZ, int S, bool ZERO, int OUT>
+__global__ void __launch_bounds__(256) k_p1_multi(P1MultiArgs<T, TZ> a, int tiles_x) {
+  constexpr int H = ZERO ? S - 1 : S;
+  constexpr int RH = kP1T + 2 * H, RW = kP1C + 2 * H, NE = RH * RW, IT = (NE + 255) / 256;
+  __shared__ T XA[NE], XB[NE];
+  const int lane = blockIdx.y, tid = threadIdx.x;
+  const T *b = a.b + lane * a.lb;
+  const int n = a.n, L = n + 1;
+  const int i0 = (blockIdx.x % tiles_x) * kP1C, j0 = (blockIdx.x / tiles_x) * kP1T;
+  const P1Table<T> &tb = *a.tab;
+  const bool pin = tb.pin != 0;
+  T bq[IT], dq[IT];
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int e = tid + 256 * q, i = i0 - H + e % RW, j = j0 - H + e / RW;
+    const bool ok = e < NE && i >= 0 && j >= 0 && i <= n && j <= n;
+    bq[q] = ok ? b[(int64_t)j * L + i] : T(0);
+    dq[q] = T(0);
+    if constexpr (!ZERO) {
+      if (e < NE) XA[e] = ok ? a.x[lane * a.lb + (int64_t)j * L + i] : T(0);
+    }
+  }
+  // a node takes part in step k when it lies within S - 1 - k of the tile
+  auto ring = [&](int i, int j) {
+    const int di = i < i0 ? i0 - i : (i >= i0 + kP1C ? i - (i0 + kP1C - 1) : 0);
+    const int dj = j < j0 ? j0 - j : (j >= j0 + kP1T ? j - (j0 + kP1T - 1) : 0);
+    return di > dj ? di : dj;
+  };
+  if constexpr (ZERO) {
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int e = tid + 256 * q, i = i0 - H + e % RW, j = j0 - H + e / RW;
+      if (e < NE) {
+        T z = T(0);
+        if (i >= 0 && j >= 0 && i <= n && j <= n) {
+          const int ci = i == 0 ? 0 : (i == n ? 2 : 1), cj = j == 0 ? 0 : (j == n ? 2 : 1);
+          z = a.c2[0] * (tb.dinv[3 * cj + ci] * bq[q]);
+        }
+        dq[q] = z;
+        XA[e] = z;
+      }
+    }
+  }
+  __syncthreads();
+  T res[IT];   // results of the last step (tile nodes)
+  constexpr int K0 = ZERO ? 1 : 0;
+#pragma unroll
+  for (int k = K0; k < S; ++k) {
+    const T *X = ((k - K0) & 1) ? XB : XA;
+    T *Xn = ((k - K0) & 1) ? XA : XB;
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int e = tid + 256 * q, i = i0 - H + e % RW, j = j0 - H + e / RW;
+      if (e >= NE || i < 0 || j < 0 || i > n || j > n || ring(i, j) > S - 1 - k) continue;
+      const int ci = i == 0 ? 0 : (i == n ? 2 : 1), cj = j == 0 ? 0 : (j == n ? 2 : 1);
+      const int cls = 3 * cj + ci;
+      const int64_t r = (int64_t)j * L + i;
+      const T xc = X[e];
+      T sum;
+      if (pin && r == 0) {
+        sum = xc;   // identity row of the pinned node
+      } else {
+        const T *c = tb.coef[cls];
+        // column 0 is zero when pinned: node (0, 0) is read as 0
+        auto ld = [&](int o, int64_t g) -> T { return (pin && g == 0) ? T(0) : X[o]; };
+        sum = c[0] * xc;
+        if (i > 0) sum += c[1] * ld(e - 1, r - 1);
+        if (i < n) sum += c[2] * X[e + 1];
+        if (j > 0) sum += c[3] * ld(e - RW, r - L);
+        if (j < n) sum += c[4] * X[e + RW];
+        if (i > 0 && j > 0) sum += c[5] * ld(e - RW - 1, r - L - 1);
+        if (i < n && j < n) sum += c[6] * X[e + RW + 1];
+      }
+      const T z = tb.dinv[cls] * (bq[q] - sum);
+      const T dn = a.c1[k] * dq[q] + a.c2[k] * z;
+      dq[q] = dn;
+      if (k < S - 1) Xn[e] = xc + dn;
+      else res[q] = xc + dn;
+    }
+    if (k < S - 1) __syncthreads();
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int e = tid + 256 * q, i = i0 - H + e % RW, j = j0 - H + e / RW;
+    if (e >= NE || i < 0 || j < 0 || i > n || j > n || ring(i, j) > 0) continue;
+    const int64_t r = (int64_t)j * L + i;
+    if constexpr (OUT == P1_OUT_X) {
+      a.y[lane * a.lb + r] = res[q];
+    } else {
+      const TZ *rr = a.r + lane * a.lz;
+      const TZ v = (TZ)(r == 0 ? (T)rr[0] : a.a * res[q] + a.b2 * a.w[lane * a.lb + r]);
+      a.z[lane * a.lz + r] = v;
+      acc += (a.r64 ? a.r64[lane * a.lz + r] : (double)rr[r]) * (double)v;
+    }
+  }
+  if constexpr (OUT == P1_OUT_SCHUR) {
+    if (a.part) {
+      const double t = block_sum(acc);
+      if (tid == 0) a.part[lane * a.lp + blockIdx.x] = t;
+    }
+  }
+}
+
+int p1_multi_tiles(int n) {
+  const int L = n + 1;
+  return ((L + kP1C - 1) / kP1C) * ((L + kP1T - 1) / kP1T);
+}
+
+template <typename T, typename TZ, int S, bool ZERO, int OUT>
+void p1_multi(const P1MultiArgs<T, TZ> &a, hipStream_t s, int K) {
+  const int L = a.n + 1, tx = (L + kP1C - 1) / kP1C;
+  hipLaunchKernelGGL((k_p1_multi<T, TZ, S, ZERO, OUT>), dim3((unsigned)p1_multi_tiles(a.n), (unsigned)K), dim3(256),
+                     0, s, a, tx);
+  FSI_CHECK_LAUNCH();
+}
+
 #define FSI_LATTICE_INST(T)                                                                                 \
   template void p1_launch<T, SP_APPLY>(int, const P1Table<T> *, LP<const T>, LP<const T>, LP<T>, LP<T>, T, T, \
                                        hipStream_t, int);                                                   \
@@ -352,9 +480,15 @@ void p1_restrict(int nf, LP<const T> r, LP<T> bc, hipStream_t s, int K) {
   template void p2_first<T>(int, const StencilTable<T> *, LP<const T>, T, LP<T>, LP<T>, hipStream_t, int);   \
   template void p2_prolong_add<T>(int, LP<const T>, LP<T>, hipStream_t, int);                               \
   template void p1_prolong_add<T>(int, LP<const T>, LP<T>, hipStream_t, int);                               \
-  template void p1_restrict<T>(int, LP<const T>, LP<T>, hipStream_t, int);
+  template void p1_restrict<T>(int, LP<const T>, LP<T>, hipStream_t, int);                                  \
+  template void p1_multi<T, T, 2, true, P1_OUT_X>(const P1MultiArgs<T, T> &, hipStream_t, int);              \
+  template void p1_multi<T, T, 2, false, P1_OUT_X>(const P1MultiArgs<T, T> &, hipStream_t, int);             \
+  template void p1_multi<T, T, 3, true, P1_OUT_X>(const P1MultiArgs<T, T> &, hipStream_t, int);              \
+  template void p1_multi<T, T, 3, false, P1_OUT_X>(const P1MultiArgs<T, T> &, hipStream_t, int);             \
+  template void p1_multi<T, T, 3, true, P1_OUT_SCHUR>(const P1MultiArgs<T, T> &, hipStream_t, int);
 
 FSI_LATTICE_INST(double)
 FSI_LATTICE_INST(float)
+template void p1_multi<float, double, 3, true, P1_OUT_SCHUR>(const P1MultiArgs<float, double> &, hipStream_t, int);
 
 }  // namespace fsi

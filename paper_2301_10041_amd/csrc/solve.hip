@@ -122,6 +122,10 @@ __global__ void k_set_pinned(T *z, const T *r, int64_t ls) {   // lane blockIdx.
 // output of the mixed form, r its FP32 copy).  Lane blockIdx.y: z, r, r64 at + lane ls, x, y
 // at + lane lx, part at + lane lp.
 constexpr int kPresDotBlocks = 256;
+// Parts of r . z from the pressure output: one per tile of the fused launch (matrix-free
+// pressure hierarchy) or kPresDotBlocks; the slots per lane hold either
+static int pres_dot_slots(int n) { return std::max(kPresDotBlocks, p1_multi_tiles(n)); }
+static int pres_dot_count(const Ctx &c) { return c.mgp.stencil ? p1_multi_tiles(c.n) : kPresDotBlocks; }
 template <typename TZ, typename T>
 __global__ void __launch_bounds__(kRedBlock) k_pres_out_dot(TZ *z, const TZ *r, const T *x, const T *y, T a, T b,
                                                             int64_t n, int64_t ls, int64_t lx, double *part,
@@ -359,6 +363,46 @@ static T *chebyshev_p1(int n, const P1Table<T> *tab, double lmin, double lmax, i
                          lmin, lmax, steps, x, x2, zero_init, s, nullptr);
 }
 
+// The Chebyshev coefficients of chebyshev_mf: step k updates d = c1[k] d + c2[k] D^{-1} r
+// (from zero, step 0 is x = d = c2[0] D^{-1} b; from x, c1[0] = 0).
+template <typename T>
+static void p1_cheb_coefs(double lmin, double lmax, int steps, T *c1, T *c2) {
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  c1[0] = (T)0;
+  c2[0] = (T)(1.0 / theta);
+  for (int k = 1; k < steps; ++k) {
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    c1[k] = (T)(rho1 * rho);
+    c2[k] = (T)(2.0 * rho1 / delta);
+    rho = rho1;
+  }
+}
+
+// The steps of chebyshev_p1 (2 or 3, the same coefficients) in one launch (k_p1_multi): the
+// result goes to y.  Returns false for other step counts.
+template <typename T>
+static bool p1_cheb_fused(int n, const P1Table<T> *tab, double lmin, double lmax, int steps, const T *b, const T *x,
+                          T *y, bool zero, hipStream_t s, int K, int64_t ls) {
+  if (steps != 2 && steps != 3) return false;
+  P1MultiArgs<T, T> a{};
+  a.n = n;
+  a.tab = tab;
+  a.b = b;
+  a.x = x;
+  a.y = y;
+  a.lb = ls;
+  p1_cheb_coefs<T>(lmin, lmax, steps, a.c1, a.c2);
+  if (steps == 2) {
+    if (zero) p1_multi<T, T, 2, true, P1_OUT_X>(a, s, K);
+    else p1_multi<T, T, 2, false, P1_OUT_X>(a, s, K);
+  } else {
+    if (zero) p1_multi<T, T, 3, true, P1_OUT_X>(a, s, K);
+    else p1_multi<T, T, 3, false, P1_OUT_X>(a, s, K);
+  }
+  return true;
+}
+
 template <typename T> static const StencilTable<T> *stab(const MgLevel &L);
 template <> const StencilTable<double> *stab<double>(const MgLevel &L) {
   return (const StencilTable<double> *)L.stab64.p;
@@ -484,6 +528,8 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
         return chebyshev_stencil<T>(L.n, stab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, pl, K, ls,
                                     zero ? nullptr : out, zero ? nullptr : out64, xcor, lc,
                                     zero ? LP<double>() : dot, zero ? LP<const double>() : b64);
+      else if (p1_cheb_fused<T>(L.n, p1tab<T>(L), lmin, lmax, degree, b, x0, zero ? x0 : x1, zero, s, K, ls))
+        return (void)xcor, zero ? x0 : x1;
       else
         return (void)xcor, chebyshev_p1<T>(L.n, p1tab<T>(L), lmin, lmax, degree, b, x0, x1, d, zero, s, K, ls);
     };
@@ -583,6 +629,53 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
   else convert_l(LP<T>(rp, Np), LP<const T>(r + 2 * N2, nf), Np, sp, K);
   fill_l(LP<T>(rp, Np), 1, (T)0, sp, K);
   T *xp = vcycle<T, 1, 1>(c.mgp, 0, rp, sp, nullptr, K);
+  if (c.mgp.stencil) {
+    // the mass solve (kMpSteps Chebyshev steps from zero) and the output z_p = nu x + (rho/dt) x_L
+    // with the pinned entry and the parts of r . z, in one launch
+    static_assert(kMpSteps == 3, "the fused mass solve takes three steps");
+    const P1Table<T> *mtab = (const P1Table<T> *)(std::is_same<T, double>::value ? c.mptab64.p : c.mptab32.p);
+    double *part = dot.p ? dot.p + cheb3_dot_count(c.n) : nullptr;
+    if (z64) {
+      P1MultiArgs<T, double> a{};
+      a.n = c.n;
+      a.tab = mtab;
+      a.b = rp;
+      p1_cheb_coefs<T>(0.5, 2.0, kMpSteps, a.c1, a.c2);
+      a.z = z64 + 2 * N2;
+      a.r = r64 + 2 * N2;
+      a.w = xp;
+      a.a = (T)c.nu;
+      a.b2 = (T)(c.rho / c.dt);
+      a.part = part;
+      a.lb = Np;
+      a.lz = nf;
+      a.lp = dot.s;
+      p1_multi<T, double, 3, true, P1_OUT_SCHUR>(a, sp, 1);
+    } else {
+      P1MultiArgs<T, T> a{};
+      a.n = c.n;
+      a.tab = mtab;
+      a.b = rp;
+      p1_cheb_coefs<T>(0.5, 2.0, kMpSteps, a.c1, a.c2);
+      a.z = z + 2 * N2;
+      a.r = r + 2 * N2;
+      a.r64 = r64 ? r64 + 2 * N2 : nullptr;
+      a.w = xp;
+      a.a = (T)c.nu;
+      a.b2 = (T)(c.rho / c.dt);
+      a.part = part;
+      a.lb = Np;
+      a.lz = nf;
+      a.lp = dot.s;
+      p1_multi<T, T, 3, true, P1_OUT_SCHUR>(a, sp, K);
+    }
+    FSI_CHECK_LAUNCH();
+    if (fork) {
+      FSI_HIP(hipEventRecord(c.ev_join, sp));
+      FSI_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
+    }
+    return;
+  }
   // mass solve scratch: x, x2, d of every lane (3 Np each) in one inner vector
   T *mx = Pr<T>::inner(c, 7).p, *mx2 = mx + (int64_t)K * Np, *md = mx + 2 * (int64_t)K * Np;
   T *mres = c.mgp.stencil
@@ -1030,8 +1123,8 @@ static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st, int K) 
   else
     hipLaunchKernelGGL(k_ms_axpy, dim3(g, K), dim3(256), 0, s, b.r1, b.r2, st, 1, nf);
   if (dot_ok) {   // beta^2 = r . z from the launches that write z
-    const int nu = cheb3_dot_count(c.n);
-    const int64_t ld = nu + kPresDotBlocks;
+    const int nu = cheb3_dot_count(c.n), np = pres_dot_count(c);
+    const int64_t ld = nu + pres_dot_slots(c.n);
     const LP<double> dot(c.ms_dot.p, ld);
     if constexpr (f32) {   // the same arithmetic as a11_precond_on64<float>, sums on FP64 r
       if (K == 1) {
@@ -1043,7 +1136,7 @@ static void ms_iteration_fused(Ctx &c, const MsBufs &b, MinresState *st, int K) 
     } else {
       a11_precond<double>(c, b.r1, b.y, K, nullptr, nullptr, dot);
     }
-    hipLaunchKernelGGL(k_ms_beta_step, dim3(1, K), dim3(1024), 0, s, c.ms_dot.p, nu, kPresDotBlocks, ld, st,
+    hipLaunchKernelGGL(k_ms_beta_step, dim3(1, K), dim3(1024), 0, s, c.ms_dot.p, nu, np, ld, st,
                        c.ms_hist.p, c.ms_B);
   } else {
     a11_precond_on64<TA>(c, b.r1, b.y, K);
@@ -1474,7 +1567,7 @@ static void ensure_inner(Ctx &c, int prec, int K = 1) {
     c.ms_state.alloc(nl * kMsDoubles);
     c.ms_red.alloc(nl * red_blocks(nf));   // dot products of one system per lane: never regrown
     c.ms_part.alloc(nl * stencil_tile_count(c.n));
-    c.ms_dot.alloc(nl * (cheb3_dot_count(c.n) + kPresDotBlocks));
+    c.ms_dot.alloc(nl * (cheb3_dot_count(c.n) + pres_dot_slots(c.n)));
   }
   if (!c.pc_in.p) {
     c.pc_in.alloc(nl * nf);
