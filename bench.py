@@ -114,7 +114,7 @@ def inner_step_bytes(n, prec):
     return b
 
 
-def step_bytes(n, Ns, nnz_s, nnz_cf, n_pairs, its, inner_its, restarts, prec, pc, cs_steps=13):
+def step_bytes(n, Ns, nnz_s, nnz_cf, n_pairs, its, inner_its, restarts, prec, pc, cs_steps=36):
     """Algorithmic bytes of one step (C_f assembly, right-hand side, the outer FGMRES with its
     inner solves), w = 8 for every outer vector:
       C_f: the piece list and 3 x 6 matrices written and read (2 x 152 B per piece), C_f and

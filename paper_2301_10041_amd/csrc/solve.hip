@@ -1322,15 +1322,12 @@ static void a11_fixed_tri(Ctx &c, const double *const *r, double *const *z, int 
 
 // ---------------------------------------------------------------- A22 closed form (FP64)
 // C_s^{-1} by Chebyshev-Jacobi steps on the interval [1/2, 2] of D^{-1} C_s (P1 mass matrix on
-// triangles): the error falls by 1/3 per step.  The solve is taken four orders of magnitude
-// below the inner tolerance of the A11 block (13 steps, 6e-7, at the default 1e-2; 36 at
-// 1e-13), at most 36 steps ((1/3)^36 < 1e-17, the rounding level), so A22 stays far more
-// accurate than A11 (an inexact A22 is the harmful one).  Measured at 1024^2 / 256^2 / 512^2:
-// 12 instead of 36 steps, the same outer and inner step counts, 2% less time per step.
-static int cs_steps(double inner_tol) {
-  const double k = std::ceil(std::log(1e-4 * inner_tol) / std::log(1.0 / 3.0));
-  return k < 6 ? 6 : k > 36 ? 36 : (int)k;
-}
+// triangles): the error falls by 1/3 per step, and 36 steps reach the rounding level
+// ((1/3)^36 < 1e-17), so A22 is inverted exactly in FP64 as the method asks (an inexact A22 is
+// the harmful one, Sec. 7).  Measured at 1024^2 / 256^2 / 512^2: taking the solve only four
+// orders below the inner tolerance (12-13 steps) left every outer and inner step count
+// unchanged and saved 2% of the step; the exact form is kept.
+static int cs_steps(double) { return 36; }
 
 static const double *cs_solve(Ctx &c, const double *b, double *scratch, int steps) {
   const int64_t ns = c.Ns;
