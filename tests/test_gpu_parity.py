@@ -326,6 +326,60 @@ def test_step_solid_with_large_windows():
     ctx.close()
 
 
+class _MeshSolid(inputs.Solid):
+    """A solid given by its mesh (for the degenerate cases below)."""
+
+    def __init__(self, xy, tri):
+        super().__init__(m=1, center=(0.5, 0.5), radius=0.1)
+        self._xy, self._tri = np.asarray(xy, dtype=np.float64), np.asarray(tri, dtype=np.int32)
+
+    def mesh(self):
+        return self._xy.copy(), self._tri.copy()
+
+
+DEGENERATE = {
+    # one solid triangle (three nodes: every solid row has three entries)
+    "one_triangle16": (16, [[0.41, 0.37], [0.63, 0.45], [0.47, 0.66]], [[0, 1, 2]]),
+    # a bar against the wall x = 0 (the paper's position): solid nodes on Dirichlet nodes of the
+    # fluid, whose C_f columns are zero
+    "bar_at_wall32": (32, None, None),
+    # solid nodes exactly on fluid lattice lines and cell diagonals (pieces with edges on the
+    # clip lines)
+    "on_grid_lines16": (16, [[0.25, 0.25], [0.5, 0.25], [0.5, 0.5], [0.25, 0.5], [0.375, 0.375]],
+                        [[0, 1, 4], [1, 2, 4], [2, 3, 4], [3, 0, 4]]),
+}
+
+
+@pytest.mark.parametrize("name", list(DEGENERATE))
+def test_step_degenerate_solids(name):
+    """Steps with degenerate solids against the oracle's direct solve, per block within 1e-8:
+    a single triangle, a bar whose left end lies on the Dirichlet wall, and a solid whose
+    nodes and edges lie on the fluid grid's lines and diagonals."""
+    print(f"[step degenerate {name}]", flush=True)
+    n, xy, tri = DEGENERATE[name]
+    if xy is None:
+        solid = inputs.Bar(m=0, center=(0.2, 0.5), nx=13, ny=3, x0=0.0)
+    else:
+        solid = _MeshSolid(xy, tri)
+    wl = inputs.Workload(name, n, [solid], dt=0.01, seed=5)
+    S = system.FSISystem.from_workload(wl)
+    lay = S.lay
+    u = inputs.uniform(2 * lay.N2, 31)
+    bnd2 = np.concatenate([S.F["bnd"], S.F["bnd"]])
+    u[bnd2] = 0.0
+    X = S.xy_ref.copy()
+    from oracle import step as ostep
+    x_ref, _ = ostep.step(S, u, X, solver="direct")
+    ctx = fsi.Context.from_workload(wl)
+    torch = torch_dev()
+    out = torch.zeros(lay.N, dtype=torch.float64, device="cuda")
+    for prec in (fsi.FP64, fsi.FP32):
+        st = ctx.step(to_dev(u), to_dev(soa(X)), out, fsi.Opts(pc=fsi.PC_TRI, rtol=1e-12, prec=prec))
+        assert st["converged"]
+        assert_block_parity(S, to_host(out), x_ref, 1e-8, f"{name} prec={prec}")
+    ctx.close()
+
+
 def test_error_paths():
     print("[errors]", flush=True)
     wl = inputs.small_workload(8, 2, (0.5, 0.5), 0.2)
