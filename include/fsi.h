@@ -225,6 +225,36 @@ int fsi_assemble_coupling(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *inf
 #define FSI_COUPLING_SCRATCH_BYTES (32u << 20)
 int fsi_assemble_coupling_noalloc(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *info);
 
+/* How fsi_assemble_coupling (and the steps that call it) finds the intersections.  The paper
+ * detects them anew at every step and proposes, against the cost of that search, to keep track
+ * of the solid's position at the previous time step (Sec. 7).
+ *  FSI_COUPLING_FULL: every call detects, clips and builds the pattern from scratch (default).
+ *  FSI_COUPLING_INCREMENTAL: the context keeps, from one call to the next, each solid
+ *    triangle's candidate box (its bounding box in fluid cells grown by one cell in x and y, two
+ *    piece slots per cell), the positions of the last call, the C_f pattern and the
+ *    permutation of C_f^T.  A call re-clips only the triangles with a vertex that moved (any
+ *    coordinate differs from the last call's), into their own slots; it keeps C_f when nothing
+ *    moved, refills only the values (pattern, C_f^T order kept) when every moved triangle kept
+ *    the same pieces, builds rows and transpose anew when one did not, and rebuilds boxes and
+ *    slots when a triangle outgrew its box (and on the first call, after fsi_set_solid, after a
+ *    call that failed, or after fsi_assemble_coupling_noalloc).  The result is bitwise that of FSI_COUPLING_FULL:
+ *    the same pieces in the same order, the same sums in the same order.  Extra device memory:
+ *    the slots hold (w + 1)(h + 1) cells per triangle instead of w h, their previous pieces,
+ *    2 Ns doubles, 3 Nt ints and two ints per C_f entry.
+ * Errors: FSI_E_ARG (unknown mode).  A change of mode drops the kept state. */
+enum fsi_coupling_mode { FSI_COUPLING_FULL = 0, FSI_COUPLING_INCREMENTAL = 1 };
+int fsi_set_coupling_mode(fsi_ctx *ctx, int mode);
+
+/* What the FSI_COUPLING_INCREMENTAL calls of a context did (cumulative, host-side counts). */
+typedef struct {
+  int64_t calls;           /* assemblies in the incremental mode */
+  int64_t rebuilds;        /* boxes and slots built (first call, overflow, after fsi_set_solid...) */
+  int64_t pattern_builds;  /* moved triangles re-clipped, some pieces changed: rows and transpose anew */
+  int64_t value_refills;   /* moved triangles re-clipped, the same pieces: values only */
+  int64_t unchanged;       /* nothing moved: C_f kept */
+} fsi_coupling_counts;
+int fsi_get_coupling_counts(const fsi_ctx *ctx, fsi_coupling_counts *out);
+
 /* (g1, 0, 0, g2) of eq. (matrix): g1 = (rho/dt) M_f u^n with boundary rows zero (u^n is
  * taken as zero on the boundary), g2 = -(1/dt) C_s X^n.  u_n: device 2 N2, X_n: device
  * 2 Ns, b: device N. */

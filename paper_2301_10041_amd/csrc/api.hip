@@ -68,6 +68,8 @@ size_t Ctx::device_bytes() const {
   b += Cf.bytes() + CfT.bytes() + cand_off.bytes() + piece_cnt.bytes() + pair_E.bytes() +
        pair_T.bytes() + piece_L.bytes() + e_piece.bytes() + cft_fill.bytes() + dflag.bytes() +
        cft_tcol.bytes() + cft_tval.bytes() + cft_long.bytes() + scan_tmp.bytes() + cf_defer.bytes() + cf_huge.bytes() + cf_wflag.bytes() + cf_wval.bytes();
+  b += inc_box.bytes() + inc_moved.bytes() + inc_prevT.bytes() + inc_X.bytes() + inc_flag.bytes() + cft_tsrc.bytes() +
+       cft_perm.bytes();
   b += mgu.bytes() + mgp.bytes();
   for (int i = 0; i < 9; ++i) b += inner.v64[i].bytes() + inner.v32[i].bytes();
   b += outer.V.bytes() + outer.Z.bytes() + outer.w.bytes() + outer.r.bytes() + outer.x32.bytes() +
@@ -207,6 +209,7 @@ int fsi_set_solid(fsi_ctx *ctx, const fsi_solid_desc *solid) {
     FSI_HIP(hipStreamSynchronize(c.stream));
     const int64_t ns = solid->n_nodes, nt = solid->n_tris;
     c.have_cf = false;
+    c.inc_valid = false;
     c.kappa = solid->kappa;
     c.Ns = ns;
     c.Nt = nt;
@@ -282,6 +285,27 @@ int fsi_assemble_coupling(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *inf
       info->nnz = ctx->c.Cf.nnz;
     }
   });
+}
+
+int fsi_set_coupling_mode(fsi_ctx *ctx, int mode) {
+  if (!ctx) return FSI_E_ARG;
+  if (mode != FSI_COUPLING_FULL && mode != FSI_COUPLING_INCREMENTAL) return FSI_E_ARG;
+  return guarded(ctx, [&] {
+    Ctx &c = ctx->c;
+    if (c.cf_mode != mode) c.inc_valid = false;
+    c.cf_mode = mode;
+  });
+}
+
+int fsi_get_coupling_counts(const fsi_ctx *ctx, fsi_coupling_counts *out) {
+  if (!ctx || !out) return FSI_E_ARG;
+  const Ctx &c = ctx->c;
+  out->calls = c.inc_counts[0];
+  out->rebuilds = c.inc_counts[1];
+  out->pattern_builds = c.inc_counts[2];
+  out->value_refills = c.inc_counts[3];
+  out->unchanged = c.inc_counts[4];
+  return FSI_OK;
 }
 
 int fsi_assemble_coupling_noalloc(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *info) {
@@ -519,6 +543,21 @@ int fsi_export_pairs(fsi_ctx *ctx, int32_t *E, int32_t *T, int64_t cap, int64_t 
                 "the allocation-free assembly keeps no piece list: call fsi_assemble_coupling");
     *count = c.n_pairs;
     int64_t m = std::min<int64_t>(cap, c.n_pairs);
+    if (c.inc_valid) {
+      // time-coherent slots: the kept pieces in slot order, which is the canonical order
+      std::vector<int32_t> hE(2 * c.n_cand), hT(2 * c.n_cand);
+      FSI_HIP(hipMemcpyAsync(hE.data(), c.pair_E.p, hE.size() * 4, hipMemcpyDeviceToHost, c.stream));
+      FSI_HIP(hipMemcpyAsync(hT.data(), c.pair_T.p, hT.size() * 4, hipMemcpyDeviceToHost, c.stream));
+      FSI_HIP(hipStreamSynchronize(c.stream));
+      int64_t k = 0;
+      for (size_t q = 0; q < hT.size() && k < m; ++q) {
+        if (hT[q] < 0) continue;
+        if (E) E[k] = hE[q];
+        if (T) T[k] = hT[q];
+        ++k;
+      }
+      return;
+    }
     if (m > 0 && E) FSI_HIP(hipMemcpyAsync(E, c.pair_E.p, m * 4, hipMemcpyDeviceToHost, c.stream));
     if (m > 0 && T) FSI_HIP(hipMemcpyAsync(T, c.pair_T.p, m * 4, hipMemcpyDeviceToHost, c.stream));
     FSI_HIP(hipStreamSynchronize(c.stream));

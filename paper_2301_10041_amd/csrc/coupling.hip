@@ -304,6 +304,7 @@ __device__ bool cf_row(int64_t l, int pass, int n, const int *__restrict__ n2e_p
     int e = n2e[q] >> 2;
     for (int p = e_piece[e] + lane; p < e_piece[e + 1]; p += kWave) {
       int T = pair_T[p];
+      if (T < 0) continue;   // an empty slot of the time-coherent layout
       int cell = T >> 1;
       int ci = cell % n, cj = cell / n;
       imin = min(imin, 2 * ci); imax = max(imax, 2 * ci + 2);
@@ -337,6 +338,7 @@ __device__ bool cf_row(int64_t l, int pass, int n, const int *__restrict__ n2e_p
     int e = n2e[q] >> 2;
     for (int p = e_piece[e] + lane; p < e_piece[e + 1]; p += kWave) {
       int T = pair_T[p], t = T & 1, cell = T >> 1;
+      if (T < 0) continue;
       int ci = cell % n, cj = cell / n;
       for (int b = 0; b < 6; ++b) {
         int I = 2 * ci + kOffC[t][b][0] - imin, J = 2 * cj + kOffC[t][b][1] - jmin;
@@ -358,6 +360,7 @@ __device__ bool cf_row(int64_t l, int pass, int n, const int *__restrict__ n2e_p
     int e = n2e[q] >> 2, a = n2e[q] & 3;
     for (int p = e_piece[e]; p < e_piece[e + 1]; ++p) {
       int T = pair_T[p], t = T & 1, cell = T >> 1;
+      if (T < 0) continue;
       int ci = cell % n, cj = cell / n;
       for (int b = 0; b < 6; ++b) {
         int I = 2 * ci + kOffC[t][b][0] - imin, J = 2 * cj + kOffC[t][b][1] - jmin;
@@ -444,7 +447,7 @@ __global__ void k_count_cols(int64_t nnz, const int *col, int *cnt) {
 }
 
 __global__ void k_scatter_t(int64_t nrows, const int *rowptr, const int *col, const double *val,
-                            const int *tptr, int *fill, int *tcol, double *tval) {
+                            const int *tptr, int *fill, int *tcol, double *tval, int *tsrc) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
@@ -452,6 +455,7 @@ __global__ void k_scatter_t(int64_t nrows, const int *rowptr, const int *col, co
     int pos = tptr[c] + atomicAdd(&fill[c], 1);
     tcol[pos] = (int)r;
     tval[pos] = val[k];
+    if (tsrc) tsrc[pos] = k;
   }
 }
 
@@ -465,7 +469,7 @@ constexpr int kShortRow = 32;
 constexpr int kRankChunk = 4096;
 
 __global__ void k_rank_short(int64_t nrows, const int *rowptr, const int *tcol, const double *tval, int *col,
-                             double *val, int *long_rows) {
+                             double *val, int *long_rows, const int *tsrc, int *perm) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   const int k0 = rowptr[r], k1 = rowptr[r + 1];
@@ -479,12 +483,13 @@ __global__ void k_rank_short(int64_t nrows, const int *rowptr, const int *tcol, 
     for (int j = k0; j < k1; ++j) rank += tcol[j] < c;
     col[k0 + rank] = c;
     val[k0 + rank] = tval[i];
+    if (perm) perm[k0 + rank] = tsrc[i];
   }
 }
 
 // One workgroup per listed row (grid-stride over the list; the count is read on the device).
 __global__ void __launch_bounds__(256) k_rank_long(const int *rowptr, const int *tcol, const double *tval, int *col,
-                                                   double *val, const int *long_rows) {
+                                                   double *val, const int *long_rows, const int *tsrc, int *perm) {
   __shared__ int keys[kRankChunk];
   const int count = long_rows[0];
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
@@ -516,6 +521,7 @@ __global__ void __launch_bounds__(256) k_rank_long(const int *rowptr, const int 
         if (i < len) {
           col[k0 + rank[t]] = mine[t];
           val[k0 + rank[t]] = tval[k0 + i];
+          if (perm) perm[k0 + rank[t]] = tsrc[k0 + i];
         }
       }
     }
@@ -598,39 +604,15 @@ struct ArenaWork {
   }
 };
 
+// Rows of C_f from a piece list (e_piece: the first slot of each element; empty slots have
+// pair_T < 0), then C_f^T and the FP32 copies.  perm, when given, receives for every C_f^T
+// entry the index of its C_f entry (the time-coherent form refills C_f^T values with it).
 template <typename Work>
-static void assemble(Ctx &c, const double *Xn, Work &w) {
+static void build_rows(Ctx &c, Work &w, const int *e_piece, const int *pair_T, const double *piece_L, int *flag,
+                       bool keep_perm) {
   hipStream_t s = c.stream;
-  const int64_t nt = c.Nt, ns = c.Ns;
+  const int64_t ns = c.Ns;
   const int n = c.n;
-  c.have_cf = false;
-  c.pairs_kept = false;
-  int *flag = w.flags();
-  int *cand_off = w.work(c.cand_off, nt + 1, "candidate offsets");
-  hipLaunchKernelGGL(k_cand_count, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, ns, n, Xn, c.tri.p, cand_off,
-                     flag);
-  FSI_CHECK_LAUNCH();
-  scan_excl(cand_off, cand_off, nt, w.scan(nt), s);
-  check_flags(flag, s);
-  const int ncand = read_int(cand_off + nt, s);
-  c.n_cand = ncand;
-  int *piece_off = w.work(c.piece_cnt, (int64_t)ncand + 1, "piece counters");
-  hipLaunchKernelGGL(k_clip_count, dim3(grid_for(ncand, 128)), dim3(128), 0, s, (int64_t)ncand, nt, ns, n, Xn,
-                     c.tri.p, cand_off, piece_off);
-  FSI_CHECK_LAUNCH();
-  scan_excl(piece_off, piece_off, ncand, w.scan(ncand), s);
-  const int npieces = read_int(piece_off + ncand, s);
-  c.n_pairs = npieces;
-  int *pair_E = w.work(c.pair_E, npieces, "piece list");
-  int *pair_T = w.work(c.pair_T, npieces, "piece list");
-  double *piece_L = w.work(c.piece_L, 18 * (int64_t)npieces, "piece matrices");
-  hipLaunchKernelGGL(k_clip_emit, dim3(grid_for(ncand, 128)), dim3(128), 0, s, (int64_t)ncand, nt, ns, n, Xn,
-                     c.tri.p, c.ref_area.p, cand_off, piece_off, pair_E, pair_T, piece_L);
-  int *e_piece = w.work(c.e_piece, nt + 1, "element piece offsets");
-  hipLaunchKernelGGL(k_elem_piece_off, dim3(grid_for(nt + 1, 256)), dim3(256), 0, s, nt, cand_off, piece_off,
-                     e_piece);
-  FSI_CHECK_LAUNCH();
-  // rows of C_f
   Csr &Cf = c.Cf;
   Cf.nrows = ns;
   Cf.ncols = c.N2;
@@ -649,6 +631,8 @@ static void assemble(Ctx &c, const double *Xn, Work &w) {
   int hcnt[2] = {0, 0};
   FSI_HIP(hipMemcpyAsync(hcnt, huge, sizeof(hcnt), hipMemcpyDeviceToHost, s));
   FSI_HIP(hipStreamSynchronize(s));
+  c.cf_hcnt[0] = hcnt[0];
+  c.cf_hcnt[1] = hcnt[1];
   int *gflag = nullptr;
   double *gval = nullptr;
   if (hcnt[0] > 0) {
@@ -689,13 +673,16 @@ static void assemble(Ctx &c, const double *Xn, Work &w) {
   double *ct_val = w.out(Ct.val, nnz, "C_f^T");
   int *tcol = w.work(c.cft_tcol, nnz, "transpose staging");
   double *tval = w.work(c.cft_tval, nnz, "transpose staging");
+  int *tsrc = keep_perm ? w.work(c.cft_tsrc, nnz, "transpose staging") : nullptr;
+  int *perm = keep_perm ? w.work(c.cft_perm, nnz, "transpose permutation") : nullptr;
   int *long_rows = w.work(c.cft_long, c.N2 + 1, "long transposed rows");
   fill(long_rows, 1, 0, s);
   hipLaunchKernelGGL(k_scatter_t, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, cf_rp, cf_col, cf_val, ct_rp,
-                     ct_fill, tcol, tval);
+                     ct_fill, tcol, tval, tsrc);
   hipLaunchKernelGGL(k_rank_short, dim3(grid_for(c.N2, 256)), dim3(256), 0, s, c.N2, ct_rp, tcol, tval, ct_col,
-                     ct_val, long_rows);
-  hipLaunchKernelGGL(k_rank_long, dim3(512), dim3(256), 0, s, ct_rp, tcol, tval, ct_col, ct_val, long_rows);
+                     ct_val, long_rows, tsrc, perm);
+  hipLaunchKernelGGL(k_rank_long, dim3(512), dim3(256), 0, s, ct_rp, tcol, tval, ct_col, ct_val, long_rows, tsrc,
+                     perm);
   FSI_CHECK_LAUNCH();
   float *cf32 = w.out(Cf.val32, nnz, "the FP32 copy of C_f");
   float *ct32 = w.out(Ct.val32, nnz, "the FP32 copy of C_f^T");
@@ -704,7 +691,301 @@ static void assemble(Ctx &c, const double *Xn, Work &w) {
   c.have_cf = true;
 }
 
+template <typename Work>
+static void assemble(Ctx &c, const double *Xn, Work &w) {
+  hipStream_t s = c.stream;
+  const int64_t nt = c.Nt, ns = c.Ns;
+  const int n = c.n;
+  c.have_cf = false;
+  c.pairs_kept = false;
+  c.inc_valid = false;   // the piece list below replaces the time-coherent slots
+  int *flag = w.flags();
+  int *cand_off = w.work(c.cand_off, nt + 1, "candidate offsets");
+  hipLaunchKernelGGL(k_cand_count, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, ns, n, Xn, c.tri.p, cand_off,
+                     flag);
+  FSI_CHECK_LAUNCH();
+  scan_excl(cand_off, cand_off, nt, w.scan(nt), s);
+  check_flags(flag, s);
+  const int ncand = read_int(cand_off + nt, s);
+  c.n_cand = ncand;
+  int *piece_off = w.work(c.piece_cnt, (int64_t)ncand + 1, "piece counters");
+  hipLaunchKernelGGL(k_clip_count, dim3(grid_for(ncand, 128)), dim3(128), 0, s, (int64_t)ncand, nt, ns, n, Xn,
+                     c.tri.p, cand_off, piece_off);
+  FSI_CHECK_LAUNCH();
+  scan_excl(piece_off, piece_off, ncand, w.scan(ncand), s);
+  const int npieces = read_int(piece_off + ncand, s);
+  c.n_pairs = npieces;
+  int *pair_E = w.work(c.pair_E, npieces, "piece list");
+  int *pair_T = w.work(c.pair_T, npieces, "piece list");
+  double *piece_L = w.work(c.piece_L, 18 * (int64_t)npieces, "piece matrices");
+  hipLaunchKernelGGL(k_clip_emit, dim3(grid_for(ncand, 128)), dim3(128), 0, s, (int64_t)ncand, nt, ns, n, Xn,
+                     c.tri.p, c.ref_area.p, cand_off, piece_off, pair_E, pair_T, piece_L);
+  int *e_piece = w.work(c.e_piece, nt + 1, "element piece offsets");
+  hipLaunchKernelGGL(k_elem_piece_off, dim3(grid_for(nt + 1, 256)), dim3(256), 0, s, nt, cand_off, piece_off,
+                     e_piece);
+  FSI_CHECK_LAUNCH();
+  build_rows(c, w, e_piece, pair_T, piece_L, flag, false);
+}
+
+// ---- the time-coherent form (Sec. 7: follow the solid from its position at the previous
+// step instead of detecting its intersections anew)
+//
+// A rebuild gives every element a candidate box of (w + 1) x (h + 1) cells, one more than its
+// bounding box spans in each direction, and two piece slots per candidate cell (the fluid
+// triangles T0, T1 of the cell; pair_T = -1 for an empty slot).  A later call re-clips only
+// the elements whose vertices moved (any coordinate differs from the previous call's), into
+// the same slots: the candidate q of an element is cell (i0 + q mod w, j0 + q div w) of its
+// current box, as in the full assembly, so the kept pieces come in the same order and every
+// C_f sum in the same order (the result is bitwise that of the full assembly).  Then
+//   - nothing moved: C_f and C_f^T are kept;
+//   - some moved element's kept pieces (read in slot order) differ from its previous ones:
+//     rows, pattern and transpose anew;
+//   - otherwise the piece list, and so the pattern, is kept: row values again (pass 1 of the
+//     rows) and C_f^T values through the stored permutation;
+//   - an element outgrew its box: a rebuild.
+enum { IF_MESH = 1, IF_OVERFLOW = 2, IF_PATTERN = 4 };
+
+// Rebuild: validity and the candidate box of every element.
+__global__ void k_inc_box(int64_t nt, int64_t ns, int n, const double *__restrict__ X, const int *__restrict__ tri,
+                          int *box, int *cnt, int *moved, int *flag) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nt) return;
+  Pt P[3];
+  load_tri(X, ns, tri, (int)e, P);
+  bool ok = tri_area(P) > 0.0;
+  for (int m = 0; m < 3; ++m)
+    ok = ok && P[m].x >= 0.0 && P[m].x <= 1.0 && P[m].y >= 0.0 && P[m].y <= 1.0;
+  moved[e] = 1;
+  if (!ok) {
+    atomicOr(flag, IF_MESH);
+    box[2 * e] = box[2 * e + 1] = 0;
+    cnt[e] = 0;
+    return;
+  }
+  int i0, i1, j0, j1;
+  cell_range(P, n, i0, i1, j0, j1);
+  const int cw = min(i1 - i0 + 2, n), ch = min(j1 - j0 + 2, n);
+  box[2 * e] = cw;
+  box[2 * e + 1] = ch;
+  cnt[e] = cw * ch;
+}
+
+// A later call: validity, which elements moved, and whether one outgrew its box.
+// inc[0]: flags, inc[1]: moved elements.
+__global__ void k_inc_moved(int64_t nt, int64_t ns, int n, const double *__restrict__ X,
+                            const double *__restrict__ Xold, const int *__restrict__ tri, const int *__restrict__ box,
+                            int *moved, int *inc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nt) return;
+  Pt P[3];
+  load_tri(X, ns, tri, (int)e, P);
+  bool mv = false;
+  for (int m = 0; m < 3; ++m) {
+    const int v = tri[3 * e + m];
+    mv = mv || P[m].x != Xold[v] || P[m].y != Xold[ns + v];
+  }
+  moved[e] = mv ? 1 : 0;
+  if (!mv) return;   // unchanged since a call that found it valid
+  atomicAdd(&inc[1], 1);
+  bool ok = tri_area(P) > 0.0;
+  for (int m = 0; m < 3; ++m)
+    ok = ok && P[m].x >= 0.0 && P[m].x <= 1.0 && P[m].y >= 0.0 && P[m].y <= 1.0;
+  if (!ok) {
+    atomicOr(&inc[0], IF_MESH);
+    return;
+  }
+  int i0, i1, j0, j1;
+  cell_range(P, n, i0, i1, j0, j1);
+  if (i1 - i0 + 1 > box[2 * e] || j1 - j0 + 1 > box[2 * e + 1]) atomicOr(&inc[0], IF_OVERFLOW);
+}
+
+// Re-clip the candidate slots of the moved elements; the previous piece of each slot goes to
+// prevT.  inc[2] keeps the number of kept pieces.  An element that outgrew its box (the host
+// then rebuilds) or is invalid (the call fails) only writes within its own slots.
+__global__ void k_inc_emit(int64_t nslot, int64_t nt, int64_t ns, int n, const double *__restrict__ X,
+                           const int *__restrict__ tri, const double *__restrict__ ref_area,
+                           const int *__restrict__ cand_off, const int *__restrict__ moved, int *pair_E, int *pair_T,
+                           int *prevT, double *piece_L, int *inc) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nslot) return;
+  const int e = find_owner(cand_off, nt, c);
+  if (!moved[e]) return;
+  Pt P[3];
+  load_tri(X, ns, tri, e, P);
+  int i0, i1, j0, j1;
+  cell_range(P, n, i0, i1, j0, j1);
+  const int w = i1 - i0 + 1;
+  const int q = (int)(c - cand_off[e]);
+  Pt qq[2][kMaxPoly];
+  int mq[2] = {0, 0};
+  int mask = 0, i = 0, j = 0;
+  const double area = tri_area(P);
+  if (area > 0.0 && q < w * (j1 - j0 + 1)) {
+    i = i0 + q % w;
+    j = j0 + q / w;
+    mask = clip_pieces(P, n, i, j, qq, mq);
+  }
+  int delta = 0;
+  for (int t = 0; t < 2; ++t) {
+    const int64_t sl = 2 * c + t;
+    const int Tn = (mask >> t) & 1 ? 2 * (j * n + i) + t : -1;
+    const int To = pair_T[sl];
+    delta += (Tn >= 0) - (To >= 0);
+    prevT[sl] = To;
+    pair_T[sl] = Tn;
+    pair_E[sl] = Tn >= 0 ? e : -1;
+    if (Tn >= 0) piece_matrix(P, qq[t], mq[t], i, j, t, n, ref_area[e] / area, piece_L + 18 * sl);
+  }
+  if (delta) atomicAdd(&inc[2], delta);
+}
+
+// inc[0] |= IF_PATTERN when a moved element's kept pieces, read in slot order, differ from
+// its previous ones.  A box that shifted with the same pieces keeps the piece list (and so
+// every row of C_f, with its sums in the same order).
+__global__ void k_inc_cmp(int64_t nt, const int *__restrict__ cand_off, const int *__restrict__ moved,
+                          const int *__restrict__ pair_T, const int *__restrict__ prevT, int *inc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nt || !moved[e]) return;
+  const int64_t s1 = 2 * (int64_t)cand_off[e + 1];
+  int64_t a = 2 * (int64_t)cand_off[e], b = a;
+  for (;;) {
+    while (a < s1 && pair_T[a] < 0) ++a;
+    while (b < s1 && prevT[b] < 0) ++b;
+    if (a == s1 || b == s1) {
+      if (a != s1 || b != s1) atomicOr(&inc[0], IF_PATTERN);
+      return;
+    }
+    if (pair_T[a] != prevT[b]) {
+      atomicOr(&inc[0], IF_PATTERN);
+      return;
+    }
+    ++a;
+    ++b;
+  }
+}
+
+__global__ void k_inc_slot_off(int64_t nt, const int *cand_off, int *e_piece) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e <= nt) e_piece[e] = 2 * cand_off[e];
+}
+
+__global__ void k_gather_vals(int64_t nnz, const int *__restrict__ perm, const double *__restrict__ src,
+                              double *__restrict__ dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) dst[k] = src[perm[k]];
+}
+
+// Pattern kept: C_f values by pass 1 of the rows (row pointers, deferred and large-window
+// lists as built), C_f^T values through the permutation.
+static void refill_values(Ctx &c) {
+  hipStream_t s = c.stream;
+  const int64_t ns = c.Ns, nnz = c.Cf.nnz;
+  const int n = c.n;
+  const int *e_piece = c.e_piece.p, *pair_T = c.pair_T.p;
+  const double *piece_L = c.piece_L.p;
+  int *defer = c.cf_defer.p;
+  fill(defer, 1, 0, s);
+  hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 1, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece,
+                     pair_T, piece_L, nullptr, c.Cf.rowptr.p, c.Cf.col.p, c.Cf.val.p, nullptr, defer);
+  hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
+                     piece_L, nullptr, c.Cf.rowptr.p, c.Cf.col.p, c.Cf.val.p, nullptr, defer, c.cf_huge.p);
+  if (c.cf_hcnt[0] > 0)
+    hipLaunchKernelGGL(k_cf_rows_huge, dim3(1), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
+                       piece_L, nullptr, c.Cf.rowptr.p, c.Cf.col.p, c.Cf.val.p, nullptr, c.cf_huge.p, c.cf_wflag.p,
+                       c.cf_wval.p);
+  hipLaunchKernelGGL(k_gather_vals, dim3(grid_for(nnz, 256)), dim3(256), 0, s, nnz, c.cft_perm.p, c.Cf.val.p,
+                     c.CfT.val.p);
+  FSI_CHECK_LAUNCH();
+  convert(c.Cf.val32.p, c.Cf.val.p, nnz, s);
+  convert(c.CfT.val32.p, c.CfT.val.p, nnz, s);
+}
+
+static void assemble_incremental(Ctx &c, const double *Xn) {
+  hipStream_t s = c.stream;
+  const int64_t nt = c.Nt, ns = c.Ns;
+  const int n = c.n;
+  GrowWork w{c};
+  ++c.inc_counts[0];
+  if (!c.inc_flag.p) c.inc_flag.alloc(4);
+  int *inc = c.inc_flag.p;
+  if (c.inc_valid && c.have_cf) {
+    fill(inc, 2, 0, s);
+    hipLaunchKernelGGL(k_inc_moved, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, ns, n, Xn, c.inc_X.p, c.tri.p,
+                       c.inc_box.p, c.inc_moved.p, inc);
+    hipLaunchKernelGGL(k_inc_emit, dim3(grid_for(c.n_cand, 128)), dim3(128), 0, s, c.n_cand, nt, ns, n, Xn,
+                       c.tri.p, c.ref_area.p, c.cand_off.p, c.inc_moved.p, c.pair_E.p, c.pair_T.p, c.inc_prevT.p,
+                       c.piece_L.p, inc);
+    hipLaunchKernelGGL(k_inc_cmp, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, c.cand_off.p, c.inc_moved.p,
+                       c.pair_T.p, c.inc_prevT.p, inc);
+    FSI_CHECK_LAUNCH();
+    FSI_HIP(hipMemcpyAsync(c.inc_X.p, Xn, 2 * ns * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int h[3] = {0, 0, 0};
+    FSI_HIP(hipMemcpyAsync(h, inc, sizeof(h), hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    if (h[0] & IF_MESH) {
+      c.inc_valid = false;
+      c.have_cf = false;
+      FSI_REQUIRE(false, FSI_E_MESH, "X^n maps a solid triangle to a degenerate/inverted triangle or outside [0,1]^2");
+    }
+    if (!(h[0] & IF_OVERFLOW)) {
+      c.n_pairs = h[2];
+      if (h[1] == 0) {
+        ++c.inc_counts[4];          // nothing moved: C_f as it is
+      } else if (!(h[0] & IF_PATTERN)) {
+        refill_values(c);
+        ++c.inc_counts[3];
+      } else {
+        c.have_cf = false;
+        build_rows(c, w, c.e_piece.p, c.pair_T.p, c.piece_L.p, w.flags(), true);
+        ++c.inc_counts[2];
+      }
+      return;
+    }
+  }
+  // rebuild: boxes, slots, every element clipped
+  ++c.inc_counts[1];
+  c.inc_valid = false;
+  c.have_cf = false;
+  c.pairs_kept = false;
+  int *box = w.work(c.inc_box, 2 * nt, "candidate boxes");
+  int *moved = w.work(c.inc_moved, nt, "moved flags");
+  double *xold = w.work(c.inc_X, 2 * ns, "previous positions");
+  int *cand_off = w.work(c.cand_off, nt + 1, "candidate offsets");
+  fill(inc, 4, 0, s);
+  hipLaunchKernelGGL(k_inc_box, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, ns, n, Xn, c.tri.p, box, cand_off,
+                     moved, inc);
+  FSI_CHECK_LAUNCH();
+  scan_excl(cand_off, cand_off, nt, w.scan(nt), s);
+  int h[2] = {0, 0};
+  FSI_HIP(hipMemcpyAsync(&h[0], inc, sizeof(int), hipMemcpyDeviceToHost, s));
+  FSI_HIP(hipMemcpyAsync(&h[1], cand_off + nt, sizeof(int), hipMemcpyDeviceToHost, s));
+  FSI_HIP(hipStreamSynchronize(s));
+  FSI_REQUIRE(!(h[0] & IF_MESH), FSI_E_MESH,
+              "X^n maps a solid triangle to a degenerate/inverted triangle or outside [0,1]^2");
+  const int64_t nslot = h[1];
+  c.n_cand = nslot;
+  int *pair_E = w.work(c.pair_E, 2 * nslot, "piece slots");
+  int *pair_T = w.work(c.pair_T, 2 * nslot, "piece slots");
+  int *prevT = w.work(c.inc_prevT, 2 * nslot, "previous piece slots");
+  double *piece_L = w.work(c.piece_L, 36 * nslot, "piece matrices");
+  int *e_piece = w.work(c.e_piece, nt + 1, "element slot offsets");
+  fill(pair_T, 2 * nslot, -1, s);
+  hipLaunchKernelGGL(k_inc_emit, dim3(grid_for(nslot, 128)), dim3(128), 0, s, nslot, nt, ns, n, Xn, c.tri.p,
+                     c.ref_area.p, cand_off, moved, pair_E, pair_T, prevT, piece_L, inc);
+  hipLaunchKernelGGL(k_inc_slot_off, dim3(grid_for(nt + 1, 256)), dim3(256), 0, s, nt, cand_off, e_piece);
+  FSI_CHECK_LAUNCH();
+  FSI_HIP(hipMemcpyAsync(xold, Xn, 2 * ns * sizeof(double), hipMemcpyDeviceToDevice, s));
+  c.n_pairs = read_int(inc + 2, s);
+  build_rows(c, w, e_piece, pair_T, piece_L, w.flags(), true);
+  c.inc_valid = true;
+  c.pairs_kept = true;
+}
+
 void assemble_coupling(Ctx &c, const double *Xn, bool) {
+  if (c.cf_mode == FSI_COUPLING_INCREMENTAL) {
+    assemble_incremental(c, Xn);
+    return;
+  }
   GrowWork w{c};
   assemble(c, Xn, w);
   c.pairs_kept = true;

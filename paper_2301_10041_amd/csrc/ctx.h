@@ -122,6 +122,21 @@ struct Ctx {
   DevBuf<int> cf_wflag;     // that window (grow-only)
   DevBuf<double> cf_wval;
   DevBuf<int> dflag;       // device error flags (mesh / capacity)
+  int cf_hcnt[2] = {0, 0};  // rows with a device-memory window: count, largest window
+  // the time-coherent form (FSI_COUPLING_INCREMENTAL): candidate boxes of (w + 1) x (h + 1)
+  // cells, two piece slots per candidate (pair_T = -1 when empty), the positions of the last
+  // call, and the permutation C_f^T entry -> C_f entry
+  int cf_mode = FSI_COUPLING_FULL;
+  bool inc_valid = false;   // the slots hold the pieces of the positions in inc_X
+  DevBuf<int> inc_box;      // 2 Nt: box width and height in cells
+  DevBuf<int> inc_moved;    // Nt
+  DevBuf<int> inc_prevT;    // the slots' pieces before the last re-clip
+  DevBuf<double> inc_X;     // 2 Ns
+  DevBuf<int> inc_flag;     // [flags, moved elements, kept pieces, -]
+  DevBuf<int> cft_tsrc;     // transpose staging: source entry of each scattered entry
+  DevBuf<int> cft_perm;     // nnz: C_f entry of each C_f^T entry
+  // calls, rebuilds, pattern rebuilds, value refills, unchanged (see fsi_coupling_counts)
+  int64_t inc_counts[5] = {0, 0, 0, 0, 0};
 
   // multigrid hierarchies of the preconditioner
   Mg mgu, mgp;

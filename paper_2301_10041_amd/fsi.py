@@ -22,6 +22,7 @@ PC_DIAG, PC_TRI = 0, 1
 # inner A11 modes (fsi_inner): MINRES with the block-diagonal approximation (default), the
 # fixed-cost block-diagonal and block-triangular forms, GMRES with the block-triangular one
 INNER_MINRES, INNER_FIXED_DIAG, INNER_FIXED_TRI, INNER_GMRES = 0, 1, 2, 3
+COUPLING_FULL, COUPLING_INCREMENTAL = 0, 1
 SMOOTH_CSR, SMOOTH_STENCIL = 0, 1
 MAX_LANES = 32                 # FSI_MAX_LANES: systems per fsi_step_batch
 COUPLING_SCRATCH_BYTES = 32 << 20   # FSI_COUPLING_SCRATCH_BYTES
@@ -58,6 +59,11 @@ class Sizes(C.Structure):
 
 class CouplingInfo(C.Structure):
     _fields_ = [("n_pairs", C.c_int64), ("nnz", C.c_int64)]
+
+
+class CouplingCounts(C.Structure):
+    _fields_ = [("calls", C.c_int64), ("rebuilds", C.c_int64), ("pattern_builds", C.c_int64),
+                ("value_refills", C.c_int64), ("unchanged", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
@@ -109,6 +115,8 @@ _SIGS = {
     "fsi_apply_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
     "fsi_set_inner": (C.c_int, [C.c_void_p, C.c_double, C.c_int32]),
     "fsi_set_inner_mode": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "fsi_set_coupling_mode": (C.c_int, [C.c_void_p, C.c_int]),
+    "fsi_get_coupling_counts": (C.c_int, [C.c_void_p, C.POINTER(CouplingCounts)]),
     "fsi_gmres_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
                                   C.POINTER(SolveStats)]),
     "fsi_step": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -313,6 +321,16 @@ class Context:
         info = CouplingInfo()
         self._check(lib().fsi_assemble_coupling_noalloc(self._h, _ptr(Xn), C.byref(info) if sync else None))
         return dict(n_pairs=info.n_pairs, nnz=info.nnz)
+
+    def set_coupling_mode(self, mode):
+        """COUPLING_FULL (detect anew every call) or COUPLING_INCREMENTAL (re-clip the moved
+        triangles into kept slots; bitwise the same C_f)."""
+        self._check(lib().fsi_set_coupling_mode(self._h, int(mode)))
+
+    def coupling_counts(self):
+        cc = CouplingCounts()
+        self._check(lib().fsi_get_coupling_counts(self._h, C.byref(cc)))
+        return {k: getattr(cc, k) for k, _ in CouplingCounts._fields_}
 
     def build_rhs(self, u_n, X_n, b):
         self._check(lib().fsi_build_rhs(self._h, _ptr(u_n), _ptr(X_n), _ptr(b)))
