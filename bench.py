@@ -19,11 +19,16 @@ Prints one JSON line.  `value` is FP64 steps/s at 1024^2.  Beside it:
              block-diagonal (one application of the MINRES preconditioner) and
              block-triangular (two stationary cycles) forms, and GMRES with the
              block-triangular approximation in the weighted norm;
+  coupling_modes  the coupling assembly per call at 1024^2 and 512^2, detected anew
+             (FSI_COUPLING_FULL) against the time-coherent form (FSI_COUPLING_INCREMENTAL), for
+             three motions between calls: the rotation step of the time loop, a step of 1e-15
+             rad (the same intersections, new values) and none;
   step_roofline   algorithmic bytes of a step (model below, from the measured outer and inner
              step counts) against the step time and 8 TB/s;
   configs    the CPU-fast 32^2 case (both preconditioners), the 256^2 ellipse (both
-             preconditioners), the 512^2 rotating-disk time loop (100 steps, dt 1e-3), the
-             nonlinear bar at 256^2 (Newton, the paper's exponential law);
+             preconditioners), the 512^2 rotating-disk time loop (100 steps, dt 1e-3; FP64 and
+             mixed, and FP64 with the time-coherent coupling), the nonlinear bar at 256^2
+             (Newton, the paper's exponential law);
   serving    the 512-request trace in mixed precision and in FP64;
   accuracy   per-run errors against the FP64 oracle (computed in the oracle leg);
   cpu_baseline / cpu_serving  the oracle on the host's cores (bounded samples).
@@ -363,6 +368,35 @@ def run_serving(count: int, slots: int, prec, per_grid: int = 1) -> dict:
     return out
 
 
+def coupling_modes(fsi, torch, ctx, position, step_angle, calls=10, warmup=2):
+    """Milliseconds per fsi_assemble_coupling call in each mode for three motions of the solid
+    between calls (position(angle) -> device X); the incremental form's branch counts."""
+    out = {}
+    for label, dang in (("rotation_step", step_angle), ("same_pieces_step", 1e-15), ("no_motion", 0.0)):
+        Xs = [position(dang * k) for k in range(warmup + calls)]
+        rec = {}
+        for mode, tag in ((fsi.COUPLING_FULL, "full"), (fsi.COUPLING_INCREMENTAL, "incremental")):
+            ctx.set_coupling_mode(mode)
+            before = ctx.coupling_counts()
+            for k in range(warmup):
+                ctx.assemble_coupling(Xs[k])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(warmup, warmup + calls):
+                ctx.assemble_coupling(Xs[k], sync=False)
+            torch.cuda.synchronize()
+            rec[f"{tag}_ms"] = round(1e3 * (time.perf_counter() - t0) / calls, 4)
+            if mode == fsi.COUPLING_INCREMENTAL:
+                after = ctx.coupling_counts()
+                rec["incremental_branches"] = {k: after[k] - before[k] for k in after if k != "calls"}
+        rec["speedup"] = round(rec["full_ms"] / rec["incremental_ms"], 3)
+        out[label] = rec
+        print(f"[bench coupling {label}] full {rec['full_ms']:.3f} ms incremental {rec['incremental_ms']:.3f} ms "
+              f"{rec['incremental_branches']}", file=sys.stderr, flush=True)
+    ctx.set_coupling_mode(fsi.COUPLING_FULL)
+    return out
+
+
 def time_loop(ctx, u0, Xs, N2, opts, warmup, steps, tag, profile=False, keep_first=False):
     """fsi_step over positions Xs (u^{n+1} of each step is u^n of the next); returns the
     timing record and (optionally) the state after the first step."""
@@ -489,13 +523,23 @@ def config_legs(args, fsi, inputs, torch, dev, save):
     rec = {"n": wl.n, "unknowns": ctx.sizes["N"], "solid_triangles": int(tri.shape[0]), "steps": steps,
            "dt": wl.dt}
     u0 = torch.zeros(2 * N2, dtype=torch.float64, device=dev)
-    for tag, prec in (("fp64", fsi.FP64), ("mixed", fsi.FP32)):
+    for tag, prec, cmode in (("fp64", fsi.FP64, fsi.COUPLING_FULL), ("mixed", fsi.FP32, fsi.COUPLING_FULL),
+                             ("fp64_incremental", fsi.FP64, fsi.COUPLING_INCREMENTAL)):
+        ctx.set_coupling_mode(cmode)
+        before = ctx.coupling_counts()
         opts = fsi.Opts(pc=fsi.PC_TRI, prec=prec, rtol=1e-8)
         r, _ = time_loop(ctx, u0, Xs, N2, opts, 1, steps, f"rotdisk512 {tag}")
         rec[tag] = dict(steps_per_s=r["value"], ms_per_step=r["ms_per_step"], t_coup_ms=r["t_coup_ms"],
                         t_sol_ms=r["t_solve_ms"], its_mean=sum(r["its"]) / steps,
                         its_max=max(r["its"]), inner_its_mean=sum(r["inner_its"]) / steps,
                         relres_true_max=r["relres_true"])
+        if cmode == fsi.COUPLING_INCREMENTAL:
+            after = ctx.coupling_counts()
+            rec[tag]["incremental_branches"] = {k: after[k] - before[k] for k in after if k != "calls"}
+    ctx.set_coupling_mode(fsi.COUPLING_FULL)
+    rec["coupling_modes"] = coupling_modes(
+        fsi, torch, ctx, lambda a: vec(np.concatenate(list(inputs.rotation(xy, (0.5, 0.5), a).T))),
+        OMEGA * wl.dt)
     ctx.close()
     out["rotdisk512"] = rec
     # the first step of the same loop at 256^2, where the oracle's counts exist
@@ -671,6 +715,10 @@ def main():
                     rec["vs_fp64_first_step"] = float(np.linalg.norm(first - save["big_fp64"]) /
                                                       np.linalg.norm(save["big_fp64"]))
                 fixed[form][tag] = rec
+    cmodes = coupling_modes(
+        fsi, torch, ctx,
+        lambda a: torch.from_numpy(np.concatenate(list(inputs.rotation(xy, (0.5, 0.5), a).T))).to(dev),
+        OMEGA * wl.dt)
     ctx.close()
     del Xs, u0
     torch.cuda.empty_cache()
@@ -723,6 +771,10 @@ def main():
             fixed, note="A11^{-1} other than by the inner MINRES: the fixed-cost forms take more outer steps than "
                         "the block inverses (outside the iteration bar), the inner GMRES more inner steps at this "
                         "size; vs_fp64_first_step: distance of the first step's solution from the headline's"))
+    out["coupling_modes"] = _round(dict(
+        cmodes, note=f"{args.workload}: ms per fsi_assemble_coupling call, detected anew (full) against the "
+                     "time-coherent form (incremental: moved triangles re-clipped into kept slots, pattern kept "
+                     "when the pieces are), bitwise the same C_f"))
     if configs:
         out["configs"] = _round(configs)
     if not args.no_serve:

@@ -67,7 +67,7 @@ size_t Ctx::device_bytes() const {
        s_ecs.bytes();
   b += Cf.bytes() + CfT.bytes() + cand_off.bytes() + piece_cnt.bytes() + pair_E.bytes() +
        pair_T.bytes() + piece_L.bytes() + e_piece.bytes() + cft_fill.bytes() + dflag.bytes() +
-       cft_tcol.bytes() + cft_tval.bytes() + cft_long.bytes() + scan_tmp.bytes() + cf_defer.bytes() + cf_huge.bytes() + cf_wflag.bytes() + cf_wval.bytes();
+       cft_tcol.bytes() + cft_tval.bytes() + cft_long.bytes() + scan_tmp.bytes() + cf_defer.bytes() + cf_defer2.bytes() + cf_huge.bytes() + cf_wflag.bytes() + cf_wval.bytes();
   b += inc_box.bytes() + inc_moved.bytes() + inc_prevT.bytes() + inc_X.bytes() + inc_flag.bytes() + cft_tsrc.bytes() +
        cft_perm.bytes();
   b += mgu.bytes() + mgp.bytes();

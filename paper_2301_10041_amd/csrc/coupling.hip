@@ -276,8 +276,17 @@ __global__ void k_elem_piece_off(int64_t nt, const int *cand_off, const int *pie
 }
 
 // ---- rows of C_f: one wavefront per solid node
-__constant__ int kOffC[2][6][2] = {{{0, 0}, {2, 0}, {2, 2}, {1, 0}, {2, 1}, {1, 1}},
-                                   {{0, 0}, {2, 2}, {0, 2}, {1, 1}, {1, 2}, {0, 1}}};
+// Lattice offsets (x, y), in half cells from the cell's lower-left corner, of the six P2 nodes
+// of fluid triangle t (vertices, then edge midpoints 01, 12, 20):
+//   t = 0: (0,0) (2,0) (2,2) (1,0) (2,1) (1,1);  t = 1: (0,0) (2,2) (0,2) (1,1) (1,2) (0,1);
+// packed two bits per node so that a runtime (t, b) costs shifts, not a table load.
+constexpr unsigned pack6(int a0, int a1, int a2, int a3, int a4, int a5) {
+  return (unsigned)(a0 | a1 << 2 | a2 << 4 | a3 << 6 | a4 << 8 | a5 << 10);
+}
+constexpr unsigned kOffX = pack6(0, 2, 2, 1, 2, 1) | pack6(0, 2, 0, 1, 1, 0) << 12;
+constexpr unsigned kOffY = pack6(0, 0, 2, 0, 1, 1) | pack6(0, 2, 2, 1, 2, 1) << 12;
+__device__ __forceinline__ int off_x(int t, int b) { return (int)(kOffX >> (12 * t + 2 * b)) & 3; }
+__device__ __forceinline__ int off_y(int t, int b) { return (int)(kOffY >> (12 * t + 2 * b)) & 3; }
 
 // One row: returns false (and does nothing) when the window exceeds CAP nodes.  The block is
 // one wavefront; every thread takes the same path.  The window is in LDS (CAP > 0), or, with
@@ -285,30 +294,55 @@ __constant__ int kOffC[2][6][2] = {{{0, 0}, {2, 0}, {2, 2}, {1, 0}, {2, 1}, {1, 
 // is written by one lane only after the marking pass, so the sums keep their fixed order).
 // Rows whose window exceeds kWinCap (the wide form) are listed in huge = [count, largest
 // window, rows...] for the device-memory form.
+// Adjacency entries [qa, min(qa + 64, q1)) of a row, one per lane: the entry (element << 2 |
+// local node) and its element's piece range.  Returns the number of entries.
+__device__ __forceinline__ int load_adj(int qa, int q1, const int *__restrict__ n2e,
+                                        const int *__restrict__ e_piece, int &av, int &aps, int &ape) {
+  const int lane = threadIdx.x;
+  const int A = min(kWave, q1 - qa);
+  av = 0;
+  aps = ape = 0;
+  if (lane < A) {
+    av = n2e[qa + lane];
+    aps = e_piece[av >> 2];
+    ape = e_piece[(av >> 2) + 1];
+  }
+  return A;
+}
+
 template <int CAP>
 __device__ bool cf_row(int64_t l, int pass, int n, const int *__restrict__ n2e_ptr, const int *__restrict__ n2e,
                        const int *__restrict__ e_piece, const int *__restrict__ pair_T,
                        const double *__restrict__ piece_L, int *cnt, const int *rowptr, int *col, double *val,
                        int *flag, int *huge = nullptr, int *gflag = nullptr, double *gval = nullptr) {
   constexpr int SCAP = CAP > 0 ? CAP : 1;
+  // windows of up to kWinSmall nodes keep their sums in registers (NACC per lane)
+  constexpr int NACC = CAP > 0 && CAP <= 256 ? CAP / kWave : 1;
   __shared__ int sflag[SCAP];
-  __shared__ double sval[SCAP];
+  __shared__ double sval[NACC > 1 ? 1 : SCAP];
+  __shared__ int kslot[kWave], kT[kWave];
   int *wflag = CAP > 0 ? sflag : gflag;
   double *wval = CAP > 0 ? sval : gval;
   int lane = threadIdx.x;
   const int L = 2 * n + 1;
-  // window of lattice nodes covered by the pieces around node l
+  // window of lattice nodes covered by the pieces around node l.  The adjacency entries are
+  // read a wavefront at a time (lane i: entry qa + i, its element's first and end piece) and
+  // passed to every lane by shuffles.
   int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
-  int q0 = n2e_ptr[l], q1 = n2e_ptr[l + 1];
-  for (int q = q0; q < q1; ++q) {
-    int e = n2e[q] >> 2;
-    for (int p = e_piece[e] + lane; p < e_piece[e + 1]; p += kWave) {
-      int T = pair_T[p];
-      if (T < 0) continue;   // an empty slot of the time-coherent layout
-      int cell = T >> 1;
-      int ci = cell % n, cj = cell / n;
-      imin = min(imin, 2 * ci); imax = max(imax, 2 * ci + 2);
-      jmin = min(jmin, 2 * cj); jmax = max(jmax, 2 * cj + 2);
+  const int q0 = n2e_ptr[l], q1 = n2e_ptr[l + 1];
+  int av, aps, ape;
+  for (int qa = q0; qa < q1; qa += kWave) {
+    const int A = load_adj(qa, q1, n2e, e_piece, av, aps, ape);
+    for (int i = 0; i < A; ++i) {
+      const int ps = __shfl(aps, i, kWave), pe = __shfl(ape, i, kWave);
+      for (int p = ps + lane; p < pe; p += kWave) {
+        int T = pair_T[p];
+        if (T < 0) continue;   // an empty slot of the time-coherent layout
+        int cell = T >> 1;
+        int ci = cell % n, cj = cell / n;
+        imin = min(imin, 2 * ci); imax = max(imax, 2 * ci + 2);
+        jmin = min(jmin, 2 * cj); jmax = max(jmax, 2 * cj + 2);
+      }
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -331,18 +365,24 @@ __device__ bool cf_row(int64_t l, int pass, int n, const int *__restrict__ n2e_p
     }
     return true;
   }
-  for (int p = lane; p < W; p += kWave) { wflag[p] = 0; wval[p] = 0.0; }
+  for (int p = lane; p < W; p += kWave) {
+    wflag[p] = 0;
+    if (NACC == 1) wval[p] = 0.0;
+  }
   __syncthreads();
   // mark the columns
-  for (int q = q0; q < q1; ++q) {
-    int e = n2e[q] >> 2;
-    for (int p = e_piece[e] + lane; p < e_piece[e + 1]; p += kWave) {
-      int T = pair_T[p], t = T & 1, cell = T >> 1;
-      if (T < 0) continue;
-      int ci = cell % n, cj = cell / n;
-      for (int b = 0; b < 6; ++b) {
-        int I = 2 * ci + kOffC[t][b][0] - imin, J = 2 * cj + kOffC[t][b][1] - jmin;
-        wflag[J * wI + I] = 1;
+  for (int qa = q0; qa < q1; qa += kWave) {
+    const int A = load_adj(qa, q1, n2e, e_piece, av, aps, ape);
+    for (int i = 0; i < A; ++i) {
+      const int ps = __shfl(aps, i, kWave), pe = __shfl(ape, i, kWave);
+      for (int p = ps + lane; p < pe; p += kWave) {
+        int T = pair_T[p], t = T & 1, cell = T >> 1;
+        if (T < 0) continue;
+        int ci = cell % n, cj = cell / n;
+        for (int b = 0; b < 6; ++b) {
+          int I = 2 * ci + off_x(t, b) - imin, J = 2 * cj + off_y(t, b) - jmin;
+          wflag[J * wI + I] = 1;
+        }
       }
     }
   }
@@ -354,18 +394,60 @@ __device__ bool cf_row(int64_t l, int pass, int n, const int *__restrict__ n2e_p
     if (lane == 0) cnt[l] = c;
     return true;
   }
-  // values: item order is fixed (adjacency, piece, local node); window position p is
-  // summed by lane p % 64 only, so the order of every sum is fixed.
-  for (int q = q0; q < q1; ++q) {
-    int e = n2e[q] >> 2, a = n2e[q] & 3;
-    for (int p = e_piece[e]; p < e_piece[e + 1]; ++p) {
-      int T = pair_T[p], t = T & 1, cell = T >> 1;
-      if (T < 0) continue;
-      int ci = cell % n, cj = cell / n;
-      for (int b = 0; b < 6; ++b) {
-        int I = 2 * ci + kOffC[t][b][0] - imin, J = 2 * cj + kOffC[t][b][1] - jmin;
-        int pos = J * wI + I;
-        if ((pos & (kWave - 1)) == lane) wval[pos] += piece_L[18 * (int64_t)p + a * 6 + b];
+  // values: item order is fixed (adjacency, piece, local node); window position p is summed
+  // by lane p % 64 only, so the order of every sum is fixed.  For each element, 64 slots at a
+  // time: the kept ones are listed in slot order (ballot), then the items of up to 10 kept
+  // pieces (lane 6 k + b: piece k, local node b) find their window positions and values at once,
+  // and every lane walks them in item order, adding those it owns (in registers for the small
+  // windows, in the window array otherwise).
+  double acc[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
+  for (int qa = q0; qa < q1; qa += kWave) {
+    const int A = load_adj(qa, q1, n2e, e_piece, av, aps, ape);
+    for (int i = 0; i < A; ++i) {
+      const int a = __shfl(av, i, kWave) & 3;
+      const int ps = __shfl(aps, i, kWave), pe = __shfl(ape, i, kWave);
+      for (int sb = ps; sb < pe; sb += kWave) {
+        const int sl = sb + lane;
+        const int Tl = sl < pe ? pair_T[sl] : -1;
+        const uint64_t kept = __ballot(Tl >= 0);
+        const int nk = __popcll(kept);
+        if (Tl >= 0) {
+          const int r = __popcll(kept & ((1ull << lane) - 1));
+          kslot[r] = sl;
+          kT[r] = Tl;
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < nk; k0 += 10) {
+          const int m = 6 * min(10, nk - k0);
+          int posl = -1;
+          double vl = 0.0;
+          if (lane < m) {
+            const int k = k0 + lane / 6, b = lane % 6;
+            const int T = kT[k], t = T & 1, cell = T >> 1;
+            const int ci = cell % n, cj = cell / n;
+            posl = (2 * cj + off_y(t, b) - jmin) * wI + 2 * ci + off_x(t, b) - imin;
+            vl = piece_L[18 * (int64_t)kslot[k] + a * 6 + b];
+          }
+          // item it is read from lane it (uniform position, so the sum it belongs to is chosen
+          // by a scalar branch; only the owning lane adds)
+          for (int it = 0; it < m; ++it) {
+            const int pos = __builtin_amdgcn_readlane(posl, it);
+            const double v = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(vl), it),
+                                              __builtin_amdgcn_readlane(__double2loint(vl), it));
+            const bool own = (pos & (kWave - 1)) == lane;
+            if (NACC > 1) {
+              const int k = pos >> 6;
+#pragma unroll
+              for (int kk = 0; kk < NACC; ++kk)
+                if (k == kk) acc[kk] = own ? acc[kk] + v : acc[kk];
+            } else if (own) {
+              wval[pos] += v;
+            }
+          }
+        }
+        __syncthreads();
       }
     }
   }
@@ -384,7 +466,15 @@ __device__ bool cf_row(int64_t l, int pass, int n, const int *__restrict__ n2e_p
       int I = imin + p % wI, J = jmin + p / wI;
       bool bndc = I == 0 || J == 0 || I == 2 * n || J == 2 * n;
       col[base + incl - 1] = J * L + I;
-      val[base + incl - 1] = bndc ? 0.0 : wval[p];
+      double v = 0.0;
+      if (NACC > 1) {
+#pragma unroll
+        for (int k = 0; k < NACC; ++k)
+          if (k == p0 / kWave) v = acc[k];
+      } else {
+        v = wval[p];
+      }
+      val[base + incl - 1] = bndc ? 0.0 : v;
     }
     base += __shfl(incl, kWave - 1, kWave);
   }
@@ -392,9 +482,11 @@ __device__ bool cf_row(int64_t l, int pass, int n, const int *__restrict__ n2e_p
 }
 
 
-// Rows with a window of up to kWinSmall nodes (12 KB of LDS: many wavefronts per CU); the
-// others are listed (defer[0] = count) for the wide form below.
-constexpr int kWinSmall = 1024;
+// Rows with a window of up to kWinSmall nodes (3 KB of LDS: many wavefronts per CU; the
+// windows of a solid about as fine as the fluid grid span a few cells); the others are listed
+// (defer[0] = count) for the wider forms below.
+constexpr int kWinSmall = 256;
+constexpr int kWinMid = 1024;
 __global__ void __launch_bounds__(kWave) k_cf_rows(int pass, int64_t ns, int n, const int *__restrict__ n2e_ptr,
                                                    const int *__restrict__ n2e, const int *__restrict__ e_piece,
                                                    const int *__restrict__ pair_T,
@@ -407,20 +499,39 @@ __global__ void __launch_bounds__(kWave) k_cf_rows(int pass, int64_t ns, int n, 
     defer[1 + atomicAdd(&defer[0], 1)] = (int)l;   // list order does not matter: rows are independent
 }
 
-// The listed rows with a window of up to kWinCap nodes (grid-stride over the list); larger
-// windows are listed in huge.
+// The rows listed in `in` with a window of up to CAP nodes (grid-stride over the list); rows
+// with larger windows go to the list `out` (CAP < kWinCap) or to huge (CAP = kWinCap).
+template <int CAP>
 __global__ void __launch_bounds__(kWave) k_cf_rows_wide(int pass, int n, const int *__restrict__ n2e_ptr,
                                                         const int *__restrict__ n2e, const int *__restrict__ e_piece,
                                                         const int *__restrict__ pair_T,
                                                         const double *__restrict__ piece_L, int *cnt,
                                                         const int *rowptr, int *col, double *val, int *flag,
-                                                        const int *defer, int *huge) {
-  const int count = defer[0];
+                                                        const int *in, int *out, int *huge) {
+  const int count = in[0];
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
-    cf_row<kWinCap>(defer[1 + q], pass, n, n2e_ptr, n2e, e_piece, pair_T, piece_L, cnt, rowptr, col, val, flag,
-                    huge);
+    const int l = in[1 + q];
+    if (!cf_row<CAP>(l, pass, n, n2e_ptr, n2e, e_piece, pair_T, piece_L, cnt, rowptr, col, val, flag, huge) &&
+        threadIdx.x == 0)
+      out[1 + atomicAdd(&out[0], 1)] = l;
     __syncthreads();
   }
+}
+
+// The three LDS forms of one pass over all rows: small windows (one wavefront per row), then
+// the listed rows of up to kWinMid and kWinCap nodes; rows above that are listed in huge.
+static void cf_rows_lds(hipStream_t s, int pass, int64_t ns, int n, const int *n2e_ptr, const int *n2e,
+                        const int *e_piece, const int *pair_T, const double *piece_L, int *cnt, const int *rowptr,
+                        int *col, double *val, int *flag, int *defer, int *defer2, int *huge) {
+  fill(defer, 1, 0, s);
+  fill(defer2, 1, 0, s);
+  hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, pass, ns, n, n2e_ptr, n2e, e_piece, pair_T,
+                     piece_L, cnt, rowptr, col, val, flag, defer);
+  hipLaunchKernelGGL(k_cf_rows_wide<kWinMid>, dim3(1024), dim3(kWave), 0, s, pass, n, n2e_ptr, n2e, e_piece, pair_T,
+                     piece_L, cnt, rowptr, col, val, flag, defer, defer2, huge);
+  hipLaunchKernelGGL(k_cf_rows_wide<kWinCap>, dim3(256), dim3(kWave), 0, s, pass, n, n2e_ptr, n2e, e_piece, pair_T,
+                     piece_L, cnt, rowptr, col, val, flag, defer2, nullptr, huge);
+  FSI_CHECK_LAUNCH();
 }
 
 // The rows with windows above kWinCap nodes (a solid much coarser than the fluid grid), one
@@ -619,14 +730,11 @@ static void build_rows(Ctx &c, Work &w, const int *e_piece, const int *pair_T, c
   Cf.width = 1;
   int *cf_rp = w.out(Cf.rowptr, ns + 1, "the C_f row pointers");
   int *defer = w.work(c.cf_defer, ns + 1, "deferred rows");
+  int *defer2 = w.work(c.cf_defer2, ns + 1, "deferred rows");
   int *huge = w.work(c.cf_huge, ns + 2, "rows with large windows");
-  fill(defer, 1, 0, s);
   fill(huge, 2, 0, s);
-  hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 0, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece,
-                     pair_T, piece_L, cf_rp, nullptr, nullptr, nullptr, flag, defer);
-  hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 0, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
-                     piece_L, cf_rp, nullptr, nullptr, nullptr, flag, defer, huge);
-  FSI_CHECK_LAUNCH();
+  cf_rows_lds(s, 0, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T, piece_L, cf_rp, nullptr, nullptr, nullptr, flag,
+              defer, defer2, huge);
   // rows whose window exceeds the LDS form: a device-memory window of the largest size
   int hcnt[2] = {0, 0};
   FSI_HIP(hipMemcpyAsync(hcnt, huge, sizeof(hcnt), hipMemcpyDeviceToHost, s));
@@ -648,11 +756,8 @@ static void build_rows(Ctx &c, Work &w, const int *e_piece, const int *pair_T, c
   Cf.nnz = nnz;
   int *cf_col = w.out(Cf.col, nnz, "C_f");
   double *cf_val = w.out(Cf.val, nnz, "C_f");
-  fill(defer, 1, 0, s);
-  hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 1, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece,
-                     pair_T, piece_L, nullptr, cf_rp, cf_col, cf_val, flag, defer);
-  hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
-                     piece_L, nullptr, cf_rp, cf_col, cf_val, flag, defer, huge);
+  cf_rows_lds(s, 1, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T, piece_L, nullptr, cf_rp, cf_col, cf_val, flag,
+              defer, defer2, huge);
   if (hcnt[0] > 0)
     hipLaunchKernelGGL(k_cf_rows_huge, dim3(1), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
                        piece_L, nullptr, cf_rp, cf_col, cf_val, flag, huge, gflag, gval);
@@ -883,12 +988,8 @@ static void refill_values(Ctx &c) {
   const int n = c.n;
   const int *e_piece = c.e_piece.p, *pair_T = c.pair_T.p;
   const double *piece_L = c.piece_L.p;
-  int *defer = c.cf_defer.p;
-  fill(defer, 1, 0, s);
-  hipLaunchKernelGGL(k_cf_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 1, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece,
-                     pair_T, piece_L, nullptr, c.Cf.rowptr.p, c.Cf.col.p, c.Cf.val.p, nullptr, defer);
-  hipLaunchKernelGGL(k_cf_rows_wide, dim3(256), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
-                     piece_L, nullptr, c.Cf.rowptr.p, c.Cf.col.p, c.Cf.val.p, nullptr, defer, c.cf_huge.p);
+  cf_rows_lds(s, 1, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T, piece_L, nullptr, c.Cf.rowptr.p, c.Cf.col.p,
+              c.Cf.val.p, nullptr, c.cf_defer.p, c.cf_defer2.p, c.cf_huge.p);
   if (c.cf_hcnt[0] > 0)
     hipLaunchKernelGGL(k_cf_rows_huge, dim3(1), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
                        piece_L, nullptr, c.Cf.rowptr.p, c.Cf.col.p, c.Cf.val.p, nullptr, c.cf_huge.p, c.cf_wflag.p,

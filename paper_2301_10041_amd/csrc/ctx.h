@@ -117,7 +117,8 @@ struct Ctx {
   DevBuf<double> cft_tval;
   DevBuf<int> cft_long;     // [count, rows...]: rows ranked by a workgroup each
   DevBuf<int> scan_tmp;     // scan partials (grow-only)
-  DevBuf<int> cf_defer;     // [count, rows...]: C_f rows assembled with the wide window
+  DevBuf<int> cf_defer;     // [count, rows...]: C_f rows assembled with the wider windows
+  DevBuf<int> cf_defer2;    // [count, rows...]: those above the middle window
   DevBuf<int> cf_huge;      // [count, largest window, rows...]: rows with a device-memory window
   DevBuf<int> cf_wflag;     // that window (grow-only)
   DevBuf<double> cf_wval;
