@@ -38,7 +38,8 @@ struct MgLevel {
 struct Mg {
   int comps = 1;           // unknowns per node: 2 (velocity, 2x2 blocks) or 1 (pressure)
   bool stencil = false;    // smoothing, residuals and transfers matrix-free (structured grid)
-  bool tail = true;        // velocity levels of n <= 16 in one launch (with the stencil form)
+  bool tail = true;        // velocity levels of n <= 16 / pressure levels of n <= 64 in one launch
+                           // (with the stencil form)
   int degree = 3;          // Chebyshev smoothing steps before and after the coarse correction
   int degree32 = 3;        // the same for the FP32 V-cycle of the mixed-precision form
   std::vector<MgLevel> lv; // lv[0] finest

@@ -190,6 +190,36 @@ struct TailArgs {
 };
 template <typename T>
 void mg_tail(const TailArgs<T> &a, hipStream_t s, int K = 1);
+// The coarse end of a pressure (P1) V-cycle in one launch per system (mgtail.hip): levels
+// lv[0..nlev) of at most kPTailMaxN cells (each the next one's fine level) and the dense
+// inverse of the coarsest.  LDS (offsets in T): level l's b at lv[l].off and x right after it
+// ((n + 1)^2 each, row-major), a shared second iterate at offx2 ((n + 1)^2 of lv[0]: the
+// ping-pong buffer of the smoothing steps, then the residual), the coarsest b at offc and x
+// after it (m each), the P1 tables of the levels (kPTailTab each) at offt, and the dense
+// inverse at offm when it fits (else offm = -1: read from device memory); lds = the total.
+// b and x in device memory: the first level's right-hand side and result (lane stride lb).
+// Each node's search direction stays in a register of the thread that owns it
+// (kPTailPer nodes per thread).
+constexpr int kPTailMax = 6, kPTailDeg = 4, kPTailMaxN = 64, kPTailPer = 5, kPTailDenseMax = 6 * 64;
+constexpr int kPTailTab = 9 * kP1Nbr + 9;   // coef[9][7], dinv[9]
+template <typename T>
+struct PTailLevel {
+  int n, off;
+  const P1Table<T> *tab;
+  T c1[kPTailDeg], c2[kPTailDeg];   // p1_cheb_coefs of the level
+};
+template <typename T>
+struct PTailArgs {
+  int nlev, degree;
+  PTailLevel<T> lv[kPTailMax];
+  int offx2, offc, offt, offm, m, lds;
+  const T *cinv;
+  const T *b;
+  T *x;
+  int64_t lb;
+};
+template <typename T>
+void p1_tail(const PTailArgs<T> &a, hipStream_t s, int K = 1);
 // bc = R (b - A_f x) in one launch (stencil.hip): the residual lives only in LDS
 template <typename T>
 void resid_restrict(int nf, const StencilTable<T> *tab, const P2RestrTable<T> *rtab, LP<const T> x,

@@ -475,6 +475,52 @@ static bool tail_args(Mg &mg, int l, int degree, const T *b, T *x, int64_t ls, T
   return true;
 }
 
+// The arguments of the one-launch coarse end of the pressure V-cycle from level l, or false
+// when the remaining levels do not fit it (too fine, too many, smoothing degree or LDS).
+template <typename T>
+static bool p1_tail_args(Mg &mg, int l, int degree, const T *b, T *x, int64_t ls, PTailArgs<T> &a) {
+  const int last = (int)mg.lv.size() - 1;   // the dense coarsest level
+  const int nlev = last - l;
+  if (!mg.stencil || mg.comps != 1 || nlev < 1 || nlev > kPTailMax || degree < 1 || degree > kPTailDeg ||
+      mg.lv[l].n > kPTailMaxN || (mg.lv[l].n + 1) * (mg.lv[l].n + 1) > kPTailPer * 1024)
+    return false;
+  a = PTailArgs<T>{};
+  a.nlev = nlev;
+  a.degree = degree;
+  int off = 0;
+  for (int k = 0; k < nlev; ++k) {
+    const MgLevel &L = mg.lv[l + k];
+    PTailLevel<T> &t = a.lv[k];
+    t.n = L.n;
+    t.off = off;
+    off += 2 * (L.n + 1) * (L.n + 1);
+    t.tab = p1tab<T>(L);
+    // the coefficients of the per-level launches on [lmax / 30, lmax]
+    p1_cheb_coefs<T>(L.lmax / 30.0, L.lmax, degree, t.c1, t.c2);
+  }
+  a.offx2 = off;
+  off += (mg.lv[l].n + 1) * (mg.lv[l].n + 1);
+  a.offc = off;
+  a.m = (int)mg.ncoarse;
+  FSI_REQUIRE(a.m == (int)mg.lv[last].nodes, FSI_E_STATE, "coarsest level size");
+  if (a.m > kPTailDenseMax) return false;
+  off += 2 * a.m;
+  a.offt = off;
+  off += nlev * kPTailTab;
+  a.lds = off;
+  if ((int64_t)a.lds * (int64_t)sizeof(T) > tail_lds_limit()) return false;
+  a.offm = -1;
+  if ((int64_t)(off + (int64_t)a.m * a.m) * (int64_t)sizeof(T) <= tail_lds_limit()) {
+    a.offm = off;
+    a.lds = off + a.m * a.m;
+  }
+  a.cinv = Pr<T>::cinv(mg);
+  a.b = b;
+  a.x = x;
+  a.lb = ls;
+  return true;
+}
+
 // ---------------------------------------------------------------- V-cycle
 // One V-cycle at level l for right-hand side b (comps * nodes entries, component-major).
 // Returns the level work vector that holds the result.
@@ -516,6 +562,12 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
     TailArgs<T> ta;
     if (mg.tail && tail_args<T>(mg, l, degree, b, x, ls, ta)) {
       mg_tail<T>(ta, s, K);
+      return x;
+    }
+  } else {                  // the coarse end of the pressure cycle in one launch
+    PTailArgs<T> pa;
+    if (mg.tail && p1_tail_args<T>(mg, l, degree, b, x, ls, pa)) {
+      p1_tail<T>(pa, s, K);
       return x;
     }
   }
