@@ -410,12 +410,13 @@ int fsi_export_lattice(int32_t n, double nu, double rdt, int32_t table, int32_t 
 enum fsi_smoother { FSI_SMOOTH_CSR = 0, FSI_SMOOTH_STENCIL = 1 };
 int fsi_set_smoother(fsi_ctx *ctx, int kind);
 
-/* Replay the A11 preconditioner (V-cycles, Chebyshev mass solve, pressure V-cycle: about
- * 60 launches) as one captured HIP graph per precision.  Default: on for n <= 32, where
- * a step is bound by launch latency (a graph keeps the pressure part on the context's
- * stream, and the convergence check of the inner solve every 2 steps runs frozen steps
- * past convergence, so larger grids run faster without).  The graph holds kernel nodes
- * only; results are the same as without it. */
+/* Replay the A11 preconditioner (V-cycles, Chebyshev mass solve, pressure V-cycle) and the
+ * inner MINRES steps as captured HIP graphs.  Default: off.  A graph keeps the pressure part
+ * on the context's stream (without it, that part runs on a second stream beside the velocity
+ * cycle) and the inner solve checks convergence every 2 steps (frozen steps past
+ * convergence); with the coarse ends of both multigrid cycles in one launch each, the two
+ * streams measured faster at every grid size.  The graph holds kernel nodes only; results
+ * are the same as without it. */
 int fsi_set_graphs(fsi_ctx *ctx, int enable);
 
 /* Measurement of the dominant kernel, the finest-level Chebyshev smoothing on A_f

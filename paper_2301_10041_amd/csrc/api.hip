@@ -169,10 +169,12 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     fsi::build_fluid(c);
     fsi::build_multigrid(c);
     c.mgu.stencil = c.mgp.stencil = true;
-    // graphs keep the preconditioner on one stream and run up to 7 frozen MINRES steps past
-    // convergence: they pay off only where launch latency dominates (measured faster at
-    // 32^2, slower from 64^2 on)
-    c.use_graphs = c.n <= 32;
+    // graphs keep the preconditioner on one stream (the pressure chain no longer beside the
+    // velocity cycle) and check convergence every second MINRES step: with the coarse ends of
+    // both cycles in one launch each they measured slower than the two streams at every size
+    // (32^2 27.1 / 23.3 ms, 128^2 54.6 / 43.8 ms per FP64 step, batches of 8 likewise), so
+    // they are off unless fsi_set_graphs asks for them
+    c.use_graphs = false;
     fsi::make_shadow(c.Af, c.stream);
     fsi::make_shadow(c.B, c.stream);
     fsi::make_shadow(c.BT, c.stream);
