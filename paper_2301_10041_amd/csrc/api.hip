@@ -22,6 +22,8 @@ Ctx::~Ctx() {
   if (aux_stream) (void)hipStreamDestroy(aux_stream);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
+  for (hipEvent_t e : ev_ms)
+    if (e) (void)hipEventDestroy(e);
   if (hpin) (void)hipHostFree(hpin);
   if (bat_h) (void)hipHostFree(bat_h);
   if (gi_h) (void)hipHostFree(gi_h);
@@ -165,6 +167,7 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     FSI_HIP(hipStreamCreateWithFlags(&c.aux_stream, hipStreamNonBlocking));
     FSI_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
     FSI_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+    for (hipEvent_t &e : c.ev_ms) FSI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     fsi::build_solid(c);
     fsi::build_fluid(c);
     fsi::build_multigrid(c);

@@ -878,6 +878,8 @@ constexpr int kMsRec = 5;                     // recorded per iteration: e, d, 1
 constexpr int kMsBMax = 32;                   // Lanczos vectors per block at most
 static_assert(kMsBMax + 2 <= kWave, "one wave computes the coefficients of a block");
 constexpr int kMsDoubles = sizeof(MinresState) / sizeof(double);
+constexpr int kMsLagMaxN = 256;   // grids whose inner steps read the state back one step late
+constexpr int kHpinHalf = 2048;   // doubles: the two halves of the pinned host buffer
 
 // The kernels below run K systems (lane = blockIdx.y): lane k uses st + k and vectors at
 // + k n (n = nf, the lane stride of every inner vector).
@@ -1247,6 +1249,12 @@ static void minres_a11(Ctx &c, const double *const *b, double *const *xout, int 
   // read-back; checking every 8 steps measured 5-12% slower at 64^2 and 128^2 from the
   // frozen steps run past convergence)
   const int check_every = graphs ? 2 : 1;
+  // Eager launches on grids of n <= kMsLagMaxN: the state of step it - 1 is read back after
+  // step it has been enqueued (a copy and an event per step, two host buffers), so the device
+  // does not wait for the host between steps; the step enqueued past convergence is frozen by
+  // the done flag, which costs one step per solve.  On larger grids a step takes long enough
+  // that the wait is the smaller cost.
+  const bool lag = !graphs && c.n <= kMsLagMaxN;
   const int pk = std::is_same<TA, double>::value ? 0 : 1;
   int it = 0, k0 = 0;   // iterations done; iterations before the current block
   const int B = c.ms_B;
@@ -1261,17 +1269,21 @@ static void minres_a11(Ctx &c, const double *const *b, double *const *xout, int 
     k0 = it;
   };
   double *h = c.hpin;
-  auto all_done = [&]() {
-    FSI_HIP(hipMemcpyAsync(h, st, (size_t)K * kMsDoubles * sizeof(double), hipMemcpyDeviceToHost, s));
-    FSI_HIP(hipStreamSynchronize(s));
+  static_assert(FSI_MAX_LANES * kMsDoubles <= kHpinHalf, "two state copies in the pinned buffer");
+  auto states_done = [&](const double *hb) {
     bool done = true;
     for (int k = 0; k < K; ++k) {
-      const MinresState *hs = (const MinresState *)h + k;
+      const MinresState *hs = (const MinresState *)hb + k;
       FSI_REQUIRE(hs->phibar == hs->phibar && hs->beta == hs->beta, FSI_E_NONFINITE,
                   "non-finite value in the inner A11 solve");
       done = done && hs->done != 0.0;
     }
     return done;
+  };
+  auto all_done = [&]() {
+    FSI_HIP(hipMemcpyAsync(h, st, (size_t)K * kMsDoubles * sizeof(double), hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    return states_done(h);
   };
   while (it < maxit) {
     // the rotation: in phase p the roles are shifted by p (r2 of phase p is y of p-1, ...)
@@ -1292,7 +1304,17 @@ static void minres_a11(Ctx &c, const double *const *b, double *const *xout, int 
     }
     ++it;
     if (it - k0 == B) flush(false);
-    if ((it % check_every == 0 || it == maxit) && all_done()) break;
+    if (lag) {
+      double *hb = h + (it & 1) * kHpinHalf;
+      FSI_HIP(hipMemcpyAsync(hb, st, (size_t)K * kMsDoubles * sizeof(double), hipMemcpyDeviceToHost, s));
+      FSI_HIP(hipEventRecord(c.ev_ms[it & 1], s));
+      if (it >= 2) {   // step it - 1, while step it runs
+        FSI_HIP(hipEventSynchronize(c.ev_ms[(it - 1) & 1]));
+        if (states_done(h + ((it - 1) & 1) * kHpinHalf)) break;
+      }
+    } else if ((it % check_every == 0 || it == maxit) && all_done()) {
+      break;
+    }
   }
   flush(true);
   all_done();
