@@ -419,6 +419,20 @@ int fsi_set_smoother(fsi_ctx *ctx, int kind);
  * are the same as without it. */
 int fsi_set_graphs(fsi_ctx *ctx, int enable);
 
+/* When the inner MINRES solve learns that it has converged (without graphs).
+ *  FSI_CHECK_AUTO (default): FSI_CHECK_LAGGED on grids of n <= 256, FSI_CHECK_EVERY_STEP above.
+ *  FSI_CHECK_EVERY_STEP: the state of each step is copied back and the host waits for it
+ *    before it enqueues the next step (the device idles for that round trip).
+ *  FSI_CHECK_LAGGED: the state of step k - 1 is read after step k has been enqueued, so the
+ *    device does not wait for the host; the step enqueued past convergence is frozen by the
+ *    device-side done flag (the same results, bitwise; one extra step of work per solve).
+ *    Faster for one solve on an idle device (32^2-256^2: 4-15% per step), slower where other
+ *    streams keep the device busy (the request loop of serve.py measured 141-147 against 151
+ *    requests/s), where the extra step takes time from the other work.
+ * Errors: FSI_E_ARG (unknown mode). */
+enum fsi_check_mode { FSI_CHECK_AUTO = 0, FSI_CHECK_EVERY_STEP = 1, FSI_CHECK_LAGGED = 2 };
+int fsi_set_inner_check(fsi_ctx *ctx, int mode);
+
 /* Measurement of the dominant kernel, the finest-level Chebyshev smoothing on A_f
  * (d = c1 d + c2 D^{-1}(b - A_f x), y = x + d on the 2x2-block system): with the
  * structured-grid products (default) the launch that takes the post-smoothing steps at

@@ -242,6 +242,13 @@ int fsi_set_smoother(fsi_ctx *ctx, int kind) {
   });
 }
 
+int fsi_set_inner_check(fsi_ctx *ctx, int mode) {
+  if (!ctx) return FSI_E_ARG;
+  if (mode != FSI_CHECK_AUTO && mode != FSI_CHECK_EVERY_STEP && mode != FSI_CHECK_LAGGED) return FSI_E_ARG;
+  ctx->c.ms_check = mode;
+  return FSI_OK;
+}
+
 int fsi_set_graphs(fsi_ctx *ctx, int enable) {
   if (!ctx) return FSI_E_ARG;
   return guarded(ctx, [&] {

@@ -188,6 +188,7 @@ struct Ctx {
   hipStream_t aux_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev_ms[2] = {nullptr, nullptr};   // the inner MINRES state copies of two steps
+  int ms_check = FSI_CHECK_AUTO;              // fsi_set_inner_check
   bool capturing = false;     // inside a graph capture: the preconditioner stays on one stream
   // inner MINRES: device-side scalar state, its own reduction buffer and solution vector
   // (allocated once: captured graphs hold these pointers), graphs per precision and phase

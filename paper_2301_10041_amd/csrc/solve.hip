@@ -1249,12 +1249,13 @@ static void minres_a11(Ctx &c, const double *const *b, double *const *xout, int 
   // read-back; checking every 8 steps measured 5-12% slower at 64^2 and 128^2 from the
   // frozen steps run past convergence)
   const int check_every = graphs ? 2 : 1;
-  // Eager launches on grids of n <= kMsLagMaxN: the state of step it - 1 is read back after
-  // step it has been enqueued (a copy and an event per step, two host buffers), so the device
-  // does not wait for the host between steps; the step enqueued past convergence is frozen by
-  // the done flag, which costs one step per solve.  On larger grids a step takes long enough
-  // that the wait is the smaller cost.
-  const bool lag = !graphs && c.n <= kMsLagMaxN;
+  // Lagged check (eager launches; by default on grids of n <= kMsLagMaxN): the state of step
+  // it - 1 is read back after step it has been enqueued (a copy and an event per step, two
+  // host buffers), so the device does not wait for the host between steps; the step enqueued
+  // past convergence is frozen by the done flag, which costs one step per solve.  On larger
+  // grids a step takes long enough that the wait is the smaller cost.
+  const bool lag = !graphs && (c.ms_check == FSI_CHECK_LAGGED ||
+                               (c.ms_check == FSI_CHECK_AUTO && c.n <= kMsLagMaxN));
   const int pk = std::is_same<TA, double>::value ? 0 : 1;
   int it = 0, k0 = 0;   // iterations done; iterations before the current block
   const int B = c.ms_B;

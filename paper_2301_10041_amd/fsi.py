@@ -23,6 +23,7 @@ PC_DIAG, PC_TRI = 0, 1
 # fixed-cost block-diagonal and block-triangular forms, GMRES with the block-triangular one
 INNER_MINRES, INNER_FIXED_DIAG, INNER_FIXED_TRI, INNER_GMRES = 0, 1, 2, 3
 COUPLING_FULL, COUPLING_INCREMENTAL = 0, 1
+CHECK_AUTO, CHECK_EVERY_STEP, CHECK_LAGGED = 0, 1, 2
 SMOOTH_CSR, SMOOTH_STENCIL = 0, 1
 MAX_LANES = 32                 # FSI_MAX_LANES: systems per fsi_step_batch
 COUPLING_SCRATCH_BYTES = 32 << 20   # FSI_COUPLING_SCRATCH_BYTES
@@ -106,6 +107,7 @@ _SIGS = {
     "fsi_set_solid": (C.c_int, [C.c_void_p, C.POINTER(SolidDesc)]),
     "fsi_set_smoother": (C.c_int, [C.c_void_p, C.c_int]),
     "fsi_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
+    "fsi_set_inner_check": (C.c_int, [C.c_void_p, C.c_int]),
     "fsi_footprint": (C.c_int, [C.POINTER(FluidDesc), C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "fsi_sizes": (C.c_int, [C.c_void_p, C.POINTER(Sizes)]),
     "fsi_assemble_coupling": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(CouplingInfo)]),
@@ -346,6 +348,11 @@ class Context:
 
     def set_graphs(self, enable=True):
         self._check(lib().fsi_set_graphs(self._h, 1 if enable else 0))
+
+    def set_inner_check(self, mode):
+        """CHECK_AUTO, CHECK_EVERY_STEP or CHECK_LAGGED: when the inner MINRES solve learns
+        that it has converged (the same results in every mode)."""
+        self._check(lib().fsi_set_inner_check(self._h, int(mode)))
 
     def set_inner(self, rtol, maxit=0):
         self._check(lib().fsi_set_inner(self._h, float(rtol), int(maxit)))

@@ -67,7 +67,11 @@ class Slot:
 
     def _new_ctx(self, wl):
         xy, tri = wl.solid_mesh()
-        return fsi.Context(wl.n, xy, tri, nu=wl.nu, rho=wl.rho, dt=wl.dt, kappa=wl.kappa, stream=self.stream)
+        ctx = fsi.Context(wl.n, xy, tri, nu=wl.nu, rho=wl.rho, dt=wl.dt, kappa=wl.kappa, stream=self.stream)
+        # jobs run concurrently: a step enqueued past convergence would take device time from
+        # the other jobs, so the inner solves wait for each step's convergence check
+        ctx.set_inner_check(fsi.CHECK_EVERY_STEP)
+        return ctx
 
     @property
     def ctx(self):

@@ -89,6 +89,42 @@ def test_batch_equals_alone_bitwise(name, n, prec, graphs, ks, inner):
         c.close()
 
 
+@pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
+def test_inner_check_modes_bitwise(prec):
+    """The inner MINRES convergence check every step, one step late (the step past convergence
+    frozen by the device's done flag) and by default: the same states and counts, bitwise, for
+    one system and for a lockstep batch of three at 48^2 (where the default is the lagged
+    check); an unknown mode is refused."""
+    torch_dev()
+    print(f"[inner check modes prec={prec}]", flush=True)
+    opts = fsi.Opts(prec=prec, pc=fsi.PC_TRI, rtol=1e-8)
+    wls = workloads(48, 3, seed=23)
+    res = {}
+    for mode in (fsi.CHECK_EVERY_STEP, fsi.CHECK_LAGGED, fsi.CHECK_AUTO):
+        ctxs = [fsi.Context.from_workload(wl) for wl in wls]
+        for c in ctxs:
+            c.set_inner_check(mode)
+        u, X, state = inputs_of(wls[0], ctxs[0])
+        st = ctxs[0].step(u, X, state, opts)
+        one = to_host(state)
+        states, stats, rcs = batch(ctxs, wls, opts)
+        assert rcs == [fsi.FSI_OK] * 3
+        res[mode] = (one, st["its"], st["inner_its"], states, [(s["its"], s["inner_its"]) for s in stats])
+        for c in ctxs:
+            c.close()
+    ref = res[fsi.CHECK_EVERY_STEP]
+    for mode in (fsi.CHECK_LAGGED, fsi.CHECK_AUTO):
+        got = res[mode]
+        assert np.array_equal(got[0], ref[0]) and got[1:3] == ref[1:3], mode
+        assert all(np.array_equal(a, b) for a, b in zip(got[3], ref[3])) and got[4] == ref[4], mode
+    with pytest.raises(fsi.FsiError):
+        ctx = fsi.Context.from_workload(wls[0])
+        try:
+            ctx.set_inner_check(3)
+        finally:
+            ctx.close()
+
+
 def test_batch_matches_oracle():
     torch_dev()
     print("[batch oracle]", flush=True)
