@@ -49,3 +49,21 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(fsi, "_lib", None)
     with pytest.raises(fsi.FsiLibraryMissing):
         fsi.lib()
+
+
+def test_null_context_and_bad_arguments_without_gpu():
+    """Every entry point that takes a context refuses a null one with FSI_E_ARG before any
+    device call; the footprint query refuses impossible sizes."""
+    import ctypes as C
+    from paper_2301_10041_amd import fsi
+    L = fsi.lib()
+    assert L.fsi_set_coupling_mode(None, fsi.COUPLING_INCREMENTAL) == fsi.FSI_E_ARG
+    assert L.fsi_set_inner_check(None, fsi.CHECK_LAGGED) == fsi.FSI_E_ARG
+    assert L.fsi_set_graphs(None, 1) == fsi.FSI_E_ARG
+    assert L.fsi_set_inner_mode(None, fsi.INNER_MINRES, 0) == fsi.FSI_E_ARG
+    assert L.fsi_get_coupling_counts(None, None) == fsi.FSI_E_ARG
+    assert L.fsi_assemble_coupling(None, None, None) == fsi.FSI_E_ARG
+    assert L.fsi_assemble_coupling_noalloc(None, None, None) == fsi.FSI_E_ARG
+    size = C.c_size_t(0)
+    bad = fsi.FluidDesc(1, 1.0, 1.0, 0.01)   # n < 2
+    assert L.fsi_footprint(C.byref(bad), 3, 1, C.byref(size)) == fsi.FSI_E_ARG
