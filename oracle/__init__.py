@@ -19,6 +19,8 @@ problems with fictitious domain approach"):
 * ``system``    the 4x4 block matrix and right-hand side of eq. (matrix), the sparse
                 direct solve, the super-blocks A11, A22, A12, A21 and the
                 block-diagonal / block-triangular preconditioners of Sec. 5;
+* ``qpair``     the paper's own element pair: Q2 velocity / discontinuous P1 pressure on
+                squares and a Q1 solid, with C_f through the inverse bilinear map;
 * ``gmres``     restarted right-preconditioned GMRES (Sec. 6 stopping rule);
 * ``step``      one semi-implicit backward-Euler step of Problem 3 and a time loop.
 

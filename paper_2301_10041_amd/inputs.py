@@ -88,6 +88,23 @@ def bar_mesh(nx: int, ny: int, x0=0.0, x1=0.4, y0=0.45, y1=0.55):
     return xy, np.asarray(tris, dtype=np.int32)
 
 
+def quad_bar(nx: int, ny: int, x0=0.3, x1=0.7, y0=0.45, y1=0.55):
+    """Q1 mesh of the rectangle [x0, x1] x [y0, y1]: nx x ny rectangular cells, node (i, j) at
+    index j (nx + 1) + i, quadrilateral (i, j), (i + 1, j), (i + 1, j + 1), (i, j + 1)
+    (counter-clockwise) with index j nx + i.  Returns ``(xy, quad)``: float64 [Ns, 2] and
+    int32 [Nq, 4]."""
+    xs = x0 + (x1 - x0) * np.arange(nx + 1) / nx
+    ys = y0 + (y1 - y0) * np.arange(ny + 1) / ny
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    quads = []
+    for j in range(ny):
+        for i in range(nx):
+            a = j * (nx + 1) + i
+            quads.append((a, a + 1, a + nx + 2, a + nx + 1))
+    return xy, np.asarray(quads, dtype=np.int32)
+
+
 def bent(xy: np.ndarray, amp: float, length: float = 0.4, x0: float = 0.0) -> np.ndarray:
     """A released position of the bar: every point moved down by amp ((s_x - x0) / length)^2 (a
     bending that leaves the left end in place)."""
@@ -198,6 +215,49 @@ WORKLOADS = {
 # wall), released from a bent position with u^0 = 0
 WORKLOADS["bar256"] = Workload("bar256", 256, [Bar(m=0, center=(0.25, 0.5), nx=102, ny=26, x0=0.05)], nu=0.2,
                                rho=1.0, kappa=1.333, dt=0.002, seed=5)
+
+
+@dataclass
+class QWorkload:
+    """A workload of the paper's own element pair (Sec. 4: Q2 velocity, discontinuous P1
+    pressure, Q1 solid): an n x n fluid grid and one bar [x0, x1] x [y0, y1] with nx x ny
+    quadrilaterals."""
+    name: str
+    n: int
+    nx: int
+    ny: int
+    x0: float = 0.3
+    x1: float = 0.7
+    y0: float = 0.45
+    y1: float = 0.55
+    nu: float = 1.0
+    rho: float = 1.0
+    kappa: float = 10.0
+    dt: float = 0.01
+    seed: int = 0
+
+    def solid_mesh(self):
+        return quad_bar(self.nx, self.ny, self.x0, self.x1, self.y0, self.y1)
+
+    @property
+    def center(self):
+        return (0.5 * (self.x0 + self.x1), 0.5 * (self.y0 + self.y1))
+
+    def sizes(self):
+        n = self.n
+        ns = (self.nx + 1) * (self.ny + 1)
+        n2 = (2 * n + 1) ** 2
+        np_ = 3 * n * n
+        return dict(N2=n2, Np=np_, Ns=ns, Nt=self.nx * self.ny, N=2 * n2 + np_ + 4 * ns)
+
+
+# the paper's element pair on the bar of the nonlinear test: 0.4 x 0.1 with quadrilaterals of
+# the fluid cell size, nu = 0.2, dt = 0.002 (Sec. 6.2), the linear law kappa = 10; qbar32 the
+# parity case, qbar256 the measured one (102 x 26 quadrilaterals)
+QWORKLOADS = {
+    "qbar32": QWorkload("qbar32", 32, 13, 3, nu=0.2, dt=0.002, seed=7),
+    "qbar256": QWorkload("qbar256", 256, 102, 26, nu=0.2, dt=0.002, seed=7),
+}
 
 
 def small_workload(n: int, m: int, center=(0.5, 0.5), radius=0.2, semi_axes=None,
