@@ -179,6 +179,34 @@ enum fsi_block {
  * FSI_E_HIP. */
 int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *hip_stream,
                size_t hbm_budget, fsi_ctx **out);
+
+/* The paper's own element pair (Sec. 4, the discrete spaces).  fsi_create_q2 makes a context
+ * of the Q2 / P1-disc fluid and the Q1 solid; every later call of this interface takes it
+ * except those that name the triangle pair's kernels (fsi_set_solid, fsi_set_smoother with
+ * FSI_SMOOTH_STENCIL, fsi_set_coupling_mode with FSI_COUPLING_INCREMENTAL,
+ * fsi_assemble_coupling_noalloc, fsi_step_batch, fsi_set_law with another law,
+ * fsi_solid_residual, fsi_solid_tangent, fsi_newton_step, inner modes other than
+ * FSI_INNER_MINRES), which return FSI_E_STATE.
+ *  - fluid: the n x n squares (no diagonal), Q2 velocity on the same node lattice as the P2
+ *    velocity (node (I,J) has index J(2n+1)+I); discontinuous P1 pressure with Np = 3 n^2
+ *    unknowns: on cell (i,j), k = j n + i, the unknowns 3k, 3k+1, 3k+2 are the coefficients
+ *    of 1, (x - x_c)/h, (y - y_c)/h (x_c, y_c the cell centre); pinned at unknown 0;
+ *    boundary conditions as for the triangle pair;
+ *  - solid: solid->tri holds 4 node indices per quadrilateral (counter-clockwise, strictly
+ *    convex) and n_tris counts the quadrilaterals; X and lam are bilinear on each (S_h = Lambda_h);
+ *  - C_f(X^n): each mapped quadrilateral X^n(E) (strictly convex and counter-clockwise, else
+ *    FSI_E_MESH) clipped against the cells of its bounding box; the integral over a piece by
+ *    the inverse of the bilinear map, on the fan of the piece with 4 x 4 conical Gauss points
+ *    per fan triangle (exact when X^n is affine on E); fsi_export_pairs gives (E, cell j n + i);
+ *  - the A11 preconditioner: the velocity V-cycle on the assembled Q2 operators (no
+ *    matrix-free form) and the diagonal Schur approximation nu / (M_p)_kk + (rho/dt) /
+ *    (B D^{-1} B^T)_kk, D the row sums of M_f.
+ * hbm_budget: checked against the device footprint after creation (0: none).
+ * Errors as for fsi_create; FSI_E_MESH also for a reference quadrilateral that is not
+ * strictly convex and counter-clockwise. */
+enum fsi_pair { FSI_PAIR_P2P1 = 0, FSI_PAIR_Q2P1DISC = 1 };
+int fsi_create_q2(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *hip_stream, size_t hbm_budget,
+                  fsi_ctx **out);
 void fsi_destroy(fsi_ctx *ctx);
 
 /* Replace the solid mesh of an existing context (fluid blocks and multigrid are kept).

@@ -156,8 +156,10 @@ def assemble_fluid(n, nu=1.0, rho=1.0, dt=0.01):
     Bxb = tfluid.zero_row(tfluid.mask_columns(Bx, bnd), 0)
     Byb = tfluid.zero_row(tfluid.mask_columns(By, bnd), 0)
     Bbc = sp.hstack([Bxb, Byb], format="csr")
+    # integrals of the pressure basis functions (h^2 for the constants, 0 for the slopes)
+    p_weights = np.tile([h * h, 0.0, 0.0], n * n)
     return dict(n=n, N2=N2, Np=Np, Mf=Mf, K=K, Bx=Bx, By=By, Mp=Mp, Af=Af, Af_blocks=blocks, Bbc=Bbc,
-                Bx_bc=Bxb, By_bc=Byb, bnd=bnd, nu=nu, rho=rho, dt=dt)
+                Bx_bc=Bxb, By_bc=Byb, bnd=bnd, nu=nu, rho=rho, dt=dt, p_weights=p_weights)
 
 
 def pressure_interpolant(n, f, fx, fy):

@@ -127,8 +127,8 @@ static int guarded(fsi_ctx *h, F &&f) {
 
 extern "C" {
 
-int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *hip_stream,
-               size_t hbm_budget, fsi_ctx **out) {
+static int create_ctx(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *hip_stream, size_t hbm_budget,
+                      fsi_ctx **out, int pair) {
   if (!out) return FSI_E_ARG;
   *out = nullptr;
   fsi_ctx *h = nullptr;
@@ -140,20 +140,23 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
                 "solid mesh needs >= 3 nodes, >= 1 triangle and non-null arrays");
     FSI_REQUIRE(solid->kappa >= 0, FSI_E_ARG, "kappa must be >= 0");
     const int64_t n = fluid->n, ns = solid->n_nodes, nt = solid->n_tris;
-    if (hbm_budget) {
+    const bool quads = pair == FSI_PAIR_Q2P1DISC;
+    FSI_REQUIRE(!quads || ns >= 4, FSI_E_ARG, "a quadrilateral mesh needs >= 4 nodes");
+    if (hbm_budget && !quads) {
       size_t est = fsi::estimate_bytes(n, ns, nt);
       FSI_REQUIRE(est <= hbm_budget, FSI_E_NOMEM,
                   "estimated footprint " + std::to_string(est) + " B exceeds the budget");
     }
     h = new fsi_ctx();
     Ctx &c = h->c;
+    c.pair = pair;
     c.n = fluid->n;
     c.nu = fluid->nu;
     c.rho = fluid->rho;
     c.dt = fluid->dt;
     c.kappa = solid->kappa;
     c.N2 = (2 * n + 1) * (2 * n + 1);
-    c.Np = (n + 1) * (n + 1);
+    c.Np = quads ? 3 * n * n : (n + 1) * (n + 1);
     c.Ns = ns;
     c.Nt = nt;
     c.N = 2 * c.N2 + c.Np + 4 * ns;
@@ -161,7 +164,7 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     c.budget = hbm_budget;
     FSI_HIP(hipGetDevice(&c.device));
     fsi::coupling_scratch_init(c.device);
-    c.h_tri.assign(solid->tri, solid->tri + 3 * nt);
+    c.h_tri.assign(solid->tri, solid->tri + (quads ? 4 : 3) * nt);
     c.h_xy.assign(solid->xy, solid->xy + 2 * ns);
     FSI_HIP(hipHostMalloc((void **)&c.hpin, 4096 * sizeof(double), hipHostMallocDefault));
     FSI_HIP(hipStreamCreateWithFlags(&c.aux_stream, hipStreamNonBlocking));
@@ -169,9 +172,14 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
     FSI_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
     for (hipEvent_t &e : c.ev_ms) FSI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     fsi::build_solid(c);
-    fsi::build_fluid(c);
-    fsi::build_multigrid(c);
-    c.mgu.stencil = c.mgp.stencil = true;
+    if (quads) {   // the assembled operators only: the matrix-free kernels are the triangle pair's
+      fsi::build_fluid_q2(c);
+      fsi::build_multigrid_q2(c);
+    } else {
+      fsi::build_fluid(c);
+      fsi::build_multigrid(c);
+      c.mgu.stencil = c.mgp.stencil = true;
+    }
     // graphs keep the preconditioner on one stream (the pressure chain no longer beside the
     // velocity cycle) and check convergence every second MINRES step: with the coarse ends of
     // both cycles in one launch each they measured slower than the two streams at every size
@@ -198,6 +206,16 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
   return FSI_OK;
 }
 
+int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *hip_stream,
+               size_t hbm_budget, fsi_ctx **out) {
+  return create_ctx(fluid, solid, hip_stream, hbm_budget, out, FSI_PAIR_P2P1);
+}
+
+int fsi_create_q2(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *hip_stream, size_t hbm_budget,
+                  fsi_ctx **out) {
+  return create_ctx(fluid, solid, hip_stream, hbm_budget, out, FSI_PAIR_Q2P1DISC);
+}
+
 void fsi_destroy(fsi_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->c.stream);
@@ -207,6 +225,7 @@ void fsi_destroy(fsi_ctx *ctx) {
 int fsi_set_solid(fsi_ctx *ctx, const fsi_solid_desc *solid) {
   if (!ctx) return FSI_E_ARG;
   return guarded(ctx, [&] {
+    FSI_REQUIRE(ctx->c.pair == FSI_PAIR_P2P1, FSI_E_STATE, "fsi_set_solid takes the triangle pair only");
     FSI_REQUIRE(solid && solid->n_nodes >= 3 && solid->n_tris >= 1 && solid->xy && solid->tri,
                 FSI_E_ARG, "solid mesh needs >= 3 nodes, >= 1 triangle and non-null arrays");
     FSI_REQUIRE(solid->kappa >= 0, FSI_E_ARG, "kappa must be >= 0");
@@ -236,6 +255,8 @@ int fsi_set_smoother(fsi_ctx *ctx, int kind) {
   if (!ctx) return FSI_E_ARG;
   if (kind != FSI_SMOOTH_CSR && kind != FSI_SMOOTH_STENCIL) return FSI_E_ARG;
   return guarded(ctx, [&] {
+    FSI_REQUIRE(ctx->c.pair == FSI_PAIR_P2P1 || kind == FSI_SMOOTH_CSR, FSI_E_STATE,
+                "the matrix-free smoother takes the triangle pair only");
     FSI_HIP(hipStreamSynchronize(ctx->c.stream));   // captured graphs may still be running
     ctx->c.drop_graphs();
     ctx->c.mgu.stencil = ctx->c.mgp.stencil = kind == FSI_SMOOTH_STENCIL;
@@ -304,6 +325,8 @@ int fsi_set_coupling_mode(fsi_ctx *ctx, int mode) {
   if (mode != FSI_COUPLING_FULL && mode != FSI_COUPLING_INCREMENTAL) return FSI_E_ARG;
   return guarded(ctx, [&] {
     Ctx &c = ctx->c;
+    FSI_REQUIRE(c.pair == FSI_PAIR_P2P1 || mode == FSI_COUPLING_FULL, FSI_E_STATE,
+                "the time-coherent coupling assembly takes the triangle pair only");
     if (c.cf_mode != mode) c.inc_valid = false;
     c.cf_mode = mode;
   });
@@ -323,6 +346,7 @@ int fsi_get_coupling_counts(const fsi_ctx *ctx, fsi_coupling_counts *out) {
 int fsi_assemble_coupling_noalloc(fsi_ctx *ctx, const double *Xn, fsi_coupling_info *info) {
   if (!ctx) return FSI_E_ARG;
   return guarded(ctx, [&] {
+    FSI_REQUIRE(ctx->c.pair == FSI_PAIR_P2P1, FSI_E_STATE, "the allocation-free coupling assembly takes the triangle pair only");
     FSI_REQUIRE(Xn, FSI_E_ARG, "null X^n");
     fsi::assemble_coupling_noalloc(ctx->c, Xn);
     if (info) {
@@ -372,6 +396,10 @@ int fsi_set_inner(fsi_ctx *ctx, double inner_rtol, int32_t inner_maxit) {
 int fsi_set_inner_mode(fsi_ctx *ctx, int32_t mode, int32_t cycles) {
   if (!ctx) return FSI_E_ARG;
   if (mode < FSI_INNER_MINRES || mode > FSI_INNER_GMRES || cycles < 0 || cycles > 100) return FSI_E_ARG;
+  if (ctx->c.pair != FSI_PAIR_P2P1 && mode != FSI_INNER_MINRES) {
+    ctx->c.last_error = "inner modes other than MINRES take the triangle pair only";
+    return FSI_E_STATE;
+  }
   ctx->c.inner_mode = mode;
   ctx->c.inner_cycles = cycles > 0 ? cycles : 1;
   return FSI_OK;
@@ -444,6 +472,7 @@ int fsi_step_batch(int32_t K, fsi_ctx *const *ctxs, const fsi_solve_opts *opts, 
     for (int k = 0; k < K; ++k) {
       FSI_REQUIRE(ctxs[k] && u_n[k] && X_n[k] && state[k], FSI_E_ARG, "null context or vector in the batch");
       cs[k] = &ctxs[k]->c;
+      FSI_REQUIRE(cs[k]->pair == FSI_PAIR_P2P1, FSI_E_STATE, "fsi_step_batch takes the triangle pair only");
       for (int q = 0; q < k; ++q) FSI_REQUIRE(cs[q] != cs[k], FSI_E_ARG, "a context appears twice in the batch");
       const Ctx &a = *cs[0], &b = *cs[k];
       FSI_REQUIRE(a.n == b.n && a.nu == b.nu && a.rho == b.rho && a.dt == b.dt, FSI_E_ARG,
@@ -498,6 +527,8 @@ int fsi_set_law(fsi_ctx *ctx, int law, double gamma, double eta) {
   if (!ctx) return FSI_E_ARG;
   return guarded(ctx, [&] {
     FSI_REQUIRE(law == FSI_LAW_LINEAR || law == FSI_LAW_EXP, FSI_E_ARG, "unknown solid law");
+    FSI_REQUIRE(ctx->c.pair == FSI_PAIR_P2P1 || law == FSI_LAW_LINEAR, FSI_E_STATE,
+                "the nonlinear solid takes the triangle pair only");
     if (law == FSI_LAW_EXP)
       FSI_REQUIRE(gamma > 0.0 && eta >= 0.0 && std::isfinite(gamma) && std::isfinite(eta), FSI_E_ARG,
                   "the exponential law needs gamma > 0 and eta >= 0");
@@ -510,6 +541,7 @@ int fsi_set_law(fsi_ctx *ctx, int law, double gamma, double eta) {
 int fsi_solid_residual(fsi_ctx *ctx, const double *X, double *R) {
   if (!ctx) return FSI_E_ARG;
   return guarded(ctx, [&] {
+    FSI_REQUIRE(ctx->c.pair == FSI_PAIR_P2P1, FSI_E_STATE, "the nonlinear solid takes the triangle pair only");
     FSI_REQUIRE(X && R && X != R, FSI_E_ARG, "null or aliased vectors");
     fsi::solid_law(ctx->c, X, R, false);
   });
@@ -518,6 +550,7 @@ int fsi_solid_residual(fsi_ctx *ctx, const double *X, double *R) {
 int fsi_solid_tangent(fsi_ctx *ctx, const double *X) {
   if (!ctx) return FSI_E_ARG;
   return guarded(ctx, [&] {
+    FSI_REQUIRE(ctx->c.pair == FSI_PAIR_P2P1, FSI_E_STATE, "the nonlinear solid takes the triangle pair only");
     if (!X) {
       ctx->c.use_kt = false;
       return;
@@ -530,6 +563,7 @@ int fsi_newton_step(fsi_ctx *ctx, const fsi_solve_opts *opts, const fsi_newton_o
                     const double *X_n, const double *f_X, double *state, fsi_newton_stats *stats) {
   if (!ctx) return FSI_E_ARG;
   return guarded(ctx, [&] {
+    FSI_REQUIRE(ctx->c.pair == FSI_PAIR_P2P1, FSI_E_STATE, "the nonlinear solid takes the triangle pair only");
     FSI_REQUIRE(opts && nopts && u_n && X_n && state, FSI_E_ARG, "null options or vectors");
     fsi_newton_stats st{};
     int rc = FSI_OK;

@@ -646,6 +646,60 @@ __global__ void k_asm_solid(int64_t ns, const int *__restrict__ n2e_ptr, const i
   }
 }
 
+// Q1: row l gathers over the quadrilaterals around node l (sorted by element id) kappa
+// (grad N_a, grad N_b) and (N_a, N_b) by the 2 x 2 Gauss rule in (xi, eta) on the bilinear map
+// of the reference element (exact on parallelograms).
+__global__ void k_asm_q1(int64_t ns, const int *__restrict__ n2e_ptr, const int *__restrict__ n2e,
+                         const int *__restrict__ quad, const double *__restrict__ xy, const int *__restrict__ rowptr,
+                         const int *__restrict__ col, double kappa, double *As, double *Cs) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= ns) return;
+  const int r0 = rowptr[l], r1 = rowptr[l + 1];
+  for (int k = r0; k < r1; ++k) { As[k] = 0.0; Cs[k] = 0.0; }
+  const double g[2] = {0.5 - 0.5 / 1.7320508075688772, 0.5 + 0.5 / 1.7320508075688772};
+  for (int q = n2e_ptr[l]; q < n2e_ptr[l + 1]; ++q) {
+    const int e = n2e[q] >> 2, a = n2e[q] & 3;
+    int v[4];
+    double x[4], y[4];
+    for (int m = 0; m < 4; ++m) {
+      v[m] = quad[4 * e + m];
+      x[m] = xy[v[m]];
+      y[m] = xy[ns + v[m]];
+    }
+    double ka[4] = {0, 0, 0, 0}, ma[4] = {0, 0, 0, 0};
+    for (int pq = 0; pq < 4; ++pq) {
+      const double xi = g[pq & 1], eta = g[pq >> 1];
+      const double N[4] = {(1 - xi) * (1 - eta), xi * (1 - eta), xi * eta, (1 - xi) * eta};
+      const double Nx[4] = {-(1 - eta), 1 - eta, eta, -eta};
+      const double Ne[4] = {-(1 - xi), -xi, xi, 1 - xi};
+      double j00 = 0, j01 = 0, j10 = 0, j11 = 0;
+      for (int m = 0; m < 4; ++m) {
+        j00 += Nx[m] * x[m];
+        j01 += Ne[m] * x[m];
+        j10 += Nx[m] * y[m];
+        j11 += Ne[m] * y[m];
+      }
+      const double det = j00 * j11 - j01 * j10;
+      double gx[4], gy[4];
+      for (int m = 0; m < 4; ++m) {
+        gx[m] = (j11 * Nx[m] - j10 * Ne[m]) / det;
+        gy[m] = (j00 * Ne[m] - j01 * Nx[m]) / det;
+      }
+      const double wt = 0.25 * det;
+      for (int b = 0; b < 4; ++b) {
+        ka[b] += wt * (gx[a] * gx[b] + gy[a] * gy[b]);
+        ma[b] += wt * N[a] * N[b];
+      }
+    }
+    for (int b = 0; b < 4; ++b) {
+      int pos = r0;
+      while (pos < r1 && col[pos] != v[b]) ++pos;
+      As[pos] += kappa * ka[b];
+      Cs[pos] += ma[b];
+    }
+  }
+}
+
 // the transposed copy of the solid pattern and its two value arrays (one thread per row)
 __global__ void k_solid_ell(int64_t ns, int w, const int *rp, const int *col, const double *as, const double *cs,
                             int *ecol, double *eas, double *ecs) {
@@ -673,34 +727,50 @@ __global__ void k_diag_inv(int64_t nrows, const int *rowptr, const int *col, con
 void build_solid(Ctx &c) {
   hipStream_t s = c.stream;
   const int64_t ns = c.Ns, nt = c.Nt;
-  // reference areas (validated on the host: counter-clockwise, non-degenerate)
+  const bool quads = c.pair == FSI_PAIR_Q2P1DISC;
+  const int nv = quads ? 4 : 3;   // vertices per element
+  // reference areas (validated on the host: counter-clockwise, non-degenerate; a
+  // quadrilateral strictly convex)
   std::vector<double> area(nt);
   for (int64_t e = 0; e < nt; ++e) {
-    const int *t = &c.h_tri[3 * e];
-    for (int m = 0; m < 3; ++m)
-      FSI_REQUIRE(t[m] >= 0 && t[m] < ns, FSI_E_ARG, "solid triangle refers to a missing node");
-    double x0 = c.h_xy[t[0]], y0 = c.h_xy[ns + t[0]];
-    double x1 = c.h_xy[t[1]], y1 = c.h_xy[ns + t[1]];
-    double x2 = c.h_xy[t[2]], y2 = c.h_xy[ns + t[2]];
-    area[e] = 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
-    FSI_REQUIRE(area[e] > 0.0, FSI_E_MESH, "solid reference triangle " + std::to_string(e) +
-                                               " is degenerate or clockwise");
+    const int *t = &c.h_tri[nv * e];
+    for (int m = 0; m < nv; ++m)
+      FSI_REQUIRE(t[m] >= 0 && t[m] < ns, FSI_E_ARG, "solid element refers to a missing node");
+    double a = 0.0;
+    bool convex = true;
+    for (int m = 0; m < nv; ++m) {
+      const int p = t[(m + nv - 1) % nv], q = t[m], r = t[(m + 1) % nv];
+      a += c.h_xy[q] * c.h_xy[ns + r] - c.h_xy[r] * c.h_xy[ns + q];
+      const double cr = (c.h_xy[q] - c.h_xy[p]) * (c.h_xy[ns + r] - c.h_xy[ns + q]) -
+                        (c.h_xy[ns + q] - c.h_xy[ns + p]) * (c.h_xy[r] - c.h_xy[q]);
+      convex = convex && cr > 0.0;
+    }
+    area[e] = 0.5 * a;
+    if (!quads) {   // the triangle's area as the coupling uses it
+      double x0 = c.h_xy[t[0]], y0 = c.h_xy[ns + t[0]];
+      double x1 = c.h_xy[t[1]], y1 = c.h_xy[ns + t[1]];
+      double x2 = c.h_xy[t[2]], y2 = c.h_xy[ns + t[2]];
+      area[e] = 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
+      convex = area[e] > 0.0;
+    }
+    FSI_REQUIRE(area[e] > 0.0 && convex, FSI_E_MESH,
+                "solid reference element " + std::to_string(e) + " is degenerate, clockwise or not convex");
   }
   // node -> (element, local vertex), sorted by element
   std::vector<int> cnt(ns + 1, 0);
   for (int64_t e = 0; e < nt; ++e)
-    for (int m = 0; m < 3; ++m) cnt[c.h_tri[3 * e + m] + 1]++;
+    for (int m = 0; m < nv; ++m) cnt[c.h_tri[nv * e + m] + 1]++;
   for (int64_t l = 0; l < ns; ++l) cnt[l + 1] += cnt[l];
   std::vector<int> adj(cnt[ns]);
   std::vector<int> fillp(cnt.begin(), cnt.end() - 1);
   c.max_adj = 0;
   for (int64_t e = 0; e < nt; ++e)
-    for (int m = 0; m < 3; ++m) adj[fillp[c.h_tri[3 * e + m]]++] = (int)(4 * e + m);
+    for (int m = 0; m < nv; ++m) adj[fillp[c.h_tri[nv * e + m]]++] = (int)(4 * e + m);
   for (int64_t l = 0; l < ns; ++l) {
     c.max_adj = std::max(c.max_adj, cnt[l + 1] - cnt[l]);
-    FSI_REQUIRE(cnt[l + 1] > cnt[l], FSI_E_MESH, "solid node " + std::to_string(l) + " is in no triangle");
+    FSI_REQUIRE(cnt[l + 1] > cnt[l], FSI_E_MESH, "solid node " + std::to_string(l) + " is in no element");
   }
-  FSI_REQUIRE(4 * nt < (int64_t)INT32_MAX, FSI_E_ARG, "too many solid triangles");
+  FSI_REQUIRE(4 * nt < (int64_t)INT32_MAX, FSI_E_ARG, "too many solid elements");
   // pattern: sorted unique neighbours
   std::vector<int> rp(ns + 1, 0), cols;
   cols.reserve(7 * ns);
@@ -709,7 +779,7 @@ void build_solid(Ctx &c) {
     tmpn.clear();
     for (int q = cnt[l]; q < cnt[l + 1]; ++q) {
       int e = adj[q] >> 2;
-      for (int m = 0; m < 3; ++m) tmpn.push_back(c.h_tri[3 * e + m]);
+      for (int m = 0; m < nv; ++m) tmpn.push_back(c.h_tri[nv * e + m]);
     }
     std::sort(tmpn.begin(), tmpn.end());
     tmpn.erase(std::unique(tmpn.begin(), tmpn.end()), tmpn.end());
@@ -733,9 +803,13 @@ void build_solid(Ctx &c) {
   up(c.S.col, cols);
   c.S.val.reserve(cols.size());
   c.Cs.reserve(cols.size());
-  hipLaunchKernelGGL(k_asm_solid, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, c.n2e_ptr.p,
-                     c.n2e.p, c.tri.p, c.ref_xy.p, c.S.rowptr.p, c.S.col.p, c.kappa, c.S.val.p,
-                     c.Cs.p);
+  if (quads)
+    hipLaunchKernelGGL(k_asm_q1, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, c.n2e_ptr.p, c.n2e.p, c.tri.p,
+                       c.ref_xy.p, c.S.rowptr.p, c.S.col.p, c.kappa, c.S.val.p, c.Cs.p);
+  else
+    hipLaunchKernelGGL(k_asm_solid, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, c.n2e_ptr.p,
+                       c.n2e.p, c.tri.p, c.ref_xy.p, c.S.rowptr.p, c.S.col.p, c.kappa, c.S.val.p,
+                       c.Cs.p);
   c.Cs_dinv.reserve(ns);
   hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, c.S.rowptr.p,
                      c.S.col.p, c.Cs.p, c.Cs_dinv.p);
@@ -753,6 +827,30 @@ void build_solid(Ctx &c) {
   c.Cs_dinv32.reserve(ns);
   convert(c.Cs_dinv32.p, c.Cs_dinv.p, ns, s);
   FSI_HIP(hipStreamSynchronize(s));
+  if (quads) {
+    // Chebyshev interval of D^{-1} C_s: [1/4, 9/4] on rectangles (the tensor product of the 1D
+    // [1/2, 3/2]); the upper end raised to the Gershgorin bound max_l sum_m |C_lm| / C_ll where
+    // a mesh exceeds it
+    std::vector<double> hc(cols.size());
+    FSI_HIP(hipMemcpy(hc.data(), c.Cs.p, hc.size() * sizeof(double), hipMemcpyDeviceToHost));
+    double g = 0.0;
+    for (int64_t l = 0; l < ns; ++l) {
+      double d = 0.0, sum = 0.0;
+      for (int k = rp[l]; k < rp[l + 1]; ++k) {
+        sum += std::fabs(hc[k]);
+        if (cols[k] == l) d = hc[k];
+      }
+      FSI_REQUIRE(d > 0.0, FSI_E_MESH, "solid mass with a non-positive diagonal");
+      g = std::max(g, sum / d);
+    }
+    c.cs_lo = 0.25;
+    c.cs_hi = std::max(2.25, g);
+    c.cs_nsteps = 56;   // (1 - 1/3)/(1 + 1/3) = 1/2 per step on [1/4, 9/4]: 2^-56 < 1e-16
+  } else {
+    c.cs_lo = 0.5;
+    c.cs_hi = 2.0;
+    c.cs_nsteps = 36;
+  }
 }
 
 // ---------------------------------------------------------------- multigrid transfers
@@ -1120,6 +1218,380 @@ void build_multigrid(Ctx &c) {
   coarse_inverse(c.mgu, s);
   coarse_inverse(c.mgp, s);
   (void)tail_lds_limit();   // the LDS grant of the coarse-tail launch, outside any graph capture
+  FSI_HIP(hipStreamSynchronize(s));
+}
+
+// ================================================================ the paper's element pair
+// Q2 velocity / discontinuous P1 pressure on the n x n squares (Sec. 4, the discrete spaces).
+// The Q2 nodes are the P2 lattice: node (I, J) at (I h/2, J h/2); cell (i, j) holds the nodes
+// (2i + a, 2j + b), local index a + 3 b, with the tensor products of the quadratic Lagrange
+// polynomials at 0, 1/2, 1; the pressure unknowns of cell k = j n + i are 3k + {0, 1, 2},
+// the coefficients of 1, (x - x_c)/h, (y - y_c)/h.  Element integrals by the 3-point Gauss
+// rule in each direction, exact for these integrands (degree <= 4 in each variable).
+// Element table: M (9 x 9), K[alpha][beta] (4 x 9 x 9, nu eps(phi_j e_beta) : eps(phi_i
+// e_alpha) at [alpha][beta][i][j]), B[alpha][k] (2 x 3 x 9, int d_alpha phi_i psi_k), M_p
+// diagonal (3: the basis is orthogonal on a square).
+constexpr int QE_M = 0, QE_K = 81, QE_B = QE_K + 324, QE_MP = QE_B + 54, QE_SIZE = QE_MP + 3;
+
+static void q2_element_table(int n, double nu, std::vector<double> &out) {
+  const double h = 1.0 / n;
+  out.assign(QE_SIZE, 0.0);
+  const double g[3] = {0.5 - std::sqrt(15.0) / 10.0, 0.5, 0.5 + std::sqrt(15.0) / 10.0};
+  const double w[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  auto lag = [](double t, double *v, double *d) {
+    v[0] = 2.0 * (t - 0.5) * (t - 1.0);
+    v[1] = 4.0 * t * (1.0 - t);
+    v[2] = 2.0 * t * (t - 0.5);
+    d[0] = 4.0 * t - 3.0;
+    d[1] = 4.0 - 8.0 * t;
+    d[2] = 4.0 * t - 1.0;
+  };
+  for (int q = 0; q < 3; ++q)
+    for (int p = 0; p < 3; ++p) {
+      double vx[3], dx[3], vy[3], dy[3];
+      lag(g[p], vx, dx);
+      lag(g[q], vy, dy);
+      const double wt = w[p] * w[q] * h * h;
+      double phi[9], gx[9], gy[9];
+      for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) {
+          phi[a + 3 * b] = vx[a] * vy[b];
+          gx[a + 3 * b] = dx[a] * vy[b] / h;
+          gy[a + 3 * b] = vx[a] * dy[b] / h;
+        }
+      const double psi[3] = {1.0, g[p] - 0.5, g[q] - 0.5};
+      for (int i = 0; i < 9; ++i) {
+        const double gi[2] = {gx[i], gy[i]};
+        for (int j = 0; j < 9; ++j) {
+          const double gj[2] = {gx[j], gy[j]};
+          out[QE_M + 9 * i + j] += wt * phi[i] * phi[j];
+          // eps(phi_j e_b) : eps(phi_i e_a) = (delta_ab grad phi_j . grad phi_i + d_a phi_j d_b phi_i) / 2
+          const double dot = gi[0] * gj[0] + gi[1] * gj[1];
+          for (int al = 0; al < 2; ++al)
+            for (int be = 0; be < 2; ++be)
+              out[QE_K + ((al * 2 + be) * 9 + i) * 9 + j] +=
+                  wt * 0.5 * nu * ((al == be ? dot : 0.0) + gj[al] * gi[be]);
+        }
+        for (int k = 0; k < 3; ++k) {
+          out[QE_B + (0 * 3 + k) * 9 + i] += wt * gx[i] * psi[k];
+          out[QE_B + (1 * 3 + k) * 9 + i] += wt * gy[i] * psi[k];
+        }
+      }
+      for (int k = 0; k < 3; ++k) out[QE_MP + k] += wt * psi[k] * psi[k];
+    }
+}
+
+// cells [c0, c1] (one direction) whose closure holds lattice line I
+__device__ __forceinline__ void q2_cells_of(int I, int n, int &c0, int &c1) {
+  c0 = max(0, (I - 1) >> 1);
+  c1 = min(n - 1, I >> 1);
+}
+
+// Row of A_f (and M_f) at Q2 node (I, J): the nodes of the 1, 2 or 4 cells around it, in
+// ascending index; the cells' contributions summed j major, i minor.
+__global__ void k_asm_q2q2(int n, int pass, const double *__restrict__ E, double rdt, int *cnt, const int *rowptr,
+                           int *col, double *A, double *M) {
+  const int64_t L = 2 * n + 1;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= L * L) return;
+  const int I = (int)(row % L), J = (int)(row / L);
+  int i0, i1, j0, j1;
+  q2_cells_of(I, n, i0, i1);
+  q2_cells_of(J, n, j0, j1);
+  if (!pass) {
+    cnt[row] = (2 * (i1 - i0) + 3) * (2 * (j1 - j0) + 3);
+    return;
+  }
+  const bool rb = p2_boundary(I, J, n);
+  int k = rowptr[row];
+  for (int J2 = 2 * j0; J2 <= 2 * j1 + 2; ++J2)
+    for (int I2 = 2 * i0; I2 <= 2 * i1 + 2; ++I2) {
+      double m = 0.0, kk[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int cj = j0; cj <= j1; ++cj) {
+        const int b = J - 2 * cj, b2 = J2 - 2 * cj;
+        if (b2 < 0 || b2 > 2) continue;
+        for (int ci = i0; ci <= i1; ++ci) {
+          const int a = I - 2 * ci, a2 = I2 - 2 * ci;
+          if (a2 < 0 || a2 > 2) continue;
+          const int li = a + 3 * b, lj = a2 + 3 * b2;
+          m += E[QE_M + 9 * li + lj];
+          for (int q = 0; q < 4; ++q) kk[q] += E[QE_K + (q * 9 + li) * 9 + lj];
+        }
+      }
+      col[k] = (int)(J2 * L + I2);
+      double *v = A + 4 * (int64_t)k;
+      if (rb || p2_boundary(I2, J2, n)) {
+        const double d = (I2 == I && J2 == J) ? 1.0 : 0.0;
+        v[0] = d; v[1] = 0.0; v[2] = 0.0; v[3] = d;
+      } else {
+        v[0] = rdt * m + kk[0]; v[1] = kk[1]; v[2] = kk[2]; v[3] = rdt * m + kk[3];
+      }
+      if (M) M[k] = m;
+      ++k;
+    }
+}
+
+// Row of B at pressure unknown 3k + q: the 9 nodes of cell k (row 0 and boundary columns zero)
+__global__ void k_asm_qb(int n, int pass, const double *__restrict__ E, int *cnt, const int *rowptr, int *col,
+                         double *V) {
+  const int64_t np = 3 * (int64_t)n * n;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= np) return;
+  if (!pass) {
+    cnt[row] = 9;
+    return;
+  }
+  const int64_t cell = row / 3, L = 2 * n + 1;
+  const int q = (int)(row % 3), i = (int)(cell % n), j = (int)(cell / n);
+  int k = rowptr[row];
+  for (int b = 0; b < 3; ++b)
+    for (int a = 0; a < 3; ++a, ++k) {
+      const int I = 2 * i + a, J = 2 * j + b;
+      const bool zero = row == 0 || p2_boundary(I, J, n);
+      col[k] = (int)(J * L + I);
+      V[2 * (int64_t)k] = zero ? 0.0 : E[QE_B + (0 * 3 + q) * 9 + a + 3 * b];
+      V[2 * (int64_t)k + 1] = zero ? 0.0 : E[QE_B + (1 * 3 + q) * 9 + a + 3 * b];
+    }
+}
+
+// Row of B^T at Q2 node (I, J): the pressure unknowns of the cells around it (boundary rows
+// and column 0 zero)
+__global__ void k_asm_qbt(int n, int pass, const double *__restrict__ E, int *cnt, const int *rowptr, int *col,
+                          double *V) {
+  const int64_t L = 2 * n + 1;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= L * L) return;
+  const int I = (int)(row % L), J = (int)(row / L);
+  int i0, i1, j0, j1;
+  q2_cells_of(I, n, i0, i1);
+  q2_cells_of(J, n, j0, j1);
+  if (!pass) {
+    cnt[row] = 3 * (i1 - i0 + 1) * (j1 - j0 + 1);
+    return;
+  }
+  const bool rb = p2_boundary(I, J, n);
+  int k = rowptr[row];
+  for (int cj = j0; cj <= j1; ++cj)
+    for (int ci = i0; ci <= i1; ++ci) {
+      const int64_t cell = (int64_t)cj * n + ci;
+      const int loc = (I - 2 * ci) + 3 * (J - 2 * cj);
+      for (int q = 0; q < 3; ++q, ++k) {
+        const int64_t pc = 3 * cell + q;
+        const bool zero = rb || pc == 0;
+        col[k] = (int)pc;
+        V[2 * (int64_t)k] = zero ? 0.0 : E[QE_B + (0 * 3 + q) * 9 + loc];
+        V[2 * (int64_t)k + 1] = zero ? 0.0 : E[QE_B + (1 * 3 + q) * 9 + loc];
+      }
+    }
+}
+
+// M_p of the discontinuous pressure: diagonal (one entry per row)
+__global__ void k_asm_qmp(int n, int pass, const double *__restrict__ E, int *cnt, const int *rowptr, int *col,
+                          double *V) {
+  const int64_t np = 3 * (int64_t)n * n;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= np) return;
+  if (!pass) {
+    cnt[row] = 1;
+    return;
+  }
+  const int k = rowptr[row];
+  col[k] = (int)row;
+  V[k] = E[QE_MP + row % 3];
+}
+
+// row sums (the lumped mass D of M_f)
+__global__ void k_row_sum(int64_t nrows, const int *rowptr, const double *v, double *d) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  double s = 0.0;
+  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) s += v[k];
+  d[r] = s;
+}
+
+// w_k = nu / (M_p)_kk + (rho/dt) / (B D^{-1} B^T)_kk (the second term left out where the row of B
+// is zero: the pinned unknown)
+__global__ void k_q_pres_weight(int64_t np, const int *brp, const int *bcol, const double *bval, const double *d,
+                                const double *mp, double nu, double rdt, double *w) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= np) return;
+  double l = 0.0;
+  for (int k = brp[r]; k < brp[r + 1]; ++k) {
+    const double bx = bval[2 * (int64_t)k], by = bval[2 * (int64_t)k + 1];
+    l += (bx * bx + by * by) / d[bcol[k]];
+  }
+  w[r] = nu / mp[r] + (l > 0.0 ? rdt / l : 0.0);
+}
+
+static void assemble_q2q2(Csr &A, DevBuf<double> *M, int n, const double *dE, double rdt, DevBuf<int> &tmp,
+                          hipStream_t s) {
+  const int64_t rows = (int64_t)(2 * n + 1) * (2 * n + 1);
+  const unsigned g = grid_for(rows, 256);
+  build_rows(A, rows, rows, 4, s, tmp,
+             [&](int pass, int *cnt, const int *rp, int *col, double *v, double *m) {
+               hipLaunchKernelGGL(k_asm_q2q2, dim3(g), dim3(256), 0, s, n, pass, dE, rdt, cnt, rp, col, v, m);
+             },
+             M != nullptr, M);
+}
+
+static DevBuf<double> upload_q2_table(int n, double nu, hipStream_t s) {
+  std::vector<double> hE;
+  q2_element_table(n, nu, hE);
+  DevBuf<double> dE(hE.size());
+  FSI_HIP(hipMemcpyAsync(dE.p, hE.data(), hE.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  FSI_HIP(hipStreamSynchronize(s));
+  return dE;
+}
+
+void build_fluid_q2(Ctx &c) {
+  hipStream_t s = c.stream;
+  const int n = c.n;
+  DevBuf<double> dE = upload_q2_table(n, c.nu, s);
+  DevBuf<int> tmp;
+  assemble_q2q2(c.Af, &c.Mf, n, dE.p, c.rho / c.dt, tmp, s);
+  const int64_t np = 3 * (int64_t)n * n, n2 = (int64_t)(2 * n + 1) * (2 * n + 1);
+  const unsigned gp = grid_for(np, 256), g2 = grid_for(n2, 256);
+  build_rows(c.B, np, n2, 2, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+    hipLaunchKernelGGL(k_asm_qb, dim3(gp), dim3(256), 0, s, n, pass, dE.p, cnt, rp, col, v);
+  });
+  build_rows(c.BT, n2, np, 2, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+    hipLaunchKernelGGL(k_asm_qbt, dim3(g2), dim3(256), 0, s, n, pass, dE.p, cnt, rp, col, v);
+  });
+  build_rows(c.Mp, np, np, 1, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+    hipLaunchKernelGGL(k_asm_qmp, dim3(gp), dim3(256), 0, s, n, pass, dE.p, cnt, rp, col, v);
+  });
+  c.Mp_dinv.alloc(np);
+  hipLaunchKernelGGL(k_diag_inv, dim3(gp), dim3(256), 0, s, np, c.Mp.rowptr.p, c.Mp.col.p, c.Mp.val.p,
+                     c.Mp_dinv.p);
+  DevBuf<double> d(n2);
+  hipLaunchKernelGGL(k_row_sum, dim3(g2), dim3(256), 0, s, n2, c.Af.rowptr.p, c.Mf.p, d.p);
+  c.qp_w.alloc(np);
+  hipLaunchKernelGGL(k_q_pres_weight, dim3(gp), dim3(256), 0, s, np, c.B.rowptr.p, c.B.col.p, c.B.val.p, d.p,
+                     c.Mp.val.p, c.nu, c.rho / c.dt, c.qp_w.p);
+  c.qp_w32.alloc(np);
+  convert(c.qp_w32.p, c.qp_w.p, np, s);
+  c.bnd.alloc(n2);
+  hipLaunchKernelGGL(k_p2_boundary_flags, dim3(g2), dim3(256), 0, s, n, c.bnd.p);
+  FSI_CHECK_LAUNCH();
+  FSI_HIP(hipStreamSynchronize(s));
+}
+
+// Coarse Q2 weights at fine lattice node (I, J) of an nf grid: the coarse cell's biquadratic
+// basis at the fine node (local coordinates multiples of 1/4: exact binary fractions), interior
+// coarse nodes only, in ascending coarse index.
+__device__ int q2_prolong_row(int I, int J, int nf, int *cidx, double *w) {
+  const int nc = nf / 2;
+  const int64_t Lc = 2 * nc + 1;
+  const int ci = min(I / 4, nc - 1), cj = min(J / 4, nc - 1);
+  const double xi = (I - 4 * ci) * 0.25, eta = (J - 4 * cj) * 0.25;
+  const double lx[3] = {2.0 * (xi - 0.5) * (xi - 1.0), 4.0 * xi * (1.0 - xi), 2.0 * xi * (xi - 0.5)};
+  const double ly[3] = {2.0 * (eta - 0.5) * (eta - 1.0), 4.0 * eta * (1.0 - eta), 2.0 * eta * (eta - 0.5)};
+  int cnt = 0;
+  for (int b = 0; b < 3; ++b)
+    for (int a = 0; a < 3; ++a) {
+      const double wt = lx[a] * ly[b];
+      if (wt == 0.0) continue;
+      const int Ic = 2 * ci + a, Jc = 2 * cj + b;
+      if (p2_boundary(Ic, Jc, nc)) continue;
+      cidx[cnt] = (int)(Jc * Lc + Ic);
+      w[cnt] = wt;
+      ++cnt;
+    }
+  return cnt;
+}
+
+__global__ void k_q2_prolong(int nf, int pass, int *cnt, const int *rowptr, int *col, double *V) {
+  const int64_t L = 2 * nf + 1;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= L * L) return;
+  const int I = (int)(row % L), J = (int)(row / L);
+  int ci[9];
+  double w[9];
+  const int m = p2_boundary(I, J, nf) ? 0 : q2_prolong_row(I, J, nf, ci, w);
+  if (!pass) {
+    cnt[row] = m;
+    return;
+  }
+  const int k = rowptr[row];
+  for (int q = 0; q < m; ++q) {
+    col[k + q] = ci[q];
+    V[k + q] = w[q];
+  }
+}
+
+__global__ void k_q2_restrict(int nf, int pass, int *cnt, const int *rowptr, int *col, double *V) {
+  const int nc = nf / 2;
+  const int64_t Lc = 2 * nc + 1, L = 2 * nf + 1;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= Lc * Lc) return;
+  const int Ic = (int)(row % Lc), Jc = (int)(row / Lc);
+  int k = pass ? rowptr[row] : 0, c = 0;
+  if (!p2_boundary(Ic, Jc, nc)) {
+    for (int J = 2 * Jc - 4; J <= 2 * Jc + 4; ++J)
+      for (int I = 2 * Ic - 4; I <= 2 * Ic + 4; ++I) {
+        if (I < 0 || J < 0 || I > 2 * nf || J > 2 * nf || p2_boundary(I, J, nf)) continue;
+        int ci[9];
+        double w[9];
+        const int m = q2_prolong_row(I, J, nf, ci, w);
+        for (int q = 0; q < m; ++q)
+          if (ci[q] == row) {
+            if (pass) {
+              col[k] = (int)((int64_t)J * L + I);
+              V[k] = w[q];
+              ++k;
+            }
+            ++c;
+          }
+      }
+  }
+  if (!pass) cnt[row] = c;
+}
+
+// The velocity hierarchy of the Q2 pair: A_f re-discretised on every level (the Galerkin
+// operator of the nested Q2 spaces), the biquadratic prolongation and its transpose, dense
+// inverse at the coarsest level; smoothing on the assembled operators (no matrix-free form).
+// The discontinuous pressure has no hierarchy: its Schur approximation is diagonal.
+void build_multigrid_q2(Ctx &c) {
+  hipStream_t s = c.stream;
+  DevBuf<int> tmp;
+  std::vector<int> ns;
+  for (int m = c.n;; m /= 2) {
+    ns.push_back(m);
+    if (m <= 4 || (m & 1)) break;
+  }
+  c.mgu.comps = 2;
+  c.mgu.degree = c.mgu.degree32 = 3;
+  c.mgu.stencil = false;
+  c.mgu.tail = false;
+  c.mgu.lv.resize(ns.size());
+  c.mgp.lv.clear();
+  c.mgp.stencil = false;
+  for (size_t l = 0; l < ns.size(); ++l) {
+    const int m = ns[l];
+    DevBuf<double> dE = upload_q2_table(m, c.nu, s);
+    MgLevel &U = c.mgu.lv[l];
+    U.n = m;
+    U.nodes = (int64_t)(2 * m + 1) * (2 * m + 1);
+    assemble_q2q2(U.A, nullptr, m, dE.p, c.rho / c.dt, tmp, s);
+    FSI_HIP(hipStreamSynchronize(s));
+    U.dinv.alloc(4 * U.nodes);
+    hipLaunchKernelGGL(k_block_diag_inv, dim3(grid_for(U.nodes, 256)), dim3(256), 0, s, U.nodes, 4, U.A.rowptr.p,
+                       U.A.col.p, U.A.val.p, U.dinv.p);
+    FSI_CHECK_LAUNCH();
+    U.lmax = 1.1 * power_lmax(U, 2, s);
+    if (l + 1 < ns.size()) {
+      const int64_t nc2 = (int64_t)(m + 1) * (m + 1);
+      const unsigned gf2 = grid_for(U.nodes, 256), gc2 = grid_for(nc2, 256);
+      build_rows(U.P, U.nodes, nc2, 1, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+        hipLaunchKernelGGL(k_q2_prolong, dim3(gf2), dim3(256), 0, s, m, pass, cnt, rp, col, v);
+      });
+      build_rows(U.R, nc2, U.nodes, 1, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+        hipLaunchKernelGGL(k_q2_restrict, dim3(gc2), dim3(256), 0, s, m, pass, cnt, rp, col, v);
+      });
+    }
+    for (int i = 0; i < 5; ++i) U.w64[i].alloc(2 * U.nodes);
+  }
+  coarse_inverse(c.mgu, s);
   FSI_HIP(hipStreamSynchronize(s));
 }
 

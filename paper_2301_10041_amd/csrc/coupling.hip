@@ -715,6 +715,9 @@ struct ArenaWork {
   }
 };
 
+template <typename Work>
+static void build_transpose(Ctx &c, Work &w, int nnz, bool keep_perm);
+
 // Rows of C_f from a piece list (e_piece: the first slot of each element; empty slots have
 // pair_T < 0), then C_f^T and the FP32 copies.  perm, when given, receives for every C_f^T
 // entry the index of its C_f entry (the time-coherent form refills C_f^T values with it).
@@ -762,6 +765,16 @@ static void build_rows(Ctx &c, Work &w, const int *e_piece, const int *pair_T, c
     hipLaunchKernelGGL(k_cf_rows_huge, dim3(1), dim3(kWave), 0, s, 1, n, c.n2e_ptr.p, c.n2e.p, e_piece, pair_T,
                        piece_L, nullptr, cf_rp, cf_col, cf_val, flag, huge, gflag, gval);
   FSI_CHECK_LAUNCH();
+  build_transpose(c, w, nnz, keep_perm);
+}
+
+// C_f^T of the rows in c.Cf (nnz entries) and the FP32 copies of both; perm as for build_rows.
+template <typename Work>
+static void build_transpose(Ctx &c, Work &w, int nnz, bool keep_perm) {
+  hipStream_t s = c.stream;
+  const int64_t ns = c.Ns;
+  const int *cf_rp = c.Cf.rowptr.p, *cf_col = c.Cf.col.p;
+  const double *cf_val = c.Cf.val.p;
   // C_f^T
   Csr &Ct = c.CfT;
   Ct.nrows = c.N2;
@@ -789,7 +802,7 @@ static void build_rows(Ctx &c, Work &w, const int *e_piece, const int *pair_T, c
   hipLaunchKernelGGL(k_rank_long, dim3(512), dim3(256), 0, s, ct_rp, tcol, tval, ct_col, ct_val, long_rows, tsrc,
                      perm);
   FSI_CHECK_LAUNCH();
-  float *cf32 = w.out(Cf.val32, nnz, "the FP32 copy of C_f");
+  float *cf32 = w.out(c.Cf.val32, nnz, "the FP32 copy of C_f");
   float *ct32 = w.out(Ct.val32, nnz, "the FP32 copy of C_f^T");
   convert(cf32, cf_val, nnz, s);
   convert(ct32, ct_val, nnz, s);
@@ -1083,12 +1096,324 @@ static void assemble_incremental(Ctx &c, const double *Xn) {
 }
 
 void assemble_coupling(Ctx &c, const double *Xn, bool) {
+  if (c.pair == FSI_PAIR_Q2P1DISC) {
+    assemble_coupling_q(c, Xn);
+    return;
+  }
   if (c.cf_mode == FSI_COUPLING_INCREMENTAL) {
     assemble_incremental(c, Xn);
     return;
   }
   GrowWork w{c};
   assemble(c, Xn, w);
+  c.pairs_kept = true;
+}
+
+// ================================================================ the paper's element pair
+// C_f of a Q1 solid against the Q2 fluid on squares (Sec. 4):
+//   (C_f)_lj = sum_E int_E N_l(s) phi_j(X^n(s)) ds.
+// X^n is bilinear on each reference quadrilateral E, so X^n(E) is the quadrilateral of the
+// mapped vertices (it must be strictly convex and counter-clockwise, and inside [0,1]^2).  It is
+// clipped against the cells of its bounding box with the arithmetic above (no diagonal) and a
+// piece is kept iff its fan area exceeds 5e-11 h^2.  On a piece q the change of variables
+// x = X^n(s) gives int_q N_l(xi(x)) phi_j(x) J_s(xi(x)) / J_X(xi(x)) dx, with xi(x) the
+// inverse of the bilinear map (Newton's method from the centre of the unit square) and J_s,
+// J_X the Jacobian determinants of the reference and the current map.  The rule: the fan of
+// q from its vertex 0 and on each fan triangle (A, B, C) the 4 x 4 conical Gauss-Legendre
+// points x = A + u (B - A) + u v (C - B), weight 2 |ABC| u w_u w_v: exact for polynomials of
+// degree <= 6, so exact whenever X^n is affine on E (the integrand is then of degree 2 + 4).
+//
+// Pipeline: per quadrilateral the count of kept pieces, a scan, per quadrilateral the pieces
+// (E, cell j n + i) and their 4 x 9 matrices, per solid node one wavefront walking the window
+// of lattice nodes its pieces cover (a lane per node, the pieces in a fixed order), and the
+// transpose of the triangle pair.
+struct GaussPts {
+  double u[4], w[4];   // Gauss-Legendre points and weights on [0, 1]
+};
+
+__device__ __forceinline__ void load_quad(const double *X, int64_t ns, const int *quad, int64_t e, Pt *P) {
+  for (int m = 0; m < 4; ++m) {
+    const int v = quad[4 * e + m];
+    P[m].x = X[v];
+    P[m].y = X[ns + v];
+  }
+}
+
+__device__ __forceinline__ bool quad_valid(const Pt *P) {
+  bool ok = true;
+  for (int k = 0; k < 4; ++k) {
+    const Pt a = P[(k + 3) & 3], b = P[k], c = P[(k + 1) & 3];
+    ok = ok && (b.x - a.x) * (c.y - b.y) - (b.y - a.y) * (c.x - b.x) > 0.0;
+    ok = ok && b.x >= 0.0 && b.x <= 1.0 && b.y >= 0.0 && b.y <= 1.0;
+  }
+  return ok;
+}
+
+__device__ __forceinline__ void quad_range(const Pt *P, int n, int &i0, int &i1, int &j0, int &j1) {
+  const double xmin = fmin(fmin(P[0].x, P[1].x), fmin(P[2].x, P[3].x));
+  const double xmax = fmax(fmax(P[0].x, P[1].x), fmax(P[2].x, P[3].x));
+  const double ymin = fmin(fmin(P[0].y, P[1].y), fmin(P[2].y, P[3].y));
+  const double ymax = fmax(fmax(P[0].y, P[1].y), fmax(P[2].y, P[3].y));
+  const double dn = (double)n;
+  i0 = min(max((int)floor(xmin * dn), 0), n - 1);
+  i1 = min(max((int)floor(xmax * dn), 0), n - 1);
+  j0 = min(max((int)floor(ymin * dn), 0), n - 1);
+  j1 = min(max((int)floor(ymax * dn), 0), n - 1);
+}
+
+// the piece of quadrilateral P in cell (i, j) into q; its vertex count, 0 when not kept
+__device__ __forceinline__ int quad_piece(const Pt *P, int n, int i, int j, Pt *q) {
+  Pt a[kMaxPoly], b[kMaxPoly];
+  const double dn = (double)n;
+  const double xi = (double)i / dn, xi1 = (double)(i + 1) / dn;
+  const double yj = (double)j / dn, yj1 = (double)(j + 1) / dn;
+  int m = clip_axis(P, 4, a, 0, xi, true);
+  m = clip_axis(a, m, b, 0, xi1, false);
+  m = clip_axis(b, m, a, 1, yj, true);
+  m = clip_axis(a, m, q, 1, yj1, false);
+  const double h = 1.0 / dn;
+  return (m >= 3 && fan_area(q, m) > 5e-11 * h * h) ? m : 0;
+}
+
+__global__ void k_q_count(int64_t nq, int64_t ns, int n, const double *__restrict__ X, const int *__restrict__ quad,
+                          int *cnt, int *flag) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nq) return;
+  Pt P[4], q[kMaxPoly];
+  load_quad(X, ns, quad, e, P);
+  if (!quad_valid(P)) {
+    atomicOr(flag, DF_MESH);
+    cnt[e] = 0;
+    return;
+  }
+  int i0, i1, j0, j1, c = 0;
+  quad_range(P, n, i0, i1, j0, j1);
+  for (int j = j0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i) c += quad_piece(P, n, i, j, q) ? 1 : 0;
+  cnt[e] = c;
+}
+
+// bilinear shape functions of the unit square at (xi, eta) and their derivatives
+__device__ __forceinline__ void q1_shape(double xi, double eta, double *N, double *Nx, double *Ne) {
+  N[0] = (1 - xi) * (1 - eta); N[1] = xi * (1 - eta); N[2] = xi * eta; N[3] = (1 - xi) * eta;
+  Nx[0] = -(1 - eta); Nx[1] = 1 - eta; Nx[2] = eta; Nx[3] = -eta;
+  Ne[0] = -(1 - xi); Ne[1] = -xi; Ne[2] = xi; Ne[3] = 1 - xi;
+}
+
+__device__ __forceinline__ double q1_jac(const Pt *P, const double *Nx, const double *Ne) {
+  double a = 0, b = 0, c = 0, d = 0;
+  for (int m = 0; m < 4; ++m) {
+    a += Nx[m] * P[m].x;
+    b += Ne[m] * P[m].x;
+    c += Nx[m] * P[m].y;
+    d += Ne[m] * P[m].y;
+  }
+  return a * d - b * c;
+}
+
+// (xi, eta) with X(xi, eta) = (x, y) on the bilinear map of P: Newton from (1/2, 1/2) until a
+// step below 1e-15 (at most 60 steps)
+__device__ __forceinline__ void q1_inverse(const Pt *P, double x, double y, double &xi, double &eta) {
+  xi = 0.5;
+  eta = 0.5;
+  for (int it = 0; it < 60; ++it) {
+    double N[4], Nx[4], Ne[4];
+    q1_shape(xi, eta, N, Nx, Ne);
+    double fx = -x, fy = -y, a = 0, b = 0, c = 0, d = 0;
+    for (int m = 0; m < 4; ++m) {
+      fx += N[m] * P[m].x;
+      fy += N[m] * P[m].y;
+      a += Nx[m] * P[m].x;
+      b += Ne[m] * P[m].x;
+      c += Nx[m] * P[m].y;
+      d += Ne[m] * P[m].y;
+    }
+    const double det = a * d - b * c;
+    const double dxi = (d * fx - b * fy) / det, deta = (a * fy - c * fx) / det;
+    xi -= dxi;
+    eta -= deta;
+    if (fmax(fabs(dxi), fabs(deta)) <= 1e-15) break;
+  }
+}
+
+__device__ __forceinline__ void lagrange2(double t, double *v) {
+  v[0] = 2.0 * (t - 0.5) * (t - 1.0);
+  v[1] = 4.0 * t * (1.0 - t);
+  v[2] = 2.0 * t * (t - 0.5);
+}
+
+// One thread per quadrilateral: its pieces in cell order and their matrices
+// L[a][b] = int_q N_a phi_b J_s / J_X (36 per piece, a major).
+__global__ void k_q_emit(int64_t nq, int64_t ns, int n, const double *__restrict__ X, const double *__restrict__ Xref,
+                         const int *__restrict__ quad, const int *__restrict__ e_piece, GaussPts g, int *pair_E,
+                         int *pair_T, double *piece_L) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nq) return;
+  Pt P[4], S[4], q[kMaxPoly];
+  load_quad(X, ns, quad, e, P);
+  load_quad(Xref, ns, quad, e, S);
+  if (!quad_valid(P)) return;
+  int i0, i1, j0, j1;
+  quad_range(P, n, i0, i1, j0, j1);
+  const double dn = (double)n;
+  int p = e_piece[e];
+  for (int j = j0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i) {
+      const int m = quad_piece(P, n, i, j, q);
+      if (!m) continue;
+      double L[36];
+      for (int k = 0; k < 36; ++k) L[k] = 0.0;
+      for (int t = 1; t < m - 1; ++t) {
+        const Pt A = q[0], B = q[t], C = q[t + 1];
+        const double two = (B.x - A.x) * (C.y - A.y) - (C.x - A.x) * (B.y - A.y);
+        for (int pu = 0; pu < 4; ++pu)
+          for (int pv = 0; pv < 4; ++pv) {
+            const double u = g.u[pu], v = g.u[pv];
+            const double x = A.x + u * (B.x - A.x) + u * v * (C.x - B.x);
+            const double y = A.y + u * (B.y - A.y) + u * v * (C.y - B.y);
+            double xi, eta;
+            q1_inverse(P, x, y, xi, eta);
+            double N[4], Nx[4], Ne[4];
+            q1_shape(xi, eta, N, Nx, Ne);
+            const double f = g.w[pu] * g.w[pv] * u * two * q1_jac(S, Nx, Ne) / q1_jac(P, Nx, Ne);
+            double vx[3], vy[3];
+            lagrange2(x * dn - i, vx);
+            lagrange2(y * dn - j, vy);
+            for (int a = 0; a < 4; ++a) {
+              const double fa = f * N[a];
+              for (int bb = 0; bb < 3; ++bb)
+                for (int ba = 0; ba < 3; ++ba) L[9 * a + ba + 3 * bb] += fa * vx[ba] * vy[bb];
+            }
+          }
+      }
+      pair_E[p] = (int)e;
+      pair_T[p] = j * n + i;
+      for (int k = 0; k < 36; ++k) piece_L[36 * (int64_t)p + k] = L[k];
+      ++p;
+    }
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Row l of C_f (one wavefront): the lattice nodes of the cells of its pieces, a lane per node
+// in ascending index; each node sums N_a-rows of the pieces of the quadrilaterals around l (in
+// element order, then piece order) whose cell holds it.  pass 0: row length; pass 1: entries
+// (Dirichlet columns kept with value 0).
+__global__ void __launch_bounds__(kWave) k_q_rows(int pass, int64_t ns, int n, const int *__restrict__ n2e_ptr,
+                                                  const int *__restrict__ n2e, const int *__restrict__ e_piece,
+                                                  const int *__restrict__ pair_T, const double *__restrict__ piece_L,
+                                                  int *cnt, const int *__restrict__ rowptr, int *col, double *val) {
+  const int64_t l = blockIdx.x;
+  if (l >= ns) return;
+  const int lane = threadIdx.x;
+  const int q0 = n2e_ptr[l], q1 = n2e_ptr[l + 1];
+  int imin = n, imax = -1, jmin = n, jmax = -1;
+  for (int q = q0; q < q1; ++q) {
+    const int e = n2e[q] >> 2;
+    for (int p = e_piece[e] + lane; p < e_piece[e + 1]; p += kWave) {
+      const int cell = pair_T[p], ci = cell % n, cj = cell / n;
+      imin = min(imin, ci);
+      imax = max(imax, ci);
+      jmin = min(jmin, cj);
+      jmax = max(jmax, cj);
+    }
+  }
+  imin = wave_min_i(imin);
+  jmin = wave_min_i(jmin);
+  imax = wave_max_i(imax);
+  jmax = wave_max_i(jmax);
+  int total = 0;
+  if (imax >= 0) {
+    const int I0 = 2 * imin, J0 = 2 * jmin, wx = 2 * (imax - imin) + 3, wn = wx * (2 * (jmax - jmin) + 3);
+    const int64_t L = 2 * n + 1;
+    const int base = pass ? rowptr[l] : 0;
+    for (int w0 = 0; w0 < wn; w0 += kWave) {
+      const int w = w0 + lane;
+      const int I = I0 + w % wx, J = J0 + w / wx;
+      bool hit = false;
+      double acc = 0.0;
+      if (w < wn)
+        for (int q = q0; q < q1; ++q) {
+          const int e = n2e[q] >> 2, a = n2e[q] & 3;
+          for (int p = e_piece[e]; p < e_piece[e + 1]; ++p) {
+            const int cell = pair_T[p];
+            const int da = I - 2 * (cell % n), db = J - 2 * (cell / n);
+            if (da < 0 || da > 2 || db < 0 || db > 2) continue;
+            hit = true;
+            if (pass) acc += piece_L[36 * (int64_t)p + 9 * a + da + 3 * db];
+          }
+        }
+      const unsigned long long mask = __ballot(hit);
+      if (pass && hit) {
+        const int pos = base + total + __popcll(mask & ((1ull << lane) - 1ull));
+        col[pos] = (int)(J * L + I);
+        val[pos] = (I == 0 || J == 0 || I == 2 * n || J == 2 * n) ? 0.0 : acc;
+      }
+      total += __popcll(mask);
+    }
+  }
+  if (!pass && lane == 0) cnt[l] = total;
+}
+
+// 4-point Gauss-Legendre rule on [0, 1] from its closed form: points 1/2 +- x/2 with
+// x = sqrt(3/7 -+ (2/7) sqrt(6/5)) and weights (18 +- sqrt(30)) / 72
+static GaussPts gauss4() {
+  const double a = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+  const double b = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+  const double wa = (18.0 + std::sqrt(30.0)) / 72.0, wb = (18.0 - std::sqrt(30.0)) / 72.0;
+  return GaussPts{{0.5 - 0.5 * b, 0.5 - 0.5 * a, 0.5 + 0.5 * a, 0.5 + 0.5 * b}, {wb, wa, wa, wb}};
+}
+
+void assemble_coupling_q(Ctx &c, const double *Xn) {
+  GrowWork w{c};
+  hipStream_t s = c.stream;
+  const int64_t nq = c.Nt, ns = c.Ns;
+  const int n = c.n;
+  c.have_cf = false;
+  c.pairs_kept = false;
+  c.inc_valid = false;
+  int *flag = w.flags();
+  int *e_piece = w.work(c.e_piece, nq + 1, "element piece offsets");
+  hipLaunchKernelGGL(k_q_count, dim3(grid_for(nq, 128)), dim3(128), 0, s, nq, ns, n, Xn, c.tri.p, e_piece, flag);
+  FSI_CHECK_LAUNCH();
+  scan_excl(e_piece, e_piece, nq, w.scan(nq), s);
+  const int f = read_int(flag, s);
+  if (f) fill(flag, 1, 0, s);
+  FSI_REQUIRE(!(f & DF_MESH), FSI_E_MESH,
+              "X^n maps a solid quadrilateral to one that is not strictly convex and counter-clockwise, or outside [0,1]^2");
+  const int npieces = read_int(e_piece + nq, s);
+  c.n_pairs = npieces;
+  c.n_cand = 0;
+  int *pair_E = w.work(c.pair_E, npieces, "piece list");
+  int *pair_T = w.work(c.pair_T, npieces, "piece list");
+  double *piece_L = w.work(c.piece_L, 36 * (int64_t)npieces, "piece matrices");
+  hipLaunchKernelGGL(k_q_emit, dim3(grid_for(nq, 64)), dim3(64), 0, s, nq, ns, n, Xn, c.ref_xy.p, c.tri.p, e_piece,
+                     gauss4(), pair_E, pair_T, piece_L);
+  FSI_CHECK_LAUNCH();
+  Csr &Cf = c.Cf;
+  Cf.nrows = ns;
+  Cf.ncols = c.N2;
+  Cf.width = 1;
+  int *cf_rp = w.out(Cf.rowptr, ns + 1, "the C_f row pointers");
+  hipLaunchKernelGGL(k_q_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 0, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece,
+                     pair_T, piece_L, cf_rp, nullptr, nullptr, nullptr);
+  FSI_CHECK_LAUNCH();
+  scan_excl(cf_rp, cf_rp, ns, w.scan(ns), s);
+  const int nnz = read_int(cf_rp + ns, s);
+  Cf.nnz = nnz;
+  int *cf_col = w.out(Cf.col, nnz, "C_f");
+  double *cf_val = w.out(Cf.val, nnz, "C_f");
+  hipLaunchKernelGGL(k_q_rows, dim3((unsigned)ns), dim3(kWave), 0, s, 1, ns, n, c.n2e_ptr.p, c.n2e.p, e_piece,
+                     pair_T, piece_L, nullptr, cf_rp, cf_col, cf_val);
+  FSI_CHECK_LAUNCH();
+  build_transpose(c, w, nnz, false);
   c.pairs_kept = true;
 }
 

@@ -64,6 +64,7 @@ struct Prof {
 
 struct Ctx {
   // problem
+  int pair = FSI_PAIR_P2P1;   // element pair (fsi_create / fsi_create_q2)
   int n = 0;
   int device = 0;          // HIP device of the context (current at fsi_create)
   double nu = 1, rho = 1, dt = 0.01, kappa = 10;
@@ -83,9 +84,13 @@ struct Ctx {
   DevBuf<unsigned char> mptab64, mptab32;  // P1Table<double/float> of M_p
   DevBuf<unsigned char> divtab64, divtab32;  // DivTable<double/float> (B and B^T)
   DevBuf<unsigned char> bnd;  // 1 on boundary P2 nodes
+  // the Q2 / P1-disc pair: the diagonal Schur approximation of its A11 preconditioner,
+  // nu / (M_p)_kk + (rho/dt) / (B D^{-1} B^T)_kk with D the row sums of M_f
+  DevBuf<double> qp_w;
+  DevBuf<float> qp_w32;
 
   // solid blocks
-  std::vector<int> h_tri;  // host copy of the connectivity
+  std::vector<int> h_tri;  // host copy of the connectivity (3 per triangle; 4 per quadrilateral of the Q pair)
   std::vector<double> h_xy;
   DevBuf<int> tri;         // 3 per triangle
   DevBuf<double> ref_xy;   // [x | y]
@@ -96,6 +101,10 @@ struct Ctx {
   DevBuf<double> Cs;       // C_s on the same pattern
   DevBuf<float> Cs32;
   DevBuf<double> Cs_dinv;  // 1 / diag(C_s)
+  // Chebyshev interval of D^{-1} C_s and the steps of the closed-form A22 solves: P1
+  // triangles [1/2, 2], 36 steps; Q1 quadrilaterals [1/4, 9/4] (or the Gershgorin bound), 56
+  double cs_lo = 0.5, cs_hi = 2.0;
+  int cs_nsteps = 36;
   DevBuf<float> Cs_dinv32;
   // the S pattern transposed for coalesced row-per-lane reads: entry u of row r at u Ns + r,
   // rows padded to s_ew entries (column r, value 0); A_s and C_s values in the same order
@@ -225,9 +234,12 @@ struct Ctx {
 void build_fluid(Ctx &c);
 void build_solid(Ctx &c);
 void build_multigrid(Ctx &c);
+void build_fluid_q2(Ctx &c);
+void build_multigrid_q2(Ctx &c);
 // coupling.hip
 void assemble_coupling(Ctx &c, const double *Xn, bool sync_check);
 void assemble_coupling_noalloc(Ctx &c, const double *Xn);
+void assemble_coupling_q(Ctx &c, const double *Xn);
 void reserve_coupling(Ctx &c);
 void coupling_scratch_init(int dev);
 // ops.hip (operator of eq. (matrix) and its pieces)

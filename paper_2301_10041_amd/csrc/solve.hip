@@ -110,6 +110,18 @@ __global__ void k_minres_update(T *wn, const T *v, const T *w1, const T *w2, T *
   }
 }
 
+// z = w r on the pressure unknowns in T, stored as TZ, except z[0] = r[0] rounded through T (the
+// pinned unknown); lane blockIdx.y at + lane ls
+template <typename TZ, typename T>
+__global__ void k_q_pres(TZ *z, const TZ *r, const T *w, int64_t np, int64_t ls) {
+  z += (int64_t)blockIdx.y * ls;
+  r += (int64_t)blockIdx.y * ls;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+    const T v = (T)r[i];
+    z[i] = (TZ)(i == 0 ? v : w[i] * v);
+  }
+}
+
 template <typename T>
 __global__ void k_set_pinned(T *z, const T *r, int64_t ls) {   // lane blockIdx.y at + lane ls
   if (threadIdx.x == 0 && blockIdx.x == 0) z[(int64_t)blockIdx.y * ls] = r[(int64_t)blockIdx.y * ls];
@@ -673,6 +685,21 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
   }
   if (part == PC_VEL) {
     FSI_CHECK_LAUNCH();
+    return;
+  }
+  if (c.pair == FSI_PAIR_Q2P1DISC) {   // the diagonal Schur approximation of the Q2 / P1-disc pair
+    FSI_REQUIRE(!dot.p, FSI_E_STATE, "the Q2 / P1-disc pair forms no tile sums");
+    const T *w = std::is_same<T, double>::value ? (const T *)c.qp_w.p : (const T *)c.qp_w32.p;
+    if (z64)
+      hipLaunchKernelGGL((k_q_pres<double, T>), dim3(vgrid(Np), 1), dim3(256), 0, sp, z64 + 2 * N2, r64 + 2 * N2, w,
+                         Np, nf);
+    else
+      hipLaunchKernelGGL((k_q_pres<T, T>), dim3(vgrid(Np), K), dim3(256), 0, sp, z + 2 * N2, r + 2 * N2, w, Np, nf);
+    FSI_CHECK_LAUNCH();
+    if (fork) {
+      FSI_HIP(hipEventRecord(c.ev_join, sp));
+      FSI_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
+    }
     return;
   }
   // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
@@ -1402,12 +1429,12 @@ static void a11_fixed_tri(Ctx &c, const double *const *r, double *const *z, int 
 // the harmful one, Sec. 7).  Measured at 1024^2 / 256^2 / 512^2: taking the solve only four
 // orders below the inner tolerance (12-13 steps) left every outer and inner step count
 // unchanged and saved 2% of the step; the exact form is kept.
-static int cs_steps(double) { return 36; }
+static int cs_steps(const Ctx &c) { return c.cs_nsteps; }
 
 static const double *cs_solve(Ctx &c, const double *b, double *scratch, int steps) {
   const int64_t ns = c.Ns;
   double *t = scratch, *t2 = t + 2 * ns, *d = t + 4 * ns;
-  return chebyshev<double, 1, 2>(ns, c.S.rowptr.p, c.S.col.p, c.Cs.p, c.Cs_dinv.p, 0.5, 2.0,
+  return chebyshev<double, 1, 2>(ns, c.S.rowptr.p, c.S.col.p, c.Cs.p, c.Cs_dinv.p, c.cs_lo, c.cs_hi,
                                  steps, b, t, t2, d, true, c.stream);
 }
 
@@ -1745,7 +1772,8 @@ void apply_precond_lanes(Ctx &c, Ctx *const *cs, int K, int pc, int prec, const 
   bool fit = true;
   int ns_max = 0;
   for (int k = 0; k < K; ++k) {
-    fit = fit && a22_fits(*cs[k]) && !cs[k]->use_kt;
+    fit = fit && a22_fits(*cs[k]) && !cs[k]->use_kt && cs[k]->cs_lo == cs[0]->cs_lo &&
+          cs[k]->cs_hi == cs[0]->cs_hi && cs[k]->cs_nsteps == cs[0]->cs_nsteps;
     ns_max = std::max(ns_max, (int)cs[k]->Ns);
   }
   A22Args aa{};
@@ -1766,12 +1794,12 @@ void apply_precond_lanes(Ctx &c, Ctx *const *cs, int K, int pc, int prec, const 
       aa.lane[k] = A22Lane{ck.S.rowptr.p, ck.s_ecol.p, ck.s_eas.p, ck.s_ecs.p, ck.Cs_dinv.p, rX, rl, zX, zl, (int)ns,
                            ck.dt};
     else
-      a22_solve(ck, rX, rl, zX, zl, cs_steps(tol));
+      a22_solve(ck, rX, rl, zX, zl, cs_steps(ck));
   }
   if (fit) {
-    aa.steps = cs_steps(tol);
-    aa.theta = 0.5 * (2.0 + 0.5);   // C_s interval [1/2, 2] (cs_solve)
-    aa.delta = 0.5 * (2.0 - 0.5);
+    aa.steps = cs_steps(*cs[0]);
+    aa.theta = 0.5 * (cs[0]->cs_hi + cs[0]->cs_lo);   // the C_s interval of cs_solve
+    aa.delta = 0.5 * (cs[0]->cs_hi - cs[0]->cs_lo);
     hipLaunchKernelGGL(k_a22_lanes, dim3(1, (unsigned)K), dim3(kA22Threads), (size_t)2 * ns_max * sizeof(double),
                        c.stream, aa);
     FSI_CHECK_LAUNCH();

@@ -102,6 +102,8 @@ _lib = None
 _SIGS = {
     "fsi_create": (C.c_int, [C.POINTER(FluidDesc), C.POINTER(SolidDesc), C.c_void_p, C.c_size_t,
                              C.POINTER(C.c_void_p)]),
+    "fsi_create_q2": (C.c_int, [C.POINTER(FluidDesc), C.POINTER(SolidDesc), C.c_void_p, C.c_size_t,
+                                C.POINTER(C.c_void_p)]),
     "fsi_destroy": (None, [C.c_void_p]),
     "fsi_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fsi_set_solid": (C.c_int, [C.c_void_p, C.POINTER(SolidDesc)]),
@@ -245,31 +247,46 @@ def step_batch(ctxs, u_n, X_n, states, opts: Opts | None = None):
     return [st[k].as_dict() for k in range(K)], [int(r) for r in rcs]
 
 
+# element pairs (fsi_pair)
+PAIR_P2P1, PAIR_Q2P1DISC = 0, 1
+
+
 class Context:
     """One fluid grid, one solid mesh and all device state of libfsi."""
 
-    def __init__(self, n, xy, tri, nu=1.0, rho=1.0, dt=0.01, kappa=10.0, stream=None, budget=0):
+    def __init__(self, n, xy, tri, nu=1.0, rho=1.0, dt=0.01, kappa=10.0, stream=None, budget=0, pair=PAIR_P2P1):
+        """``pair`` PAIR_P2P1: P2/P1 fluid, ``tri`` [Nt, 3] triangles; PAIR_Q2P1DISC: the paper's
+        Q2 / P1-disc fluid, ``tri`` [Nq, 4] quadrilaterals of the Q1 solid (fsi_create_q2)."""
         L = lib()
         xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64))
         if xy.ndim != 2 or xy.shape[1] != 2:
             raise ValueError("xy must be [Ns, 2]")
+        nv = 4 if pair == PAIR_Q2P1DISC else 3
         self._xy_soa = np.ascontiguousarray(np.concatenate([xy[:, 0], xy[:, 1]]))
         self._tri = np.ascontiguousarray(np.asarray(tri, dtype=np.int32).reshape(-1))
+        if self._tri.size % nv:
+            raise ValueError(f"the solid elements need {nv} nodes each")
         fd = FluidDesc(int(n), float(nu), float(rho), float(dt))
-        sd = SolidDesc(xy.shape[0], self._tri.size // 3,
+        sd = SolidDesc(xy.shape[0], self._tri.size // nv,
                        self._xy_soa.ctypes.data_as(C.POINTER(C.c_double)),
                        self._tri.ctypes.data_as(C.POINTER(C.c_int32)), float(kappa))
         h = C.c_void_p()
-        rc = L.fsi_create(C.byref(fd), C.byref(sd), _stream_handle(stream), int(budget), C.byref(h))
+        create = L.fsi_create_q2 if pair == PAIR_Q2P1DISC else L.fsi_create
+        rc = create(C.byref(fd), C.byref(sd), _stream_handle(stream), int(budget), C.byref(h))
         if rc != FSI_OK:
             raise FsiError(rc, L.fsi_last_error(None).decode())
         self._h = h
+        self.pair = pair
         self.n, self.nu, self.rho, self.dt, self.kappa = int(n), nu, rho, dt, kappa
         self.sizes = self._sizes()
 
     @classmethod
     def from_workload(cls, wl, **kw):
+        """A context of an ``inputs.Workload`` (triangle pair) or ``inputs.QWorkload`` (the paper's
+        Q2 / P1-disc pair with a Q1 solid)."""
         xy, tri = wl.solid_mesh()
+        if np.asarray(tri).shape[-1] == 4:
+            kw.setdefault("pair", PAIR_Q2P1DISC)
         return cls(wl.n, xy, tri, nu=wl.nu, rho=wl.rho, dt=wl.dt, kappa=wl.kappa, **kw)
 
     def close(self):

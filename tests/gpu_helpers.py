@@ -66,15 +66,16 @@ def small_workloads():
 
 def block_errors(S, x, x_ref):
     """Relative errors of x against x_ref (the oracle's) per block of the unknown vector and
-    over the whole vector: u (both components), p with its mean removed (weights: the row
-    sums of the P1 pressure mass, i.e. the integrals of the basis functions), X and lam (both
+    over the whole vector: u (both components), p with its mean removed (weights: the
+    integrals of the basis functions, the oracle's p_weights or else the row sums of the
+    pressure mass), X and lam (both
     components).  For each: 'l2' = ||x - x_ref||_2 / ||x_ref||_2 and 'max' = max |x - x_ref| /
     max |x_ref| (element by element against the block's largest entry)."""
     lay = S.lay
     sl = lay.slices()
     x = np.asarray(x, dtype=np.float64)
     x_ref = np.asarray(x_ref, dtype=np.float64)
-    w = np.asarray(S.F["Mp"].sum(axis=1)).ravel()
+    w = S.F["p_weights"] if "p_weights" in S.F else np.asarray(S.F["Mp"].sum(axis=1)).ravel()
 
     def mean_free(p):
         return p - (w @ p) / w.sum()

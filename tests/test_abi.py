@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "fsi.h")
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = set(re.findall(r"\b(fsi_[a-z_]+)\s*\(", text))
+    names = set(re.findall(r"\b(fsi_[a-z0-9_]+)\s*\(", text))
     return sorted(names)
 
 

@@ -1,0 +1,198 @@
+"""The paper's own element pair (Sec. 4: Q2 velocity / discontinuous P1 pressure on squares, Q1
+solid) through the C-ABI (fsi_create_q2) against the oracle's ``qpair``: every block's pattern
+exactly and values to 1e-12; the coupling's piece list bit for bit and C_f to 1e-12 for an affine
+(rotated) and a non-affine (bent and sheared) position and for quadrilaterals spanning several
+cells; steps per block within 1e-8 of the oracle's direct solve (FP64 and mixed, both
+preconditioners) with outer counts within the bar of the exact-block counts; a time loop."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gmres as ogmres
+from oracle import qpair
+from oracle import step as ostep
+from paper_2301_10041_amd import fsi, inputs
+
+from gpu_helpers import assert_block_parity, soa, to_dev, to_host, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch_dev()
+    fsi.lib()
+
+
+def _same_pattern(rp, col, A):
+    A = A.tocsr()
+    A.sort_indices()
+    assert np.array_equal(rp, A.indptr.astype(np.int32))
+    assert np.array_equal(col, A.indices.astype(np.int32))
+
+
+def _ctx(wl):
+    return fsi.Context.from_workload(wl)
+
+
+@pytest.mark.parametrize("n", [4, 8, 12])
+def test_q_fluid_blocks(n):
+    print(f"[Q2/P1-disc fluid blocks n={n}]", flush=True)
+    wl = inputs.QWorkload(f"q{n}", n, 3, 1, nu=1.3, rho=0.9, dt=0.02)
+    ctx = _ctx(wl)
+    F = qpair.assemble_fluid(n, nu=1.3, rho=0.9, dt=0.02)
+    assert ctx.sizes["Np"] == 3 * n * n and ctx.sizes["N2"] == (2 * n + 1) ** 2
+    rp, col, val = ctx.export_csr("AF")
+    blk = F["Af_blocks"]
+    scale = max(abs(blk[(0, 0)].data).max(), 1.0)
+    for k, key in enumerate([(0, 0), (0, 1), (1, 0), (1, 1)]):
+        _same_pattern(rp, col, blk[key])
+        assert np.abs(val[:, k] - blk[key].tocsr().data).max() <= 1e-12 * scale, key
+    rp, col, val = ctx.export_csr("MF")
+    _same_pattern(rp, col, F["Mf"])
+    assert np.abs(val[:, 0] - F["Mf"].tocsr().data).max() <= 1e-14 * abs(F["Mf"].data).max()
+    rp, col, val = ctx.export_csr("B")
+    for k, B in enumerate([F["Bx_bc"], F["By_bc"]]):
+        _same_pattern(rp, col, B)
+        assert np.abs(val[:, k] - B.tocsr().data).max() <= 1e-13 * abs(B.data).max()
+    rp, col, val = ctx.export_csr("BT")
+    for k, B in enumerate([F["Bx_bc"], F["By_bc"]]):
+        Bt = B.T.tocsr()
+        Bt.sort_indices()
+        _same_pattern(rp, col, Bt)
+        assert np.abs(val[:, k] - Bt.data).max() <= 1e-13 * abs(B.data).max()
+    # M_p: the diagonal of the oracle's (its off-diagonal entries vanish: orthogonal basis)
+    rp, col, val = ctx.export_csr("MP")
+    assert np.array_equal(col, np.arange(3 * n * n)) and np.array_equal(rp, np.arange(3 * n * n + 1))
+    assert np.abs(val[:, 0] - F["Mp"].diagonal()).max() <= 1e-15 * F["Mp"].diagonal().max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("shear", [0.0, 0.3])
+def test_q_solid_blocks(shear):
+    print(f"[Q1 solid blocks shear={shear}]", flush=True)
+    xy, quad = inputs.quad_bar(7, 3, 0.3, 0.7, 0.45, 0.55)
+    xy[:, 0] += shear * (xy[:, 1] - 0.45)
+    ctx = fsi.Context(16, xy, quad, kappa=3.5, pair=fsi.PAIR_Q2P1DISC)
+    S = qpair.assemble_solid(xy, quad, kappa=3.5)
+    for name, A in (("AS", S["As"]), ("CS", S["Ms"])):
+        rp, col, val = ctx.export_csr(name)
+        _same_pattern(rp, col, A)
+        assert np.abs(val[:, 0] - A.tocsr().data).max() <= 1e-12 * abs(A.data).max(), name
+    ctx.close()
+
+
+def _coupling_cases():
+    xy, quad = inputs.quad_bar(6, 2, 0.3, 0.7, 0.45, 0.55)
+    bent = inputs.bent(xy, 0.05, 0.4, 0.3)
+    bent[:, 0] += 0.02 * np.sin(7.0 * xy[:, 1])
+    cxy, cquad = inputs.quad_bar(3, 1, 0.27, 0.71, 0.43, 0.56)     # quadrilaterals of ~5 x 4 cells
+    axy, aquad = inputs.quad_bar(4, 2, 0.25, 0.75, 0.375, 0.625)   # edges on the grid lines of 8^2
+    return {
+        "rotated16": (16, xy, quad, inputs.rotation(xy, (0.5, 0.5), 0.3)),
+        "bent16": (16, xy, quad, bent),
+        "coarse32": (32, cxy, cquad, inputs.rotation(cxy, (0.49, 0.5), 0.7)),
+        "grid_aligned8": (8, axy, aquad, axy),
+    }
+
+
+@pytest.mark.parametrize("case", ["rotated16", "bent16", "coarse32", "grid_aligned8"])
+def test_q_coupling(case):
+    n, xy, quad, X = _coupling_cases()[case]
+    print(f"[Q1/Q2 coupling {case} n={n} Nq={quad.shape[0]}]", flush=True)
+    Cf, pieces = qpair.assemble_coupling(X, xy, quad, n)
+    ctx = fsi.Context(n, xy, quad, pair=fsi.PAIR_Q2P1DISC)
+    info = ctx.assemble_coupling(to_dev(soa(X)))
+    E, T = ctx.export_pairs()
+    ref = np.array(pieces, dtype=np.int64).reshape(-1, 2)
+    assert np.array_equal(E, ref[:, 0]) and np.array_equal(T, ref[:, 1]), case
+    rp, col, val = ctx.export_csr("CF")
+    _same_pattern(rp, col, Cf)
+    err = np.abs(val[:, 0] - Cf.tocsr().data).max() / abs(Cf.data).max()
+    print(f"  pieces {len(pieces)} nnz {Cf.nnz} C_f err {err:.1e}", flush=True)
+    assert err <= 1e-12, case
+    rp, col, val = ctx.export_csr("CFT")
+    CfT = Cf.T.tocsr()
+    CfT.sort_indices()
+    _same_pattern(rp, col, CfT)
+    assert np.abs(val[:, 0] - CfT.data).max() <= 1e-12 * abs(Cf.data).max()
+    ctx.close()
+
+
+def test_q_invalid_position_and_refusals():
+    xy, quad = inputs.quad_bar(3, 1, 0.3, 0.7, 0.45, 0.55)
+    ctx = fsi.Context(8, xy, quad, pair=fsi.PAIR_Q2P1DISC)
+    X = xy.copy()
+    X[1] = X[2] - [0.0, 0.2]     # a reflex corner
+    with pytest.raises(fsi.FsiError) as e:
+        ctx.assemble_coupling(to_dev(soa(X)))
+    assert e.value.code == fsi.FSI_E_MESH
+    ctx.assemble_coupling(to_dev(soa(xy)))     # and the context still works
+    for call in (lambda: ctx.set_smoother(fsi.SMOOTH_STENCIL),
+                 lambda: ctx.set_coupling_mode(fsi.COUPLING_INCREMENTAL),
+                 lambda: ctx.set_inner_mode(fsi.INNER_GMRES),
+                 lambda: ctx.set_solid(xy, quad)):
+        with pytest.raises(fsi.FsiError) as e:
+            call()
+        assert e.value.code == fsi.FSI_E_STATE
+    ctx.close()
+    with pytest.raises(fsi.FsiError) as e:    # a clockwise reference quadrilateral
+        fsi.Context(8, xy, quad[:, ::-1], pair=fsi.PAIR_Q2P1DISC)
+    assert e.value.code == fsi.FSI_E_MESH
+
+
+def _oracle_its(S, b, kind):
+    A = S.matrix()
+    _, info = ogmres.gmres(lambda v: A @ v, b, precond=lambda r: S.apply_precond(r, kind), rtol=1e-8, restart=30)
+    return info["its"]
+
+
+@pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
+@pytest.mark.parametrize("pc", [fsi.PC_DIAG, fsi.PC_TRI])
+def test_q_step_parity(prec, pc):
+    """The qbar32 bar, bent and rotated: per block within 1e-8 of the oracle's direct solve at
+    rtol 1e-10; at rtol 1e-8 the outer count within max(2, 10%) of the exact-block count."""
+    wl = inputs.QWORKLOADS["qbar32"]
+    xy, quad = wl.solid_mesh()
+    X = inputs.rotation(inputs.bent(xy, 0.03, 0.4, wl.x0), wl.center, 0.2)
+    S = qpair.QSystem.from_workload(wl)
+    u0 = inputs.uniform(2 * S.lay.N2, wl.seed)
+    S.set_position(X)
+    b = S.rhs(u0, X)
+    ref = S.solve_direct(b)
+    ctx = _ctx(wl)
+    print(f"[Q pair step qbar32 prec={prec} pc={pc} N={S.lay.N}]", flush=True)
+    out = to_dev(np.zeros(S.lay.N))
+    st = ctx.step(to_dev(u0), to_dev(soa(X)), out, fsi.Opts(pc=pc, rtol=1e-10, prec=prec))
+    assert st["converged"]
+    assert_block_parity(S, to_host(out), ref, 1e-8, f"qbar32 prec={prec} pc={pc}")
+    st = ctx.step(to_dev(u0), to_dev(soa(X)), out, fsi.Opts(pc=pc, rtol=1e-8, prec=prec))
+    its_o = _oracle_its(S, b, "tri" if pc == fsi.PC_TRI else "diag")
+    print(f"  outer its {st['its']} (oracle exact blocks {its_o}), inner its {st.get('inner_its')}", flush=True)
+    assert st["its"] <= its_o + max(2, math.ceil(0.1 * its_o))
+    ctx.close()
+
+
+def test_q_time_loop():
+    """Three steps of a bar bending and turning at 16^2: each state within 1e-8 per block of the
+    oracle's time loop (direct solves)."""
+    wl = inputs.QWorkload("qbar16", 16, 6, 2, nu=0.2, dt=0.002, seed=3)
+    xy, quad = wl.solid_mesh()
+    S = qpair.QSystem.from_workload(wl)
+
+    def Xk(k):
+        return inputs.rotation(inputs.bent(xy, 0.01 * (k + 1), 0.4, wl.x0), wl.center, 0.05 * k)
+
+    u0 = inputs.uniform(2 * S.lay.N2, 11)
+    ref = ostep.time_loop(S, Xk, 3, u0=u0, solver="direct")
+    ctx = _ctx(wl)
+    u = to_dev(u0)
+    out = to_dev(np.zeros(S.lay.N))
+    for k in range(3):
+        print(f"[Q pair time loop step {k}]", flush=True)
+        st = ctx.step(u, to_dev(soa(Xk(k))), out, fsi.Opts(pc=fsi.PC_TRI, rtol=1e-10))
+        assert st["converged"]
+        assert_block_parity(S, to_host(out), ref[k], 1e-8, f"step {k}")
+        u = out[:2 * S.lay.N2].clone()
+    ctx.close()
