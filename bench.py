@@ -192,7 +192,7 @@ def _errs(S, x, xs):
     """||x - x*|| / ||x*|| over the whole vector and per block (u, mean-free p, X, lam)."""
     import numpy as np
     sl = S.lay.slices()
-    w = np.asarray(S.F["Mp"].sum(axis=1)).ravel()
+    w = S.F["p_weights"] if "p_weights" in S.F else np.asarray(S.F["Mp"].sum(axis=1)).ravel()
     mf = lambda p: p - (w @ p) / w.sum()
     cat = lambda v, a, b: np.concatenate([v[sl[a]], v[sl[b]]])
     parts = {"u": (cat(x, "ux", "uy"), cat(xs, "ux", "uy")), "p": (mf(x[sl["p"]]), mf(xs[sl["p"]])),
@@ -254,6 +254,14 @@ def oracle_leg(args) -> dict:
         S32.set_position(S32.xy_ref)
         xs32 = S32.solve_direct(S32.random_rhs(w32.seed))
         acc["disk32"] = {k[len("disk32_"):]: _errs(S32, data[k], xs32) for k in data.files if k.startswith("disk32_")}
+        if any(k.startswith("qbar32_") for k in data.files):   # the paper's pair against its direct solve
+            from oracle import qpair
+            wq = inputs.QWORKLOADS["qbar32"]
+            Sq = qpair.QSystem.from_workload(wq)
+            Xq = q_position(inputs, wq, Sq.xy_ref, 0)
+            Sq.set_position(Xq)
+            xq = Sq.solve_direct(Sq.rhs(inputs.uniform(2 * Sq.lay.N2, wq.seed), Xq))
+            acc["qbar32"] = {k[len("qbar32_"):]: _errs(Sq, data[k], xq) for k in data.files if k.startswith("qbar32_")}
         if "big_fp64" in data.files:
             wb = inputs.WORKLOADS["twodisk1024"]
             xy, tri = wb.solid_mesh()
@@ -559,7 +567,56 @@ def config_legs(args, fsi, inputs, torch, dev, save):
         ctx.close()
         out["rotdisk256_step0"] = r
     out["bar256_nonlinear"] = nonlinear_leg(args, fsi, inputs, torch, dev)
+    out["qbar256"] = qpair_leg(args, fsi, inputs, torch, dev, save)
     return out
+
+
+def q_position(inputs, wl, xy, k):
+    """The prescribed motion of the paper's-pair bar: bent by 0.02 (non-affine on every
+    quadrilateral) and turned about its centre at 0.5 rad/s."""
+    return inputs.rotation(inputs.bent(xy, 0.02, 0.4, wl.x0), wl.center, 0.5 * k * wl.dt)
+
+
+def qpair_leg(args, fsi, inputs, torch, dev, save):
+    """The paper's own element pair (Q2 / P1-disc fluid, Q1 solid; fsi_create_q2): a time loop
+    of the 256^2 bar (102 x 26 quadrilaterals) with a prescribed bending-and-turning motion,
+    block-triangular, FP64 and mixed: T_coup and T_sol per step, outer and inner counts; and
+    the 32^2 bar's step saved for the oracle's accuracy check."""
+    import numpy as np
+
+    def vec(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    w32 = inputs.QWORKLOADS["qbar32"]
+    xy, _ = w32.solid_mesh()
+    ctx = fsi.Context.from_workload(w32)
+    N = ctx.sizes["N"]
+    u = vec(inputs.uniform(2 * ctx.sizes["N2"], w32.seed))
+    X = vec(np.concatenate(list(q_position(inputs, w32, xy, 0).T)))
+    for tag, prec in (("fp64", fsi.FP64), ("mixed", fsi.FP32)):
+        x = torch.zeros(N, dtype=torch.float64, device=dev)
+        ctx.step(u, X, x, fsi.Opts(pc=fsi.PC_TRI, prec=prec, rtol=1e-8))
+        save[f"qbar32_tri_{tag}"] = x.cpu().numpy()
+    ctx.close()
+    wl = inputs.QWORKLOADS["qbar256"]
+    xy, quad = wl.solid_mesh()
+    ctx = fsi.Context.from_workload(wl)
+    N2 = ctx.sizes["N2"]
+    steps = args.q_steps
+    Xs = [vec(np.concatenate(list(q_position(inputs, wl, xy, k).T))) for k in range(steps + 1)]
+    rec = {"n": wl.n, "unknowns": ctx.sizes["N"], "pressure_unknowns": ctx.sizes["Np"],
+           "solid_quadrilaterals": int(quad.shape[0]), "steps": steps, "dt": wl.dt}
+    u0 = vec(inputs.uniform(2 * N2, wl.seed))
+    for tag, prec in (("fp64", fsi.FP64), ("mixed", fsi.FP32)):
+        r, _ = time_loop(ctx, u0, Xs, N2, fsi.Opts(pc=fsi.PC_TRI, prec=prec, rtol=1e-8), 1, steps, f"qbar256 {tag}")
+        rec[tag] = dict(steps_per_s=r["value"], ms_per_step=r["ms_per_step"], t_coup_ms=r["t_coup_ms"],
+                        t_sol_ms=r["t_solve_ms"], its_mean=sum(r["its"]) / steps, its_max=max(r["its"]),
+                        inner_its_mean=sum(r["inner_its"]) / steps, relres_true_max=r["relres_true"])
+    sz = ctx.refresh_sizes()
+    rec["pieces"] = sz["n_pairs"]
+    rec["nnz_Cf"] = sz["nnz_Cf"]
+    ctx.close()
+    return rec
 
 
 def nonlinear_leg(args, fsi, inputs, torch, dev):
@@ -618,6 +675,7 @@ def main():
     ap.add_argument("--pc", choices=["tri", "diag"], default="tri")
     ap.add_argument("--loop-steps", type=int, default=100, help="steps of the 512^2 time loop")
     ap.add_argument("--nl-steps", type=int, default=10, help="steps of the nonlinear bar loop")
+    ap.add_argument("--q-steps", type=int, default=10, help="steps of the paper's-pair bar loop")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true", help="skip the whole oracle leg")
     ap.add_argument("--oracle-leg", action="store_true", help=argparse.SUPPRESS)

@@ -198,9 +198,10 @@ int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *h
  *    FSI_E_MESH) clipped against the cells of its bounding box; the integral over a piece by
  *    the inverse of the bilinear map, on the fan of the piece with 4 x 4 conical Gauss points
  *    per fan triangle (exact when X^n is affine on E); fsi_export_pairs gives (E, cell j n + i);
- *  - the A11 preconditioner: the velocity V-cycle on the assembled Q2 operators (no
- *    matrix-free form) and the diagonal Schur approximation nu / (M_p)_kk + (rho/dt) /
- *    (B D^{-1} B^T)_kk, D the row sums of M_f.
+ *  - the A11 preconditioner: V-cycles on the assembled operators (no matrix-free form):
+ *    velocity on the Q2 A_f of every level, and the Cahouet-Chabard approximation
+ *    nu M_p^{-1} + (rho/dt) L^{-1} with L = B D^{-1} B^T (D the row sums of M_f) re-formed on
+ *    every level and the P1-disc prolongation between levels.
  * hbm_budget: checked against the device footprint after creation (0: none).
  * Errors as for fsi_create; FSI_E_MESH also for a reference quadrilateral that is not
  * strictly convex and counter-clockwise. */

@@ -1409,18 +1409,121 @@ __global__ void k_row_sum(int64_t nrows, const int *rowptr, const double *v, dou
   d[r] = s;
 }
 
-// w_k = nu / (M_p)_kk + (rho/dt) / (B D^{-1} B^T)_kk (the second term left out where the row of B
-// is zero: the pinned unknown)
-__global__ void k_q_pres_weight(int64_t np, const int *brp, const int *bcol, const double *bval, const double *d,
-                                const double *mp, double nu, double rdt, double *w) {
+// Row r of the pressure Laplacian of the discontinuous pair, L = B D^{-1} B^T (D the row sums
+// of M_f, B with its Dirichlet columns and pinned row): the unknowns of the cells around r's cell
+// (3 x 3 clamped at the boundary), in ascending order; sum over the 9 nodes v of r's cell of
+// B_rv . B_sv / D_v.  Row 0 (the pinned unknown) is the identity row.
+__global__ void k_q_lp(int n, int pass, const int *__restrict__ brp, const int *__restrict__ bcol,
+                       const double *__restrict__ bval, const int *__restrict__ trp, const int *__restrict__ tcol,
+                       const double *__restrict__ tval, const double *__restrict__ d, int *cnt, const int *rowptr,
+                       int *col, double *V) {
+  const int64_t np = 3 * (int64_t)n * n;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= np) return;
-  double l = 0.0;
-  for (int k = brp[r]; k < brp[r + 1]; ++k) {
-    const double bx = bval[2 * (int64_t)k], by = bval[2 * (int64_t)k + 1];
-    l += (bx * bx + by * by) / d[bcol[k]];
+  const int64_t cell = r / 3;
+  const int ci = (int)(cell % n), cj = (int)(cell / n);
+  const int i0 = max(ci - 1, 0), i1 = min(ci + 1, n - 1), j0 = max(cj - 1, 0), j1 = min(cj + 1, n - 1);
+  const int wi = i1 - i0 + 1;
+  if (!pass) {
+    cnt[r] = 3 * wi * (j1 - j0 + 1);
+    return;
   }
-  w[r] = nu / mp[r] + (l > 0.0 ? rdt / l : 0.0);
+  const int k0 = rowptr[r];
+  for (int j = j0, k = k0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i)
+      for (int q = 0; q < 3; ++q, ++k) {
+        col[k] = (int)(3 * ((int64_t)j * n + i) + q);
+        V[k] = 0.0;
+      }
+  for (int e = brp[r]; e < brp[r + 1]; ++e) {
+    const int v = bcol[e];
+    const double bx = bval[2 * (int64_t)e], by = bval[2 * (int64_t)e + 1], dv = d[v];
+    if (bx == 0.0 && by == 0.0) continue;
+    for (int f = trp[v]; f < trp[v + 1]; ++f) {
+      const int sc = tcol[f];
+      const int64_t sk = sc / 3;
+      const int si = (int)(sk % n), sj = (int)(sk / n);
+      V[k0 + 3 * ((sj - j0) * wi + (si - i0)) + sc % 3] += (bx * tval[2 * (int64_t)f] + by * tval[2 * (int64_t)f + 1]) / dv;
+    }
+  }
+  if (r == 0) V[k0] = 1.0;   // the row's first column is unknown 0: B's row 0 left it zero
+}
+
+// Prolongation of the discontinuous P1 pressure from an nf / 2 grid into the nf grid: the coarse
+// cell's linear function on each of its four children (fine constant = the coarse function at
+// the child's centre, x_c +- h_c / 4; fine slopes = half the coarse ones); the pinned unknown 0
+// excluded on both grids.
+__device__ int pd_prolong_row(int64_t r, int nf, int *cidx, double *w) {
+  const int nc = nf / 2;
+  const int64_t cell = r / 3;
+  const int q = (int)(r % 3), i = (int)(cell % nf), j = (int)(cell / nf);
+  const int64_t cc = 3 * ((int64_t)(j >> 1) * nc + (i >> 1));
+  const double sx = (i & 1) ? 0.25 : -0.25, sy = (j & 1) ? 0.25 : -0.25;
+  int m = 0;
+  auto put = [&](int64_t c, double v) {
+    if (c == 0) return;
+    cidx[m] = (int)c;
+    w[m] = v;
+    ++m;
+  };
+  if (q == 0) {
+    put(cc, 1.0);
+    put(cc + 1, sx);
+    put(cc + 2, sy);
+  } else {
+    put(cc + q, 0.5);
+  }
+  return m;
+}
+
+__global__ void k_pd_prolong(int nf, int pass, int *cnt, const int *rowptr, int *col, double *V) {
+  const int64_t np = 3 * (int64_t)nf * nf;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= np) return;
+  int ci[3];
+  double w[3];
+  const int m = r == 0 ? 0 : pd_prolong_row(r, nf, ci, w);
+  if (!pass) {
+    cnt[r] = m;
+    return;
+  }
+  const int k = rowptr[r];
+  for (int t = 0; t < m; ++t) {
+    col[k + t] = ci[t];
+    V[k + t] = w[t];
+  }
+}
+
+__global__ void k_pd_restrict(int nf, int pass, int *cnt, const int *rowptr, int *col, double *V) {
+  const int nc = nf / 2;
+  const int64_t npc = 3 * (int64_t)nc * nc;
+  const int64_t rc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rc >= npc) return;
+  const int64_t cell = rc / 3;
+  const int ic = (int)(cell % nc), jc = (int)(cell / nc);
+  int k = pass ? rowptr[rc] : 0, c = 0;
+  if (rc != 0)
+    for (int dj = 0; dj < 2; ++dj)
+      for (int di = 0; di < 2; ++di) {
+        const int64_t fcell = (int64_t)(2 * jc + dj) * nf + 2 * ic + di;
+        for (int q = 0; q < 3; ++q) {
+          const int64_t f = 3 * fcell + q;
+          if (f == 0) continue;
+          int ci[3];
+          double w[3];
+          const int m = pd_prolong_row(f, nf, ci, w);
+          for (int t = 0; t < m; ++t)
+            if (ci[t] == rc) {
+              if (pass) {
+                col[k] = (int)f;
+                V[k] = w[t];
+                ++k;
+              }
+              ++c;
+            }
+        }
+      }
+  if (!pass) cnt[rc] = c;
 }
 
 static void assemble_q2q2(Csr &A, DevBuf<double> *M, int n, const double *dE, double rdt, DevBuf<int> &tmp,
@@ -1463,13 +1566,6 @@ void build_fluid_q2(Ctx &c) {
   c.Mp_dinv.alloc(np);
   hipLaunchKernelGGL(k_diag_inv, dim3(gp), dim3(256), 0, s, np, c.Mp.rowptr.p, c.Mp.col.p, c.Mp.val.p,
                      c.Mp_dinv.p);
-  DevBuf<double> d(n2);
-  hipLaunchKernelGGL(k_row_sum, dim3(g2), dim3(256), 0, s, n2, c.Af.rowptr.p, c.Mf.p, d.p);
-  c.qp_w.alloc(np);
-  hipLaunchKernelGGL(k_q_pres_weight, dim3(gp), dim3(256), 0, s, np, c.B.rowptr.p, c.B.col.p, c.B.val.p, d.p,
-                     c.Mp.val.p, c.nu, c.rho / c.dt, c.qp_w.p);
-  c.qp_w32.alloc(np);
-  convert(c.qp_w32.p, c.qp_w.p, np, s);
   c.bnd.alloc(n2);
   hipLaunchKernelGGL(k_p2_boundary_flags, dim3(g2), dim3(256), 0, s, n, c.bnd.p);
   FSI_CHECK_LAUNCH();
@@ -1547,10 +1643,11 @@ __global__ void k_q2_restrict(int nf, int pass, int *cnt, const int *rowptr, int
   if (!pass) cnt[row] = c;
 }
 
-// The velocity hierarchy of the Q2 pair: A_f re-discretised on every level (the Galerkin
-// operator of the nested Q2 spaces), the biquadratic prolongation and its transpose, dense
-// inverse at the coarsest level; smoothing on the assembled operators (no matrix-free form).
-// The discontinuous pressure has no hierarchy: its Schur approximation is diagonal.
+// The hierarchies of the Q2 pair, smoothed on the assembled operators (no matrix-free form):
+// velocity, A_f re-discretised on every level (the Galerkin operator of the nested Q2 spaces)
+// with the biquadratic prolongation and its transpose; pressure, L = B D^{-1} B^T of each level
+// (the Laplacian of the Cahouet-Chabard approximation for a discontinuous pressure) with the
+// P1-disc prolongation and its transpose; dense inverses at the coarsest level.
 void build_multigrid_q2(Ctx &c) {
   hipStream_t s = c.stream;
   DevBuf<int> tmp;
@@ -1564,16 +1661,56 @@ void build_multigrid_q2(Ctx &c) {
   c.mgu.stencil = false;
   c.mgu.tail = false;
   c.mgu.lv.resize(ns.size());
-  c.mgp.lv.clear();
+  c.mgp.comps = 1;
+  c.mgp.degree = c.mgp.degree32 = 2;
   c.mgp.stencil = false;
+  c.mgp.tail = false;
+  c.mgp.lv.resize(ns.size());
   for (size_t l = 0; l < ns.size(); ++l) {
     const int m = ns[l];
     DevBuf<double> dE = upload_q2_table(m, c.nu, s);
     MgLevel &U = c.mgu.lv[l];
     U.n = m;
     U.nodes = (int64_t)(2 * m + 1) * (2 * m + 1);
-    assemble_q2q2(U.A, nullptr, m, dE.p, c.rho / c.dt, tmp, s);
+    DevBuf<double> Ml;
+    assemble_q2q2(U.A, &Ml, m, dE.p, c.rho / c.dt, tmp, s);
     FSI_HIP(hipStreamSynchronize(s));
+    {   // the pressure level: L = B D^{-1} B^T from this level's B, B^T and lumped M_f
+      MgLevel &P = c.mgp.lv[l];
+      P.n = m;
+      P.nodes = 3 * (int64_t)m * m;
+      const unsigned gp = grid_for(P.nodes, 256), g2 = grid_for(U.nodes, 256);
+      Csr Bl, BTl;
+      build_rows(Bl, P.nodes, U.nodes, 2, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+        hipLaunchKernelGGL(k_asm_qb, dim3(gp), dim3(256), 0, s, m, pass, dE.p, cnt, rp, col, v);
+      });
+      build_rows(BTl, U.nodes, P.nodes, 2, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+        hipLaunchKernelGGL(k_asm_qbt, dim3(g2), dim3(256), 0, s, m, pass, dE.p, cnt, rp, col, v);
+      });
+      DevBuf<double> d(U.nodes);
+      hipLaunchKernelGGL(k_row_sum, dim3(g2), dim3(256), 0, s, U.nodes, U.A.rowptr.p, Ml.p, d.p);
+      build_rows(P.A, P.nodes, P.nodes, 1, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+        hipLaunchKernelGGL(k_q_lp, dim3(gp), dim3(256), 0, s, m, pass, Bl.rowptr.p, Bl.col.p, Bl.val.p, BTl.rowptr.p,
+                           BTl.col.p, BTl.val.p, d.p, cnt, rp, col, v);
+      });
+      FSI_HIP(hipStreamSynchronize(s));
+      P.dinv.alloc(P.nodes);
+      hipLaunchKernelGGL(k_block_diag_inv, dim3(gp), dim3(256), 0, s, P.nodes, 1, P.A.rowptr.p, P.A.col.p, P.A.val.p,
+                         P.dinv.p);
+      FSI_CHECK_LAUNCH();
+      P.lmax = 1.1 * power_lmax(P, 1, s);
+      if (l + 1 < ns.size()) {
+        const int64_t npc = 3 * (int64_t)(m / 2) * (m / 2);
+        build_rows(P.P, P.nodes, npc, 1, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+          hipLaunchKernelGGL(k_pd_prolong, dim3(gp), dim3(256), 0, s, m, pass, cnt, rp, col, v);
+        });
+        build_rows(P.R, npc, P.nodes, 1, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
+          hipLaunchKernelGGL(k_pd_restrict, dim3(grid_for(npc, 256)), dim3(256), 0, s, m, pass, cnt, rp, col, v);
+        });
+      }
+      for (int i = 0; i < 5; ++i) P.w64[i].alloc(P.nodes);
+      FSI_HIP(hipStreamSynchronize(s));   // the level's B, B^T and D are freed below
+    }
     U.dinv.alloc(4 * U.nodes);
     hipLaunchKernelGGL(k_block_diag_inv, dim3(grid_for(U.nodes, 256)), dim3(256), 0, s, U.nodes, 4, U.A.rowptr.p,
                        U.A.col.p, U.A.val.p, U.dinv.p);
@@ -1592,6 +1729,7 @@ void build_multigrid_q2(Ctx &c) {
     for (int i = 0; i < 5; ++i) U.w64[i].alloc(2 * U.nodes);
   }
   coarse_inverse(c.mgu, s);
+  coarse_inverse(c.mgp, s);
   FSI_HIP(hipStreamSynchronize(s));
 }
 

@@ -84,10 +84,6 @@ struct Ctx {
   DevBuf<unsigned char> mptab64, mptab32;  // P1Table<double/float> of M_p
   DevBuf<unsigned char> divtab64, divtab32;  // DivTable<double/float> (B and B^T)
   DevBuf<unsigned char> bnd;  // 1 on boundary P2 nodes
-  // the Q2 / P1-disc pair: the diagonal Schur approximation of its A11 preconditioner,
-  // nu / (M_p)_kk + (rho/dt) / (B D^{-1} B^T)_kk with D the row sums of M_f
-  DevBuf<double> qp_w;
-  DevBuf<float> qp_w32;
 
   // solid blocks
   std::vector<int> h_tri;  // host copy of the connectivity (3 per triangle; 4 per quadrilateral of the Q pair)

@@ -110,15 +110,14 @@ __global__ void k_minres_update(T *wn, const T *v, const T *w1, const T *w2, T *
   }
 }
 
-// z = w r on the pressure unknowns in T, stored as TZ, except z[0] = r[0] rounded through T (the
-// pinned unknown); lane blockIdx.y at + lane ls
+// The Schur approximation of the discontinuous pair on the pressure unknowns:
+// z = nu M_p^{-1} r + (rho/dt) x_L (M_p diagonal, x_L the V-cycle on L = B D^{-1} B^T) in T, stored
+// as TZ, except z[0] = r[0] rounded through T (the pinned unknown)
 template <typename TZ, typename T>
-__global__ void k_q_pres(TZ *z, const TZ *r, const T *w, int64_t np, int64_t ls) {
-  z += (int64_t)blockIdx.y * ls;
-  r += (int64_t)blockIdx.y * ls;
+__global__ void k_q_pres(TZ *z, const TZ *r, const T *xl, const T *mpinv, T nu, T rdt, int64_t np) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
     const T v = (T)r[i];
-    z[i] = (TZ)(i == 0 ? v : w[i] * v);
+    z[i] = (TZ)(i == 0 ? v : nu * mpinv[i] * v + rdt * xl[i]);
   }
 }
 
@@ -687,14 +686,20 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
     FSI_CHECK_LAUNCH();
     return;
   }
-  if (c.pair == FSI_PAIR_Q2P1DISC) {   // the diagonal Schur approximation of the Q2 / P1-disc pair
-    FSI_REQUIRE(!dot.p, FSI_E_STATE, "the Q2 / P1-disc pair forms no tile sums");
-    const T *w = std::is_same<T, double>::value ? (const T *)c.qp_w.p : (const T *)c.qp_w32.p;
+  // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
+  T *rp = Pr<T>::inner(c, 8).p;
+  if (z64) convert(rp, r64 + 2 * N2, Np, sp);
+  else convert_l(LP<T>(rp, Np), LP<const T>(r + 2 * N2, nf), Np, sp, K);
+  fill_l(LP<T>(rp, Np), 1, (T)0, sp, K);
+  T *xp = vcycle<T, 1, 1>(c.mgp, 0, rp, sp, nullptr, K);
+  if (c.pair == FSI_PAIR_Q2P1DISC) {   // M_p of the discontinuous pressure is diagonal: no mass solve
+    FSI_REQUIRE(!dot.p && K == 1, FSI_E_STATE, "the Q2 / P1-disc pair runs one system and forms no tile sums");
     if (z64)
-      hipLaunchKernelGGL((k_q_pres<double, T>), dim3(vgrid(Np), 1), dim3(256), 0, sp, z64 + 2 * N2, r64 + 2 * N2, w,
-                         Np, nf);
+      hipLaunchKernelGGL((k_q_pres<double, T>), dim3(vgrid(Np)), dim3(256), 0, sp, z64 + 2 * N2, r64 + 2 * N2, xp,
+                         mp_dinv<T>(c), (T)c.nu, (T)(c.rho / c.dt), Np);
     else
-      hipLaunchKernelGGL((k_q_pres<T, T>), dim3(vgrid(Np), K), dim3(256), 0, sp, z + 2 * N2, r + 2 * N2, w, Np, nf);
+      hipLaunchKernelGGL((k_q_pres<T, T>), dim3(vgrid(Np)), dim3(256), 0, sp, z + 2 * N2, r + 2 * N2, xp,
+                         mp_dinv<T>(c), (T)c.nu, (T)(c.rho / c.dt), Np);
     FSI_CHECK_LAUNCH();
     if (fork) {
       FSI_HIP(hipEventRecord(c.ev_join, sp));
@@ -702,12 +707,6 @@ static void a11_precond(Ctx &c, const T *r, T *z, int K = 1, const double *r64 =
     }
     return;
   }
-  // r' = pressure residual with the pinned entry removed (keeps the operator symmetric)
-  T *rp = Pr<T>::inner(c, 8).p;
-  if (z64) convert(rp, r64 + 2 * N2, Np, sp);
-  else convert_l(LP<T>(rp, Np), LP<const T>(r + 2 * N2, nf), Np, sp, K);
-  fill_l(LP<T>(rp, Np), 1, (T)0, sp, K);
-  T *xp = vcycle<T, 1, 1>(c.mgp, 0, rp, sp, nullptr, K);
   if (c.mgp.stencil) {
     // the mass solve (kMpSteps Chebyshev steps from zero) and the output z_p = nu x + (rho/dt) x_L
     // with the pinned entry and the parts of r . z, in one launch
