@@ -676,6 +676,8 @@ def main():
     ap.add_argument("--loop-steps", type=int, default=100, help="steps of the 512^2 time loop")
     ap.add_argument("--nl-steps", type=int, default=10, help="steps of the nonlinear bar loop")
     ap.add_argument("--q-steps", type=int, default=10, help="steps of the paper's-pair bar loop")
+    ap.add_argument("--leg", choices=["qbar256"], default="",
+                    help="run only this leg and print its record (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true", help="skip the whole oracle leg")
     ap.add_argument("--oracle-leg", action="store_true", help=argparse.SUPPRESS)
@@ -708,6 +710,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
+    if args.leg == "qbar256":
+        print(json.dumps(_round(qpair_leg(args, fsi, inputs, torch, dev, {}))), flush=True)
+        return
     if args.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

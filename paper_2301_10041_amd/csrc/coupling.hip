@@ -1123,8 +1123,8 @@ void assemble_coupling(Ctx &c, const double *Xn, bool) {
 // points x = A + u (B - A) + u v (C - B), weight 2 |ABC| u w_u w_v: exact for polynomials of
 // degree <= 6, so exact whenever X^n is affine on E (the integrand is then of degree 2 + 4).
 //
-// Pipeline: per quadrilateral the count of kept pieces, a scan, per quadrilateral the pieces
-// (E, cell j n + i) and their 4 x 9 matrices, per solid node one wavefront walking the window
+// Pipeline: per quadrilateral the count of kept pieces, a scan, per quadrilateral (a wavefront)
+// the pieces (E, cell j n + i) and their 4 x 9 matrices, per solid node one wavefront walking the window
 // of lattice nodes its pieces cover (a lane per node, the pieces in a fixed order), and the
 // transpose of the triangle pair.
 struct GaussPts {
@@ -1242,13 +1242,17 @@ __device__ __forceinline__ void lagrange2(double t, double *v) {
   v[2] = 2.0 * t * (t - 0.5);
 }
 
-// One thread per quadrilateral: its pieces in cell order and their matrices
-// L[a][b] = int_q N_a phi_b J_s / J_X (36 per piece, a major).
-__global__ void k_q_emit(int64_t nq, int64_t ns, int n, const double *__restrict__ X, const double *__restrict__ Xref,
-                         const int *__restrict__ quad, const int *__restrict__ e_piece, GaussPts g, int *pair_E,
-                         int *pair_T, double *piece_L) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per quadrilateral: its pieces in cell order (every lane clips the same piece) and
+// their matrices L[a][b] = int_q N_a phi_b J_s / J_X (36 per piece, a major): the lanes share the
+// 16 (m - 2) points of a piece's fan triangles, then each entry is summed over the wave (a fixed
+// butterfly order).
+__global__ void __launch_bounds__(kWave) k_q_emit(int64_t nq, int64_t ns, int n, const double *__restrict__ X,
+                                                  const double *__restrict__ Xref, const int *__restrict__ quad,
+                                                  const int *__restrict__ e_piece, GaussPts g, int *pair_E,
+                                                  int *pair_T, double *piece_L) {
+  const int64_t e = blockIdx.x;
   if (e >= nq) return;
+  const int lane = threadIdx.x;
   Pt P[4], S[4], q[kMaxPoly];
   load_quad(X, ns, quad, e, P);
   load_quad(Xref, ns, quad, e, S);
@@ -1263,32 +1267,35 @@ __global__ void k_q_emit(int64_t nq, int64_t ns, int n, const double *__restrict
       if (!m) continue;
       double L[36];
       for (int k = 0; k < 36; ++k) L[k] = 0.0;
-      for (int t = 1; t < m - 1; ++t) {
+      for (int it = lane; it < 16 * (m - 2); it += kWave) {
+        const int t = 1 + (it >> 4), pu = (it >> 2) & 3, pv = it & 3;
         const Pt A = q[0], B = q[t], C = q[t + 1];
         const double two = (B.x - A.x) * (C.y - A.y) - (C.x - A.x) * (B.y - A.y);
-        for (int pu = 0; pu < 4; ++pu)
-          for (int pv = 0; pv < 4; ++pv) {
-            const double u = g.u[pu], v = g.u[pv];
-            const double x = A.x + u * (B.x - A.x) + u * v * (C.x - B.x);
-            const double y = A.y + u * (B.y - A.y) + u * v * (C.y - B.y);
-            double xi, eta;
-            q1_inverse(P, x, y, xi, eta);
-            double N[4], Nx[4], Ne[4];
-            q1_shape(xi, eta, N, Nx, Ne);
-            const double f = g.w[pu] * g.w[pv] * u * two * q1_jac(S, Nx, Ne) / q1_jac(P, Nx, Ne);
-            double vx[3], vy[3];
-            lagrange2(x * dn - i, vx);
-            lagrange2(y * dn - j, vy);
-            for (int a = 0; a < 4; ++a) {
-              const double fa = f * N[a];
-              for (int bb = 0; bb < 3; ++bb)
-                for (int ba = 0; ba < 3; ++ba) L[9 * a + ba + 3 * bb] += fa * vx[ba] * vy[bb];
-            }
-          }
+        const double u = g.u[pu], v = g.u[pv];
+        const double x = A.x + u * (B.x - A.x) + u * v * (C.x - B.x);
+        const double y = A.y + u * (B.y - A.y) + u * v * (C.y - B.y);
+        double xi, eta;
+        q1_inverse(P, x, y, xi, eta);
+        double N[4], Nx[4], Ne[4];
+        q1_shape(xi, eta, N, Nx, Ne);
+        const double f = g.w[pu] * g.w[pv] * u * two * q1_jac(S, Nx, Ne) / q1_jac(P, Nx, Ne);
+        double vx[3], vy[3];
+        lagrange2(x * dn - i, vx);
+        lagrange2(y * dn - j, vy);
+        for (int a = 0; a < 4; ++a) {
+          const double fa = f * N[a];
+          for (int bb = 0; bb < 3; ++bb)
+            for (int ba = 0; ba < 3; ++ba) L[9 * a + ba + 3 * bb] += fa * vx[ba] * vy[bb];
+        }
       }
-      pair_E[p] = (int)e;
-      pair_T[p] = j * n + i;
-      for (int k = 0; k < 36; ++k) piece_L[36 * (int64_t)p + k] = L[k];
+      for (int k = 0; k < 36; ++k) {
+        const double v = wave_sum(L[k]);
+        if (lane == 0) piece_L[36 * (int64_t)p + k] = v;
+      }
+      if (lane == 0) {
+        pair_E[p] = (int)e;
+        pair_T[p] = j * n + i;
+      }
       ++p;
     }
 }
@@ -1394,7 +1401,7 @@ void assemble_coupling_q(Ctx &c, const double *Xn) {
   int *pair_E = w.work(c.pair_E, npieces, "piece list");
   int *pair_T = w.work(c.pair_T, npieces, "piece list");
   double *piece_L = w.work(c.piece_L, 36 * (int64_t)npieces, "piece matrices");
-  hipLaunchKernelGGL(k_q_emit, dim3(grid_for(nq, 64)), dim3(64), 0, s, nq, ns, n, Xn, c.ref_xy.p, c.tri.p, e_piece,
+  hipLaunchKernelGGL(k_q_emit, dim3((unsigned)nq), dim3(kWave), 0, s, nq, ns, n, Xn, c.ref_xy.p, c.tri.p, e_piece,
                      gauss4(), pair_E, pair_T, piece_L);
   FSI_CHECK_LAUNCH();
   Csr &Cf = c.Cf;
