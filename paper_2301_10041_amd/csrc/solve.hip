@@ -1725,10 +1725,16 @@ double inner_pressure_weight(Ctx &c) {
   return c.gi_wp;
 }
 
+// The paper's element pair, block-triangular: 1e-4.  Its pressure slopes leave little trace in
+// the outer residual, so looser inner solves stop the outer iteration with the pressure far from
+// the solution: the 32^2 bar's step at rtol 1e-8 was 3.9e-7 (p) from the oracle's direct solve at
+// 1e-2, 1.9e-7 at 1e-3 and 1.7e-9 (the oracle's exact-block GMRES: 1.6e-9) at 1e-4, with 76 /
+// 101 / 122 inner steps.
 double inner_tol(const Ctx &c, int prec, int pc) {
   (void)prec;
   if (c.inner_rtol > 0) return c.inner_rtol;
-  return pc == FSI_PC_DIAG ? 1e-6 : 1e-2;
+  if (pc == FSI_PC_DIAG) return 1e-6;
+  return c.pair == FSI_PAIR_Q2P1DISC ? 1e-4 : 1e-2;
 }
 
 template <typename TA>
