@@ -28,7 +28,8 @@ Prints one JSON line.  `value` is FP64 steps/s at 1024^2.  Beside it:
   configs    the CPU-fast 32^2 case (both preconditioners), the 256^2 ellipse (both
              preconditioners), the 512^2 rotating-disk time loop (100 steps, dt 1e-3; FP64 and
              mixed, and FP64 with the time-coherent coupling), the nonlinear bar at 256^2
-             (Newton, the paper's exponential law);
+             (Newton, the paper's exponential law), and the paper's own element pair (Q2 /
+             P1-disc fluid, Q1 solid) on a 256^2 bar with a bending-and-turning motion;
   serving    the 512-request trace in mixed precision and in FP64;
   accuracy   per-run errors against the FP64 oracle (computed in the oracle leg);
   cpu_baseline / cpu_serving  the oracle on the host's cores (bounded samples).
