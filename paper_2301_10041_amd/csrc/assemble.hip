@@ -14,6 +14,7 @@
 #include "ctx.h"
 #include "kernels.h"
 #include "lattice.h"
+#include "q2.h"
 #include "stencil.h"
 
 namespace fsi {
@@ -1117,7 +1118,7 @@ size_t Mg::bytes() const {
   size_t b = cinv.bytes() + cinv32.bytes() + rtab64.bytes() + rtab32.bytes();
   for (auto &L : lv) {
     b += L.A.bytes() + L.P.bytes() + L.R.bytes() + L.dinv.bytes() + L.dinv32.bytes() + L.stab64.bytes() +
-         L.stab32.bytes() + L.p1tab64.bytes() + L.p1tab32.bytes();
+         L.stab32.bytes() + L.p1tab64.bytes() + L.p1tab32.bytes() + L.q2tab64.bytes() + L.q2tab32.bytes();
     for (int i = 0; i < 5; ++i) b += L.w64[i].bytes() + L.w32[i].bytes();
   }
   return b;
@@ -1572,6 +1573,122 @@ void build_fluid_q2(Ctx &c) {
   FSI_HIP(hipStreamSynchronize(s));
 }
 
+// Class stencils of the Q2 A_f: the row of an interior node of each class summed over its cells
+// as k_asm_q2q2 sums them (node (2 + a, 2 + b) of class a + 2 b has every cell inside for n >= 2).
+void q2_tables(int n, double nu, double rdt, Q2Table<double> &t64, Q2Table<float> &t32) {
+  FSI_REQUIRE(n >= 2, FSI_E_ARG, "Q2 class stencils need n >= 2");
+  std::vector<double> E;
+  q2_element_table(n, nu, E);
+  std::memset(&t64, 0, sizeof(t64));
+  std::memset(&t32, 0, sizeof(t32));
+  for (int cls = 0; cls < 4; ++cls) {
+    const int I = 2 + (cls & 1), J = 2 + (cls >> 1);
+    const int i0 = std::max(0, (I - 1) >> 1), i1 = std::min(n - 1, I >> 1);
+    const int j0 = std::max(0, (J - 1) >> 1), j1 = std::min(n - 1, J >> 1);
+    int cnt = 0;
+    for (int J2 = 2 * j0; J2 <= 2 * j1 + 2; ++J2)
+      for (int I2 = 2 * i0; I2 <= 2 * i1 + 2; ++I2) {
+        double m = 0.0, kk[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int cj = j0; cj <= j1; ++cj) {
+          const int b = J - 2 * cj, b2 = J2 - 2 * cj;
+          if (b2 < 0 || b2 > 2) continue;
+          for (int ci = i0; ci <= i1; ++ci) {
+            const int a = I - 2 * ci, a2 = I2 - 2 * ci;
+            if (a2 < 0 || a2 > 2) continue;
+            const int li = a + 3 * b, lj = a2 + 3 * b2;
+            m += E[QE_M + 9 * li + lj];
+            for (int q = 0; q < 4; ++q) kk[q] += E[QE_K + (q * 9 + li) * 9 + lj];
+          }
+        }
+        FSI_REQUIRE(cnt < kQ2Max, FSI_E_ARG, "Q2 stencil too wide");
+        const double v[4] = {rdt * m + kk[0], kk[1], kk[2], rdt * m + kk[3]};
+        t64.off[cls][cnt][0] = t32.off[cls][cnt][0] = I2 - I;
+        t64.off[cls][cnt][1] = t32.off[cls][cnt][1] = J2 - J;
+        for (int q = 0; q < 4; ++q) {
+          t64.coef[cls][cnt][q] = v[q];
+          t32.coef[cls][cnt][q] = (float)v[q];
+        }
+        if (I2 == I && J2 == J) {
+          const double det = v[0] * v[3] - v[1] * v[2];
+          const double di[4] = {v[3] / det, -v[1] / det, -v[2] / det, v[0] / det};
+          for (int q = 0; q < 4; ++q) {
+            t64.dinv[cls][q] = di[q];
+            t32.dinv[cls][q] = (float)di[q];
+          }
+        }
+        ++cnt;
+      }
+    t64.count[cls] = t32.count[cls] = cnt;
+  }
+}
+
+// One thread per lattice node; the table staged in LDS (the lanes of a wave take different
+// classes).  Interior rows: the class stencil without the Dirichlet neighbours; boundary rows:
+// the identity.
+template <typename T, bool RESID>
+__global__ void __launch_bounds__(256) k_q2_stencil(int n, const Q2Table<T> *__restrict__ tab, const T *__restrict__ x,
+                                                    const T *__restrict__ b, T *__restrict__ d, T *__restrict__ y,
+                                                    T c1, T c2) {
+  __shared__ Q2Table<T> t;
+  {
+    const int *src = (const int *)tab;
+    int *dst = (int *)&t;
+    for (int k = threadIdx.x; k < (int)(sizeof(Q2Table<T>) / sizeof(int)); k += blockDim.x) dst[k] = src[k];
+  }
+  __syncthreads();
+  const int64_t L = 2 * n + 1, N = L * L;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const int I = (int)(r % L), J = (int)(r / L);
+  T r0, r1, z0, z1;
+  if (I == 0 || J == 0 || I == 2 * n || J == 2 * n) {
+    r0 = b[r] - x[r];
+    r1 = b[N + r] - x[N + r];
+    z0 = r0;
+    z1 = r1;
+  } else {
+    const int cls = (I & 1) + 2 * (J & 1);
+    T s0 = 0, s1 = 0;
+    for (int k = 0; k < t.count[cls]; ++k) {
+      const int I2 = I + t.off[cls][k][0], J2 = J + t.off[cls][k][1];
+      if (I2 == 0 || J2 == 0 || I2 == 2 * n || J2 == 2 * n) continue;
+      const int64_t j = (int64_t)J2 * L + I2;
+      const T x0 = x[j], x1 = x[N + j];
+      s0 += t.coef[cls][k][0] * x0 + t.coef[cls][k][1] * x1;
+      s1 += t.coef[cls][k][2] * x0 + t.coef[cls][k][3] * x1;
+    }
+    r0 = b[r] - s0;
+    r1 = b[N + r] - s1;
+    z0 = t.dinv[cls][0] * r0 + t.dinv[cls][1] * r1;
+    z1 = t.dinv[cls][2] * r0 + t.dinv[cls][3] * r1;
+  }
+  if constexpr (RESID) {
+    y[r] = r0;
+    y[N + r] = r1;
+  } else {
+    const T d0 = c1 * d[r] + c2 * z0, d1 = c1 * d[N + r] + c2 * z1;
+    d[r] = d0;
+    d[N + r] = d1;
+    y[r] = x[r] + d0;
+    y[N + r] = x[N + r] + d1;
+  }
+}
+
+template <typename T>
+void q2_stencil(int n, const Q2Table<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2, bool resid,
+                hipStream_t s) {
+  const int64_t N = (int64_t)(2 * n + 1) * (2 * n + 1);
+  if (resid)
+    hipLaunchKernelGGL((k_q2_stencil<T, true>), dim3(grid_for(N, 256)), dim3(256), 0, s, n, tab, x, b, d, y, c1, c2);
+  else
+    hipLaunchKernelGGL((k_q2_stencil<T, false>), dim3(grid_for(N, 256)), dim3(256), 0, s, n, tab, x, b, d, y, c1, c2);
+  FSI_CHECK_LAUNCH();
+}
+template void q2_stencil<double>(int, const Q2Table<double> *, const double *, const double *, double *, double *,
+                                 double, double, bool, hipStream_t);
+template void q2_stencil<float>(int, const Q2Table<float> *, const float *, const float *, float *, float *, float,
+                                float, bool, hipStream_t);
+
 // Coarse Q2 weights at fine lattice node (I, J) of an nf grid: the coarse cell's biquadratic
 // basis at the fine node (local coordinates multiples of 1/4: exact binary fractions), interior
 // coarse nodes only, in ascending coarse index.
@@ -1716,6 +1833,13 @@ void build_multigrid_q2(Ctx &c) {
                        U.A.col.p, U.A.val.p, U.dinv.p);
     FSI_CHECK_LAUNCH();
     U.lmax = 1.1 * power_lmax(U, 2, s);
+    if (m >= 2) {   // the class stencils of the smoothing steps and residuals
+      Q2Table<double> t64;
+      Q2Table<float> t32;
+      q2_tables(m, c.nu, c.rho / c.dt, t64, t32);
+      upload_bytes(U.q2tab64, &t64, sizeof(t64), s);
+      upload_bytes(U.q2tab32, &t32, sizeof(t32), s);
+    }
     if (l + 1 < ns.size()) {
       const int64_t nc2 = (int64_t)(m + 1) * (m + 1);
       const unsigned gf2 = grid_for(U.nodes, 256), gc2 = grid_for(nc2, 256);

@@ -33,6 +33,7 @@ struct MgLevel {
   DevBuf<float> w32[5];
   DevBuf<unsigned char> stab64, stab32;   // StencilTable<double/float> (velocity levels)
   DevBuf<unsigned char> p1tab64, p1tab32; // P1Table<double/float> of L_p (pressure levels)
+  DevBuf<unsigned char> q2tab64, q2tab32; // Q2Table<double/float> (velocity levels of the Q2 pair)
 };
 
 struct Mg {

@@ -1,0 +1,32 @@
+// The velocity operator of the paper's element pair (Q2 on the n x n squares) in class form:
+// an interior Q2 node of class c = (I & 1) + 2 (J & 1) (vertex, x-edge midpoint, y-edge midpoint,
+// centre) couples with the nodes of the 4, 2, 2 or 1 cells around it (25, 15, 15 or 9 offsets in
+// [-2, 2]^2); every interior row of A_f = (rho/dt) M_f + K_f is the class's stencil with the
+// Dirichlet neighbours left out, and a boundary row is the identity.
+#pragma once
+
+#include "common.h"
+
+namespace fsi {
+
+constexpr int kQ2Max = 25;
+
+template <typename T>
+struct Q2Table {
+  int count[4];
+  int off[4][kQ2Max][2];   // (dI, dJ), dJ major
+  T coef[4][kQ2Max][4];    // 2 x 2 blocks: xx, xy, yx, yy
+  T dinv[4][4];            // inverse of the diagonal block
+};
+
+// One pass over the velocity lattice of an n x n grid (components at x and x + (2n+1)^2):
+//   resid: y = b - A x
+//   else:  d = c1 d + c2 D^{-1} (b - A x), y = x + d   (a Chebyshev step)
+template <typename T>
+void q2_stencil(int n, const Q2Table<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2, bool resid,
+                hipStream_t s);
+
+// Host: the class stencils of A_f on an n x n grid (n >= 2) from the Q2 element matrices.
+void q2_tables(int n, double nu, double rdt, Q2Table<double> &t64, Q2Table<float> &t32);
+
+}  // namespace fsi

@@ -27,6 +27,7 @@
 #include "ctx.h"
 #include "kernels.h"
 #include "lattice.h"
+#include "q2.h"
 #include "stencil.h"
 
 namespace fsi {
@@ -243,6 +244,31 @@ static T *chebyshev(int64_t nrows, const int *rp, const int *col, const T *val, 
 
 // The same Chebyshev iteration with matrix-free products: first(scale, d, x) does the
 // step from zero (d = x = scale D^{-1} b), step(x, x2, c1, c2) one step from x into x2.
+// The same iteration on the velocity levels of the Q2 pair with the class stencils
+// (q2_stencil) in place of the assembled rows; the first step from zero as chebyshev's.
+template <typename T>
+static T *chebyshev_q2(const MgLevel &L, const Q2Table<T> *tab, const T *dinv, double lmin, double lmax, int steps,
+                       const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s) {
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (zero_init) {
+    hipLaunchKernelGGL((k_dinv_first<T, 4, 2>), dim3(grid_for(L.nodes, 256)), dim3(256), 0, s, L.nodes, dinv, b,
+                       (T)(1.0 / theta), d, x);
+    FSI_CHECK_LAUNCH();
+  } else {
+    q2_stencil<T>(L.n, tab, x, b, d, x2, (T)0, (T)(1.0 / theta), false, s);
+    std::swap(x, x2);
+  }
+  for (int k = 1; k < steps; ++k) {
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    q2_stencil<T>(L.n, tab, x, b, d, x2, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), false, s);
+    std::swap(x, x2);
+    rho = rho1;
+  }
+  return x;
+}
+
 template <typename T, typename First, typename Step>
 static T *chebyshev_mf(First first, Step step, double lmin, double lmax, int steps, T *x, T *x2,
                        bool zero_init, hipStream_t s, Prof *prof) {
@@ -614,15 +640,22 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
     }
     return smooth(xs, xo, false, fuse ? xc : nullptr);
   }
-  T *xs = chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b, x,
-                              x2, d, true, s, pl);
+  // the Q2 pair's velocity levels: class stencils for the smoothing steps and the residual
+  const Q2Table<T> *q2 = nullptr;
+  if constexpr (W == 4)
+    q2 = (const Q2Table<T> *)(std::is_same<T, double>::value ? L.q2tab64.p : L.q2tab32.p);
+  T *xs = q2 ? chebyshev_q2<T>(L, q2, dinv, lmin, lmax, degree, b, x, x2, d, true, s)
+             : chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b, x,
+                                   x2, d, true, s, pl);
   T *xo = (xs == x) ? x2 : x;
-  spmv<T, W, NC, SP_RESID>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, xs, L.nodes, r, L.nodes, s, b);
+  if (q2) q2_stencil<T>(L.n, q2, xs, b, nullptr, r, (T)0, (T)0, true, s);
+  else spmv<T, W, NC, SP_RESID>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, xs, L.nodes, r, L.nodes, s, b);
   spmv<T, 1, NC, SP_APPLY>(L.R.nrows, L.R.rowptr.p, L.R.col.p, Pr<T>::val(L.R), r, L.nodes, bc,
                            C.nodes, s);
   T *xc = vcycle<T, W, NC>(mg, l + 1, bc, s);
   spmv<T, 1, NC, SP_ADD>(L.P.nrows, L.P.rowptr.p, L.P.col.p, Pr<T>::val(L.P), xc, C.nodes, xs,
                          L.nodes, s);
+  if (q2) return chebyshev_q2<T>(L, q2, dinv, lmin, lmax, degree, b, xs, xo, d, false, s);
   return chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b,
                              xs, xo, d, false, s, pl);
 }
