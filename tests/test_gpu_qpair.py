@@ -196,3 +196,65 @@ def test_q_time_loop():
         assert_block_parity(S, to_host(out), ref[k], 1e-8, f"step {k}")
         u = out[:2 * S.lay.N2].clone()
     ctx.close()
+
+
+def test_q_fullsize_qbar256():
+    """The measured 256^2 bar at a position of its loop: A_f, M_f, B and B^T whole against the
+    oracle's assembly (patterns exactly, values to 1e-12); the pieces of 60 sampled
+    quadrilaterals bitwise and the C_f rows of 40 sampled solid nodes to 1e-12, each computed by
+    the oracle from the quadrilaterals involved alone (the whole oracle coupling takes about a
+    minute on one core)."""
+    wl = inputs.QWORKLOADS["qbar256"]
+    n = wl.n
+    xy, quad = wl.solid_mesh()
+    # the loop's position at step 3: bent by 0.02 and turned at 0.5 rad/s about the centre
+    X = inputs.rotation(inputs.bent(xy, 0.02, 0.4, wl.x0), wl.center, 0.5 * 3 * wl.dt)
+    print(f"[Q pair full size qbar256: n={n} Nq={quad.shape[0]}]", flush=True)
+    ctx = _ctx(wl)
+    F = qpair.assemble_fluid(n, nu=wl.nu, rho=wl.rho, dt=wl.dt)
+    rp, col, val = ctx.export_csr("AF")
+    scale = abs(F["Af_blocks"][(0, 0)].data).max()
+    for k, key in enumerate([(0, 0), (0, 1), (1, 0), (1, 1)]):
+        _same_pattern(rp, col, F["Af_blocks"][key])
+        assert np.abs(val[:, k] - F["Af_blocks"][key].tocsr().data).max() <= 1e-12 * scale, key
+    rp, col, val = ctx.export_csr("B")
+    for k, B in enumerate([F["Bx_bc"], F["By_bc"]]):
+        _same_pattern(rp, col, B)
+        assert np.abs(val[:, k] - B.tocsr().data).max() <= 1e-12 * abs(B.data).max()
+    del F
+    ctx.assemble_coupling(to_dev(soa(X)))
+    E, T = ctx.export_pairs()
+    rng = np.random.default_rng(23)
+    # pieces of sampled quadrilaterals, in the canonical order of each
+    for e in rng.choice(quad.shape[0], 60, replace=False):
+        P = [tuple(X[k]) for k in quad[e]]
+        i0, i1, j0, j1 = qpair.cell_range(P, n)
+        ref = [j * n + i for j in range(j0, j1 + 1) for i in range(i0, i1 + 1)
+               if qpair.cell_piece(P, n, i, j) is not None]
+        assert np.array_equal(T[E == e], ref), e
+    # C_f rows of sampled solid nodes from the pieces of the quadrilaterals around each
+    rp, col, val = ctx.export_csr("CF")
+    q2, _ = qpair.cell_nodes(n)
+    L2 = 2 * n + 1
+    for l in rng.choice(xy.shape[0], 40, replace=False):
+        row = {}
+        for e in np.flatnonzero((quad == l).any(axis=1)):
+            a = int(np.flatnonzero(quad[e] == l)[0])
+            P = [tuple(X[k]) for k in quad[e]]
+            i0, i1, j0, j1 = qpair.cell_range(P, n)
+            for j in range(j0, j1 + 1):
+                for i in range(i0, i1 + 1):
+                    q = qpair.cell_piece(P, n, i, j)
+                    if q is None:
+                        continue
+                    Lm = qpair.piece_matrix(X[quad[e]], xy[quad[e]], q, i, j, n)
+                    for b in range(9):
+                        c = int(q2[j * n + i, b])
+                        row[c] = row.get(c, 0.0) + Lm[a, b]
+        cols = np.array(sorted(row), dtype=np.int32)
+        ref = np.array([0.0 if (c % L2 in (0, 2 * n) or c // L2 in (0, 2 * n)) else row[c] for c in cols])
+        got_c = col[rp[l]:rp[l + 1]]
+        got_v = val[rp[l]:rp[l + 1], 0]
+        assert np.array_equal(got_c, cols), l
+        assert np.abs(got_v - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300), l
+    ctx.close()
