@@ -419,9 +419,12 @@ int fsi_export_csr(fsi_ctx *ctx, int block, int64_t *nrows, int64_t *nnz, int32_
  *               (2i, 2j); vals = (B_x, B_y); Dirichlet columns are applied by the caller.
  *   FSI_LAT_R:  P2 restriction R = P^T at interior coarse nodes by parity class; offsets of
  *               fine nodes from (2 Ic, 2 Jc) in fine lattice units; vals[.][0] = weight.
+ *   FSI_LAT_Q2AF: A_f of the paper's element pair (Q2 on squares, fsi_create_q2) at interior
+ *               nodes by parity class (vertex, x-edge, y-edge, centre: 25, 15, 15, 9 entries);
+ *               offsets and vals as FSI_LAT_AF.
  * Errors: FSI_E_ARG (n outside [2, 4096], unknown table, null buffer). */
 enum fsi_lattice_table { FSI_LAT_AF = 0, FSI_LAT_LP = 1, FSI_LAT_MP = 2, FSI_LAT_BT = 3, FSI_LAT_B = 4,
-                         FSI_LAT_R = 5 };
+                         FSI_LAT_R = 5, FSI_LAT_Q2AF = 6 };
 #define FSI_LAT_MAX_ENTRIES 81
 int fsi_export_lattice(int32_t n, double nu, double rdt, int32_t table, int32_t *counts, int32_t *offs,
                        double *vals);

@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "ctx.h"
+#include "q2.h"
 #include "lattice.h"
 #include "stencil.h"
 #include "kernels.h"
@@ -686,6 +687,20 @@ int fsi_export_lattice(int32_t n, double nu, double rdt, int32_t table, int32_t 
             offs[(c * E + k) * 2] = t.off[c][k][0];
             offs[(c * E + k) * 2 + 1] = t.off[c][k][1];
             vals[(c * E + k) * 4] = t.w[c][k];
+          }
+        }
+        break;
+      }
+      case FSI_LAT_Q2AF: {
+        fsi::Q2Table<double> t;
+        fsi::Q2Table<float> tf;
+        fsi::q2_tables(n, nu, rdt, t, tf);
+        for (int c = 0; c < 4; ++c) {
+          counts[c] = t.count[c];
+          for (int k = 0; k < t.count[c]; ++k) {
+            offs[(c * E + k) * 2] = t.off[c][k][0];
+            offs[(c * E + k) * 2 + 1] = t.off[c][k][1];
+            for (int q = 0; q < 4; ++q) vals[(c * E + k) * 4 + q] = t.coef[c][k][q];
           }
         }
         break;

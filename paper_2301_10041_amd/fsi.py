@@ -179,7 +179,7 @@ def _stream_handle(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-LAT_AF, LAT_LP, LAT_MP, LAT_BT, LAT_B, LAT_R = 0, 1, 2, 3, 4, 5
+LAT_AF, LAT_LP, LAT_MP, LAT_BT, LAT_B, LAT_R, LAT_Q2AF = 0, 1, 2, 3, 4, 5, 6
 LAT_MAX_ENTRIES = 81
 
 

@@ -45,6 +45,37 @@ def test_af_stencils_reproduce_the_assembled_af(n):
     assert np.abs(A - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("n", [2, 4, 7])
+def test_q2_class_stencils_reproduce_the_assembled_af(n):
+    """The class stencils of the paper's element pair (the velocity levels of its V-cycles)
+    rebuild the oracle's Q2 A_f (Dirichlet rows and columns applied by position)."""
+    from oracle import qpair
+    F = qpair.assemble_fluid(n, nu=0.7, rho=RHO, dt=DT)
+    counts, offs, vals = fsi.export_lattice(n, fsi.LAT_Q2AF, nu=0.7, rdt=RHO / DT)
+    L = 2 * n + 1
+    N2 = L * L
+    A = np.zeros((2 * N2, 2 * N2))
+    for J in range(L):
+        for I in range(L):
+            r = J * L + I
+            if _p2_boundary(n, I, J):
+                A[r, r] = A[N2 + r, N2 + r] = 1.0
+                continue
+            c = (I & 1) | ((J & 1) << 1)
+            for k in range(counts[c]):
+                I2, J2 = I + offs[c, k, 0], J + offs[c, k, 1]
+                if _p2_boundary(n, I2, J2):
+                    continue
+                q = J2 * L + I2
+                A[r, q] += vals[c, k, 0]
+                A[r, N2 + q] += vals[c, k, 1]
+                A[N2 + r, q] += vals[c, k, 2]
+                A[N2 + r, N2 + q] += vals[c, k, 3]
+    ref = F["Af"].toarray()
+    assert list(counts[:4]) == [25, 15, 15, 9]
+    assert np.abs(A - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 def _from_p1_table(n, counts, offs, vals, pin):
     L = n + 1
     A = np.zeros((L * L, L * L))
