@@ -609,10 +609,18 @@ def qpair_leg(args, fsi, inputs, torch, dev, save):
            "solid_quadrilaterals": int(quad.shape[0]), "steps": steps, "dt": wl.dt}
     u0 = vec(inputs.uniform(2 * N2, wl.seed))
     for tag, prec in (("fp64", fsi.FP64), ("mixed", fsi.FP32)):
-        r, _ = time_loop(ctx, u0, Xs, N2, fsi.Opts(pc=fsi.PC_TRI, prec=prec, rtol=1e-8), 1, steps, f"qbar256 {tag}")
+        r, _ = time_loop(ctx, u0, Xs, N2, fsi.Opts(pc=fsi.PC_TRI, prec=prec, rtol=1e-8), 1, steps, f"qbar256 {tag}",
+                         profile=True)
         rec[tag] = dict(steps_per_s=r["value"], ms_per_step=r["ms_per_step"], t_coup_ms=r["t_coup_ms"],
                         t_sol_ms=r["t_solve_ms"], its_mean=sum(r["its"]) / steps, its_max=max(r["its"]),
                         inner_its_mean=sum(r["inner_its"]) / steps, relres_true_max=r["relres_true"])
+        k = r.get("kernel")
+        if k and k["launches"]:   # the finest velocity level's class-stencil Chebyshev step (HIP events)
+            rec[tag]["roofline"] = dict(
+                bound="hbm", kernel="k_q2_stencil (finest velocity level, one Chebyshev step: x, b, d read, d, y "
+                                    "written)", launches=k["launches"], avg_us=k["avg_us"],
+                bytes_per_launch=k["bytes_per_launch"], achieved=k["achieved_gbs"], peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=k["achieved_gbs"] / HBM_PEAK_GBS)
     sz = ctx.refresh_sizes()
     rec["pieces"] = sz["n_pairs"]
     rec["nnz_Cf"] = sz["nnz_Cf"]

@@ -776,10 +776,11 @@ int fsi_profile_read(fsi_ctx *ctx, int prec, int64_t *launches, double *total_ms
     const double wy = (prec == FSI_FP32 && degree == 3) ? 8.0 : w;
     const double wd = degree > 3 ? w : 0.0;
     const double coarse = (degree >= 3 && c.mgu.lv.size() > 1) ? (double)c.mgu.lv[1].nodes * 2 * w : 0.0;
+    // the class-stencil step of the Q2 pair: x, b and d read, d and y written (two components)
     if (bytes_per_launch)
-      *bytes_per_launch = c.mgu.stencil
-                              ? (double)L.nodes * 2 * (2 * w + wd + wy) + coarse
-                              : (double)L.A.nnz * (4 * w + 4) + (double)L.nodes * (4 + 14 * w) + 4.0;
+      *bytes_per_launch = c.mgu.stencil ? (double)L.nodes * 2 * (2 * w + wd + wy) + coarse
+                          : L.q2tab64.p ? (double)L.nodes * 2 * 5 * w
+                                        : (double)L.A.nnz * (4 * w + 4) + (double)L.nodes * (4 + 14 * w) + 4.0;
   });
 }
 

@@ -248,7 +248,7 @@ static T *chebyshev(int64_t nrows, const int *rp, const int *col, const T *val, 
 // (q2_stencil) in place of the assembled rows; the first step from zero as chebyshev's.
 template <typename T>
 static T *chebyshev_q2(const MgLevel &L, const Q2Table<T> *tab, const T *dinv, double lmin, double lmax, int steps,
-                       const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s) {
+                       const T *b, T *x, T *x2, T *d, bool zero_init, hipStream_t s, Prof *prof = nullptr) {
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
@@ -257,12 +257,16 @@ static T *chebyshev_q2(const MgLevel &L, const Q2Table<T> *tab, const T *dinv, d
                        (T)(1.0 / theta), d, x);
     FSI_CHECK_LAUNCH();
   } else {
+    if (prof) prof->begin(s);
     q2_stencil<T>(L.n, tab, x, b, d, x2, (T)0, (T)(1.0 / theta), false, s);
+    if (prof) prof->end(s);
     std::swap(x, x2);
   }
   for (int k = 1; k < steps; ++k) {
     const double rho1 = 1.0 / (2.0 * sigma - rho);
+    if (prof) prof->begin(s);
     q2_stencil<T>(L.n, tab, x, b, d, x2, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), false, s);
+    if (prof) prof->end(s);
     std::swap(x, x2);
     rho = rho1;
   }
@@ -644,7 +648,7 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
   const Q2Table<T> *q2 = nullptr;
   if constexpr (W == 4)
     q2 = (const Q2Table<T> *)(std::is_same<T, double>::value ? L.q2tab64.p : L.q2tab32.p);
-  T *xs = q2 ? chebyshev_q2<T>(L, q2, dinv, lmin, lmax, degree, b, x, x2, d, true, s)
+  T *xs = q2 ? chebyshev_q2<T>(L, q2, dinv, lmin, lmax, degree, b, x, x2, d, true, s, pl)
              : chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b, x,
                                    x2, d, true, s, pl);
   T *xo = (xs == x) ? x2 : x;
@@ -655,7 +659,7 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
   T *xc = vcycle<T, W, NC>(mg, l + 1, bc, s);
   spmv<T, 1, NC, SP_ADD>(L.P.nrows, L.P.rowptr.p, L.P.col.p, Pr<T>::val(L.P), xc, C.nodes, xs,
                          L.nodes, s);
-  if (q2) return chebyshev_q2<T>(L, q2, dinv, lmin, lmax, degree, b, xs, xo, d, false, s);
+  if (q2) return chebyshev_q2<T>(L, q2, dinv, lmin, lmax, degree, b, xs, xo, d, false, s, pl);
   return chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b,
                              xs, xo, d, false, s, pl);
 }
