@@ -1604,9 +1604,10 @@ void q2_tables(int n, double nu, double rdt, Q2Table<double> &t64, Q2Table<float
         const double v[4] = {rdt * m + kk[0], kk[1], kk[2], rdt * m + kk[3]};
         t64.off[cls][cnt][0] = t32.off[cls][cnt][0] = I2 - I;
         t64.off[cls][cnt][1] = t32.off[cls][cnt][1] = J2 - J;
+        const int dk = (I2 - I + 2) + 5 * (J2 - J + 2);
         for (int q = 0; q < 4; ++q) {
-          t64.coef[cls][cnt][q] = v[q];
-          t32.coef[cls][cnt][q] = (float)v[q];
+          t64.coef[cls][cnt][q] = t64.dense[cls][dk][q] = v[q];
+          t32.coef[cls][cnt][q] = t32.dense[cls][dk][q] = (float)v[q];
         }
         if (I2 == I && J2 == J) {
           const double det = v[0] * v[3] - v[1] * v[2];
@@ -1622,24 +1623,35 @@ void q2_tables(int n, double nu, double rdt, Q2Table<double> &t64, Q2Table<float
   }
 }
 
-// One thread per lattice node; the table staged in LDS (the lanes of a wave take different
-// classes).  Interior rows: the class stencil without the Dirichlet neighbours; boundary rows:
-// the identity.
+// A tile of kQ2TW x kQ2TH lattice nodes per workgroup, one thread per node: x of the tile and a
+// halo of two nodes staged in LDS (two components; Dirichlet and outside nodes stored as zero,
+// which leaves them out of every row), the class's 2 x 2 blocks on the full 5 x 5 window with
+// compile-time LDS offsets (the entries a class lacks are zero).  Boundary rows: the identity.
+constexpr int kQ2TW = 64, kQ2TH = 4, kQ2SW = kQ2TW + 4, kQ2SH = kQ2TH + 4;
 template <typename T, bool RESID>
-__global__ void __launch_bounds__(256) k_q2_stencil(int n, const Q2Table<T> *__restrict__ tab, const T *__restrict__ x,
-                                                    const T *__restrict__ b, T *__restrict__ d, T *__restrict__ y,
-                                                    T c1, T c2) {
-  __shared__ Q2Table<T> t;
-  {
-    const int *src = (const int *)tab;
-    int *dst = (int *)&t;
-    for (int k = threadIdx.x; k < (int)(sizeof(Q2Table<T>) / sizeof(int)); k += blockDim.x) dst[k] = src[k];
+__global__ void __launch_bounds__(kQ2TW * kQ2TH) k_q2_stencil(int n, const Q2Table<T> *__restrict__ tab,
+                                                             const T *__restrict__ x, const T *__restrict__ b,
+                                                             T *__restrict__ d, T *__restrict__ y, T c1, T c2) {
+  __shared__ T cs[4][25][4];
+  __shared__ T dv[4][4];
+  __shared__ T xs[2][kQ2SH * kQ2SW];
+  const int tid = threadIdx.x;
+  for (int k = tid; k < 4 * 25 * 4; k += kQ2TW * kQ2TH) (&cs[0][0][0])[k] = (&tab->dense[0][0][0])[k];
+  if (tid < 16) (&dv[0][0])[tid] = (&tab->dinv[0][0])[tid];
+  const int64_t L = 2 * n + 1, N = L * L;
+  const int I0 = blockIdx.x * kQ2TW, J0 = blockIdx.y * kQ2TH;
+  for (int k = tid; k < kQ2SH * kQ2SW; k += kQ2TW * kQ2TH) {
+    const int I = I0 - 2 + k % kQ2SW, J = J0 - 2 + k / kQ2SW;
+    const bool in = I > 0 && J > 0 && I < 2 * n && J < 2 * n;
+    const int64_t j = (int64_t)J * L + I;
+    xs[0][k] = in ? x[j] : (T)0;
+    xs[1][k] = in ? x[N + j] : (T)0;
   }
   __syncthreads();
-  const int64_t L = 2 * n + 1, N = L * L;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= N) return;
-  const int I = (int)(r % L), J = (int)(r / L);
+  const int tx = tid % kQ2TW, ty = tid / kQ2TW;
+  const int I = I0 + tx, J = J0 + ty;
+  if (I >= L || J >= L) return;
+  const int64_t r = (int64_t)J * L + I;
   T r0, r1, z0, z1;
   if (I == 0 || J == 0 || I == 2 * n || J == 2 * n) {
     r0 = b[r] - x[r];
@@ -1648,19 +1660,22 @@ __global__ void __launch_bounds__(256) k_q2_stencil(int n, const Q2Table<T> *__r
     z1 = r1;
   } else {
     const int cls = (I & 1) + 2 * (J & 1);
+    const T(*c)[4] = cs[cls];
+    const T *x0p = &xs[0][ty * kQ2SW + tx], *x1p = &xs[1][ty * kQ2SW + tx];
     T s0 = 0, s1 = 0;
-    for (int k = 0; k < t.count[cls]; ++k) {
-      const int I2 = I + t.off[cls][k][0], J2 = J + t.off[cls][k][1];
-      if (I2 == 0 || J2 == 0 || I2 == 2 * n || J2 == 2 * n) continue;
-      const int64_t j = (int64_t)J2 * L + I2;
-      const T x0 = x[j], x1 = x[N + j];
-      s0 += t.coef[cls][k][0] * x0 + t.coef[cls][k][1] * x1;
-      s1 += t.coef[cls][k][2] * x0 + t.coef[cls][k][3] * x1;
-    }
+#pragma unroll
+    for (int dJ = 0; dJ < 5; ++dJ)
+#pragma unroll
+      for (int dI = 0; dI < 5; ++dI) {
+        const int k = dI + 5 * dJ, o = dJ * kQ2SW + dI;
+        const T x0 = x0p[o], x1 = x1p[o];
+        s0 += c[k][0] * x0 + c[k][1] * x1;
+        s1 += c[k][2] * x0 + c[k][3] * x1;
+      }
     r0 = b[r] - s0;
     r1 = b[N + r] - s1;
-    z0 = t.dinv[cls][0] * r0 + t.dinv[cls][1] * r1;
-    z1 = t.dinv[cls][2] * r0 + t.dinv[cls][3] * r1;
+    z0 = dv[cls][0] * r0 + dv[cls][1] * r1;
+    z1 = dv[cls][2] * r0 + dv[cls][3] * r1;
   }
   if constexpr (RESID) {
     y[r] = r0;
@@ -1677,11 +1692,12 @@ __global__ void __launch_bounds__(256) k_q2_stencil(int n, const Q2Table<T> *__r
 template <typename T>
 void q2_stencil(int n, const Q2Table<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2, bool resid,
                 hipStream_t s) {
-  const int64_t N = (int64_t)(2 * n + 1) * (2 * n + 1);
+  const int L = 2 * n + 1;
+  const dim3 grid((unsigned)((L + kQ2TW - 1) / kQ2TW), (unsigned)((L + kQ2TH - 1) / kQ2TH));
   if (resid)
-    hipLaunchKernelGGL((k_q2_stencil<T, true>), dim3(grid_for(N, 256)), dim3(256), 0, s, n, tab, x, b, d, y, c1, c2);
+    hipLaunchKernelGGL((k_q2_stencil<T, true>), grid, dim3(kQ2TW * kQ2TH), 0, s, n, tab, x, b, d, y, c1, c2);
   else
-    hipLaunchKernelGGL((k_q2_stencil<T, false>), dim3(grid_for(N, 256)), dim3(256), 0, s, n, tab, x, b, d, y, c1, c2);
+    hipLaunchKernelGGL((k_q2_stencil<T, false>), grid, dim3(kQ2TW * kQ2TH), 0, s, n, tab, x, b, d, y, c1, c2);
   FSI_CHECK_LAUNCH();
 }
 template void q2_stencil<double>(int, const Q2Table<double> *, const double *, const double *, double *, double *,

@@ -17,6 +17,8 @@ struct Q2Table {
   int off[4][kQ2Max][2];   // (dI, dJ), dJ major
   T coef[4][kQ2Max][4];    // 2 x 2 blocks: xx, xy, yx, yy
   T dinv[4][4];            // inverse of the diagonal block
+  T dense[4][25][4];       // the same blocks on the full 5 x 5 window, entry (dI + 2) + 5 (dJ + 2) (zero
+                           // where the class has no neighbour)
 };
 
 // One pass over the velocity lattice of an n x n grid (components at x and x + (2n+1)^2):
