@@ -1118,7 +1118,8 @@ size_t Mg::bytes() const {
   size_t b = cinv.bytes() + cinv32.bytes() + rtab64.bytes() + rtab32.bytes();
   for (auto &L : lv) {
     b += L.A.bytes() + L.P.bytes() + L.R.bytes() + L.dinv.bytes() + L.dinv32.bytes() + L.stab64.bytes() +
-         L.stab32.bytes() + L.p1tab64.bytes() + L.p1tab32.bytes() + L.q2tab64.bytes() + L.q2tab32.bytes();
+         L.stab32.bytes() + L.p1tab64.bytes() + L.p1tab32.bytes() + L.q2tab64.bytes() + L.q2tab32.bytes() +
+         L.pdst64.bytes() + L.pdst32.bytes();
     for (int i = 0; i < 5; ++i) b += L.w64[i].bytes() + L.w32[i].bytes();
   }
   return b;
@@ -1700,6 +1701,61 @@ void q2_stencil(int n, const Q2Table<T> *tab, const T *x, const T *b, T *d, T *y
     hipLaunchKernelGGL((k_q2_stencil<T, false>), grid, dim3(kQ2TW * kQ2TH), 0, s, n, tab, x, b, d, y, c1, c2);
   FSI_CHECK_LAUNCH();
 }
+// One thread per row of L; the three unknowns of a cell read the same 27 neighbours (through
+// the caches).
+template <typename T, bool RESID>
+__global__ void __launch_bounds__(256) k_pd_stencil(int n, const T *__restrict__ st, const int *__restrict__ rp,
+                                                    const int *__restrict__ col, const T *__restrict__ val,
+                                                    const T *__restrict__ dinv, const T *__restrict__ x,
+                                                    const T *__restrict__ b, T *__restrict__ d, T *__restrict__ y,
+                                                    T c1, T c2) {
+  const int64_t np = 3 * (int64_t)n * n;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= np) return;
+  const int64_t cell = r / 3;
+  const int q = (int)(r % 3), ci = (int)(cell % n), cj = (int)(cell / n);
+  T s = 0;
+  // cell (1, 1) touches cell 0, whose constant is the pinned unknown (a zero column of L)
+  if (ci >= 1 && ci <= n - 2 && cj >= 1 && cj <= n - 2 && (ci > 1 || cj > 1)) {
+    const T *c = st + 27 * q;
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const int k = 3 * ((dj + 1) * 3 + di + 1);
+        const int64_t base = 3 * ((int64_t)(cj + dj) * n + ci + di);
+        s += c[k] * x[base] + c[k + 1] * x[base + 1] + c[k + 2] * x[base + 2];
+      }
+  } else {
+    for (int e = rp[r]; e < rp[r + 1]; ++e) s += val[e] * x[col[e]];
+  }
+  const T res = b[r] - s;
+  if constexpr (RESID) {
+    y[r] = res;
+  } else {
+    const T dn = c1 * d[r] + c2 * dinv[r] * res;
+    d[r] = dn;
+    y[r] = x[r] + dn;
+  }
+}
+
+template <typename T>
+void pd_stencil(int n, const T *st, const int *rp, const int *col, const T *val, const T *dinv, const T *x,
+                const T *b, T *d, T *y, T c1, T c2, bool resid, hipStream_t s) {
+  const int64_t np = 3 * (int64_t)n * n;
+  if (resid)
+    hipLaunchKernelGGL((k_pd_stencil<T, true>), dim3(grid_for(np, 256)), dim3(256), 0, s, n, st, rp, col, val, dinv,
+                       x, b, d, y, c1, c2);
+  else
+    hipLaunchKernelGGL((k_pd_stencil<T, false>), dim3(grid_for(np, 256)), dim3(256), 0, s, n, st, rp, col, val, dinv,
+                       x, b, d, y, c1, c2);
+  FSI_CHECK_LAUNCH();
+}
+template void pd_stencil<double>(int, const double *, const int *, const int *, const double *, const double *,
+                                 const double *, const double *, double *, double *, double, double, bool, hipStream_t);
+template void pd_stencil<float>(int, const float *, const int *, const int *, const float *, const float *,
+                                const float *, const float *, float *, float *, float, float, bool, hipStream_t);
+
 template void q2_stencil<double>(int, const Q2Table<double> *, const double *, const double *, double *, double *,
                                  double, double, bool, hipStream_t);
 template void q2_stencil<float>(int, const Q2Table<float> *, const float *, const float *, float *, float *, float,
@@ -1832,6 +1888,18 @@ void build_multigrid_q2(Ctx &c) {
                          P.dinv.p);
       FSI_CHECK_LAUNCH();
       P.lmax = 1.1 * power_lmax(P, 1, s);
+      if (m >= 4) {   // the interior rows' stencils: the rows of cell (2, 2), 27 entries each
+        const int64_t r0 = 3 * (2 * (int64_t)m + 2);
+        int h[4] = {0, 0, 0, 0};
+        FSI_HIP(hipMemcpy(h, P.A.rowptr.p + r0, sizeof(h), hipMemcpyDeviceToHost));
+        for (int q = 0; q < 3; ++q) FSI_REQUIRE(h[q + 1] - h[q] == 27, FSI_E_STATE, "interior row of L without 27 entries");
+        P.pdst64.alloc(81);
+        for (int q = 0; q < 3; ++q)
+          FSI_HIP(hipMemcpyAsync(P.pdst64.p + 27 * q, P.A.val.p + h[q], 27 * sizeof(double), hipMemcpyDeviceToDevice,
+                                 s));
+        P.pdst32.alloc(81);
+        convert(P.pdst32.p, P.pdst64.p, 81, s);
+      }
       if (l + 1 < ns.size()) {
         const int64_t npc = 3 * (int64_t)(m / 2) * (m / 2);
         build_rows(P.P, P.nodes, npc, 1, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
