@@ -67,3 +67,10 @@ def test_null_context_and_bad_arguments_without_gpu():
     size = C.c_size_t(0)
     bad = fsi.FluidDesc(1, 1.0, 1.0, 0.01)   # n < 2
     assert L.fsi_footprint(C.byref(bad), 3, 1, C.byref(size)) == fsi.FSI_E_ARG
+    # both creation entry points refuse missing or impossible descriptors before any device call
+    h = C.c_void_p()
+    for create in (L.fsi_create, L.fsi_create_q2):
+        assert create(None, None, None, 0, C.byref(h)) == fsi.FSI_E_ARG
+        assert create(C.byref(bad), None, None, 0, C.byref(h)) == fsi.FSI_E_ARG
+        assert create(None, None, None, 0, None) == fsi.FSI_E_ARG
+        assert not h.value
