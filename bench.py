@@ -279,6 +279,25 @@ def oracle_leg(args) -> dict:
             acc["twodisk1024"] = big
         out["accuracy"] = acc
     if not args.no_cpu_baseline:
+        # the paper's element pair: one oracle step of the 32^2 bar in the same phases (setup with
+        # the exact block factorisations, clipping and integration, exact-block GMRES to 1e-8)
+        from oracle import qpair
+        wq = inputs.QWORKLOADS["qbar32"]
+        t0 = time.perf_counter()
+        Sq = qpair.QSystem.from_workload(wq)
+        t1 = time.perf_counter()
+        Xq = q_position(inputs, wq, Sq.xy_ref, 0)
+        Sq.set_position(Xq)
+        t2 = time.perf_counter()
+        Sq._factor()
+        t3 = time.perf_counter()
+        bq = Sq.rhs(inputs.uniform(2 * Sq.lay.N2, wq.seed), Xq)
+        Aq = Sq.matrix()
+        _, iq = gmres.gmres(lambda v: Aq @ v, bq, precond=lambda r: Sq.apply_precond(r, "tri"), restart=30, rtol=1e-8)
+        t4 = time.perf_counter()
+        out["cpu_qbar32"] = {"T_setup_s": (t1 - t0) + (t3 - t2), "T_coup_s": t2 - t1, "T_sol_s": t4 - t3,
+                             "its": iq["its"], "N": Sq.lay.N, "cores": 1, "kind": "oracle",
+                             "sample": "one step of the paper's element pair on the 32^2 bar (qbar32)"}
         trace = inputs.request_trace(args.serve_requests, 200.0, seed=4)
         svc = {}
         for n in (32, 64):
@@ -594,10 +613,19 @@ def qpair_leg(args, fsi, inputs, torch, dev, save):
     N = ctx.sizes["N"]
     u = vec(inputs.uniform(2 * ctx.sizes["N2"], w32.seed))
     X = vec(np.concatenate(list(q_position(inputs, w32, xy, 0).T)))
+    small = {}
     for tag, prec in (("fp64", fsi.FP64), ("mixed", fsi.FP32)):
         x = torch.zeros(N, dtype=torch.float64, device=dev)
         ctx.step(u, X, x, fsi.Opts(pc=fsi.PC_TRI, prec=prec, rtol=1e-8))
         save[f"qbar32_tri_{tag}"] = x.cpu().numpy()
+        ts = []
+        for _ in range(3):   # the same step again, timed (beside the oracle's in the oracle leg)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = ctx.step(u, X, x, fsi.Opts(pc=fsi.PC_TRI, prec=prec, rtol=1e-8))
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        small[tag] = dict(step_ms=1e3 * sorted(ts)[1], its=st["its"], t_coup_ms=1e3 * st["t_coup"])
     ctx.close()
     wl = inputs.QWORKLOADS["qbar256"]
     xy, quad = wl.solid_mesh()
@@ -625,6 +653,7 @@ def qpair_leg(args, fsi, inputs, torch, dev, save):
     sz = ctx.refresh_sizes()
     rec["pieces"] = sz["n_pairs"]
     rec["nnz_Cf"] = sz["nnz_Cf"]
+    rec["qbar32"] = small
     ctx.close()
     return rec
 
