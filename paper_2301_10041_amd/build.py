@@ -16,8 +16,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libfsi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "assemble.hip", "coupling.hip", "hyper.hip", "lattice.hip", "mgtail.hip", "ops.hip", "solve.hip",
-           "stencil.hip"]
+SOURCES = ["api.hip", "assemble.hip", "coupling.hip", "hyper.hip", "lattice.hip", "mgtail.hip", "ops.hip", "q2.hip",
+           "solve.hip", "stencil.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", INCLUDE,
           # no packed FP32 instructions (hardware notes)
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

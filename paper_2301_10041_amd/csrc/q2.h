@@ -5,11 +5,19 @@
 // Dirichlet neighbours left out, and a boundary row is the identity.
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace fsi {
 
 constexpr int kQ2Max = 25;
+
+// Element table of the pair on a cell of side 1/n (assemble.hip): M (9 x 9) at QE_M,
+// K[alpha][beta] (nu eps(phi_j e_beta) : eps(phi_i e_alpha), 4 x 9 x 9) at QE_K, B[alpha][k]
+// (2 x 3 x 9) at QE_B, the diagonal of M_p (3) at QE_MP
+constexpr int QE_M = 0, QE_K = 81, QE_B = QE_K + 324, QE_MP = QE_B + 54, QE_SIZE = QE_MP + 3;
+void q2_element_table(int n, double nu, std::vector<double> &out);
 
 template <typename T>
 struct Q2Table {
