@@ -890,6 +890,8 @@ def main():
         for key in ("cpu_baseline", "cpu_serving", "accuracy"):
             if key in leg:
                 out[key] = _round(leg[key])
+        if "cpu_qbar32" in leg and "qbar256" in out.get("configs", {}):   # beside the GPU's 32^2 step
+            out["configs"]["qbar256"]["qbar32"]["cpu_oracle"] = _round(leg["cpu_qbar32"])
         if "error" in leg:
             out["oracle_leg_error"] = leg["error"]
     out["step_roofline"] = _round(out["step_roofline"])
