@@ -1118,8 +1118,7 @@ size_t Mg::bytes() const {
   size_t b = cinv.bytes() + cinv32.bytes() + rtab64.bytes() + rtab32.bytes();
   for (auto &L : lv) {
     b += L.A.bytes() + L.P.bytes() + L.R.bytes() + L.dinv.bytes() + L.dinv32.bytes() + L.stab64.bytes() +
-         L.stab32.bytes() + L.p1tab64.bytes() + L.p1tab32.bytes() + L.q2tab64.bytes() + L.q2tab32.bytes() +
-         L.pdst64.bytes() + L.pdst32.bytes();
+         L.stab32.bytes() + L.p1tab64.bytes() + L.p1tab32.bytes() + L.q2tab64.bytes() + L.q2tab32.bytes();
     for (int i = 0; i < 5; ++i) b += L.w64[i].bytes() + L.w32[i].bytes();
   }
   return b;
@@ -1700,18 +1699,6 @@ void build_multigrid_q2(Ctx &c) {
                          P.dinv.p);
       FSI_CHECK_LAUNCH();
       P.lmax = 1.1 * power_lmax(P, 1, s);
-      if (m >= 4) {   // the interior rows' stencils: the rows of cell (2, 2), 27 entries each
-        const int64_t r0 = 3 * (2 * (int64_t)m + 2);
-        int h[4] = {0, 0, 0, 0};
-        FSI_HIP(hipMemcpy(h, P.A.rowptr.p + r0, sizeof(h), hipMemcpyDeviceToHost));
-        for (int q = 0; q < 3; ++q) FSI_REQUIRE(h[q + 1] - h[q] == 27, FSI_E_STATE, "interior row of L without 27 entries");
-        P.pdst64.alloc(81);
-        for (int q = 0; q < 3; ++q)
-          FSI_HIP(hipMemcpyAsync(P.pdst64.p + 27 * q, P.A.val.p + h[q], 27 * sizeof(double), hipMemcpyDeviceToDevice,
-                                 s));
-        P.pdst32.alloc(81);
-        convert(P.pdst32.p, P.pdst64.p, 81, s);
-      }
       if (l + 1 < ns.size()) {
         const int64_t npc = 3 * (int64_t)(m / 2) * (m / 2);
         build_rows(P.P, P.nodes, npc, 1, s, tmp, [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {

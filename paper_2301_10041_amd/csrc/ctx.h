@@ -34,8 +34,6 @@ struct MgLevel {
   DevBuf<unsigned char> stab64, stab32;   // StencilTable<double/float> (velocity levels)
   DevBuf<unsigned char> p1tab64, p1tab32; // P1Table<double/float> of L_p (pressure levels)
   DevBuf<unsigned char> q2tab64, q2tab32; // Q2Table<double/float> (velocity levels of the Q2 pair)
-  DevBuf<double> pdst64;                  // the interior stencils of L (pressure levels of the Q2 pair)
-  DevBuf<float> pdst32;
 };
 
 struct Mg {

@@ -36,16 +36,6 @@ template <typename T>
 void q2_stencil(int n, const Q2Table<T> *tab, const T *x, const T *b, T *d, T *y, T c1, T c2, bool resid,
                 hipStream_t s);
 
-// The pressure Laplacian L = B D^{-1} B^T of the discontinuous pressure on an n x n grid: rows of
-// cells with 1 <= i, j <= n - 2 (every node of their cell interior) other than cell (1, 1) (a
-// neighbour of the pinned unknown) are the same for each of the three unknowns of a cell, 27
-// entries over the 3 x 3 cells around it (st: 3 x 27, row q of cell (2, 2) of the assembled L,
-// columns cell-major then unknown; n >= 4); other rows from the CSR.
-//   resid: y = b - L x;  else d = c1 d + c2 dinv (b - L x), y = x + d
-template <typename T>
-void pd_stencil(int n, const T *st, const int *rp, const int *col, const T *val, const T *dinv, const T *x,
-                const T *b, T *d, T *y, T c1, T c2, bool resid, hipStream_t s);
-
 // Host: the class stencils of A_f on an n x n grid (n >= 2) from the Q2 element matrices.
 void q2_tables(int n, double nu, double rdt, Q2Table<double> &t64, Q2Table<float> &t32);
 

@@ -1,6 +1,5 @@
 // Class stencils of the paper's element pair (Q2 velocity, discontinuous P1 pressure) and the
-// smoothing kernels of its V-cycles that use them: the Q2 A_f rows by class, and the interior
-// rows of the pressure Laplacian L = B D^{-1} B^T.
+// smoothing kernel of its velocity V-cycle that uses them (the Q2 A_f rows by class).
 #include <algorithm>
 #include <cstring>
 
@@ -137,61 +136,6 @@ void q2_stencil(int n, const Q2Table<T> *tab, const T *x, const T *b, T *d, T *y
     hipLaunchKernelGGL((k_q2_stencil<T, false>), grid, dim3(kQ2TW * kQ2TH), 0, s, n, tab, x, b, d, y, c1, c2);
   FSI_CHECK_LAUNCH();
 }
-// One thread per row of L; the three unknowns of a cell read the same 27 neighbours (through
-// the caches).
-template <typename T, bool RESID>
-__global__ void __launch_bounds__(256) k_pd_stencil(int n, const T *__restrict__ st, const int *__restrict__ rp,
-                                                    const int *__restrict__ col, const T *__restrict__ val,
-                                                    const T *__restrict__ dinv, const T *__restrict__ x,
-                                                    const T *__restrict__ b, T *__restrict__ d, T *__restrict__ y,
-                                                    T c1, T c2) {
-  const int64_t np = 3 * (int64_t)n * n;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= np) return;
-  const int64_t cell = r / 3;
-  const int q = (int)(r % 3), ci = (int)(cell % n), cj = (int)(cell / n);
-  T s = 0;
-  // cell (1, 1) touches cell 0, whose constant is the pinned unknown (a zero column of L)
-  if (ci >= 1 && ci <= n - 2 && cj >= 1 && cj <= n - 2 && (ci > 1 || cj > 1)) {
-    const T *c = st + 27 * q;
-#pragma unroll
-    for (int dj = -1; dj <= 1; ++dj)
-#pragma unroll
-      for (int di = -1; di <= 1; ++di) {
-        const int k = 3 * ((dj + 1) * 3 + di + 1);
-        const int64_t base = 3 * ((int64_t)(cj + dj) * n + ci + di);
-        s += c[k] * x[base] + c[k + 1] * x[base + 1] + c[k + 2] * x[base + 2];
-      }
-  } else {
-    for (int e = rp[r]; e < rp[r + 1]; ++e) s += val[e] * x[col[e]];
-  }
-  const T res = b[r] - s;
-  if constexpr (RESID) {
-    y[r] = res;
-  } else {
-    const T dn = c1 * d[r] + c2 * dinv[r] * res;
-    d[r] = dn;
-    y[r] = x[r] + dn;
-  }
-}
-
-template <typename T>
-void pd_stencil(int n, const T *st, const int *rp, const int *col, const T *val, const T *dinv, const T *x,
-                const T *b, T *d, T *y, T c1, T c2, bool resid, hipStream_t s) {
-  const int64_t np = 3 * (int64_t)n * n;
-  if (resid)
-    hipLaunchKernelGGL((k_pd_stencil<T, true>), dim3(grid_for(np, 256)), dim3(256), 0, s, n, st, rp, col, val, dinv,
-                       x, b, d, y, c1, c2);
-  else
-    hipLaunchKernelGGL((k_pd_stencil<T, false>), dim3(grid_for(np, 256)), dim3(256), 0, s, n, st, rp, col, val, dinv,
-                       x, b, d, y, c1, c2);
-  FSI_CHECK_LAUNCH();
-}
-template void pd_stencil<double>(int, const double *, const int *, const int *, const double *, const double *,
-                                 const double *, const double *, double *, double *, double, double, bool, hipStream_t);
-template void pd_stencil<float>(int, const float *, const int *, const int *, const float *, const float *,
-                                const float *, const float *, float *, float *, float, float, bool, hipStream_t);
-
 template void q2_stencil<double>(int, const Q2Table<double> *, const double *, const double *, double *, double *,
                                  double, double, bool, hipStream_t);
 template void q2_stencil<float>(int, const Q2Table<float> *, const float *, const float *, float *, float *, float,

@@ -244,28 +244,6 @@ static T *chebyshev(int64_t nrows, const int *rp, const int *col, const T *val, 
 
 // The same Chebyshev iteration with matrix-free products: first(scale, d, x) does the
 // step from zero (d = x = scale D^{-1} b), step(x, x2, c1, c2) one step from x into x2.
-// The same iteration on the pressure levels of the Q2 pair (pd_stencil: the interior rows of L
-// from their three stencils, the others from the CSR).
-template <typename T>
-static T *chebyshev_pd(const MgLevel &L, const T *st, const T *dinv, double lmin, double lmax, int steps,
-                       const T *b, T *x, T *x2, T *d, hipStream_t s) {
-  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
-  const double sigma = theta / delta;
-  double rho = 1.0 / sigma;
-  const T *val = Pr<T>::val(L.A);
-  hipLaunchKernelGGL((k_dinv_first<T, 1, 1>), dim3(grid_for(L.nodes, 256)), dim3(256), 0, s, L.nodes, dinv, b,
-                     (T)(1.0 / theta), d, x);
-  FSI_CHECK_LAUNCH();
-  for (int k = 1; k < steps; ++k) {
-    const double rho1 = 1.0 / (2.0 * sigma - rho);
-    pd_stencil<T>(L.n, st, L.A.rowptr.p, L.A.col.p, val, dinv, x, b, d, x2, (T)(rho1 * rho),
-                  (T)(2.0 * rho1 / delta), false, s);
-    std::swap(x, x2);
-    rho = rho1;
-  }
-  return x;
-}
-
 // The same iteration on the velocity levels of the Q2 pair with the class stencils
 // (q2_stencil) in place of the assembled rows; the first step from zero as chebyshev's.
 template <typename T>
@@ -667,20 +645,14 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
     return smooth(xs, xo, false, fuse ? xc : nullptr);
   }
   // the Q2 pair's velocity levels: class stencils for the smoothing steps and the residual
-  // and its pressure levels: the interior rows of L from three stencils
   const Q2Table<T> *q2 = nullptr;
-  const T *pd = nullptr;
   if constexpr (W == 4)
     q2 = (const Q2Table<T> *)(std::is_same<T, double>::value ? L.q2tab64.p : L.q2tab32.p);
-  else
-    pd = std::is_same<T, double>::value ? (const T *)L.pdst64.p : (const T *)L.pdst32.p;
-  T *xs = q2   ? chebyshev_q2<T>(L, q2, dinv, lmin, lmax, degree, b, x, x2, d, true, s, pl)
-          : pd ? chebyshev_pd<T>(L, pd, dinv, lmin, lmax, degree, b, x, x2, d, s)
-               : chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b, x,
-                                     x2, d, true, s, pl);
+  T *xs = q2 ? chebyshev_q2<T>(L, q2, dinv, lmin, lmax, degree, b, x, x2, d, true, s, pl)
+             : chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b, x,
+                                   x2, d, true, s, pl);
   T *xo = (xs == x) ? x2 : x;
   if (q2) q2_stencil<T>(L.n, q2, xs, b, nullptr, r, (T)0, (T)0, true, s);
-  else if (pd) pd_stencil<T>(L.n, pd, L.A.rowptr.p, L.A.col.p, val, dinv, xs, b, nullptr, r, (T)0, (T)0, true, s);
   else spmv<T, W, NC, SP_RESID>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, xs, L.nodes, r, L.nodes, s, b);
   spmv<T, 1, NC, SP_APPLY>(L.R.nrows, L.R.rowptr.p, L.R.col.p, Pr<T>::val(L.R), r, L.nodes, bc,
                            C.nodes, s);
@@ -688,21 +660,6 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
   spmv<T, 1, NC, SP_ADD>(L.P.nrows, L.P.rowptr.p, L.P.col.p, Pr<T>::val(L.P), xc, C.nodes, xs,
                          L.nodes, s);
   if (q2) return chebyshev_q2<T>(L, q2, dinv, lmin, lmax, degree, b, xs, xo, d, false, s, pl);
-  if (pd) {   // post-smoothing from xs (the first step with c1 = 0)
-    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
-    double rho = 1.0 / sigma;
-    T *xa = xs, *xb = xo;
-    pd_stencil<T>(L.n, pd, L.A.rowptr.p, L.A.col.p, val, dinv, xa, b, d, xb, (T)0, (T)(1.0 / theta), false, s);
-    std::swap(xa, xb);
-    for (int k = 1; k < degree; ++k) {
-      const double rho1 = 1.0 / (2.0 * sigma - rho);
-      pd_stencil<T>(L.n, pd, L.A.rowptr.p, L.A.col.p, val, dinv, xa, b, d, xb, (T)(rho1 * rho),
-                    (T)(2.0 * rho1 / delta), false, s);
-      std::swap(xa, xb);
-      rho = rho1;
-    }
-    return xa;
-  }
   return chebyshev<T, W, NC>(L.A.nrows, L.A.rowptr.p, L.A.col.p, val, dinv, lmin, lmax, degree, b,
                              xs, xo, d, false, s, pl);
 }
