@@ -1654,7 +1654,11 @@ void build_multigrid_q2(Ctx &c) {
   std::vector<int> ns;
   for (int m = c.n;; m /= 2) {
     ns.push_back(m);
-    if (m <= 4 || (m & 1)) break;
+    // the coarsest level at 8^2 or below (a dense inverse of at most 578 unknowns): the levels
+    // below 16^2 are launch latency, and the exact solve there also cuts the inner steps (256^2
+    // bar: 125 against 151 per step, 76.3 against 96.3 ms FP64; at 16^2 the host inverse of
+    // 2,178 unknowns takes 5 s per context)
+    if (m <= 8 || (m & 1)) break;
   }
   c.mgu.comps = 2;
   c.mgu.degree = c.mgu.degree32 = 3;
