@@ -1114,6 +1114,79 @@ static void coarse_inverse(Mg &mg, hipStream_t s) {
   FSI_HIP(hipStreamSynchronize(s));
 }
 
+// The same dense inverse on the device, for symmetric positive definite coarsest operators
+// (the Q2 pair's A_f with its Dirichlet identity rows, and L with its pinned identity row):
+// Gauss-Jordan elimination without pivoting, one column per step (the pivot row scaled by one
+// workgroup, the column's factors copied, then every other row of A and X updated in parallel).
+__global__ void k_dense_from_csr(int64_t nodes, int comps, const int *rp, const int *col, const double *v, int64_t m,
+                                 double *A) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nodes) return;
+  for (int k = rp[r]; k < rp[r + 1]; ++k) {
+    const int64_t cc = col[k];
+    if (comps == 2) {
+      A[r * m + cc] = v[4 * (int64_t)k];
+      A[r * m + nodes + cc] = v[4 * (int64_t)k + 1];
+      A[(nodes + r) * m + cc] = v[4 * (int64_t)k + 2];
+      A[(nodes + r) * m + nodes + cc] = v[4 * (int64_t)k + 3];
+    } else {
+      A[r * m + cc] = v[k];
+    }
+  }
+}
+
+__global__ void k_gj_identity(int64_t m, double *X) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) X[i * m + i] = 1.0;
+}
+
+// one workgroup: row col of A (from col on: the entries before are zero) and of X divided by the
+// pivot, which every thread reads before any is written
+__global__ void __launch_bounds__(1024) k_gj_pivot(int64_t m, int64_t col, double *A, double *X) {
+  const double inv = 1.0 / A[col * m + col];
+  __syncthreads();
+  for (int64_t k = col + threadIdx.x; k < m; k += blockDim.x) A[col * m + k] *= inv;
+  for (int64_t k = threadIdx.x; k < m; k += blockDim.x) X[col * m + k] *= inv;
+}
+
+__global__ void k_gj_factors(int64_t m, int64_t col, const double *A, double *f) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < m) f[r] = r == col ? 0.0 : A[r * m + col];
+}
+
+// row r = blockIdx.y, entry k: A[r][k] -= f[r] A[col][k] (k >= col), X[r][k] -= f[r] X[col][k]
+__global__ void k_gj_eliminate(int64_t m, int64_t col, double *A, double *X, const double *f) {
+  const int64_t r = blockIdx.y, k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double fr = f[r];
+  if (k >= m || fr == 0.0) return;
+  if (k >= col) A[r * m + k] -= fr * A[col * m + k];
+  X[r * m + k] -= fr * X[col * m + k];
+}
+
+static void coarse_inverse_spd_device(Mg &mg, hipStream_t s) {
+  MgLevel &L = mg.lv.back();
+  const int64_t nodes = L.nodes, m = mg.comps * nodes;
+  FSI_REQUIRE(m <= 8192, FSI_E_ARG, "coarsest multigrid level too large for the dense inverse");
+  DevBuf<double> A(m * m), f(m);
+  mg.cinv.alloc(m * m);
+  fill(A.p, m * m, 0.0, s);
+  fill(mg.cinv.p, m * m, 0.0, s);
+  hipLaunchKernelGGL(k_dense_from_csr, dim3(grid_for(nodes, 256)), dim3(256), 0, s, nodes, mg.comps, L.A.rowptr.p,
+                     L.A.col.p, L.A.val.p, m, A.p);
+  hipLaunchKernelGGL(k_gj_identity, dim3(grid_for(m, 256)), dim3(256), 0, s, m, mg.cinv.p);
+  const dim3 eg((unsigned)((m + 255) / 256), (unsigned)m);
+  for (int64_t col = 0; col < m; ++col) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, m, col, A.p, mg.cinv.p);
+    hipLaunchKernelGGL(k_gj_factors, dim3(grid_for(m, 256)), dim3(256), 0, s, m, col, A.p, f.p);
+    hipLaunchKernelGGL(k_gj_eliminate, eg, dim3(256), 0, s, m, col, A.p, mg.cinv.p, f.p);
+  }
+  FSI_CHECK_LAUNCH();
+  mg.ncoarse = m;
+  mg.cinv32.alloc(m * m);
+  convert(mg.cinv32.p, mg.cinv.p, m * m, s);
+  FSI_HIP(hipStreamSynchronize(s));
+}
+
 size_t Mg::bytes() const {
   size_t b = cinv.bytes() + cinv32.bytes() + rtab64.bytes() + rtab32.bytes();
   for (auto &L : lv) {
@@ -1654,11 +1727,10 @@ void build_multigrid_q2(Ctx &c) {
   std::vector<int> ns;
   for (int m = c.n;; m /= 2) {
     ns.push_back(m);
-    // the coarsest level at 8^2 or below (a dense inverse of at most 578 unknowns): the levels
-    // below 16^2 are launch latency, and the exact solve there also cuts the inner steps (256^2
-    // bar: 125 against 151 per step, 76.3 against 96.3 ms FP64; at 16^2 the host inverse of
-    // 2,178 unknowns takes 5 s per context)
-    if (m <= 8 || (m & 1)) break;
+    // the coarsest level at 16^2 or below (dense inverses of at most 2,178 velocity and 768
+    // pressure unknowns, formed on the device): the levels below 32^2 are launch latency, and
+    // the exact solve there also cuts the inner steps (256^2 bar: 114 against 151 per step)
+    if (m <= 16 || (m & 1)) break;
   }
   c.mgu.comps = 2;
   c.mgu.degree = c.mgu.degree32 = 3;
@@ -1739,8 +1811,8 @@ void build_multigrid_q2(Ctx &c) {
     }
     for (int i = 0; i < 5; ++i) U.w64[i].alloc(2 * U.nodes);
   }
-  coarse_inverse(c.mgu, s);
-  coarse_inverse(c.mgp, s);
+  coarse_inverse_spd_device(c.mgu, s);
+  coarse_inverse_spd_device(c.mgp, s);
   FSI_HIP(hipStreamSynchronize(s));
 }
 
