@@ -176,6 +176,33 @@ def test_q_step_parity(prec, pc):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", [fsi.FP64, fsi.FP32])
+def test_q_step_parity_three_levels(prec):
+    """A 64^2 bar (26 x 7 quadrilaterals): the velocity and pressure cycles run three levels
+    (64^2, 32^2, the dense 16^2), class-stencil smoothing and transfers on two of them; per block
+    within 1e-8 of the oracle's direct solve at rtol 1e-10, outer counts within the bar."""
+    wl = inputs.QWorkload("qbar64", 64, 26, 7, nu=0.2, dt=0.002, seed=9)
+    xy, quad = wl.solid_mesh()
+    X = inputs.rotation(inputs.bent(xy, 0.02, 0.4, wl.x0), wl.center, 0.15)
+    S = qpair.QSystem.from_workload(wl)
+    u0 = inputs.uniform(2 * S.lay.N2, wl.seed)
+    S.set_position(X)
+    b = S.rhs(u0, X)
+    ref = S.solve_direct(b)
+    ctx = _ctx(wl)
+    assert ctx.sizes["mg_levels_u"] == 3 and ctx.sizes["mg_levels_p"] == 3
+    print(f"[Q pair step qbar64 prec={prec} N={S.lay.N}]", flush=True)
+    out = to_dev(np.zeros(S.lay.N))
+    st = ctx.step(to_dev(u0), to_dev(soa(X)), out, fsi.Opts(pc=fsi.PC_TRI, rtol=1e-10, prec=prec))
+    assert st["converged"]
+    assert_block_parity(S, to_host(out), ref, 1e-8, f"qbar64 prec={prec}")
+    st = ctx.step(to_dev(u0), to_dev(soa(X)), out, fsi.Opts(pc=fsi.PC_TRI, rtol=1e-8, prec=prec))
+    its_o = _oracle_its(S, b, "tri")
+    print(f"  outer its {st['its']} (oracle exact blocks {its_o}), inner its {st.get('inner_its')}", flush=True)
+    assert st["its"] <= its_o + max(2, math.ceil(0.1 * its_o))
+    ctx.close()
+
+
 def test_q_time_loop():
     """Three steps of a bar bending and turning at 16^2: each state within 1e-8 per block of the
     oracle's time loop (direct solves)."""
