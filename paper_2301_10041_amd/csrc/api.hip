@@ -85,8 +85,8 @@ size_t Ctx::device_bytes() const {
   return b;
 }
 
-// Footprint estimate made before any allocation (FP64 + FP32 shadows, MG, Krylov with
-// m = 30 and both precisions' inner vectors).
+// Footprint estimate made before any allocation (FP64 + FP32 shadows, MG with the dense
+// coarsest inverses, Krylov with m = 30 and both precisions' inner vectors).
 static size_t estimate_bytes(int64_t n, int64_t ns, int64_t nt) {
   double n2 = (double)n * n;
   double zaf = 46 * n2, zb = 19 * n2, N2 = 4 * n2, Np = n2, N = 2 * N2 + Np + 4 * ns;
@@ -94,6 +94,11 @@ static size_t estimate_bytes(int64_t n, int64_t ns, int64_t nt) {
   double mg = fluid * 0.45 + 10 * N2 * 12 / 3;
   double krylov = 61 * N * 8 + 9 * (2 * N2 + Np) * 12 + 4 * N * 8 +
                   std::min(32 * (2 * N2 + Np) * 8, (double)(2ll << 30));   // MINRES Lanczos block
+  // the dense inverses of the coarsest velocity and pressure levels (FP64 + FP32)
+  const std::vector<int> lc = mg_level_cells((int)n);
+  const int cu = lc[mg_velocity_levels(lc) - 1], cp = lc.back();
+  const double mu = 2.0 * (2 * cu + 1) * (2 * cu + 1), mp = (double)(cp + 1) * (cp + 1);
+  mg += (mu * mu + mp * mp) * 12;
   double solid = ns * (7 * 12 * 2 + 200 + 8 * 20) + nt * 60 + 60 * ns * 12;
   double cf = nt * 12 * (18 * 8 + 16) + 2 * 60 * ns * 12 + N2 * 8;
   // fixed work space (reduction partials, device scalars, pinned staging, small

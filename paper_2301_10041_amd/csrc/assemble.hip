@@ -1197,14 +1197,11 @@ size_t Mg::bytes() const {
   return b;
 }
 
+
 void build_multigrid(Ctx &c) {
   hipStream_t s = c.stream;
   DevBuf<int> tmp;
-  std::vector<int> ns;
-  for (int m = c.n;; m /= 2) {
-    ns.push_back(m);
-    if (m <= 4 || (m & 1)) break;
-  }
+  const std::vector<int> ns = mg_level_cells(c.n);
   // velocity: A_f per level (re-discretised = Galerkin for nested P2 spaces)
   c.mgu.comps = 2;
   c.mgp.comps = 1;
@@ -1213,7 +1210,12 @@ void build_multigrid(Ctx &c) {
   // as many or more inner steps: 1024^2 FP64 234 -> 207 inner steps, -13% step time)
   c.mgu.degree = c.mgu.degree32 = 3;
   c.mgp.degree = c.mgp.degree32 = 2;
-  c.mgu.lv.resize(ns.size());
+  // velocity levels down to the first coarse level of 16^2 or less, whose dense inverse is
+  // formed on the device (1024^2 FP64 step 130.9 -> 127.3 ms against cycling on to 4^2: the
+  // smoothing launches of 16^2 .. 8^2 and the one-block coarse end cost more than one dense
+  // product); the finest level always smooths when the grid coarsens at all
+  const size_t nu = mg_velocity_levels(ns);
+  c.mgu.lv.resize(nu);
   c.mgp.lv.resize(ns.size());
   for (size_t l = 0; l < ns.size(); ++l) {
     int m = ns[l];
@@ -1221,23 +1223,27 @@ void build_multigrid(Ctx &c) {
     element_tables(m, c.nu, hE);
     DevBuf<double> dE(hE.size());
     FSI_HIP(hipMemcpyAsync(dE.p, hE.data(), hE.size() * 8, hipMemcpyHostToDevice, s));
-    MgLevel &U = c.mgu.lv[l];
+    const bool vel = l < nu;   // below the velocity coarsest only the pressure level is built
+    MgLevel Udummy;
+    MgLevel &U = vel ? c.mgu.lv[l] : Udummy;
     MgLevel &P = c.mgp.lv[l];
     U.n = P.n = m;
     U.nodes = (int64_t)(2 * m + 1) * (2 * m + 1);
     P.nodes = (int64_t)(m + 1) * (m + 1);
-    assemble_p2p2(U.A, nullptr, m, dE.p, c.rho / c.dt, tmp, s);
+    if (vel) assemble_p2p2(U.A, nullptr, m, dE.p, c.rho / c.dt, tmp, s);
     assemble_p1p1(P.A, m, dE.p, EM_LP, 1, tmp, s);
     FSI_HIP(hipStreamSynchronize(s));
-    U.dinv.alloc(4 * U.nodes);
     P.dinv.alloc(P.nodes);
-    hipLaunchKernelGGL(k_block_diag_inv, dim3(grid_for(U.nodes, 256)), dim3(256), 0, s, U.nodes, 4,
-                       U.A.rowptr.p, U.A.col.p, U.A.val.p, U.dinv.p);
+    if (vel) {
+      U.dinv.alloc(4 * U.nodes);
+      hipLaunchKernelGGL(k_block_diag_inv, dim3(grid_for(U.nodes, 256)), dim3(256), 0, s, U.nodes, 4,
+                         U.A.rowptr.p, U.A.col.p, U.A.val.p, U.dinv.p);
+    }
     hipLaunchKernelGGL(k_block_diag_inv, dim3(grid_for(P.nodes, 256)), dim3(256), 0, s, P.nodes, 1,
                        P.A.rowptr.p, P.A.col.p, P.A.val.p, P.dinv.p);
     FSI_CHECK_LAUNCH();
-    U.lmax = 1.1 * power_lmax(U, 2, s);
-    {
+    if (vel) U.lmax = 1.1 * power_lmax(U, 2, s);
+    if (vel) {
       StencilTable<double> t64;
       StencilTable<float> t32;
       stencil_tables(m, c.nu, c.rho / c.dt, t64, t32);
@@ -1259,11 +1265,11 @@ void build_multigrid(Ctx &c) {
       int64_t nc2 = (int64_t)(m + 1) * (m + 1);          // coarse P2 nodes = (2 (m/2) + 1)^2
       int64_t nc1 = (int64_t)(m / 2 + 1) * (m / 2 + 1);
       unsigned gf2 = grid_for(U.nodes, 256), gc2 = grid_for(nc2, 256);
-      build_rows(U.P, U.nodes, nc2, 1, s, tmp,
+      if (l + 1 < nu) build_rows(U.P, U.nodes, nc2, 1, s, tmp,
                  [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
                    hipLaunchKernelGGL(k_p2_prolong, dim3(gf2), dim3(256), 0, s, m, pass, cnt, rp, col, v);
                  });
-      build_rows(U.R, nc2, U.nodes, 1, s, tmp,
+      if (l + 1 < nu) build_rows(U.R, nc2, U.nodes, 1, s, tmp,
                  [&](int pass, int *cnt, const int *rp, int *col, double *v, double *) {
                    hipLaunchKernelGGL(k_p2_restrict, dim3(gc2), dim3(256), 0, s, m, pass, cnt, rp, col, v);
                  });
@@ -1278,7 +1284,7 @@ void build_multigrid(Ctx &c) {
                  });
     }
     for (int i = 0; i < 5; ++i) {
-      U.w64[i].alloc(2 * U.nodes);
+      if (vel) U.w64[i].alloc(2 * U.nodes);
       P.w64[i].alloc(P.nodes);
     }
   }
@@ -1289,9 +1295,9 @@ void build_multigrid(Ctx &c) {
     upload_bytes(c.mgu.rtab64, &t64, sizeof(t64), s);
     upload_bytes(c.mgu.rtab32, &t32, sizeof(t32), s);
   }
-  coarse_inverse(c.mgu, s);
+  coarse_inverse_spd_device(c.mgu, s);
   coarse_inverse(c.mgp, s);
-  (void)tail_lds_limit();   // the LDS grant of the coarse-tail launch, outside any graph capture
+  (void)tail_lds_limit();   // the LDS grant of the pressure tail launch, outside any graph capture
   FSI_HIP(hipStreamSynchronize(s));
 }
 

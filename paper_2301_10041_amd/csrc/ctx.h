@@ -20,6 +20,23 @@ struct Csr {
   size_t bytes() const { return rowptr.bytes() + col.bytes() + val.bytes() + val32.bytes(); }
 };
 
+// Cells per side of the levels of the triangle pair's hierarchies on an n x n grid: halved
+// while even and above 4 (the pressure levels, the last one solved densely); the velocity
+// levels stop at the first coarse level of 16 x 16 cells or fewer, also solved densely.
+inline std::vector<int> mg_level_cells(int n) {
+  std::vector<int> ns;
+  for (int m = n;; m /= 2) {
+    ns.push_back(m);
+    if (m <= 4 || (m & 1)) break;
+  }
+  return ns;
+}
+inline size_t mg_velocity_levels(const std::vector<int> &ns) {
+  size_t nu = 0;
+  while (nu + 1 < ns.size() && (nu == 0 || ns[nu] > 16)) ++nu;
+  return nu + 1;
+}
+
 // One level of a geometric multigrid hierarchy on the structured grid.
 struct MgLevel {
   int n = 0;               // cells per side at this level
@@ -39,8 +56,7 @@ struct MgLevel {
 struct Mg {
   int comps = 1;           // unknowns per node: 2 (velocity, 2x2 blocks) or 1 (pressure)
   bool stencil = false;    // smoothing, residuals and transfers matrix-free (structured grid)
-  bool tail = true;        // velocity levels of n <= 16 / pressure levels of n <= 64 in one launch
-                           // (with the stencil form)
+  bool tail = true;        // pressure levels of n <= 64 in one launch (with the stencil form)
   int degree = 3;          // Chebyshev smoothing steps before and after the coarse correction
   int degree32 = 3;        // the same for the FP32 V-cycle of the mixed-precision form
   std::vector<MgLevel> lv; // lv[0] finest
