@@ -1210,10 +1210,8 @@ void build_multigrid(Ctx &c) {
   // as many or more inner steps: 1024^2 FP64 234 -> 207 inner steps, -13% step time)
   c.mgu.degree = c.mgu.degree32 = 3;
   c.mgp.degree = c.mgp.degree32 = 2;
-  // velocity levels down to the first coarse level of 16^2 or less, whose dense inverse is
-  // formed on the device (1024^2 FP64 step 130.9 -> 127.3 ms against cycling on to 4^2: the
-  // smoothing launches of 16^2 .. 8^2 and the one-block coarse end cost more than one dense
-  // product); the finest level always smooths when the grid coarsens at all
+  // velocity levels: all of them, or from 512^2 on down to the first coarse level of 16^2 or
+  // less, whose dense inverse is then formed on the device
   const size_t nu = mg_velocity_levels(ns);
   c.mgu.lv.resize(nu);
   c.mgp.lv.resize(ns.size());
@@ -1295,9 +1293,10 @@ void build_multigrid(Ctx &c) {
     upload_bytes(c.mgu.rtab64, &t64, sizeof(t64), s);
     upload_bytes(c.mgu.rtab32, &t32, sizeof(t32), s);
   }
-  coarse_inverse_spd_device(c.mgu, s);
+  if (nu < ns.size()) coarse_inverse_spd_device(c.mgu, s);
+  else coarse_inverse(c.mgu, s);
   coarse_inverse(c.mgp, s);
-  (void)tail_lds_limit();   // the LDS grant of the pressure tail launch, outside any graph capture
+  (void)tail_lds_limit();   // the LDS grant of the coarse-tail launches, outside any graph capture
   FSI_HIP(hipStreamSynchronize(s));
 }
 

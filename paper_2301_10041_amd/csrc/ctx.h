@@ -21,8 +21,7 @@ struct Csr {
 };
 
 // Cells per side of the levels of the triangle pair's hierarchies on an n x n grid: halved
-// while even and above 4 (the pressure levels, the last one solved densely); the velocity
-// levels stop at the first coarse level of 16 x 16 cells or fewer, also solved densely.
+// while even and above 4 (the pressure levels, the last one solved densely).
 inline std::vector<int> mg_level_cells(int n) {
   std::vector<int> ns;
   for (int m = n;; m /= 2) {
@@ -31,9 +30,18 @@ inline std::vector<int> mg_level_cells(int n) {
   }
   return ns;
 }
+// Finest grid from which the velocity levels stop at the first coarse level of 16 x 16 cells
+// or fewer, solved densely (a product with 2 (33)^2 = 2178 rows, 4.7 M words).  From 512^2 on
+// that product reads at most a fifth of a cycle's words, and one wide launch beats the
+// one-block coarse end (1024^2 FP64 step 130.9 -> 127.3 ms).  On smaller grids the levels go on
+// to the last one: there the dense product would outweigh the rest of the cycle, and under
+// concurrent systems its whole-chip launch costs more than the one-block coarse end (serving
+// mix of 32^2 .. 256^2 grids: 166.6 -> 152.6 requests/s with the dense level everywhere).
+constexpr int kDenseVelocityFromN = 512;
 inline size_t mg_velocity_levels(const std::vector<int> &ns) {
-  size_t nu = 0;
-  while (nu + 1 < ns.size() && (nu == 0 || ns[nu] > 16)) ++nu;
+  if (ns[0] < kDenseVelocityFromN) return ns.size();
+  size_t nu = 1;
+  while (nu + 1 < ns.size() && ns[nu] > 16) ++nu;
   return nu + 1;
 }
 
@@ -56,7 +64,8 @@ struct MgLevel {
 struct Mg {
   int comps = 1;           // unknowns per node: 2 (velocity, 2x2 blocks) or 1 (pressure)
   bool stencil = false;    // smoothing, residuals and transfers matrix-free (structured grid)
-  bool tail = true;        // pressure levels of n <= 64 in one launch (with the stencil form)
+  bool tail = true;        // velocity levels of n <= 16 / pressure levels of n <= 64 in one launch
+                           // (with the stencil form)
   int degree = 3;          // Chebyshev smoothing steps before and after the coarse correction
   int degree32 = 3;        // the same for the FP32 V-cycle of the mixed-precision form
   std::vector<MgLevel> lv; // lv[0] finest

@@ -150,9 +150,46 @@ struct P1MultiArgs {
 int p1_multi_tiles(int n);
 template <typename T, typename TZ, int S, bool ZERO, int OUT>
 void p1_multi(const P1MultiArgs<T, TZ> &a, hipStream_t s, int K = 1);
-// Largest LDS block of the pressure tail launch on the current device (queried once, at most
-// 160 KiB).
+// The coarse end of a velocity V-cycle in one launch per system (mgtail.hip): levels
+// lv[0..nlev) (n <= kTailMaxN cells, each the next one's fine level) and the coarsest
+// level's dense inverse.  Vectors in LDS (offsets in T): level l's b at lv[l].off and x
+// right after it (2 N each, N = tail_plane_entries(n)), one shared direction at offd (2 N of
+// lv[0]),
+// the coarsest b at offc and x after it (m each), then the stencil coefficients and
+// inverse diagonal blocks of every level (kTailTab each) and the restriction weights
+// (kTailRw) at offt; the dense inverse of the coarsest level (m x m, row-major) at offm when
+// it fits the block's LDS, else offm = -1 and it is read from device memory; lds = the
+// total.  b and x in device memory: the first level's right-hand side and result (lane
+// stride lb).
+constexpr int kTailMax = 4, kTailDeg = 8, kTailMaxN = 16, kTailDenseMax = 6 * 64;
+constexpr int kTailCoef[4] = {0, 76, 112, 148};   // class offsets of 4 coefficients per entry
+constexpr int kTailTab = 184 + 16, kTailRw = 25 + 9 + 9 + 9;
+constexpr int kTailRs[4] = {0, 25, 34, 43};       // class offsets of the restriction weights
+// Largest LDS block of the tail launch on the current device (queried once, at most 160 KiB).
 int tail_lds_limit();
+// Entries per component of a smoothing level of n cells in the tail's LDS: even and odd
+// column planes of n + 1 columns and 2n + 1 rows.
+inline int tail_plane_entries(int n) { return 2 * (2 * n + 1) * (n + 1); }
+template <typename T>
+struct TailLevel {
+  int n, off;
+  const StencilTable<T> *tab;
+  T s;                                     // 1 / theta: the first step of both smoothings
+  T c1[kTailDeg - 1], c2[kTailDeg - 1];    // the later Chebyshev steps
+};
+template <typename T>
+struct TailArgs {
+  int nlev, degree;
+  TailLevel<T> lv[kTailMax];
+  int offd, offc, offt, offm, m, lds;
+  const P2RestrTable<T> *rt;
+  const T *cinv;
+  const T *b;
+  T *x;
+  int64_t lb;
+};
+template <typename T>
+void mg_tail(const TailArgs<T> &a, hipStream_t s, int K = 1);
 // The coarse end of a pressure (P1) V-cycle in one launch per system (mgtail.hip): levels
 // lv[0..nlev) of at most kPTailMaxN cells (each the next one's fine level) and the dense
 // inverse of the coarsest.  LDS (offsets in T): level l's b at lv[l].off and x right after it

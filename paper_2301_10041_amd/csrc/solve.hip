@@ -458,6 +458,64 @@ template <typename T> static const P2RestrTable<T> *rtab(const Mg &mg) {
   return (const P2RestrTable<T> *)(std::is_same<T, double>::value ? mg.rtab64.p : mg.rtab32.p);
 }
 
+// The arguments of the one-launch coarse end of the velocity V-cycle from level l (l >= 1,
+// where the restricted right-hand side vanishes at Dirichlet nodes), or false when the
+// remaining levels do not fit it (too fine, too many, smoothing degree or LDS).
+template <typename T>
+static bool tail_args(Mg &mg, int l, int degree, const T *b, T *x, int64_t ls, TailArgs<T> &a) {
+  const int last = (int)mg.lv.size() - 1;   // the dense coarsest level
+  const int nlev = last - l;
+  if (!mg.stencil || mg.comps != 2 || l < 1 || nlev < 1 || nlev > kTailMax || degree < 1 || degree > kTailDeg ||
+      mg.lv[l].n > kTailMaxN)
+    return false;
+  a = TailArgs<T>{};
+  a.nlev = nlev;
+  a.degree = degree;
+  int off = 0;
+  for (int k = 0; k < nlev; ++k) {
+    const MgLevel &L = mg.lv[l + k];
+    TailLevel<T> &t = a.lv[k];
+    t.n = L.n;
+    t.off = off;
+    off += 4 * tail_plane_entries(L.n);
+    t.tab = stab<T>(L);
+    // the coefficients of chebyshev_stencil on [lmax / 15, lmax]
+    const double lmax = L.lmax, lmin = L.lmax / 15.0;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    t.s = (T)(1.0 / theta);
+    for (int j = 0; j + 1 < degree; ++j) {
+      const double rho1 = 1.0 / (2.0 * sigma - rho);
+      t.c1[j] = (T)(rho1 * rho);
+      t.c2[j] = (T)(2.0 * rho1 / delta);
+      rho = rho1;
+    }
+  }
+  a.offd = off;
+  off += 2 * tail_plane_entries(mg.lv[l].n);
+  a.offc = off;
+  a.m = (int)mg.ncoarse;
+  FSI_REQUIRE(a.m == 2 * (int)mg.lv[last].nodes, FSI_E_STATE, "coarsest level size");
+  if (a.m > kTailDenseMax) return false;
+  off += 2 * a.m;
+  a.offt = off;
+  off += nlev * kTailTab + kTailRw;
+  a.lds = off;
+  if ((int64_t)a.lds * (int64_t)sizeof(T) > tail_lds_limit()) return false;
+  // the dense inverse in LDS too when it fits (loaded with the tables at the start)
+  a.offm = -1;
+  if ((int64_t)(off + (int64_t)a.m * a.m) * (int64_t)sizeof(T) <= tail_lds_limit()) {
+    a.offm = off;
+    a.lds = off + a.m * a.m;
+  }
+  a.rt = rtab<T>(mg);
+  a.cinv = Pr<T>::cinv(mg);
+  a.b = b;
+  a.x = x;
+  a.lb = ls;
+  return true;
+}
+
 // The arguments of the one-launch coarse end of the pressure V-cycle from level l, or false
 // when the remaining levels do not fit it (too fine, too many, smoothing degree or LDS).
 template <typename T>
@@ -541,7 +599,13 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
   MgLevel &C = mg.lv[l + 1];
   T *bc = Pr<T>::w(C, 1);
   const int64_t lc = (int64_t)mg.comps * C.nodes;
-  if constexpr (W != 4) {   // the coarse end of the pressure cycle in one launch
+  if constexpr (W == 4) {   // the coarse end of the velocity cycle in one launch
+    TailArgs<T> ta;
+    if (mg.tail && tail_args<T>(mg, l, degree, b, x, ls, ta)) {
+      mg_tail<T>(ta, s, K);
+      return x;
+    }
+  } else {                  // the coarse end of the pressure cycle in one launch
     PTailArgs<T> pa;
     if (mg.tail && p1_tail_args<T>(mg, l, degree, b, x, ls, pa)) {
       p1_tail<T>(pa, s, K);

@@ -1,8 +1,8 @@
 """Parity at the sizes the tiled kernels run at full scale, through the C-ABI.
 
 * A full step (fsi_step) of the two-disk geometry on a 128^2 grid (257-node lattice: three
-  tile columns of every tiled launch with a ragged last one; three smoothing levels above the
-  dense 16^2 level) against the oracle's direct solve, block-diagonal and block-triangular,
+  tile columns of every tiled launch with a ragged last one; five multigrid levels above the
+  one-launch tail) against the oracle's direct solve, block-diagonal and block-triangular,
   FP64 and mixed precision: every block (u, mean-free p, X, lam) within 1e-8 in the 2-norm and
   element by element (parity solves at rtol 1e-10).
 * Outer iteration counts at rtol 1e-8 against the oracle's exact-block counts stored in

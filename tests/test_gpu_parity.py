@@ -478,7 +478,8 @@ def test_stencil_smoother_equals_csr(pair32, prec, inner):
     assembled blocks: after one or two inner steps (isolating the V-cycle) and converged.
     At 32^2 the matrix-free cycle runs every fused launch against the CSR products and
     separate transfers: the post-smoothing launch that adds the coarse correction, the
-    residual kept in LDS and restricted in one launch, and the dense solve on 16^2."""
+    residual kept in LDS and restricted in one launch, and the one-launch tail (16^2, 8^2
+    and the dense 4^2 solve)."""
     print(f"[stencil vs csr prec={prec} inner {inner}]", flush=True)
     S, ctx, wl = pair32
     ctx.set_inner_mode(inner)
@@ -508,9 +509,9 @@ def test_stencil_smoother_equals_csr(pair32, prec, inner):
 
 @pytest.mark.parametrize("n", [24, 48, 64, 96])
 def test_multigrid_tiles_and_odd_coarsest(n):
-    """Grids of 3 x 2^k cells (24, 48, 96): the velocity hierarchy ends on a dense 12^2 level
-    and the pressure hierarchy on the odd 3^2 one; 64 ends on dense 16^2 (velocity) and 4^2
-    (pressure) levels.  At 64 and 96 the finest lattice is 129 and 193 nodes wide, so the tiled launches
+    """Grids of 3 x 2^k cells (24, 48, 96): the velocity hierarchy ends on the odd 3^2 level
+    (dense solve) and the one-launch tail starts at 12^2; 64 ends on 4^2 with the tail from
+    16^2.  At 64 and 96 the finest lattice is 129 and 193 nodes wide, so the tiled launches
     (120-node tiles of the post-smoothing, 124 of the pre-smoothing, 128 of the single-step
     and A11 launches) have two tile columns with a ragged last one, and the seams of the
     smoothing, of the fused residual-restriction and of the coarse-correction fold are
