@@ -70,16 +70,62 @@ __global__ void k_dinv_first(int64_t nodes, const T *dinv, const T *b, T scale, 
   }
 }
 
-template <typename T>
-__global__ void k_dense_mv(int m, const T *A, const T *x, T *y) {   // lane blockIdx.y: x, y + lane m
-  int r = blockIdx.x;
-  if (r >= m) return;
+// y = A x for a dense row-major m x m matrix (the coarsest multigrid level); lane
+// blockIdx.y reads x and writes y at + lane m.  One wave per row, four rows per block; each
+// lane loads VW consecutive entries at once (16 B when the row length and x allow it) and
+// keeps four loads in flight, with a partial sum in double for each.
+template <typename T, int VW>
+struct alignas(sizeof(T) * VW) DenseVec {
+  T v[VW];
+};
+constexpr int kDenseRows = 4, kDenseUnroll = 4;
+template <typename T, int VW>
+__global__ void __launch_bounds__(kDenseRows * kWave) k_dense_mv(int m, const T *A, const T *x, T *y) {
+  const int lane = threadIdx.x % kWave;
+  const int r = blockIdx.x * kDenseRows + threadIdx.x / kWave;
+  if (r >= m) return;   // whole waves leave: the sums below stay within a wave
   x += (int64_t)blockIdx.y * m;
   y += (int64_t)blockIdx.y * m;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < m; k += kWave) s += (double)A[(int64_t)r * m + k] * (double)x[k];
-  s = wave_sum(s);
-  if (threadIdx.x == 0) y[r] = (T)s;
+  using V = DenseVec<T, VW>;
+  const V *a = reinterpret_cast<const V *>(A + (int64_t)r * m);
+  const V *xv = reinterpret_cast<const V *>(x);
+  const int mv = m / VW;
+  double sum[kDenseUnroll] = {};
+  int k = lane;
+  for (; k + (kDenseUnroll - 1) * kWave < mv; k += kDenseUnroll * kWave) {
+    V av[kDenseUnroll], xx[kDenseUnroll];
+#pragma unroll
+    for (int u = 0; u < kDenseUnroll; ++u) {
+      av[u] = a[k + u * kWave];
+      xx[u] = xv[k + u * kWave];
+    }
+#pragma unroll
+    for (int u = 0; u < kDenseUnroll; ++u)
+#pragma unroll
+      for (int c = 0; c < VW; ++c) sum[u] += (double)av[u].v[c] * (double)xx[u].v[c];
+  }
+  for (; k < mv; k += kWave) {
+    const V a0 = a[k], x0 = xv[k];
+#pragma unroll
+    for (int c = 0; c < VW; ++c) sum[0] += (double)a0.v[c] * (double)x0.v[c];
+  }
+  const double s = wave_sum((sum[0] + sum[1]) + (sum[2] + sum[3]));
+  if (lane == 0) y[r] = (T)s;
+}
+
+// the launch: the widest load the row length and the alignment of A and x allow
+template <typename T>
+static void dense_mv(int m, const T *A, const T *x, T *y, int K, hipStream_t s) {
+  const dim3 grid((unsigned)((m + kDenseRows - 1) / kDenseRows), (unsigned)K), block(kDenseRows * kWave);
+  auto fits = [&](int vw) {
+    const uintptr_t b = sizeof(T) * vw;
+    return m % vw == 0 && (uintptr_t)A % b == 0 && (uintptr_t)x % b == 0;
+  };
+  constexpr int W16 = 16 / (int)sizeof(T);
+  if (fits(W16)) hipLaunchKernelGGL((k_dense_mv<T, W16>), grid, block, 0, s, m, A, x, y);
+  else if (fits(2)) hipLaunchKernelGGL((k_dense_mv<T, 2>), grid, block, 0, s, m, A, x, y);
+  else hipLaunchKernelGGL((k_dense_mv<T, 1>), grid, block, 0, s, m, A, x, y);
+  FSI_CHECK_LAUNCH();
 }
 
 // y = a x + b y + c z
@@ -583,9 +629,7 @@ static T *vcycle(Mg &mg, int l, const T *b, hipStream_t s, Prof *prof = nullptr,
               "tile sums only from the finest velocity level of a matrix-free cycle");
   const int64_t ls = (int64_t)mg.comps * L.nodes;
   if (l + 1 == (int)mg.lv.size()) {
-    hipLaunchKernelGGL(k_dense_mv<T>, dim3((unsigned)mg.ncoarse, (unsigned)K), dim3(kWave), 0, s,
-                       (int)mg.ncoarse, Pr<T>::cinv(mg), b, x);
-    FSI_CHECK_LAUNCH();
+    dense_mv<T>((int)mg.ncoarse, Pr<T>::cinv(mg), b, x, K, s);
     return x;
   }
   // Chebyshev interval [lmax / R, lmax] of D^{-1} A: R = 15 on the velocity levels, 30 on the
