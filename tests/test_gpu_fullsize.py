@@ -126,15 +126,19 @@ def test_step_residual_on_sampled_rows(full, prec):
     """The GPU step solution satisfies the oracle's equations on sampled rows to the solve
     tolerance: |b_i - (A x)_i| <= 1e-8 ||b||_2, with b_i and (A x)_i the oracle's rows (the
     GPU's right-hand side is checked against the oracle's on the same rows: g1 on velocity
-    rows, zero on pressure and X rows, g2 on lam rows)."""
+    rows, zero on pressure and X rows, g2 on lam rows).  The inner solves stay healthy: at
+    most 40 inner MINRES steps per outer step (16-21 here), which a wrong coarse solve or
+    transfer at these sizes (the dense 16^2 velocity level from 512^2 on) would break."""
     wl, ctx = full["wl"], full["ctx"]
     N, N2 = ctx.sizes["N"], ctx.sizes["N2"]
     u = inputs.uniform(2 * N2, wl.seed)
     torch = torch_dev()
     out = torch.zeros(N, dtype=torch.float64, device="cuda")
     st = ctx.step(to_dev(u), to_dev(soa(full["X"])), out, fsi.Opts(pc=fsi.PC_TRI, prec=prec))
-    print(f"  step prec={prec}: its={st['its']} relres={st['relres_true']:.2e}", flush=True)
+    print(f"  step prec={prec}: its={st['its']} inner={st['inner_its']} relres={st['relres_true']:.2e}",
+          flush=True)
     assert st["converged"] and st["relres_true"] <= 1e-8
+    assert 0 < st["inner_its"] <= 40 * st["its"]
     x = to_host(out)
     b = torch.zeros(N, dtype=torch.float64, device="cuda")
     ctx.build_rhs(to_dev(u), to_dev(soa(full["X"])), b)
