@@ -73,14 +73,15 @@ __global__ void k_dinv_first(int64_t nodes, const T *dinv, const T *b, T scale, 
 // y = A x for a dense row-major m x m matrix (the coarsest multigrid level); lane
 // blockIdx.y reads x and writes y at + lane m.  One wave per row, four rows per block; each
 // lane loads VW consecutive entries at once (16 B when the row length and x allow it) and
-// keeps four loads in flight, with a partial sum in double for each.
+// keeps 64 B of the row in flight (U loads), with a partial sum in double for each load.
 template <typename T, int VW>
 struct alignas(sizeof(T) * VW) DenseVec {
   T v[VW];
 };
-constexpr int kDenseRows = 4, kDenseUnroll = 4;
+constexpr int kDenseRows = 4;
 template <typename T, int VW>
 __global__ void __launch_bounds__(kDenseRows * kWave) k_dense_mv(int m, const T *A, const T *x, T *y) {
+  constexpr int U = 64 / (VW * (int)sizeof(T));
   const int lane = threadIdx.x % kWave;
   const int r = blockIdx.x * kDenseRows + threadIdx.x / kWave;
   if (r >= m) return;   // whole waves leave: the sums below stay within a wave
@@ -90,17 +91,17 @@ __global__ void __launch_bounds__(kDenseRows * kWave) k_dense_mv(int m, const T 
   const V *a = reinterpret_cast<const V *>(A + (int64_t)r * m);
   const V *xv = reinterpret_cast<const V *>(x);
   const int mv = m / VW;
-  double sum[kDenseUnroll] = {};
+  double sum[U] = {};
   int k = lane;
-  for (; k + (kDenseUnroll - 1) * kWave < mv; k += kDenseUnroll * kWave) {
-    V av[kDenseUnroll], xx[kDenseUnroll];
+  for (; k + (U - 1) * kWave < mv; k += U * kWave) {
+    V av[U], xx[U];
 #pragma unroll
-    for (int u = 0; u < kDenseUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       av[u] = a[k + u * kWave];
       xx[u] = xv[k + u * kWave];
     }
 #pragma unroll
-    for (int u = 0; u < kDenseUnroll; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int c = 0; c < VW; ++c) sum[u] += (double)av[u].v[c] * (double)xx[u].v[c];
   }
@@ -109,7 +110,11 @@ __global__ void __launch_bounds__(kDenseRows * kWave) k_dense_mv(int m, const T 
 #pragma unroll
     for (int c = 0; c < VW; ++c) sum[0] += (double)a0.v[c] * (double)x0.v[c];
   }
-  const double s = wave_sum((sum[0] + sum[1]) + (sum[2] + sum[3]));
+#pragma unroll
+  for (int h = U / 2; h > 0; h /= 2)   // pairwise: the U = 4 order (s0 + s1) + (s2 + s3)
+#pragma unroll
+    for (int u = 0; u < h; ++u) sum[u] = sum[2 * u] + sum[2 * u + 1];
+  const double s = wave_sum(sum[0]);
   if (lane == 0) y[r] = (T)s;
 }
 
