@@ -1197,7 +1197,6 @@ size_t Mg::bytes() const {
   return b;
 }
 
-
 void build_multigrid(Ctx &c) {
   hipStream_t s = c.stream;
   DevBuf<int> tmp;
@@ -1221,7 +1220,9 @@ void build_multigrid(Ctx &c) {
     element_tables(m, c.nu, hE);
     DevBuf<double> dE(hE.size());
     FSI_HIP(hipMemcpyAsync(dE.p, hE.data(), hE.size() * 8, hipMemcpyHostToDevice, s));
-    const bool vel = l < nu;   // below the velocity coarsest only the pressure level is built
+    // below the velocity coarsest only the pressure level is built (U is then a throw-away
+    // level of which only the sizes are set)
+    const bool vel = l < nu;
     MgLevel Udummy;
     MgLevel &U = vel ? c.mgu.lv[l] : Udummy;
     MgLevel &P = c.mgp.lv[l];
