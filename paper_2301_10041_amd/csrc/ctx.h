@@ -39,7 +39,7 @@ inline std::vector<int> mg_level_cells(int n) {
 // mix of 32^2 .. 256^2 grids: 166.6 -> 152.6 requests/s with the dense level everywhere).
 constexpr int kDenseVelocityFromN = 512;
 inline size_t mg_velocity_levels(const std::vector<int> &ns) {
-  if (ns[0] < kDenseVelocityFromN) return ns.size();
+  if (ns.size() < 2 || ns[0] < kDenseVelocityFromN) return ns.size();
   size_t nu = 1;
   while (nu + 1 < ns.size() && ns[nu] > 16) ++nu;
   return nu + 1;

@@ -67,6 +67,15 @@ def test_null_context_and_bad_arguments_without_gpu():
     size = C.c_size_t(0)
     bad = fsi.FluidDesc(1, 1.0, 1.0, 0.01)   # n < 2
     assert L.fsi_footprint(C.byref(bad), 3, 1, C.byref(size)) == fsi.FSI_E_ARG
+    # grids of one multigrid level (odd n, also above the size where the velocity levels end
+    # on a dense 16^2 level) and of several are estimated; a large odd grid's only level
+    # would be its dense coarsest level, far beyond any device (creation refuses it)
+    est = {}
+    for n in (3, 511, 512, 513, 1024):
+        assert L.fsi_footprint(C.byref(fsi.FluidDesc(n, 1.0, 1.0, 0.01)), 100, 150, C.byref(size)) == fsi.FSI_OK
+        est[n] = size.value
+    assert est[3] < est[512] < est[1024] < (64 << 30)
+    assert min(est[511], est[513]) > (1 << 40)
     # both creation entry points refuse missing or impossible descriptors before any device call
     h = C.c_void_p()
     for create in (L.fsi_create, L.fsi_create_q2):

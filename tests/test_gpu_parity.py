@@ -408,6 +408,11 @@ def test_error_paths():
     with pytest.raises(fsi.FsiError) as e:
         fsi.Context(8, xy, tri[:, ::-1])
     assert e.value.code == fsi.FSI_E_MESH
+    # an odd grid above the dense-16^2 threshold has one multigrid level, too large for a
+    # dense coarsest inverse: refused with FSI_E_ARG
+    with pytest.raises(fsi.FsiError) as e:
+        fsi.Context(513, xy, tri)
+    assert e.value.code == fsi.FSI_E_ARG
     ctx.close()
 
 
