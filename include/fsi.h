@@ -175,8 +175,11 @@ enum fsi_block {
  * hierarchies of the preconditioner and all work space on the current HIP device.
  * hip_stream: a hipStream_t (NULL = default stream).  hbm_budget: maximum device
  * bytes the context may hold (0 = no limit); FSI_E_NOMEM if the footprint exceeds it.
- * Errors: FSI_E_ARG, FSI_E_MESH (a reference triangle with area <= 0), FSI_E_NOMEM,
- * FSI_E_HIP. */
+ * The hierarchies halve n while it is even and above 4 and solve their last level densely
+ * (from n = 512 the velocity levels end on the first of 16 x 16 cells or fewer instead).
+ * Errors: FSI_E_ARG (n outside [2, 4096], or a dense coarsest level of more than 6,000
+ * unknowns, 8,192 for the velocity levels from n = 512, such as the single level of an odd
+ * n above 25), FSI_E_MESH (a reference triangle with area <= 0), FSI_E_NOMEM, FSI_E_HIP. */
 int fsi_create(const fsi_fluid_desc *fluid, const fsi_solid_desc *solid, void *hip_stream,
                size_t hbm_budget, fsi_ctx **out);
 
